@@ -1,0 +1,57 @@
+"""Dense direct-quadrature reference of the same scalar operator (oracle).
+
+D_ij = sum_p sum_q (A_i/3)(A_j/3) G_d(k, |r_ip - r_jq|)
+       + A_s,NR[i, j]                                  if (i, j) is near,
+       + sum_p sum_q (A_i/3)(A_j/3) G_s(|r_ip - r_jq|)  otherwise.
+
+This is the Galerkin matrix with the kernel split of eq. hgfdecomp0: the
+singular static part integrated directly where it matters (the near region)
+and the smooth dynamic part G_d (eq. hgfd, with G_d(0) = -jk/(4 pi) from
+eq. hgfdtaylor) by the 3 x 3 point rule everywhere.  It measures the
+approximation error of the grid-accelerated operator (the "direct" matrix of
+Sec. IV-B); it is not the parity target of the GPU path.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import mesh as _mesh
+from .green import green_dynamic, green_static
+
+
+def dense_rows(V, T, k: float, rows, near_static) -> np.ndarray:
+    """Rows of D as a dense array [len(rows), N].
+
+    ``near_static`` is a scipy.sparse matrix holding A_s,NR on the near list.
+    """
+    qp = _mesh.quad_points(V, T)                  # [N, 3, 3]
+    w = _mesh.quad_weights(V, T)                  # [N, 3]
+    rows = np.asarray(rows, dtype=np.int64)
+    N = T.shape[0]
+    out = np.zeros((rows.size, N), dtype=np.complex128)
+    ns = near_static.tocsr()
+    for t, i in enumerate(rows):
+        d = qp[i][:, None, None, :] - qp[None, :, :, :]
+        # d: [3 (p of i), N, 3 (q of j), 3 xyz]
+        R = np.linalg.norm(d, axis=-1)
+        ww = w[i][:, None, None] * w[None, :, :]
+        dyn = np.sum(ww * green_dynamic(k, R), axis=(0, 2))
+        with np.errstate(divide="ignore"):
+            st = np.sum(ww * np.where(R > 0, green_static(np.where(R > 0, R, 1.0)), 0.0),
+                        axis=(0, 2))
+        row = ns.getrow(int(i))
+        st[row.indices] = row.data
+        out[t] = dyn + st
+    return out
+
+
+def dense_matvec(V, T, k: float, x, near_static, rows=None) -> np.ndarray:
+    """(D x) on all rows, or on ``rows`` only."""
+    N = T.shape[0]
+    rows = np.arange(N) if rows is None else np.asarray(rows)
+    x = np.asarray(x, dtype=np.complex128)
+    y = np.empty(rows.size, dtype=np.complex128)
+    chunk = 64
+    for s in range(0, rows.size, chunk):
+        y[s:s + chunk] = dense_rows(V, T, k, rows[s:s + chunk], near_static) @ x
+    return y
