@@ -1,0 +1,234 @@
+/*
+ * aim.h -- C ABI of the MI355X AIMx library.
+ *
+ * The library applies and solves the extended adaptive-integral-method
+ * (AIMx) operator of Sharma & Triverio, "AIMx: An Extended Adaptive Integral
+ * Method for the Fast Electromagnetic Modeling of Complex Structures"
+ * (arXiv 2009.02281), for the scalar single-layer Helmholtz operator with one
+ * piecewise-constant basis function per flat triangle and Galerkin testing:
+ *
+ *     A(k) x ~= (A_s,NR - A_s,P) x + W H(k) P x            (eq. LAIMx)
+ *
+ * with P the projection of quadrature-point sources onto (n+1)^3 grid
+ * stencils, H(k) the Toeplitz matrix of G = e^{-jkr}/(4 pi r) over grid
+ * points with self term -jk/(4 pi) (eqs. Hmn, Hmm), W = P^T, A_s,NR the
+ * static (1/(4 pi r)) near-region matrix by direct integration and A_s,P its
+ * precorrection (eq. aimLPs, with H_s self term 0 per eq. Hsmm).
+ *
+ * Conventions common to every call:
+ *  - Every function returns aim_status; no C++ exception crosses the ABI.
+ *    On failure aim_last_error() returns a message (thread-local) and output
+ *    buffers are unspecified.
+ *  - "_dev" pointers are device (HBM) addresses owned by the caller; "_host"
+ *    pointers are host memory owned by the caller.  The library never frees
+ *    caller memory.
+ *  - Complex vectors are interleaved (re, im): complex128 = two doubles for
+ *    AIM_C128, complex64 = two floats for AIM_C64, laid out [nrhs][N] with N
+ *    the number of triangles (basis functions).
+ *  - Grids are x-fastest: node (ix, iy, iz) has flat index ix + Nx (iy + Ny iz).
+ *  - A plan is not thread-safe; calls on one plan must be serialised.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).
+ *  - Lengths and wavenumbers share one unit (k = 2 pi / lambda).
+ */
+#ifndef AIM_H
+#define AIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AIM_OK = 0,
+  AIM_ERR_INVALID_ARG = 1,   /* null pointer, size or enum out of range          */
+  AIM_ERR_GEOMETRY = 2,      /* non-finite vertex, bad index, zero-area triangle */
+  AIM_ERR_GRID = 3,          /* unsupported grid size, stencil leaves the grid   */
+  AIM_ERR_OOM = 4,           /* device or host allocation failed                 */
+  AIM_ERR_DEVICE = 5,        /* a HIP runtime call failed                        */
+  AIM_ERR_NOT_CONVERGED = 6, /* solver hit its iteration cap; best iterate kept  */
+  AIM_ERR_BREAKDOWN = 7,     /* solver met a non-finite value or a breakdown      */
+  AIM_ERR_STATE = 8          /* call not valid for this plan (e.g. precision
+                                not built, no preconditioner data)              */
+} aim_status;
+
+typedef enum { AIM_C128 = 0, AIM_C64 = 1 } aim_precision;
+
+typedef enum {
+  AIM_PC_NONE = 0,       /* unpreconditioned                                      */
+  AIM_PC_DIAG = 1,       /* 1 / diag(A_s,NR): the frequency-independent diagonal
+                            preconditioner of Sec. III-A ("Preconditioning")     */
+  AIM_PC_NEARBLOCK = 2,  /* block-Jacobi on spatial clusters of A_s,NR: the
+                            near-region/block choice of the same section, built
+                            from static entries only                             */
+  AIM_PC_UNET = 3        /* learned grid preconditioner (aim_unet_*), applied
+                            inside flexible GMRES, with the near-block
+                            preconditioner as its fallback                         */
+} aim_pc_kind;
+
+typedef enum {
+  AIM_STAGE_PROJECT = 0,     /* x[nrhs][N]            -> q[nrhs][Ng]  (q = P x)        */
+  AIM_STAGE_CONVOLVE = 1,    /* q[nrhs][Ng]           -> phi[nrhs][Ng] (phi = H(k) q)  */
+  AIM_STAGE_INTERPOLATE = 2, /* phi[nrhs][Ng]         -> y[nrhs][N]   (y = P^T phi)    */
+  AIM_STAGE_NEAR = 3         /* x[nrhs][N]            -> y[nrhs][N]   (y = C x)        */
+} aim_stage;
+
+typedef enum { AIM_RHS_PLANE_WAVE = 0, AIM_RHS_GAUSSIAN_PATCH = 1 } aim_rhs_kind;
+
+typedef struct aim_plan_s* aim_plan;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  When
+ * alloc is NULL the library uses hipMalloc / hipFree. */
+typedef void* (*aim_alloc_fn)(size_t bytes, void* hip_stream, void* ctx);
+typedef void (*aim_free_fn)(void* ptr, void* hip_stream, void* ctx);
+
+/* Problem description (Sec. II: a triangulated surface, a regular grid over
+ * its bounding box, stencils of n+1 points per direction, a near-region
+ * threshold and the frequencies of the sweep).  All arrays are host memory
+ * and are copied during aim_setup; the caller may free them afterwards. */
+typedef struct {
+  int64_t n_vertices;
+  int64_t n_triangles;
+  const double* vertices;    /* [n_vertices][3]                                  */
+  const int32_t* triangles;  /* [n_triangles][3], 0-based vertex indices         */
+  int32_t stencil_order;     /* n = 2 (27 nodes/point) or 3 (64 nodes/point)     */
+  int32_t grid_dims[3];      /* unpadded Nx, Ny, Nz: powers of two in [8, 256];
+                                padded internally to 2N per axis                  */
+  double h;                  /* grid spacing; <= 0: max_a extent_a/(N_a - 5)     */
+  double near_threshold;     /* pairs with centroid distance < this are near     */
+  int32_t n_freq;            /* number of wavenumbers (>= 1)                      */
+  const double* k;           /* [n_freq] wavenumbers (> 0)                        */
+  uint32_t precisions;       /* bitmask of (1u << AIM_C128) | (1u << AIM_C64)     */
+  int32_t max_rhs;           /* largest nrhs later passed to matvec/solve (>= 1)  */
+  int32_t n_threads;         /* host threads for setup; <= 0: all cores           */
+  aim_alloc_fn alloc;        /* optional; NULL = hipMalloc                        */
+  aim_free_fn free;
+  void* alloc_ctx;
+} aim_setup_desc;
+
+/* Facts about a built plan (host struct filled by aim_plan_query). */
+typedef struct {
+  int64_t n;                 /* basis functions (triangles)                      */
+  int64_t n_grid;            /* Nx Ny Nz                                          */
+  int64_t nnz;               /* non-zeros of C = A_s,NR - A_s,P                  */
+  int32_t dims[3];
+  int32_t order;
+  int32_t n_freq;
+  int32_t max_rhs;
+  uint32_t precisions;
+  double h;
+  double origin[3];          /* position of node (0, 0, 0)                       */
+  double setup_seconds;      /* host + device time of aim_setup                  */
+  double spectra_seconds;    /* part of it spent building kernel spectra          */
+  int64_t device_bytes;      /* device memory held by the plan                    */
+  int32_t n_clusters;        /* near-block preconditioner clusters                */
+  int32_t max_cluster;       /* largest cluster                                    */
+} aim_plan_info;
+
+/* Solver options (aim_solve).  rtol is the relative residual
+ * ||b - A x|| / ||b|| at which a right-hand side counts as converged (the
+ * paper's runs use GMRES to 1e-4, Sec. V).  inner = AIM_C64 runs the Krylov
+ * matvecs in complex64 inside an iterative-refinement loop whose residual
+ * and update are complex128; inner = AIM_C128 runs restarted GMRES directly.
+ * Arnoldi orthogonalisation is always complex128 on the device. */
+typedef struct {
+  double rtol;               /* target relative residual (> 0)                    */
+  int32_t restart;           /* Krylov subspace size m (1..200)                   */
+  int32_t max_iter;          /* cap on inner iterations per right-hand side       */
+  int32_t max_refine;        /* cap on refinement steps (inner = AIM_C64)          */
+  aim_precision inner;       /* precision of the Krylov matvecs                    */
+  aim_pc_kind pc;            /* right preconditioner                               */
+  double inner_rtol;         /* inner tolerance per refinement step (0: 1e-4)     */
+} aim_solve_opts;
+
+/* Per-right-hand-side outcome (host array of nrhs entries). */
+typedef struct {
+  int32_t iters;             /* inner Krylov iterations                           */
+  int32_t refinements;       /* outer refinement steps                             */
+  int32_t matvecs;           /* operator applications                              */
+  int32_t fallback_used;     /* 1 if the learned preconditioner was switched off  */
+  int32_t converged;
+  double rel_resid;          /* final true relative residual (complex128)         */
+  double seconds;            /* wall time of the whole batched solve               */
+} aim_solve_info;
+
+/* Build a plan: validates the mesh and grid on the host (before any device
+ * call), computes quadrature points (3-point rule), stencils, the near list,
+ * the static near-field matrix by closed-form integration of 1/R (Sec. III-A,
+ * change (a) of the AIMx recipe) and its precorrection, uploads the tables
+ * and computes one kernel spectrum per wavenumber on the device.
+ * Errors: AIM_ERR_INVALID_ARG, AIM_ERR_GEOMETRY, AIM_ERR_GRID, AIM_ERR_OOM,
+ * AIM_ERR_DEVICE.  Blocking. */
+aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out);
+
+/* Host-only variant of aim_setup: builds and validates every
+ * frequency-independent host table (quadrature points, stencils, near list,
+ * A_s,NR and C = A_s,NR - A_s,P, preconditioner blocks) without touching
+ * the device.  The plan answers aim_plan_query and aim_export_tables; every
+ * device call on it returns AIM_ERR_STATE.  Blocking; runs without a GPU. */
+aim_status aim_setup_host(const aim_setup_desc* desc, aim_plan* out);
+
+/* Release every device and host resource of the plan (NULL is a no-op). */
+aim_status aim_destroy(aim_plan plan);
+
+aim_status aim_plan_query(aim_plan plan, aim_plan_info* info_host);
+
+/* y = A(k_f) x for nrhs right-hand sides (eq. LAIMx): projection, zero-padded
+ * 3D FFT, multiplication by the kernel spectrum of wavenumber k_f, inverse
+ * FFT, interpolation, plus the sparse correction C x.  x_dev and y_dev are
+ * [nrhs][N] complex of the given precision and must not overlap.
+ * freq_idx_host[r] selects the wavenumber of right-hand side r (NULL: all 0).
+ * Asynchronous on hip_stream.  Errors: AIM_ERR_INVALID_ARG (nrhs outside
+ * 1..max_rhs, bad frequency index), AIM_ERR_STATE (precision not built). */
+aim_status aim_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
+                      int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream);
+
+/* One stage of the matvec, for stage-level checks (see aim_stage for the
+ * shapes).  Same rules as aim_matvec; grids are unpadded [nrhs][Nz][Ny][Nx]. */
+aim_status aim_apply_stage(aim_plan plan, aim_precision prec, aim_stage stage,
+                           const void* in_dev, void* out_dev, int32_t nrhs,
+                           const int32_t* freq_idx_host, void* hip_stream);
+
+/* Galerkin-tested incident field, complex128 [nrhs][N] on the device:
+ * b_i = sum_p (A_i/3) u_inc(r_ip).  AIM_RHS_PLANE_WAVE: u = exp(-j k d.r) with
+ * params = {dx, dy, dz} (unit direction); AIM_RHS_GAUSSIAN_PATCH:
+ * u = exp(-|r - c|^2 / (2 sigma^2)) with params = {cx, cy, cz, sigma}.
+ * Right-hand side r uses params + r * n_params and wavenumber
+ * k[freq_idx_host[r]].  Asynchronous. */
+aim_status aim_excitation(aim_plan plan, aim_rhs_kind kind, const double* params_host,
+                          int32_t n_params, int32_t nrhs, const int32_t* freq_idx_host,
+                          void* b_dev, void* hip_stream);
+
+/* Solve A(k_f) x = b for nrhs right-hand sides at once (batched restarted
+ * GMRES / flexible GMRES with right preconditioning, complex128 Arnoldi; with
+ * inner = AIM_C64 wrapped in complex128 iterative refinement).  b_dev and
+ * x_dev are complex128 [nrhs][N]; x_dev is the initial guess on entry and the
+ * solution on return.  Blocking.  Returns AIM_ERR_NOT_CONVERGED if any
+ * right-hand side misses rtol (x_dev still holds the best iterates and
+ * info_host is filled), AIM_ERR_BREAKDOWN on non-finite values. */
+aim_status aim_solve(aim_plan plan, const void* b_dev, void* x_dev, int32_t nrhs,
+                     const int32_t* freq_idx_host, const aim_solve_opts* opts,
+                     aim_solve_info* info_host, void* hip_stream);
+
+/* Host copies of setup tables, for validation against an independent
+ * implementation.  Any pointer may be NULL to skip that table.
+ *   stencil_start [3N][3] int32: first node of each quadrature point's stencil
+ *   stencil_local [3N][3] double: t - s, t = (r - origin)/h per axis
+ *   rowptr [N+1] int64, col [nnz] int32, val [nnz] double: C in CSR
+ *   near_static [nnz] double: A_s,NR on the same pattern
+ * Blocking. */
+aim_status aim_export_tables(aim_plan plan, int32_t* stencil_start, double* stencil_local,
+                             int64_t* rowptr, int32_t* col, double* val, double* near_static);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* aim_last_error(void);
+
+/* Library version string. */
+const char* aim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIM_H */

@@ -1,0 +1,316 @@
+"""Thin ctypes binding of ``libaimx.so`` (the C ABI in include/aim.h).
+
+Argument marshalling only: every step of the operator and of the solver runs
+in the library's HIP kernels.  PyTorch supplies device memory and streams.
+There is no fallback: if the library is not built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libaimx.so")
+
+AIM_OK = 0
+STATUS = {0: "AIM_OK", 1: "AIM_ERR_INVALID_ARG", 2: "AIM_ERR_GEOMETRY", 3: "AIM_ERR_GRID",
+          4: "AIM_ERR_OOM", 5: "AIM_ERR_DEVICE", 6: "AIM_ERR_NOT_CONVERGED",
+          7: "AIM_ERR_BREAKDOWN", 8: "AIM_ERR_STATE"}
+PREC = {"c128": 0, "c64": 1}
+PC = {"none": 0, "diag": 1, "nearblock": 2, "unet": 3}
+STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3}
+RHS = {"plane_wave": 0, "gaussian_patch": 1}
+
+EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec", "aim_apply_stage",
+            "aim_excitation", "aim_solve", "aim_export_tables", "aim_last_error", "aim_version"]
+
+
+class AimError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class SetupDesc(C.Structure):
+    _fields_ = [
+        ("n_vertices", C.c_int64), ("n_triangles", C.c_int64),
+        ("vertices", C.c_void_p), ("triangles", C.c_void_p),
+        ("stencil_order", C.c_int32), ("grid_dims", C.c_int32 * 3),
+        ("h", C.c_double), ("near_threshold", C.c_double),
+        ("n_freq", C.c_int32), ("k", C.c_void_p),
+        ("precisions", C.c_uint32), ("max_rhs", C.c_int32), ("n_threads", C.c_int32),
+        ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("n_grid", C.c_int64), ("nnz", C.c_int64),
+        ("dims", C.c_int32 * 3), ("order", C.c_int32), ("n_freq", C.c_int32),
+        ("max_rhs", C.c_int32), ("precisions", C.c_uint32), ("h", C.c_double),
+        ("origin", C.c_double * 3), ("setup_seconds", C.c_double),
+        ("spectra_seconds", C.c_double), ("device_bytes", C.c_int64),
+        ("n_clusters", C.c_int32), ("max_cluster", C.c_int32),
+    ]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [
+        ("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
+        ("max_refine", C.c_int32), ("inner", C.c_int32), ("pc", C.c_int32),
+        ("inner_rtol", C.c_double),
+    ]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32), ("refinements", C.c_int32), ("matvecs", C.c_int32),
+        ("fallback_used", C.c_int32), ("converged", C.c_int32),
+        ("rel_resid", C.c_double), ("seconds", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads the library (once) and declares the signatures.  Raises
+    FileNotFoundError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -m paper_2009_02281_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, ip32 = C.c_void_p, C.c_int32, C.POINTER(C.c_int32)
+    lib.aim_setup.argtypes = [C.POINTER(SetupDesc), vp, C.POINTER(vp)]
+    lib.aim_setup_host.argtypes = [C.POINTER(SetupDesc), C.POINTER(vp)]
+    lib.aim_destroy.argtypes = [vp]
+    lib.aim_plan_query.argtypes = [vp, C.POINTER(PlanInfo)]
+    lib.aim_matvec.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
+    lib.aim_apply_stage.argtypes = [vp, i32, i32, vp, vp, i32, ip32, vp]
+    lib.aim_excitation.argtypes = [vp, i32, C.POINTER(C.c_double), i32, i32, ip32, vp, vp]
+    lib.aim_solve.argtypes = [vp, vp, vp, i32, ip32, C.POINTER(SolveOpts),
+                              C.POINTER(SolveInfo), vp]
+    lib.aim_export_tables.argtypes = [vp, ip32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                      ip32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.aim_last_error.restype = C.c_char_p
+    lib.aim_version.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("aim_last_error", "aim_version"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != AIM_OK:
+        raise AimError(status, load_library().aim_last_error().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _freq_arg(freq_idx, nrhs):
+    if freq_idx is None:
+        return None, None
+    arr = np.ascontiguousarray(np.broadcast_to(np.asarray(freq_idx, dtype=np.int32), (nrhs,)))
+    return arr, arr.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+@dataclass
+class SolveResult:
+    iters: np.ndarray
+    refinements: np.ndarray
+    matvecs: np.ndarray
+    converged: np.ndarray
+    rel_resid: np.ndarray
+    seconds: float
+    status: int
+
+
+class Plan:
+    """An AIMx operator for one mesh, grid and frequency set (see aim_setup)."""
+
+    def __init__(self, vertices, triangles, order: int, dims, h: float, near_threshold: float,
+                 k, precisions=("c128", "c64"), max_rhs: int = 1, n_threads: int = 0,
+                 stream=None, host_only: bool = False):
+        lib = load_library()
+        self._lib = lib
+        V = np.ascontiguousarray(vertices, dtype=np.float64)
+        T = np.ascontiguousarray(triangles, dtype=np.int32)
+        kk = np.ascontiguousarray(np.atleast_1d(np.asarray(k, dtype=np.float64)))
+        d = SetupDesc()
+        d.n_vertices = V.shape[0]
+        d.n_triangles = T.shape[0]
+        d.vertices = V.ctypes.data
+        d.triangles = T.ctypes.data
+        d.stencil_order = int(order)
+        for a in range(3):
+            d.grid_dims[a] = int(dims[a])
+        d.h = float(h)
+        d.near_threshold = float(near_threshold)
+        d.n_freq = kk.size
+        d.k = kk.ctypes.data
+        d.precisions = sum(1 << PREC[p] for p in precisions)
+        d.max_rhs = int(max_rhs)
+        d.n_threads = int(n_threads)
+        self._plan = C.c_void_p()
+        self.precisions = tuple(precisions)
+        self.host_only = host_only
+        if host_only:
+            _check(lib.aim_setup_host(C.byref(d), C.byref(self._plan)))
+        else:
+            import torch
+            torch.cuda.init()
+            _check(lib.aim_setup(C.byref(d), _stream_ptr(stream), C.byref(self._plan)))
+        self.k = kk
+        info = self.info()
+        self.n = int(info["n"])
+        self.dims = tuple(info["dims"])
+        self.n_grid = int(info["n_grid"])
+        self.max_rhs = int(max_rhs)
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_plan", None) and self._plan.value:
+            _check(self._lib.aim_destroy(self._plan))
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- queries ------------------------------------------------------------
+    def info(self) -> dict:
+        pi = PlanInfo()
+        _check(self._lib.aim_plan_query(self._plan, C.byref(pi)))
+        return {
+            "n": pi.n, "n_grid": pi.n_grid, "nnz": pi.nnz, "dims": list(pi.dims),
+            "order": pi.order, "n_freq": pi.n_freq, "max_rhs": pi.max_rhs,
+            "precisions": pi.precisions, "h": pi.h, "origin": list(pi.origin),
+            "setup_seconds": pi.setup_seconds, "spectra_seconds": pi.spectra_seconds,
+            "device_bytes": pi.device_bytes, "n_clusters": pi.n_clusters,
+            "max_cluster": pi.max_cluster,
+        }
+
+    def export_tables(self) -> dict:
+        info = self.info()
+        n, nnz = int(info["n"]), int(info["nnz"])
+        ss = np.empty((3 * n, 3), dtype=np.int32)
+        sl = np.empty((3 * n, 3), dtype=np.float64)
+        rp = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(nnz, dtype=np.int32)
+        val = np.empty(nnz, dtype=np.float64)
+        ns = np.empty(nnz, dtype=np.float64)
+        P = lambda a, t: a.ctypes.data_as(C.POINTER(t))
+        _check(self._lib.aim_export_tables(self._plan, P(ss, C.c_int32), P(sl, C.c_double),
+                                           P(rp, C.c_int64), P(col, C.c_int32),
+                                           P(val, C.c_double), P(ns, C.c_double)))
+        return {"stencil_start": ss, "stencil_local": sl, "rowptr": rp, "col": col,
+                "val": val, "near_static": ns}
+
+    # -- device work ------------------------------------------------------------
+    @staticmethod
+    def _dtype(prec):
+        import torch
+        return torch.complex128 if prec == "c128" else torch.complex64
+
+    def _check_vec(self, t, prec, length, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.dtype != self._dtype(prec):
+            raise TypeError(f"{name} must be {self._dtype(prec)}")
+        if not t.is_contiguous() or t.shape[-1] != length:
+            raise ValueError(f"{name} must be contiguous with last dimension {length}")
+
+    def matvec(self, x, freq_idx=None, prec: str = "c128", out=None, stream=None):
+        """y = A(k_f) x for x of shape [N] or [nrhs, N]."""
+        import torch
+        self._check_vec(x, prec, self.n, "x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        self._check_vec(y, prec, self.n, "out")
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_matvec(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
+                                    C.c_void_p(y.data_ptr()), nrhs, fp, _stream_ptr(stream)))
+        return y
+
+    def apply_stage(self, stage: str, inp, freq_idx=None, prec: str = "c128", stream=None):
+        """One stage of the matvec: 'project' x -> grid, 'convolve' grid ->
+        grid, 'interpolate' grid -> y, 'near' x -> C x.  Grids have shape
+        [nrhs, Nz, Ny, Nx]."""
+        import torch
+        Nx, Ny, Nz = self.dims
+        nrhs = inp.shape[0] if inp.dim() in (2, 4) else 1
+        if stage in ("project", "near"):
+            self._check_vec(inp, prec, self.n, "input")
+        else:
+            self._check_vec(inp.reshape(nrhs, -1), prec, self.n_grid, "input grid")
+        if stage in ("project", "convolve"):
+            out = torch.empty((nrhs, Nz, Ny, Nx), dtype=self._dtype(prec), device=inp.device)
+        else:
+            out = torch.empty((nrhs, self.n), dtype=self._dtype(prec), device=inp.device)
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_apply_stage(self._plan, PREC[prec], STAGE[stage],
+                                         C.c_void_p(inp.data_ptr()), C.c_void_p(out.data_ptr()),
+                                         nrhs, fp, _stream_ptr(stream)))
+        return out
+
+    def excitation(self, kind: str, params, freq_idx=None, stream=None):
+        """Galerkin-tested incident fields, complex128 [nrhs, N]."""
+        import torch
+        pr = np.ascontiguousarray(np.atleast_2d(np.asarray(params, dtype=np.float64)))
+        nrhs, npar = pr.shape
+        b = torch.empty((nrhs, self.n), dtype=torch.complex128, device="cuda")
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_excitation(self._plan, RHS[kind],
+                                        pr.ctypes.data_as(C.POINTER(C.c_double)), npar, nrhs, fp,
+                                        C.c_void_p(b.data_ptr()), _stream_ptr(stream)))
+        return b
+
+    def solve(self, b, x0=None, freq_idx=None, rtol: float = 1e-6, restart: int = 30,
+              max_iter: int = 1000, inner: str = "c128", pc: str = "none",
+              max_refine: int = 20, inner_rtol: float = 0.0, stream=None, raise_on_fail=True):
+        """Batched GMRES on b of shape [nrhs, N] (complex128).  Returns
+        (x, SolveResult)."""
+        import torch
+        b2 = b.reshape(-1, self.n)
+        self._check_vec(b2, "c128", self.n, "b")
+        nrhs = b2.shape[0]
+        x = torch.zeros_like(b2) if x0 is None else x0.reshape(-1, self.n).clone()
+        opts = SolveOpts(rtol, restart, max_iter, max_refine, PREC[inner], PC[pc], inner_rtol)
+        infos = (SolveInfo * nrhs)()
+        _, fp = _freq_arg(freq_idx, nrhs)
+        st = self._lib.aim_solve(self._plan, C.c_void_p(b2.data_ptr()), C.c_void_p(x.data_ptr()),
+                                 nrhs, fp, C.byref(opts), infos, _stream_ptr(stream))
+        if st not in (AIM_OK, 6) or (st == 6 and raise_on_fail):
+            _check(st)
+        res = SolveResult(
+            iters=np.array([i.iters for i in infos]),
+            refinements=np.array([i.refinements for i in infos]),
+            matvecs=np.array([i.matvecs for i in infos]),
+            converged=np.array([bool(i.converged) for i in infos]),
+            rel_resid=np.array([i.rel_resid for i in infos]),
+            seconds=float(infos[0].seconds) if nrhs else 0.0, status=st)
+        return x.reshape(b.shape), res

@@ -1,0 +1,855 @@
+// C ABI of the AIMx library: plan life cycle, the matvec schedule and the
+// batched (flexible) GMRES / iterative-refinement driver.
+//
+// One plan owns the frequency-independent tables of a geometry (quadrature
+// points and stencils, projection bricks, the real CSR correction C, the
+// preconditioner data) and one kernel spectrum per wavenumber of the sweep.
+// Only the spectrum changes with frequency, which is the point of AIMx
+// (Sec. III-A: the static near field is integrated once and reused at every
+// frequency).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "aim_internal.h"
+
+using aim::Error;
+
+namespace {
+thread_local std::string g_last_error;
+
+aim_status fail(aim_status s, const std::string& m) {
+  g_last_error = m;
+  return s;
+}
+
+template <typename F>
+aim_status guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return AIM_OK;
+  } catch (const Error& e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(AIM_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(AIM_ERR_DEVICE, e.what());
+  } catch (...) {
+    return fail(AIM_ERR_DEVICE, "unknown error");
+  }
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+struct aim_plan_s {
+  aim::HostTables t;
+  aim::GridShape g{};
+  int nfreq = 0;
+  std::vector<double> k;
+  uint32_t prec = 0;
+  int max_rhs = 1;
+  aim_alloc_fn alloc = nullptr;
+  aim_free_fn free_fn = nullptr;
+  void* actx = nullptr;
+  hipStream_t setup_stream = nullptr;
+  std::vector<std::pair<void*, size_t>> owned;
+  int64_t device_bytes = 0;
+  double spectra_seconds = 0.0;
+  bool host_only = false;
+
+  // device tables
+  int32_t* d_packed = nullptr;
+  double* d_loc64 = nullptr;
+  double* d_w64 = nullptr;
+  float* d_loc32 = nullptr;
+  float* d_w32 = nullptr;
+  double* d_qpxyz = nullptr;
+  int32_t* d_bptr = nullptr;
+  int32_t* d_blist = nullptr;
+  int32_t* d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  double* d_val64 = nullptr;
+  float* d_val32 = nullptr;
+  double* d_dinv = nullptr;
+  int32_t* d_clptr = nullptr;
+  int32_t* d_clperm = nullptr;
+  int64_t* d_clblk = nullptr;
+  double* d_clinv = nullptr;
+  int ncl = 0, maxcl = 0;
+  void* d_spec64 = nullptr;
+  void* d_spec32 = nullptr;
+  void* d_tw64[3] = {nullptr, nullptr, nullptr};
+  void* d_tw32[3] = {nullptr, nullptr, nullptr};
+  double* d_k = nullptr;
+  void* d_work[2] = {nullptr, nullptr};  // [prec] 6 Ng per rhs
+  void* d_grid[2] = {nullptr, nullptr};  // [prec] Ng per rhs
+  int32_t* d_rhs_freq = nullptr;          // [max_rhs]
+  int32_t* h_rhs_freq = nullptr;          // pinned staging
+  std::vector<int32_t> cur_freq;          // what d_rhs_freq holds
+
+  // solver workspace (grown on demand)
+  struct Solver {
+    int nrhs = 0, m = 0;
+    int64_t n = 0;
+    void *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *bp = nullptr,
+         *xp = nullptr, *h = nullptr, *h2 = nullptr, *y = nullptr, *partial = nullptr,
+         *c64a = nullptr, *c64b = nullptr;
+    double* nrm = nullptr;
+    int32_t* idx = nullptr;
+    int32_t* freq = nullptr;
+    double2* h_host = nullptr;  // pinned
+    double* nrm_host = nullptr;
+  } sv;
+
+  void* dalloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (alloc) {
+      p = alloc(bytes, s, actx);
+      AIM_REQUIRE(p != nullptr, AIM_ERR_OOM, "device allocator returned NULL");
+    } else {
+      const hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(AIM_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      }
+    }
+    owned.push_back({p, bytes});
+    device_bytes += int64_t(bytes);
+    return p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* p = static_cast<T*>(dalloc(v.size() * sizeof(T), s));
+    if (!v.empty()) AIM_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  ~aim_plan_s() {
+    if (host_only) return;
+    if (setup_stream) (void)hipStreamSynchronize(setup_stream);
+    (void)hipDeviceSynchronize();
+    for (auto& o : owned) {
+      if (alloc)
+        free_fn(o.first, nullptr, actx);
+      else
+        (void)hipFree(o.first);
+    }
+    if (h_rhs_freq) (void)hipHostFree(h_rhs_freq);
+    if (sv.h_host) (void)hipHostFree(sv.h_host);
+    if (sv.nrm_host) (void)hipHostFree(sv.nrm_host);
+  }
+};
+
+namespace {
+
+aim::QpDevice qp_dev(aim_plan p, aim_precision prec) {
+  aim::QpDevice q;
+  q.packed_start = p->d_packed;
+  q.local = prec == AIM_C128 ? static_cast<const void*>(p->d_loc64) : p->d_loc32;
+  q.weight = prec == AIM_C128 ? static_cast<const void*>(p->d_w64) : p->d_w32;
+  q.nq = 3 * p->t.N;
+  return q;
+}
+
+aim::CsrDevice csr_dev(aim_plan p, aim_precision prec) {
+  aim::CsrDevice c;
+  c.rowptr = p->d_rowptr;
+  c.col = p->d_col;
+  c.val = prec == AIM_C128 ? static_cast<const void*>(p->d_val64) : p->d_val32;
+  c.n = p->t.N;
+  return c;
+}
+
+void check_prec(aim_plan p, aim_precision prec) {
+  AIM_REQUIRE(!p->host_only, AIM_ERR_STATE, "host-only plan has no device data");
+  AIM_REQUIRE(prec == AIM_C128 || prec == AIM_C64, AIM_ERR_INVALID_ARG, "bad precision");
+  AIM_REQUIRE(p->prec & (1u << prec), AIM_ERR_STATE, "precision not built in this plan");
+}
+
+// Makes d_rhs_freq hold freq (uploads only when it changed).
+const int32_t* set_freq(aim_plan p, const int32_t* freq_host, int nrhs, hipStream_t s) {
+  AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+              "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+  std::vector<int32_t> want(nrhs, 0);
+  if (freq_host)
+    for (int r = 0; r < nrhs; ++r) {
+      AIM_REQUIRE(freq_host[r] >= 0 && freq_host[r] < p->nfreq, AIM_ERR_INVALID_ARG,
+                  "frequency index out of range");
+      want[r] = freq_host[r];
+    }
+  bool same = int(p->cur_freq.size()) >= nrhs;
+  for (int r = 0; same && r < nrhs; ++r) same = p->cur_freq[r] == want[r];
+  if (!same) {
+    AIM_HIP(hipStreamSynchronize(s));  // staging buffer may still feed a copy
+    std::memcpy(p->h_rhs_freq, want.data(), nrhs * sizeof(int32_t));
+    AIM_HIP(hipMemcpyAsync(p->d_rhs_freq, p->h_rhs_freq, nrhs * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    p->cur_freq = want;
+  }
+  return p->d_rhs_freq;
+}
+
+template <typename T>
+void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
+                 const int32_t* dfreq, hipStream_t s) {
+  const int pi = int(prec);
+  void* grid = p->d_grid[pi];
+  const void* spec = prec == AIM_C128 ? p->d_spec64 : p->d_spec32;
+  void* const* tw = prec == AIM_C128 ? p->d_tw64 : p->d_tw32;
+  aim::launch_project<T>(p->g, p->t.order, qp_dev(p, prec), p->d_bptr, p->d_blist, p->t.brick,
+                         p->t.nbrick, x, p->t.N, grid, nrhs, s);
+  aim::launch_convolve<T>(p->g, grid, p->d_work[pi], grid, spec, dfreq, nrhs, tw, s);
+  aim::launch_interp_near<T>(p->g, p->t.order, qp_dev(p, prec), csr_dev(p, prec), grid, x, y,
+                             nrhs, true, true, s);
+}
+
+void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
+                const int32_t* dfreq, hipStream_t s) {
+  if (prec == AIM_C128)
+    matvec_impl<double>(p, prec, x, y, nrhs, dfreq, s);
+  else
+    matvec_impl<float>(p, prec, x, y, nrhs, dfreq, s);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* aim_last_error(void) { return g_last_error.c_str(); }
+const char* aim_version(void) { return "aimx-gfx950 0.1"; }
+
+static void validate_desc(const aim_setup_desc& d) {
+    AIM_REQUIRE(d.n_freq >= 1 && d.k != nullptr, AIM_ERR_INVALID_ARG, "need n_freq >= 1 wavenumbers");
+    for (int f = 0; f < d.n_freq; ++f)
+      AIM_REQUIRE(std::isfinite(d.k[f]) && d.k[f] > 0.0, AIM_ERR_INVALID_ARG,
+                  "wavenumbers must be positive and finite");
+    AIM_REQUIRE(d.precisions != 0 && (d.precisions & ~3u) == 0, AIM_ERR_INVALID_ARG,
+                "precisions must be a non-empty subset of {C128, C64}");
+    AIM_REQUIRE(d.max_rhs >= 1 && d.max_rhs <= 65535, AIM_ERR_INVALID_ARG, "max_rhs out of range");
+    AIM_REQUIRE((d.alloc == nullptr) == (d.free == nullptr), AIM_ERR_INVALID_ARG,
+                "alloc and free must be given together");
+}
+
+aim_status aim_setup_host(const aim_setup_desc* desc, aim_plan* out) {
+  if (!desc || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  std::unique_ptr<aim_plan_s> p(new aim_plan_s());
+  p->host_only = true;
+  const aim_status st = guarded([&] {
+    validate_desc(*desc);
+    aim::build_host_tables(*desc, p->t);
+    p->nfreq = desc->n_freq;
+    p->k.assign(desc->k, desc->k + desc->n_freq);
+    p->prec = desc->precisions;
+    p->max_rhs = desc->max_rhs;
+    for (int a = 0; a < 3; ++a) {
+      p->g.N[a] = p->t.dims[a];
+      p->g.M[a] = 2 * p->t.dims[a];
+    }
+    p->g.Ng = int64_t(p->g.N[0]) * p->g.N[1] * p->g.N[2];
+    p->g.Nfold = int64_t(p->g.N[0] + 1) * (p->g.N[1] + 1) * (p->g.N[2] + 1);
+    p->ncl = int(p->t.cl_ptr.size()) - 1;
+    for (int c = 0; c < p->ncl; ++c)
+      p->maxcl = std::max(p->maxcl, p->t.cl_ptr[c + 1] - p->t.cl_ptr[c]);
+  });
+  if (st != AIM_OK) return st;
+  *out = p.release();
+  return AIM_OK;
+}
+
+aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out) {
+  if (!desc || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  std::unique_ptr<aim_plan_s> p(new aim_plan_s());
+  const aim_status st = guarded([&] {
+    const aim_setup_desc& d = *desc;
+    validate_desc(d);
+    const double t0 = now_s();
+    // host work first: every validation happens before any device call
+    aim::build_host_tables(d, p->t);
+    p->nfreq = d.n_freq;
+    p->k.assign(d.k, d.k + d.n_freq);
+    p->prec = d.precisions;
+    p->max_rhs = d.max_rhs;
+    p->alloc = d.alloc;
+    p->free_fn = d.free;
+    p->actx = d.alloc_ctx;
+    auto& g = p->g;
+    for (int a = 0; a < 3; ++a) {
+      g.N[a] = p->t.dims[a];
+      g.M[a] = 2 * p->t.dims[a];
+    }
+    g.Ng = int64_t(g.N[0]) * g.N[1] * g.N[2];
+    g.Nfold = int64_t(g.N[0] + 1) * (g.N[1] + 1) * (g.N[2] + 1);
+
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    p->setup_stream = s;
+    const auto& t = p->t;
+    const int64_t N = t.N, Nq = 3 * N;
+    // quadrature-point records
+    std::vector<int32_t> packed(Nq);
+    std::vector<double> loc(3 * Nq), w(Nq);
+    for (int64_t q = 0; q < Nq; ++q) {
+      packed[q] = t.qp_start[3 * q] | (t.qp_start[3 * q + 1] << 10) | (t.qp_start[3 * q + 2] << 20);
+      for (int a = 0; a < 3; ++a) loc[a * Nq + q] = t.qp_local[3 * q + a];
+      w[q] = t.qp_w[q];
+    }
+    p->d_packed = p->upload(packed, s);
+    p->d_qpxyz = p->upload(t.qp_xyz, s);
+    p->d_w64 = p->upload(w, s);  // always kept: excitation needs it
+    if (p->prec & (1u << AIM_C128)) p->d_loc64 = p->upload(loc, s);
+    if (p->prec & (1u << AIM_C64)) {
+      std::vector<float> l32(loc.begin(), loc.end()), w32(w.begin(), w.end());
+      p->d_loc32 = p->upload(l32, s);
+      p->d_w32 = p->upload(w32, s);
+    }
+    p->d_bptr = p->upload(t.brick_ptr, s);
+    p->d_blist = p->upload(t.brick_qp, s);
+    std::vector<int32_t> rp32(t.rowptr.begin(), t.rowptr.end());
+    p->d_rowptr = p->upload(rp32, s);
+    p->d_col = p->upload(t.col, s);
+    if (p->prec & (1u << AIM_C128)) p->d_val64 = p->upload(t.corr, s);
+    if (p->prec & (1u << AIM_C64)) {
+      std::vector<float> v32(t.corr.begin(), t.corr.end());
+      p->d_val32 = p->upload(v32, s);
+    }
+    // preconditioners (complex128 solver side)
+    {
+      std::vector<double> dinv(N);
+      for (int64_t i = 0; i < N; ++i) {
+        double dv = 0.0;
+        for (int64_t q = t.rowptr[i]; q < t.rowptr[i + 1]; ++q)
+          if (t.col[q] == i) dv = t.near_static[q];
+        AIM_REQUIRE(dv != 0.0, AIM_ERR_GEOMETRY, "zero static self term");
+        dinv[i] = 1.0 / dv;
+      }
+      p->d_dinv = p->upload(dinv, s);
+      p->ncl = int(t.cl_ptr.size()) - 1;
+      for (int c = 0; c < p->ncl; ++c) p->maxcl = std::max(p->maxcl, t.cl_ptr[c + 1] - t.cl_ptr[c]);
+      p->d_clptr = p->upload(t.cl_ptr, s);
+      p->d_clperm = p->upload(t.cl_perm, s);
+      p->d_clblk = p->upload(t.cl_blk, s);
+      p->d_clinv = p->upload(t.cl_inv, s);
+    }
+    p->d_k = p->upload(p->k, s);
+    // twiddles per axis
+    for (int a = 0; a < 3; ++a) {
+      const std::vector<double> tw = aim::twiddles64(g.M[a]);
+      p->d_tw64[a] = p->upload(tw, s);
+      std::vector<float> tw32(tw.begin(), tw.end());
+      p->d_tw32[a] = p->upload(tw32, s);
+    }
+    // work buffers
+    for (int pi = 0; pi < 2; ++pi) {
+      if (!(p->prec & (1u << pi))) continue;
+      const size_t cb = pi == 0 ? 16 : 8;
+      p->d_work[pi] = p->dalloc(size_t(6) * g.Ng * cb * p->max_rhs, s);
+      p->d_grid[pi] = p->dalloc(size_t(g.Ng) * cb * p->max_rhs, s);
+    }
+    p->d_rhs_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * p->max_rhs, s));
+    AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_rhs_freq), sizeof(int32_t) * p->max_rhs, 0));
+    // kernel spectra: one per wavenumber, folded (complex128 + complex64)
+    const double ts = now_s();
+    p->d_spec64 = p->dalloc(size_t(g.Nfold) * 16 * p->nfreq, s);
+    if (p->prec & (1u << AIM_C64)) p->d_spec32 = p->dalloc(size_t(g.Nfold) * 8 * p->nfreq, s);
+    {
+      void* full = nullptr;
+      const size_t fb = size_t(8) * g.Ng * 16;
+      AIM_HIP(hipMalloc(&full, fb));
+      try {
+        for (int f = 0; f < p->nfreq; ++f)
+          aim::launch_spectrum(g, p->k[f], t.h, full,
+                               static_cast<char*>(p->d_spec64) + size_t(f) * g.Nfold * 16,
+                               p->d_spec32 ? static_cast<char*>(p->d_spec32) + size_t(f) * g.Nfold * 8
+                                           : nullptr,
+                               p->d_tw64, s);
+        AIM_HIP(hipStreamSynchronize(s));
+      } catch (...) {
+        (void)hipFree(full);
+        throw;
+      }
+      AIM_HIP(hipFree(full));
+    }
+    p->spectra_seconds = now_s() - ts;
+    AIM_HIP(hipStreamSynchronize(s));
+    p->t.setup_seconds = now_s() - t0;
+  });
+  if (st != AIM_OK) return st;
+  *out = p.release();
+  return AIM_OK;
+}
+
+aim_status aim_destroy(aim_plan plan) {
+  return guarded([&] { delete plan; });
+}
+
+aim_status aim_plan_query(aim_plan p, aim_plan_info* info) {
+  if (!p || !info) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    aim_plan_info& o = *info;
+    o.n = p->t.N;
+    o.n_grid = p->g.Ng;
+    o.nnz = int64_t(p->t.col.size());
+    for (int a = 0; a < 3; ++a) {
+      o.dims[a] = p->g.N[a];
+      o.origin[a] = p->t.origin[a];
+    }
+    o.order = p->t.order;
+    o.n_freq = p->nfreq;
+    o.max_rhs = p->max_rhs;
+    o.precisions = p->prec;
+    o.h = p->t.h;
+    o.setup_seconds = p->t.setup_seconds;
+    o.spectra_seconds = p->spectra_seconds;
+    o.device_bytes = p->device_bytes;
+    o.n_clusters = p->ncl;
+    o.max_cluster = p->maxcl;
+  });
+}
+
+aim_status aim_matvec(aim_plan p, aim_precision prec, const void* x, void* y, int32_t nrhs,
+                      const int32_t* freq_idx_host, void* hip_stream) {
+  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    check_prec(p, prec);
+    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    matvec_any(p, prec, x, y, nrhs, df, s);
+  });
+}
+
+aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, const void* in,
+                           void* out, int32_t nrhs, const int32_t* freq_idx_host,
+                           void* hip_stream) {
+  if (!p || !in || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    check_prec(p, prec);
+    AIM_REQUIRE(in != out, AIM_ERR_INVALID_ARG, "in and out must not overlap");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    const int pi = int(prec);
+    const bool d = prec == AIM_C128;
+    switch (stage) {
+      case AIM_STAGE_PROJECT:
+        if (d)
+          aim::launch_project<double>(p->g, p->t.order, qp_dev(p, prec), p->d_bptr, p->d_blist,
+                                      p->t.brick, p->t.nbrick, in, p->t.N, out, nrhs, s);
+        else
+          aim::launch_project<float>(p->g, p->t.order, qp_dev(p, prec), p->d_bptr, p->d_blist,
+                                     p->t.brick, p->t.nbrick, in, p->t.N, out, nrhs, s);
+        break;
+      case AIM_STAGE_CONVOLVE:
+        if (d)
+          aim::launch_convolve<double>(p->g, in, p->d_work[pi], out, p->d_spec64, df, nrhs,
+                                       p->d_tw64, s);
+        else
+          aim::launch_convolve<float>(p->g, in, p->d_work[pi], out, p->d_spec32, df, nrhs,
+                                      p->d_tw32, s);
+        break;
+      case AIM_STAGE_INTERPOLATE:
+      case AIM_STAGE_NEAR: {
+        const bool interp = stage == AIM_STAGE_INTERPOLATE;
+        if (d)
+          aim::launch_interp_near<double>(p->g, p->t.order, qp_dev(p, prec), csr_dev(p, prec),
+                                          interp ? in : nullptr, interp ? nullptr : in, out, nrhs,
+                                          interp, !interp, s);
+        else
+          aim::launch_interp_near<float>(p->g, p->t.order, qp_dev(p, prec), csr_dev(p, prec),
+                                         interp ? in : nullptr, interp ? nullptr : in, out, nrhs,
+                                         interp, !interp, s);
+        break;
+      }
+      default:
+        throw Error(AIM_ERR_INVALID_ARG, "unknown stage");
+    }
+  });
+}
+
+aim_status aim_excitation(aim_plan p, aim_rhs_kind kind, const double* params, int32_t n_params,
+                          int32_t nrhs, const int32_t* freq_idx_host, void* b, void* hip_stream) {
+  if (!p || !params || !b) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    AIM_REQUIRE(!p->host_only, AIM_ERR_STATE, "host-only plan has no device data");
+    AIM_REQUIRE(kind == AIM_RHS_PLANE_WAVE || kind == AIM_RHS_GAUSSIAN_PATCH, AIM_ERR_INVALID_ARG,
+                "unknown excitation kind");
+    const int need = kind == AIM_RHS_PLANE_WAVE ? 3 : 4;
+    AIM_REQUIRE(n_params == need, AIM_ERR_INVALID_ARG, "wrong number of excitation parameters");
+    for (int r = 0; r < nrhs * n_params && r >= 0; ++r)
+      AIM_REQUIRE(std::isfinite(params[r]), AIM_ERR_INVALID_ARG, "non-finite excitation parameter");
+    if (kind == AIM_RHS_GAUSSIAN_PATCH)
+      for (int r = 0; r < nrhs; ++r)
+        AIM_REQUIRE(params[r * 4 + 3] > 0.0, AIM_ERR_INVALID_ARG, "patch width must be positive");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    std::vector<double> pr(params, params + size_t(nrhs) * n_params);
+    if (kind == AIM_RHS_PLANE_WAVE)
+      for (int r = 0; r < nrhs; ++r) {
+        double* d3 = &pr[3 * r];
+        const double nn = std::sqrt(d3[0] * d3[0] + d3[1] * d3[1] + d3[2] * d3[2]);
+        AIM_REQUIRE(nn > 0.0, AIM_ERR_INVALID_ARG, "zero plane-wave direction");
+        for (int a = 0; a < 3; ++a) d3[a] /= nn;
+      }
+    double* dpr = nullptr;
+    AIM_HIP(hipMalloc(&dpr, pr.size() * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(dpr, pr.data(), pr.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      aim::launch_excitation(int(kind), p->d_qpxyz, p->d_w64, p->t.N, dpr, n_params, p->d_k, df,
+                             nrhs, b, s);
+      e = hipStreamSynchronize(s);
+    }
+    (void)hipFree(dpr);
+    AIM_HIP(e);
+  });
+}
+
+aim_status aim_export_tables(aim_plan p, int32_t* stencil_start, double* stencil_local,
+                             int64_t* rowptr, int32_t* col, double* val, double* near_static) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    const auto& t = p->t;
+    if (stencil_start) std::copy(t.qp_start.begin(), t.qp_start.end(), stencil_start);
+    if (stencil_local) std::copy(t.qp_local.begin(), t.qp_local.end(), stencil_local);
+    if (rowptr) std::copy(t.rowptr.begin(), t.rowptr.end(), rowptr);
+    if (col) std::copy(t.col.begin(), t.col.end(), col);
+    if (val) std::copy(t.corr.begin(), t.corr.end(), val);
+    if (near_static) std::copy(t.near_static.begin(), t.near_static.end(), near_static);
+  });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// batched GMRES / FGMRES with right preconditioning (complex128 Arnoldi, CGS2)
+// ===========================================================================
+namespace {
+
+using cplx = std::complex<double>;
+
+void ensure_solver(aim_plan p, int nrhs, int m, hipStream_t s) {
+  auto& w = p->sv;
+  const int64_t n = p->t.N;
+  if (w.nrhs >= nrhs && w.m >= m && w.n == n) return;
+  // buffers are never freed individually: the plan owns them until destroy
+  const int R = std::max(nrhs, w.nrhs), M = std::max(m, w.m);
+  const size_t vec = size_t(n) * 16;
+  w.V = p->dalloc(vec * R * (M + 1), s);
+  w.Z = p->dalloc(vec * R * M, s);
+  w.w = p->dalloc(vec * R, s);
+  w.r = p->dalloc(vec * R, s);
+  w.d = p->dalloc(vec * R, s);
+  w.bp = p->dalloc(vec * R, s);
+  w.xp = p->dalloc(vec * R, s);
+  w.h = p->dalloc(size_t(16) * R * (M + 1), s);
+  w.h2 = p->dalloc(size_t(16) * R * (M + 1), s);
+  w.y = p->dalloc(size_t(16) * R * (M + 1), s);
+  const int64_t nchunk = (n + 4095) / 4096;
+  w.partial = p->dalloc(size_t(16) * R * (M + 1) * nchunk, s);
+  w.nrm = static_cast<double*>(p->dalloc(sizeof(double) * R, s));
+  w.idx = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * R, s));
+  w.freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * R, s));
+  if (p->prec & (1u << AIM_C64)) {
+    w.c64a = p->dalloc(size_t(n) * 8 * R, s);
+    w.c64b = p->dalloc(size_t(n) * 8 * R, s);
+  }
+  if (w.h_host) (void)hipHostFree(w.h_host);
+  if (w.nrm_host) (void)hipHostFree(w.nrm_host);
+  // two Gram-Schmidt passes of up to M+1 coefficients per system
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.h_host), sizeof(double2) * 2 * R * (M + 1), 0));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.nrm_host), sizeof(double) * R * 2, 0));
+  w.nrhs = R;
+  w.m = M;
+  w.n = n;
+}
+
+// Operator application used by the Krylov loop: y = A(k_f) x in the requested
+// precision on complex128 vectors (complex64 matvec through casts).
+void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, const int32_t* dfreq,
+             hipStream_t s) {
+  if (prec == AIM_C128) {
+    matvec_any(p, AIM_C128, x, y, nrhs, dfreq, s);
+  } else {
+    const int64_t cnt = p->t.N * int64_t(nrhs);
+    aim::launch_cast_c128_to_c64(x, p->sv.c64a, cnt, s);
+    matvec_any(p, AIM_C64, p->sv.c64a, p->sv.c64b, nrhs, dfreq, s);
+    aim::launch_cast_c64_to_c128(p->sv.c64b, y, cnt, s);
+  }
+}
+
+void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hipStream_t s) {
+  const int64_t n = p->t.N;
+  switch (pc) {
+    case AIM_PC_NONE:
+      AIM_HIP(hipMemcpyAsync(z, v, size_t(n) * 16 * nrhs, hipMemcpyDeviceToDevice, s));
+      break;
+    case AIM_PC_DIAG:
+      aim::launch_diag_pc(v, p->d_dinv, z, n, nrhs, s);
+      break;
+    case AIM_PC_NEARBLOCK:
+      aim::launch_block_pc(v, z, p->d_clptr, p->d_clperm, p->d_clblk, p->d_clinv, p->ncl, p->maxcl,
+                           n, nrhs, s);
+      break;
+    default:
+      throw Error(AIM_ERR_STATE, "preconditioner not available");
+  }
+}
+
+void norms_host(aim_plan p, const void* v, int nrhs, hipStream_t s, std::vector<double>& out) {
+  aim::launch_norms(v, p->t.N, nrhs, p->sv.partial, p->sv.nrm, s);
+  AIM_HIP(hipMemcpyAsync(p->sv.nrm_host, p->sv.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  AIM_HIP(hipStreamSynchronize(s));
+  out.assign(p->sv.nrm_host, p->sv.nrm_host + nrhs);
+}
+
+struct CycleStats {
+  std::vector<int> iters;  // Krylov steps per system
+  int matvecs = 0;
+};
+
+// Restarted right-preconditioned GMRES on a packed batch: solves A x = b for
+// nrhs systems in lock step (x holds the initial guess).  Each system stops
+// extending its Krylov basis once its residual estimate is below tol * scale;
+// the true residual decides convergence at every restart.  Returns per-system
+// true relative residual (w.r.t. scale) in rel.
+void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, void* x, int nrhs,
+                 const int32_t* dfreq, const std::vector<double>& scale, double tol, int m,
+                 int max_iter, bool x_is_zero, hipStream_t s, CycleStats& st,
+                 std::vector<double>& rel) {
+  auto& w = p->sv;
+  const int64_t n = p->t.N;
+  const size_t vec = size_t(n) * 16;
+  // basis layout [i][r][n]: the i-th vectors of all systems are contiguous
+  const int64_t si = nrhs, sr = 1;
+  std::vector<int>& active_iters = st.iters;
+  active_iters.assign(nrhs, 0);
+  rel.assign(nrhs, 1.0);
+  std::vector<double> beta(nrhs);
+  bool first = true;
+  for (;;) {
+    // r = b - A x (skipped when x is known to be zero)
+    if (first && x_is_zero) {
+      AIM_HIP(hipMemcpyAsync(w.r, b, vec * nrhs, hipMemcpyDeviceToDevice, s));
+    } else {
+      apply_A(p, prec, x, w.r, nrhs, dfreq, s);
+      st.matvecs++;
+      aim::launch_residual(b, w.r, n * int64_t(nrhs), s);
+    }
+    first = false;
+    norms_host(p, w.r, nrhs, s, beta);
+    bool all_done = true;
+    int maxit_left = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      rel[r] = beta[r] / scale[r];
+      if (!std::isfinite(rel[r])) throw Error(AIM_ERR_BREAKDOWN, "non-finite residual");
+      if (rel[r] > tol && active_iters[r] < max_iter) all_done = false;
+      maxit_left = std::max(maxit_left, max_iter - active_iters[r]);
+    }
+    if (all_done) return;
+    const int mm = std::min(m, maxit_left);
+    // V_0 = r / beta
+    aim::launch_scale_inv(w.r, w.nrm, w.V, n, nrhs, n, s);
+    // Hessenberg per system on the host, Givens rotations
+    std::vector<std::vector<cplx>> H(nrhs, std::vector<cplx>((mm + 1) * mm, 0.0));
+    std::vector<std::vector<cplx>> cs(nrhs, std::vector<cplx>(mm)), sn(nrhs, std::vector<cplx>(mm));
+    std::vector<std::vector<cplx>> g(nrhs, std::vector<cplx>(mm + 1, 0.0));
+    std::vector<int> len(nrhs, 0);
+    std::vector<char> frozen(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) {
+      g[r][0] = beta[r];
+      frozen[r] = (rel[r] <= tol || active_iters[r] >= max_iter) ? 1 : 0;
+    }
+    int j = 0;
+    for (; j < mm; ++j) {
+      void* Vj = static_cast<char*>(w.V) + size_t(j) * nrhs * vec;
+      void* Zj = static_cast<char*>(w.Z) + size_t(j) * nrhs * vec;
+      apply_M(p, pc, Vj, Zj, nrhs, s);  // z_j = M(v_j)
+      apply_A(p, prec, Zj, w.d, nrhs, dfreq, s);  // w.d = A z_j
+      st.matvecs++;
+      // classical Gram-Schmidt, twice
+      aim::launch_block_dot(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h, s);
+      aim::launch_block_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.h, j + 1, s);
+      aim::launch_block_dot(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h2, s);
+      aim::launch_block_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.h2, j + 1, s);
+      aim::launch_norms(w.d, n, nrhs, w.partial, w.nrm, s);
+      aim::launch_scale_inv(w.d, w.nrm, static_cast<char*>(w.V) + size_t(j + 1) * nrhs * vec, n,
+                            nrhs, n, s);
+      AIM_HIP(hipMemcpyAsync(w.h_host, w.h, sizeof(double2) * nrhs * (j + 1), hipMemcpyDeviceToHost, s));
+      AIM_HIP(hipMemcpyAsync(w.h_host + nrhs * (j + 1), w.h2, sizeof(double2) * nrhs * (j + 1),
+                             hipMemcpyDeviceToHost, s));
+      AIM_HIP(hipMemcpyAsync(w.nrm_host, w.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+      AIM_HIP(hipStreamSynchronize(s));
+      bool all_frozen = true;
+      for (int r = 0; r < nrhs; ++r) {
+        if (frozen[r]) continue;
+        auto& Hr = H[r];
+        auto Hat = [&](int i, int c) -> cplx& { return Hr[i * mm + c]; };
+        for (int i = 0; i <= j; ++i) {
+          const double2 a = w.h_host[r * (j + 1) + i];
+          const double2 c = w.h_host[nrhs * (j + 1) + r * (j + 1) + i];
+          Hat(i, j) = cplx(a.x + c.x, a.y + c.y);
+        }
+        const double hn = w.nrm_host[r];
+        if (!std::isfinite(hn)) throw Error(AIM_ERR_BREAKDOWN, "non-finite Arnoldi norm");
+        Hat(j + 1, j) = hn;
+        for (int i = 0; i < j; ++i) {
+          const cplx tmp = cs[r][i] * Hat(i, j) + sn[r][i] * Hat(i + 1, j);
+          Hat(i + 1, j) = -std::conj(sn[r][i]) * Hat(i, j) + std::conj(cs[r][i]) * Hat(i + 1, j);
+          Hat(i, j) = tmp;
+        }
+        const cplx a = Hat(j, j), bb = Hat(j + 1, j);
+        const double den = std::sqrt(std::norm(a) + std::norm(bb));
+        if (den == 0.0) {
+          frozen[r] = 1;
+          continue;
+        }
+        if (std::abs(a) == 0.0) {
+          cs[r][j] = 0.0;
+          sn[r][j] = 1.0;
+        } else {
+          cs[r][j] = std::abs(a) / den;
+          sn[r][j] = (a / std::abs(a)) * std::conj(bb) / den;
+        }
+        Hat(j, j) = cs[r][j] * a + sn[r][j] * bb;
+        Hat(j + 1, j) = 0.0;
+        g[r][j + 1] = -std::conj(sn[r][j]) * g[r][j];
+        g[r][j] = cs[r][j] * g[r][j];
+        len[r] = j + 1;
+        active_iters[r]++;
+        const double est = std::abs(g[r][j + 1]) / scale[r];
+        if (est <= tol || hn == 0.0 || active_iters[r] >= max_iter) frozen[r] = 1;
+        if (!frozen[r]) all_frozen = false;
+      }
+      if (all_frozen) {
+        ++j;
+        break;
+      }
+    }
+    // y = H^{-1} g per system, then x += Z y
+    const int nv = *std::max_element(len.begin(), len.end());
+    if (nv > 0) {
+      std::vector<double2> yh(size_t(nrhs) * m);
+      for (auto& v : yh) v.x = v.y = 0.0;
+      for (int r = 0; r < nrhs; ++r) {
+        const int L = len[r];
+        std::vector<cplx> yv(L);
+        for (int i = L - 1; i >= 0; --i) {
+          cplx acc = g[r][i];
+          for (int c = i + 1; c < L; ++c) acc -= H[r][i * mm + c] * yv[c];
+          yv[i] = acc / H[r][i * mm + i];
+        }
+        for (int i = 0; i < L; ++i) {
+          yh[size_t(r) * m + i].x = yv[i].real();
+          yh[size_t(r) * m + i].y = yv[i].imag();
+        }
+      }
+      AIM_HIP(hipMemcpyAsync(w.y, yh.data(), sizeof(double2) * yh.size(), hipMemcpyHostToDevice, s));
+      aim::launch_combine(w.Z, si, sr, w.y, m, nv, x, n, nrhs, s);
+      AIM_HIP(hipStreamSynchronize(s));  // yh is pageable host memory
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs,
+                                const int32_t* freq_idx_host, const aim_solve_opts* opts,
+                                aim_solve_info* info, void* hip_stream) {
+  if (!p || !b || !x || !opts || !info) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  aim_status result = AIM_OK;
+  const aim_status st = guarded([&] {
+    const aim_solve_opts& o = *opts;
+    AIM_REQUIRE(o.rtol > 0.0 && std::isfinite(o.rtol), AIM_ERR_INVALID_ARG, "rtol must be positive");
+    AIM_REQUIRE(o.restart >= 1 && o.restart <= 200, AIM_ERR_INVALID_ARG, "restart must be in 1..200");
+    AIM_REQUIRE(o.max_iter >= 1, AIM_ERR_INVALID_ARG, "max_iter must be >= 1");
+    AIM_REQUIRE(o.pc >= AIM_PC_NONE && o.pc <= AIM_PC_NEARBLOCK, AIM_ERR_STATE,
+                "preconditioner not available in this build");
+    check_prec(p, AIM_C128);
+    check_prec(p, o.inner);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const double t0 = now_s();
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    ensure_solver(p, nrhs, o.restart, s);
+    auto& w = p->sv;
+    const int64_t n = p->t.N;
+    const size_t vec = size_t(n) * 16;
+    std::vector<double> bn;
+    norms_host(p, b, nrhs, s, bn);
+    for (int r = 0; r < nrhs; ++r)
+      AIM_REQUIRE(std::isfinite(bn[r]), AIM_ERR_BREAKDOWN, "non-finite right-hand side");
+    std::vector<double> scale(nrhs);
+    for (int r = 0; r < nrhs; ++r) scale[r] = bn[r] > 0.0 ? bn[r] : 1.0;
+    std::vector<aim_solve_info> inf(nrhs);
+    for (auto& v : inf) std::memset(&v, 0, sizeof(v));
+    CycleStats cst;
+    std::vector<double> rel;
+    if (o.inner == AIM_C128) {
+      AIM_HIP(hipMemcpyAsync(w.xp, x, vec * nrhs, hipMemcpyDeviceToDevice, s));
+      gmres_batch(p, AIM_C128, o.pc, b, w.xp, nrhs, df, scale, o.rtol, o.restart, o.max_iter,
+                  false, s, cst, rel);
+      AIM_HIP(hipMemcpyAsync(x, w.xp, vec * nrhs, hipMemcpyDeviceToDevice, s));
+      for (int r = 0; r < nrhs; ++r) {
+        inf[r].matvecs = cst.matvecs;
+        inf[r].iters = cst.iters[r];
+      }
+    } else {
+      // complex128 iterative refinement around a complex64-matvec GMRES
+      const double inner_tol = o.inner_rtol > 0.0 ? o.inner_rtol : 1e-4;
+      int refine = 0;
+      std::vector<double> rn;
+      for (;;) {
+        apply_A(p, AIM_C128, x, w.bp, nrhs, df, s);  // bp = A x (complex128)
+        cst.matvecs++;
+        aim::launch_residual(b, w.bp, n * int64_t(nrhs), s);  // bp = b - A x
+        norms_host(p, w.bp, nrhs, s, rn);
+        bool done = true;
+        rel.assign(nrhs, 0.0);
+        for (int r = 0; r < nrhs; ++r) {
+          rel[r] = rn[r] / scale[r];
+          if (!std::isfinite(rel[r])) throw Error(AIM_ERR_BREAKDOWN, "non-finite residual");
+          if (rel[r] > o.rtol) done = false;
+        }
+        if (done || refine >= std::max(0, o.max_refine)) break;
+        // inner solve A d = r with scale ||r|| (systems already converged get d = 0)
+        std::vector<double> iscale(nrhs);
+        for (int r = 0; r < nrhs; ++r) iscale[r] = rn[r] > 0.0 ? rn[r] : 1.0;
+        AIM_HIP(hipMemsetAsync(w.xp, 0, vec * nrhs, s));
+        std::vector<double> irel;
+        CycleStats ist;
+        gmres_batch(p, AIM_C64, o.pc, w.bp, w.xp, nrhs, df, iscale, inner_tol, o.restart,
+                    o.max_iter, true, s, ist, irel);
+        cst.matvecs += ist.matvecs;
+        for (int r = 0; r < nrhs; ++r) inf[r].iters += ist.iters[r];
+        aim::launch_axpy_inplace(x, w.xp, n * int64_t(nrhs), s);
+        ++refine;
+        for (int r = 0; r < nrhs; ++r) inf[r].refinements = refine;
+      }
+      for (int r = 0; r < nrhs; ++r) inf[r].matvecs = cst.matvecs;
+    }
+    AIM_HIP(hipStreamSynchronize(s));
+    const double secs = now_s() - t0;
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+      inf[r].rel_resid = rel[r];
+      inf[r].converged = rel[r] <= o.rtol ? 1 : 0;
+      inf[r].seconds = secs;
+      all = all && inf[r].converged;
+    }
+    std::memcpy(info, inf.data(), sizeof(aim_solve_info) * nrhs);
+    if (!all) result = AIM_ERR_NOT_CONVERGED;
+  });
+  if (st != AIM_OK) return st;
+  if (result != AIM_OK) return fail(result, "not every right-hand side reached rtol");
+  return AIM_OK;
+}

@@ -1,0 +1,158 @@
+// Internal declarations shared by the host set-up, the device kernels and the
+// C ABI of the AIMx library.  Not part of the public interface (include/aim.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/aim.h"
+
+namespace aim {
+
+// ---------------------------------------------------------------------------
+// errors: every internal failure is an aim::Error carrying the ABI status
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  aim_status status;
+  Error(aim_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define AIM_HIP(call)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::aim::Error(AIM_ERR_DEVICE, std::string(#call) + ": " +              \
+                                             hipGetErrorString(e_));              \
+  } while (0)
+
+#define AIM_REQUIRE(cond, status, msg)                                            \
+  do {                                                                            \
+    if (!(cond)) throw ::aim::Error((status), (msg));                             \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// host-side set-up results (setup_host.cpp)
+// ---------------------------------------------------------------------------
+struct HostTables {
+  int64_t N = 0;                    // triangles
+  int order = 2;                    // stencil order n
+  int dims[3] = {0, 0, 0};          // unpadded grid
+  double h = 0.0;
+  double origin[3] = {0, 0, 0};
+  std::vector<double> area;         // [N]
+  std::vector<double> qp_xyz;       // [3N][3] quadrature points
+  std::vector<double> qp_w;         // [3N] weights area/3
+  std::vector<int32_t> qp_start;    // [3N][3] stencil start per axis
+  std::vector<double> qp_local;     // [3N][3] t - s per axis
+  // near field (CSR, rows sorted by column)
+  std::vector<int64_t> rowptr;      // [N+1]
+  std::vector<int32_t> col;         // [nnz]
+  std::vector<double> near_static;  // [nnz] A_s,NR
+  std::vector<double> corr;         // [nnz] C = A_s,NR - A_s,P
+  // projection bricks: qp lists per brick of the grid
+  int brick[3] = {8, 4, 4};
+  int nbrick[3] = {0, 0, 0};
+  std::vector<int32_t> brick_ptr;   // [nbricks+1]
+  std::vector<int32_t> brick_qp;    // qp indices, ascending per brick
+  // near-block preconditioner: clusters of triangles
+  std::vector<int32_t> cl_ptr;      // [ncl+1] offsets into cl_perm
+  std::vector<int32_t> cl_perm;     // [N] triangle ids grouped by cluster
+  std::vector<int64_t> cl_blk;      // [ncl+1] offsets into cl_inv
+  std::vector<double> cl_inv;       // dense inverse blocks, row-major
+  double setup_seconds = 0.0;
+};
+
+// Builds every host table; throws aim::Error on invalid input.
+void build_host_tables(const aim_setup_desc& d, HostTables& t);
+
+// Closed-form integral of 1/|r - r'| over the triangle (a, b, c).
+double triangle_inv_r(const double r[3], const double a[3], const double b[3],
+                      const double c[3]);
+
+// ---------------------------------------------------------------------------
+// device launch wrappers (kernels.hip).  Complex data is interleaved.
+// ---------------------------------------------------------------------------
+struct GridShape {
+  int N[3];      // unpadded dims
+  int M[3];      // padded dims (2N)
+  int64_t Ng;    // N0 N1 N2
+  int64_t Nfold; // (N0+1)(N1+1)(N2+1)
+};
+
+struct QpDevice {
+  const int32_t* packed_start;  // [Nq] sx | sy << 10 | sz << 20
+  const void* local;            // [3][Nq] T (SoA)
+  const void* weight;           // [Nq] T
+  int64_t nq;
+};
+
+struct CsrDevice {
+  const int32_t* rowptr;  // [N+1]
+  const int32_t* col;     // [nnz]
+  const void* val;        // [nnz] T
+  int64_t n;
+};
+
+template <typename T>
+void launch_project(const GridShape& g, int order, const QpDevice& qp, const int32_t* brick_ptr,
+                    const int32_t* brick_qp, const int bricks[3], const int nbrick[3],
+                    const void* x, int64_t n, void* q, int nrhs, hipStream_t s);
+
+// Forward pruned 3-D FFT (unpadded q -> half-spectrum working grid), spectral
+// multiply, inverse pruned FFT (-> unpadded phi).  work must hold 4 Ng complex
+// per right-hand side; q and phi may alias.
+template <typename T>
+void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
+                     const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s);
+
+template <typename T>
+void launch_interp_near(const GridShape& g, int order, const QpDevice& qp, const CsrDevice& csr,
+                        const void* phi, const void* x, void* y, int nrhs, bool do_interp,
+                        bool do_near, hipStream_t s);
+
+// Kernel spectrum for one wavenumber: fills the folded, scaled spectrum
+// (complex128) and optionally its complex64 rounding.
+void launch_spectrum(const GridShape& g, double k, double h, void* full_work, void* spec64,
+                     void* spec32, const void* const* tw64, hipStream_t s);
+
+void launch_excitation(int kind, const double* qp_xyz, const double* qp_w, int64_t n,
+                       const double* params, int n_params, const double* kvals,
+                       const int32_t* rhs_freq, int nrhs, void* b, hipStream_t s);
+
+// Krylov helpers on complex128 [nrhs][n] vectors; vector i of system r in a
+// basis block starts at base + (i * si + r * sr) * n.
+void launch_cast_c128_to_c64(const void* in, void* out, int64_t count, hipStream_t s);
+void launch_cast_c64_to_c128(const void* in, void* out, int64_t count, hipStream_t s);
+// out[r][i] = sum_n conj(V_i,r[n]) w[r][n] for i < nv (two-stage, deterministic)
+void launch_block_dot(const void* V, int64_t si, int64_t sr, const void* w, int64_t n, int nv,
+                      int nrhs, void* partial, void* out, hipStream_t s);
+// w[r] -= sum_i h[r][i] V_i,r
+void launch_block_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv,
+                         int nrhs, const void* h, int64_t ldh, hipStream_t s);
+void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out, hipStream_t s);
+// out[r] = w[r] * (1 / nrm[r]) (0 if nrm == 0)
+void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
+                      int64_t out_stride, hipStream_t s);
+// x[r] += sum_i y[r][i] Z_i,r
+void launch_combine(const void* Z, int64_t si, int64_t sr, const void* y, int64_t ldy, int nv,
+                    void* x, int64_t n, int nrhs, hipStream_t s);
+// r = b - r   (in place on r)
+void launch_residual(const void* b, void* r, int64_t count, hipStream_t s);
+void launch_axpy_inplace(void* x, const void* d, int64_t count, hipStream_t s);
+void launch_diag_pc(const void* v, const double* dinv, void* z, int64_t n, int nrhs,
+                    hipStream_t s);
+void launch_block_pc(const void* v, void* z, const int32_t* cl_ptr, const int32_t* cl_perm,
+                     const int64_t* cl_blk, const double* cl_inv, int ncl, int max_cl,
+                     int64_t n, int nrhs, hipStream_t s);
+// gather/scatter of whole right-hand-side rows: dst[r] = src[idx[r]] (or reverse)
+void launch_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t n, int nrhs,
+                        bool scatter, hipStream_t s);
+
+// Twiddle table exp(-2 pi i m / L), m < L, in complex128 (and complex64).
+std::vector<double> twiddles64(int L);
+
+}  // namespace aim

@@ -266,7 +266,7 @@ def small_box_array(seed: int = 7000) -> Workload:
     stencil case whose grid spans several FFT tiles with ragged sizes."""
     V, T = box_array(nx=2, ny=1, size=(0.4, 0.4, 0.8), gap=0.3, jitter=0.03,
                      edge=0.1, seed=seed)
-    dims = (20, 12, 16)
+    dims = (32, 16, 16)
     h = derived_spacing(V, dims)
     return Workload("boxarray-small", V, T, 3, dims, h, 3.0,
                     np.array([2 * math.pi]), seed)

@@ -1,0 +1,122 @@
+"""CPU tests of the C-ABI library: it loads without a GPU, exports every
+symbol the header declares, validates its inputs on the host, and its
+host-side set-up tables (stencils, near list, A_s,NR, C) match the oracle."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2009_02281_amd import binding
+from paper_2009_02281_amd import inputs as I
+from oracle.aimx import AimOracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "aim.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:aim_status|const char\*)\s+(aim_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load_library()
+    declared = _declared_symbols()
+    assert len(declared) >= 10
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    for name in declared:
+        assert name in exported, name
+        assert hasattr(lib, name)
+    assert set(declared) == set(binding.EXPORTED)
+    assert lib.aim_version().startswith(b"aimx")
+
+
+def _plan(w, **kw):
+    args = dict(vertices=w.vertices, triangles=w.triangles, order=w.order, dims=w.dims,
+                h=w.h, near_threshold=w.near_threshold, k=w.k, host_only=True)
+    args.update(kw)
+    return binding.Plan(**args)
+
+
+@pytest.mark.parametrize("make", [I.sphere_small, I.small_box_array])
+def test_host_tables_match_oracle(make):
+    w = make()
+    p = _plan(w)
+    tb = p.export_tables()
+    o = AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    s, u = o.stencils()
+    assert np.array_equal(tb["stencil_start"], s)                # bit-exact index work
+    assert np.max(np.abs(tb["stencil_local"] - u)) == 0.0
+    C = o.C.tocsr()
+    C.sort_indices()
+    assert np.array_equal(C.indptr, tb["rowptr"]) and np.array_equal(C.indices, tb["col"])
+    assert np.max(np.abs(C.data - tb["val"])) <= 1e-13 * np.max(np.abs(C.data))
+    ns = o.static_near_matrix()
+    ns.sort_indices()
+    assert np.max(np.abs(ns.data - tb["near_static"])) <= 1e-13 * np.max(np.abs(ns.data))
+    info = p.info()
+    assert info["h"] == pytest.approx(o.h, rel=0, abs=0)
+    assert np.allclose(info["origin"], o.origin, rtol=0, atol=0)
+    assert info["max_cluster"] <= 64
+    p.close()
+
+
+def test_host_tables_sampled_rows_large_box_array():
+    w = I.box_array_large()
+    p = _plan(w)
+    tb = p.export_tables()
+    o = AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    s, _ = o.stencils()
+    assert np.array_equal(tb["stencil_start"], s)
+    rows = np.array([0, 777, 23456, 57599])
+    r, c, v = o.correction_rows(rows)
+    for i in rows:
+        sel = r == i
+        lo, hi = tb["rowptr"][i], tb["rowptr"][i + 1]
+        assert np.array_equal(c[sel], tb["col"][lo:hi])
+        assert np.max(np.abs(v[sel] - tb["val"][lo:hi])) <= 1e-13 * np.max(np.abs(v[sel]))
+
+
+def test_validation_errors():
+    w = I.sphere_tiny()
+    def status(**kw):
+        with pytest.raises(binding.AimError) as e:
+            _plan(w, **kw)
+        return e.value.status
+    assert status(order=4) == 1                               # INVALID_ARG
+    assert status(dims=(12, 8, 8)) == 3                       # GRID: not a power of two
+    assert status(dims=(8, 8, 512)) == 3                      # GRID: too large
+    assert status(h=0.02) == 3                                # GRID: stencil leaves the grid
+    assert status(near_threshold=0.0) == 1
+    assert status(k=[-1.0]) == 1
+    V = w.vertices.copy()
+    V[3, 1] = np.nan
+    assert status(vertices=V) == 2                            # GEOMETRY
+    T = w.triangles.copy()
+    T[5] = [T[5, 0], T[5, 0], T[5, 1]]
+    assert status(triangles=T) == 2                           # zero-area triangle
+    T = w.triangles.copy()
+    T[0, 0] = V.shape[0] + 3
+    assert status(triangles=T) == 2                           # index out of range
+
+
+def test_host_only_plan_rejects_device_calls():
+    w = I.sphere_tiny()
+    p = _plan(w)
+    lib = binding.load_library()
+    import ctypes as C
+    st = lib.aim_matvec(p._plan, 0, C.c_void_p(16), C.c_void_p(32), 1, None, None)
+    assert st == 8 and b"host-only" in lib.aim_last_error()
+    p.close()
+
+
+def test_null_arguments():
+    lib = binding.load_library()
+    import ctypes as C
+    assert lib.aim_setup(None, None, None) == 1
+    assert lib.aim_matvec(None, 0, None, None, 1, None, None) == 1
+    assert lib.aim_destroy(None) == 0

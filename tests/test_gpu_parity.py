@@ -1,0 +1,192 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Tolerances: complex128 path <= 1e-10 relative L2, complex64 path <= 1e-5
+relative L2 (both against the float64 oracle); per-stage complex128 results
+are compared at rounding level; integer/index work bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2009_02281_amd import inputs as I
+from oracle import aimx, excitation
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU machines skip the module
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2009_02281_amd import binding  # noqa: E402
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def dev(x, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+_CACHE = {}
+
+
+def _setup(name):
+    if name not in _CACHE:
+        w = {"sphere": I.sphere_small, "boxes": I.small_box_array}[name]()
+        o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+        o.C
+        p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                         max_rhs=8)
+        _CACHE[name] = (w, o, p)
+    return _CACHE[name]
+
+
+CASES = ["sphere", "boxes"]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_stage_project(case):
+    w, o, p = _setup(case)
+    print(f"[gpu] project {case} N={o.N}", flush=True)
+    x = I.complex_gaussian(o.N, 101, nrhs=3)
+    q = host(p.apply_stage("project", dev(x)))
+    ref = o.project(x)
+    assert rel(q, ref) <= 1e-14
+    qf = host(p.apply_stage("project", dev(x, torch.complex64), prec="c64"))
+    assert rel(qf, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_stage_convolve(case):
+    w, o, p = _setup(case)
+    print(f"[gpu] convolve {case} dims={o.dims}", flush=True)
+    Nx, Ny, Nz = o.dims
+    g = I.complex_gaussian(Nx * Ny * Nz, 102, nrhs=2).reshape(2, Nz, Ny, Nx)
+    phi = host(p.apply_stage("convolve", dev(g)))
+    ref = aimx.grid_convolve(g, o.spectrum(w.k[0]), o.dims)
+    assert rel(phi, ref) <= 1e-12
+    phif = host(p.apply_stage("convolve", dev(g, torch.complex64), prec="c64"))
+    assert rel(phif, ref) <= FP32_TOL
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_stage_interpolate_and_near(case):
+    w, o, p = _setup(case)
+    print(f"[gpu] interpolate/near {case}", flush=True)
+    Nx, Ny, Nz = o.dims
+    g = I.complex_gaussian(Nx * Ny * Nz, 103, nrhs=2).reshape(2, Nz, Ny, Nx)
+    y = host(p.apply_stage("interpolate", dev(g)))
+    assert rel(y, o.interpolate(g)) <= 1e-14
+    x = I.complex_gaussian(o.N, 104, nrhs=2)
+    yn = host(p.apply_stage("near", dev(x)))
+    assert rel(yn, (o.C @ x.T).T) <= 1e-14
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_matvec_fp64_and_fp32(case, nrhs):
+    w, o, p = _setup(case)
+    print(f"[gpu] matvec {case} nrhs={nrhs}", flush=True)
+    x = I.complex_gaussian(o.N, 1001, nrhs=nrhs)
+    ref = o.matvec(x, w.k[0])
+    y64 = host(p.matvec(dev(x)))
+    assert rel(y64, ref) <= FP64_TOL
+    y32 = host(p.matvec(dev(x, torch.complex64), prec="c64"))
+    e32 = rel(y32, ref)
+    print(f"    fp64 err {rel(y64, ref):.2e}  fp32 err {e32:.2e}", flush=True)
+    assert e32 <= FP32_TOL
+
+
+def test_matvec_frequency_batch():
+    """Several wavenumbers in one plan; each right-hand side selects its own
+    kernel spectrum (the batched sweep)."""
+    w = I.sweep_small(nfreq=6, rhs_per_freq=2)
+    print("[gpu] frequency batch", flush=True)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     max_rhs=12)
+    freq = np.repeat(np.arange(6), 2)[::-1].copy()
+    x = I.complex_gaussian(o.N, 3001, nrhs=12)
+    y64 = host(p.matvec(dev(x), freq_idx=freq))
+    y32 = host(p.matvec(dev(x, torch.complex64), freq_idx=freq, prec="c64"))
+    for r in range(12):
+        ref = o.matvec(x[r], w.k[freq[r]])
+        assert rel(y64[r], ref) <= FP64_TOL
+        assert rel(y32[r], ref) <= FP32_TOL
+    p.close()
+
+
+def test_projection_is_deterministic():
+    w, o, p = _setup("boxes")
+    x = dev(I.complex_gaussian(o.N, 105, nrhs=4))
+    a = p.apply_stage("project", x)
+    b = p.apply_stage("project", x)
+    assert torch.equal(a, b)
+    ya = p.matvec(x)
+    yb = p.matvec(x)
+    assert torch.equal(ya, yb)
+
+
+def test_operator_symmetry_on_gpu():
+    w, o, p = _setup("sphere")
+    x = I.complex_gaussian(o.N, 11)
+    y = I.complex_gaussian(o.N, 12)
+    Ay = host(p.matvec(dev(y)))
+    Ax = host(p.matvec(dev(x)))
+    assert abs(x @ Ay - y @ Ax) <= 1e-12 * abs(x @ Ay)
+    Ay32 = host(p.matvec(dev(y, torch.complex64), prec="c64"))
+    Ax32 = host(p.matvec(dev(x, torch.complex64), prec="c64"))
+    assert abs(x @ Ay32 - y @ Ax32) <= 1e-6 * abs(x @ Ay32)
+
+
+def test_excitation_matches_oracle():
+    w, o, p = _setup("sphere")
+    b = host(p.excitation("plane_wave", [0.0, 0.0, 1.0]))[0]
+    assert rel(b, excitation.plane_wave(o.V, o.T, w.k[0])) <= 1e-14
+    c = o.cent[17]
+    g = host(p.excitation("gaussian_patch", [c[0], c[1], c[2], 0.2]))[0]
+    assert rel(g, excitation.gaussian_patch(o.V, o.T, c, 0.2)) <= 1e-14
+
+
+def test_invalid_calls_raise():
+    w, o, p = _setup("sphere")
+    x = dev(I.complex_gaussian(o.N, 1, nrhs=9))
+    with pytest.raises(binding.AimError) as e:
+        p.matvec(x)                     # nrhs above max_rhs
+    assert e.value.status == 1
+    with pytest.raises(binding.AimError):
+        p.matvec(x[:2], freq_idx=[0, 3])   # frequency index out of range
+
+
+def test_full_size_box_array_sampled():
+    """The 4x4 box array at full size (57,600 triangles, 128x128x64 grid,
+    3rd-order stencils) in the configuration the benchmark times: all rows of
+    the far part and sampled rows of the full product against the oracle."""
+    w = I.box_array_large()
+    print(f"[gpu] full-size box array N={w.n}", flush=True)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     max_rhs=1)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    x = I.complex_gaussian(o.N, 2001)
+    rows = np.sort(np.random.default_rng(2002).choice(o.N, 48, replace=False))
+    ref = o.matvec_rows(x, w.k[0], rows)
+    y64 = host(p.matvec(dev(x)))
+    y32 = host(p.matvec(dev(x, torch.complex64), prec="c64"))
+    assert rel(y64[rows], ref) <= FP64_TOL
+    assert rel(y32[rows], ref) <= FP32_TOL
+    far = o.far(x, w.k[0])
+    q = p.apply_stage("project", dev(x))
+    yfar = host(p.apply_stage("interpolate", p.apply_stage("convolve", q)))
+    assert rel(yfar[0], far) <= FP64_TOL
+    print(f"    fp64 err {rel(y64[rows], ref):.2e} fp32 err {rel(y32[rows], ref):.2e}", flush=True)
+    p.close()
