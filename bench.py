@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput of the AIMx matvec on one MI355X.
+
+One step = one application of the AIMx operator (eq. LAIMx) to one input
+vector: projection onto the grid, pruned zero-padded 3-D FFT, multiplication
+by the kernel spectrum, inverse FFT, interpolation and the sparse near-field
+correction -- all in the library's HIP kernels.  Inputs are resident in HBM
+when the timed region starts.
+
+Default workload: the 4x4 array of 1x1x4-wavelength conductor boxes
+(57,600 triangles, 3rd-order stencils, 128x128x64 grid zero-padded to
+256x256x128, near threshold 3h, k = 2 pi), complex128.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_02281_amd", "csrc", "kernels.hip")
+
+
+def algorithmic_bytes(info: dict, prec: str, nrhs: int = 1) -> dict:
+    """Bytes each matvec kernel must move at minimum (per launch over nrhs
+    right-hand sides); b = bytes per complex value, s = per real value."""
+    b = 16 if prec == "c128" else 8
+    s = b // 2
+    N, Ng, nnz = info["n"], info["n_grid"], info["nnz"]
+    Nq = 3 * N
+    dims = info["dims"]
+    nfold = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
+    qp = Nq * (4 + 4 * s)              # packed stencil start + 3 local coordinates + weight
+    return {
+        "project": nrhs * (N * b + Ng * b) + qp,
+        "fft_x_fwd": nrhs * 3 * Ng * b,    # read Ng, write 2 Ng
+        "fft_y_fwd": nrhs * 6 * Ng * b,    # read 2 Ng, write 4 Ng
+        "fft_z_conv": nrhs * 8 * Ng * b + nfold * b,   # read/write 4 Ng, spectrum once
+        "fft_y_inv": nrhs * 6 * Ng * b,
+        "fft_x_inv": nrhs * 3 * Ng * b,
+        "interp_near": nrhs * (Ng * b + 2 * N * b) + qp + nnz * (4 + s) + 4 * (N + 1),
+    }
+
+
+def make_workload(name: str):
+    from paper_2009_02281_amd import inputs as I
+    return {"boxarray": I.box_array_large, "sphere": I.sphere_small,
+            "sphere-large": I.sphere_large}[name]()
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, prec: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, only if
+    they were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(f"{workload}/{prec}/{kernel}")
+    if not ent or ent.get("kernel_sha") != kernel_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(w, x, reps: int = 3, near_rows: int = 512) -> dict:
+    """The oracle (NumPy/SciPy float64) timed on this host: the whole far part
+    plus the near-field correction on a row sample, scaled to all rows."""
+    import numpy as np
+    import scipy.sparse as sp
+    from oracle import aimx
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    k = float(w.k[0])
+    o.spectrum(k)
+    rows = np.sort(np.random.default_rng(5).choice(o.N, min(near_rows, o.N), replace=False))
+    r, c, v = o.correction_rows(rows)
+    Cs = sp.csr_matrix((v, (r, c)), shape=(o.N, o.N))
+    t_far, t_near = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        o.far(x, k)
+        t1 = time.perf_counter()
+        Cs @ x
+        t2 = time.perf_counter()
+        t_far.append(t1 - t0)
+        t_near.append(t2 - t1)
+    t = min(t_far) + min(t_near) * o.N / rows.size
+    cores = os.cpu_count() or 1
+    return {"value": o.N / t, "unit": "unknowns*matvecs/s", "cores": cores, "kind": "oracle",
+            "sample": (f"one matvec of the same workload: full far part (P x, scipy.fft "
+                       f"over the 256x256x128 padded grid with {cores} workers, P^T), "
+                       f"near correction on {rows.size} sampled rows scaled by "
+                       f"{o.N}/{rows.size}; best of {reps}; oracle set-up excluded"),
+            "seconds_per_matvec": t}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="boxarray", choices=["boxarray", "sphere", "sphere-large"])
+    ap.add_argument("--prec", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; the multi-GPU design is "
+              "described, not run (use --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2009_02281_amd import binding
+    from paper_2009_02281_amd import inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    w = make_workload(args.workload)
+    print(f"[bench] workload {w.name}: N={w.n} dims={w.dims} order={w.order} "
+          f"prec={args.prec} nrhs={args.nrhs}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plan = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                        precisions=(args.prec,), max_rhs=args.nrhs)
+    setup_s = time.perf_counter() - t0
+    info = plan.info()
+    print(f"[bench] setup {setup_s:.2f}s (host tables {info['setup_seconds']:.2f}s, "
+          f"spectra {info['spectra_seconds']:.3f}s), nnz={info['nnz']}", file=sys.stderr,
+          flush=True)
+    dtype = torch.complex128 if args.prec == "c128" else torch.complex64
+    xh = I.complex_gaussian(w.n, w.seed_base + 1, nrhs=args.nrhs)
+    x = torch.from_numpy(xh).to(dtype).cuda()
+    y = torch.empty_like(x)
+
+    for _ in range(args.warmup):
+        plan.matvec(x, prec=args.prec, out=y)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        plan.matvec(x, prec=args.prec, out=y)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    value = w.n * args.nrhs / (ms * 1e-3)
+    print(f"[bench] {ms:.4f} ms/matvec -> {value:.4e} unknowns*matvecs/s", file=sys.stderr,
+          flush=True)
+
+    out = {
+        "metric": "AIM matvec unknowns/s",
+        "value": value,
+        "unit": "unknowns*matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": w.name, "triangles": w.n, "order": w.order,
+                   "grid": list(w.dims), "padded_grid": [2 * d for d in w.dims],
+                   "near_threshold_h": w.near_factor, "k": float(w.k[0]),
+                   "nrhs": args.nrhs, "nnz": info["nnz"]},
+    }
+
+    if not args.no_profile:
+        reps = max(5, min(50, args.steps))
+        kms = plan.profile_matvec(x, reps=reps, prec=args.prec, out=y)
+        ab = algorithmic_bytes(info, args.prec, args.nrhs)
+        dom = max(kms, key=kms.get)
+        achieved = ab[dom] / (kms[dom] * 1e-3) / 1e9
+        stages = {k: {"ms": kms[k], "alg_bytes": ab[k],
+                      "gbs": ab[k] / (kms[k] * 1e-3) / 1e9 if kms[k] > 0 else None}
+                  for k in kms}
+        total_b = sum(ab.values())
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": load_traffic(dom, w.name, args.prec)}
+        out["stages"] = stages
+        out["matvec_alg_gbs"] = total_b / (ms * 1e-3) / 1e9
+        print(f"[bench] kernels (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in kms.items()),
+              file=sys.stderr, flush=True)
+
+    if not args.no_cpu:
+        print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)
+        cb = cpu_baseline(w, xh[0] if xh.ndim == 2 else xh)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        print(f"[bench] oracle {cb['seconds_per_matvec']:.3f} s/matvec", file=sys.stderr,
+              flush=True)
+    plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -211,6 +211,21 @@ aim_status aim_solve(aim_plan plan, const void* b_dev, void* x_dev, int32_t nrhs
                      const int32_t* freq_idx_host, const aim_solve_opts* opts,
                      aim_solve_info* info_host, void* hip_stream);
 
+/* Kernels of one matvec, in launch order (aim_profile_matvec). */
+#define AIM_N_KERNELS 7
+/* 0 project (P x), 1 x-forward FFT, 2 y-forward FFT, 3 z FFT * spectrum *
+ * inverse z FFT, 4 y-inverse FFT, 5 x-inverse FFT, 6 interpolation + C x */
+
+/* Runs aim_matvec `reps` times with a HIP event recorded between every two
+ * kernels on hip_stream, and returns in kernel_ms_host[AIM_N_KERNELS] the
+ * average duration of each kernel in milliseconds (the stages of eq. LAIMx:
+ * projection, the zero-padded FFT convolution with the Toeplitz kernel, the
+ * interpolation and the near-field correction).  Same arguments and errors
+ * as aim_matvec (y_dev receives the product); blocking. */
+aim_status aim_profile_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
+                              int32_t nrhs, const int32_t* freq_idx_host, int32_t reps,
+                              double* kernel_ms_host, void* hip_stream);
+
 /* Host copies of setup tables, for validation against an independent
  * implementation.  Any pointer may be NULL to skip that table.
  *   stencil_start [3N][3] int32: first node of each quadrature point's stencil

@@ -25,7 +25,10 @@ STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3}
 RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec", "aim_apply_stage",
-            "aim_excitation", "aim_solve", "aim_export_tables", "aim_last_error", "aim_version"]
+            "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
+            "aim_last_error", "aim_version"]
+KERNELS = ["project", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
+           "interp_near"]
 
 
 class AimError(RuntimeError):
@@ -102,6 +105,8 @@ def load_library(path: str = LIB_PATH):
                               C.POINTER(SolveInfo), vp]
     lib.aim_export_tables.argtypes = [vp, ip32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                       ip32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.aim_profile_matvec.argtypes = [vp, i32, vp, vp, i32, ip32, i32,
+                                       C.POINTER(C.c_double), vp]
     lib.aim_last_error.restype = C.c_char_p
     lib.aim_version.restype = C.c_char_p
     for name in EXPORTED:
@@ -255,6 +260,21 @@ class Plan:
         _check(self._lib.aim_matvec(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
                                     C.c_void_p(y.data_ptr()), nrhs, fp, _stream_ptr(stream)))
         return y
+
+    def profile_matvec(self, x, reps: int = 10, freq_idx=None, prec: str = "c128", out=None,
+                       stream=None) -> dict:
+        """Average duration (ms) of each matvec kernel over ``reps`` runs,
+        timed with HIP events on the stream."""
+        import torch
+        self._check_vec(x, prec, self.n, "x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        ms = (C.c_double * len(KERNELS))()
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_profile_matvec(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(y.data_ptr()), nrhs, fp, int(reps), ms,
+                                            _stream_ptr(stream)))
+        return {k: float(ms[i]) for i, k in enumerate(KERNELS)}
 
     def apply_stage(self, stage: str, inp, freq_idx=None, prec: str = "c128", stream=None):
         """One stage of the matvec: 'project' x -> grid, 'convolve' grid ->

@@ -69,14 +69,18 @@ struct aim_plan_s {
   bool host_only = false;
 
   // device tables
-  int32_t* d_packed = nullptr;
-  double* d_loc64 = nullptr;
-  double* d_w64 = nullptr;
-  float* d_loc32 = nullptr;
-  float* d_w32 = nullptr;
-  double* d_qpxyz = nullptr;
-  int32_t* d_bptr = nullptr;
-  int32_t* d_blist = nullptr;
+  double* d_w64 = nullptr;     // quadrature weights (excitation)
+  double* d_qpxyz = nullptr;   // quadrature points (excitation)
+  int32_t* d_pblk = nullptr;   // row blocks of P
+  int nblk = 0;
+  int32_t* d_prow = nullptr;   // P by grid node
+  int32_t* d_pcol = nullptr;
+  double* d_pval64 = nullptr;
+  float* d_pval32 = nullptr;
+  int32_t* d_ptrow = nullptr;  // P^T by triangle
+  int32_t* d_ptcol = nullptr;
+  double* d_ptval64 = nullptr;
+  float* d_ptval32 = nullptr;
   int32_t* d_rowptr = nullptr;
   int32_t* d_col = nullptr;
   double* d_val64 = nullptr;
@@ -153,13 +157,22 @@ struct aim_plan_s {
 
 namespace {
 
-aim::QpDevice qp_dev(aim_plan p, aim_precision prec) {
-  aim::QpDevice q;
-  q.packed_start = p->d_packed;
-  q.local = prec == AIM_C128 ? static_cast<const void*>(p->d_loc64) : p->d_loc32;
-  q.weight = prec == AIM_C128 ? static_cast<const void*>(p->d_w64) : p->d_w32;
-  q.nq = 3 * p->t.N;
-  return q;
+aim::CsrDevice p_dev(aim_plan p, aim_precision prec) {
+  aim::CsrDevice c;
+  c.rowptr = p->d_prow;
+  c.col = p->d_pcol;
+  c.val = prec == AIM_C128 ? static_cast<const void*>(p->d_pval64) : p->d_pval32;
+  c.n = p->g.Ng;
+  return c;
+}
+
+aim::CsrDevice pt_dev(aim_plan p, aim_precision prec) {
+  aim::CsrDevice c;
+  c.rowptr = p->d_ptrow;
+  c.col = p->d_ptcol;
+  c.val = prec == AIM_C128 ? static_cast<const void*>(p->d_ptval64) : p->d_ptval32;
+  c.n = p->t.N;
+  return c;
 }
 
 aim::CsrDevice csr_dev(aim_plan p, aim_precision prec) {
@@ -200,26 +213,33 @@ const int32_t* set_freq(aim_plan p, const int32_t* freq_host, int nrhs, hipStrea
   return p->d_rhs_freq;
 }
 
+// The matvec schedule: projection, the pruned FFT convolution (five passes),
+// then interpolation fused with the near-field correction.  With ev != NULL,
+// ev[0..7] are recorded before, between and after the seven kernels.
 template <typename T>
 void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
-                 const int32_t* dfreq, hipStream_t s) {
+                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev) {
   const int pi = int(prec);
   void* grid = p->d_grid[pi];
   const void* spec = prec == AIM_C128 ? p->d_spec64 : p->d_spec32;
   void* const* tw = prec == AIM_C128 ? p->d_tw64 : p->d_tw32;
-  aim::launch_project<T>(p->g, p->t.order, qp_dev(p, prec), p->d_bptr, p->d_blist, p->t.brick,
-                         p->t.nbrick, x, p->t.N, grid, nrhs, s);
-  aim::launch_convolve<T>(p->g, grid, p->d_work[pi], grid, spec, dfreq, nrhs, tw, s);
-  aim::launch_interp_near<T>(p->g, p->t.order, qp_dev(p, prec), csr_dev(p, prec), grid, x, y,
-                             nrhs, true, true, s);
+  if (ev) AIM_HIP(hipEventRecord(ev[0], s));
+  aim::launch_project<T>(p->g, p_dev(p, prec), p->d_pblk, p->nblk, x, p->t.N, grid, nrhs, s);
+  if (ev) AIM_HIP(hipEventRecord(ev[1], s));
+  aim::launch_convolve<T>(p->g, grid, p->d_work[pi], grid, spec, dfreq, nrhs, tw, s,
+                          ev ? ev + 2 : nullptr);
+  if (ev) AIM_HIP(hipEventRecord(ev[6], s));
+  aim::launch_interp_near<T>(p->g, pt_dev(p, prec), csr_dev(p, prec), grid, x, y, nrhs, true,
+                             true, s);
+  if (ev) AIM_HIP(hipEventRecord(ev[7], s));
 }
 
 void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
-                const int32_t* dfreq, hipStream_t s) {
+                const int32_t* dfreq, hipStream_t s, hipEvent_t* ev = nullptr) {
   if (prec == AIM_C128)
-    matvec_impl<double>(p, prec, x, y, nrhs, dfreq, s);
+    matvec_impl<double>(p, prec, x, y, nrhs, dfreq, s, ev);
   else
-    matvec_impl<float>(p, prec, x, y, nrhs, dfreq, s);
+    matvec_impl<float>(p, prec, x, y, nrhs, dfreq, s, ev);
 }
 
 }  // namespace
@@ -298,25 +318,24 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
     p->setup_stream = s;
     const auto& t = p->t;
     const int64_t N = t.N, Nq = 3 * N;
-    // quadrature-point records
-    std::vector<int32_t> packed(Nq);
-    std::vector<double> loc(3 * Nq), w(Nq);
-    for (int64_t q = 0; q < Nq; ++q) {
-      packed[q] = t.qp_start[3 * q] | (t.qp_start[3 * q + 1] << 10) | (t.qp_start[3 * q + 2] << 20);
-      for (int a = 0; a < 3; ++a) loc[a * Nq + q] = t.qp_local[3 * q + a];
-      w[q] = t.qp_w[q];
-    }
-    p->d_packed = p->upload(packed, s);
+    // quadrature points (excitation) and the projection matrix in two layouts
     p->d_qpxyz = p->upload(t.qp_xyz, s);
-    p->d_w64 = p->upload(w, s);  // always kept: excitation needs it
-    if (p->prec & (1u << AIM_C128)) p->d_loc64 = p->upload(loc, s);
-    if (p->prec & (1u << AIM_C64)) {
-      std::vector<float> l32(loc.begin(), loc.end()), w32(w.begin(), w.end());
-      p->d_loc32 = p->upload(l32, s);
-      p->d_w32 = p->upload(w32, s);
+    p->d_w64 = p->upload(t.qp_w, s);
+    p->d_prow = p->upload(t.p_rowptr, s);
+    p->d_pblk = p->upload(t.p_blk, s);
+    p->nblk = int(t.p_blk.size()) - 1;
+    p->d_pcol = p->upload(t.p_col, s);
+    p->d_ptrow = p->upload(t.pt_rowptr, s);
+    p->d_ptcol = p->upload(t.pt_col, s);
+    if (p->prec & (1u << AIM_C128)) {
+      p->d_pval64 = p->upload(t.p_val, s);
+      p->d_ptval64 = p->upload(t.pt_val, s);
     }
-    p->d_bptr = p->upload(t.brick_ptr, s);
-    p->d_blist = p->upload(t.brick_qp, s);
+    if (p->prec & (1u << AIM_C64)) {
+      std::vector<float> a(t.p_val.begin(), t.p_val.end()), b(t.pt_val.begin(), t.pt_val.end());
+      p->d_pval32 = p->upload(a, s);
+      p->d_ptval32 = p->upload(b, s);
+    }
     std::vector<int32_t> rp32(t.rowptr.begin(), t.rowptr.end());
     p->d_rowptr = p->upload(rp32, s);
     p->d_col = p->upload(t.col, s);
@@ -431,6 +450,40 @@ aim_status aim_matvec(aim_plan p, aim_precision prec, const void* x, void* y, in
   });
 }
 
+aim_status aim_profile_matvec(aim_plan p, aim_precision prec, const void* x, void* y,
+                              int32_t nrhs, const int32_t* freq_idx_host, int32_t reps,
+                              double* kernel_ms, void* hip_stream) {
+  if (!p || !x || !y || !kernel_ms) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    check_prec(p, prec);
+    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+    AIM_REQUIRE(reps >= 1, AIM_ERR_INVALID_ARG, "reps must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    std::vector<hipEvent_t> ev(8 * size_t(reps), nullptr);
+    auto destroy = [&] {
+      for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    };
+    try {
+      for (auto& e : ev) AIM_HIP(hipEventCreate(&e));
+      for (int r = 0; r < reps; ++r) matvec_any(p, prec, x, y, nrhs, df, s, &ev[8 * size_t(r)]);
+      AIM_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < AIM_N_KERNELS; ++k) kernel_ms[k] = 0.0;
+      for (int r = 0; r < reps; ++r)
+        for (int k = 0; k < AIM_N_KERNELS; ++k) {
+          float ms = 0.f;
+          AIM_HIP(hipEventElapsedTime(&ms, ev[8 * size_t(r) + k], ev[8 * size_t(r) + k + 1]));
+          kernel_ms[k] += ms / reps;
+        }
+    } catch (...) {
+      destroy();
+      throw;
+    }
+    destroy();
+  });
+}
+
 aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, const void* in,
                            void* out, int32_t nrhs, const int32_t* freq_idx_host,
                            void* hip_stream) {
@@ -445,11 +498,11 @@ aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, cons
     switch (stage) {
       case AIM_STAGE_PROJECT:
         if (d)
-          aim::launch_project<double>(p->g, p->t.order, qp_dev(p, prec), p->d_bptr, p->d_blist,
-                                      p->t.brick, p->t.nbrick, in, p->t.N, out, nrhs, s);
+          aim::launch_project<double>(p->g, p_dev(p, prec), p->d_pblk, p->nblk, in, p->t.N, out,
+                                      nrhs, s);
         else
-          aim::launch_project<float>(p->g, p->t.order, qp_dev(p, prec), p->d_bptr, p->d_blist,
-                                     p->t.brick, p->t.nbrick, in, p->t.N, out, nrhs, s);
+          aim::launch_project<float>(p->g, p_dev(p, prec), p->d_pblk, p->nblk, in, p->t.N, out,
+                                     nrhs, s);
         break;
       case AIM_STAGE_CONVOLVE:
         if (d)
@@ -463,11 +516,11 @@ aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, cons
       case AIM_STAGE_NEAR: {
         const bool interp = stage == AIM_STAGE_INTERPOLATE;
         if (d)
-          aim::launch_interp_near<double>(p->g, p->t.order, qp_dev(p, prec), csr_dev(p, prec),
+          aim::launch_interp_near<double>(p->g, pt_dev(p, prec), csr_dev(p, prec),
                                           interp ? in : nullptr, interp ? nullptr : in, out, nrhs,
                                           interp, !interp, s);
         else
-          aim::launch_interp_near<float>(p->g, p->t.order, qp_dev(p, prec), csr_dev(p, prec),
+          aim::launch_interp_near<float>(p->g, pt_dev(p, prec), csr_dev(p, prec),
                                          interp ? in : nullptr, interp ? nullptr : in, out, nrhs,
                                          interp, !interp, s);
         break;

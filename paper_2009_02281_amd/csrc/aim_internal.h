@@ -53,11 +53,16 @@ struct HostTables {
   std::vector<int32_t> col;         // [nnz]
   std::vector<double> near_static;  // [nnz] A_s,NR
   std::vector<double> corr;         // [nnz] C = A_s,NR - A_s,P
-  // projection bricks: qp lists per brick of the grid
-  int brick[3] = {8, 4, 4};
-  int nbrick[3] = {0, 0, 0};
-  std::vector<int32_t> brick_ptr;   // [nbricks+1]
-  std::vector<int32_t> brick_qp;    // qp indices, ascending per brick
+  // projection P[u, j] = sum_q (A_j/3) Lambda_u(r_jq), merged per triangle,
+  // stored twice: by grid node (rows = nodes, for q = P x) and by triangle
+  // (rows = triangles, for y = P^T phi); rows sorted by column
+  std::vector<int32_t> p_rowptr;    // [Ng+1]
+  std::vector<int32_t> p_col;       // triangle ids
+  std::vector<double> p_val;
+  std::vector<int32_t> p_blk;       // row blocks of P for the projection kernel
+  std::vector<int32_t> pt_rowptr;   // [N+1]
+  std::vector<int32_t> pt_col;      // grid node ids
+  std::vector<double> pt_val;
   // near-block preconditioner: clusters of triangles
   std::vector<int32_t> cl_ptr;      // [ncl+1] offsets into cl_perm
   std::vector<int32_t> cl_perm;     // [N] triangle ids grouped by cluster
@@ -83,13 +88,6 @@ struct GridShape {
   int64_t Nfold; // (N0+1)(N1+1)(N2+1)
 };
 
-struct QpDevice {
-  const int32_t* packed_start;  // [Nq] sx | sy << 10 | sz << 20
-  const void* local;            // [3][Nq] T (SoA)
-  const void* weight;           // [Nq] T
-  int64_t nq;
-};
-
 struct CsrDevice {
   const int32_t* rowptr;  // [N+1]
   const int32_t* col;     // [nnz]
@@ -97,9 +95,12 @@ struct CsrDevice {
   int64_t n;
 };
 
+// q = P x over row blocks of P (each block holds at most kProjNnz non-zeros
+// and kProjRows rows, or is one longer row on its own)
+constexpr int kProjNnz = 2048;
+constexpr int kProjRows = 1024;
 template <typename T>
-void launch_project(const GridShape& g, int order, const QpDevice& qp, const int32_t* brick_ptr,
-                    const int32_t* brick_qp, const int bricks[3], const int nbrick[3],
+void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, int nblk,
                     const void* x, int64_t n, void* q, int nrhs, hipStream_t s);
 
 // Forward pruned 3-D FFT (unpadded q -> half-spectrum working grid), spectral
@@ -107,10 +108,13 @@ void launch_project(const GridShape& g, int order, const QpDevice& qp, const int
 // per right-hand side; q and phi may alias.
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
-                     const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s);
+                     const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
+                     hipEvent_t* between = nullptr);  // 4 events recorded between passes
 
+// y = P^T phi + C x: rows of P^T (by triangle) and of C, one group of lanes
+// per triangle
 template <typename T>
-void launch_interp_near(const GridShape& g, int order, const QpDevice& qp, const CsrDevice& csr,
+void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice& csr,
                         const void* phi, const void* x, void* y, int nrhs, bool do_interp,
                         bool do_near, hipStream_t s);
 

@@ -2,10 +2,9 @@
 // gfx950 (CDNA4: 64-lane wavefronts, 160 KB LDS per CU).
 //
 // Matvec (eq. LAIMx): y = P^T IFFT( H_hat * FFT( pad(P x) ) ) + C x
-//   project        brick-tiled scatter of quadrature-point sources onto the
-//                  grid; each thread owns one grid node of an LDS-staged brick
-//                  and walks that brick's sorted source list, so the sum order
-//                  is fixed and no atomics are used;
+//   project        q = P x with P assembled at set-up and sorted by grid node;
+//                  each thread owns one node and sums its row in a fixed
+//                  order (reproducible, no atomics);
 //   fft_row/col    LDS-staged Stockham passes (radix 8 with one radix-2/4
 //                  stage), pruned: forward passes read only the non-zero half
 //                  of each padded line, inverse passes write only the half that
@@ -13,8 +12,8 @@
 //                  the strided y/z lines are read and written coalesced;
 //                  the z pass multiplies by the kernel spectrum between its
 //                  forward and inverse transforms without leaving LDS;
-//   interp_near    gather of the stencil potentials per quadrature point plus
-//                  the real CSR near-field correction, one pass over y.
+//   interp_near    rows of P^T (stencil potentials of each triangle) plus the
+//                  rows of the real CSR near-field correction, one pass over y.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -136,75 +135,97 @@ struct Dft<T, 8, INV> {
   }
 };
 
-// One Stockham stage on L points held in LDS (element e at s[e * es]).
-// Butterfly j reads j + r L/R, twiddles by W_{Ns R}^{r (j mod Ns)}, runs the
-// R-point DFT and writes (j div Ns) Ns R + (j mod Ns) + r Ns; Ns is the
-// product of the radices of the previous stages.
-template <typename T, int L, int R, int NT, bool INV>
-__device__ __forceinline__ void stockham_stage(cx<T>* s, int es, int t, int lgNs,
-                                               const cx<T>* tw) {
+// ---------------------------------------------------------------------------
+// Register-resident Stockham FFT.  A length-L line is shared by NT threads;
+// each holds E = L/NT elements in registers.  Stage s with radix R treats
+// butterfly j (= t + i NT) as elements j + r L/R, twiddles them by
+// W_{Ns R}^{r (j mod Ns)}, runs the R-point DFT and leaves element
+// (j div Ns) Ns R + (j mod Ns) + r Ns, with Ns the product of the earlier
+// radices.  Elements move through LDS only between stages; the first stage
+// reads straight from memory (skipping the zero padding) and the last writes
+// straight to memory (skipping the discarded half).  Forward passes put the
+// small radix (2 or 4) first and inverse passes last, so a forward transform
+// ends, and an inverse one starts, with radix 8 and the same element
+// ownership: the spectral multiply between them needs no exchange.
+// ---------------------------------------------------------------------------
+template <int L, bool SMALL_FIRST>
+struct Sched {
+  static constexpr int P = ilog2(L);
+  static constexpr int SMALL = P % 3 == 1 ? 2 : (P % 3 == 2 ? 4 : 8);
+  static constexpr int NST = P % 3 == 0 ? P / 3 : P / 3 + 1;
+  static constexpr int radix(int st) {
+    return P % 3 == 0 ? 8 : (SMALL_FIRST ? (st == 0 ? SMALL : 8) : (st == NST - 1 ? SMALL : 8));
+  }
+  static constexpr int lgns(int st) {
+    int a = 0;
+    for (int q = 0; q < st; ++q) a += ilog2(radix(q));
+    return a;
+  }
+};
+
+template <typename T, int L, int NT, bool INV, int R, int LGNS>
+__device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* tw) {
   constexpr int NB = L / (R * NT);
   static_assert(NB >= 1, "too many threads per line for this radix");
-  constexpr int lgL = ilog2(L), lgR = ilog2(R);
-  const int Ns = 1 << lgNs;
-  const int twsh = lgL - lgNs - lgR;  // log2(L / (Ns R))
-  cx<T> v[NB][R];
+  constexpr int twsh = ilog2(L) - LGNS - ilog2(R);  // log2(L / (Ns R))
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int j = t + i * NT;
-    const int k = j & (Ns - 1);
+    if constexpr (LGNS > 0) {
+      const int k = (t + i * NT) & ((1 << LGNS) - 1);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      cx<T> a = s[(j + r * (L / R)) * es];
-      if (r > 0) {
+      for (int r = 1; r < R; ++r) {
         cx<T> w = tw[(r * k) << twsh];
         if (INV) w.y = -w.y;
-        a = cmul(a, w);
+        v[i * R + r] = cmul(v[i * R + r], w);
       }
-      v[i][r] = a;
     }
-    Dft<T, R, INV>::run(v[i]);
+    Dft<T, R, INV>::run(v + i * R);
   }
-  __syncthreads();
+}
+
+template <typename T, int L, int NT, int R, int LGNS, int R2>
+__device__ __forceinline__ void exchange(cx<T>* v, cx<T>* s, int es, int t) {
+  constexpr int NB = L / (R * NT), NB2 = L / (R2 * NT);
+  constexpr int lgR = ilog2(R), Ns = 1 << LGNS;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int j = t + i * NT;
-    const int k = j & (Ns - 1);
-    const int d = ((j >> lgNs) << (lgNs + lgR)) + k;
+    const int d = ((j >> LGNS) << (LGNS + lgR)) + (j & (Ns - 1));
 #pragma unroll
-    for (int r = 0; r < R; ++r) s[(d + r * Ns) * es] = v[i][r];
+    for (int r = 0; r < R; ++r) s[(d + r * Ns) * es] = v[i * R + r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB2; ++i) {
+    const int j = t + i * NT;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) v[i * R2 + r] = s[(j + r * (L / R2)) * es];
   }
   __syncthreads();
 }
 
-// Full length-L transform in LDS: one radix-2 or radix-4 stage if log2 L is
-// not a multiple of 3, then radix-8 stages.
-template <typename T, int L, int NT, bool INV>
-__device__ __forceinline__ void fft_lds(cx<T>* s, int es, int t, const cx<T>* tw) {
-  constexpr int P = ilog2(L);
-  int lg = 0;
-  if constexpr (P % 3 == 1) {
-    stockham_stage<T, L, 2, NT, INV>(s, es, t, lg, tw);
-    lg = 1;
-  } else if constexpr (P % 3 == 2) {
-    stockham_stage<T, L, 4, NT, INV>(s, es, t, lg, tw);
-    lg = 2;
-  }
-#pragma unroll
-  for (int q = 0; q < P / 3; ++q) {
-    stockham_stage<T, L, 8, NT, INV>(s, es, t, lg, tw);
-    lg += 3;
+template <typename T, int L, int NT, bool INV, bool SF, int ST>
+__device__ __forceinline__ void run_stages(cx<T>* v, cx<T>* s, int es, int t, const cx<T>* tw) {
+  using Sc = Sched<L, SF>;
+  constexpr int R = Sc::radix(ST), LG = Sc::lgns(ST);
+  stage_compute<T, L, NT, INV, R, LG>(v, t, tw);
+  if constexpr (ST + 1 < Sc::NST) {
+    exchange<T, L, NT, R, LG, Sc::radix(ST + 1)>(v, s, es, t);
+    run_stages<T, L, NT, INV, SF, ST + 1>(v, s, es, t, tw);
   }
 }
 
 // ---------------------------------------------------------------------------
-// FFT pass kernels
+// FFT pass kernel.  Lines are addressed as (line >> lg_nli) * os + e * es +
+// (line & (2^lg_nli - 1)): column passes (y, z) have lg_nli = log2(Mx) so
+// that consecutive lines are consecutive x positions (coalesced rows of
+// TL elements); row passes (x) have lg_nli = 0, es = 1 and os = line pitch.
+// MODE 0: forward, 1: inverse, 2: forward * spectrum then inverse.
 // ---------------------------------------------------------------------------
-struct ColArgs {
-  int64_t nlines;        // total lines = nli * nlo
-  int lg_nli;            // log2 of lines along the contiguous dimension
-  int64_t in_es, in_os;  // element and outer strides of the input (elements)
-  int64_t out_es, out_os;
+struct PassArgs {
+  int64_t nlines;
+  int lg_nli;
+  int64_t in_es, in_os, out_es, out_os;
   int64_t in_bs, out_bs;  // per right-hand-side strides
   int Lin, Lout;          // leading elements read / written per line
   // spectral multiply (fused z pass): line (li, lo) = (kx, ky), element = kz
@@ -214,98 +235,78 @@ struct ColArgs {
   int Mx, Nx, My, Ny, Mz, Nz;
 };
 
-struct RowArgs {
-  int64_t nlines;
-  int64_t in_ls, out_ls;
-  int64_t in_bs, out_bs;
-  int Lin, Lout;
-};
-
-// MODE 0: forward, 1: inverse, 2: forward * spectrum then inverse.
-template <typename T, int L, int TL, int NT, int MODE>
-__global__ __launch_bounds__(TL* NT) void fft_col_kernel(const cx<T>* in, cx<T>* out,
-                                                         const cx<T>* __restrict__ twg, ColArgs a) {
-  __shared__ cx<T> s[L * TL];
-  __shared__ cx<T> tw[L];
+template <typename T, int L, int TL, int NT, int MODE, bool COL>
+__global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>* out,
+                                                          const cx<T>* __restrict__ twg,
+                                                          PassArgs a) {
+  constexpr int E = L / NT;
   constexpr int NTH = TL * NT;
+  __shared__ cx<T> s[COL ? L * TL : TL * (L + 1)];
+  __shared__ cx<T> tw[L];
   const int tid = threadIdx.x;
   const int rhs = blockIdx.y;
-  const int64_t line0 = int64_t(blockIdx.x) * TL;
   in += rhs * a.in_bs;
   out += rhs * a.out_bs;
-  const int64_t nli_mask = (int64_t(1) << a.lg_nli) - 1;
   for (int m = tid; m < L; m += NTH) tw[m] = twg[m];
-  for (int idx = tid; idx < L * TL; idx += NTH) {
-    const int l = idx & (TL - 1), e = idx / TL;
-    const int64_t line = line0 + l;
-    cx<T> v = mkc<T>(T(0), T(0));
-    if (e < a.Lin && line < a.nlines)
-      v = in[(line >> a.lg_nli) * a.in_os + e * a.in_es + (line & nli_mask)];
-    s[e * TL + l] = v;
-  }
+  const int l = COL ? (tid & (TL - 1)) : (tid / NT);
+  const int t = COL ? (tid / TL) : (tid & (NT - 1));
+  const int64_t line = int64_t(blockIdx.x) * TL + l;
+  const bool valid = line < a.nlines;
+  const int64_t mask = (int64_t(1) << a.lg_nli) - 1;
+  const int64_t li = line & mask, lo = line >> a.lg_nli;
+  const cx<T>* src = in + lo * a.in_os + li;
+  cx<T>* dst = out + lo * a.out_os + li;
+  cx<T>* sl = COL ? s + l : s + l * (L + 1);
+  const int es = COL ? TL : 1;
   __syncthreads();
-  const int l = tid & (TL - 1), t = tid / TL;
-  if constexpr (MODE == 1) {
-    fft_lds<T, L, NT, true>(s + l, TL, t, tw);
-  } else {
-    fft_lds<T, L, NT, false>(s + l, TL, t, tw);
-  }
+
+  constexpr bool SF = MODE != 1;
+  using S0 = Sched<L, SF>;
+  constexpr int R0 = S0::radix(0), NB0 = L / (R0 * NT);
+  cx<T> v[E];
+#pragma unroll
+  for (int i = 0; i < NB0; ++i)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int e = t + i * NT + r * (L / R0);
+      v[i * R0 + r] = (valid && e < a.Lin) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
+    }
+  run_stages<T, L, NT, MODE == 1, SF, 0>(v, sl, es, t, tw);
   if constexpr (MODE == 2) {
-    const int64_t line = line0 + l;
-    if (line < a.nlines) {
-      const int kx = int(line & nli_mask), ky = int(line >> a.lg_nli);
+    static_assert(Sched<L, true>::radix(Sched<L, true>::NST - 1) == 8, "forward must end in radix 8");
+    static_assert(Sched<L, false>::radix(0) == 8, "inverse must start in radix 8");
+    if (valid) {
+      const int kx = int(li), ky = int(lo);
       const int fx = kx <= a.Nx ? kx : a.Mx - kx;
       const int fy = ky <= a.Ny ? ky : a.My - ky;
-      const cx<T>* sp = static_cast<const cx<T>*>(a.spec) + int64_t(a.rhs_freq[rhs]) * a.spec_fs;
-      for (int e = t; e < L; e += NT) {
-        const int fz = e <= a.Nz ? e : a.Mz - e;
-        const cx<T> hv = sp[(int64_t(fz) * (a.Ny + 1) + fy) * (a.Nx + 1) + fx];
-        s[e * TL + l] = cmul(s[e * TL + l], hv);
-      }
+      const cx<T>* sp = static_cast<const cx<T>*>(a.spec) + int64_t(a.rhs_freq[rhs]) * a.spec_fs +
+                        int64_t(fy) * (a.Nx + 1) + fx;
+      const int64_t zst = int64_t(a.Ny + 1) * (a.Nx + 1);
+#pragma unroll
+      for (int i = 0; i < L / (8 * NT); ++i)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int e = t + i * NT + r * (L / 8);
+          const int fz = e <= a.Nz ? e : a.Mz - e;
+          v[i * 8 + r] = cmul(v[i * 8 + r], sp[fz * zst]);
+        }
     }
-    __syncthreads();
-    fft_lds<T, L, NT, true>(s + l, TL, t, tw);
+    run_stages<T, L, NT, true, false, 0>(v, sl, es, t, tw);
   }
-  for (int idx = tid; idx < a.Lout * TL; idx += NTH) {
-    const int ll = idx & (TL - 1), e = idx / TL;
-    const int64_t line = line0 + ll;
-    if (line < a.nlines)
-      out[(line >> a.lg_nli) * a.out_os + e * a.out_es + (line & nli_mask)] = s[e * TL + ll];
-  }
-}
-
-template <typename T, int L, int TL, int NT, bool INV>
-__global__ __launch_bounds__(TL* NT) void fft_row_kernel(const cx<T>* in, cx<T>* out,
-                                                         const cx<T>* __restrict__ twg, RowArgs a) {
-  constexpr int LP = L + 1;  // padded pitch staggers lines across LDS banks
-  __shared__ cx<T> s[TL * LP];
-  __shared__ cx<T> tw[L];
-  constexpr int NTH = TL * NT;
-  const int tid = threadIdx.x;
-  const int rhs = blockIdx.y;
-  const int64_t line0 = int64_t(blockIdx.x) * TL;
-  in += rhs * a.in_bs;
-  out += rhs * a.out_bs;
-  for (int m = tid; m < L; m += NTH) tw[m] = twg[m];
-  for (int idx = tid; idx < L * TL; idx += NTH) {
-    const int l = idx / L, e = idx & (L - 1);
-    const int64_t line = line0 + l;
-    cx<T> v = mkc<T>(T(0), T(0));
-    if (e < a.Lin && line < a.nlines) v = in[line * a.in_ls + e];
-    s[l * LP + e] = v;
-  }
-  __syncthreads();
-  const int l = tid / NT, t = tid & (NT - 1);
-  fft_lds<T, L, NT, INV>(s + l * LP, 1, t, tw);
-  const int lg_out = __builtin_ctz(unsigned(a.Lout));  // Lout is a power of two
-  for (int idx = tid; idx < a.Lout * TL; idx += NTH) {
-    const int ll = idx >> lg_out, e = idx & (a.Lout - 1);
-    const int64_t line = line0 + ll;
-    if (line < a.nlines) out[line * a.out_ls + e] = s[ll * LP + e];
+  using Sf = Sched<L, MODE == 0>;
+  constexpr int Rf = Sf::radix(Sf::NST - 1), NBf = L / (Rf * NT);
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < NBf; ++i)
+#pragma unroll
+      for (int r = 0; r < Rf; ++r) {
+        const int e = t + i * NT + r * (L / Rf);
+        if (e < a.Lout) dst[e * a.out_es] = v[i * Rf + r];
+      }
   }
 }
 
-// launch configuration: 256 threads, LDS <= 64 KB of line data
+// launch configuration: 256 threads per block
 template <typename T>
 struct ColCfg {
   static constexpr int kTLmin = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
@@ -320,63 +321,60 @@ struct PassCfg {
 };
 
 template <typename T, int L>
-void col_pass_L(int mode, const void* in, void* out, const void* tw, const ColArgs& a, int nrhs,
-                hipStream_t s) {
+void pass_L(bool col, int mode, const void* in, void* out, const void* tw, const PassArgs& a,
+            int nrhs, hipStream_t s) {
   using C = PassCfg<T, L>;
-  dim3 grid(unsigned((a.nlines + C::COL_TL - 1) / C::COL_TL), unsigned(nrhs));
   const cx<T>* i = static_cast<const cx<T>*>(in);
   cx<T>* o = static_cast<cx<T>*>(out);
   const cx<T>* w = static_cast<const cx<T>*>(tw);
-  if (mode == 0)
-    hipLaunchKernelGGL((fft_col_kernel<T, L, C::COL_TL, C::COL_NT, 0>), grid, dim3(256), 0, s, i, o, w, a);
-  else if (mode == 1)
-    hipLaunchKernelGGL((fft_col_kernel<T, L, C::COL_TL, C::COL_NT, 1>), grid, dim3(256), 0, s, i, o, w, a);
-  else
-    hipLaunchKernelGGL((fft_col_kernel<T, L, C::COL_TL, C::COL_NT, 2>), grid, dim3(256), 0, s, i, o, w, a);
-}
-
-template <typename T, int L>
-void row_pass_L(bool inv, const void* in, void* out, const void* tw, const RowArgs& a, int nrhs,
-                hipStream_t s) {
-  using C = PassCfg<T, L>;
-  dim3 grid(unsigned((a.nlines + C::ROW_TL - 1) / C::ROW_TL), unsigned(nrhs));
-  const cx<T>* i = static_cast<const cx<T>*>(in);
-  cx<T>* o = static_cast<cx<T>*>(out);
-  const cx<T>* w = static_cast<const cx<T>*>(tw);
-  if (inv)
-    hipLaunchKernelGGL((fft_row_kernel<T, L, C::ROW_TL, C::ROW_NT, true>), grid, dim3(256), 0, s, i, o, w, a);
-  else
-    hipLaunchKernelGGL((fft_row_kernel<T, L, C::ROW_TL, C::ROW_NT, false>), grid, dim3(256), 0, s, i, o, w, a);
+  if (col) {
+    dim3 grid(unsigned((a.nlines + C::COL_TL - 1) / C::COL_TL), unsigned(nrhs));
+    if (mode == 0)
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::COL_TL, C::COL_NT, 0, true>), grid, dim3(256), 0, s, i, o, w, a);
+    else if (mode == 1)
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::COL_TL, C::COL_NT, 1, true>), grid, dim3(256), 0, s, i, o, w, a);
+    else
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::COL_TL, C::COL_NT, 2, true>), grid, dim3(256), 0, s, i, o, w, a);
+  } else {
+    dim3 grid(unsigned((a.nlines + C::ROW_TL - 1) / C::ROW_TL), unsigned(nrhs));
+    if (mode == 0)
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::ROW_TL, C::ROW_NT, 0, false>), grid, dim3(256), 0, s, i, o, w, a);
+    else
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::ROW_TL, C::ROW_NT, 1, false>), grid, dim3(256), 0, s, i, o, w, a);
+  }
 }
 
 template <typename T>
-void col_pass(int L, int mode, const void* in, void* out, const void* tw, const ColArgs& a,
-              int nrhs, hipStream_t s) {
+void fft_pass(int L, bool col, int mode, const void* in, void* out, const void* tw,
+              const PassArgs& a, int nrhs, hipStream_t s) {
   switch (L) {
-    case 16: col_pass_L<T, 16>(mode, in, out, tw, a, nrhs, s); break;
-    case 32: col_pass_L<T, 32>(mode, in, out, tw, a, nrhs, s); break;
-    case 64: col_pass_L<T, 64>(mode, in, out, tw, a, nrhs, s); break;
-    case 128: col_pass_L<T, 128>(mode, in, out, tw, a, nrhs, s); break;
-    case 256: col_pass_L<T, 256>(mode, in, out, tw, a, nrhs, s); break;
-    case 512: col_pass_L<T, 512>(mode, in, out, tw, a, nrhs, s); break;
+    case 16: pass_L<T, 16>(col, mode, in, out, tw, a, nrhs, s); break;
+    case 32: pass_L<T, 32>(col, mode, in, out, tw, a, nrhs, s); break;
+    case 64: pass_L<T, 64>(col, mode, in, out, tw, a, nrhs, s); break;
+    case 128: pass_L<T, 128>(col, mode, in, out, tw, a, nrhs, s); break;
+    case 256: pass_L<T, 256>(col, mode, in, out, tw, a, nrhs, s); break;
+    case 512: pass_L<T, 512>(col, mode, in, out, tw, a, nrhs, s); break;
     default: throw Error(AIM_ERR_GRID, "unsupported FFT length");
   }
   AIM_HIP(hipGetLastError());
 }
 
+// row (x) pass over nlines contiguous lines
 template <typename T>
-void row_pass(int L, bool inv, const void* in, void* out, const void* tw, const RowArgs& a,
+void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_t nlines,
+              int64_t in_ls, int64_t out_ls, int64_t in_bs, int64_t out_bs, int Lin, int Lout,
               int nrhs, hipStream_t s) {
-  switch (L) {
-    case 16: row_pass_L<T, 16>(inv, in, out, tw, a, nrhs, s); break;
-    case 32: row_pass_L<T, 32>(inv, in, out, tw, a, nrhs, s); break;
-    case 64: row_pass_L<T, 64>(inv, in, out, tw, a, nrhs, s); break;
-    case 128: row_pass_L<T, 128>(inv, in, out, tw, a, nrhs, s); break;
-    case 256: row_pass_L<T, 256>(inv, in, out, tw, a, nrhs, s); break;
-    case 512: row_pass_L<T, 512>(inv, in, out, tw, a, nrhs, s); break;
-    default: throw Error(AIM_ERR_GRID, "unsupported FFT length");
-  }
-  AIM_HIP(hipGetLastError());
+  PassArgs a{};
+  a.nlines = nlines;
+  a.lg_nli = 0;
+  a.in_es = a.out_es = 1;
+  a.in_os = in_ls;
+  a.out_os = out_ls;
+  a.in_bs = in_bs;
+  a.out_bs = out_bs;
+  a.Lin = Lin;
+  a.Lout = Lout;
+  fft_pass<T>(L, false, inv ? 1 : 0, in, out, tw, a, nrhs, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,41 +384,42 @@ void row_pass(int L, bool inv, const void* in, void* out, const void* tw, const 
 // ---------------------------------------------------------------------------
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
-                     const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s) {
+                     const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
+                     hipEvent_t* between) {
+  auto mark = [&](int i) {
+    if (between) AIM_HIP(hipEventRecord(between[i], s));
+  };
   const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
   const int64_t Ng = g.Ng;
   cx<T>* B = static_cast<cx<T>*>(work);
   cx<T>* A = B + 4 * Ng;
-  // x forward: rows (y, z) of q, Nx -> Mx
-  {
-    RowArgs a{int64_t(Ny) * Nz, Nx, Mx, Ng, 6 * Ng, Nx, Mx};
-    row_pass<T>(Mx, false, q, A, tw[0], a, nrhs, s);
-  }
+  auto col_args = [&](int64_t nlines, int64_t in_es, int64_t in_os, int64_t out_es,
+                      int64_t out_os, int Lin, int Lout) {
+    PassArgs a{};
+    a.nlines = nlines;
+    a.lg_nli = ilog2(Mx);
+    a.in_es = in_es;
+    a.in_os = in_os;
+    a.out_es = out_es;
+    a.out_os = out_os;
+    a.in_bs = a.out_bs = 6 * Ng;
+    a.Lin = Lin;
+    a.Lout = Lout;
+    return a;
+  };
+  // x forward: rows (y, z) of q, Nx -> Mx, into A [Nz][Ny][Mx]
+  row_pass<T>(Mx, false, q, A, tw[0], int64_t(Ny) * Nz, Nx, Mx, Ng, 6 * Ng, Nx, Mx, nrhs, s);
+  mark(0);
   // y forward: A [Nz][Ny][Mx] -> B [Nz][My][Mx]
   {
-    ColArgs a{};
-    a.nlines = int64_t(Mx) * Nz;
-    a.lg_nli = ilog2(Mx);
-    a.in_es = Mx;
-    a.in_os = int64_t(Ny) * Mx;
-    a.out_es = Mx;
-    a.out_os = int64_t(My) * Mx;
-    a.in_bs = a.out_bs = 6 * Ng;
-    a.Lin = Ny;
-    a.Lout = My;
-    col_pass<T>(My, 0, A, B, tw[1], a, nrhs, s);
+    const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, int64_t(Ny) * Mx, Mx, int64_t(My) * Mx, Ny, My);
+    fft_pass<T>(My, true, 0, A, B, tw[1], a, nrhs, s);
   }
+  mark(1);
   // z forward * spectrum * z inverse, in place on B, keeping z < Nz
   {
-    ColArgs a{};
-    a.nlines = int64_t(Mx) * My;
-    a.lg_nli = ilog2(Mx);
-    a.in_es = a.out_es = int64_t(My) * Mx;
-    a.in_os = a.out_os = Mx;
-    a.in_bs = a.out_bs = 6 * Ng;
-    a.Lin = Nz;
-    a.Lout = Nz;
+    PassArgs a = col_args(int64_t(Mx) * My, int64_t(My) * Mx, Mx, int64_t(My) * Mx, Mx, Nz, Nz);
     a.spec = spec;
     a.spec_fs = g.Nfold;
     a.rhs_freq = rhs_freq;
@@ -430,33 +429,25 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     a.Ny = Ny;
     a.Mz = Mz;
     a.Nz = Nz;
-    col_pass<T>(Mz, 2, B, B, tw[2], a, nrhs, s);
+    fft_pass<T>(Mz, true, 2, B, B, tw[2], a, nrhs, s);
   }
+  mark(2);
   // y inverse: B [Nz][My][Mx] -> A [Nz][Ny][Mx]
   {
-    ColArgs a{};
-    a.nlines = int64_t(Mx) * Nz;
-    a.lg_nli = ilog2(Mx);
-    a.in_es = Mx;
-    a.in_os = int64_t(My) * Mx;
-    a.out_es = Mx;
-    a.out_os = int64_t(Ny) * Mx;
-    a.in_bs = a.out_bs = 6 * Ng;
-    a.Lin = My;
-    a.Lout = Ny;
-    col_pass<T>(My, 1, B, A, tw[1], a, nrhs, s);
+    const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, int64_t(My) * Mx, Mx, int64_t(Ny) * Mx, My, Ny);
+    fft_pass<T>(My, true, 1, B, A, tw[1], a, nrhs, s);
   }
+  mark(3);
   // x inverse: rows of A (Mx) -> phi (Nx)
-  {
-    RowArgs a{int64_t(Ny) * Nz, Mx, Nx, 6 * Ng, Ng, Mx, Nx};
-    row_pass<T>(Mx, true, A, phi, tw[0], a, nrhs, s);
-  }
+  row_pass<T>(Mx, true, A, phi, tw[0], int64_t(Ny) * Nz, Mx, Nx, 6 * Ng, Ng, Mx, Nx, nrhs, s);
 }
 
 template void launch_convolve<double>(const GridShape&, const void*, void*, void*, const void*,
-                                      const int32_t*, int, const void* const*, hipStream_t);
+                                      const int32_t*, int, const void* const*, hipStream_t,
+                                      hipEvent_t*);
 template void launch_convolve<float>(const GridShape&, const void*, void*, void*, const void*,
-                                     const int32_t*, int, const void* const*, hipStream_t);
+                                     const int32_t*, int, const void* const*, hipStream_t,
+                                     hipEvent_t*);
 
 // ---------------------------------------------------------------------------
 // kernel spectrum: circulant embedding of G on the padded grid, full 3-D FFT,
@@ -524,27 +515,24 @@ void launch_spectrum(const GridShape& g, double k, double h, void* full_work, vo
   hipLaunchKernelGGL(green_sample_kernel, dim3(4096), dim3(256), 0, s, F, Nx, Ny, Nz, k, h);
   AIM_HIP(hipGetLastError());
   const int64_t Np = int64_t(Mx) * My * Mz;
+  row_pass<double>(Mx, false, F, F, tw64[0], int64_t(My) * Mz, Mx, Mx, 0, 0, Mx, Mx, 1, s);
   {
-    RowArgs a{int64_t(My) * Mz, Mx, Mx, 0, 0, Mx, Mx};
-    row_pass<double>(Mx, false, F, F, tw64[0], a, 1, s);
-  }
-  {
-    ColArgs a{};
+    PassArgs a{};
     a.nlines = int64_t(Mx) * Mz;
     a.lg_nli = ilog2(Mx);
     a.in_es = a.out_es = Mx;
     a.in_os = a.out_os = int64_t(My) * Mx;
     a.Lin = a.Lout = My;
-    col_pass<double>(My, 0, F, F, tw64[1], a, 1, s);
+    fft_pass<double>(My, true, 0, F, F, tw64[1], a, 1, s);
   }
   {
-    ColArgs a{};
+    PassArgs a{};
     a.nlines = int64_t(Mx) * My;
     a.lg_nli = ilog2(Mx);
     a.in_es = a.out_es = int64_t(My) * Mx;
     a.in_os = a.out_os = Mx;
     a.Lin = a.Lout = Mz;
-    col_pass<double>(Mz, 0, F, F, tw64[2], a, 1, s);
+    fft_pass<double>(Mz, true, 0, F, F, tw64[2], a, 1, s);
   }
   hipLaunchKernelGGL(fold_spectrum_kernel, dim3(2048), dim3(256), 0, s, F,
                      static_cast<double2*>(spec64), static_cast<float2*>(spec32), Nx, Ny, Nz,
@@ -564,198 +552,160 @@ std::vector<double> twiddles64(int L) {
 }
 
 // ---------------------------------------------------------------------------
-// projection q = P x (brick-tiled, node-owner gather from an LDS source list)
+// projection q = P x
+//
+// P is assembled once at set-up (the quadrature-point stencil weights of each
+// triangle merged into one row per grid node, sorted by node) and cut into
+// blocks of consecutive rows holding at most kProjNnz non-zeros.  A block
+// loads all its non-zeros at once (coalesced, independent gathers of x) into
+// LDS, then each thread sums whole rows from LDS in a fixed order, so the
+// result is reproducible and no atomics are needed.  Nodes that no stencil
+// reaches get their zero written by the same pass.
 // ---------------------------------------------------------------------------
-template <typename T, int ORD>
-struct QpEntry {
-  int sx, sy, sz;
-  T wx[ORD + 1], wy[ORD + 1], wz[ORD + 1];
-  cx<T> amp;  // (A/3) x_j
-};
-
-template <typename T, int ORD>
-__device__ __forceinline__ void lagrange_dev(T u, T* out) {
-#pragma unroll
-  for (int a = 0; a <= ORD; ++a) {
-    T w = T(1);
-#pragma unroll
-    for (int b = 0; b <= ORD; ++b)
-      if (b != a) w = w * (u - T(b)) / T(a - b);
-    out[a] = w;
-  }
-}
-
-template <typename T, int ORD, int BX, int BY, int BZ>
-__global__ __launch_bounds__(BX* BY* BZ) void project_kernel(
-    const cx<T>* __restrict__ x, cx<T>* __restrict__ q, const int32_t* __restrict__ packed,
-    const T* __restrict__ local, const T* __restrict__ weight, const int32_t* __restrict__ bptr,
-    const int32_t* __restrict__ blist, int64_t nq, int64_t n, int Nx, int Ny, int Nz, int nbx,
-    int nby, int64_t Ng) {
-  constexpr int NTH = BX * BY * BZ;
-  __shared__ QpEntry<T, ORD> ent[NTH];
+template <typename T>
+__global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ x,
+                                                      cx<T>* __restrict__ q,
+                                                      const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const T* __restrict__ val,
+                                                      const int32_t* __restrict__ blk, int64_t n,
+                                                      int64_t Ng) {
+  __shared__ cx<T> prod[kProjNnz];
+  __shared__ T red[2 * 256];
   const int tid = threadIdx.x;
-  const int b = blockIdx.x;
   const int rhs = blockIdx.y;
-  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-  const int nx = bx * BX + (tid % BX);
-  const int ny = by * BY + ((tid / BX) % BY);
-  const int nz = bz * BZ + (tid / (BX * BY));
   x += rhs * n;
   q += rhs * Ng;
-  cx<T> acc = mkc<T>(T(0), T(0));
-  const int beg = bptr[b], end = bptr[b + 1];
-  for (int c0 = beg; c0 < end; c0 += NTH) {
-    const int cnt = min(NTH, end - c0);
-    if (tid < cnt) {
-      const int p = blist[c0 + tid];
-      const int pk = packed[p];
-      QpEntry<T, ORD> e;
-      e.sx = pk & 1023;
-      e.sy = (pk >> 10) & 1023;
-      e.sz = (pk >> 20) & 1023;
-      lagrange_dev<T, ORD>(local[p], e.wx);
-      lagrange_dev<T, ORD>(local[nq + p], e.wy);
-      lagrange_dev<T, ORD>(local[2 * nq + p], e.wz);
-      e.amp = cscale(x[p / 3], weight[p]);
-      ent[tid] = e;
+  const int r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
+  const int k0 = rowptr[r0], k1 = rowptr[r1];
+  if (k1 - k0 > kProjNnz) {  // one long row: strided partial sums, block reduction
+    T ar = T(0), ai = T(0);
+    for (int k = k0 + tid; k < k1; k += 256) {
+      const T w = val[k];
+      const cx<T> xv = x[col[k]];
+      ar += w * xv.x;
+      ai += w * xv.y;
     }
+    red[tid] = ar;
+    red[256 + tid] = ai;
     __syncthreads();
-    for (int i = 0; i < cnt; ++i) {
-      const int dx = nx - ent[i].sx, dy = ny - ent[i].sy, dz = nz - ent[i].sz;
-      if (unsigned(dx) <= unsigned(ORD) && unsigned(dy) <= unsigned(ORD) &&
-          unsigned(dz) <= unsigned(ORD)) {
-        const T w = ent[i].wx[dx] * ent[i].wy[dy] * ent[i].wz[dz];
-        acc.x += w * ent[i].amp.x;
-        acc.y += w * ent[i].amp.y;
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) {
+        red[tid] += red[tid + o];
+        red[256 + tid] += red[256 + tid + o];
       }
+      __syncthreads();
     }
-    __syncthreads();
+    if (tid == 0) q[r0] = mkc<T>(red[0], red[256]);
+    return;
   }
-  if (nx < Nx && ny < Ny && nz < Nz) q[(int64_t(nz) * Ny + ny) * Nx + nx] = acc;
+  // all non-zeros of the block at once (independent loads), then row sums
+  for (int k = k0 + tid; k < k1; k += 256) {
+    const T w = val[k];
+    const cx<T> xv = x[col[k]];
+    prod[k - k0] = mkc<T>(w * xv.x, w * xv.y);
+  }
+  __syncthreads();
+  for (int r = r0 + tid; r < r1; r += 256) {
+    T ar = T(0), ai = T(0);
+    const int e = rowptr[r + 1] - k0;
+    for (int k = rowptr[r] - k0; k < e; ++k) {
+      ar += prod[k].x;
+      ai += prod[k].y;
+    }
+    q[r] = mkc<T>(ar, ai);
+  }
 }
 
 template <typename T>
-void launch_project(const GridShape& g, int order, const QpDevice& qp, const int32_t* brick_ptr,
-                    const int32_t* brick_qp, const int bricks[3], const int nbrick[3],
+void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, int nblk,
                     const void* x, int64_t n, void* q, int nrhs, hipStream_t s) {
-  AIM_REQUIRE(bricks[0] == 8 && bricks[1] == 4 && bricks[2] == 4, AIM_ERR_STATE,
-              "projection bricks must be 8x4x4");
-  dim3 grid(unsigned(nbrick[0] * nbrick[1] * nbrick[2]), unsigned(nrhs));
-  const cx<T>* xi = static_cast<const cx<T>*>(x);
-  cx<T>* qo = static_cast<cx<T>*>(q);
-  const T* loc = static_cast<const T*>(qp.local);
-  const T* w = static_cast<const T*>(qp.weight);
-  if (order == 2)
-    hipLaunchKernelGGL((project_kernel<T, 2, 8, 4, 4>), grid, dim3(128), 0, s, xi, qo,
-                       qp.packed_start, loc, w, brick_ptr, brick_qp, qp.nq, n, g.N[0], g.N[1],
-                       g.N[2], nbrick[0], nbrick[1], g.Ng);
-  else
-    hipLaunchKernelGGL((project_kernel<T, 3, 8, 4, 4>), grid, dim3(128), 0, s, xi, qo,
-                       qp.packed_start, loc, w, brick_ptr, brick_qp, qp.nq, n, g.N[0], g.N[1],
-                       g.N[2], nbrick[0], nbrick[1], g.Ng);
+  hipLaunchKernelGGL(project_kernel<T>, dim3(unsigned(nblk), unsigned(nrhs)), dim3(256), 0, s,
+                     static_cast<const cx<T>*>(x), static_cast<cx<T>*>(q), P.rowptr, P.col,
+                     static_cast<const T*>(P.val), blk, n, g.Ng);
   AIM_HIP(hipGetLastError());
 }
 
-template void launch_project<double>(const GridShape&, int, const QpDevice&, const int32_t*,
-                                     const int32_t*, const int*, const int*, const void*, int64_t,
-                                     void*, int, hipStream_t);
-template void launch_project<float>(const GridShape&, int, const QpDevice&, const int32_t*,
-                                    const int32_t*, const int*, const int*, const void*, int64_t,
-                                    void*, int, hipStream_t);
+template void launch_project<double>(const GridShape&, const CsrDevice&, const int32_t*, int,
+                                     const void*, int64_t, void*, int, hipStream_t);
+template void launch_project<float>(const GridShape&, const CsrDevice&, const int32_t*, int,
+                                    const void*, int64_t, void*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// interpolation y = P^T phi and near correction y += C x (one thread per row)
+// interpolation y = P^T phi and near correction y += C x
+//
+// LPR lanes share one basis function: they stride over its row of P^T
+// (grid potentials at the stencil nodes of its three quadrature points) and
+// then over its row of C, and a reduction across the LPR lanes gives y_i.
 // ---------------------------------------------------------------------------
-template <typename T, int ORD, bool INTERP, bool NEARC>
+template <int LPR, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T, int LPR, bool INTERP, bool NEARC>
 __global__ __launch_bounds__(256) void interp_near_kernel(
     const cx<T>* __restrict__ phi, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
-    const int32_t* __restrict__ packed, const T* __restrict__ local, const T* __restrict__ weight,
+    const int32_t* __restrict__ prow, const int32_t* __restrict__ pcol, const T* __restrict__ pval,
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const T* __restrict__ val, int64_t n, int64_t nq, int Nx, int Ny, int64_t Ng) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const T* __restrict__ val, int64_t n, int64_t Ng) {
+  const int sub = threadIdx.x % LPR;
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
   const int rhs = blockIdx.y;
-  if (i >= n) return;
-  cx<T> acc = mkc<T>(T(0), T(0));
-  if constexpr (INTERP) {
-    const cx<T>* ph = phi + rhs * Ng;
-#pragma unroll
-    for (int qq = 0; qq < 3; ++qq) {
-      const int64_t p = 3 * i + qq;
-      const int pk = packed[p];
-      const int sx = pk & 1023, sy = (pk >> 10) & 1023, sz = (pk >> 20) & 1023;
-      T wx[ORD + 1], wy[ORD + 1], wz[ORD + 1];
-      lagrange_dev<T, ORD>(local[p], wx);
-      lagrange_dev<T, ORD>(local[nq + p], wy);
-      lagrange_dev<T, ORD>(local[2 * nq + p], wz);
-      const cx<T>* base = ph + (int64_t(sz) * Ny + sy) * Nx + sx;
-      cx<T> sq = mkc<T>(T(0), T(0));
-#pragma unroll
-      for (int c = 0; c <= ORD; ++c) {
-#pragma unroll
-        for (int b = 0; b <= ORD; ++b) {
-          const cx<T>* rowp = base + (int64_t(c) * Ny + b) * Nx;
-          cx<T> sr = mkc<T>(T(0), T(0));
-#pragma unroll
-          for (int a = 0; a <= ORD; ++a) {
-            const cx<T> v = rowp[a];
-            sr.x += wx[a] * v.x;
-            sr.y += wx[a] * v.y;
-          }
-          const T wyz = wy[b] * wz[c];
-          sq.x += wyz * sr.x;
-          sq.y += wyz * sr.y;
-        }
+  T ar = T(0), ai = T(0);
+  if (i < n) {
+    if constexpr (INTERP) {
+      const cx<T>* ph = phi + rhs * Ng;
+      for (int k = prow[i] + sub; k < prow[i + 1]; k += LPR) {
+        const T w = pval[k];
+        const cx<T> v = ph[pcol[k]];
+        ar += w * v.x;
+        ai += w * v.y;
       }
-      const T w = weight[p];
-      acc.x += w * sq.x;
-      acc.y += w * sq.y;
+    }
+    if constexpr (NEARC) {
+      const cx<T>* xr = x + rhs * n;
+      for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
+        const T v = val[k];
+        const cx<T> xv = xr[col[k]];
+        ar += v * xv.x;
+        ai += v * xv.y;
+      }
     }
   }
-  if constexpr (NEARC) {
-    const cx<T>* xr = x + rhs * n;
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-      const T v = val[k];
-      const cx<T> xv = xr[col[k]];
-      acc.x += v * xv.x;
-      acc.y += v * xv.y;
-    }
-  }
-  y[rhs * n + i] = acc;
+  ar = group_sum<LPR>(ar);
+  ai = group_sum<LPR>(ai);
+  if (sub == 0 && i < n) y[rhs * n + i] = mkc<T>(ar, ai);
 }
 
 template <typename T>
-void launch_interp_near(const GridShape& g, int order, const QpDevice& qp, const CsrDevice& csr,
+void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice& csr,
                         const void* phi, const void* x, void* y, int nrhs, bool do_interp,
                         bool do_near, hipStream_t s) {
+  constexpr int LPR = 16;
   const int64_t n = csr.n;
-  dim3 grid(unsigned((n + 255) / 256), unsigned(nrhs));
+  dim3 grid(unsigned((n * LPR + 255) / 256), unsigned(nrhs));
   const cx<T>* ph = static_cast<const cx<T>*>(phi);
   const cx<T>* xi = static_cast<const cx<T>*>(x);
   cx<T>* yo = static_cast<cx<T>*>(y);
-  const T* loc = static_cast<const T*>(qp.local);
-  const T* w = static_cast<const T*>(qp.weight);
+  const T* pv = static_cast<const T*>(Pt.val);
   const T* v = static_cast<const T*>(csr.val);
-#define AIM_IN_LAUNCH(ORD, I, NR)                                                               \
-  hipLaunchKernelGGL((interp_near_kernel<T, ORD, I, NR>), grid, dim3(256), 0, s, ph, xi, yo,    \
-                     qp.packed_start, loc, w, csr.rowptr, csr.col, v, n, qp.nq, g.N[0], g.N[1], \
-                     g.Ng)
-  if (order == 2) {
-    if (do_interp && do_near) AIM_IN_LAUNCH(2, true, true);
-    else if (do_interp) AIM_IN_LAUNCH(2, true, false);
-    else AIM_IN_LAUNCH(2, false, true);
-  } else {
-    if (do_interp && do_near) AIM_IN_LAUNCH(3, true, true);
-    else if (do_interp) AIM_IN_LAUNCH(3, true, false);
-    else AIM_IN_LAUNCH(3, false, true);
-  }
+#define AIM_IN_LAUNCH(I, NR)                                                                  \
+  hipLaunchKernelGGL((interp_near_kernel<T, LPR, I, NR>), grid, dim3(256), 0, s, ph, xi, yo,  \
+                     Pt.rowptr, Pt.col, pv, csr.rowptr, csr.col, v, n, g.Ng)
+  if (do_interp && do_near) AIM_IN_LAUNCH(true, true);
+  else if (do_interp) AIM_IN_LAUNCH(true, false);
+  else AIM_IN_LAUNCH(false, true);
 #undef AIM_IN_LAUNCH
   AIM_HIP(hipGetLastError());
 }
 
-template void launch_interp_near<double>(const GridShape&, int, const QpDevice&, const CsrDevice&,
+template void launch_interp_near<double>(const GridShape&, const CsrDevice&, const CsrDevice&,
                                          const void*, const void*, void*, int, bool, bool,
                                          hipStream_t);
-template void launch_interp_near<float>(const GridShape&, int, const QpDevice&, const CsrDevice&,
+template void launch_interp_near<float>(const GridShape&, const CsrDevice&, const CsrDevice&,
                                         const void*, const void*, void*, int, bool, bool,
                                         hipStream_t);
 

@@ -13,7 +13,8 @@
 //  * A_s,P = W H_s,NR P on the near list (eq. aimLPs, H_s self term 0 per
 //    eq. Hsmm), evaluated per quadrature-point pair through the separable
 //    correlation of the two stencils' 1-D weights;
-//  * projection bricks and near-block preconditioner clusters.
+//  * the projection matrix P (merged over each triangle's three points) in
+//    two sparse layouts, and near-block preconditioner clusters.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -366,29 +367,82 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t) {
       }
   });
 
-  // -- projection bricks -------------------------------------------------------
-  const int64_t Nq = 3 * N;
-  for (int a = 0; a < 3; ++a) t.nbrick[a] = (t.dims[a] + t.brick[a] - 1) / t.brick[a];
-  const int64_t nb = int64_t(t.nbrick[0]) * t.nbrick[1] * t.nbrick[2];
-  t.brick_ptr.assign(nb + 1, 0);
-  auto for_bricks = [&](int64_t p, auto&& f) {
-    int b0[3], b1[3];
-    for (int a = 0; a < 3; ++a) {
-      b0[a] = t.qp_start[3 * p + a] / t.brick[a];
-      b1[a] = (t.qp_start[3 * p + a] + n) / t.brick[a];
-    }
-    for (int z = b0[2]; z <= b1[2]; ++z)
-      for (int y = b0[1]; y <= b1[1]; ++y)
-        for (int x = b0[0]; x <= b1[0]; ++x) f((int64_t(z) * t.nbrick[1] + y) * t.nbrick[0] + x);
-  };
-  for (int64_t p = 0; p < Nq; ++p) for_bricks(p, [&](int64_t bi) { t.brick_ptr[bi + 1]++; });
-  for (int64_t b = 0; b < nb; ++b) t.brick_ptr[b + 1] += t.brick_ptr[b];
-  AIM_REQUIRE(t.brick_ptr[nb] < (int64_t(1) << 31), AIM_ERR_INVALID_ARG, "too many stencils");
-  t.brick_qp.resize(t.brick_ptr[nb]);
+  // -- projection matrix P (merged per triangle) -------------------------------
   {
-    std::vector<int32_t> fill(t.brick_ptr.begin(), t.brick_ptr.end() - 1);
-    for (int64_t p = 0; p < Nq; ++p)
-      for_bricks(p, [&](int64_t bi) { t.brick_qp[fill[bi]++] = int32_t(p); });
+    const int64_t Ng = int64_t(t.dims[0]) * t.dims[1] * t.dims[2];
+    const int S3 = S * S * S;
+    t.pt_rowptr.assign(N + 1, 0);
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(N);
+    parallel_for(N, nthreads, [&](int64_t b, int64_t e) {
+      std::vector<std::pair<int32_t, double>> tmp;
+      for (int64_t j = b; j < e; ++j) {
+        tmp.clear();
+        for (int qd = 0; qd < 3; ++qd) {
+          const int64_t p = 3 * j + qd;
+          const int* s0 = &t.qp_start[3 * p];
+          const double* lx = &lw[(3 * p + 0) * S];
+          const double* ly = &lw[(3 * p + 1) * S];
+          const double* lz = &lw[(3 * p + 2) * S];
+          for (int c = 0; c < S; ++c)
+            for (int bb = 0; bb < S; ++bb)
+              for (int a = 0; a < S; ++a) {
+                const int32_t u = int32_t((int64_t(s0[2] + c) * t.dims[1] + (s0[1] + bb)) *
+                                              t.dims[0] + s0[0] + a);
+                tmp.push_back({u, t.qp_w[p] * (lx[a] * ly[bb] * lz[c])});
+              }
+        }
+        std::stable_sort(tmp.begin(), tmp.end(),
+                         [](const auto& x, const auto& y) { return x.first < y.first; });
+        auto& r = rows[j];
+        r.reserve(std::min<size_t>(tmp.size(), size_t(3 * S3)));
+        for (const auto& pr : tmp) {
+          if (!r.empty() && r.back().first == pr.first)
+            r.back().second += pr.second;
+          else
+            r.push_back(pr);
+        }
+      }
+    });
+    for (int64_t j = 0; j < N; ++j) t.pt_rowptr[j + 1] = t.pt_rowptr[j] + int32_t(rows[j].size());
+    const int64_t nnzp = t.pt_rowptr[N];
+    AIM_REQUIRE(nnzp < (int64_t(1) << 31), AIM_ERR_INVALID_ARG, "projection matrix too large");
+    t.pt_col.resize(nnzp);
+    t.pt_val.resize(nnzp);
+    t.p_rowptr.assign(Ng + 1, 0);
+    for (int64_t j = 0; j < N; ++j)
+      for (int64_t k = 0; k < int64_t(rows[j].size()); ++k) {
+        t.pt_col[t.pt_rowptr[j] + k] = rows[j][k].first;
+        t.pt_val[t.pt_rowptr[j] + k] = rows[j][k].second;
+        t.p_rowptr[rows[j][k].first + 1]++;
+      }
+    rows.clear();
+    rows.shrink_to_fit();
+    for (int64_t u = 0; u < Ng; ++u) t.p_rowptr[u + 1] += t.p_rowptr[u];
+    t.p_col.resize(nnzp);
+    t.p_val.resize(nnzp);
+    std::vector<int32_t> fill(t.p_rowptr.begin(), t.p_rowptr.end() - 1);
+    for (int64_t j = 0; j < N; ++j)  // ascending j keeps each node row sorted
+      for (int64_t k = t.pt_rowptr[j]; k < t.pt_rowptr[j + 1]; ++k) {
+        const int32_t u = t.pt_col[k];
+        t.p_col[fill[u]] = int32_t(j);
+        t.p_val[fill[u]++] = t.pt_val[k];
+      }
+    // row blocks: consecutive rows with at most kProjNnz non-zeros and
+    // kProjRows rows; a longer row forms a block of its own
+    t.p_blk.assign(1, 0);
+    int64_t r = 0;
+    while (r < Ng) {
+      int64_t e = r, nz = 0;
+      while (e < Ng && e - r < kProjRows) {
+        const int64_t len = t.p_rowptr[e + 1] - t.p_rowptr[e];
+        if (e > r && nz + len > kProjNnz) break;
+        nz += len;
+        ++e;
+        if (nz > kProjNnz) break;  // a single long row
+      }
+      t.p_blk.push_back(int32_t(e));
+      r = e;
+    }
   }
 
   // -- near-block preconditioner clusters (recursive coordinate bisection) ----
