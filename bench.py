@@ -116,6 +116,8 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -131,6 +133,21 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            b.copy_(a)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / 5
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+        return 0
     w = make_workload(args.workload)
     print(f"[bench] workload {w.name}: N={w.n} dims={w.dims} order={w.order} "
           f"prec={args.prec} nrhs={args.nrhs}", file=sys.stderr, flush=True)
