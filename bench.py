@@ -106,6 +106,36 @@ def cpu_baseline(w, x, reps: int = 3, near_rows: int = 512) -> dict:
             "seconds_per_matvec": t}
 
 
+RESTART = 60
+
+
+def solve_leg(plan, rtol: float) -> dict:
+    """Time to rtol for the +z plane wave: complex128 GMRES(RESTART) without
+    preconditioner (the reference) against complex64-matvec GMRES inside
+    complex128 refinement, with the static preconditioners."""
+    import torch
+    b = plan.excitation("plane_wave", [0.0, 0.0, 1.0])
+    runs = [("c128", "none"), ("c128", "diag"), ("c64", "none"), ("c64", "diag")]
+    res = {}
+    for inner, pc in runs:
+        plan.solve(b, rtol=1e-2, restart=RESTART, max_iter=30, inner=inner, pc=pc,
+                   raise_on_fail=False)                    # warm-up (workspace, graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, r = plan.solve(b, rtol=rtol, restart=RESTART, max_iter=4000, inner=inner, pc=pc,
+                          max_refine=20, raise_on_fail=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[f"{inner}+{pc}"] = {"seconds": dt, "iters": int(r.iters[0]),
+                                "matvecs": int(r.matvecs[0]),
+                                "refinements": int(r.refinements[0]),
+                                "rel_resid": float(r.rel_resid[0]),
+                                "converged": bool(r.converged[0])}
+        print(f"[bench] gmres {inner}+{pc}: {dt:.3f}s iters={r.iters[0]} "
+              f"resid={r.rel_resid[0]:.2e}", file=sys.stderr, flush=True)
+    return {"rtol": rtol, "rhs": "plane wave +z", "restart": RESTART, "runs": res}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +146,8 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--no-solve", action="store_true", help="skip the GMRES time-to-tolerance leg")
+    ap.add_argument("--solve-rtol", type=float, default=1e-6)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -152,13 +184,20 @@ def main() -> int:
     print(f"[bench] workload {w.name}: N={w.n} dims={w.dims} order={w.order} "
           f"prec={args.prec} nrhs={args.nrhs}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
+    precs = ("c128", "c64") if not args.no_solve else (args.prec,)
     plan = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
-                        precisions=(args.prec,), max_rhs=args.nrhs)
+                        precisions=precs, max_rhs=args.nrhs)
     setup_s = time.perf_counter() - t0
     info = plan.info()
     print(f"[bench] setup {setup_s:.2f}s (host tables {info['setup_seconds']:.2f}s, "
           f"spectra {info['spectra_seconds']:.3f}s), nnz={info['nnz']}", file=sys.stderr,
           flush=True)
+    tuned = {}
+    for pr in precs:
+        tuned[pr] = plan.autotune(prec=pr, nrhs=args.nrhs, reps=5)
+        print(f"[bench] autotuned FFT launch shapes ({pr}): {tuned[pr]['schedule']} "
+              f"pass ms {[round(t, 4) for t in tuned[pr]['pass_ms']]}", file=sys.stderr,
+              flush=True)
     dtype = torch.complex128 if args.prec == "c128" else torch.complex64
     xh = I.complex_gaussian(w.n, w.seed_base + 1, nrhs=args.nrhs)
     x = torch.from_numpy(xh).to(dtype).cuda()
@@ -195,6 +234,7 @@ def main() -> int:
                    "grid": list(w.dims), "padded_grid": [2 * d for d in w.dims],
                    "near_threshold_h": w.near_factor, "k": float(w.k[0]),
                    "nrhs": args.nrhs, "nnz": info["nnz"]},
+        "fft_schedule": {pr: tuned[pr]["schedule"] for pr in tuned},
     }
 
     if not args.no_profile:
@@ -215,6 +255,9 @@ def main() -> int:
         out["matvec_alg_gbs"] = total_b / (ms * 1e-3) / 1e9
         print(f"[bench] kernels (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in kms.items()),
               file=sys.stderr, flush=True)
+
+    if not args.no_solve:
+        out["gmres"] = solve_leg(plan, args.solve_rtol)
 
     if not args.no_cpu:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)

@@ -77,6 +77,7 @@ typedef enum {
 typedef enum { AIM_RHS_PLANE_WAVE = 0, AIM_RHS_GAUSSIAN_PATCH = 1 } aim_rhs_kind;
 
 typedef struct aim_plan_s* aim_plan;
+typedef struct aim_graph_s* aim_graph;
 
 /* Optional device allocator (e.g. a framework's caching allocator).  When
  * alloc is NULL the library uses hipMalloc / hipFree. */
@@ -134,12 +135,16 @@ typedef struct {
  * Arnoldi orthogonalisation is always complex128 on the device. */
 typedef struct {
   double rtol;               /* target relative residual (> 0)                    */
+  /* (the solver replays captured matvec graphs; set AIM_SOLVER_GRAPHS=0 in
+     the environment to launch kernels one by one instead) */
   int32_t restart;           /* Krylov subspace size m (1..200)                   */
   int32_t max_iter;          /* cap on inner iterations per right-hand side       */
   int32_t max_refine;        /* cap on refinement steps (inner = AIM_C64)          */
   aim_precision inner;       /* precision of the Krylov matvecs                    */
   aim_pc_kind pc;            /* right preconditioner                               */
-  double inner_rtol;         /* inner tolerance per refinement step (0: 1e-4)     */
+  double inner_rtol;         /* inner tolerance per refinement step (0: adaptive,
+                                0.3 rtol / current residual, kept within
+                                [3e-6, 0.1])                                      */
 } aim_solve_opts;
 
 /* Per-right-hand-side outcome (host array of nrhs entries). */
@@ -225,6 +230,34 @@ aim_status aim_solve(aim_plan plan, const void* b_dev, void* x_dev, int32_t nrhs
 aim_status aim_profile_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
                               int32_t nrhs, const int32_t* freq_idx_host, int32_t reps,
                               double* kernel_ms_host, void* hip_stream);
+
+/* Captures one aim_matvec (the seven kernels of eq. LAIMx's product: P x,
+ * the five FFT passes with the spectral multiply, P^T phi + C x) on the given
+ * buffers, precision, batch width and frequency indices into an
+ * instantiated HIP graph.  aim_graph_launch replays it on any stream; the
+ * buffers, the plan and its schedule must stay as they were at capture.
+ * The graph holds no memset nodes.  Errors as aim_matvec. */
+aim_status aim_matvec_capture(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
+                              int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream,
+                              aim_graph* out);
+aim_status aim_graph_launch(aim_graph graph, void* hip_stream);
+aim_status aim_graph_destroy(aim_graph graph);  /* NULL is a no-op */
+
+/* Launch-shape autotuner for the five FFT passes of the convolution (x
+ * forward, y forward, z forward * spectrum * inverse, y inverse, x inverse):
+ * times every available shape (lines per workgroup x threads per line) of
+ * each pass over `reps` runs with nrhs right-hand sides on hip_stream, keeps
+ * the fastest per pass in the plan for this precision, and returns the
+ * choices in sched_out[5] and their average times (ms) in pass_ms_out[5]
+ * (either may be NULL).  Overwrites the plan's internal grid workspace;
+ * blocking.  The schedule does not change results beyond rounding order. */
+aim_status aim_autotune(aim_plan plan, aim_precision prec, int32_t nrhs, int32_t reps,
+                        int32_t* sched_out, double* pass_ms_out, void* hip_stream);
+
+/* Installs a schedule returned earlier by aim_autotune (for example from a
+ * cache keyed by grid, precision and batch width).  AIM_ERR_INVALID_ARG if a
+ * shape is out of range or not available for that pass. */
+aim_status aim_set_schedule(aim_plan plan, aim_precision prec, const int32_t* sched);
 
 /* Host copies of setup tables, for validation against an independent
  * implementation.  Any pointer may be NULL to skip that table.

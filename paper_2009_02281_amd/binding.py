@@ -26,6 +26,8 @@ RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
+            "aim_autotune", "aim_set_schedule", "aim_matvec_capture", "aim_graph_launch",
+            "aim_graph_destroy",
             "aim_last_error", "aim_version"]
 KERNELS = ["project", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
            "interp_near"]
@@ -107,6 +109,11 @@ def load_library(path: str = LIB_PATH):
                                       ip32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.aim_profile_matvec.argtypes = [vp, i32, vp, vp, i32, ip32, i32,
                                        C.POINTER(C.c_double), vp]
+    lib.aim_matvec_capture.argtypes = [vp, i32, vp, vp, i32, ip32, vp, C.POINTER(vp)]
+    lib.aim_graph_launch.argtypes = [vp, vp]
+    lib.aim_graph_destroy.argtypes = [vp]
+    lib.aim_autotune.argtypes = [vp, i32, i32, i32, ip32, C.POINTER(C.c_double), vp]
+    lib.aim_set_schedule.argtypes = [vp, i32, ip32]
     lib.aim_last_error.restype = C.c_char_p
     lib.aim_version.restype = C.c_char_p
     for name in EXPORTED:
@@ -143,6 +150,27 @@ class SolveResult:
     rel_resid: np.ndarray
     seconds: float
     status: int
+
+
+class MatvecGraph:
+    """A captured matvec (see aim_matvec_capture); keeps its tensors alive."""
+
+    def __init__(self, lib, handle, keep):
+        self._lib, self._g, self._keep = lib, handle, keep
+
+    def launch(self, stream=None):
+        _check(self._lib.aim_graph_launch(self._g, _stream_ptr(stream)))
+
+    def close(self):
+        if self._g and self._g.value:
+            _check(self._lib.aim_graph_destroy(self._g))
+            self._g = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:
@@ -275,6 +303,48 @@ class Plan:
                                             C.c_void_p(y.data_ptr()), nrhs, fp, int(reps), ms,
                                             _stream_ptr(stream)))
         return {k: float(ms[i]) for i, k in enumerate(KERNELS)}
+
+    def capture_matvec(self, x, y, freq_idx=None, prec: str = "c128", stream=None):
+        """Captures y = A x on these tensors into a replayable graph."""
+        self._check_vec(x, prec, self.n, "x")
+        self._check_vec(y, prec, self.n, "y")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _, fp = _freq_arg(freq_idx, nrhs)
+        g = C.c_void_p()
+        _check(self._lib.aim_matvec_capture(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(y.data_ptr()), nrhs, fp,
+                                            _stream_ptr(stream), C.byref(g)))
+        return MatvecGraph(self._lib, g, (x, y))
+
+    def autotune(self, prec: str = "c128", nrhs: int = 1, reps: int = 5, cache_path=None,
+                 stream=None) -> dict:
+        """Picks the FFT launch shapes for this plan.  With ``cache_path`` a
+        JSON file keyed by (grid, precision, nrhs, gfx950) is read first and
+        updated after tuning."""
+        import json
+        key = f"gfx950|{'x'.join(map(str, self.dims))}|{prec}|nrhs={nrhs}"
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        if key in cache:
+            sched = (C.c_int32 * 5)(*cache[key]["schedule"])
+            _check(self._lib.aim_set_schedule(self._plan, PREC[prec], sched))
+            return dict(cache[key], cached=True)
+        sched = (C.c_int32 * 5)()
+        ms = (C.c_double * 5)()
+        _check(self._lib.aim_autotune(self._plan, PREC[prec], int(nrhs), int(reps), sched, ms,
+                                      _stream_ptr(stream)))
+        ent = {"schedule": list(sched), "pass_ms": list(ms)}
+        if cache_path:
+            cache[key] = ent
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        return dict(ent, cached=False)
+
+    def set_schedule(self, sched, prec: str = "c128"):
+        arr = (C.c_int32 * 5)(*sched)
+        _check(self._lib.aim_set_schedule(self._plan, PREC[prec], arr))
 
     def apply_stage(self, stage: str, inp, freq_idx=None, prec: str = "c128", stream=None):
         """One stage of the matvec: 'project' x -> grid, 'convolve' grid ->

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -21,6 +22,15 @@
 #include "aim_internal.h"
 
 using aim::Error;
+
+struct aim_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~aim_graph_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
 
 namespace {
 thread_local std::string g_last_error;
@@ -98,9 +108,19 @@ struct aim_plan_s {
   double* d_k = nullptr;
   void* d_work[2] = {nullptr, nullptr};  // [prec] 6 Ng per rhs
   void* d_grid[2] = {nullptr, nullptr};  // [prec] Ng per rhs
+  int sched[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};  // FFT launch shapes per precision
   int32_t* d_rhs_freq = nullptr;          // [max_rhs]
   int32_t* h_rhs_freq = nullptr;          // pinned staging
   std::vector<int32_t> cur_freq;          // what d_rhs_freq holds
+
+  // captured matvec graphs used by the solver, keyed by (prec, nrhs, in, out, freq)
+  struct GraphKey {
+    int prec, nrhs;
+    const void* in;
+    void* out;
+    std::vector<int32_t> freq;
+  };
+  std::vector<std::pair<GraphKey, std::unique_ptr<aim_graph_s>>> graphs;
 
   // solver workspace (grown on demand)
   struct Solver {
@@ -108,7 +128,7 @@ struct aim_plan_s {
     int64_t n = 0;
     void *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *bp = nullptr,
          *xp = nullptr, *h = nullptr, *h2 = nullptr, *y = nullptr, *partial = nullptr,
-         *c64a = nullptr, *c64b = nullptr;
+         *c64a = nullptr, *c64b = nullptr, *ain = nullptr;
     double* nrm = nullptr;
     int32_t* idx = nullptr;
     int32_t* freq = nullptr;
@@ -141,6 +161,7 @@ struct aim_plan_s {
   }
   ~aim_plan_s() {
     if (host_only) return;
+    graphs.clear();
     if (setup_stream) (void)hipStreamSynchronize(setup_stream);
     (void)hipDeviceSynchronize();
     for (auto& o : owned) {
@@ -227,7 +248,7 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
   aim::launch_project<T>(p->g, p_dev(p, prec), p->d_pblk, p->nblk, x, p->t.N, grid, nrhs, s);
   if (ev) AIM_HIP(hipEventRecord(ev[1], s));
   aim::launch_convolve<T>(p->g, grid, p->d_work[pi], grid, spec, dfreq, nrhs, tw, s,
-                          ev ? ev + 2 : nullptr);
+                          ev ? ev + 2 : nullptr, p->sched[pi]);
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
   aim::launch_interp_near<T>(p->g, pt_dev(p, prec), csr_dev(p, prec), grid, x, y, nrhs, true,
                              true, s);
@@ -242,10 +263,60 @@ void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs
     matvec_impl<float>(p, prec, x, y, nrhs, dfreq, s, ev);
 }
 
+// Captures matvec_any on the given operands into an instantiated graph.
+std::unique_ptr<aim_graph_s> capture_matvec(aim_plan p, aim_precision prec, const void* x, void* y,
+                                            int nrhs, const int32_t* dfreq, hipStream_t s) {
+  // the default (legacy) stream cannot be captured: capture on a private one
+  hipStream_t cs = nullptr;
+  AIM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  AIM_HIP(hipStreamSynchronize(s));  // frequency indices uploaded on s are in place
+  std::unique_ptr<aim_graph_s> g(new aim_graph_s());
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    try {
+      matvec_any(p, prec, x, y, nrhs, dfreq, cs);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(cs, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      (void)hipStreamDestroy(cs);
+      throw;
+    }
+    e = hipStreamEndCapture(cs, &g->graph);
+  }
+  (void)hipStreamDestroy(cs);
+  AIM_HIP(e);
+  AIM_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  return g;
+}
+
 }  // namespace
 
 // ===========================================================================
 extern "C" {
+
+aim_status aim_matvec_capture(aim_plan p, aim_precision prec, const void* x, void* y,
+                              int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream,
+                              aim_graph* out) {
+  if (!p || !x || !y || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  return guarded([&] {
+    check_prec(p, prec);
+    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    *out = capture_matvec(p, prec, x, y, nrhs, df, s).release();
+  });
+}
+
+aim_status aim_graph_launch(aim_graph g, void* hip_stream) {
+  if (!g || !g->exec) return fail(AIM_ERR_INVALID_ARG, "null graph");
+  return guarded([&] { AIM_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream))); });
+}
+
+aim_status aim_graph_destroy(aim_graph g) {
+  return guarded([&] { delete g; });
+}
 
 const char* aim_last_error(void) { return g_last_error.c_str(); }
 const char* aim_version(void) { return "aimx-gfx950 0.1"; }
@@ -484,6 +555,97 @@ aim_status aim_profile_matvec(aim_plan p, aim_precision prec, const void* x, voi
   });
 }
 
+// the five FFT passes: (length index into g.M, column pass?)
+static const int kPassAxis[5] = {0, 1, 2, 1, 0};
+static const bool kPassCol[5] = {false, true, true, true, false};
+
+aim_status aim_set_schedule(aim_plan p, aim_precision prec, const int32_t* sched) {
+  if (!p || !sched) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    check_prec(p, prec);
+    for (int k = 0; k < 5; ++k)
+      AIM_REQUIRE(sched[k] >= 0 && sched[k] < aim::kFftVariants &&
+                      aim::fft_variant_ok(prec == AIM_C128, p->g.M[kPassAxis[k]], kPassCol[k],
+                                          sched[k]),
+                  AIM_ERR_INVALID_ARG, "launch shape not available for this pass");
+    for (int k = 0; k < 5; ++k) p->sched[int(prec)][k] = sched[k];
+  });
+}
+
+aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t reps,
+                        int32_t* sched_out, double* pass_ms_out, void* hip_stream) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    check_prec(p, prec);
+    AIM_REQUIRE(reps >= 1 && reps <= 1000, AIM_ERR_INVALID_ARG, "reps must be in 1..1000");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t* df = set_freq(p, nullptr, nrhs, s);
+    const int pi = int(prec);
+    const bool dbl = prec == AIM_C128;
+    const size_t cb = dbl ? 16 : 8;
+    void* grid = p->d_grid[pi];
+    AIM_HIP(hipMemsetAsync(grid, 0, size_t(p->g.Ng) * cb * nrhs, s));
+    std::vector<hipEvent_t> ev(6 * size_t(reps), nullptr);
+    auto destroy = [&] {
+      for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    };
+    double best[5];
+    int pick[5];
+    for (int k = 0; k < 5; ++k) {
+      best[k] = 1e300;
+      pick[k] = 0;
+    }
+    try {
+      for (auto& e : ev) AIM_HIP(hipEventCreate(&e));
+      for (int v = 0; v < aim::kFftVariants; ++v) {
+        int sch[5];
+        bool any = false;
+        for (int k = 0; k < 5; ++k) {
+          const bool ok = aim::fft_variant_ok(dbl, p->g.M[kPassAxis[k]], kPassCol[k], v);
+          sch[k] = ok ? v : 0;
+          any = any || ok;
+        }
+        if (!any) continue;
+        for (int r = -1; r < reps; ++r) {  // r = -1: warm-up
+          hipEvent_t* e = &ev[6 * size_t(std::max(r, 0))];
+          if (r >= 0) AIM_HIP(hipEventRecord(e[0], s));
+          if (dbl)
+            aim::launch_convolve<double>(p->g, grid, p->d_work[pi], grid, p->d_spec64, df, nrhs,
+                                         p->d_tw64, s, r >= 0 ? e + 1 : nullptr, sch);
+          else
+            aim::launch_convolve<float>(p->g, grid, p->d_work[pi], grid, p->d_spec32, df, nrhs,
+                                        p->d_tw32, s, r >= 0 ? e + 1 : nullptr, sch);
+          if (r >= 0) AIM_HIP(hipEventRecord(e[5], s));
+        }
+        AIM_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < 5; ++k) {
+          if (sch[k] != v) continue;
+          double tot = 0.0;
+          for (int r = 0; r < reps; ++r) {
+            float ms = 0.f;
+            AIM_HIP(hipEventElapsedTime(&ms, ev[6 * size_t(r) + k], ev[6 * size_t(r) + k + 1]));
+            tot += ms;
+          }
+          if (tot / reps < best[k]) {
+            best[k] = tot / reps;
+            pick[k] = v;
+          }
+        }
+      }
+    } catch (...) {
+      destroy();
+      throw;
+    }
+    destroy();
+    for (int k = 0; k < 5; ++k) {
+      p->sched[pi][k] = pick[k];
+      if (sched_out) sched_out[k] = pick[k];
+      if (pass_ms_out) pass_ms_out[k] = best[k];
+    }
+  });
+}
+
 aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, const void* in,
                            void* out, int32_t nrhs, const int32_t* freq_idx_host,
                            void* hip_stream) {
@@ -507,10 +669,10 @@ aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, cons
       case AIM_STAGE_CONVOLVE:
         if (d)
           aim::launch_convolve<double>(p->g, in, p->d_work[pi], out, p->d_spec64, df, nrhs,
-                                       p->d_tw64, s);
+                                       p->d_tw64, s, nullptr, p->sched[pi]);
         else
           aim::launch_convolve<float>(p->g, in, p->d_work[pi], out, p->d_spec32, df, nrhs,
-                                      p->d_tw32, s);
+                                      p->d_tw32, s, nullptr, p->sched[pi]);
         break;
       case AIM_STAGE_INTERPOLATE:
       case AIM_STAGE_NEAR: {
@@ -595,6 +757,7 @@ void ensure_solver(aim_plan p, int nrhs, int m, hipStream_t s) {
   auto& w = p->sv;
   const int64_t n = p->t.N;
   if (w.nrhs >= nrhs && w.m >= m && w.n == n) return;
+  p->graphs.clear();  // captured graphs point at the old staging buffers
   // buffers are never freed individually: the plan owns them until destroy
   const int R = std::max(nrhs, w.nrhs), M = std::max(m, w.m);
   const size_t vec = size_t(n) * 16;
@@ -605,6 +768,7 @@ void ensure_solver(aim_plan p, int nrhs, int m, hipStream_t s) {
   w.d = p->dalloc(vec * R, s);
   w.bp = p->dalloc(vec * R, s);
   w.xp = p->dalloc(vec * R, s);
+  w.ain = p->dalloc(vec * R, s);
   w.h = p->dalloc(size_t(16) * R * (M + 1), s);
   w.h2 = p->dalloc(size_t(16) * R * (M + 1), s);
   w.y = p->dalloc(size_t(16) * R * (M + 1), s);
@@ -628,15 +792,46 @@ void ensure_solver(aim_plan p, int nrhs, int m, hipStream_t s) {
 }
 
 // Operator application used by the Krylov loop: y = A(k_f) x in the requested
-// precision on complex128 vectors (complex64 matvec through casts).
+// precision on complex128 vectors (complex64 matvec through casts).  The
+// matvec runs from fixed staging buffers through a captured graph (one per
+// precision, batch width and frequency set), so each Krylov step replays the
+// seven kernels with one launch.
+bool solver_graphs_enabled() {
+  const char* e = std::getenv("AIM_SOLVER_GRAPHS");
+  return !(e && e[0] == '0');
+}
+
+void graph_matvec(aim_plan p, aim_precision prec, const void* in, void* out, int nrhs,
+                  const int32_t* dfreq, hipStream_t s) {
+  if (!solver_graphs_enabled()) {
+    matvec_any(p, prec, in, out, nrhs, dfreq, s);
+    return;
+  }
+  for (auto& kv : p->graphs) {
+    const auto& k = kv.first;
+    if (k.prec == int(prec) && k.nrhs == nrhs && k.in == in && k.out == out &&
+        int(k.freq.size()) >= nrhs &&
+        std::equal(p->cur_freq.begin(), p->cur_freq.begin() + nrhs, k.freq.begin())) {
+      AIM_HIP(hipGraphLaunch(kv.second->exec, s));
+      return;
+    }
+  }
+  if (p->graphs.size() >= 16) p->graphs.erase(p->graphs.begin());
+  aim_plan_s::GraphKey key{int(prec), nrhs, in, out,
+                           std::vector<int32_t>(p->cur_freq.begin(), p->cur_freq.begin() + nrhs)};
+  p->graphs.emplace_back(std::move(key), capture_matvec(p, prec, in, out, nrhs, dfreq, s));
+  AIM_HIP(hipGraphLaunch(p->graphs.back().second->exec, s));
+}
+
 void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, const int32_t* dfreq,
              hipStream_t s) {
+  const int64_t cnt = p->t.N * int64_t(nrhs);
   if (prec == AIM_C128) {
-    matvec_any(p, AIM_C128, x, y, nrhs, dfreq, s);
+    AIM_HIP(hipMemcpyAsync(p->sv.ain, x, size_t(cnt) * 16, hipMemcpyDeviceToDevice, s));
+    graph_matvec(p, AIM_C128, p->sv.ain, y, nrhs, dfreq, s);
   } else {
-    const int64_t cnt = p->t.N * int64_t(nrhs);
     aim::launch_cast_c128_to_c64(x, p->sv.c64a, cnt, s);
-    matvec_any(p, AIM_C64, p->sv.c64a, p->sv.c64b, nrhs, dfreq, s);
+    graph_matvec(p, AIM_C64, p->sv.c64a, p->sv.c64b, nrhs, dfreq, s);
     aim::launch_cast_c64_to_c128(p->sv.c64b, y, cnt, s);
   }
 }
@@ -878,9 +1073,17 @@ extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs
         std::vector<double> iscale(nrhs);
         for (int r = 0; r < nrhs; ++r) iscale[r] = rn[r] > 0.0 ? rn[r] : 1.0;
         AIM_HIP(hipMemsetAsync(w.xp, 0, vec * nrhs, s));
+        // inner tolerance: enough to reach rtol from here, but not below what
+        // complex64 matvecs can resolve (unless the caller fixed it)
+        double itol = inner_tol;
+        if (o.inner_rtol <= 0.0) {
+          double worst = 0.0;
+          for (int r = 0; r < nrhs; ++r) worst = std::max(worst, rel[r]);
+          itol = std::max(3e-6, std::min(0.1, 0.3 * o.rtol / std::max(worst, 1e-300)));
+        }
         std::vector<double> irel;
         CycleStats ist;
-        gmres_batch(p, AIM_C64, o.pc, w.bp, w.xp, nrhs, df, iscale, inner_tol, o.restart,
+        gmres_batch(p, AIM_C64, o.pc, w.bp, w.xp, nrhs, df, iscale, itol, o.restart,
                     o.max_iter, true, s, ist, irel);
         cst.matvecs += ist.matvecs;
         for (int r = 0; r < nrhs; ++r) inf[r].iters += ist.iters[r];

@@ -106,10 +106,16 @@ void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, 
 // Forward pruned 3-D FFT (unpadded q -> half-spectrum working grid), spectral
 // multiply, inverse pruned FFT (-> unpadded phi).  work must hold 4 Ng complex
 // per right-hand side; q and phi may alias.
+// sched[5] selects the launch shape of the x-forward, y-forward, z, y-inverse
+// and x-inverse passes (NULL: shape 0 everywhere).
+constexpr int kFftVariants = 4;
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
-                     hipEvent_t* between = nullptr);  // 4 events recorded between passes
+                     hipEvent_t* between = nullptr,  // 4 events recorded between passes
+                     const int* sched = nullptr);
+// whether launch shape v exists for an FFT pass of length L
+bool fft_variant_ok(bool dbl, int L, bool col, int v);
 
 // y = P^T phi + C x: rows of P^T (by triangle) and of C, one group of lanes
 // per triangle

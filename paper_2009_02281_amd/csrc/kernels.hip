@@ -250,7 +250,27 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
   for (int m = tid; m < L; m += NTH) tw[m] = twg[m];
   const int l = COL ? (tid & (TL - 1)) : (tid / NT);
   const int t = COL ? (tid / TL) : (tid & (NT - 1));
-  const int64_t line = int64_t(blockIdx.x) * TL + l;
+  int64_t line0 = int64_t(blockIdx.x) * TL;
+  if constexpr (MODE == 2) {
+    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so
+    // hardware block b runs on XCD b % 8.  Give each XCD a contiguous run of
+    // logical blocks, and order rows as 0, 1, My-1, 2, My-2, ..., My/2: the
+    // rows ky and My-ky (and, within a row, kx and Mx-kx) read the same folded
+    // spectrum plane, which then stays in that XCD's L2.
+    if (a.Mx >= TL) {                                // a block stays within one row
+      const int nbx = a.Mx / TL;                     // both powers of two
+      const int nb = nbx * a.My;
+      const int b = int(blockIdx.x);
+      const int lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+      const int rowpos = lb / nbx, g = lb % nbx;
+      const int h = a.My / 2;
+      const int ky = rowpos == 0 ? 0
+                   : rowpos == a.My - 1 ? h
+                   : (rowpos & 1) ? (rowpos + 1) / 2 : a.My - rowpos / 2;
+      line0 = int64_t(ky) * a.Mx + int64_t(g) * TL;
+    }
+  }
+  const int64_t line = line0 + l;
   const bool valid = line < a.nlines;
   const int64_t mask = (int64_t(1) << a.lg_nli) - 1;
   const int64_t li = line & mask, lo = line >> a.lg_nli;
@@ -279,9 +299,10 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
       const int kx = int(li), ky = int(lo);
       const int fx = kx <= a.Nx ? kx : a.Mx - kx;
       const int fy = ky <= a.Ny ? ky : a.My - ky;
+      // folded spectrum layout [fy][fz][fx]: one contiguous plane per fy
       const cx<T>* sp = static_cast<const cx<T>*>(a.spec) + int64_t(a.rhs_freq[rhs]) * a.spec_fs +
-                        int64_t(fy) * (a.Nx + 1) + fx;
-      const int64_t zst = int64_t(a.Ny + 1) * (a.Nx + 1);
+                        int64_t(fy) * (a.Nz + 1) * (a.Nx + 1) + fx;
+      const int64_t zst = int64_t(a.Nx + 1);
 #pragma unroll
       for (int i = 0; i < L / (8 * NT); ++i)
 #pragma unroll
@@ -306,64 +327,128 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
   }
 }
 
-// launch configuration: 256 threads per block
-template <typename T>
-struct ColCfg {
-  static constexpr int kTLmin = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
+// ---------------------------------------------------------------------------
+// launch shapes.  Each pass can run with one of kFftVariants (TL lines per
+// block, NT threads per line) shapes; the autotuner picks one per pass.
+// Column passes keep TL * sizeof(complex) >= 64 bytes so that each row of a
+// block is one or two whole cache lines; row passes read whole lines.
+// ---------------------------------------------------------------------------
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <typename T, int L, bool COL, int V>
+struct Shape {
+  static constexpr int kTL = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
+  static constexpr int NT = COL ? (V == 0 ? cmin(L / 8, 256 / kTL)
+                                  : V == 1 ? cmin(L / 8, 512 / kTL)
+                                  : V == 2 ? cmin(L / 8, 256 / (2 * kTL))
+                                           : cmin(L / 8, 512 / (2 * kTL)))
+                                : (V == 0 ? cmin(L / 8, 64)
+                                  : V == 1 ? cmin(L / 8, 128)
+                                  : V == 2 ? cmin(L / 8, 32)
+                                           : cmin(L / 8, 64));
+  static constexpr int TL = COL ? (V == 0 ? 256 / cmin(L / 8, 256 / kTL)
+                                  : V == 1 ? 512 / cmin(L / 8, 512 / kTL)
+                                  : V == 2 ? 256 / cmin(L / 8, 256 / (2 * kTL))
+                                           : 512 / cmin(L / 8, 512 / (2 * kTL)))
+                                : (V == 3 ? 512 / NT : cmax(1, 256 / NT));
+  static constexpr int THREADS = TL * NT;
+  static constexpr size_t LDS = sizeof(cx<T>) * (COL ? size_t(L) * TL : size_t(TL) * (L + 1)) +
+                                sizeof(cx<T>) * L;
+  static constexpr bool OK = THREADS >= 64 && THREADS <= 1024 && LDS <= 160 * 1024 &&
+                             (TL & (TL - 1)) == 0;
 };
 
-template <typename T, int L>
-struct PassCfg {
-  static constexpr int COL_NT = (L / 8) < (256 / ColCfg<T>::kTLmin) ? (L / 8) : (256 / ColCfg<T>::kTLmin);
-  static constexpr int COL_TL = 256 / COL_NT;
-  static constexpr int ROW_NT = (L / 8) < 64 ? (L / 8) : 64;
-  static constexpr int ROW_TL = 256 / ROW_NT;
-};
+template <typename T, int L, bool COL, int V>
+void launch_shape(int mode, const cx<T>* i, cx<T>* o, const cx<T>* w, const PassArgs& a,
+                  int nrhs, hipStream_t s) {
+  using S = Shape<T, L, COL, V>;
+  if constexpr (!S::OK) {
+    throw Error(AIM_ERR_INVALID_ARG, "FFT launch shape not available for this length");
+  } else {
+    dim3 grid(unsigned((a.nlines + S::TL - 1) / S::TL), unsigned(nrhs));
+    if (mode == 0)
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 0, COL>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+    else if (mode == 1)
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 1, COL>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+    else if constexpr (COL)
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 2, COL>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+    else
+      throw Error(AIM_ERR_INVALID_ARG, "row passes have no spectral multiply");
+  }
+}
 
 template <typename T, int L>
-void pass_L(bool col, int mode, const void* in, void* out, const void* tw, const PassArgs& a,
-            int nrhs, hipStream_t s) {
-  using C = PassCfg<T, L>;
+void pass_L(bool col, int mode, int variant, const void* in, void* out, const void* tw,
+            const PassArgs& a, int nrhs, hipStream_t s) {
   const cx<T>* i = static_cast<const cx<T>*>(in);
   cx<T>* o = static_cast<cx<T>*>(out);
   const cx<T>* w = static_cast<const cx<T>*>(tw);
-  if (col) {
-    dim3 grid(unsigned((a.nlines + C::COL_TL - 1) / C::COL_TL), unsigned(nrhs));
-    if (mode == 0)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::COL_TL, C::COL_NT, 0, true>), grid, dim3(256), 0, s, i, o, w, a);
-    else if (mode == 1)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::COL_TL, C::COL_NT, 1, true>), grid, dim3(256), 0, s, i, o, w, a);
-    else
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::COL_TL, C::COL_NT, 2, true>), grid, dim3(256), 0, s, i, o, w, a);
-  } else {
-    dim3 grid(unsigned((a.nlines + C::ROW_TL - 1) / C::ROW_TL), unsigned(nrhs));
-    if (mode == 0)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::ROW_TL, C::ROW_NT, 0, false>), grid, dim3(256), 0, s, i, o, w, a);
-    else
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, C::ROW_TL, C::ROW_NT, 1, false>), grid, dim3(256), 0, s, i, o, w, a);
+  switch (variant * 2 + (col ? 1 : 0)) {
+    case 0: launch_shape<T, L, false, 0>(mode, i, o, w, a, nrhs, s); break;
+    case 1: launch_shape<T, L, true, 0>(mode, i, o, w, a, nrhs, s); break;
+    case 2: launch_shape<T, L, false, 1>(mode, i, o, w, a, nrhs, s); break;
+    case 3: launch_shape<T, L, true, 1>(mode, i, o, w, a, nrhs, s); break;
+    case 4: launch_shape<T, L, false, 2>(mode, i, o, w, a, nrhs, s); break;
+    case 5: launch_shape<T, L, true, 2>(mode, i, o, w, a, nrhs, s); break;
+    case 6: launch_shape<T, L, false, 3>(mode, i, o, w, a, nrhs, s); break;
+    case 7: launch_shape<T, L, true, 3>(mode, i, o, w, a, nrhs, s); break;
+    default: throw Error(AIM_ERR_INVALID_ARG, "FFT launch shape out of range");
   }
 }
 
 template <typename T>
 void fft_pass(int L, bool col, int mode, const void* in, void* out, const void* tw,
-              const PassArgs& a, int nrhs, hipStream_t s) {
+              const PassArgs& a, int nrhs, hipStream_t s, int variant = 0) {
   switch (L) {
-    case 16: pass_L<T, 16>(col, mode, in, out, tw, a, nrhs, s); break;
-    case 32: pass_L<T, 32>(col, mode, in, out, tw, a, nrhs, s); break;
-    case 64: pass_L<T, 64>(col, mode, in, out, tw, a, nrhs, s); break;
-    case 128: pass_L<T, 128>(col, mode, in, out, tw, a, nrhs, s); break;
-    case 256: pass_L<T, 256>(col, mode, in, out, tw, a, nrhs, s); break;
-    case 512: pass_L<T, 512>(col, mode, in, out, tw, a, nrhs, s); break;
+    case 16: pass_L<T, 16>(col, mode, variant, in, out, tw, a, nrhs, s); break;
+    case 32: pass_L<T, 32>(col, mode, variant, in, out, tw, a, nrhs, s); break;
+    case 64: pass_L<T, 64>(col, mode, variant, in, out, tw, a, nrhs, s); break;
+    case 128: pass_L<T, 128>(col, mode, variant, in, out, tw, a, nrhs, s); break;
+    case 256: pass_L<T, 256>(col, mode, variant, in, out, tw, a, nrhs, s); break;
+    case 512: pass_L<T, 512>(col, mode, variant, in, out, tw, a, nrhs, s); break;
     default: throw Error(AIM_ERR_GRID, "unsupported FFT length");
   }
   AIM_HIP(hipGetLastError());
+}
+
+template <typename T, int L>
+bool shape_ok_L(bool col, int v) {
+  switch (v * 2 + (col ? 1 : 0)) {
+    case 0: return Shape<T, L, false, 0>::OK;
+    case 1: return Shape<T, L, true, 0>::OK;
+    case 2: return Shape<T, L, false, 1>::OK;
+    case 3: return Shape<T, L, true, 1>::OK;
+    case 4: return Shape<T, L, false, 2>::OK;
+    case 5: return Shape<T, L, true, 2>::OK;
+    case 6: return Shape<T, L, false, 3>::OK;
+    case 7: return Shape<T, L, true, 3>::OK;
+    default: return false;
+  }
+}
+
+template <typename T>
+bool fft_shape_ok(int L, bool col, int v) {
+  switch (L) {
+    case 16: return shape_ok_L<T, 16>(col, v);
+    case 32: return shape_ok_L<T, 32>(col, v);
+    case 64: return shape_ok_L<T, 64>(col, v);
+    case 128: return shape_ok_L<T, 128>(col, v);
+    case 256: return shape_ok_L<T, 256>(col, v);
+    case 512: return shape_ok_L<T, 512>(col, v);
+    default: return false;
+  }
+}
+
+bool fft_variant_ok(bool dbl, int L, bool col, int v) {
+  return dbl ? fft_shape_ok<double>(L, col, v) : fft_shape_ok<float>(L, col, v);
 }
 
 // row (x) pass over nlines contiguous lines
 template <typename T>
 void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_t nlines,
               int64_t in_ls, int64_t out_ls, int64_t in_bs, int64_t out_bs, int Lin, int Lout,
-              int nrhs, hipStream_t s) {
+              int nrhs, hipStream_t s, int variant = 0) {
   PassArgs a{};
   a.nlines = nlines;
   a.lg_nli = 0;
@@ -374,7 +459,7 @@ void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_
   a.out_bs = out_bs;
   a.Lin = Lin;
   a.Lout = Lout;
-  fft_pass<T>(L, false, inv ? 1 : 0, in, out, tw, a, nrhs, s);
+  fft_pass<T>(L, false, inv ? 1 : 0, in, out, tw, a, nrhs, s, variant);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,7 +470,9 @@ void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
-                     hipEvent_t* between) {
+                     hipEvent_t* between, const int* sched) {
+  static const int kDefault[5] = {0, 0, 0, 0, 0};
+  if (!sched) sched = kDefault;
   auto mark = [&](int i) {
     if (between) AIM_HIP(hipEventRecord(between[i], s));
   };
@@ -409,12 +496,13 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     return a;
   };
   // x forward: rows (y, z) of q, Nx -> Mx, into A [Nz][Ny][Mx]
-  row_pass<T>(Mx, false, q, A, tw[0], int64_t(Ny) * Nz, Nx, Mx, Ng, 6 * Ng, Nx, Mx, nrhs, s);
+  row_pass<T>(Mx, false, q, A, tw[0], int64_t(Ny) * Nz, Nx, Mx, Ng, 6 * Ng, Nx, Mx, nrhs, s,
+              sched[0]);
   mark(0);
   // y forward: A [Nz][Ny][Mx] -> B [Nz][My][Mx]
   {
     const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, int64_t(Ny) * Mx, Mx, int64_t(My) * Mx, Ny, My);
-    fft_pass<T>(My, true, 0, A, B, tw[1], a, nrhs, s);
+    fft_pass<T>(My, true, 0, A, B, tw[1], a, nrhs, s, sched[1]);
   }
   mark(1);
   // z forward * spectrum * z inverse, in place on B, keeping z < Nz
@@ -429,30 +517,31 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     a.Ny = Ny;
     a.Mz = Mz;
     a.Nz = Nz;
-    fft_pass<T>(Mz, true, 2, B, B, tw[2], a, nrhs, s);
+    fft_pass<T>(Mz, true, 2, B, B, tw[2], a, nrhs, s, sched[2]);
   }
   mark(2);
   // y inverse: B [Nz][My][Mx] -> A [Nz][Ny][Mx]
   {
     const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, int64_t(My) * Mx, Mx, int64_t(Ny) * Mx, My, Ny);
-    fft_pass<T>(My, true, 1, B, A, tw[1], a, nrhs, s);
+    fft_pass<T>(My, true, 1, B, A, tw[1], a, nrhs, s, sched[3]);
   }
   mark(3);
   // x inverse: rows of A (Mx) -> phi (Nx)
-  row_pass<T>(Mx, true, A, phi, tw[0], int64_t(Ny) * Nz, Mx, Nx, 6 * Ng, Ng, Mx, Nx, nrhs, s);
+  row_pass<T>(Mx, true, A, phi, tw[0], int64_t(Ny) * Nz, Mx, Nx, 6 * Ng, Ng, Mx, Nx, nrhs, s,
+              sched[4]);
 }
 
 template void launch_convolve<double>(const GridShape&, const void*, void*, void*, const void*,
                                       const int32_t*, int, const void* const*, hipStream_t,
-                                      hipEvent_t*);
+                                      hipEvent_t*, const int*);
 template void launch_convolve<float>(const GridShape&, const void*, void*, void*, const void*,
                                      const int32_t*, int, const void* const*, hipStream_t,
-                                     hipEvent_t*);
+                                     hipEvent_t*, const int*);
 
 // ---------------------------------------------------------------------------
 // kernel spectrum: circulant embedding of G on the padded grid, full 3-D FFT,
 // folded to its (Nx+1)(Ny+1)(Nz+1) distinct entries (the embedding is even in
-// every axis) and scaled by 1/(Mx My Mz)
+// every axis), scaled by 1/(Mx My Mz) and stored [fy][fz][fx]
 // ---------------------------------------------------------------------------
 __global__ void green_sample_kernel(double2* c, int Nx, int Ny, int Nz, double k, double h) {
   const int Mx = 2 * Nx, My = 2 * Ny, Mz = 2 * Nz;
@@ -493,7 +582,8 @@ __global__ void fold_spectrum_kernel(const double2* full, double2* s64, float2* 
   const int Mx = 2 * Nx, My = 2 * Ny;
   for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
        idx += int64_t(gridDim.x) * blockDim.x) {
-    const int fx = int(idx % Fx), fy = int((idx / Fx) % Fy), fz = int(idx / (int64_t(Fx) * Fy));
+    // output layout [fy][fz][fx]
+    const int fx = int(idx % Fx), fz = int((idx / Fx) % Fz), fy = int(idx / (int64_t(Fx) * Fz));
     double2 v = full[(int64_t(fz) * My + fy) * Mx + fx];
     v.x *= scale;
     v.y *= scale;

@@ -190,3 +190,54 @@ def test_full_size_box_array_sampled():
     assert rel(yfar[0], far) <= FP64_TOL
     print(f"    fp64 err {rel(y64[rows], ref):.2e} fp32 err {rel(y32[rows], ref):.2e}", flush=True)
     p.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_every_fft_launch_shape_matches_oracle(prec):
+    """Each launch shape of each FFT pass gives the oracle's result."""
+    w, o, p = _setup("boxes")
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = FP64_TOL if prec == "c128" else FP32_TOL
+    x = I.complex_gaussian(o.N, 77, nrhs=3)
+    ref = o.matvec(x, w.k[0])
+    xd = dev(x, dt)
+    tried = 0
+    for k in range(5):
+        for v in range(4):
+            sched = [0] * 5
+            sched[k] = v
+            try:
+                p.set_schedule(sched, prec=prec)
+            except binding.AimError:
+                continue
+            tried += 1
+            assert rel(host(p.matvec(xd, prec=prec)), ref) <= tol, (k, v)
+    assert tried >= 10
+    res = p.autotune(prec=prec, nrhs=3, reps=3)
+    assert len(res["schedule"]) == 5 and all(t > 0 for t in res["pass_ms"])
+    assert rel(host(p.matvec(xd, prec=prec)), ref) <= tol
+    p.set_schedule([0] * 5, prec=prec)
+
+
+def test_captured_graph_replays_match_eager():
+    """A captured matvec graph, replayed several times with eager work and
+    synchronisations in between, gives the eager result every time."""
+    w, o, p = _setup("sphere")
+    x = dev(I.complex_gaussian(o.N, 88, nrhs=4))
+    y_eager = p.matvec(x)
+    y = torch.empty_like(x)
+    g = p.capture_matvec(x, y)
+    for rep in range(4):
+        y.zero_()
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_eager), rep
+        p.matvec(x[:2])           # unrelated eager work between replays
+        torch.cuda.synchronize()
+    x2 = dev(I.complex_gaussian(o.N, 89, nrhs=4))
+    x.copy_(x2)                    # new input in the captured buffer
+    g.launch()
+    torch.cuda.synchronize()
+    assert rel(host(y), o.matvec(host(x2), w.k[0])) <= FP64_TOL
+    g.close()
