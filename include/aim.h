@@ -78,6 +78,7 @@ typedef enum { AIM_RHS_PLANE_WAVE = 0, AIM_RHS_GAUSSIAN_PATCH = 1 } aim_rhs_kind
 
 typedef struct aim_plan_s* aim_plan;
 typedef struct aim_graph_s* aim_graph;
+typedef struct aim_unet_s* aim_unet;
 
 /* Optional device allocator (e.g. a framework's caching allocator).  When
  * alloc is NULL the library uses hipMalloc / hipFree. */
@@ -258,6 +259,47 @@ aim_status aim_autotune(aim_plan plan, aim_precision prec, int32_t nrhs, int32_t
  * cache keyed by grid, precision and batch width).  AIM_ERR_INVALID_ARG if a
  * shape is out of range or not available for that pass. */
 aim_status aim_set_schedule(aim_plan plan, aim_precision prec, const int32_t* sched);
+
+/* ---------------------------------------------------------------------
+ * Learned grid preconditioner (a project addition; the paper's own
+ * preconditioners are the static diagonal and near-region blocks of
+ * Sec. III-A).  A 3-level 3-D U-Net maps a grid field of 2 channels (the
+ * real and imaginary parts of a complex64 grid [Nz][Ny][Nx], i.e. the
+ * projected residual) to a grid field of 2 channels (a correction).
+ * Layers, channels-last [z][y][x][c], base width C = 16:
+ *   a0 = relu(conv3(in, 2->C)),  s0 = relu(conv3(a0, C->C))
+ *   a1 = relu(conv3(pool(s0), C->2C)),  s1 = relu(conv3(a1, 2C->2C))
+ *   a2 = relu(conv3(pool(s1), 2C->4C)), a3 = relu(conv3(a2, 4C->4C))
+ *   a4 = relu(conv3([up(a3), s1], 6C->2C)), a5 = relu(conv3(a4, 2C->2C))
+ *   a6 = relu(conv3([up(a5), s0], 3C->C)),  a7 = relu(conv3(a6, C->C))
+ *   out = a7 W^T + b (1x1x1, C->2)
+ * 3x3x3 "same" convolutions, 2x2x2 average pooling, nearest upsampling.
+ * Weights and activations are bfloat16 with fp32 accumulation on MFMA;
+ * master weights, gradients and Adam moments are fp32.  Parameters are one
+ * flat fp32 vector: for every layer in the order above, W[co][tap][ci] with
+ * tap = (dz+1)*9 + (dy+1)*3 + (dx+1), then b[co].  Grid dimensions must be
+ * multiples of 4.  A network is not thread-safe.
+ * --------------------------------------------------------------------- */
+aim_status aim_unet_create(int32_t base_channels /* 16 */, uint64_t seed, aim_unet* out);
+aim_status aim_unet_destroy(aim_unet net);
+aim_status aim_unet_num_params(aim_unet net, int64_t* n);
+/* host copies of the parameters and of the last accumulated gradient
+ * (either pointer may be NULL); blocking */
+aim_status aim_unet_get_params(aim_unet net, float* params_host, float* grads_host);
+aim_status aim_unet_set_params(aim_unet net, const float* params_host);
+/* out = U(in) for nbatch grids (complex64 [nbatch][Nz][Ny][Nx] in and out,
+ * device); dims = {Nx, Ny, Nz}; asynchronous */
+aim_status aim_unet_forward(aim_unet net, const void* in_dev, void* out_dev, int32_t nbatch,
+                            const int32_t dims[3], void* hip_stream);
+/* One training step on grid pairs: gradients of the mean squared error
+ * between U(in) and target over the batch (all on the device), then, if
+ * apply != 0, one Adam step (beta 0.9/0.999, eps 1e-8) with rate lr.  The
+ * loss value is returned in loss_host; blocking. */
+aim_status aim_unet_train_grid(aim_unet net, const void* in_dev, const void* target_dev,
+                               int32_t nbatch, const int32_t dims[3], double lr, int32_t apply,
+                               double* loss_host, void* hip_stream);
+aim_status aim_unet_save(aim_unet net, const char* path);
+aim_status aim_unet_load(const char* path, aim_unet* out);
 
 /* Host copies of setup tables, for validation against an independent
  * implementation.  Any pointer may be NULL to skip that table.

@@ -27,7 +27,9 @@ RHS = {"plane_wave": 0, "gaussian_patch": 1}
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
             "aim_autotune", "aim_set_schedule", "aim_matvec_capture", "aim_graph_launch",
-            "aim_graph_destroy",
+            "aim_graph_destroy", "aim_unet_create", "aim_unet_destroy", "aim_unet_num_params",
+            "aim_unet_get_params", "aim_unet_set_params", "aim_unet_forward",
+            "aim_unet_train_grid", "aim_unet_save", "aim_unet_load",
             "aim_last_error", "aim_version"]
 KERNELS = ["project", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
            "interp_near"]
@@ -112,6 +114,17 @@ def load_library(path: str = LIB_PATH):
     lib.aim_matvec_capture.argtypes = [vp, i32, vp, vp, i32, ip32, vp, C.POINTER(vp)]
     lib.aim_graph_launch.argtypes = [vp, vp]
     lib.aim_graph_destroy.argtypes = [vp]
+    fp = C.POINTER(C.c_float)
+    lib.aim_unet_create.argtypes = [i32, C.c_uint64, C.POINTER(vp)]
+    lib.aim_unet_destroy.argtypes = [vp]
+    lib.aim_unet_num_params.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.aim_unet_get_params.argtypes = [vp, fp, fp]
+    lib.aim_unet_set_params.argtypes = [vp, fp]
+    lib.aim_unet_forward.argtypes = [vp, vp, vp, i32, ip32, vp]
+    lib.aim_unet_train_grid.argtypes = [vp, vp, vp, i32, ip32, C.c_double, i32,
+                                        C.POINTER(C.c_double), vp]
+    lib.aim_unet_save.argtypes = [vp, C.c_char_p]
+    lib.aim_unet_load.argtypes = [C.c_char_p, C.POINTER(vp)]
     lib.aim_autotune.argtypes = [vp, i32, i32, i32, ip32, C.POINTER(C.c_double), vp]
     lib.aim_set_schedule.argtypes = [vp, i32, ip32]
     lib.aim_last_error.restype = C.c_char_p
@@ -150,6 +163,101 @@ class SolveResult:
     rel_resid: np.ndarray
     seconds: float
     status: int
+
+
+class UNet:
+    """The learned grid preconditioner network (see aim_unet_* in aim.h)."""
+
+    def __init__(self, seed: int = 0, base_channels: int = 16, handle=None):
+        self._lib = load_library()
+        self._h = C.c_void_p()
+        if handle is not None:
+            self._h = handle
+        else:
+            _check(self._lib.aim_unet_create(base_channels, seed, C.byref(self._h)))
+        n = C.c_int64()
+        _check(self._lib.aim_unet_num_params(self._h, C.byref(n)))
+        self.nparam = int(n.value)
+
+    @classmethod
+    def load(cls, path: str):
+        lib = load_library()
+        h = C.c_void_p()
+        _check(lib.aim_unet_load(path.encode(), C.byref(h)))
+        return cls(handle=h)
+
+    def save(self, path: str):
+        _check(self._lib.aim_unet_save(self._h, path.encode()))
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.nparam, dtype=np.float32)
+        _check(self._lib.aim_unet_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                             None))
+        return out
+
+    def grads(self) -> np.ndarray:
+        out = np.empty(self.nparam, dtype=np.float32)
+        _check(self._lib.aim_unet_get_params(self._h, None,
+                                             out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_params(self, p):
+        arr = np.ascontiguousarray(p, dtype=np.float32)
+        assert arr.size == self.nparam
+        _check(self._lib.aim_unet_set_params(self._h, arr.ctypes.data_as(C.POINTER(C.c_float))))
+
+    @staticmethod
+    def _dims(t):
+        nz, ny, nx = t.shape[-3:]
+        return (C.c_int32 * 3)(nx, ny, nz)
+
+    def forward(self, grid, stream=None):
+        """grid: complex64 CUDA tensor [nbatch, Nz, Ny, Nx] (or 3-D)."""
+        import torch
+        g = grid.reshape((-1,) + tuple(grid.shape[-3:]))
+        assert g.dtype == torch.complex64 and g.is_cuda and g.is_contiguous()
+        out = torch.empty_like(g)
+        _check(self._lib.aim_unet_forward(self._h, C.c_void_p(g.data_ptr()),
+                                          C.c_void_p(out.data_ptr()), g.shape[0], self._dims(g),
+                                          _stream_ptr(stream)))
+        return out.reshape(grid.shape)
+
+    def train_grid(self, grid, target, lr: float = 1e-3, apply: bool = True, stream=None) -> float:
+        g = grid.reshape((-1,) + tuple(grid.shape[-3:]))
+        t = target.reshape(g.shape)
+        loss = C.c_double()
+        _check(self._lib.aim_unet_train_grid(self._h, C.c_void_p(g.data_ptr()),
+                                             C.c_void_p(t.data_ptr()), g.shape[0], self._dims(g),
+                                             float(lr), 1 if apply else 0, C.byref(loss),
+                                             _stream_ptr(stream)))
+        return float(loss.value)
+
+    def close(self):
+        if self._h and self._h.value:
+            _check(self._lib.aim_unet_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def unet_params_to_layers(flat, C0: int = 16):
+    """Splits the flat parameter vector into [(W[co, t, ci], b[co]), ...]."""
+    c0, c1, c2 = C0, 2 * C0, 4 * C0
+    spec = [(c0, 2, 27), (c0, c0, 27), (c1, c0, 27), (c1, c1, 27), (c2, c1, 27), (c2, c2, 27),
+            (c1, c2 + c1, 27), (c1, c1, 27), (c0, c1 + c0, 27), (c0, c0, 27), (2, c0, 1)]
+    out, off = [], 0
+    for co, ci, t in spec:
+        W = np.asarray(flat[off:off + co * t * ci], dtype=np.float64).reshape(co, t, ci)
+        off += co * t * ci
+        b = np.asarray(flat[off:off + co], dtype=np.float64)
+        off += co
+        out.append((W, b))
+    assert off == len(flat)
+    return out
 
 
 class MatvecGraph:

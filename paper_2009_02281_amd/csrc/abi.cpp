@@ -34,6 +34,13 @@ struct aim_graph_s {
 
 namespace {
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace aim {
+void set_last_error(const std::string& m) { g_last_error = m; }
+}  // namespace aim
+
+namespace {
 
 aim_status fail(aim_status s, const std::string& m) {
   g_last_error = m;

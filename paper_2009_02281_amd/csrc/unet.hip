@@ -1,0 +1,936 @@
+// Learned grid preconditioner: a 3-level 3-D U-Net on the AIM grid with
+// hand-written inference and training kernels for gfx950.
+//
+// The network (channels-last tensors [z][y][x][c], base width C):
+//   a0 = relu(conv3(in, 2->C))           s0 = relu(conv3(a0, C->C))
+//   a1 = relu(conv3(pool(s0), C->2C))    s1 = relu(conv3(a1, 2C->2C))
+//   a2 = relu(conv3(pool(s1), 2C->4C))   a3 = relu(conv3(a2, 4C->4C))
+//   a4 = relu(conv3([up(a3), s1], 6C->2C))  a5 = relu(conv3(a4, 2C->2C))
+//   a6 = relu(conv3([up(a5), s0], 3C->C))   a7 = relu(conv3(a6, C->C))
+//   out = a7 W^T + b (1x1x1, C->2)
+// with 3x3x3 "same" convolutions, 2x2x2 average pooling and nearest
+// upsampling.  Weights and activations are bfloat16; the convolutions are
+// implicit GEMMs on the 16x16x16 bf16 MFMA with fp32 accumulation (the data
+// gradient is the same GEMM with flipped, transposed weights); weight
+// gradients are fp32 reductions; master weights and Adam moments are fp32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "aim_internal.h"
+
+namespace aim {
+namespace unetk {
+
+typedef short bf16x4 __attribute__((__vector_size__(4 * sizeof(short))));
+typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+__device__ __forceinline__ void pos_xyz(int64_t p, int W, int H, int& x, int& y, int& z) {
+  x = int(p % W);
+  y = int((p / W) % H);
+  z = int(p / (int64_t(W) * H));
+}
+
+// ---------------------------------------------------------------------------
+// 3x3x3 convolution as implicit GEMM on MFMA: Y[p][co] = sum_{t,ci}
+// X[p + d(t)][ci] Wt[co][t][ci] (+ bias, relu).  A wavefront computes 16
+// consecutive positions for all output channels; per tap and 16-channel
+// chunk, lane l loads four bf16 of position l%16 (B operand) and four of the
+// weight row l%16 of each 16-channel output tile (A operand); the result
+// tile holds channels 4*(l/16)..+3 of position l%16.
+// ---------------------------------------------------------------------------
+template <int TILES, bool OUT_BF16>
+__global__ __launch_bounds__(256) void conv3_mfma_kernel(const uint16_t* __restrict__ X, int ldx,
+                                                         int ox, int Cin, int D, int H, int W,
+                                                         const uint16_t* __restrict__ Wt,
+                                                         const float* __restrict__ bias, void* Y,
+                                                         int ldy, int oy, int relu) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t P = int64_t(D) * H * W;
+  const int64_t p0 = (int64_t(blockIdx.x) * 4 + wave) * 16;
+  if (p0 >= P) return;  // whole wavefront
+  const int col = lane & 15, kg = lane >> 4;
+  const int64_t p = p0 + col;
+  const bool pv = p < P;
+  int x = 0, y = 0, z = 0;
+  if (pv) pos_xyz(p, W, H, x, y, z);
+  f32x4 acc[TILES];
+#pragma unroll
+  for (int t = 0; t < TILES; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int K = 27 * Cin;
+  for (int tap = 0; tap < 27; ++tap) {
+    const int nx = x + tap % 3 - 1, ny = y + (tap / 3) % 3 - 1, nz = z + tap / 9 - 1;
+    const bool inb = pv && nx >= 0 && ny >= 0 && nz >= 0 && nx < W && ny < H && nz < D;
+    const uint16_t* xp = X + ((int64_t(nz) * H + ny) * W + nx) * ldx + ox + 4 * kg;
+    const uint16_t* wp = Wt + int64_t(col) * K + tap * Cin + 4 * kg;
+    for (int c0 = 0; c0 < Cin; c0 += 16) {
+      bf16x4 b = bf16x4{0, 0, 0, 0};
+      if (inb) b = *reinterpret_cast<const bf16x4*>(xp + c0);
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(wp + int64_t(t) * 16 * K + c0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  if (!pv) return;
+#pragma unroll
+  for (int t = 0; t < TILES; ++t) {
+    const int co = t * 16 + 4 * kg;
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[i] = acc[t][i] + (bias ? bias[co + i] : 0.f);
+      if (relu) v[i] = fmaxf(v[i], 0.f);
+    }
+    if constexpr (OUT_BF16) {
+      ushort4 o;
+      o.x = f2bf(v[0]);
+      o.y = f2bf(v[1]);
+      o.z = f2bf(v[2]);
+      o.w = f2bf(v[3]);
+      *reinterpret_cast<ushort4*>(static_cast<uint16_t*>(Y) + p * ldy + oy + co) = o;
+    } else {
+      *reinterpret_cast<float4*>(static_cast<float*>(Y) + p * ldy + oy + co) =
+          make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// first layer: 2 fp32 input channels (the complex64 grid), C outputs, relu
+template <int C>
+__global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict__ in, int D, int H,
+                                                         int W, const float* __restrict__ Wm,
+                                                         const float* __restrict__ bias,
+                                                         uint16_t* __restrict__ Y, int ldy, int oy) {
+  __shared__ float w[C * 27 * 2];
+  for (int i = threadIdx.x; i < C * 54; i += blockDim.x) w[i] = bf2f(f2bf(Wm[i]));  // bf16 weights
+  __syncthreads();
+  const int64_t P = int64_t(D) * H * W;
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  int x, y, z;
+  pos_xyz(p, W, H, x, y, z);
+  float acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = bias[c];
+  for (int tap = 0; tap < 27; ++tap) {
+    const int nx = x + tap % 3 - 1, ny = y + (tap / 3) % 3 - 1, nz = z + tap / 9 - 1;
+    if (nx < 0 || ny < 0 || nz < 0 || nx >= W || ny >= H || nz >= D) continue;
+    const float2 v = *reinterpret_cast<const float2*>(in + 2 * ((int64_t(nz) * H + ny) * W + nx));
+    // the first layer reads bf16-rounded inputs, like every other layer
+    const float v0 = bf2f(f2bf(v.x)), v1 = bf2f(f2bf(v.y));
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] += w[(c * 27 + tap) * 2] * v0 + w[(c * 27 + tap) * 2 + 1] * v1;
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) Y[p * ldy + oy + c] = f2bf(fmaxf(acc[c], 0.f));
+}
+
+// 1x1 output layer: out[p][2] = a[p][:] W^T + b (fp32)
+template <int C>
+__global__ void conv_out_kernel(const uint16_t* __restrict__ a, int64_t P,
+                                const float* __restrict__ Wm, const float* __restrict__ b,
+                                float* __restrict__ out) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  float o0 = b[0], o1 = b[1];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float v = bf2f(a[p * C + c]);
+    o0 += bf2f(f2bf(Wm[c])) * v;
+    o1 += bf2f(f2bf(Wm[C + c])) * v;
+  }
+  out[2 * p] = o0;
+  out[2 * p + 1] = o1;
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: dW[co][t][ci] (+)= sum_p dY[p][co] X[p + d(t)][ci],
+// computed per chunk of positions (two-stage, deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float ldv(const uint16_t* p, int64_t i) { return bf2f(p[i]); }
+__device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
+
+constexpr int kWgPos = 32;  // positions staged per step
+
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void wgrad_partial_kernel(
+    const TX* __restrict__ X, int ldx, int ox, int Cin, const TY* __restrict__ dY, int ldy, int oy,
+    int Cout, int D, int H, int W, int ntaps, int64_t chunk, float* __restrict__ part) {
+  extern __shared__ float sm[];
+  float* sy = sm;                     // [kWgPos][Cout]
+  float* sx = sm + kWgPos * Cout;     // [kWgPos][Cin]
+  const int tap = blockIdx.y;
+  const int64_t P = int64_t(D) * H * W;
+  const int64_t pb = int64_t(blockIdx.x) * chunk, pe = min(P, pb + chunk);
+  const int dx = ntaps == 1 ? 0 : tap % 3 - 1, dy = ntaps == 1 ? 0 : (tap / 3) % 3 - 1,
+            dz = ntaps == 1 ? 0 : tap / 9 - 1;
+  const int nent = Cout * Cin;
+  constexpr int kMaxPer = 24;  // Cout * Cin <= 256 * 24
+  float acc[kMaxPer];
+#pragma unroll
+  for (int j = 0; j < kMaxPer; ++j) acc[j] = 0.f;
+  for (int64_t s0 = pb; s0 < pe; s0 += kWgPos) {
+    const int cnt = int(min(int64_t(kWgPos), pe - s0));
+    for (int i = threadIdx.x; i < kWgPos * Cout; i += 256) {
+      const int pp = i / Cout, c = i % Cout;
+      sy[i] = pp < cnt ? ldv(dY, (s0 + pp) * ldy + oy + c) : 0.f;
+    }
+    for (int i = threadIdx.x; i < kWgPos * Cin; i += 256) {
+      const int pp = i / Cin, c = i % Cin;
+      float v = 0.f;
+      if (pp < cnt) {
+        int x, y, z;
+        pos_xyz(s0 + pp, W, H, x, y, z);
+        const int nx = x + dx, ny = y + dy, nz = z + dz;
+        if (nx >= 0 && ny >= 0 && nz >= 0 && nx < W && ny < H && nz < D)
+          v = ldv(X, ((int64_t(nz) * H + ny) * W + nx) * ldx + ox + c);
+      }
+      sx[i] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) {
+      const int e = threadIdx.x + j * 256;
+      if (e < nent) {
+        const int co = e / Cin, ci = e % Cin;
+        float a = acc[j];
+        for (int pp = 0; pp < kWgPos; ++pp) a += sy[pp * Cout + co] * sx[pp * Cin + ci];
+        acc[j] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxPer; ++j) {
+    const int e = threadIdx.x + j * 256;
+    if (e < nent) {
+      const int co = e / Cin, ci = e % Cin;
+      part[(int64_t(blockIdx.x) * ntaps * Cout + int64_t(co) * ntaps + tap) * Cin + ci] = acc[j];
+    }
+  }
+}
+
+// grad[i] (+)= sum_c part[c][i]
+__global__ void reduce_chunks_kernel(const float* __restrict__ part, int nchunk, int64_t n,
+                                     float* __restrict__ grad) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * n + i];
+    grad[i] += s;
+  }
+}
+
+// bias gradient: db[c] += sum_p dY[p][c]
+template <typename TY>
+__global__ __launch_bounds__(256) void bgrad_kernel(const TY* __restrict__ dY, int ldy, int oy,
+                                                    int C, int64_t P, float* __restrict__ db) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (int64_t p = threadIdx.x; p < P; p += 256) s += ldv(dY, p * ldy + oy + c);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[c] += red[0];
+}
+
+// ---------------------------------------------------------------------------
+// pooling, upsampling, masks
+// ---------------------------------------------------------------------------
+__global__ void pool_kernel(const uint16_t* __restrict__ X, int ldx, int ox, int C, int D, int H,
+                            int W, uint16_t* __restrict__ Y) {  // Y [P/8][C]
+  const int Dc = D / 2, Hc = H / 2, Wc = W / 2;
+  const int64_t n = int64_t(Dc) * Hc * Wc * C;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const int64_t q = i / C;
+    int x, y, z;
+    pos_xyz(q, Wc, Hc, x, y, z);
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+      const int64_t pf = (int64_t(2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
+      s += bf2f(X[pf * ldx + ox + c]);
+    }
+    Y[q * C + c] = f2bf(s * 0.125f);
+  }
+}
+
+__global__ void up_kernel(const uint16_t* __restrict__ X, int C, int Dc, int Hc, int Wc,
+                          uint16_t* __restrict__ Y, int ldy, int oy) {  // fine [8 Pc][ldy]
+  const int D = 2 * Dc, H = 2 * Hc, W = 2 * Wc;
+  const int64_t n = int64_t(D) * H * W * C;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const int64_t p = i / C;
+    int x, y, z;
+    pos_xyz(p, W, H, x, y, z);
+    const int64_t q = (int64_t(z / 2) * Hc + y / 2) * Wc + x / 2;
+    Y[p * ldy + oy + c] = X[q * C + c];
+  }
+}
+
+// gb[p][c] = bf16(g[p][og + c]) where act[p][oa + c] > 0, else 0
+__global__ void mask_kernel(const float* __restrict__ g, int ldg, int og,
+                            const uint16_t* __restrict__ act, int lda, int oa, int C, int64_t P,
+                            uint16_t* __restrict__ gb) {
+  const int64_t n = P * C;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const int64_t p = i / C;
+    const float v = bf2f(act[p * lda + oa + c]) > 0.f ? g[p * ldg + og + c] : 0.f;
+    gb[i] = f2bf(v);
+  }
+}
+
+// coarse gb[q][c] = bf16(sum of the 8 children g[child][og + c]) masked by act[q][c] > 0
+__global__ void up_backward_kernel(const float* __restrict__ g, int ldg, int og, int C, int Dc,
+                                   int Hc, int Wc, const uint16_t* __restrict__ act,
+                                   uint16_t* __restrict__ gb) {
+  const int H = 2 * Hc, W = 2 * Wc;
+  const int64_t n = int64_t(Dc) * Hc * Wc * C;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const int64_t q = i / C;
+    int x, y, z;
+    pos_xyz(q, Wc, Hc, x, y, z);
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+      const int64_t pf = (int64_t(2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
+      s += g[pf * ldg + og + c];
+    }
+    gb[i] = f2bf(bf2f(act[i]) > 0.f ? s : 0.f);
+  }
+}
+
+// fine gb[p][c] = bf16((gc[parent][c] / 8 + skip[p][os + c]) * (act[p][oa + c] > 0))
+__global__ void pool_backward_kernel(const float* __restrict__ gc, int C, int D, int H, int W,
+                                     const float* __restrict__ skip, int lds, int os,
+                                     const uint16_t* __restrict__ act, int lda, int oa,
+                                     uint16_t* __restrict__ gb) {
+  const int Hc = H / 2, Wc = W / 2;
+  const int64_t n = int64_t(D) * H * W * C;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const int64_t p = i / C;
+    int x, y, z;
+    pos_xyz(p, W, H, x, y, z);
+    const int64_t q = (int64_t(z / 2) * Hc + y / 2) * Wc + x / 2;
+    float v = gc[q * C + c] * 0.125f + skip[p * lds + os + c];
+    if (!(bf2f(act[p * lda + oa + c]) > 0.f)) v = 0.f;
+    gb[i] = f2bf(v);
+  }
+}
+
+// gradient through the 1x1 output layer: ga[p][c] = bf16((dout[p] W)[c]) masked by a7 > 0
+template <int C>
+__global__ void out_backward_kernel(const float* __restrict__ dout, const float* __restrict__ Wm,
+                                    const uint16_t* __restrict__ act, int64_t P,
+                                    uint16_t* __restrict__ ga) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const float d0 = dout[2 * p], d1 = dout[2 * p + 1];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float v = d0 * bf2f(f2bf(Wm[c])) + d1 * bf2f(f2bf(Wm[C + c]));
+    ga[p * C + c] = f2bf(bf2f(act[p * C + c]) > 0.f ? v : 0.f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// parameters: fp32 master -> bf16 (same layout) and flipped [ci][26 - t][co]
+// ---------------------------------------------------------------------------
+__global__ void to_bf16_kernel(const float* __restrict__ w, int64_t n, uint16_t* __restrict__ o) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    o[i] = f2bf(w[i]);
+}
+
+__global__ void flip_kernel(const float* __restrict__ w, int Cout, int Cin,
+                            uint16_t* __restrict__ o) {
+  const int64_t n = int64_t(Cout) * 27 * Cin;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int ci = int(i % Cin), t = int((i / Cin) % 27), co = int(i / (int64_t(Cin) * 27));
+    o[(int64_t(ci) * 27 + (26 - t)) * Cout + co] = f2bf(w[i]);
+  }
+}
+
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
+                            float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// mean-squared error: dout = scale (out - tgt); per-block partial sums of
+// (out - tgt)^2 * lscale into part[blockIdx.x]
+__global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ out,
+                                                  const float* __restrict__ tgt, int64_t n,
+                                                  float scale, float lscale,
+                                                  float* __restrict__ dout,
+                                                  float* __restrict__ part) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const float d = out[i] - tgt[i];
+    dout[i] = scale * d;
+    s += d * d * lscale;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void fill_kernel(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+inline unsigned gsz(int64_t n, int per = 256) {
+  int64_t g = (n + per - 1) / per;
+  return unsigned(g < 1 ? 1 : (g > 16384 ? 16384 : g));
+}
+
+}  // namespace unetk
+}  // namespace aim
+
+// ===========================================================================
+// the network object
+// ===========================================================================
+using namespace aim::unetk;
+
+namespace {
+
+struct Layer {
+  int cout, cin, taps;
+  int64_t w_off, b_off;  // into the flat fp32 parameter vector
+  int64_t flip_off;      // into the flipped bf16 vector (3x3x3 layers)
+};
+
+struct Acts {  // per-level activation / gradient buffers for one grid size
+  int D = 0, H = 0, W = 0;
+  std::vector<void*> bufs;
+  uint16_t *a0, *cat0, *p0, *a1, *cat1, *p1, *a2, *a3, *a4, *a5, *a6, *a7;
+  float *out, *gcat0, *g0, *gcat1, *g1, *g2, *part;
+  uint16_t *gb0, *gb1, *gb2;
+  int64_t part_n = 0;
+};
+
+thread_local std::string g_unet_err;
+
+}  // namespace
+
+struct aim_unet_s {
+  int C = 16;
+  std::vector<Layer> layers;
+  int64_t nparam = 0, nflip = 0;
+  float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t *wb = nullptr, *wf = nullptr;
+  int64_t step = 0;
+  Acts acts;
+
+  void build_layers() {
+    const int c0 = C, c1 = 2 * C, c2 = 4 * C;
+    const int spec[11][3] = {{c0, 2, 27},       {c0, c0, 27}, {c1, c0, 27}, {c1, c1, 27},
+                             {c2, c1, 27},      {c2, c2, 27}, {c1, c2 + c1, 27},
+                             {c1, c1, 27},      {c0, c1 + c0, 27}, {c0, c0, 27}, {2, c0, 1}};
+    int64_t off = 0, foff = 0;
+    for (auto& s : spec) {
+      Layer L{s[0], s[1], s[2], off, 0, foff};
+      off += int64_t(s[0]) * s[1] * s[2];
+      L.b_off = off;
+      off += s[0];
+      if (s[2] == 27) foff += int64_t(s[0]) * s[1] * 27;
+      layers.push_back(L);
+    }
+    nparam = off;
+    nflip = foff;
+  }
+
+  void alloc_params() {
+    AIM_HIP(hipMalloc(&w, nparam * 4));
+    AIM_HIP(hipMalloc(&g, nparam * 4));
+    AIM_HIP(hipMalloc(&m, nparam * 4));
+    AIM_HIP(hipMalloc(&v, nparam * 4));
+    AIM_HIP(hipMalloc(&wb, nparam * 2));
+    AIM_HIP(hipMalloc(&wf, nflip * 2));
+    AIM_HIP(hipMemset(g, 0, nparam * 4));
+    AIM_HIP(hipMemset(m, 0, nparam * 4));
+    AIM_HIP(hipMemset(v, 0, nparam * 4));
+  }
+
+  void free_acts() {
+    for (void* p : acts.bufs) (void)hipFree(p);
+    acts = Acts();
+  }
+
+  ~aim_unet_s() {
+    (void)hipDeviceSynchronize();
+    free_acts();
+    for (void* p : {(void*)w, (void*)g, (void*)m, (void*)v, (void*)wb, (void*)wf})
+      if (p) (void)hipFree(p);
+  }
+
+  // derived bf16 copies of the master weights
+  void refresh(hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(gsz(nparam)), dim3(256), 0, s, w, nparam, wb);
+    AIM_HIP(hipGetLastError());
+    for (const auto& L : layers) {
+      if (L.taps != 27 || L.cin == 2) continue;
+      hipLaunchKernelGGL(flip_kernel, dim3(gsz(int64_t(L.cout) * 27 * L.cin)), dim3(256), 0, s,
+                         w + L.w_off, L.cout, L.cin, wf + L.flip_off);
+      AIM_HIP(hipGetLastError());
+    }
+  }
+
+  void ensure_acts(int D, int H, int W) {
+    AIM_REQUIRE(D % 4 == 0 && H % 4 == 0 && W % 4 == 0 && D >= 4 && H >= 4 && W >= 4,
+                AIM_ERR_GRID, "U-Net grid dimensions must be multiples of 4");
+    if (acts.D == D && acts.H == H && acts.W == W) return;
+    free_acts();
+    acts.D = D;
+    acts.H = H;
+    acts.W = W;
+    const int64_t P0 = int64_t(D) * H * W, P1 = P0 / 8, P2 = P1 / 8;
+    const int c0 = C, c1 = 2 * C, c2 = 4 * C;
+    auto al = [&](int64_t bytes) {
+      void* p = nullptr;
+      AIM_HIP(hipMalloc(&p, bytes < 256 ? 256 : bytes));
+      acts.bufs.push_back(p);
+      return p;
+    };
+    auto b16 = [&](int64_t n) { return static_cast<uint16_t*>(al(n * 2)); };
+    auto f32 = [&](int64_t n) { return static_cast<float*>(al(n * 4)); };
+    acts.a0 = b16(P0 * c0);
+    acts.cat0 = b16(P0 * (c1 + c0));
+    acts.p0 = b16(P1 * c0);
+    acts.a1 = b16(P1 * c1);
+    acts.cat1 = b16(P1 * (c2 + c1));
+    acts.p1 = b16(P2 * c1);
+    acts.a2 = b16(P2 * c2);
+    acts.a3 = b16(P2 * c2);
+    acts.a4 = b16(P1 * c1);
+    acts.a5 = b16(P1 * c1);
+    acts.a6 = b16(P0 * c0);
+    acts.a7 = b16(P0 * c0);
+    acts.out = f32(P0 * 2);
+    acts.gcat0 = f32(P0 * (c1 + c0));
+    acts.g0 = f32(P0 * c0);
+    acts.gcat1 = f32(P1 * (c2 + c1));
+    acts.g1 = f32(P1 * c1);
+    acts.g2 = f32(P2 * c2);
+    acts.gb0 = b16(P0 * c0);
+    acts.gb1 = b16(P1 * c1);
+    acts.gb2 = b16(P2 * c2);
+    // weight-gradient partials: chunks * taps * cout * cin, largest layer
+    int64_t mx = 0;
+    for (const auto& L : layers) mx = std::max<int64_t>(mx, int64_t(L.cout) * L.cin * L.taps);
+    acts.part_n = 64 * mx;
+    acts.part = f32(acts.part_n);
+  }
+
+  // -- launch helpers --------------------------------------------------------
+  void conv(const uint16_t* X, int ldx, int ox, int cin, int D, int H, int W, const uint16_t* Wt,
+            const float* bias, void* Y, int ldy, int oy, int cout, bool out_bf16, bool relu,
+            hipStream_t s) {
+    const int64_t P = int64_t(D) * H * W;
+    dim3 grid(unsigned((P + 63) / 64));
+    const int tiles = cout / 16;
+#define AIM_CONV(T)                                                                           \
+  if (out_bf16)                                                                               \
+    hipLaunchKernelGGL((conv3_mfma_kernel<T, true>), grid, dim3(256), 0, s, X, ldx, ox, cin, D, \
+                       H, W, Wt, bias, Y, ldy, oy, relu ? 1 : 0);                              \
+  else                                                                                        \
+    hipLaunchKernelGGL((conv3_mfma_kernel<T, false>), grid, dim3(256), 0, s, X, ldx, ox, cin, D, \
+                       H, W, Wt, bias, Y, ldy, oy, relu ? 1 : 0);
+    switch (tiles) {
+      case 1: AIM_CONV(1) break;
+      case 2: AIM_CONV(2) break;
+      case 3: AIM_CONV(3) break;
+      case 4: AIM_CONV(4) break;
+      case 6: AIM_CONV(6) break;
+      default: throw aim::Error(AIM_ERR_STATE, "unsupported channel count");
+    }
+#undef AIM_CONV
+    AIM_HIP(hipGetLastError());
+  }
+
+  template <typename TX, typename TY>
+  void wgrad(const TX* X, int ldx, int ox, int cin, const TY* dY, int ldy, int oy, int cout, int D,
+             int H, int W, const Layer& L, hipStream_t s) {
+    const int64_t P = int64_t(D) * H * W;
+    AIM_REQUIRE(int64_t(cout) * cin <= 256 * 24, AIM_ERR_STATE, "layer too wide for wgrad");
+    int64_t nchunk = std::min<int64_t>(64, (P + kWgPos - 1) / kWgPos);
+    const int64_t chunk = (P + nchunk - 1) / nchunk;
+    nchunk = (P + chunk - 1) / chunk;
+    const size_t shm = size_t(kWgPos) * (cout + cin) * sizeof(float);
+    hipLaunchKernelGGL((wgrad_partial_kernel<TX, TY>), dim3(unsigned(nchunk), L.taps), dim3(256),
+                       shm, s, X, ldx, ox, cin, dY, ldy, oy, cout, D, H, W, L.taps, chunk,
+                       acts.part);
+    AIM_HIP(hipGetLastError());
+    const int64_t n = int64_t(cout) * L.taps * cin;
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(gsz(n)), dim3(256), 0, s, acts.part,
+                       int(nchunk), n, g + L.w_off);
+    AIM_HIP(hipGetLastError());
+    hipLaunchKernelGGL((bgrad_kernel<TY>), dim3(cout), dim3(256), 0, s, dY, ldy, oy, cout, P,
+                       g + L.b_off);
+    AIM_HIP(hipGetLastError());
+  }
+
+  // forward pass on one sample: in = complex64 grid [D][H][W] (2 fp32), out fp32 [P][2]
+  void forward(const float* in, int D, int H, int W, float* out, hipStream_t s) {
+    ensure_acts(D, H, W);
+    Acts& a = acts;
+    const int c0 = C, c1 = 2 * C, c2 = 4 * C;
+    const int D1 = D / 2, H1 = H / 2, W1 = W / 2, D2 = D / 4, H2 = H / 4, W2 = W / 4;
+    const int64_t P0 = int64_t(D) * H * W, P1 = P0 / 8;
+    const Layer* Ls = layers.data();
+    AIM_REQUIRE(C == 16, AIM_ERR_STATE, "only base width 16 is built");
+    hipLaunchKernelGGL((conv_first_kernel<16>), dim3(gsz(P0)), dim3(256), 0, s, in, D, H, W,
+                       w + Ls[0].w_off, w + Ls[0].b_off, a.a0, c0, 0);
+    AIM_HIP(hipGetLastError());
+    conv(a.a0, c0, 0, c0, D, H, W, wb + Ls[1].w_off, w + Ls[1].b_off, a.cat0, c1 + c0, c1, c0, true, true, s);
+    hipLaunchKernelGGL(pool_kernel, dim3(gsz(P1 * c0)), dim3(256), 0, s, a.cat0, c1 + c0, c1, c0, D, H, W, a.p0);
+    conv(a.p0, c0, 0, c0, D1, H1, W1, wb + Ls[2].w_off, w + Ls[2].b_off, a.a1, c1, 0, c1, true, true, s);
+    conv(a.a1, c1, 0, c1, D1, H1, W1, wb + Ls[3].w_off, w + Ls[3].b_off, a.cat1, c2 + c1, c2, c1, true, true, s);
+    hipLaunchKernelGGL(pool_kernel, dim3(gsz(P1 / 8 * c1)), dim3(256), 0, s, a.cat1, c2 + c1, c2, c1, D1, H1, W1, a.p1);
+    conv(a.p1, c1, 0, c1, D2, H2, W2, wb + Ls[4].w_off, w + Ls[4].b_off, a.a2, c2, 0, c2, true, true, s);
+    conv(a.a2, c2, 0, c2, D2, H2, W2, wb + Ls[5].w_off, w + Ls[5].b_off, a.a3, c2, 0, c2, true, true, s);
+    hipLaunchKernelGGL(up_kernel, dim3(gsz(P1 * c2)), dim3(256), 0, s, a.a3, c2, D2, H2, W2, a.cat1, c2 + c1, 0);
+    conv(a.cat1, c2 + c1, 0, c2 + c1, D1, H1, W1, wb + Ls[6].w_off, w + Ls[6].b_off, a.a4, c1, 0, c1, true, true, s);
+    conv(a.a4, c1, 0, c1, D1, H1, W1, wb + Ls[7].w_off, w + Ls[7].b_off, a.a5, c1, 0, c1, true, true, s);
+    hipLaunchKernelGGL(up_kernel, dim3(gsz(P0 * c1)), dim3(256), 0, s, a.a5, c1, D1, H1, W1, a.cat0, c1 + c0, 0);
+    conv(a.cat0, c1 + c0, 0, c1 + c0, D, H, W, wb + Ls[8].w_off, w + Ls[8].b_off, a.a6, c0, 0, c0, true, true, s);
+    conv(a.a6, c0, 0, c0, D, H, W, wb + Ls[9].w_off, w + Ls[9].b_off, a.a7, c0, 0, c0, true, true, s);
+    hipLaunchKernelGGL((conv_out_kernel<16>), dim3(gsz(P0)), dim3(256), 0, s, a.a7, P0,
+                       w + Ls[10].w_off, w + Ls[10].b_off, out ? out : a.out);
+    AIM_HIP(hipGetLastError());
+  }
+
+  // backward pass after forward(in) on the same sample; dout fp32 [P][2];
+  // gradients are added to g
+  void backward(const float* in, const float* dout, hipStream_t s) {
+    Acts& a = acts;
+    const int D = a.D, H = a.H, W = a.W;
+    const int c0 = C, c1 = 2 * C, c2 = 4 * C;
+    const int D1 = D / 2, H1 = H / 2, W1 = W / 2, D2 = D / 4, H2 = H / 4, W2 = W / 4;
+    const int64_t P0 = int64_t(D) * H * W, P1 = P0 / 8, P2 = P1 / 8;
+    const Layer* Ls = layers.data();
+    // output layer
+    wgrad<uint16_t, float>(a.a7, c0, 0, c0, dout, 2, 0, 2, D, H, W, Ls[10], s);
+    hipLaunchKernelGGL((out_backward_kernel<16>), dim3(gsz(P0)), dim3(256), 0, s, dout,
+                       w + Ls[10].w_off, a.a7, P0, a.gb0);
+    // conv9
+    wgrad<uint16_t, uint16_t>(a.a6, c0, 0, c0, a.gb0, c0, 0, c0, D, H, W, Ls[9], s);
+    conv(a.gb0, c0, 0, c0, D, H, W, wf + Ls[9].flip_off, nullptr, a.g0, c0, 0, c0, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P0 * c0)), dim3(256), 0, s, a.g0, c0, 0, a.a6, c0, 0, c0, P0, a.gb0);
+    // conv8 (input cat0 = [up(a5) | s0])
+    wgrad<uint16_t, uint16_t>(a.cat0, c1 + c0, 0, c1 + c0, a.gb0, c0, 0, c0, D, H, W, Ls[8], s);
+    conv(a.gb0, c0, 0, c0, D, H, W, wf + Ls[8].flip_off, nullptr, a.gcat0, c1 + c0, 0, c1 + c0, false, false, s);
+    hipLaunchKernelGGL(up_backward_kernel, dim3(gsz(P1 * c1)), dim3(256), 0, s, a.gcat0, c1 + c0, 0, c1, D1, H1, W1, a.a5, a.gb1);
+    // conv7
+    wgrad<uint16_t, uint16_t>(a.a4, c1, 0, c1, a.gb1, c1, 0, c1, D1, H1, W1, Ls[7], s);
+    conv(a.gb1, c1, 0, c1, D1, H1, W1, wf + Ls[7].flip_off, nullptr, a.g1, c1, 0, c1, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P1 * c1)), dim3(256), 0, s, a.g1, c1, 0, a.a4, c1, 0, c1, P1, a.gb1);
+    // conv6 (input cat1 = [up(a3) | s1])
+    wgrad<uint16_t, uint16_t>(a.cat1, c2 + c1, 0, c2 + c1, a.gb1, c1, 0, c1, D1, H1, W1, Ls[6], s);
+    conv(a.gb1, c1, 0, c1, D1, H1, W1, wf + Ls[6].flip_off, nullptr, a.gcat1, c2 + c1, 0, c2 + c1, false, false, s);
+    hipLaunchKernelGGL(up_backward_kernel, dim3(gsz(P2 * c2)), dim3(256), 0, s, a.gcat1, c2 + c1, 0, c2, D2, H2, W2, a.a3, a.gb2);
+    // conv5
+    wgrad<uint16_t, uint16_t>(a.a2, c2, 0, c2, a.gb2, c2, 0, c2, D2, H2, W2, Ls[5], s);
+    conv(a.gb2, c2, 0, c2, D2, H2, W2, wf + Ls[5].flip_off, nullptr, a.g2, c2, 0, c2, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P2 * c2)), dim3(256), 0, s, a.g2, c2, 0, a.a2, c2, 0, c2, P2, a.gb2);
+    // conv4 (input p1)
+    wgrad<uint16_t, uint16_t>(a.p1, c1, 0, c1, a.gb2, c2, 0, c2, D2, H2, W2, Ls[4], s);
+    conv(a.gb2, c2, 0, c2, D2, H2, W2, wf + Ls[4].flip_off, nullptr, a.g2, c1, 0, c1, false, false, s);
+    hipLaunchKernelGGL(pool_backward_kernel, dim3(gsz(P1 * c1)), dim3(256), 0, s, a.g2, c1, D1, H1, W1,
+                       a.gcat1, c2 + c1, c2, a.cat1, c2 + c1, c2, a.gb1);
+    // conv3
+    wgrad<uint16_t, uint16_t>(a.a1, c1, 0, c1, a.gb1, c1, 0, c1, D1, H1, W1, Ls[3], s);
+    conv(a.gb1, c1, 0, c1, D1, H1, W1, wf + Ls[3].flip_off, nullptr, a.g1, c1, 0, c1, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P1 * c1)), dim3(256), 0, s, a.g1, c1, 0, a.a1, c1, 0, c1, P1, a.gb1);
+    // conv2 (input p0)
+    wgrad<uint16_t, uint16_t>(a.p0, c0, 0, c0, a.gb1, c1, 0, c1, D1, H1, W1, Ls[2], s);
+    conv(a.gb1, c1, 0, c1, D1, H1, W1, wf + Ls[2].flip_off, nullptr, a.g1, c0, 0, c0, false, false, s);
+    hipLaunchKernelGGL(pool_backward_kernel, dim3(gsz(P0 * c0)), dim3(256), 0, s, a.g1, c0, D, H, W,
+                       a.gcat0, c1 + c0, c1, a.cat0, c1 + c0, c1, a.gb0);
+    // conv1
+    wgrad<uint16_t, uint16_t>(a.a0, c0, 0, c0, a.gb0, c0, 0, c0, D, H, W, Ls[1], s);
+    conv(a.gb0, c0, 0, c0, D, H, W, wf + Ls[1].flip_off, nullptr, a.g0, c0, 0, c0, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P0 * c0)), dim3(256), 0, s, a.g0, c0, 0, a.a0, c0, 0, c0, P0, a.gb0);
+    // conv0 (fp32 input, 2 channels)
+    wgrad<float, uint16_t>(in, 2, 0, 2, a.gb0, c0, 0, c0, D, H, W, Ls[0], s);
+    AIM_HIP(hipGetLastError());
+  }
+
+  void zero_grad(hipStream_t s) {
+    hipLaunchKernelGGL(fill_kernel, dim3(gsz(nparam)), dim3(256), 0, s, g, nparam, 0.f);
+    AIM_HIP(hipGetLastError());
+  }
+
+  void adam(double lr, hipStream_t s) {
+    ++step;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, float(step)), c2 = 1.f - std::pow(b2, float(step));
+    hipLaunchKernelGGL(adam_kernel, dim3(gsz(nparam)), dim3(256), 0, s, w, g, m, v, nparam,
+                       float(lr), b1, b2, 1e-8f, c1, c2);
+    AIM_HIP(hipGetLastError());
+    refresh(s);
+  }
+};
+
+namespace aim {
+// used by the solver integration in abi.cpp
+void unet_forward(aim_unet u, const void* in, int D, int H, int W, void* out, hipStream_t s) {
+  u->forward(static_cast<const float*>(in), D, H, W, static_cast<float*>(out), s);
+}
+void unet_backward(aim_unet u, const void* in, const void* dout, hipStream_t s) {
+  u->backward(static_cast<const float*>(in), static_cast<const float*>(dout), s);
+}
+void unet_zero_grad(aim_unet u, hipStream_t s) { u->zero_grad(s); }
+void unet_adam(aim_unet u, double lr, hipStream_t s) { u->adam(lr, s); }
+}  // namespace aim
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+namespace {
+aim_status ufail(aim_status s, const std::string& m);
+template <typename F>
+aim_status uguard(F&& f) {
+  try {
+    f();
+    return AIM_OK;
+  } catch (const aim::Error& e) {
+    return ufail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return ufail(AIM_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return ufail(AIM_ERR_DEVICE, e.what());
+  }
+}
+}  // namespace
+
+// error text shared with the rest of the library
+namespace aim {
+void set_last_error(const std::string& m);
+}
+namespace {
+aim_status ufail(aim_status s, const std::string& m) {
+  aim::set_last_error(m);
+  return s;
+}
+}  // namespace
+
+extern "C" {
+
+aim_status aim_unet_create(int32_t base_channels, uint64_t seed, aim_unet* out) {
+  if (!out) return ufail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (base_channels != 16) return ufail(AIM_ERR_INVALID_ARG, "base_channels must be 16");
+  std::unique_ptr<aim_unet_s> u(new aim_unet_s());
+  const aim_status st = uguard([&] {
+    u->C = base_channels;
+    u->build_layers();
+    u->alloc_params();
+    // He-normal weights (the 1x1 output layer: variance 1/fan_in), zero biases
+    std::vector<float> h(u->nparam, 0.f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (size_t li = 0; li < u->layers.size(); ++li) {
+      const auto& L = u->layers[li];
+      const int64_t n = int64_t(L.cout) * L.taps * L.cin;
+      const double fan = double(L.cin) * L.taps;
+      const double std = li + 1 == u->layers.size() ? std::sqrt(1.0 / fan) : std::sqrt(2.0 / fan);
+      for (int64_t i = 0; i < n; ++i) h[L.w_off + i] = float(nd(rng) * std);
+    }
+    AIM_HIP(hipMemcpy(u->w, h.data(), u->nparam * 4, hipMemcpyHostToDevice));
+    u->refresh(nullptr);
+    AIM_HIP(hipDeviceSynchronize());
+  });
+  if (st != AIM_OK) return st;
+  *out = u.release();
+  return AIM_OK;
+}
+
+aim_status aim_unet_destroy(aim_unet u) {
+  return uguard([&] { delete u; });
+}
+
+aim_status aim_unet_num_params(aim_unet u, int64_t* n) {
+  if (!u || !n) return ufail(AIM_ERR_INVALID_ARG, "null argument");
+  *n = u->nparam;
+  return AIM_OK;
+}
+
+aim_status aim_unet_get_params(aim_unet u, float* host, float* grad_host) {
+  if (!u) return ufail(AIM_ERR_INVALID_ARG, "null argument");
+  return uguard([&] {
+    AIM_HIP(hipDeviceSynchronize());
+    if (host) AIM_HIP(hipMemcpy(host, u->w, u->nparam * 4, hipMemcpyDeviceToHost));
+    if (grad_host) AIM_HIP(hipMemcpy(grad_host, u->g, u->nparam * 4, hipMemcpyDeviceToHost));
+  });
+}
+
+aim_status aim_unet_set_params(aim_unet u, const float* host) {
+  if (!u || !host) return ufail(AIM_ERR_INVALID_ARG, "null argument");
+  return uguard([&] {
+    for (int64_t i = 0; i < u->nparam; ++i)
+      AIM_REQUIRE(std::isfinite(host[i]), AIM_ERR_INVALID_ARG, "non-finite parameter");
+    AIM_HIP(hipMemcpy(u->w, host, u->nparam * 4, hipMemcpyHostToDevice));
+    u->refresh(nullptr);
+    AIM_HIP(hipDeviceSynchronize());
+  });
+}
+
+aim_status aim_unet_forward(aim_unet u, const void* in_dev, void* out_dev, int32_t nbatch,
+                            const int32_t dims[3], void* hip_stream) {
+  if (!u || !in_dev || !out_dev || !dims) return ufail(AIM_ERR_INVALID_ARG, "null argument");
+  return uguard([&] {
+    AIM_REQUIRE(nbatch >= 1, AIM_ERR_INVALID_ARG, "nbatch must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int64_t P = int64_t(dims[0]) * dims[1] * dims[2];
+    for (int b = 0; b < nbatch; ++b)
+      u->forward(static_cast<const float*>(in_dev) + 2 * P * b, dims[2], dims[1], dims[0],
+                 static_cast<float*>(out_dev) + 2 * P * b, s);
+  });
+}
+
+aim_status aim_unet_train_grid(aim_unet u, const void* in_dev, const void* target_dev,
+                               int32_t nbatch, const int32_t dims[3], double lr, int32_t apply,
+                               double* loss_host, void* hip_stream) {
+  if (!u || !in_dev || !target_dev || !dims) return ufail(AIM_ERR_INVALID_ARG, "null argument");
+  return uguard([&] {
+    AIM_REQUIRE(nbatch >= 1, AIM_ERR_INVALID_ARG, "nbatch must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int64_t P = int64_t(dims[0]) * dims[1] * dims[2];
+    u->zero_grad(s);
+    constexpr int kParts = 256;
+    float* dout = nullptr;
+    float* part = nullptr;
+    AIM_HIP(hipMalloc(&dout, 2 * P * 4));
+    hipError_t e = hipMalloc(&part, size_t(kParts) * nbatch * 4);
+    if (e != hipSuccess) {
+      (void)hipFree(dout);
+      AIM_HIP(e);
+    }
+    std::vector<float> hp(size_t(kParts) * nbatch);
+    try {
+      for (int b = 0; b < nbatch; ++b) {
+        const float* in = static_cast<const float*>(in_dev) + 2 * P * b;
+        const float* tg = static_cast<const float*>(target_dev) + 2 * P * b;
+        u->forward(in, dims[2], dims[1], dims[0], nullptr, s);
+        // mean squared error over all entries of the batch
+        const float inv = 1.f / (float(2 * P) * float(nbatch));
+        hipLaunchKernelGGL(mse_kernel, dim3(kParts), dim3(256), 0, s, u->acts.out, tg, 2 * P,
+                           2.f * inv, inv, dout, part + size_t(kParts) * b);
+        AIM_HIP(hipGetLastError());
+        u->backward(in, dout, s);
+      }
+      if (apply) u->adam(lr, s);
+      AIM_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * 4, hipMemcpyDeviceToHost, s));
+      AIM_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipFree(dout);
+      (void)hipFree(part);
+      throw;
+    }
+    (void)hipFree(dout);
+    (void)hipFree(part);
+    double loss = 0.0;
+    for (float v : hp) loss += v;
+    if (loss_host) *loss_host = loss;
+  });
+}
+
+aim_status aim_unet_save(aim_unet u, const char* path) {
+  if (!u || !path) return ufail(AIM_ERR_INVALID_ARG, "null argument");
+  return uguard([&] {
+    std::vector<float> h(u->nparam);
+    AIM_HIP(hipDeviceSynchronize());
+    AIM_HIP(hipMemcpy(h.data(), u->w, u->nparam * 4, hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    AIM_REQUIRE(f != nullptr, AIM_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    const char magic[8] = {'A', 'I', 'M', 'U', 'N', 'E', 'T', '1'};
+    const int64_t hdr[2] = {u->C, u->nparam};
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, 8, 2, f) == 2 &&
+              std::fwrite(h.data(), 4, h.size(), f) == h.size();
+    ok = (std::fclose(f) == 0) && ok;
+    AIM_REQUIRE(ok, AIM_ERR_INVALID_ARG, "write failed");
+  });
+}
+
+aim_status aim_unet_load(const char* path, aim_unet* out) {
+  if (!path || !out) return ufail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return ufail(AIM_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  char magic[8];
+  int64_t hdr[2];
+  const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "AIMUNET1", 8) == 0 &&
+                  std::fread(hdr, 8, 2, f) == 2;
+  if (!ok || hdr[0] != 16) {
+    std::fclose(f);
+    return ufail(AIM_ERR_INVALID_ARG, "not a U-Net weight file");
+  }
+  aim_unet u = nullptr;
+  aim_status st = aim_unet_create(int32_t(hdr[0]), 0, &u);
+  if (st != AIM_OK) {
+    std::fclose(f);
+    return st;
+  }
+  std::vector<float> h(u->nparam);
+  const bool ok2 = hdr[1] == u->nparam && std::fread(h.data(), 4, h.size(), f) == h.size();
+  std::fclose(f);
+  if (!ok2) {
+    aim_unet_destroy(u);
+    return ufail(AIM_ERR_INVALID_ARG, "weight file size mismatch");
+  }
+  st = aim_unet_set_params(u, h.data());
+  if (st != AIM_OK) {
+    aim_unet_destroy(u);
+    return st;
+  }
+  *out = u;
+  return AIM_OK;
+}
+
+}  // extern "C"

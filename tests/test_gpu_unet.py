@@ -1,0 +1,99 @@
+"""GPU U-Net kernels against the NumPy reference (oracle/unet.py): forward
+output, gradients of every layer, and training progress.  The reference is
+evaluated with the same bfloat16 rounding points as the kernels, so the
+remaining differences come from accumulation order (forward) and from the
+bfloat16 storage of gradient tensors between layers (backward)."""
+import numpy as np
+import pytest
+
+from oracle import unet as ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2009_02281_amd import binding  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def grid_c64(shape_zyx, seed):
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(shape_zyx + (2,)).astype(np.float32)
+    return g
+
+
+def to_dev(g):
+    return torch.from_numpy(np.ascontiguousarray(g)).view(torch.complex64)[..., 0].cuda()
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 16), (12, 8, 8)])
+def test_forward_matches_reference(shape):
+    net = binding.UNet(seed=5)
+    p = binding.unet_params_to_layers(net.params())
+    x = grid_c64(shape, 7)
+    out = net.forward(to_dev(x)).cpu().numpy()
+    out = np.stack([out.real, out.imag], axis=-1)
+    want = ref.UNet(p, bf16=True).forward(x.astype(np.float64))
+    err = rel(out, want)
+    print(f"[gpu] unet forward {shape}: rel err {err:.2e}", flush=True)
+    assert err <= 1e-2
+    net.close()
+
+
+def test_gradients_match_reference():
+    net = binding.UNet(seed=11)
+    rng = np.random.default_rng(12)
+    flat = net.params()
+    layers = binding.unet_params_to_layers(flat)
+    # small random biases so that no layer is silent
+    off = 0
+    for W, b in layers:
+        off += W.size
+        flat[off:off + b.size] = 0.05 * rng.standard_normal(b.size)
+        off += b.size
+    net.set_params(flat)
+    layers = binding.unet_params_to_layers(flat)
+    shape = (8, 8, 16)
+    x = grid_c64(shape, 13)
+    t = grid_c64(shape, 14)
+    loss = net.train_grid(to_dev(x), to_dev(t), apply=False)
+    g = binding.unet_params_to_layers(net.grads())
+    r = ref.UNet(layers, bf16=True)
+    want_loss = r.loss(x.astype(np.float64), t.astype(np.float64))
+    gw = r.backward(t.astype(np.float64))
+    assert loss == pytest.approx(want_loss, rel=1e-2)
+    for i, ((dW, db), (rW, rb)) in enumerate(zip(g, gw)):
+        e_w, e_b = rel(dW, rW), rel(db, rb)
+        print(f"    layer {i}: dW {e_w:.2e} db {e_b:.2e}", flush=True)
+        assert e_w <= 3e-2 and e_b <= 3e-2, i
+    net.close()
+
+
+def test_training_reduces_loss_and_weights_roundtrip(tmp_path):
+    net = binding.UNet(seed=21)
+    shape = (8, 8, 8)
+    xs = [to_dev(grid_c64(shape, 30 + i)) for i in range(4)]
+    # a fixed, learnable target: a smoothed copy of the input
+    ts = []
+    for x in xs:
+        h = x.cpu().numpy()
+        sm = (np.roll(h, 1, 0) + h + np.roll(h, -1, 0)) / 3.0
+        ts.append(torch.from_numpy(sm.astype(np.complex64)).cuda())
+    X = torch.stack(xs)
+    T = torch.stack(ts)
+    first = net.train_grid(X, T, lr=2e-3)
+    for _ in range(60):
+        last = net.train_grid(X, T, lr=2e-3)
+    print(f"[gpu] unet training loss {first:.4f} -> {last:.4f}", flush=True)
+    assert last < 0.5 * first
+    path = str(tmp_path / "w.bin")
+    net.save(path)
+    net2 = binding.UNet.load(path)
+    assert np.array_equal(net.params(), net2.params())
+    assert torch.equal(net.forward(X), net2.forward(X))
+    net.close()
+    net2.close()
