@@ -62,16 +62,20 @@ typedef enum {
   AIM_PC_NEARBLOCK = 2,  /* block-Jacobi on spatial clusters of A_s,NR: the
                             near-region/block choice of the same section, built
                             from static entries only                             */
-  AIM_PC_UNET = 3        /* learned grid preconditioner (aim_unet_*), applied
-                            inside flexible GMRES, with the near-block
-                            preconditioner as its fallback                         */
+  AIM_PC_UNET = 3        /* learned grid preconditioner attached with
+                            aim_plan_set_unet, applied inside flexible GMRES
+                            (right preconditioning with stored Z), gated, with
+                            aim_solve_opts.fallback_pc as its fallback             */
 } aim_pc_kind;
 
 typedef enum {
   AIM_STAGE_PROJECT = 0,     /* x[nrhs][N]            -> q[nrhs][Ng]  (q = P x)        */
   AIM_STAGE_CONVOLVE = 1,    /* q[nrhs][Ng]           -> phi[nrhs][Ng] (phi = H(k) q)  */
   AIM_STAGE_INTERPOLATE = 2, /* phi[nrhs][Ng]         -> y[nrhs][N]   (y = P^T phi)    */
-  AIM_STAGE_NEAR = 3         /* x[nrhs][N]            -> y[nrhs][N]   (y = C x)        */
+  AIM_STAGE_NEAR = 3,        /* x[nrhs][N]            -> y[nrhs][N]   (y = C x)        */
+  AIM_STAGE_LEARNED_PC = 4   /* x[nrhs][N] complex128 -> y[nrhs][N] complex128,
+                                y = M(x) of the attached network (aim_plan_set_unet);
+                                prec must be AIM_C128                             */
 } aim_stage;
 
 typedef enum { AIM_RHS_PLANE_WAVE = 0, AIM_RHS_GAUSSIAN_PATCH = 1 } aim_rhs_kind;
@@ -146,6 +150,12 @@ typedef struct {
   double inner_rtol;         /* inner tolerance per refinement step (0: adaptive,
                                 0.3 rtol / current residual, kept within
                                 [3e-6, 0.1])                                      */
+  aim_pc_kind fallback_pc;   /* pc = AIM_PC_UNET only: preconditioner the solve
+                                continues with when the learned one is gated out
+                                (AIM_PC_NONE or AIM_PC_NEARBLOCK; 0 = none)        */
+  double gate;               /* pc = AIM_PC_UNET only: a restart cycle must cut
+                                every unconverged residual to below gate times
+                                its previous value (0: 0.7)                        */
 } aim_solve_opts;
 
 /* Per-right-hand-side outcome (host array of nrhs entries). */
@@ -300,6 +310,63 @@ aim_status aim_unet_train_grid(aim_unet net, const void* in_dev, const void* tar
                                double* loss_host, void* hip_stream);
 aim_status aim_unet_save(aim_unet net, const char* path);
 aim_status aim_unet_load(const char* path, aim_unet* out);
+
+/* ---- Learned preconditioner on a plan ------------------------------------
+ * The paper has no learned component; this is an addition on top of the
+ * AIMx solve.  The network U maps the projected, normalised residual on the
+ * AIM grid to a grid correction, which W = P^T (the interpolation of
+ * eq. LAIMx) brings back to the mesh.  With B the base preconditioner:
+ *   M(v) = B v + tau ||v|| (P^T U(g(v))) / area,
+ *   g(v) = P (v/||v||) in complex64, scaled to unit RMS over the grid.
+ * M is nonlinear, so aim_solve runs flexible GMRES (the stored Z basis).
+ * Grid dimensions must be multiples of 4 and the plan must hold the
+ * complex64 tables (precisions bit 1).  The network must have base width 16.
+ *
+ * Training data are pairs (r_t, e_t = x* - x_t) logged from plain GMRES on
+ * training geometries; the network is trained so that
+ *   (P^T U(g(r_t))) / area  ~  (e_t - B r_t) / (tau ||r_t||)
+ * in the mean square over triangles (aim_pc_targets, aim_pc_train_step). */
+
+/* Attach (net != NULL) or detach (net == NULL) a network.  base_pc is B
+ * (AIM_PC_NONE, AIM_PC_DIAG or AIM_PC_NEARBLOCK) and tau > 0 the target scale
+ * used in training.  The plan keeps the pointer, not a copy: the network
+ * must outlive its use by aim_solve.  Blocking. */
+aim_status aim_plan_set_unet(aim_plan plan, aim_unet net, aim_pc_kind base_pc, double tau);
+
+/* Solve A x = b with plain restarted GMRES (complex128, no preconditioner,
+ * x0 = 0) and log a training pair at every restart of every unconverged
+ * system: r_out[k] = r_t, e_out[k] = x* - x_t ([max_pairs][N] complex128
+ * device buffers, caller-owned), rhs_out_host[k] = the system it came from
+ * (may be NULL).  At most max_pairs pairs are written; *npairs is the
+ * count.  Returns AIM_ERR_NOT_CONVERGED (pairs still written) if a system
+ * did not reach rtol, since e_t is then inexact.  Blocking. */
+aim_status aim_log_pairs(aim_plan plan, const void* b_dev, int32_t nrhs,
+                         const int32_t* freq_idx_host, double rtol, int32_t restart,
+                         int32_t max_iter, void* r_out_dev, void* e_out_dev,
+                         int32_t* rhs_out_host, int32_t max_pairs, int32_t* npairs,
+                         void* hip_stream);
+
+/* Network inputs and targets of npairs logged pairs:
+ *   grid_out[k]   = g(r_k)                      [npairs][Ng] complex64
+ *   target_out[k] = (e_k - B r_k) / ||r_k||     [npairs][N]  complex128
+ * (device buffers, caller-owned).  *sumsq_host = sum of |target|^2 over all
+ * entries (tau^2 = sumsq / (pairs * N) over the whole training set gives a
+ * unit-scale target).  Blocking. */
+aim_status aim_pc_targets(aim_plan plan, aim_pc_kind base_pc, const void* r_pairs_dev,
+                          const void* e_pairs_dev, int32_t npairs, void* grid_out_dev,
+                          void* target_out_dev, double* sumsq_host, void* hip_stream);
+
+/* One optimiser step over the samples sample_idx_host[0..nsamples) (indices
+ * into grids/targets as written by aim_pc_targets on this plan, each in
+ * [0, npairs)): loss = mean over samples and triangles of
+ * |(P^T U(grid))/area - target/tau|^2, gradients through P^T, the network's
+ * backward pass, then Adam with learning rate lr if apply != 0.  *loss_host
+ * receives the loss before the step.  nsamples is limited by the plan's
+ * scratch (at least 128).  Blocking. */
+aim_status aim_pc_train_step(aim_plan plan, aim_unet net, const void* grids_dev,
+                             const void* targets_dev, int32_t npairs,
+                             const int32_t* sample_idx_host, int32_t nsamples, double tau,
+                             double lr, int32_t apply, double* loss_host, void* hip_stream);
 
 /* Host copies of setup tables, for validation against an independent
  * implementation.  Any pointer may be NULL to skip that table.

@@ -26,6 +26,7 @@ class SolveInfo:
     rel_resid: float = np.inf
     history: list = field(default_factory=list)
     breakdown: bool = False
+    fallback_used: bool = False
 
 
 def fgmres(A, b, tol: float = 1e-6, restart: int = 30, max_iter: int = 1000,
@@ -71,6 +72,9 @@ def fgmres(A, b, tol: float = 1e-6, restart: int = 30, max_iter: int = 1000,
                 H[i, j] = np.vdot(Vb[i], w)
                 w = w - H[i, j] * Vb[i]
             H[j + 1, j] = np.linalg.norm(w)
+            if not np.all(np.isfinite(H[:j + 2, j])):    # e.g. a non-finite M(v)
+                info.breakdown = True
+                break
             for i in range(j):                           # earlier rotations
                 t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
                 H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + np.conj(cs[i]) * H[i + 1, j]
@@ -121,3 +125,46 @@ def iterative_refinement(A_hi, inner_solve, b, tol: float, max_refine: int = 20)
             return x, rel <= tol, hist
         x = x + inner_solve(r)
     return x, False, hist
+
+
+def gated_fgmres(A, b, M, M_fallback=None, gate: float = 0.7, tol: float = 1e-6,
+                 restart: int = 30, max_iter: int = 1000):
+    """FGMRES with a gate on an untrusted (learned) preconditioner ``M``.
+
+    Restart cycles run with ``M``.  After every cycle the true relative
+    residual must have fallen below ``gate`` times its value at the start of
+    the cycle (or below ``tol``); if it has not, or a value is not finite,
+    the rest of the solve runs with ``M_fallback`` (identity if None) from
+    the last finite iterate, and ``info.fallback_used`` is set."""
+    b = np.asarray(b, dtype=np.complex128)
+    x = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    rel = 1.0 if bnorm > 0 else 0.0
+    total = SolveInfo()
+    switch = False
+    while total.iters < max_iter and rel > tol:
+        xn, info = fgmres(A, b, tol=tol, restart=restart,
+                          max_iter=min(restart, max_iter - total.iters), M=M, x0=x)
+        total.iters += info.iters
+        total.matvecs += info.matvecs
+        total.history += info.history
+        if info.breakdown or not np.isfinite(info.rel_resid) or not np.all(np.isfinite(xn)):
+            switch = True
+            break
+        x = xn
+        if info.rel_resid > tol and info.rel_resid > gate * rel:
+            rel = info.rel_resid
+            switch = True
+            break
+        rel = info.rel_resid
+    if switch:
+        total.fallback_used = True
+        x, info = fgmres(A, b, tol=tol, restart=restart,
+                         max_iter=max(1, max_iter - total.iters), M=M_fallback, x0=x)
+        total.iters += info.iters
+        total.matvecs += info.matvecs
+        total.history += info.history
+        rel = info.rel_resid
+    total.rel_resid = float(np.linalg.norm(b - A(x)) / bnorm) if bnorm > 0 else 0.0
+    total.converged = total.rel_resid <= tol
+    return x, total

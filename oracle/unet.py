@@ -166,9 +166,14 @@ class UNet:
     def backward(self, target):
         """Parameter gradients of the mean-squared loss after forward()."""
         a = self.act
+        return self.backward_from(2.0 * (a["out"] - target) / a["out"].size)
+
+    def backward_from(self, dout):
+        """Parameter gradients of a loss whose gradient with respect to the
+        output is ``dout`` (same shape as the output), after forward()."""
+        a = self.act
         P = self.params
         g = [None] * len(P)
-        dout = 2.0 * (a["out"] - target) / a["out"].size
         W, _ = P[10]
         g[10] = (np.einsum("zyxo,zyxi->oi", dout, a["a7"])[:, None, :], dout.reshape(-1, 2).sum(0))
         d = (dout @ W[:, 0, :]) * (a["a7"] > 0)

@@ -21,7 +21,7 @@ STATUS = {0: "AIM_OK", 1: "AIM_ERR_INVALID_ARG", 2: "AIM_ERR_GEOMETRY", 3: "AIM_
           7: "AIM_ERR_BREAKDOWN", 8: "AIM_ERR_STATE"}
 PREC = {"c128": 0, "c64": 1}
 PC = {"none": 0, "diag": 1, "nearblock": 2, "unet": 3}
-STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3}
+STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc": 4}
 RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec", "aim_apply_stage",
@@ -30,6 +30,7 @@ EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim
             "aim_graph_destroy", "aim_unet_create", "aim_unet_destroy", "aim_unet_num_params",
             "aim_unet_get_params", "aim_unet_set_params", "aim_unet_forward",
             "aim_unet_train_grid", "aim_unet_save", "aim_unet_load",
+            "aim_plan_set_unet", "aim_log_pairs", "aim_pc_targets", "aim_pc_train_step",
             "aim_last_error", "aim_version"]
 KERNELS = ["project", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
            "interp_near"]
@@ -72,7 +73,7 @@ class SolveOpts(C.Structure):
     _fields_ = [
         ("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
         ("max_refine", C.c_int32), ("inner", C.c_int32), ("pc", C.c_int32),
-        ("inner_rtol", C.c_double),
+        ("inner_rtol", C.c_double), ("fallback_pc", C.c_int32), ("gate", C.c_double),
     ]
 
 
@@ -127,6 +128,13 @@ def load_library(path: str = LIB_PATH):
     lib.aim_unet_load.argtypes = [C.c_char_p, C.POINTER(vp)]
     lib.aim_autotune.argtypes = [vp, i32, i32, i32, ip32, C.POINTER(C.c_double), vp]
     lib.aim_set_schedule.argtypes = [vp, i32, ip32]
+    dp = C.POINTER(C.c_double)
+    lib.aim_plan_set_unet.argtypes = [vp, vp, i32, C.c_double]
+    lib.aim_log_pairs.argtypes = [vp, vp, i32, ip32, C.c_double, i32, i32, vp, vp, ip32, i32,
+                                  ip32, vp]
+    lib.aim_pc_targets.argtypes = [vp, i32, vp, vp, i32, vp, vp, dp, vp]
+    lib.aim_pc_train_step.argtypes = [vp, vp, vp, vp, i32, ip32, i32, C.c_double, C.c_double,
+                                      i32, dp, vp]
     lib.aim_last_error.restype = C.c_char_p
     lib.aim_version.restype = C.c_char_p
     for name in EXPORTED:
@@ -163,6 +171,7 @@ class SolveResult:
     rel_resid: np.ndarray
     seconds: float
     status: int
+    fallback_used: np.ndarray = None
 
 
 class UNet:
@@ -456,12 +465,12 @@ class Plan:
 
     def apply_stage(self, stage: str, inp, freq_idx=None, prec: str = "c128", stream=None):
         """One stage of the matvec: 'project' x -> grid, 'convolve' grid ->
-        grid, 'interpolate' grid -> y, 'near' x -> C x.  Grids have shape
-        [nrhs, Nz, Ny, Nx]."""
+        grid, 'interpolate' grid -> y, 'near' x -> C x; or 'learned_pc'
+        x -> M(x) of the attached network.  Grids have shape [nrhs, Nz, Ny, Nx]."""
         import torch
         Nx, Ny, Nz = self.dims
         nrhs = inp.shape[0] if inp.dim() in (2, 4) else 1
-        if stage in ("project", "near"):
+        if stage in ("project", "near", "learned_pc"):
             self._check_vec(inp, prec, self.n, "input")
         else:
             self._check_vec(inp.reshape(nrhs, -1), prec, self.n_grid, "input grid")
@@ -489,15 +498,18 @@ class Plan:
 
     def solve(self, b, x0=None, freq_idx=None, rtol: float = 1e-6, restart: int = 30,
               max_iter: int = 1000, inner: str = "c128", pc: str = "none",
-              max_refine: int = 20, inner_rtol: float = 0.0, stream=None, raise_on_fail=True):
+              max_refine: int = 20, inner_rtol: float = 0.0, fallback_pc: str = "none",
+              gate: float = 0.0, stream=None, raise_on_fail=True):
         """Batched GMRES on b of shape [nrhs, N] (complex128).  Returns
-        (x, SolveResult)."""
+        (x, SolveResult).  pc="unet" needs a network attached with set_unet;
+        fallback_pc and gate govern its fallback."""
         import torch
         b2 = b.reshape(-1, self.n)
         self._check_vec(b2, "c128", self.n, "b")
         nrhs = b2.shape[0]
         x = torch.zeros_like(b2) if x0 is None else x0.reshape(-1, self.n).clone()
-        opts = SolveOpts(rtol, restart, max_iter, max_refine, PREC[inner], PC[pc], inner_rtol)
+        opts = SolveOpts(rtol, restart, max_iter, max_refine, PREC[inner], PC[pc], inner_rtol,
+                         PC[fallback_pc], gate)
         infos = (SolveInfo * nrhs)()
         _, fp = _freq_arg(freq_idx, nrhs)
         st = self._lib.aim_solve(self._plan, C.c_void_p(b2.data_ptr()), C.c_void_p(x.data_ptr()),
@@ -510,5 +522,72 @@ class Plan:
             matvecs=np.array([i.matvecs for i in infos]),
             converged=np.array([bool(i.converged) for i in infos]),
             rel_resid=np.array([i.rel_resid for i in infos]),
-            seconds=float(infos[0].seconds) if nrhs else 0.0, status=st)
+            seconds=float(infos[0].seconds) if nrhs else 0.0, status=st,
+            fallback_used=np.array([bool(i.fallback_used) for i in infos]))
         return x.reshape(b.shape), res
+
+    # ---- learned preconditioner -------------------------------------------
+    def set_unet(self, net, base_pc: str = "diag", tau: float = 1.0):
+        """Attach a UNet (or detach with None) as the pc="unet" preconditioner."""
+        self._unet_ref = net
+        _check(self._lib.aim_plan_set_unet(self._plan, net._h if net is not None else None,
+                                           PC[base_pc], tau))
+
+    def log_pairs(self, b, rtol: float = 1e-8, restart: int = 10, max_iter: int = 2000,
+                  max_pairs: int = 256, freq_idx=None, stream=None):
+        """Plain GMRES on b [nrhs, N]; returns (r, e, rhs) of the logged pairs:
+        r_t, e_t = x* - x_t at each restart (complex128 device tensors)."""
+        import torch
+        b2 = b.reshape(-1, self.n)
+        self._check_vec(b2, "c128", self.n, "b")
+        nrhs = b2.shape[0]
+        r = torch.empty((max_pairs, self.n), dtype=torch.complex128, device=b2.device)
+        e = torch.empty_like(r)
+        owner = np.zeros(max(max_pairs, 1), dtype=np.int32)
+        cnt = C.c_int32(0)
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_log_pairs(self._plan, C.c_void_p(b2.data_ptr()), nrhs, fp, rtol,
+                                       restart, max_iter, C.c_void_p(r.data_ptr()),
+                                       C.c_void_p(e.data_ptr()),
+                                       owner.ctypes.data_as(C.POINTER(C.c_int32)), max_pairs,
+                                       C.byref(cnt), _stream_ptr(stream)))
+        k = cnt.value
+        return r[:k], e[:k], owner[:k].copy()
+
+    def pc_targets(self, r, e, base_pc: str = "diag", stream=None):
+        """Network inputs [npairs, Nz, Ny, Nx] complex64 and targets [npairs, N]
+        complex128 of logged pairs, and the sum of |target|^2."""
+        import torch
+        self._check_vec(r, "c128", self.n, "r")
+        self._check_vec(e, "c128", self.n, "e")
+        if r.shape != e.shape:
+            raise ValueError("r and e must have the same shape")
+        npairs = r.shape[0]
+        Nx, Ny, Nz = self.dims
+        grids = torch.empty((npairs, Nz, Ny, Nx), dtype=torch.complex64, device=r.device)
+        tg = torch.empty_like(r)
+        ss = C.c_double(0.0)
+        _check(self._lib.aim_pc_targets(self._plan, PC[base_pc], C.c_void_p(r.data_ptr()),
+                                        C.c_void_p(e.data_ptr()), npairs,
+                                        C.c_void_p(grids.data_ptr()), C.c_void_p(tg.data_ptr()),
+                                        C.byref(ss), _stream_ptr(stream)))
+        return grids, tg, ss.value
+
+    def pc_train_step(self, net, grids, targets, idx, tau: float, lr: float = 1e-3,
+                      apply: bool = True, stream=None) -> float:
+        """One Adam step on the samples idx of (grids, targets); returns the
+        loss before the step."""
+        Nx, Ny, Nz = self.dims
+        if grids.shape[1:] != (Nz, Ny, Nx) or grids.dtype != self._dtype("c64"):
+            raise ValueError("grids must be [npairs, Nz, Ny, Nx] complex64")
+        self._check_vec(targets, "c128", self.n, "targets")
+        if targets.shape[0] != grids.shape[0]:
+            raise ValueError("grids and targets hold different numbers of pairs")
+        ia = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).ravel())
+        loss = C.c_double(0.0)
+        _check(self._lib.aim_pc_train_step(self._plan, net._h, C.c_void_p(grids.data_ptr()),
+                                           C.c_void_p(targets.data_ptr()), grids.shape[0],
+                                           ia.ctypes.data_as(C.POINTER(C.c_int32)), ia.size,
+                                           tau, lr, int(apply), C.byref(loss),
+                                           _stream_ptr(stream)))
+        return loss.value

@@ -14,6 +14,8 @@
 #include <cmath>
 #include <complex>
 #include <cstdlib>
+#include <functional>
+#include <random>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -113,6 +115,14 @@ struct aim_plan_s {
   void* d_tw64[3] = {nullptr, nullptr, nullptr};
   void* d_tw32[3] = {nullptr, nullptr, nullptr};
   double* d_k = nullptr;
+  double* d_area = nullptr;              // triangle areas (learned preconditioner)
+  // learned preconditioner (not owned) and its buffers
+  aim_unet unet = nullptr;
+  aim_pc_kind unet_base = AIM_PC_DIAG;
+  double unet_tau = 1.0;
+  void *ug_in = nullptr, *ug_out = nullptr, *um1 = nullptr, *um2 = nullptr, *upart = nullptr;
+  double* u_s = nullptr;
+  double* u_s2 = nullptr;
   void* d_work[2] = {nullptr, nullptr};  // [prec] 6 Ng per rhs
   void* d_grid[2] = {nullptr, nullptr};  // [prec] Ng per rhs
   int sched[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};  // FFT launch shapes per precision
@@ -441,6 +451,7 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
       p->d_clinv = p->upload(t.cl_inv, s);
     }
     p->d_k = p->upload(p->k, s);
+    p->d_area = p->upload(t.area, s);
     // twiddles per axis
     for (int a = 0; a < 3; ++a) {
       const std::vector<double> tw = aim::twiddles64(g.M[a]);
@@ -653,6 +664,11 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
   });
 }
 
+namespace {
+void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s);
+void check_unet_plan(aim_plan p);
+}  // namespace
+
 aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, const void* in,
                            void* out, int32_t nrhs, const int32_t* freq_idx_host,
                            void* hip_stream) {
@@ -694,6 +710,14 @@ aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, cons
                                          interp, !interp, s);
         break;
       }
+      case AIM_STAGE_LEARNED_PC:
+        AIM_REQUIRE(d, AIM_ERR_INVALID_ARG,
+                    "the learned preconditioner maps complex128 vectors (prec = AIM_C128)");
+        AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+                    "nrhs must be in 1..max_rhs");
+        check_unet_plan(p);
+        apply_unet_pc(p, in, out, nrhs, s);
+        break;
       default:
         throw Error(AIM_ERR_INVALID_ARG, "unknown stage");
     }
@@ -843,7 +867,22 @@ void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, c
   }
 }
 
-void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hipStream_t s) {
+void ensure_unet_buffers(aim_plan p, hipStream_t s) {
+  if (p->ug_in) return;
+  const int R = p->max_rhs;
+  const int64_t n = p->t.N, Ng = p->g.Ng;
+  p->ug_in = p->dalloc(size_t(Ng) * 8 * R, s);
+  p->ug_out = p->dalloc(size_t(Ng) * 8 * R, s);
+  p->um1 = p->dalloc(size_t(n) * 8 * R, s);
+  p->um2 = p->dalloc(size_t(n) * 8 * R, s);
+  const int64_t nchunk = (std::max(n, Ng) + 4095) / 4096;
+  p->upart = p->dalloc(size_t(16) * R * nchunk + 16 * 4096, s);
+  p->u_s = static_cast<double*>(p->dalloc(sizeof(double) * R, s));
+  p->u_s2 = static_cast<double*>(p->dalloc(sizeof(double) * R, s));
+}
+
+// Classical (linear) preconditioners: z = v, D^{-1} v or the near-block inverse.
+void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hipStream_t s) {
   const int64_t n = p->t.N;
   switch (pc) {
     case AIM_PC_NONE:
@@ -861,6 +900,50 @@ void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hipSt
   }
 }
 
+// Network input for nrhs complex128 mesh vectors v: the complex64 grid
+// P (v / ||v||) scaled to unit RMS over the grid, written to grid[r] (Ng
+// complex64 each).  Leaves 1/||v|| in p->u_s.
+void unet_input(aim_plan p, const void* v, int nrhs, void* grid, hipStream_t s) {
+  ensure_unet_buffers(p, s);
+  const int64_t n = p->t.N, Ng = p->g.Ng;
+  aim::launch_inv_norms_c128(v, n, nrhs, 1.0, p->upart, p->u_s, s);
+  aim::launch_scale_cast_c64(v, p->u_s, p->um1, n, nrhs, s);
+  aim::launch_project<float>(p->g, p_dev(p, AIM_C64), p->d_pblk, p->nblk, p->um1, n, grid, nrhs, s);
+  aim::launch_inv_norms_c64(grid, Ng, nrhs, std::sqrt(double(Ng)), p->upart, p->u_s2, s);
+  aim::launch_scale_c64(grid, p->u_s2, Ng, nrhs, s);
+}
+
+void check_unet_plan(aim_plan p) {
+  AIM_REQUIRE(!p->host_only, AIM_ERR_STATE, "host-only plan");
+  AIM_REQUIRE(p->prec & (1u << AIM_C64), AIM_ERR_STATE,
+              "the learned preconditioner needs the complex64 tables (precisions bit 1)");
+  for (int d = 0; d < 3; ++d)
+    AIM_REQUIRE(p->g.N[d] % 4 == 0, AIM_ERR_GRID, "grid dimensions must be multiples of 4");
+}
+
+// Learned preconditioner (a nonlinear map, so the solve is flexible GMRES):
+//   z = B v + tau ||v|| (P^T U(g)) / area,   g = unet_input(v),
+// B the base preconditioner, U the network; the grid work is complex64.
+void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s) {
+  AIM_REQUIRE(p->unet != nullptr, AIM_ERR_STATE, "no learned preconditioner attached");
+  const int64_t n = p->t.N, Ng = p->g.Ng;
+  unet_input(p, v, nrhs, p->ug_in, s);
+  for (int r = 0; r < nrhs; ++r)
+    aim::unet_forward(p->unet, static_cast<char*>(p->ug_in) + size_t(r) * Ng * 8, p->g.N[2],
+                      p->g.N[1], p->g.N[0], static_cast<char*>(p->ug_out) + size_t(r) * Ng * 8, s);
+  aim::launch_interp_near<float>(p->g, pt_dev(p, AIM_C64), csr_dev(p, AIM_C64), p->ug_out,
+                                 nullptr, p->um2, nrhs, true, false, s);
+  apply_base(p, p->unet_base, v, z, nrhs, s);
+  aim::launch_unet_combine(p->um2, p->d_area, p->unet_tau, p->u_s, z, n, nrhs, s);
+}
+
+void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hipStream_t s) {
+  if (pc == AIM_PC_UNET)
+    apply_unet_pc(p, v, z, nrhs, s);
+  else
+    apply_base(p, pc, v, z, nrhs, s);
+}
+
 void norms_host(aim_plan p, const void* v, int nrhs, hipStream_t s, std::vector<double>& out) {
   aim::launch_norms(v, p->t.N, nrhs, p->sv.partial, p->sv.nrm, s);
   AIM_HIP(hipMemcpyAsync(p->sv.nrm_host, p->sv.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
@@ -873,6 +956,13 @@ struct CycleStats {
   int matvecs = 0;
 };
 
+// raised when a restart cycle with the learned preconditioner makes too
+// little progress (the gate of the fallback logic)
+struct GateFail {};
+
+// called at every restart with (x, r, relative residuals) of all systems
+using CycleHook = std::function<void(const void*, const void*, const std::vector<double>&)>;
+
 // Restarted right-preconditioned GMRES on a packed batch: solves A x = b for
 // nrhs systems in lock step (x holds the initial guess).  Each system stops
 // extending its Krylov basis once its residual estimate is below tol * scale;
@@ -881,7 +971,8 @@ struct CycleStats {
 void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, void* x, int nrhs,
                  const int32_t* dfreq, const std::vector<double>& scale, double tol, int m,
                  int max_iter, bool x_is_zero, hipStream_t s, CycleStats& st,
-                 std::vector<double>& rel) {
+                 std::vector<double>& rel, const CycleHook* hook = nullptr, double gate = 0.0) {
+  std::vector<double> prev_rel;
   auto& w = p->sv;
   const int64_t n = p->t.N;
   const size_t vec = size_t(n) * 16;
@@ -911,6 +1002,11 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
       if (rel[r] > tol && active_iters[r] < max_iter) all_done = false;
       maxit_left = std::max(maxit_left, max_iter - active_iters[r]);
     }
+    if (gate > 0.0 && !prev_rel.empty())
+      for (int r = 0; r < nrhs; ++r)
+        if (rel[r] > tol && rel[r] > gate * prev_rel[r]) throw GateFail{};
+    prev_rel = rel;
+    if (hook) (*hook)(x, w.r, rel);
     if (all_done) return;
     const int mm = std::min(m, maxit_left);
     // V_0 = r / beta
@@ -1028,8 +1124,12 @@ extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs
     AIM_REQUIRE(o.rtol > 0.0 && std::isfinite(o.rtol), AIM_ERR_INVALID_ARG, "rtol must be positive");
     AIM_REQUIRE(o.restart >= 1 && o.restart <= 200, AIM_ERR_INVALID_ARG, "restart must be in 1..200");
     AIM_REQUIRE(o.max_iter >= 1, AIM_ERR_INVALID_ARG, "max_iter must be >= 1");
-    AIM_REQUIRE(o.pc >= AIM_PC_NONE && o.pc <= AIM_PC_NEARBLOCK, AIM_ERR_STATE,
-                "preconditioner not available in this build");
+    AIM_REQUIRE(o.pc >= AIM_PC_NONE && o.pc <= AIM_PC_UNET, AIM_ERR_INVALID_ARG,
+                "unknown preconditioner");
+    AIM_REQUIRE(o.fallback_pc >= AIM_PC_NONE && o.fallback_pc <= AIM_PC_NEARBLOCK,
+                AIM_ERR_INVALID_ARG, "fallback preconditioner must be none, diag or nearblock");
+    AIM_REQUIRE(o.pc != AIM_PC_UNET || p->unet != nullptr, AIM_ERR_STATE,
+                "no learned preconditioner attached (aim_plan_set_unet)");
     check_prec(p, AIM_C128);
     check_prec(p, o.inner);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -1049,57 +1149,97 @@ extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs
     for (auto& v : inf) std::memset(&v, 0, sizeof(v));
     CycleStats cst;
     std::vector<double> rel;
-    if (o.inner == AIM_C128) {
-      AIM_HIP(hipMemcpyAsync(w.xp, x, vec * nrhs, hipMemcpyDeviceToDevice, s));
-      gmres_batch(p, AIM_C128, o.pc, b, w.xp, nrhs, df, scale, o.rtol, o.restart, o.max_iter,
-                  false, s, cst, rel);
-      AIM_HIP(hipMemcpyAsync(x, w.xp, vec * nrhs, hipMemcpyDeviceToDevice, s));
-      for (int r = 0; r < nrhs; ++r) {
-        inf[r].matvecs = cst.matvecs;
-        inf[r].iters = cst.iters[r];
-      }
-    } else {
-      // complex128 iterative refinement around a complex64-matvec GMRES
-      const double inner_tol = o.inner_rtol > 0.0 ? o.inner_rtol : 1e-4;
-      int refine = 0;
-      std::vector<double> rn;
-      for (;;) {
-        apply_A(p, AIM_C128, x, w.bp, nrhs, df, s);  // bp = A x (complex128)
-        cst.matvecs++;
-        aim::launch_residual(b, w.bp, n * int64_t(nrhs), s);  // bp = b - A x
-        norms_host(p, w.bp, nrhs, s, rn);
-        bool done = true;
-        rel.assign(nrhs, 0.0);
+    // The learned preconditioner is gated: if a restart cycle fails to cut a
+    // residual by at least the gate factor, or a value is not finite, the
+    // solve continues from the current iterate with the fallback
+    // preconditioner (unpreconditioned or near-block GMRES).
+    aim_pc_kind pc = o.pc;
+    const double gate = pc == AIM_PC_UNET ? (o.gate > 0.0 ? o.gate : 0.7) : 0.0;
+    int fallback = 0;
+    auto run = [&](aim_pc_kind use_pc, double use_gate) {
+      if (o.inner == AIM_C128) {
+        AIM_HIP(hipMemcpyAsync(w.xp, x, vec * nrhs, hipMemcpyDeviceToDevice, s));
+        CycleStats cs;
+        gmres_batch(p, AIM_C128, use_pc, b, w.xp, nrhs, df, scale, o.rtol, o.restart, o.max_iter,
+                    false, s, cs, rel, nullptr, use_gate);
+        AIM_HIP(hipMemcpyAsync(x, w.xp, vec * nrhs, hipMemcpyDeviceToDevice, s));
+        cst.matvecs += cs.matvecs;
         for (int r = 0; r < nrhs; ++r) {
-          rel[r] = rn[r] / scale[r];
-          if (!std::isfinite(rel[r])) throw Error(AIM_ERR_BREAKDOWN, "non-finite residual");
-          if (rel[r] > o.rtol) done = false;
+          inf[r].matvecs = cst.matvecs;
+          inf[r].iters += cs.iters[r];
         }
-        if (done || refine >= std::max(0, o.max_refine)) break;
-        // inner solve A d = r with scale ||r|| (systems already converged get d = 0)
-        std::vector<double> iscale(nrhs);
-        for (int r = 0; r < nrhs; ++r) iscale[r] = rn[r] > 0.0 ? rn[r] : 1.0;
-        AIM_HIP(hipMemsetAsync(w.xp, 0, vec * nrhs, s));
-        // inner tolerance: enough to reach rtol from here, but not below what
-        // complex64 matvecs can resolve (unless the caller fixed it)
-        double itol = inner_tol;
-        if (o.inner_rtol <= 0.0) {
-          double worst = 0.0;
-          for (int r = 0; r < nrhs; ++r) worst = std::max(worst, rel[r]);
-          itol = std::max(3e-6, std::min(0.1, 0.3 * o.rtol / std::max(worst, 1e-300)));
+      } else {
+        // complex128 iterative refinement around a complex64-matvec GMRES
+        const double inner_tol = o.inner_rtol > 0.0 ? o.inner_rtol : 1e-4;
+        int refine = 0;
+        std::vector<double> rn;
+        for (;;) {
+          apply_A(p, AIM_C128, x, w.bp, nrhs, df, s);  // bp = A x (complex128)
+          cst.matvecs++;
+          aim::launch_residual(b, w.bp, n * int64_t(nrhs), s);  // bp = b - A x
+          norms_host(p, w.bp, nrhs, s, rn);
+          bool done = true;
+          rel.assign(nrhs, 0.0);
+          for (int r = 0; r < nrhs; ++r) {
+            rel[r] = rn[r] / scale[r];
+            if (!std::isfinite(rel[r])) throw Error(AIM_ERR_BREAKDOWN, "non-finite residual");
+            if (rel[r] > o.rtol) done = false;
+          }
+          if (done || refine >= std::max(0, o.max_refine)) break;
+          std::vector<double> iscale(nrhs);
+          for (int r = 0; r < nrhs; ++r) iscale[r] = rn[r] > 0.0 ? rn[r] : 1.0;
+          AIM_HIP(hipMemsetAsync(w.xp, 0, vec * nrhs, s));
+          // inner tolerance: enough to reach rtol from here, but not below what
+          // complex64 matvecs can resolve (unless the caller fixed it)
+          double itol = inner_tol;
+          if (o.inner_rtol <= 0.0) {
+            double worst = 0.0;
+            for (int r = 0; r < nrhs; ++r) worst = std::max(worst, rel[r]);
+            itol = std::max(3e-6, std::min(0.1, 0.3 * o.rtol / std::max(worst, 1e-300)));
+          }
+          std::vector<double> irel;
+          CycleStats ist;
+          gmres_batch(p, AIM_C64, use_pc, w.bp, w.xp, nrhs, df, iscale, itol, o.restart,
+                      o.max_iter, true, s, ist, irel, nullptr, use_gate);
+          cst.matvecs += ist.matvecs;
+          for (int r = 0; r < nrhs; ++r) inf[r].iters += ist.iters[r];
+          aim::launch_axpy_inplace(x, w.xp, n * int64_t(nrhs), s);
+          ++refine;
+          for (int r = 0; r < nrhs; ++r) inf[r].refinements = refine;
         }
-        std::vector<double> irel;
-        CycleStats ist;
-        gmres_batch(p, AIM_C64, o.pc, w.bp, w.xp, nrhs, df, iscale, itol, o.restart,
-                    o.max_iter, true, s, ist, irel);
-        cst.matvecs += ist.matvecs;
-        for (int r = 0; r < nrhs; ++r) inf[r].iters += ist.iters[r];
-        aim::launch_axpy_inplace(x, w.xp, n * int64_t(nrhs), s);
-        ++refine;
-        for (int r = 0; r < nrhs; ++r) inf[r].refinements = refine;
+        for (int r = 0; r < nrhs; ++r) inf[r].matvecs = cst.matvecs;
       }
-      for (int r = 0; r < nrhs; ++r) inf[r].matvecs = cst.matvecs;
+    };
+    if (pc == AIM_PC_UNET) {
+      try {
+        run(pc, gate);
+        bool ok = true;
+        for (int r = 0; r < nrhs; ++r) ok = ok && rel[r] <= o.rtol;
+        if (!ok) fallback = 1;
+      } catch (const GateFail&) {
+        // the gate fires at a restart, where the iterate is finite and its
+        // residual was just measured: keep the progress made so far
+        fallback = 1;
+        if (o.inner == AIM_C128)
+          AIM_HIP(hipMemcpyAsync(x, w.xp, vec * nrhs, hipMemcpyDeviceToDevice, s));
+        else
+          aim::launch_axpy_inplace(x, w.xp, n * int64_t(nrhs), s);
+      } catch (const Error& e) {
+        if (e.status != AIM_ERR_BREAKDOWN) throw;
+        // a non-finite value: x holds the last finite iterate unless the
+        // breakdown came from the outer residual, in which case start over
+        fallback = 1;
+        std::vector<double> xn;
+        norms_host(p, x, nrhs, s, xn);
+        bool finite = true;
+        for (double v : xn) finite = finite && std::isfinite(v);
+        if (!finite) AIM_HIP(hipMemsetAsync(x, 0, vec * nrhs, s));
+      }
+      if (fallback) run(o.fallback_pc, 0.0);
+    } else {
+      run(pc, 0.0);
     }
+    for (int r = 0; r < nrhs; ++r) inf[r].fallback_used = fallback;
     AIM_HIP(hipStreamSynchronize(s));
     const double secs = now_s() - t0;
     bool all = true;
@@ -1115,4 +1255,166 @@ extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs
   if (st != AIM_OK) return st;
   if (result != AIM_OK) return fail(result, "not every right-hand side reached rtol");
   return AIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned preconditioner: attach, training pairs, targets, training steps
+// ---------------------------------------------------------------------------
+extern "C" aim_status aim_plan_set_unet(aim_plan p, aim_unet net, aim_pc_kind base_pc,
+                                        double tau) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK, AIM_ERR_INVALID_ARG,
+                "base preconditioner must be none, diag or nearblock");
+    AIM_REQUIRE(std::isfinite(tau) && tau > 0.0, AIM_ERR_INVALID_ARG, "tau must be positive");
+    if (net) check_unet_plan(p);
+    p->unet = net;
+    p->unet_base = base_pc;
+    p->unet_tau = tau;
+  });
+}
+
+extern "C" aim_status aim_log_pairs(aim_plan p, const void* b, int32_t nrhs,
+                                    const int32_t* freq_idx_host, double rtol, int32_t restart,
+                                    int32_t max_iter, void* r_out, void* e_out,
+                                    int32_t* rhs_out_host, int32_t max_pairs, int32_t* npairs,
+                                    void* hip_stream) {
+  if (!p || !b || !r_out || !e_out || !npairs) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  aim_status result = AIM_OK;
+  const aim_status st = guarded([&] {
+    AIM_REQUIRE(rtol > 0.0 && std::isfinite(rtol), AIM_ERR_INVALID_ARG, "rtol must be positive");
+    AIM_REQUIRE(restart >= 1 && restart <= 200, AIM_ERR_INVALID_ARG, "restart must be in 1..200");
+    AIM_REQUIRE(max_iter >= 1, AIM_ERR_INVALID_ARG, "max_iter must be >= 1");
+    AIM_REQUIRE(max_pairs >= 0, AIM_ERR_INVALID_ARG, "max_pairs must be >= 0");
+    check_prec(p, AIM_C128);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    ensure_solver(p, nrhs, restart, s);
+    auto& w = p->sv;
+    const int64_t n = p->t.N;
+    const size_t vec = size_t(n) * 16;
+    std::vector<double> bn;
+    norms_host(p, b, nrhs, s, bn);
+    std::vector<double> scale(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      AIM_REQUIRE(std::isfinite(bn[r]), AIM_ERR_BREAKDOWN, "non-finite right-hand side");
+      scale[r] = bn[r] > 0.0 ? bn[r] : 1.0;
+    }
+    AIM_HIP(hipMemsetAsync(w.xp, 0, vec * nrhs, s));
+    int count = 0;
+    std::vector<int32_t> owner;
+    // at every restart, (r_t, x_t) of each unconverged system is stored
+    CycleHook hook = [&](const void* x, const void* rr, const std::vector<double>& rel) {
+      for (int r = 0; r < nrhs && count < max_pairs; ++r) {
+        if (!(rel[r] > rtol)) continue;
+        AIM_HIP(hipMemcpyAsync(static_cast<char*>(r_out) + size_t(count) * vec,
+                               static_cast<const char*>(rr) + size_t(r) * vec, vec,
+                               hipMemcpyDeviceToDevice, s));
+        AIM_HIP(hipMemcpyAsync(static_cast<char*>(e_out) + size_t(count) * vec,
+                               static_cast<const char*>(x) + size_t(r) * vec, vec,
+                               hipMemcpyDeviceToDevice, s));
+        owner.push_back(r);
+        ++count;
+      }
+    };
+    CycleStats cs;
+    std::vector<double> rel;
+    gmres_batch(p, AIM_C128, AIM_PC_NONE, b, w.xp, nrhs, df, scale, rtol, restart, max_iter, true,
+                s, cs, rel, &hook);
+    // e_t = x* - x_t against the converged solution
+    for (int k = 0; k < count; ++k)
+      aim::launch_pair_error(static_cast<const char*>(w.xp) + size_t(owner[k]) * vec,
+                             static_cast<char*>(e_out) + size_t(k) * vec, n, s);
+    AIM_HIP(hipStreamSynchronize(s));
+    *npairs = count;
+    if (rhs_out_host) std::copy(owner.begin(), owner.end(), rhs_out_host);
+    for (int r = 0; r < nrhs; ++r)
+      if (!(rel[r] <= rtol)) result = AIM_ERR_NOT_CONVERGED;
+  });
+  if (st != AIM_OK) return st;
+  if (result != AIM_OK) return fail(result, "a logging solve did not reach rtol");
+  return AIM_OK;
+}
+
+extern "C" aim_status aim_pc_targets(aim_plan p, aim_pc_kind base_pc, const void* r_pairs,
+                                     const void* e_pairs, int32_t npairs, void* grid_out,
+                                     void* target_out, double* sumsq_host, void* hip_stream) {
+  if (!p || (npairs > 0 && (!r_pairs || !e_pairs || !grid_out || !target_out)))
+    return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    AIM_REQUIRE(npairs >= 0, AIM_ERR_INVALID_ARG, "npairs must be >= 0");
+    AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK, AIM_ERR_INVALID_ARG,
+                "base preconditioner must be none, diag or nearblock");
+    check_unet_plan(p);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    ensure_solver(p, p->max_rhs, 1, s);  // norms of up to max_rhs targets at once
+    const int64_t n = p->t.N, Ng = p->g.Ng;
+    const size_t vec = size_t(n) * 16;
+    double total = 0.0;
+    std::vector<double> tn;
+    for (int k0 = 0; k0 < npairs; k0 += p->max_rhs) {
+      const int nb = std::min(p->max_rhs, npairs - k0);
+      const char* rr = static_cast<const char*>(r_pairs) + size_t(k0) * vec;
+      char* tg = static_cast<char*>(target_out) + size_t(k0) * vec;
+      unet_input(p, rr, nb, static_cast<char*>(grid_out) + size_t(k0) * Ng * 8, s);
+      apply_base(p, base_pc, rr, tg, nb, s);
+      aim::launch_unet_resid_target(static_cast<const char*>(e_pairs) + size_t(k0) * vec, p->u_s,
+                                    tg, n, nb, s);
+      norms_host(p, tg, nb, s, tn);
+      for (double v : tn) total += v * v;
+    }
+    AIM_HIP(hipStreamSynchronize(s));
+    AIM_REQUIRE(std::isfinite(total), AIM_ERR_BREAKDOWN, "non-finite training target");
+    if (sumsq_host) *sumsq_host = total;
+  });
+}
+
+extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, const void* grids,
+                                        const void* targets, int32_t npairs,
+                                        const int32_t* sample_idx_host, int32_t nsamples,
+                                        double tau, double lr, int32_t apply, double* loss_host,
+                                        void* hip_stream) {
+  if (!p || !net || !grids || !targets || !sample_idx_host)
+    return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    AIM_REQUIRE(nsamples >= 1, AIM_ERR_INVALID_ARG, "nsamples must be >= 1");
+    AIM_REQUIRE(std::isfinite(tau) && tau > 0.0, AIM_ERR_INVALID_ARG, "tau must be positive");
+    AIM_REQUIRE(std::isfinite(lr) && lr >= 0.0, AIM_ERR_INVALID_ARG, "lr must be >= 0");
+    for (int i = 0; i < nsamples; ++i)
+      AIM_REQUIRE(sample_idx_host[i] >= 0 && sample_idx_host[i] < npairs, AIM_ERR_INVALID_ARG,
+                  "sample index out of range");
+    check_unet_plan(p);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    ensure_unet_buffers(p, s);
+    const int64_t n = p->t.N, Ng = p->g.Ng;
+    constexpr int kParts = 64;
+    AIM_REQUIRE(int64_t(kParts) * nsamples * 8 <= int64_t(16) * 4096 +
+                    int64_t(16) * p->max_rhs * ((std::max(n, Ng) + 4095) / 4096),
+                AIM_ERR_INVALID_ARG, "too many samples in one step");
+    double* part = static_cast<double*>(p->upart);
+    aim::unet_zero_grad(net, s);
+    const double inv_cnt = 1.0 / (double(n) * nsamples);
+    for (int i = 0; i < nsamples; ++i) {
+      const int64_t k = sample_idx_host[i];
+      const char* g = static_cast<const char*>(grids) + size_t(k) * Ng * 8;
+      aim::unet_forward(net, g, p->g.N[2], p->g.N[1], p->g.N[0], p->ug_out, s);
+      aim::launch_interp_near<float>(p->g, pt_dev(p, AIM_C64), csr_dev(p, AIM_C64), p->ug_out,
+                                     nullptr, p->um2, 1, true, false, s);
+      aim::launch_mesh_mse(p->um2, static_cast<const char*>(targets) + size_t(k) * n * 16,
+                           p->d_area, 1.0 / tau, n, inv_cnt, p->um1, part + size_t(i) * kParts,
+                           kParts, s);
+      // d loss / d grid output = P (d loss / d mesh output), as the mesh
+      // output is P^T of the grid output
+      aim::launch_project<float>(p->g, p_dev(p, AIM_C64), p->d_pblk, p->nblk, p->um1, n,
+                                 p->ug_in, 1, s);
+      aim::unet_backward(net, g, p->ug_in, s);
+    }
+    if (apply) aim::unet_adam(net, lr, s);
+    std::vector<double> hp(size_t(kParts) * nsamples);
+    AIM_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, s));
+    AIM_HIP(hipStreamSynchronize(s));
+    double loss = 0.0;
+    for (double v : hp) loss += v;
+    if (loss_host) *loss_host = loss;
+  });
 }

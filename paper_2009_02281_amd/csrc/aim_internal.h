@@ -162,6 +162,29 @@ void launch_block_pc(const void* v, void* z, const int32_t* cl_ptr, const int32_
 void launch_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t n, int nrhs,
                         bool scatter, hipStream_t s);
 
+// learned-preconditioner glue
+void launch_inv_norms_c64(const void* x, int64_t n, int nrhs, double mul, void* partial, double* s,
+                          hipStream_t st);
+void launch_inv_norms_c128(const void* v, int64_t n, int nrhs, double mul, void* partial,
+                           double* s, hipStream_t st);
+void launch_scale_cast_c64(const void* v, const double* s, void* out, int64_t n, int nrhs,
+                           hipStream_t st);
+void launch_scale_c64(void* x, const double* s, int64_t n, int nrhs, hipStream_t st);
+// z += tau c / (area sv)   (z = base preconditioner applied to v on entry)
+void launch_unet_combine(const void* c, const double* area, double tau, const double* sv, void* z,
+                         int64_t n, int nrhs, hipStream_t st);
+// w = (e - w) ir           (w = base preconditioner applied to r on entry)
+void launch_unet_resid_target(const void* e, const double* ir, void* w, int64_t n, int nrhs,
+                              hipStream_t st);
+void launch_mesh_mse(const void* c, const void* w, const double* area, double inv_tau, int64_t n,
+                     double inv_cnt, void* d, double* part, int nparts, hipStream_t st);
+// e = xs - e (one vector)
+void launch_pair_error(const void* xs, void* e, int64_t n, hipStream_t st);
+void unet_forward(aim_unet u, const void* in, int D, int H, int W, void* out, hipStream_t s);
+void unet_backward(aim_unet u, const void* in, const void* dout, hipStream_t s);
+void unet_zero_grad(aim_unet u, hipStream_t s);
+void unet_adam(aim_unet u, double lr, hipStream_t s);
+
 // Twiddle table exp(-2 pi i m / L), m < L, in complex128 (and complex64).
 std::vector<double> twiddles64(int L);
 

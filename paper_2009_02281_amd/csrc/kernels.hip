@@ -1161,3 +1161,218 @@ void launch_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t 
 }
 
 }  // namespace aim
+
+// ===========================================================================
+// learned-preconditioner glue (complex64 grids and meshes)
+// ===========================================================================
+namespace aim {
+
+__global__ void scale_cast_c64_kernel(const double2* v, const double* s, float2* out, int64_t n) {
+  const int r = blockIdx.y;
+  const double sc = s ? s[r] : 1.0;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const double2 a = v[int64_t(r) * n + k];
+    float2 o;
+    o.x = float(a.x * sc);
+    o.y = float(a.y * sc);
+    out[int64_t(r) * n + k] = o;
+  }
+}
+
+// out[r] = 1 / ||v[r]|| (0 if the norm is 0), from partial sums of squares
+__global__ void inv_norm_finish_kernel(const double2* partial, int nchunk, int nrhs, double mul,
+                                       double* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partial[int64_t(r) * nchunk + c].x;
+  out[r] = s > 0.0 ? mul / sqrt(s) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void sumsq_c64_kernel(const float2* __restrict__ w, int64_t n,
+                                                        int nchunk, double2* partial) {
+  __shared__ double2 sh[256];
+  const int c = blockIdx.x, r = blockIdx.y;
+  const float2* wr = w + int64_t(r) * n;
+  double acc = 0.0;
+  const int64_t b = int64_t(c) * 4096, e = min(n, b + 4096);
+  for (int64_t k = b + threadIdx.x; k < e; k += 256)
+    acc += double(wr[k].x) * wr[k].x + double(wr[k].y) * wr[k].y;
+  sh[threadIdx.x].x = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x].x += sh[threadIdx.x + o].x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[int64_t(r) * nchunk + c] = make_double2(sh[0].x, 0.0);
+}
+
+// s[r] = mul / ||x[r]|| for complex64 vectors
+void launch_inv_norms_c64(const void* x, int64_t n, int nrhs, double mul, void* partial, double* s,
+                          hipStream_t st) {
+  const int nchunk = int((n + 4095) / 4096);
+  hipLaunchKernelGGL(sumsq_c64_kernel, dim3(nchunk, nrhs), dim3(256), 0, st,
+                     static_cast<const float2*>(x), n, nchunk, static_cast<double2*>(partial));
+  AIM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(inv_norm_finish_kernel, dim3((nrhs + 127) / 128), dim3(128), 0, st,
+                     static_cast<const double2*>(partial), nchunk, nrhs, mul, s);
+  AIM_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void sumsq_c128_kernel(const double2* __restrict__ w, int64_t n,
+                                                         int nchunk, double2* partial) {
+  __shared__ double sh[256];
+  const int c = blockIdx.x, r = blockIdx.y;
+  const double2* wr = w + int64_t(r) * n;
+  double acc = 0.0;
+  const int64_t b = int64_t(c) * 4096, e = min(n, b + 4096);
+  for (int64_t k = b + threadIdx.x; k < e; k += 256) acc += wr[k].x * wr[k].x + wr[k].y * wr[k].y;
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[int64_t(r) * nchunk + c] = make_double2(sh[0], 0.0);
+}
+
+// s[r] = mul / ||v[r]|| for complex128 vectors
+void launch_inv_norms_c128(const void* v, int64_t n, int nrhs, double mul, void* partial,
+                           double* s, hipStream_t st) {
+  const int nchunk = int((n + 4095) / 4096);
+  hipLaunchKernelGGL(sumsq_c128_kernel, dim3(nchunk, nrhs), dim3(256), 0, st,
+                     static_cast<const double2*>(v), n, nchunk, static_cast<double2*>(partial));
+  AIM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(inv_norm_finish_kernel, dim3((nrhs + 127) / 128), dim3(128), 0, st,
+                     static_cast<const double2*>(partial), nchunk, nrhs, mul, s);
+  AIM_HIP(hipGetLastError());
+}
+
+void launch_scale_cast_c64(const void* v, const double* s, void* out, int64_t n, int nrhs,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(scale_cast_c64_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, st,
+                     static_cast<const double2*>(v), s, static_cast<float2*>(out), n);
+  AIM_HIP(hipGetLastError());
+}
+
+__global__ void scale_c64_kernel(float2* x, const double* s, int64_t n) {
+  const int r = blockIdx.y;
+  const float sc = float(s[r]);
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    float2 a = x[int64_t(r) * n + k];
+    a.x *= sc;
+    a.y *= sc;
+    x[int64_t(r) * n + k] = a;
+  }
+}
+
+void launch_scale_c64(void* x, const double* s, int64_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(scale_c64_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, st,
+                     static_cast<float2*>(x), s, n);
+  AIM_HIP(hipGetLastError());
+}
+
+// z[r][i] += tau * c[r][i] / (area[i] * sv[r]) with sv = 1/||v||; z holds the
+// base preconditioner applied to v on entry
+__global__ void unet_combine_kernel(const float2* c, const double* area, double tau,
+                                    const double* sv, double2* z, int64_t n) {
+  const int r = blockIdx.y;
+  const double sc = sv[r] > 0.0 ? tau / sv[r] : 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const float2 b = c[int64_t(r) * n + k];
+    const double f = sc / area[k];
+    double2 o = z[int64_t(r) * n + k];
+    o.x += f * b.x;
+    o.y += f * b.y;
+    z[int64_t(r) * n + k] = o;
+  }
+}
+
+void launch_unet_combine(const void* c, const double* area, double tau, const double* sv, void* z,
+                         int64_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(unet_combine_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, st,
+                     static_cast<const float2*>(c), area, tau, sv, static_cast<double2*>(z), n);
+  AIM_HIP(hipGetLastError());
+}
+
+// w[r][i] = (e[r][i] - w[r][i]) * ir[r]: on entry w holds the base
+// preconditioner applied to the residual, so the result is the part of the
+// normalised error the base preconditioner misses (complex128)
+__global__ void unet_resid_target_kernel(const double2* e, const double* ir, double2* w,
+                                         int64_t n) {
+  const int r = blockIdx.y;
+  const double s = ir[r];
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const double2 b = e[int64_t(r) * n + k];
+    double2 o = w[int64_t(r) * n + k];
+    o.x = (b.x - o.x) * s;
+    o.y = (b.y - o.y) * s;
+    w[int64_t(r) * n + k] = o;
+  }
+}
+
+void launch_unet_resid_target(const void* e, const double* ir, void* w, int64_t n, int nrhs,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(unet_resid_target_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, st,
+                     static_cast<const double2*>(e), ir, static_cast<double2*>(w), n);
+  AIM_HIP(hipGetLastError());
+}
+
+// mesh loss: mean over n (x nb) of |c/area - t|^2 with t = w / tau; gradient
+// d = 2 (c/area - t) / (area cnt) in complex64; per-block partial losses
+__global__ __launch_bounds__(256) void mesh_mse_kernel(const float2* c, const double2* w,
+                                                       const double* area, double inv_tau,
+                                                       int64_t n, double inv_cnt, float2* d,
+                                                       double* part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const double ia = 1.0 / area[k];
+    const double dx = c[k].x * ia - w[k].x * inv_tau, dy = c[k].y * ia - w[k].y * inv_tau;
+    acc += (dx * dx + dy * dy) * inv_cnt;
+    float2 o;
+    o.x = float(2.0 * dx * ia * inv_cnt);
+    o.y = float(2.0 * dy * ia * inv_cnt);
+    d[k] = o;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+void launch_mesh_mse(const void* c, const void* w, const double* area, double inv_tau, int64_t n,
+                     double inv_cnt, void* d, double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(mesh_mse_kernel, dim3(nparts), dim3(256), 0, st,
+                     static_cast<const float2*>(c), static_cast<const double2*>(w), area, inv_tau,
+                     n, inv_cnt, static_cast<float2*>(d), part);
+  AIM_HIP(hipGetLastError());
+}
+
+// e = xs - e for a logged iterate (in place): the error of the iterate
+// against the converged solution
+__global__ void pair_error_kernel(const double2* xs, double2* e, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    double2 a = e[i];
+    a.x = xs[i].x - a.x;
+    a.y = xs[i].y - a.y;
+    e[i] = a;
+  }
+}
+
+void launch_pair_error(const void* xs, void* e, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(pair_error_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, st,
+                     static_cast<const double2*>(xs), static_cast<double2*>(e), n);
+  AIM_HIP(hipGetLastError());
+}
+
+}  // namespace aim

@@ -270,3 +270,25 @@ def small_box_array(seed: int = 7000) -> Workload:
     h = derived_spacing(V, dims)
     return Workload("boxarray-small", V, T, 3, dims, h, 3.0,
                     np.array([2 * math.pi]), seed)
+
+
+def ellipsoid(level: int, radii, center=(0.0, 0.0, 0.0)):
+    """Icosphere of the given level stretched to semi-axes ``radii``."""
+    V, T = icosphere(level, 1.0)
+    return V * np.asarray(radii, dtype=np.float64) + np.asarray(center, dtype=np.float64), T
+
+
+def learned_pc_geometries(count: int, seed: int = 5004, level: int = 3,
+                          k: float = 5.0) -> list:
+    """Ellipsoids for the learned preconditioner: semi-axes drawn uniformly in
+    [0.35, 0.6] with ``seed`` (training sets and held-out sets use different
+    seeds), all on a 16^3 grid at h = 0.1 with 2nd-order stencils and a 2h
+    near threshold, at wavenumber k."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        radii = rng.uniform(0.35, 0.6, size=3)
+        V, T = ellipsoid(level, radii)
+        out.append(Workload(f"ellipsoid-{seed}-{i}", V, T, 2, (16, 16, 16), 0.1, 2.0,
+                            np.array([k]), seed, extra={"radii": radii}))
+    return out

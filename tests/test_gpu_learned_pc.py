@@ -1,0 +1,242 @@
+"""GPU tests of the learned grid preconditioner through the C ABI: logged
+training pairs, network inputs and targets, the preconditioner application
+and one training step against the oracle (oracle/learned_pc.py with the
+bfloat16 U-Net reference), and the solve with its gate and fallback.
+
+Tolerances: inputs and targets are complex64 / complex128 plain arithmetic
+(1e-5 / 1e-12 relative); anything through the network carries bfloat16
+weights and activations (2e-2 relative for outputs, 3e-2 for gradients, as
+for the network alone).  The iteration count the trained network saves on a
+held-out geometry is reported, not asserted: it is an empirical property of
+training, with no closed form to pin it to."""
+import numpy as np
+import pytest
+
+from paper_2009_02281_amd import inputs as I
+from oracle import aimx, learned_pc, unet as ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2009_02281_amd import binding  # noqa: E402
+
+_C = {}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def setup(w, key):
+    if key not in _C:
+        o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+        p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                         max_rhs=8)
+        _C[key] = (w, o, p)
+    return _C[key]
+
+
+def held_out():
+    return setup(I.learned_pc_geometries(1, seed=5005)[0], "held")
+
+
+def diag_base(o):
+    d = o.static_near_matrix().diagonal()
+    return lambda v: v / d
+
+
+def directions(n):
+    rng = np.random.default_rng(5006)
+    d = rng.standard_normal((n, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def logged(key="held"):
+    """Pairs from plain GMRES on the held-out geometry (two plane waves)."""
+    ck = ("pairs", key)
+    if ck not in _C:
+        w, o, p = held_out()
+        b = p.excitation("plane_wave", directions(2))
+        r, e, owner = p.log_pairs(b, rtol=1e-10, restart=8, max_pairs=64)
+        _C[ck] = (b, r, e, owner)
+    return _C[ck]
+
+
+def random_net(seed):
+    net = binding.UNet(seed=seed)
+    flat = net.params()
+    rng = np.random.default_rng(seed + 1)
+    off = 0
+    for W, b in binding.unet_params_to_layers(flat):
+        off += W.size
+        flat[off:off + b.size] = 0.05 * rng.standard_normal(b.size)
+        off += b.size
+    net.set_params(flat)
+    return net, binding.unet_params_to_layers(flat)
+
+
+def test_logged_pairs_are_consistent():
+    """r_t and e_t = x* - x_t satisfy A e_t = r_t - r*, with ||r*|| <= rtol
+    ||b||, and the first pair of each system is (b, x*)."""
+    w, o, p = held_out()
+    b, r, e, owner = logged()
+    print(f"[gpu] logged {r.shape[0]} pairs from {b.shape[0]} systems", flush=True)
+    assert r.shape[0] >= 4 and set(owner.tolist()) == {0, 1}
+    bh, rh, eh = host(b), host(r), host(e)
+    k = float(w.k[0])
+    firsts = [int(np.flatnonzero(owner == s)[0]) for s in (0, 1)]
+    for s, f in zip((0, 1), firsts):
+        assert np.array_equal(rh[f], bh[s])
+    for i in range(rh.shape[0]):
+        Ae = o.matvec(eh[i], k)
+        bound = 1.5e-10 * np.linalg.norm(bh[owner[i]]) + 1e-10 * np.linalg.norm(Ae)
+        assert np.linalg.norm(Ae - rh[i]) <= bound, i
+
+
+@pytest.mark.parametrize("base", ["none", "diag"])
+def test_inputs_and_targets_match_oracle(base):
+    w, o, p = held_out()
+    b, r, e, owner = logged()
+    grids, tg, sumsq = p.pc_targets(r, e, base_pc=base)
+    B = (lambda v: v) if base == "none" else diag_base(o)
+    rh, eh, gh, th = host(r), host(e), host(grids), host(tg)
+    for i in range(rh.shape[0]):
+        assert rel(gh[i], learned_pc.network_input(o, rh[i])) <= 1e-5, i
+        assert rel(th[i], learned_pc.target(B, rh[i], eh[i])) <= 1e-12, i
+    assert sumsq == pytest.approx(float(np.sum(np.abs(th) ** 2)), rel=1e-10)
+
+
+@pytest.mark.parametrize("base", ["none", "diag"])
+def test_preconditioner_application_matches_oracle(base):
+    w, o, p = held_out()
+    net, layers = random_net(31)
+    tau = 0.3
+    p.set_unet(net, base_pc=base, tau=tau)
+    v = I.complex_gaussian(o.N, 32, nrhs=3)
+    z = host(p.apply_stage("learned_pc", torch.from_numpy(v).cuda()))
+    B = (lambda x: x) if base == "none" else diag_base(o)
+    rn = ref.UNet(layers, bf16=True)
+    for i in range(3):
+        want = learned_pc.apply(o, rn, B, tau, v[i])
+        corr_err = rel(z[i] - B(v[i]), want - B(v[i]))
+        print(f"    base={base} rhs {i}: correction rel err {corr_err:.2e}", flush=True)
+        assert corr_err <= 2e-2
+        assert rel(z[i], want) <= 2e-2
+    p.set_unet(None)
+    net.close()
+
+
+def test_training_step_matches_oracle():
+    w, o, p = held_out()
+    b, r, e, owner = logged()
+    grids, tg, sumsq = p.pc_targets(r, e, base_pc="diag")
+    tau = float(np.sqrt(sumsq / (r.shape[0] * o.N)))
+    net, layers = random_net(41)
+    idx = [0, 2]
+    loss = p.pc_train_step(net, grids, tg, idx, tau=tau, apply=False)
+    g = binding.unet_params_to_layers(net.grads())
+    rn = ref.UNet(layers, bf16=True)
+    gh, th = host(grids).astype(np.complex128), host(tg)
+    want_loss, want = 0.0, None
+    for i in idx:
+        l, gi = learned_pc.mesh_loss(o, rn, gh[i], th[i], tau)
+        want_loss += l / len(idx)
+        gi = [(W / len(idx), bb / len(idx)) for W, bb in gi]
+        want = gi if want is None else [(a + c, bb + d) for (a, bb), (c, d) in zip(want, gi)]
+    print(f"[gpu] train step loss {loss:.6f} (oracle {want_loss:.6f})", flush=True)
+    assert loss == pytest.approx(want_loss, rel=1e-2)
+    for li, ((dW, db), (rW, rb)) in enumerate(zip(g, want)):
+        e_w, e_b = rel(dW, rW), rel(db, rb)
+        print(f"    layer {li}: dW {e_w:.2e} db {e_b:.2e}", flush=True)
+        assert e_w <= 3e-2 and e_b <= 3e-2, li
+    net.close()
+
+
+def test_poisoned_network_falls_back():
+    """A network that returns non-finite values is switched off and the solve
+    finishes with the fallback preconditioner."""
+    w, o, p = held_out()
+    net = binding.UNet(seed=3)
+    flat = net.params()
+    flat[-2:] = np.nan              # output bias
+    net.set_params(flat)
+    p.set_unet(net, base_pc="diag", tau=1.0)
+    b = p.excitation("plane_wave", [0, 0, 1])
+    for inner in ("c128", "c64"):
+        x, res = p.solve(b, rtol=1e-6, restart=20, pc="unet", fallback_pc="diag", inner=inner)
+        xh = host(x)[0]
+        tr = np.linalg.norm(host(b)[0] - o.matvec(xh, float(w.k[0]))) / np.linalg.norm(host(b)[0])
+        print(f"[gpu] poisoned ({inner}): iters {res.iters[0]} fallback {res.fallback_used[0]} "
+              f"true resid {tr:.2e}", flush=True)
+        assert res.converged[0] and res.fallback_used[0]
+        assert tr <= 1.5e-6
+    p.set_unet(None)
+    net.close()
+
+
+def test_gate_switches_to_fallback():
+    """A gate no restart cycle can pass (a 1e12-fold cut per cycle) hands the
+    solve to the fallback preconditioner from the current iterate."""
+    w, o, p = held_out()
+    net, _ = random_net(51)
+    p.set_unet(net, base_pc="diag", tau=0.1)
+    b = p.excitation("plane_wave", [1, 0, 0])
+    x, res = p.solve(b, rtol=1e-6, restart=3, pc="unet", fallback_pc="nearblock", gate=1e-12)
+    assert res.converged[0] and res.fallback_used[0]
+    xh = host(x)[0]
+    tr = np.linalg.norm(host(b)[0] - o.matvec(xh, float(w.k[0]))) / np.linalg.norm(host(b)[0])
+    assert tr <= 1.5e-6
+    p.set_unet(None)
+    net.close()
+
+
+def test_train_on_other_geometries_then_solve_held_out():
+    """Pairs from plain GMRES on three training ellipsoids (seed 5004) train
+    the network; the held-out ellipsoid (seed 5005) is then solved with it.
+    Asserted: the loss falls and the learned solve converges (with or without
+    fallback); reported: iterations against the classical preconditioners."""
+    train = [setup(wk, f"train{i}") for i, wk in enumerate(I.learned_pc_geometries(3))]
+    data = []
+    sumsq, count = 0.0, 0
+    for w, o, p in train:
+        b = p.excitation("plane_wave", directions(6))
+        r, e, _ = p.log_pairs(b, rtol=1e-9, restart=6, max_pairs=96)
+        grids, tg, ss = p.pc_targets(r, e, base_pc="diag")
+        data.append((p, grids, tg))
+        sumsq += ss
+        count += r.shape[0] * o.N
+    tau = float(np.sqrt(sumsq / count))
+    net = binding.UNet(seed=61)
+    rng = np.random.default_rng(62)
+    hist = []
+    for epoch in range(6):
+        tot, nb = 0.0, 0
+        for gi in rng.permutation(len(data)):
+            p, grids, tg = data[gi]
+            order = rng.permutation(grids.shape[0])
+            for s in range(0, len(order), 4):
+                tot += p.pc_train_step(net, grids, tg, order[s:s + 4], tau=tau, lr=1e-3)
+                nb += 1
+        hist.append(tot / nb)
+    print(f"[gpu] learned-pc training: tau {tau:.3e} loss by epoch "
+          + " ".join(f"{v:.4f}" for v in hist), flush=True)
+    assert hist[-1] < 0.9 * hist[0]
+    w, o, p = held_out()
+    p.set_unet(net, base_pc="diag", tau=tau)
+    b = p.excitation("plane_wave", [0, 0, 1])
+    its = {}
+    for pc in ("none", "diag", "unet"):
+        x, res = p.solve(b, rtol=1e-6, restart=30, pc=pc, fallback_pc="diag")
+        its[pc] = (int(res.iters[0]), bool(res.fallback_used[0]), res.seconds)
+        assert res.converged[0], pc
+    print("[gpu] held-out iterations: " + ", ".join(
+        f"{k}={v[0]}{' (fallback)' if v[1] else ''} {v[2] * 1e3:.1f} ms" for k, v in its.items()),
+        flush=True)
+    p.set_unet(None)
+    net.close()
