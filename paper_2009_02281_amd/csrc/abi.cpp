@@ -905,6 +905,7 @@ void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hi
 // complex64 each).  Leaves 1/||v|| in p->u_s.
 void unet_input(aim_plan p, const void* v, int nrhs, void* grid, hipStream_t s) {
   ensure_unet_buffers(p, s);
+  AIM_REQUIRE(grid != nullptr, AIM_ERR_STATE, "network input buffer missing");
   const int64_t n = p->t.N, Ng = p->g.Ng;
   aim::launch_inv_norms_c128(v, n, nrhs, 1.0, p->upart, p->u_s, s);
   aim::launch_scale_cast_c64(v, p->u_s, p->um1, n, nrhs, s);
@@ -926,6 +927,7 @@ void check_unet_plan(aim_plan p) {
 // B the base preconditioner, U the network; the grid work is complex64.
 void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s) {
   AIM_REQUIRE(p->unet != nullptr, AIM_ERR_STATE, "no learned preconditioner attached");
+  ensure_unet_buffers(p, s);  // before any of the buffers is read below
   const int64_t n = p->t.N, Ng = p->g.Ng;
   unet_input(p, v, nrhs, p->ug_in, s);
   for (int r = 0; r < nrhs; ++r)

@@ -112,6 +112,24 @@ def test_inputs_and_targets_match_oracle(base):
     assert sumsq == pytest.approx(float(np.sum(np.abs(th) ** 2)), rel=1e-10)
 
 
+def test_application_as_first_learned_call_on_a_plan():
+    """Regression: applying the preconditioner on a plan whose learned-PC
+    buffers have not been created yet (no pairs, targets or solve before)."""
+    w = I.learned_pc_geometries(2, seed=5005)[1]
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     max_rhs=2)
+    net, layers = random_net(33)
+    p.set_unet(net, base_pc="none", tau=0.5)
+    v = I.complex_gaussian(o.N, 34)
+    z = host(p.apply_stage("learned_pc", torch.from_numpy(v[None]).cuda()))[0]
+    want = learned_pc.apply(o, ref.UNet(layers, bf16=True), lambda x: x, 0.5, v)
+    assert rel(z - v, want - v) <= 2e-2
+    p.set_unet(None)
+    net.close()
+    p.close()
+
+
 @pytest.mark.parametrize("base", ["none", "diag"])
 def test_preconditioner_application_matches_oracle(base):
     w, o, p = held_out()
@@ -160,14 +178,20 @@ def test_training_step_matches_oracle():
 
 def test_poisoned_network_falls_back():
     """A network that returns non-finite values is switched off and the solve
-    finishes with the fallback preconditioner."""
+    finishes with the fallback preconditioner.  Non-finite parameters are
+    refused outright, so the poison is finite weights scaled by 1e15 per
+    layer: the activations overflow float32 range within a few layers."""
     w, o, p = held_out()
     net = binding.UNet(seed=3)
     flat = net.params()
-    flat[-2:] = np.nan              # output bias
-    net.set_params(flat)
+    bad = flat.copy()
+    bad[0] = np.nan
+    with pytest.raises(binding.AimError):
+        net.set_params(bad)
+    net.set_params(flat * np.float32(1e15))
     p.set_unet(net, base_pc="diag", tau=1.0)
     b = p.excitation("plane_wave", [0, 0, 1])
+    assert not torch.isfinite(p.apply_stage("learned_pc", b)).all()
     for inner in ("c128", "c64"):
         x, res = p.solve(b, rtol=1e-6, restart=20, pc="unet", fallback_pc="diag", inner=inner)
         xh = host(x)[0]
