@@ -323,9 +323,15 @@ aim_status aim_unet_load(const char* path, aim_unet* out);
  * complex64 tables (precisions bit 1).  The network must have base width 16.
  *
  * Training data are pairs (r_t, e_t = x* - x_t) logged from plain GMRES on
- * training geometries; the network is trained so that
- *   (P^T U(g(r_t))) / area  ~  (e_t - B r_t) / (tau ||r_t||)
- * in the mean square over triangles (aim_pc_targets, aim_pc_train_step). */
+ * training geometries.  Two losses (aim_pc_targets, aim_pc_train_step), with
+ * r^ = r_t/||r_t||, c = P^T U(g(r_t)) and means over triangles:
+ *   AIM_LOSS_ERROR:    mean |c/area - t/tau|^2,  t = (e_t - B r_t)/||r_t||,
+ *                      the error itself;
+ *   AIM_LOSS_RESIDUAL: weight mean |s - A (tau c/area)|^2,
+ *                      s = r^ - A B r^, the same error measured through A
+ *                      (A e_t = r_t up to the logging tolerance), which
+ *                      weights the smooth components a grid can represent. */
+typedef enum { AIM_LOSS_ERROR = 0, AIM_LOSS_RESIDUAL = 1 } aim_pc_loss;
 
 /* Attach (net != NULL) or detach (net == NULL) a network.  base_pc is B
  * (AIM_PC_NONE, AIM_PC_DIAG or AIM_PC_NEARBLOCK) and tau > 0 the target scale
@@ -347,26 +353,32 @@ aim_status aim_log_pairs(aim_plan plan, const void* b_dev, int32_t nrhs,
                          void* hip_stream);
 
 /* Network inputs and targets of npairs logged pairs:
- *   grid_out[k]   = g(r_k)                      [npairs][Ng] complex64
- *   target_out[k] = (e_k - B r_k) / ||r_k||     [npairs][N]  complex128
- * (device buffers, caller-owned).  *sumsq_host = sum of |target|^2 over all
- * entries (tau^2 = sumsq / (pairs * N) over the whole training set gives a
- * unit-scale target).  Blocking. */
-aim_status aim_pc_targets(aim_plan plan, aim_pc_kind base_pc, const void* r_pairs_dev,
-                          const void* e_pairs_dev, int32_t npairs, void* grid_out_dev,
-                          void* target_out_dev, double* sumsq_host, void* hip_stream);
+ *   grid_out[k]   = g(r_k)                           [npairs][Ng] complex64
+ *   target_out[k] = (e_k - B r_k)/||r_k||   (ERROR)  [npairs][N]  complex128
+ *                 = (r_k - A B r_k)/||r_k|| (RESIDUAL, frequency index 0)
+ * (device buffers, caller-owned).  sums_host[0] = sum over all entries of
+ * |(e_k - B r_k)/||r_k|| |^2 and sums_host[1] = the same of the RESIDUAL
+ * target (0 for ERROR); over the whole training set, tau^2 = sums[0] /
+ * (pairs N) makes the ERROR target unit-scale and weight = pairs N / sums[1]
+ * the RESIDUAL loss.  Blocking. */
+aim_status aim_pc_targets(aim_plan plan, aim_pc_kind base_pc, aim_pc_loss kind,
+                          const void* r_pairs_dev, const void* e_pairs_dev, int32_t npairs,
+                          void* grid_out_dev, void* target_out_dev, double* sums_host,
+                          void* hip_stream);
 
 /* One optimiser step over the samples sample_idx_host[0..nsamples) (indices
- * into grids/targets as written by aim_pc_targets on this plan, each in
- * [0, npairs)): loss = mean over samples and triangles of
- * |(P^T U(grid))/area - target/tau|^2, gradients through P^T, the network's
- * backward pass, then Adam with learning rate lr if apply != 0.  *loss_host
- * receives the loss before the step.  nsamples is limited by the plan's
- * scratch (at least 128).  Blocking. */
-aim_status aim_pc_train_step(aim_plan plan, aim_unet net, const void* grids_dev,
-                             const void* targets_dev, int32_t npairs,
+ * into grids/targets as written by aim_pc_targets on this plan with the same
+ * kind, each in [0, npairs)): the loss of the given kind (ERROR: weight
+ * times the ERROR loss) averaged over the samples, gradients through P^T
+ * (and, for RESIDUAL, through A and its adjoint, complex64 products at
+ * frequency index 0), the network's backward pass, then Adam with learning
+ * rate lr if apply != 0.  *loss_host receives the loss before the step.
+ * nsamples is limited by the plan's scratch (at least 128).  Blocking. */
+aim_status aim_pc_train_step(aim_plan plan, aim_unet net, aim_pc_loss kind,
+                             const void* grids_dev, const void* targets_dev, int32_t npairs,
                              const int32_t* sample_idx_host, int32_t nsamples, double tau,
-                             double lr, int32_t apply, double* loss_host, void* hip_stream);
+                             double weight, double lr, int32_t apply, double* loss_host,
+                             void* hip_stream);
 
 /* Host copies of setup tables, for validation against an independent
  * implementation.  Any pointer may be NULL to skip that table.

@@ -15,7 +15,11 @@ with it:
   preconditioner (identity or the diagonal of A_s,NR of Sec. III-A) and
   tau a fixed scale;
 * training pair (r, e) logged from plain GMRES: target t = (e - B r)/||r||,
-  loss = mean over triangles of |(W U(g(r)))/area - t/tau|^2.
+  loss = mean over triangles of |(W U(g(r)))/area - t/tau|^2 ("error"
+  loss); or the same error seen through the operator ("residual" loss):
+  with r^ = r/||r|| and s = r^ - A B r^,
+  loss = weight * mean |s - A (tau (W U(g(r)))/area)|^2,
+  since A e = r when e is the exact error of the iterate.
 
 Because M is nonlinear the Krylov solve must be flexible GMRES
 (``oracle.solver.fgmres`` keeps Z).
@@ -74,3 +78,29 @@ def mesh_loss(o, net: UNet, grid, t, tau: float):
     dphi = o.project(dc)
     dout = np.stack([dphi.real, dphi.imag], axis=-1)
     return loss, net.backward_from(dout)
+
+
+def residual_target(A, base, r):
+    """s = r^ - A B r^ with r^ = r/||r|| (A a callable on complex128)."""
+    r = np.asarray(r, dtype=np.complex128)
+    rh = r / np.linalg.norm(r)
+    return rh - A(base(rh))
+
+
+def residual_loss(o, net: UNet, A, grid, s, tau: float, weight: float):
+    """Residual loss of one sample and its parameter gradients.  The
+    gradient with respect to the mesh output c (as Re + i Im) is
+    -2 weight tau A^H rho / (area N) with rho = s - A z, z = tau c/area; A^H is
+    applied as a dense adjoint of the callable (built column by column), so
+    no symmetry of A is assumed."""
+    area = _mesh.areas(o.V, o.T)
+    out = net.forward(as_channels(grid))
+    c = o.interpolate(out[..., 0] + 1j * out[..., 1])
+    rho = np.asarray(s) - A(tau * c / area)
+    N = rho.size
+    loss = float(weight * np.mean(np.abs(rho) ** 2))
+    eye = np.eye(N, dtype=np.complex128)
+    Ad = np.stack([A(eye[j]) for j in range(N)], axis=1)
+    dc = -2.0 * weight * tau * (Ad.conj().T @ rho) / (area * N)
+    dphi = o.project(dc)
+    return loss, net.backward_from(np.stack([dphi.real, dphi.imag], axis=-1))

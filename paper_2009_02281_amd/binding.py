@@ -21,6 +21,7 @@ STATUS = {0: "AIM_OK", 1: "AIM_ERR_INVALID_ARG", 2: "AIM_ERR_GEOMETRY", 3: "AIM_
           7: "AIM_ERR_BREAKDOWN", 8: "AIM_ERR_STATE"}
 PREC = {"c128": 0, "c64": 1}
 PC = {"none": 0, "diag": 1, "nearblock": 2, "unet": 3}
+LOSS = {"error": 0, "residual": 1}
 STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc": 4}
 RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
@@ -132,9 +133,9 @@ def load_library(path: str = LIB_PATH):
     lib.aim_plan_set_unet.argtypes = [vp, vp, i32, C.c_double]
     lib.aim_log_pairs.argtypes = [vp, vp, i32, ip32, C.c_double, i32, i32, vp, vp, ip32, i32,
                                   ip32, vp]
-    lib.aim_pc_targets.argtypes = [vp, i32, vp, vp, i32, vp, vp, dp, vp]
-    lib.aim_pc_train_step.argtypes = [vp, vp, vp, vp, i32, ip32, i32, C.c_double, C.c_double,
-                                      i32, dp, vp]
+    lib.aim_pc_targets.argtypes = [vp, i32, i32, vp, vp, i32, vp, vp, dp, vp]
+    lib.aim_pc_train_step.argtypes = [vp, vp, i32, vp, vp, i32, ip32, i32, C.c_double,
+                                      C.c_double, C.c_double, i32, dp, vp]
     lib.aim_last_error.restype = C.c_char_p
     lib.aim_version.restype = C.c_char_p
     for name in EXPORTED:
@@ -554,9 +555,10 @@ class Plan:
         k = cnt.value
         return r[:k], e[:k], owner[:k].copy()
 
-    def pc_targets(self, r, e, base_pc: str = "diag", stream=None):
-        """Network inputs [npairs, Nz, Ny, Nx] complex64 and targets [npairs, N]
-        complex128 of logged pairs, and the sum of |target|^2."""
+    def pc_targets(self, r, e, base_pc: str = "diag", loss: str = "error", stream=None):
+        """Network inputs [npairs, Nz, Ny, Nx] complex64, targets [npairs, N]
+        complex128 of logged pairs for the given loss kind, and the sums
+        (sum |error target|^2, sum |residual target|^2)."""
         import torch
         self._check_vec(r, "c128", self.n, "r")
         self._check_vec(e, "c128", self.n, "e")
@@ -566,15 +568,16 @@ class Plan:
         Nx, Ny, Nz = self.dims
         grids = torch.empty((npairs, Nz, Ny, Nx), dtype=torch.complex64, device=r.device)
         tg = torch.empty_like(r)
-        ss = C.c_double(0.0)
-        _check(self._lib.aim_pc_targets(self._plan, PC[base_pc], C.c_void_p(r.data_ptr()),
-                                        C.c_void_p(e.data_ptr()), npairs,
-                                        C.c_void_p(grids.data_ptr()), C.c_void_p(tg.data_ptr()),
-                                        C.byref(ss), _stream_ptr(stream)))
-        return grids, tg, ss.value
+        sums = (C.c_double * 2)()
+        _check(self._lib.aim_pc_targets(self._plan, PC[base_pc], LOSS[loss],
+                                        C.c_void_p(r.data_ptr()), C.c_void_p(e.data_ptr()),
+                                        npairs, C.c_void_p(grids.data_ptr()),
+                                        C.c_void_p(tg.data_ptr()), sums, _stream_ptr(stream)))
+        return grids, tg, (sums[0], sums[1])
 
-    def pc_train_step(self, net, grids, targets, idx, tau: float, lr: float = 1e-3,
-                      apply: bool = True, stream=None) -> float:
+    def pc_train_step(self, net, grids, targets, idx, tau: float, weight: float = 1.0,
+                      loss: str = "error", lr: float = 1e-3, apply: bool = True,
+                      stream=None) -> float:
         """One Adam step on the samples idx of (grids, targets); returns the
         loss before the step."""
         Nx, Ny, Nz = self.dims
@@ -584,10 +587,11 @@ class Plan:
         if targets.shape[0] != grids.shape[0]:
             raise ValueError("grids and targets hold different numbers of pairs")
         ia = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).ravel())
-        loss = C.c_double(0.0)
-        _check(self._lib.aim_pc_train_step(self._plan, net._h, C.c_void_p(grids.data_ptr()),
+        out = C.c_double(0.0)
+        _check(self._lib.aim_pc_train_step(self._plan, net._h, LOSS[loss],
+                                           C.c_void_p(grids.data_ptr()),
                                            C.c_void_p(targets.data_ptr()), grids.shape[0],
                                            ia.ctypes.data_as(C.POINTER(C.c_int32)), ia.size,
-                                           tau, lr, int(apply), C.byref(loss),
+                                           tau, weight, lr, int(apply), C.byref(out),
                                            _stream_ptr(stream)))
-        return loss.value
+        return out.value

@@ -1338,50 +1338,75 @@ extern "C" aim_status aim_log_pairs(aim_plan p, const void* b, int32_t nrhs,
   return AIM_OK;
 }
 
-extern "C" aim_status aim_pc_targets(aim_plan p, aim_pc_kind base_pc, const void* r_pairs,
-                                     const void* e_pairs, int32_t npairs, void* grid_out,
-                                     void* target_out, double* sumsq_host, void* hip_stream) {
+extern "C" aim_status aim_pc_targets(aim_plan p, aim_pc_kind base_pc, aim_pc_loss kind,
+                                     const void* r_pairs, const void* e_pairs, int32_t npairs,
+                                     void* grid_out, void* target_out, double* sums_host,
+                                     void* hip_stream) {
   if (!p || (npairs > 0 && (!r_pairs || !e_pairs || !grid_out || !target_out)))
     return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
     AIM_REQUIRE(npairs >= 0, AIM_ERR_INVALID_ARG, "npairs must be >= 0");
     AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK, AIM_ERR_INVALID_ARG,
                 "base preconditioner must be none, diag or nearblock");
+    AIM_REQUIRE(kind == AIM_LOSS_ERROR || kind == AIM_LOSS_RESIDUAL, AIM_ERR_INVALID_ARG,
+                "unknown loss kind");
     check_unet_plan(p);
+    if (kind == AIM_LOSS_RESIDUAL) check_prec(p, AIM_C128);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     ensure_solver(p, p->max_rhs, 1, s);  // norms of up to max_rhs targets at once
     const int64_t n = p->t.N, Ng = p->g.Ng;
     const size_t vec = size_t(n) * 16;
-    double total = 0.0;
+    double err2 = 0.0, res2 = 0.0;
     std::vector<double> tn;
     for (int k0 = 0; k0 < npairs; k0 += p->max_rhs) {
       const int nb = std::min(p->max_rhs, npairs - k0);
       const char* rr = static_cast<const char*>(r_pairs) + size_t(k0) * vec;
+      const char* ee = static_cast<const char*>(e_pairs) + size_t(k0) * vec;
       char* tg = static_cast<char*>(target_out) + size_t(k0) * vec;
       unet_input(p, rr, nb, static_cast<char*>(grid_out) + size_t(k0) * Ng * 8, s);
-      apply_base(p, base_pc, rr, tg, nb, s);
-      aim::launch_unet_resid_target(static_cast<const char*>(e_pairs) + size_t(k0) * vec, p->u_s,
-                                    tg, n, nb, s);
-      norms_host(p, tg, nb, s, tn);
-      for (double v : tn) total += v * v;
+      void* br = p->sv.w;
+      apply_base(p, base_pc, rr, br, nb, s);  // B r
+      if (kind == AIM_LOSS_RESIDUAL) {
+        // s = (r - A B r) / ||r||: what is left of the normalised residual
+        // after the base preconditioner's step
+        const int32_t* df = set_freq(p, nullptr, nb, s);
+        matvec_any(p, AIM_C128, br, tg, nb, df, s);
+        aim::launch_unet_resid_target(rr, p->u_s, tg, n, nb, s);
+        norms_host(p, tg, nb, s, tn);
+        for (double v : tn) res2 += v * v;
+      }
+      // (e - B r) / ||r||: the error the network has to supply
+      aim::launch_unet_resid_target(ee, p->u_s, br, n, nb, s);
+      if (kind == AIM_LOSS_ERROR)
+        AIM_HIP(hipMemcpyAsync(tg, br, vec * nb, hipMemcpyDeviceToDevice, s));
+      norms_host(p, br, nb, s, tn);
+      for (double v : tn) err2 += v * v;
     }
     AIM_HIP(hipStreamSynchronize(s));
-    AIM_REQUIRE(std::isfinite(total), AIM_ERR_BREAKDOWN, "non-finite training target");
-    if (sumsq_host) *sumsq_host = total;
+    AIM_REQUIRE(std::isfinite(err2) && std::isfinite(res2), AIM_ERR_BREAKDOWN,
+                "non-finite training target");
+    if (sums_host) {
+      sums_host[0] = err2;
+      sums_host[1] = res2;
+    }
   });
 }
 
-extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, const void* grids,
-                                        const void* targets, int32_t npairs,
+extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, aim_pc_loss kind,
+                                        const void* grids, const void* targets, int32_t npairs,
                                         const int32_t* sample_idx_host, int32_t nsamples,
-                                        double tau, double lr, int32_t apply, double* loss_host,
-                                        void* hip_stream) {
+                                        double tau, double weight, double lr, int32_t apply,
+                                        double* loss_host, void* hip_stream) {
   if (!p || !net || !grids || !targets || !sample_idx_host)
     return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
     AIM_REQUIRE(nsamples >= 1, AIM_ERR_INVALID_ARG, "nsamples must be >= 1");
     AIM_REQUIRE(std::isfinite(tau) && tau > 0.0, AIM_ERR_INVALID_ARG, "tau must be positive");
     AIM_REQUIRE(std::isfinite(lr) && lr >= 0.0, AIM_ERR_INVALID_ARG, "lr must be >= 0");
+    AIM_REQUIRE(kind == AIM_LOSS_ERROR || kind == AIM_LOSS_RESIDUAL, AIM_ERR_INVALID_ARG,
+                "unknown loss kind");
+    AIM_REQUIRE(std::isfinite(weight) && weight > 0.0, AIM_ERR_INVALID_ARG,
+                "weight must be positive");
     for (int i = 0; i < nsamples; ++i)
       AIM_REQUIRE(sample_idx_host[i] >= 0 && sample_idx_host[i] < npairs, AIM_ERR_INVALID_ARG,
                   "sample index out of range");
@@ -1394,6 +1419,7 @@ extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, const void* gr
                     int64_t(16) * p->max_rhs * ((std::max(n, Ng) + 4095) / 4096),
                 AIM_ERR_INVALID_ARG, "too many samples in one step");
     double* part = static_cast<double*>(p->upart);
+    const int32_t* df = kind == AIM_LOSS_RESIDUAL ? set_freq(p, nullptr, 1, s) : nullptr;
     aim::unet_zero_grad(net, s);
     const double inv_cnt = 1.0 / (double(n) * nsamples);
     for (int i = 0; i < nsamples; ++i) {
@@ -1402,9 +1428,20 @@ extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, const void* gr
       aim::unet_forward(net, g, p->g.N[2], p->g.N[1], p->g.N[0], p->ug_out, s);
       aim::launch_interp_near<float>(p->g, pt_dev(p, AIM_C64), csr_dev(p, AIM_C64), p->ug_out,
                                      nullptr, p->um2, 1, true, false, s);
-      aim::launch_mesh_mse(p->um2, static_cast<const char*>(targets) + size_t(k) * n * 16,
-                           p->d_area, 1.0 / tau, n, inv_cnt, p->um1, part + size_t(i) * kParts,
-                           kParts, s);
+      const char* tk = static_cast<const char*>(targets) + size_t(k) * n * 16;
+      if (kind == AIM_LOSS_ERROR) {
+        aim::launch_mesh_mse(p->um2, tk, p->d_area, 1.0 / tau, n, inv_cnt * weight, p->um1,
+                             part + size_t(i) * kParts, kParts, s);
+      } else {
+        // loss = weight mean |s - A z|^2, z = tau c / area; its gradient with
+        // respect to c is -2 weight tau A^H (s - A z) / (area cnt)
+        aim::launch_area_scale_c64(p->um2, p->d_area, tau, p->um1, n, s);
+        matvec_any(p, AIM_C64, p->um1, p->um2, 1, df, s);
+        aim::launch_resid_loss(p->um2, tk, weight * inv_cnt, n, p->um1,
+                               part + size_t(i) * kParts, kParts, s);
+        matvec_any(p, AIM_C64, p->um1, p->um2, 1, df, s);
+        aim::launch_resid_grad(p->um2, p->d_area, -2.0 * weight * tau * inv_cnt, p->um1, n, s);
+      }
       // d loss / d grid output = P (d loss / d mesh output), as the mesh
       // output is P^T of the grid output
       aim::launch_project<float>(p->g, p_dev(p, AIM_C64), p->d_pblk, p->nblk, p->um1, n,

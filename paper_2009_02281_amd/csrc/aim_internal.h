@@ -178,6 +178,15 @@ void launch_unet_resid_target(const void* e, const double* ir, void* w, int64_t 
                               hipStream_t st);
 void launch_mesh_mse(const void* c, const void* w, const double* area, double inv_tau, int64_t n,
                      double inv_cnt, void* d, double* part, int nparts, hipStream_t st);
+// out = tau c / area (complex64, one vector)
+void launch_area_scale_c64(const void* c, const double* area, double tau, void* out, int64_t n,
+                           hipStream_t st);
+// rho = s - az; part[b] = partial sums of wgt |rho|^2; out = conj(rho)
+void launch_resid_loss(const void* az, const void* sv, double wgt, int64_t n, void* out,
+                       double* part, int nparts, hipStream_t st);
+// d = coef conj(y) / area
+void launch_resid_grad(const void* y, const double* area, double coef, void* d, int64_t n,
+                       hipStream_t st);
 // e = xs - e (one vector)
 void launch_pair_error(const void* xs, void* e, int64_t n, hipStream_t st);
 void unet_forward(aim_unet u, const void* in, int D, int H, int W, void* out, hipStream_t s);

@@ -1357,6 +1357,71 @@ void launch_mesh_mse(const void* c, const void* w, const double* area, double in
   AIM_HIP(hipGetLastError());
 }
 
+// out = tau c / area (complex64), one vector
+__global__ void area_scale_c64_kernel(const float2* c, const double* area, double tau, float2* out,
+                                      int64_t n) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const double f = tau / area[k];
+    out[k] = make_float2(float(f * c[k].x), float(f * c[k].y));
+  }
+}
+
+void launch_area_scale_c64(const void* c, const double* area, double tau, void* out, int64_t n,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(area_scale_c64_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, st,
+                     static_cast<const float2*>(c), area, tau, static_cast<float2*>(out), n);
+  AIM_HIP(hipGetLastError());
+}
+
+// residual loss of one sample: rho = s - Az; partial sums of wgt |rho|^2 per
+// block; out = conj(rho) (complex64), the input of the adjoint product
+__global__ __launch_bounds__(256) void resid_loss_kernel(const float2* az, const double2* sv,
+                                                         double wgt, int64_t n, float2* out,
+                                                         double* part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const double rx = sv[k].x - az[k].x, ry = sv[k].y - az[k].y;
+    acc += (rx * rx + ry * ry) * wgt;
+    out[k] = make_float2(float(rx), float(-ry));
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+void launch_resid_loss(const void* az, const void* sv, double wgt, int64_t n, void* out,
+                       double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(resid_loss_kernel, dim3(nparts), dim3(256), 0, st,
+                     static_cast<const float2*>(az), static_cast<const double2*>(sv), wgt, n,
+                     static_cast<float2*>(out), part);
+  AIM_HIP(hipGetLastError());
+}
+
+// d = coef conj(y) / area (complex64): with y = A conj(rho) this is
+// coef A^H rho / area, A being complex symmetric
+__global__ void resid_grad_kernel(const float2* y, const double* area, double coef, float2* d,
+                                  int64_t n) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const double f = coef / area[k];
+    d[k] = make_float2(float(f * y[k].x), float(-f * y[k].y));
+  }
+}
+
+void launch_resid_grad(const void* y, const double* area, double coef, void* d, int64_t n,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(resid_grad_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, st,
+                     static_cast<const float2*>(y), area, coef, static_cast<float2*>(d), n);
+  AIM_HIP(hipGetLastError());
+}
+
 // e = xs - e for a logged iterate (in place): the error of the iterate
 // against the converged solution
 __global__ void pair_error_kernel(const double2* xs, double2* e, int64_t n) {

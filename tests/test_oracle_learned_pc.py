@@ -74,6 +74,43 @@ def test_mesh_loss_gradient_matches_finite_differences(tiny):
             assert g[li][0][idx] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-11)
 
 
+def test_residual_loss_gradient_matches_finite_differences(tiny):
+    params = _net(4)
+    k = 2.0
+    A = lambda x: tiny.matvec(x, k)
+    r = I.complex_gaussian(tiny.N, 12)
+    d = np.linspace(1.0, 2.0, tiny.N)
+    base = lambda v: v / d
+    s = learned_pc.residual_target(A, base, r)
+    grid = learned_pc.network_input(tiny, r)
+    tau, weight = 0.6, 3.0
+    loss, g = learned_pc.residual_loss(tiny, unet.UNet(params), A, grid, s, tau, weight)
+    rng = np.random.default_rng(13)
+    eps = 1e-6
+    for li in (0, 5, 10):
+        W, _ = params[li]
+        for _ in range(2):
+            idx = tuple(int(rng.integers(0, n)) for n in W.shape)
+            Pp = [(w.copy(), bb.copy()) for w, bb in params]
+            Pm = [(w.copy(), bb.copy()) for w, bb in params]
+            Pp[li][0][idx] += eps
+            Pm[li][0][idx] -= eps
+            lp, _ = learned_pc.residual_loss(tiny, unet.UNet(Pp), A, grid, s, tau, weight)
+            lm, _ = learned_pc.residual_loss(tiny, unet.UNet(Pm), A, grid, s, tau, weight)
+            assert g[li][0][idx] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-11)
+
+
+def test_residual_target_of_an_exact_base_is_zero(tiny):
+    """If B inverts A, nothing is left for the network: s = 0."""
+    k = 2.0
+    N = tiny.N
+    Ad = np.stack([tiny.matvec(np.eye(N, dtype=complex)[j], k) for j in range(N)], axis=1)
+    Ainv = np.linalg.inv(Ad)
+    s = learned_pc.residual_target(lambda x: Ad @ x, lambda v: Ainv @ v,
+                                   I.complex_gaussian(N, 14))
+    assert np.linalg.norm(s) <= 1e-10
+
+
 def _dense_system(n=60, seed=11):
     rng = np.random.default_rng(seed)
     A = np.eye(n) * 4 + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
