@@ -53,7 +53,7 @@ def algorithmic_bytes(info: dict, prec: str, nrhs: int = 1) -> dict:
 def make_workload(name: str):
     from paper_2009_02281_amd import inputs as I
     return {"boxarray": I.box_array_large, "sphere": I.sphere_small,
-            "sphere-large": I.sphere_large}[name]()
+            "sphere-large": I.sphere_large, "sweep": I.sweep_small}[name]()
 
 
 def kernel_sha() -> str:
@@ -136,17 +136,98 @@ def solve_leg(plan, rtol: float) -> dict:
     return {"rtol": rtol, "rhs": "plane wave +z", "restart": RESTART, "runs": res}
 
 
+def learned_pc_leg(rtol: float) -> dict:
+    """GMRES time to rtol on a held-out ellipsoid (4 plane waves, batched):
+    complex128 GMRES without and with the near-block preconditioner against
+    complex64-matvec GMRES in complex128 refinement with the learned grid
+    preconditioner (diagonal base, near-block fallback).  The network is
+    trained first on pairs logged from plain GMRES on three other ellipsoids;
+    logging and training are timed separately."""
+    import numpy as np
+    import torch
+    from paper_2009_02281_amd import binding
+    from paper_2009_02281_amd import inputs as I
+
+    def plan(w):
+        return binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold,
+                            w.k, max_rhs=8)
+
+    rng = np.random.default_rng(5006)
+
+    def dirs(n):
+        d = rng.standard_normal((n, 3))
+        return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+    t0 = time.perf_counter()
+    data, err2, res2, count = [], 0.0, 0.0, 0
+    for w in I.learned_pc_geometries(3):
+        p = plan(w)
+        r, e, _ = p.log_pairs(p.excitation("plane_wave", dirs(8)), rtol=1e-9, restart=6,
+                              max_pairs=256)
+        grids, ts, sums = p.pc_targets(r, e, base_pc="diag", loss="residual")
+        data.append((p, grids, ts))
+        err2, res2, count = err2 + sums[0], res2 + sums[1], count + r.shape[0] * p.n
+    torch.cuda.synchronize()
+    t_log = time.perf_counter() - t0
+    tau, weight = math.sqrt(err2 / count), count / res2
+    net = binding.UNet(seed=61)
+    order_rng = np.random.default_rng(62)
+    t0 = time.perf_counter()
+    loss = []
+    for _ in range(10):
+        tot, nb = 0.0, 0
+        for gi in order_rng.permutation(len(data)):
+            p, grids, ts = data[gi]
+            idx = order_rng.permutation(grids.shape[0])
+            for s0 in range(0, len(idx), 8):
+                tot += p.pc_train_step(net, grids, ts, idx[s0:s0 + 8], tau=tau, weight=weight,
+                                       loss="residual", lr=2e-3)
+                nb += 1
+        loss.append(tot / nb)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    w = I.learned_pc_geometries(1, seed=5005)[0]
+    p = plan(w)
+    p.set_unet(net, base_pc="diag", tau=tau)
+    b = p.excitation("plane_wave", dirs(4))
+    runs = {}
+    for inner, pc in (("c128", "none"), ("c128", "nearblock"), ("c64", "nearblock"),
+                      ("c64", "unet")):
+        p.solve(b, rtol=1e-2, restart=RESTART, max_iter=20, inner=inner, pc=pc,
+                fallback_pc="nearblock", raise_on_fail=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, r = p.solve(b, rtol=rtol, restart=RESTART, max_iter=4000, inner=inner, pc=pc,
+                       fallback_pc="nearblock", raise_on_fail=False)
+        torch.cuda.synchronize()
+        runs[f"{inner}+{pc}"] = {"seconds": time.perf_counter() - t0,
+                                 "iters": r.iters.tolist(),
+                                 "fallback_used": bool(r.fallback_used.any()),
+                                 "converged": bool(r.converged.all())}
+        print(f"[bench] learned-pc leg {inner}+{pc}: {runs[f'{inner}+{pc}']}", file=sys.stderr,
+              flush=True)
+    p.set_unet(None)
+    net.close()
+    return {"rtol": rtol, "workload": f"{w.name} (N={w.n}, grid {list(w.dims)}, k={w.k[0]})",
+            "rhs": "4 plane waves, one batch", "training_pairs": sum(d[1].shape[0] for d in data),
+            "log_seconds": t_log, "train_seconds": t_train, "train_loss": loss, "runs": runs}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="boxarray", choices=["boxarray", "sphere", "sphere-large"])
+    ap.add_argument("--workload", default="boxarray",
+                    choices=["boxarray", "sphere", "sphere-large", "sweep"])
     ap.add_argument("--prec", default="c128", choices=["c128", "c64"])
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=0,
+                    help="right-hand sides per matvec (default 1; the sweep: all 512)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES time-to-tolerance leg")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-preconditioner time-to-tolerance leg")
     ap.add_argument("--solve-rtol", type=float, default=1e-6)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -181,6 +262,14 @@ def main() -> int:
                           "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
         return 0
     w = make_workload(args.workload)
+    freq = None
+    if args.workload == "sweep":
+        nf = len(w.k)
+        args.nrhs = args.nrhs or 8 * nf
+        freq = np.arange(args.nrhs) % nf          # each vector at its own wavenumber
+        args.no_solve = True
+        args.no_cpu = True
+    args.nrhs = args.nrhs or 1
     print(f"[bench] workload {w.name}: N={w.n} dims={w.dims} order={w.order} "
           f"prec={args.prec} nrhs={args.nrhs}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -194,7 +283,7 @@ def main() -> int:
           flush=True)
     tuned = {}
     for pr in precs:
-        tuned[pr] = plan.autotune(prec=pr, nrhs=args.nrhs, reps=5)
+        tuned[pr] = plan.autotune(prec=pr, nrhs=min(args.nrhs, 8), reps=5)
         print(f"[bench] autotuned FFT launch shapes ({pr}): {tuned[pr]['schedule']} "
               f"pass ms {[round(t, 4) for t in tuned[pr]['pass_ms']]}", file=sys.stderr,
               flush=True)
@@ -204,12 +293,12 @@ def main() -> int:
     y = torch.empty_like(x)
 
     for _ in range(args.warmup):
-        plan.matvec(x, prec=args.prec, out=y)
+        plan.matvec(x, prec=args.prec, out=y, freq_idx=freq)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(args.steps):
-        plan.matvec(x, prec=args.prec, out=y)
+        plan.matvec(x, prec=args.prec, out=y, freq_idx=freq)
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / args.steps
@@ -233,13 +322,14 @@ def main() -> int:
         "config": {"workload": w.name, "triangles": w.n, "order": w.order,
                    "grid": list(w.dims), "padded_grid": [2 * d for d in w.dims],
                    "near_threshold_h": w.near_factor, "k": float(w.k[0]),
-                   "nrhs": args.nrhs, "nnz": info["nnz"]},
+                   "nrhs": args.nrhs, "nnz": info["nnz"],
+                   "n_freq": int(len(w.k))},
         "fft_schedule": {pr: tuned[pr]["schedule"] for pr in tuned},
     }
 
     if not args.no_profile:
         reps = max(5, min(50, args.steps))
-        kms = plan.profile_matvec(x, reps=reps, prec=args.prec, out=y)
+        kms = plan.profile_matvec(x, reps=reps, prec=args.prec, out=y, freq_idx=freq)
         ab = algorithmic_bytes(info, args.prec, args.nrhs)
         dom = max(kms, key=kms.get)
         achieved = ab[dom] / (kms[dom] * 1e-3) / 1e9
@@ -258,6 +348,8 @@ def main() -> int:
 
     if not args.no_solve:
         out["gmres"] = solve_leg(plan, args.solve_rtol)
+    if not args.no_learned and args.workload != "sweep":
+        out["learned_pc"] = learned_pc_leg(args.solve_rtol)
 
     if not args.no_cpu:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)
