@@ -213,6 +213,58 @@ def learned_pc_leg(rtol: float) -> dict:
             "log_seconds": t_log, "train_seconds": t_train, "train_loss": loss, "runs": runs}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16, published
+
+
+def unet_flops(P0: int, C: int = 16) -> float:
+    """Multiply-adds x 2 of one U-Net forward pass on P0 grid points: the
+    3x3x3 convolutions at full, 1/8 and 1/64 resolution plus the 1x1 output."""
+    c0, c1, c2 = C, 2 * C, 4 * C
+    full = [(2, c0), (c0, c0), (c1 + c0, c0), (c0, c0)]
+    half = [(c0, c1), (c1, c1), (c2 + c1, c1), (c1, c1)]
+    quarter = [(c1, c2), (c2, c2)]
+    f = sum(2 * 27 * ci * co * P0 for ci, co in full)
+    f += sum(2 * 27 * ci * co * P0 / 8 for ci, co in half)
+    f += sum(2 * 27 * ci * co * P0 / 64 for ci, co in quarter)
+    return f + 2 * c0 * 2 * P0
+
+
+def unet_leg(dims=(64, 64, 64), reps: int = 20) -> dict:
+    """Forward pass and training step (forward + backward + Adam) of the
+    learned preconditioner's network on one grid, timed with events on the
+    stream the kernels run on; bf16 MFMA roofline."""
+    import numpy as np
+    import torch
+    from paper_2009_02281_amd import binding
+    net = binding.UNet(seed=1)
+    nx, ny, nz = dims
+    g = torch.from_numpy((np.random.default_rng(7).standard_normal((nz, ny, nx, 2)))
+                         .astype(np.float32)).view(torch.complex64)[..., 0].contiguous().cuda()
+    t = torch.zeros_like(g)
+    P0 = nx * ny * nz
+    res = {}
+    for name, fn, mult in (("forward", lambda: net.forward(g), 1.0),
+                           ("train_step", lambda: net.train_grid(g, t, lr=1e-4), 3.0)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        tf = mult * unet_flops(P0) / (ms * 1e-3) / 1e12
+        res[name] = {"ms": ms, "tflops": tf, "frac_bf16_peak": tf / MFMA_BF16_PEAK_TFLOPS}
+        print(f"[bench] unet {name} {list(dims)}: {ms:.3f} ms, {tf:.1f} TFLOP/s", file=sys.stderr,
+              flush=True)
+    net.close()
+    return {"grid": list(dims), "flops_forward": unet_flops(P0),
+            "note": "train_step counted as 3x the forward flops (data and weight gradients); "
+                    "it also holds host synchronisation for the loss", **res}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +280,7 @@ def main() -> int:
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES time-to-tolerance leg")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner time-to-tolerance leg")
+    ap.add_argument("--no-unet", action="store_true", help="skip the U-Net throughput leg")
     ap.add_argument("--solve-rtol", type=float, default=1e-6)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -350,6 +403,8 @@ def main() -> int:
         out["gmres"] = solve_leg(plan, args.solve_rtol)
     if not args.no_learned and args.workload != "sweep":
         out["learned_pc"] = learned_pc_leg(args.solve_rtol)
+    if not args.no_unet and args.workload != "sweep":
+        out["unet"] = unet_leg()
 
     if not args.no_cpu:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)

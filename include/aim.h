@@ -265,6 +265,10 @@ aim_status aim_graph_destroy(aim_graph graph);  /* NULL is a no-op */
 aim_status aim_autotune(aim_plan plan, aim_precision prec, int32_t nrhs, int32_t reps,
                         int32_t* sched_out, double* pass_ms_out, void* hip_stream);
 
+/* Number of launch shapes per FFT pass (shape indices 0 .. AIM_FFT_SHAPES-1;
+ * not every shape exists for every transform length). */
+#define AIM_FFT_SHAPES 6
+
 /* Installs a schedule returned earlier by aim_autotune (for example from a
  * cache keyed by grid, precision and batch width).  AIM_ERR_INVALID_ARG if a
  * shape is out of range or not available for that pass. */

@@ -108,7 +108,7 @@ void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, 
 // per right-hand side; q and phi may alias.
 // sched[5] selects the launch shape of the x-forward, y-forward, z, y-inverse
 // and x-inverse passes (NULL: shape 0 everywhere).
-constexpr int kFftVariants = 4;
+constexpr int kFftVariants = AIM_FFT_SHAPES;
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,

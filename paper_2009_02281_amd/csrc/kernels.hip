@@ -5,8 +5,8 @@
 //   project        q = P x with P assembled at set-up and sorted by grid node;
 //                  each thread owns one node and sums its row in a fixed
 //                  order (reproducible, no atomics);
-//   fft_row/col    LDS-staged Stockham passes (radix 8 with one radix-2/4
-//                  stage), pruned: forward passes read only the non-zero half
+//   fft_row/col    register-resident Stockham passes (radix 8 or 16 with
+//                  one smaller stage, exchanges through LDS), pruned: forward passes read only the non-zero half
 //                  of each padded line, inverse passes write only the half that
 //                  is kept; column passes move whole 128-byte row segments so
 //                  the strided y/z lines are read and written coalesced;
@@ -135,6 +135,43 @@ struct Dft<T, 8, INV> {
   }
 };
 
+// 16 points as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2; 4-point DFTs over n1,
+// twiddles W16^(n2 k1), 4-point DFTs over n2
+template <typename T, bool INV>
+struct Dft<T, 16, INV> {
+  static __device__ __forceinline__ cx<T> tw(cx<T> a, T c, T sf) {  // a * (c + i sf), sf forward
+    return cmul(a, mkc<T>(c, INV ? -sf : sf));
+  }
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+    const T r2 = T(0.70710678118654752440);
+    cx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cx<T> u[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Dft<T, 4, INV>::run(u);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = u[k1];
+    }
+    a[1][1] = tw(a[1][1], c1, -s1);   // W^1
+    a[1][2] = tw(a[1][2], r2, -r2);   // W^2
+    a[1][3] = tw(a[1][3], s1, -c1);   // W^3
+    a[2][1] = tw(a[2][1], r2, -r2);   // W^2
+    a[2][2] = rot90<T, INV>(a[2][2]); // W^4
+    a[2][3] = tw(a[2][3], -r2, -r2);  // W^6
+    a[3][1] = tw(a[3][1], s1, -c1);   // W^3
+    a[3][2] = tw(a[3][2], -r2, -r2);  // W^6
+    a[3][3] = tw(a[3][3], -c1, s1);   // W^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cx<T> u[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<T, 4, INV>::run(u);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = u[k2];
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Register-resident Stockham FFT.  A length-L line is shared by NT threads;
 // each holds E = L/NT elements in registers.  Stage s with radix R treats
@@ -148,13 +185,16 @@ struct Dft<T, 8, INV> {
 // ends, and an inverse one starts, with radix 8 and the same element
 // ownership: the spectral multiply between them needs no exchange.
 // ---------------------------------------------------------------------------
-template <int L, bool SMALL_FIRST>
+template <int L, bool SMALL_FIRST, int RMAX>
 struct Sched {
   static constexpr int P = ilog2(L);
-  static constexpr int SMALL = P % 3 == 1 ? 2 : (P % 3 == 2 ? 4 : 8);
-  static constexpr int NST = P % 3 == 0 ? P / 3 : P / 3 + 1;
+  static constexpr int Q = ilog2(RMAX);                 // bits per full stage (3 or 4)
+  static constexpr int REM = P % Q;
+  static constexpr int SMALL = 1 << REM;               // the one smaller radix, if any
+  static constexpr int NST = P / Q + (REM ? 1 : 0);
   static constexpr int radix(int st) {
-    return P % 3 == 0 ? 8 : (SMALL_FIRST ? (st == 0 ? SMALL : 8) : (st == NST - 1 ? SMALL : 8));
+    return REM == 0 ? RMAX : (SMALL_FIRST ? (st == 0 ? SMALL : RMAX)
+                                          : (st == NST - 1 ? SMALL : RMAX));
   }
   static constexpr int lgns(int st) {
     int a = 0;
@@ -204,14 +244,14 @@ __device__ __forceinline__ void exchange(cx<T>* v, cx<T>* s, int es, int t) {
   __syncthreads();
 }
 
-template <typename T, int L, int NT, bool INV, bool SF, int ST>
+template <typename T, int L, int NT, bool INV, bool SF, int RMAX, int ST>
 __device__ __forceinline__ void run_stages(cx<T>* v, cx<T>* s, int es, int t, const cx<T>* tw) {
-  using Sc = Sched<L, SF>;
+  using Sc = Sched<L, SF, RMAX>;
   constexpr int R = Sc::radix(ST), LG = Sc::lgns(ST);
   stage_compute<T, L, NT, INV, R, LG>(v, t, tw);
   if constexpr (ST + 1 < Sc::NST) {
     exchange<T, L, NT, R, LG, Sc::radix(ST + 1)>(v, s, es, t);
-    run_stages<T, L, NT, INV, SF, ST + 1>(v, s, es, t, tw);
+    run_stages<T, L, NT, INV, SF, RMAX, ST + 1>(v, s, es, t, tw);
   }
 }
 
@@ -235,7 +275,7 @@ struct PassArgs {
   int Mx, Nx, My, Ny, Mz, Nz;
 };
 
-template <typename T, int L, int TL, int NT, int MODE, bool COL>
+template <typename T, int L, int TL, int NT, int MODE, bool COL, int RMAX>
 __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>* out,
                                                           const cx<T>* __restrict__ twg,
                                                           PassArgs a) {
@@ -281,7 +321,8 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
   __syncthreads();
 
   constexpr bool SF = MODE != 1;
-  using S0 = Sched<L, SF>;
+  static_assert(RMAX <= E, "a thread must hold a whole butterfly");
+  using S0 = Sched<L, SF, RMAX>;
   constexpr int R0 = S0::radix(0), NB0 = L / (R0 * NT);
   cx<T> v[E];
 #pragma unroll
@@ -291,10 +332,12 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
       const int e = t + i * NT + r * (L / R0);
       v[i * R0 + r] = (valid && e < a.Lin) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
     }
-  run_stages<T, L, NT, MODE == 1, SF, 0>(v, sl, es, t, tw);
+  run_stages<T, L, NT, MODE == 1, SF, RMAX, 0>(v, sl, es, t, tw);
   if constexpr (MODE == 2) {
-    static_assert(Sched<L, true>::radix(Sched<L, true>::NST - 1) == 8, "forward must end in radix 8");
-    static_assert(Sched<L, false>::radix(0) == 8, "inverse must start in radix 8");
+    using Fw = Sched<L, true, RMAX>;
+    constexpr int RM = Fw::radix(Fw::NST - 1);
+    static_assert(RM == Sched<L, false, RMAX>::radix(0),
+                  "the forward transform must end with the radix the inverse starts with");
     if (valid) {
       const int kx = int(li), ky = int(lo);
       const int fx = kx <= a.Nx ? kx : a.Mx - kx;
@@ -304,17 +347,17 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
                         int64_t(fy) * (a.Nz + 1) * (a.Nx + 1) + fx;
       const int64_t zst = int64_t(a.Nx + 1);
 #pragma unroll
-      for (int i = 0; i < L / (8 * NT); ++i)
+      for (int i = 0; i < L / (RM * NT); ++i)
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int e = t + i * NT + r * (L / 8);
+        for (int r = 0; r < RM; ++r) {
+          const int e = t + i * NT + r * (L / RM);
           const int fz = e <= a.Nz ? e : a.Mz - e;
-          v[i * 8 + r] = cmul(v[i * 8 + r], sp[fz * zst]);
+          v[i * RM + r] = cmul(v[i * RM + r], sp[fz * zst]);
         }
     }
-    run_stages<T, L, NT, true, false, 0>(v, sl, es, t, tw);
+    run_stages<T, L, NT, true, false, RMAX, 0>(v, sl, es, t, tw);
   }
-  using Sf = Sched<L, MODE == 0>;
+  using Sf = Sched<L, MODE == 0, RMAX>;
   constexpr int Rf = Sf::radix(Sf::NST - 1), NBf = L / (Rf * NT);
   if (valid) {
 #pragma unroll
@@ -339,7 +382,9 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <typename T, int L, bool COL, int V>
 struct Shape {
   static constexpr int kTL = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
-  static constexpr int NT = COL ? (V == 0 ? cmin(L / 8, 256 / kTL)
+  // V 0-3: 8 elements per thread (radix-8 stages); V 4-5: 16 (radix 16)
+  static constexpr int NT = V >= 4 ? cmax(1, L / 16)
+                          : COL ? (V == 0 ? cmin(L / 8, 256 / kTL)
                                   : V == 1 ? cmin(L / 8, 512 / kTL)
                                   : V == 2 ? cmin(L / 8, 256 / (2 * kTL))
                                            : cmin(L / 8, 512 / (2 * kTL)))
@@ -347,16 +392,21 @@ struct Shape {
                                   : V == 1 ? cmin(L / 8, 128)
                                   : V == 2 ? cmin(L / 8, 32)
                                            : cmin(L / 8, 64));
-  static constexpr int TL = COL ? (V == 0 ? 256 / cmin(L / 8, 256 / kTL)
+  static constexpr int TL = V >= 4 ? cmax(1, (V == 4 ? 256 : 128) / NT)
+                          : COL ? (V == 0 ? 256 / cmin(L / 8, 256 / kTL)
                                   : V == 1 ? 512 / cmin(L / 8, 512 / kTL)
                                   : V == 2 ? 256 / cmin(L / 8, 256 / (2 * kTL))
                                            : 512 / cmin(L / 8, 512 / (2 * kTL)))
                                 : (V == 3 ? 512 / NT : cmax(1, 256 / NT));
+  // radix-16 stages for the 16-element shapes: one exchange fewer per
+  // transform for L = 128 and 256
+  static constexpr int RMAX = V >= 4 && L >= 16 ? 16 : 8;
   static constexpr int THREADS = TL * NT;
   static constexpr size_t LDS = sizeof(cx<T>) * (COL ? size_t(L) * TL : size_t(TL) * (L + 1)) +
                                 sizeof(cx<T>) * L;
   static constexpr bool OK = THREADS >= 64 && THREADS <= 1024 && LDS <= 160 * 1024 &&
-                             (TL & (TL - 1)) == 0;
+                             (TL & (TL - 1)) == 0 &&
+                             (V < 4 || (L >= 16 && (!COL || TL * sizeof(T) * 2 >= 64)));
 };
 
 template <typename T, int L, bool COL, int V>
@@ -368,11 +418,11 @@ void launch_shape(int mode, const cx<T>* i, cx<T>* o, const cx<T>* w, const Pass
   } else {
     dim3 grid(unsigned((a.nlines + S::TL - 1) / S::TL), unsigned(nrhs));
     if (mode == 0)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 0, COL>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 0, COL, S::RMAX>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
     else if (mode == 1)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 1, COL>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 1, COL, S::RMAX>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
     else if constexpr (COL)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 2, COL>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 2, COL, S::RMAX>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
     else
       throw Error(AIM_ERR_INVALID_ARG, "row passes have no spectral multiply");
   }
@@ -393,6 +443,10 @@ void pass_L(bool col, int mode, int variant, const void* in, void* out, const vo
     case 5: launch_shape<T, L, true, 2>(mode, i, o, w, a, nrhs, s); break;
     case 6: launch_shape<T, L, false, 3>(mode, i, o, w, a, nrhs, s); break;
     case 7: launch_shape<T, L, true, 3>(mode, i, o, w, a, nrhs, s); break;
+    case 8: launch_shape<T, L, false, 4>(mode, i, o, w, a, nrhs, s); break;
+    case 9: launch_shape<T, L, true, 4>(mode, i, o, w, a, nrhs, s); break;
+    case 10: launch_shape<T, L, false, 5>(mode, i, o, w, a, nrhs, s); break;
+    case 11: launch_shape<T, L, true, 5>(mode, i, o, w, a, nrhs, s); break;
     default: throw Error(AIM_ERR_INVALID_ARG, "FFT launch shape out of range");
   }
 }
@@ -423,6 +477,10 @@ bool shape_ok_L(bool col, int v) {
     case 5: return Shape<T, L, true, 2>::OK;
     case 6: return Shape<T, L, false, 3>::OK;
     case 7: return Shape<T, L, true, 3>::OK;
+    case 8: return Shape<T, L, false, 4>::OK;
+    case 9: return Shape<T, L, true, 4>::OK;
+    case 10: return Shape<T, L, false, 5>::OK;
+    case 11: return Shape<T, L, true, 5>::OK;
     default: return false;
   }
 }
