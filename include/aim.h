@@ -254,24 +254,38 @@ aim_status aim_matvec_capture(aim_plan plan, aim_precision prec, const void* x_d
 aim_status aim_graph_launch(aim_graph graph, void* hip_stream);
 aim_status aim_graph_destroy(aim_graph graph);  /* NULL is a no-op */
 
-/* Launch-shape autotuner for the five FFT passes of the convolution (x
- * forward, y forward, z forward * spectrum * inverse, y inverse, x inverse):
- * times every available shape (lines per workgroup x threads per line) of
- * each pass over `reps` runs with nrhs right-hand sides on hip_stream, keeps
- * the fastest per pass in the plan for this precision, and returns the
- * choices in sched_out[5] and their average times (ms) in pass_ms_out[5]
- * (either may be NULL).  Overwrites the plan's internal grid workspace;
- * blocking.  The schedule does not change results beyond rounding order. */
+/* A schedule is AIM_SCHEDULE_LEN integers: the launch shape of each of the
+ * five FFT passes (indices 0 .. AIM_FFT_SHAPES-1; not every shape exists for
+ * every transform length), then the layout of the convolution workspace
+ * (0 .. AIM_FFT_LAYOUTS-1: 0, 1, 4 or 12 KiB of padding after every z plane,
+ * which keeps the strided z lines from falling on one memory channel), then
+ * the interpolation mode (0: the assembled P^T; 1: the weights of P^T
+ * recomputed from the quadrature points' stencil coordinates). */
+#define AIM_FFT_SHAPES 6
+#define AIM_FFT_LAYOUTS 4
+#define AIM_SCHEDULE_LEN 7
+
+/* Schedule autotuner for the convolution's five FFT passes (x forward,
+ * y forward, z forward * spectrum * inverse, y inverse, x inverse) and the
+ * interpolation: for every workspace layout, times every available launch
+ * shape (lines per workgroup x threads per line) of each pass over `reps`
+ * runs with nrhs right-hand sides on hip_stream and keeps the layout with
+ * the smallest sum of per-pass best times and those shapes; then times both
+ * interpolation modes and keeps the faster.  The schedule is stored in the
+ * plan for this precision and returned in sched_out[AIM_SCHEDULE_LEN], the
+ * chosen passes' average times (ms) in pass_ms_out[5] (either may be NULL).
+ * Overwrites the plan's internal grid workspace; allocates and frees two
+ * vectors of scratch; blocking.  The schedule does not change results beyond
+ * rounding order. */
 aim_status aim_autotune(aim_plan plan, aim_precision prec, int32_t nrhs, int32_t reps,
                         int32_t* sched_out, double* pass_ms_out, void* hip_stream);
 
-/* Number of launch shapes per FFT pass (shape indices 0 .. AIM_FFT_SHAPES-1;
- * not every shape exists for every transform length). */
-#define AIM_FFT_SHAPES 6
 
-/* Installs a schedule returned earlier by aim_autotune (for example from a
- * cache keyed by grid, precision and batch width).  AIM_ERR_INVALID_ARG if a
- * shape is out of range or not available for that pass. */
+/* Installs a schedule (AIM_SCHEDULE_LEN entries) returned earlier by
+ * aim_autotune (for example from a cache keyed by grid, precision and batch
+ * width).  AIM_ERR_INVALID_ARG if a shape is out of range or not available
+ * for that pass, or the layout or mode is out of range.  Graphs captured before keep
+ * the schedule they were captured with. */
 aim_status aim_set_schedule(aim_plan plan, aim_precision prec, const int32_t* sched);
 
 /* ---------------------------------------------------------------------

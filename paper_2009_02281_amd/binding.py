@@ -23,6 +23,8 @@ PREC = {"c128": 0, "c64": 1}
 PC = {"none": 0, "diag": 1, "nearblock": 2, "unet": 3}
 LOSS = {"error": 0, "residual": 1}
 FFT_SHAPES = 6          # AIM_FFT_SHAPES
+FFT_LAYOUTS = 4         # AIM_FFT_LAYOUTS
+SCHEDULE_LEN = 7        # AIM_SCHEDULE_LEN: five pass shapes, the layout, the interpolation mode
 STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc": 4}
 RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
@@ -437,20 +439,20 @@ class Plan:
 
     def autotune(self, prec: str = "c128", nrhs: int = 1, reps: int = 5, cache_path=None,
                  stream=None) -> dict:
-        """Picks the FFT launch shapes for this plan.  With ``cache_path`` a
-        JSON file keyed by (grid, precision, nrhs, gfx950) is read first and
-        updated after tuning."""
+        """Picks the FFT launch shapes and workspace layout for this plan.
+        With ``cache_path`` a JSON file keyed by (grid, precision, nrhs,
+        gfx950) is read first and updated after tuning."""
         import json
-        key = f"gfx950|{'x'.join(map(str, self.dims))}|{prec}|nrhs={nrhs}"
+        key = f"gfx950|{'x'.join(map(str, self.dims))}|{prec}|nrhs={nrhs}|s{SCHEDULE_LEN}"
         cache = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as f:
                 cache = json.load(f)
         if key in cache:
-            sched = (C.c_int32 * 5)(*cache[key]["schedule"])
+            sched = (C.c_int32 * SCHEDULE_LEN)(*cache[key]["schedule"])
             _check(self._lib.aim_set_schedule(self._plan, PREC[prec], sched))
             return dict(cache[key], cached=True)
-        sched = (C.c_int32 * 5)()
+        sched = (C.c_int32 * SCHEDULE_LEN)()
         ms = (C.c_double * 5)()
         _check(self._lib.aim_autotune(self._plan, PREC[prec], int(nrhs), int(reps), sched, ms,
                                       _stream_ptr(stream)))
@@ -462,7 +464,12 @@ class Plan:
         return dict(ent, cached=False)
 
     def set_schedule(self, sched, prec: str = "c128"):
-        arr = (C.c_int32 * 5)(*sched)
+        """Five pass shapes, the layout and the interpolation mode (missing
+        trailing entries are 0)."""
+        sched = list(sched) + [0] * (SCHEDULE_LEN - len(sched))
+        if len(sched) != SCHEDULE_LEN:
+            raise ValueError(f"a schedule has {SCHEDULE_LEN} entries")
+        arr = (C.c_int32 * SCHEDULE_LEN)(*sched)
         _check(self._lib.aim_set_schedule(self._plan, PREC[prec], arr))
 
     def apply_stage(self, stage: str, inp, freq_idx=None, prec: str = "c128", stream=None):

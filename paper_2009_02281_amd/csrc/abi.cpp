@@ -88,8 +88,12 @@ struct aim_plan_s {
   bool host_only = false;
 
   // device tables
-  double* d_w64 = nullptr;     // quadrature weights (excitation)
+  double* d_w64 = nullptr;     // quadrature weights (excitation, implicit interpolation)
   double* d_qpxyz = nullptr;   // quadrature points (excitation)
+  float* d_w32 = nullptr;
+  int32_t* d_qporigin = nullptr;  // grid index of each point's first stencil node
+  double* d_qplocal64 = nullptr;  // [3N][3] local stencil coordinates
+  float* d_qplocal32 = nullptr;
   int32_t* d_pblk = nullptr;   // row blocks of P
   int nblk = 0;
   int32_t* d_prow = nullptr;   // P by grid node
@@ -125,7 +129,8 @@ struct aim_plan_s {
   double* u_s2 = nullptr;
   void* d_work[2] = {nullptr, nullptr};  // [prec] 6 Ng per rhs
   void* d_grid[2] = {nullptr, nullptr};  // [prec] Ng per rhs
-  int sched[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};  // FFT launch shapes per precision
+  // FFT launch shapes, workspace layout and interpolation mode per precision
+  int sched[2][aim::kSchedLen] = {{0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0}};
   int32_t* d_rhs_freq = nullptr;          // [max_rhs]
   int32_t* h_rhs_freq = nullptr;          // pinned staging
   std::vector<int32_t> cur_freq;          // what d_rhs_freq holds
@@ -222,6 +227,29 @@ aim::CsrDevice csr_dev(aim_plan p, aim_precision prec) {
   return c;
 }
 
+aim::QpDevice qp_dev(aim_plan p, aim_precision prec) {
+  aim::QpDevice q;
+  q.origin = p->d_qporigin;
+  q.local = prec == AIM_C128 ? static_cast<const void*>(p->d_qplocal64) : p->d_qplocal32;
+  q.w = prec == AIM_C128 ? static_cast<const void*>(p->d_w64) : p->d_w32;
+  q.order = p->t.order;
+  return q;
+}
+
+// y = P^T phi (+ C x) with the plan's interpolation mode for this precision,
+// or y = C x alone (do_interp false)
+template <typename T>
+void interp_near(aim_plan p, aim_precision prec, const void* phi, const void* x, void* y,
+                 int nrhs, bool do_interp, bool do_near, hipStream_t s, int mode = -1) {
+  if (mode < 0) mode = p->sched[int(prec)][6];
+  if (do_interp && mode == 1)
+    aim::launch_interp_implicit<T>(p->g, qp_dev(p, prec), csr_dev(p, prec), phi, x, y, nrhs,
+                                   do_near, s);
+  else
+    aim::launch_interp_near<T>(p->g, pt_dev(p, prec), csr_dev(p, prec), phi, x, y, nrhs,
+                               do_interp, do_near, s);
+}
+
 void check_prec(aim_plan p, aim_precision prec) {
   AIM_REQUIRE(!p->host_only, AIM_ERR_STATE, "host-only plan has no device data");
   AIM_REQUIRE(prec == AIM_C128 || prec == AIM_C64, AIM_ERR_INVALID_ARG, "bad precision");
@@ -267,8 +295,7 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
   aim::launch_convolve<T>(p->g, grid, p->d_work[pi], grid, spec, dfreq, nrhs, tw, s,
                           ev ? ev + 2 : nullptr, p->sched[pi]);
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
-  aim::launch_interp_near<T>(p->g, pt_dev(p, prec), csr_dev(p, prec), grid, x, y, nrhs, true,
-                             true, s);
+  interp_near<T>(p, prec, grid, x, y, nrhs, true, true, s);
   if (ev) AIM_HIP(hipEventRecord(ev[7], s));
 }
 
@@ -409,6 +436,19 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
     // quadrature points (excitation) and the projection matrix in two layouts
     p->d_qpxyz = p->upload(t.qp_xyz, s);
     p->d_w64 = p->upload(t.qp_w, s);
+    {
+      const int64_t nq = 3 * t.N;
+      std::vector<int32_t> org(nq);
+      for (int64_t q = 0; q < nq; ++q)
+        org[q] = int32_t((int64_t(t.qp_start[3 * q + 2]) * t.dims[1] + t.qp_start[3 * q + 1]) *
+                             t.dims[0] + t.qp_start[3 * q]);
+      p->d_qporigin = p->upload(org, s);
+      p->d_qplocal64 = p->upload(t.qp_local, s);
+      if (p->prec & (1u << AIM_C64)) {
+        p->d_qplocal32 = p->upload(std::vector<float>(t.qp_local.begin(), t.qp_local.end()), s);
+        p->d_w32 = p->upload(std::vector<float>(t.qp_w.begin(), t.qp_w.end()), s);
+      }
+    }
     p->d_prow = p->upload(t.p_rowptr, s);
     p->d_pblk = p->upload(t.p_blk, s);
     p->nblk = int(t.p_blk.size()) - 1;
@@ -463,7 +503,9 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
     for (int pi = 0; pi < 2; ++pi) {
       if (!(p->prec & (1u << pi))) continue;
       const size_t cb = pi == 0 ? 16 : 8;
-      p->d_work[pi] = p->dalloc(size_t(6) * g.Ng * cb * p->max_rhs, s);
+      // room for the layout with the largest plane padding
+      p->d_work[pi] = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, cb)) * cb * p->max_rhs,
+                                s);
       p->d_grid[pi] = p->dalloc(size_t(g.Ng) * cb * p->max_rhs, s);
     }
     p->d_rhs_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * p->max_rhs, s));
@@ -586,7 +628,12 @@ aim_status aim_set_schedule(aim_plan p, aim_precision prec, const int32_t* sched
                       aim::fft_variant_ok(prec == AIM_C128, p->g.M[kPassAxis[k]], kPassCol[k],
                                           sched[k]),
                   AIM_ERR_INVALID_ARG, "launch shape not available for this pass");
-    for (int k = 0; k < 5; ++k) p->sched[int(prec)][k] = sched[k];
+    AIM_REQUIRE(sched[5] >= 0 && sched[5] < aim::kLayouts, AIM_ERR_INVALID_ARG,
+                "workspace layout out of range");
+    AIM_REQUIRE(sched[6] == 0 || sched[6] == 1, AIM_ERR_INVALID_ARG,
+                "interpolation mode must be 0 or 1");
+    for (int k = 0; k < aim::kSchedLen; ++k) p->sched[int(prec)][k] = sched[k];
+    p->graphs.clear();
   });
 }
 
@@ -608,47 +655,64 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
       for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     };
-    double best[5];
-    int pick[5];
-    for (int k = 0; k < 5; ++k) {
-      best[k] = 1e300;
-      pick[k] = 0;
-    }
+    double best[5], lbest[5];
+    int pick[aim::kSchedLen], lpick[5];
+    double best_total = 1e300;
+    for (int k = 0; k < aim::kSchedLen; ++k) pick[k] = 0;
+    for (int k = 0; k < 5; ++k) best[k] = 0.0;
     try {
       for (auto& e : ev) AIM_HIP(hipEventCreate(&e));
-      for (int v = 0; v < aim::kFftVariants; ++v) {
-        int sch[5];
-        bool any = false;
+      for (int layout = 0; layout < aim::kLayouts; ++layout) {
         for (int k = 0; k < 5; ++k) {
-          const bool ok = aim::fft_variant_ok(dbl, p->g.M[kPassAxis[k]], kPassCol[k], v);
-          sch[k] = ok ? v : 0;
-          any = any || ok;
+          lbest[k] = 1e300;
+          lpick[k] = 0;
         }
-        if (!any) continue;
-        for (int r = -1; r < reps; ++r) {  // r = -1: warm-up
-          hipEvent_t* e = &ev[6 * size_t(std::max(r, 0))];
-          if (r >= 0) AIM_HIP(hipEventRecord(e[0], s));
-          if (dbl)
-            aim::launch_convolve<double>(p->g, grid, p->d_work[pi], grid, p->d_spec64, df, nrhs,
-                                         p->d_tw64, s, r >= 0 ? e + 1 : nullptr, sch);
-          else
-            aim::launch_convolve<float>(p->g, grid, p->d_work[pi], grid, p->d_spec32, df, nrhs,
-                                        p->d_tw32, s, r >= 0 ? e + 1 : nullptr, sch);
-          if (r >= 0) AIM_HIP(hipEventRecord(e[5], s));
+        for (int v = 0; v < aim::kFftVariants; ++v) {
+          int sch[aim::kSchedLen];
+          bool any = false;
+          for (int k = 0; k < 5; ++k) {
+            const bool ok = aim::fft_variant_ok(dbl, p->g.M[kPassAxis[k]], kPassCol[k], v);
+            sch[k] = ok ? v : 0;
+            any = any || ok;
+          }
+          sch[5] = layout;
+          sch[6] = 0;
+          if (!any) continue;
+          for (int r = -1; r < reps; ++r) {  // r = -1: warm-up
+            hipEvent_t* e = &ev[6 * size_t(std::max(r, 0))];
+            if (r >= 0) AIM_HIP(hipEventRecord(e[0], s));
+            if (dbl)
+              aim::launch_convolve<double>(p->g, grid, p->d_work[pi], grid, p->d_spec64, df, nrhs,
+                                           p->d_tw64, s, r >= 0 ? e + 1 : nullptr, sch);
+            else
+              aim::launch_convolve<float>(p->g, grid, p->d_work[pi], grid, p->d_spec32, df, nrhs,
+                                          p->d_tw32, s, r >= 0 ? e + 1 : nullptr, sch);
+            if (r >= 0) AIM_HIP(hipEventRecord(e[5], s));
+          }
+          AIM_HIP(hipStreamSynchronize(s));
+          for (int k = 0; k < 5; ++k) {
+            if (sch[k] != v) continue;
+            double tot = 0.0;
+            for (int r = 0; r < reps; ++r) {
+              float ms = 0.f;
+              AIM_HIP(hipEventElapsedTime(&ms, ev[6 * size_t(r) + k], ev[6 * size_t(r) + k + 1]));
+              tot += ms;
+            }
+            if (tot / reps < lbest[k]) {
+              lbest[k] = tot / reps;
+              lpick[k] = v;
+            }
+          }
         }
-        AIM_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < 5; ++k) {
-          if (sch[k] != v) continue;
-          double tot = 0.0;
-          for (int r = 0; r < reps; ++r) {
-            float ms = 0.f;
-            AIM_HIP(hipEventElapsedTime(&ms, ev[6 * size_t(r) + k], ev[6 * size_t(r) + k + 1]));
-            tot += ms;
+        double total = 0.0;
+        for (int k = 0; k < 5; ++k) total += lbest[k];
+        if (total < best_total) {
+          best_total = total;
+          for (int k = 0; k < 5; ++k) {
+            best[k] = lbest[k];
+            pick[k] = lpick[k];
           }
-          if (tot / reps < best[k]) {
-            best[k] = tot / reps;
-            pick[k] = v;
-          }
+          pick[5] = layout;
         }
       }
     } catch (...) {
@@ -656,11 +720,56 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
       throw;
     }
     destroy();
-    for (int k = 0; k < 5; ++k) {
+    // interpolation: assembled P^T against recomputed weights, with the near
+    // correction, on the grid workspace as phi
+    {
+      const size_t vb = size_t(p->t.N) * cb * nrhs;
+      void* xy = nullptr;
+      AIM_HIP(hipMalloc(&xy, 2 * vb));
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      double tm[2] = {0.0, 0.0};
+      try {
+        AIM_HIP(hipMemsetAsync(xy, 0, 2 * vb, s));
+        AIM_HIP(hipEventCreate(&e0));
+        AIM_HIP(hipEventCreate(&e1));
+        for (int mode = 0; mode < 2; ++mode) {
+          auto run = [&] {
+            if (dbl)
+              interp_near<double>(p, prec, grid, xy, static_cast<char*>(xy) + vb, nrhs, true,
+                                  true, s, mode);
+            else
+              interp_near<float>(p, prec, grid, xy, static_cast<char*>(xy) + vb, nrhs, true,
+                                 true, s, mode);
+          };
+          run();  // warm-up
+          AIM_HIP(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) run();
+          AIM_HIP(hipEventRecord(e1, s));
+          AIM_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          AIM_HIP(hipEventElapsedTime(&ms, e0, e1));
+          tm[mode] = ms / reps;
+        }
+      } catch (...) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(xy);
+        throw;
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      AIM_HIP(hipStreamSynchronize(s));
+      AIM_HIP(hipFree(xy));
+      pick[6] = tm[1] < tm[0] ? 1 : 0;
+    }
+    for (int k = 0; k < aim::kSchedLen; ++k) {
       p->sched[pi][k] = pick[k];
       if (sched_out) sched_out[k] = pick[k];
-      if (pass_ms_out) pass_ms_out[k] = best[k];
     }
+    for (int k = 0; k < 5; ++k)
+      if (pass_ms_out) pass_ms_out[k] = best[k];
+    p->graphs.clear();
   });
 }
 
@@ -701,13 +810,11 @@ aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, cons
       case AIM_STAGE_NEAR: {
         const bool interp = stage == AIM_STAGE_INTERPOLATE;
         if (d)
-          aim::launch_interp_near<double>(p->g, pt_dev(p, prec), csr_dev(p, prec),
-                                          interp ? in : nullptr, interp ? nullptr : in, out, nrhs,
-                                          interp, !interp, s);
+          interp_near<double>(p, prec, interp ? in : nullptr, interp ? nullptr : in, out, nrhs,
+                              interp, !interp, s);
         else
-          aim::launch_interp_near<float>(p->g, pt_dev(p, prec), csr_dev(p, prec),
-                                         interp ? in : nullptr, interp ? nullptr : in, out, nrhs,
-                                         interp, !interp, s);
+          interp_near<float>(p, prec, interp ? in : nullptr, interp ? nullptr : in, out, nrhs,
+                             interp, !interp, s);
         break;
       }
       case AIM_STAGE_LEARNED_PC:
@@ -933,8 +1040,7 @@ void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s) 
   for (int r = 0; r < nrhs; ++r)
     aim::unet_forward(p->unet, static_cast<char*>(p->ug_in) + size_t(r) * Ng * 8, p->g.N[2],
                       p->g.N[1], p->g.N[0], static_cast<char*>(p->ug_out) + size_t(r) * Ng * 8, s);
-  aim::launch_interp_near<float>(p->g, pt_dev(p, AIM_C64), csr_dev(p, AIM_C64), p->ug_out,
-                                 nullptr, p->um2, nrhs, true, false, s);
+  interp_near<float>(p, AIM_C64, p->ug_out, nullptr, p->um2, nrhs, true, false, s);
   apply_base(p, p->unet_base, v, z, nrhs, s);
   aim::launch_unet_combine(p->um2, p->d_area, p->unet_tau, p->u_s, z, n, nrhs, s);
 }
@@ -1426,8 +1532,7 @@ extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, aim_pc_loss ki
       const int64_t k = sample_idx_host[i];
       const char* g = static_cast<const char*>(grids) + size_t(k) * Ng * 8;
       aim::unet_forward(net, g, p->g.N[2], p->g.N[1], p->g.N[0], p->ug_out, s);
-      aim::launch_interp_near<float>(p->g, pt_dev(p, AIM_C64), csr_dev(p, AIM_C64), p->ug_out,
-                                     nullptr, p->um2, 1, true, false, s);
+      interp_near<float>(p, AIM_C64, p->ug_out, nullptr, p->um2, 1, true, false, s);
       const char* tk = static_cast<const char*>(targets) + size_t(k) * n * 16;
       if (kind == AIM_LOSS_ERROR) {
         aim::launch_mesh_mse(p->um2, tk, p->d_area, 1.0 / tau, n, inv_cnt * weight, p->um1,

@@ -109,6 +109,14 @@ void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, 
 // sched[5] selects the launch shape of the x-forward, y-forward, z, y-inverse
 // and x-inverse passes (NULL: shape 0 everywhere).
 constexpr int kFftVariants = AIM_FFT_SHAPES;
+// schedule = launch shape of each of the five FFT passes, the work layout,
+// and the interpolation mode (0: assembled P^T, 1: recomputed weights)
+constexpr int kSchedLen = 7;
+constexpr int kLayouts = AIM_FFT_LAYOUTS;
+// bytes added to every z plane of the convolution work grid, per layout
+constexpr int64_t kLayoutPadBytes[kLayouts] = {0, 1024, 4096, 12288};
+// complex elements of convolution workspace per right-hand side
+int64_t work_elems(const GridShape& g, int layout, size_t elem_bytes);
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
@@ -119,6 +127,20 @@ bool fft_variant_ok(bool dbl, int L, bool col, int v);
 
 // y = P^T phi + C x: rows of P^T (by triangle) and of C, one group of lanes
 // per triangle
+// quadrature-point stencil records (implicit interpolation)
+struct QpDevice {
+  const int32_t* origin;  // [3N] grid index of the stencil's first node
+  const void* local;      // [3N][3] t - s per axis (T)
+  const void* w;          // [3N] quadrature weights (T)
+  int order;
+};
+
+// y = P^T phi (+ C x) with the weights of P^T recomputed from the points
+template <typename T>
+void launch_interp_implicit(const GridShape& g, const QpDevice& qp, const CsrDevice& csr,
+                            const void* phi, const void* x, void* y, int nrhs, bool do_near,
+                            hipStream_t s);
+
 template <typename T>
 void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice& csr,
                         const void* phi, const void* x, void* y, int nrhs, bool do_interp,

@@ -257,15 +257,17 @@ __device__ __forceinline__ void run_stages(cx<T>* v, cx<T>* s, int es, int t, co
 
 // ---------------------------------------------------------------------------
 // FFT pass kernel.  Lines are addressed as (line >> lg_nli) * os + e * es +
-// (line & (2^lg_nli - 1)): column passes (y, z) have lg_nli = log2(Mx) so
-// that consecutive lines are consecutive x positions (coalesced rows of
-// TL elements); row passes (x) have lg_nli = 0, es = 1 and os = line pitch.
+// (line & (2^lg_nli - 1)) * p0: column passes (y, z) have lg_nli = log2(Mx)
+// and p0 = 1 so that consecutive lines are consecutive x positions (coalesced
+// rows of TL elements); row passes (x) have lg_nli = log2(rows per plane),
+// p0 = row pitch, os = plane pitch and es = 1.
 // MODE 0: forward, 1: inverse, 2: forward * spectrum then inverse.
 // ---------------------------------------------------------------------------
 struct PassArgs {
   int64_t nlines;
   int lg_nli;
   int64_t in_es, in_os, out_es, out_os;
+  int64_t in_p0, out_p0;  // stride of the inner line index (1 for column passes)
   int64_t in_bs, out_bs;  // per right-hand-side strides
   int Lin, Lout;          // leading elements read / written per line
   // spectral multiply (fused z pass): line (li, lo) = (kx, ky), element = kz
@@ -314,8 +316,8 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
   const bool valid = line < a.nlines;
   const int64_t mask = (int64_t(1) << a.lg_nli) - 1;
   const int64_t li = line & mask, lo = line >> a.lg_nli;
-  const cx<T>* src = in + lo * a.in_os + li;
-  cx<T>* dst = out + lo * a.out_os + li;
+  const cx<T>* src = in + lo * a.in_os + li * a.in_p0;
+  cx<T>* dst = out + lo * a.out_os + li * a.out_p0;
   cx<T>* sl = COL ? s + l : s + l * (L + 1);
   const int es = COL ? TL : 1;
   __syncthreads();
@@ -502,17 +504,21 @@ bool fft_variant_ok(bool dbl, int L, bool col, int v) {
   return dbl ? fft_shape_ok<double>(L, col, v) : fft_shape_ok<float>(L, col, v);
 }
 
-// row (x) pass over nlines contiguous lines
+// row (x) pass over nplanes x rows lines: line (z, y) starts at
+// z * ps + y * ls
 template <typename T>
-void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_t nlines,
-              int64_t in_ls, int64_t out_ls, int64_t in_bs, int64_t out_bs, int Lin, int Lout,
-              int nrhs, hipStream_t s, int variant = 0) {
+void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_t nplanes,
+              int rows, int64_t in_ls, int64_t out_ls, int64_t in_ps, int64_t out_ps,
+              int64_t in_bs, int64_t out_bs, int Lin, int Lout, int nrhs, hipStream_t s,
+              int variant = 0) {
   PassArgs a{};
-  a.nlines = nlines;
-  a.lg_nli = 0;
+  a.nlines = nplanes * rows;
+  a.lg_nli = ilog2(rows);
   a.in_es = a.out_es = 1;
-  a.in_os = in_ls;
-  a.out_os = out_ls;
+  a.in_os = in_ps;
+  a.out_os = out_ps;
+  a.in_p0 = in_ls;
+  a.out_p0 = out_ls;
   a.in_bs = in_bs;
   a.out_bs = out_bs;
   a.Lin = Lin;
@@ -522,14 +528,21 @@ void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_
 
 // ---------------------------------------------------------------------------
 // convolution phi = H q: pruned forward FFT, spectral multiply, pruned inverse
-// work layout per right-hand side (6 Ng complex): B = [Nz][My][Mx] (4 Ng)
-// followed by A = [Nz][Ny][Mx] (2 Ng).
+// work layout per right-hand side: B = [Nz][My][Mx] (4 Ng) followed by
+// A = [Nz][Ny][Mx] (2 Ng), each z plane padded by the layout's pad so that
+// the z lines (one element per plane) do not all fall on the same memory
+// channel when the plane size is a large power of two.
 // ---------------------------------------------------------------------------
+int64_t work_elems(const GridShape& g, int layout, size_t elem_bytes) {
+  const int64_t pad = kLayoutPadBytes[layout] / int64_t(elem_bytes);
+  return int64_t(g.N[2]) * (int64_t(g.M[1]) * g.M[0] + pad + int64_t(g.N[1]) * g.M[0] + pad);
+}
+
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
                      hipEvent_t* between, const int* sched) {
-  static const int kDefault[5] = {0, 0, 0, 0, 0};
+  static const int kDefault[kSchedLen] = {0, 0, 0, 0, 0, 0, 0};
   if (!sched) sched = kDefault;
   auto mark = [&](int i) {
     if (between) AIM_HIP(hipEventRecord(between[i], s));
@@ -537,8 +550,11 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
   const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
   const int64_t Ng = g.Ng;
+  const int64_t pad = kLayoutPadBytes[sched[5]] / int64_t(sizeof(cx<T>));
+  const int64_t PB = int64_t(My) * Mx + pad, PA = int64_t(Ny) * Mx + pad;  // plane pitches
+  const int64_t W = work_elems(g, sched[5], sizeof(cx<T>));                 // per right-hand side
   cx<T>* B = static_cast<cx<T>*>(work);
-  cx<T>* A = B + 4 * Ng;
+  cx<T>* A = B + int64_t(Nz) * PB;
   auto col_args = [&](int64_t nlines, int64_t in_es, int64_t in_os, int64_t out_es,
                       int64_t out_os, int Lin, int Lout) {
     PassArgs a{};
@@ -548,24 +564,25 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     a.in_os = in_os;
     a.out_es = out_es;
     a.out_os = out_os;
-    a.in_bs = a.out_bs = 6 * Ng;
+    a.in_p0 = a.out_p0 = 1;
+    a.in_bs = a.out_bs = W;
     a.Lin = Lin;
     a.Lout = Lout;
     return a;
   };
   // x forward: rows (y, z) of q, Nx -> Mx, into A [Nz][Ny][Mx]
-  row_pass<T>(Mx, false, q, A, tw[0], int64_t(Ny) * Nz, Nx, Mx, Ng, 6 * Ng, Nx, Mx, nrhs, s,
-              sched[0]);
+  row_pass<T>(Mx, false, q, A, tw[0], Nz, Ny, Nx, Mx, int64_t(Ny) * Nx, PA, Ng, W, Nx, Mx, nrhs,
+              s, sched[0]);
   mark(0);
   // y forward: A [Nz][Ny][Mx] -> B [Nz][My][Mx]
   {
-    const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, int64_t(Ny) * Mx, Mx, int64_t(My) * Mx, Ny, My);
+    const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, PA, Mx, PB, Ny, My);
     fft_pass<T>(My, true, 0, A, B, tw[1], a, nrhs, s, sched[1]);
   }
   mark(1);
   // z forward * spectrum * z inverse, in place on B, keeping z < Nz
   {
-    PassArgs a = col_args(int64_t(Mx) * My, int64_t(My) * Mx, Mx, int64_t(My) * Mx, Mx, Nz, Nz);
+    PassArgs a = col_args(int64_t(Mx) * My, PB, Mx, PB, Mx, Nz, Nz);
     a.spec = spec;
     a.spec_fs = g.Nfold;
     a.rhs_freq = rhs_freq;
@@ -580,13 +597,13 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
   mark(2);
   // y inverse: B [Nz][My][Mx] -> A [Nz][Ny][Mx]
   {
-    const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, int64_t(My) * Mx, Mx, int64_t(Ny) * Mx, My, Ny);
+    const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, PB, Mx, PA, My, Ny);
     fft_pass<T>(My, true, 1, B, A, tw[1], a, nrhs, s, sched[3]);
   }
   mark(3);
   // x inverse: rows of A (Mx) -> phi (Nx)
-  row_pass<T>(Mx, true, A, phi, tw[0], int64_t(Ny) * Nz, Mx, Nx, 6 * Ng, Ng, Mx, Nx, nrhs, s,
-              sched[4]);
+  row_pass<T>(Mx, true, A, phi, tw[0], Nz, Ny, Mx, Nx, PA, int64_t(Ny) * Nx, W, Ng, Mx, Nx, nrhs,
+              s, sched[4]);
 }
 
 template void launch_convolve<double>(const GridShape&, const void*, void*, void*, const void*,
@@ -663,11 +680,13 @@ void launch_spectrum(const GridShape& g, double k, double h, void* full_work, vo
   hipLaunchKernelGGL(green_sample_kernel, dim3(4096), dim3(256), 0, s, F, Nx, Ny, Nz, k, h);
   AIM_HIP(hipGetLastError());
   const int64_t Np = int64_t(Mx) * My * Mz;
-  row_pass<double>(Mx, false, F, F, tw64[0], int64_t(My) * Mz, Mx, Mx, 0, 0, Mx, Mx, 1, s);
+  row_pass<double>(Mx, false, F, F, tw64[0], Mz, My, Mx, Mx, int64_t(My) * Mx,
+                   int64_t(My) * Mx, 0, 0, Mx, Mx, 1, s);
   {
     PassArgs a{};
     a.nlines = int64_t(Mx) * Mz;
     a.lg_nli = ilog2(Mx);
+    a.in_p0 = a.out_p0 = 1;
     a.in_es = a.out_es = Mx;
     a.in_os = a.out_os = int64_t(My) * Mx;
     a.Lin = a.Lout = My;
@@ -677,6 +696,7 @@ void launch_spectrum(const GridShape& g, double k, double h, void* full_work, vo
     PassArgs a{};
     a.nlines = int64_t(Mx) * My;
     a.lg_nli = ilog2(Mx);
+    a.in_p0 = a.out_p0 = 1;
     a.in_es = a.out_es = int64_t(My) * Mx;
     a.in_os = a.out_os = Mx;
     a.Lin = a.Lout = Mz;
@@ -849,6 +869,118 @@ void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice
 #undef AIM_IN_LAUNCH
   AIM_HIP(hipGetLastError());
 }
+
+// ---------------------------------------------------------------------------
+// interpolation without the assembled P^T: y_i = sum over the triangle's three
+// quadrature points q and their (n+1)^3 stencil nodes of
+// w_q (Lx Ly Lz)(node) phi(node), with the tensor Lagrange weights recomputed
+// from the stored local coordinates (36 bytes per point instead of ~12 bytes
+// per merged non-zero), plus the near-field rows of C.  Order 3: 16 lanes per
+// triangle, lane = (ix, iy), looping over q and iz; order 2: 32 lanes, lane =
+// (q, ix, iy), looping over iz.  Blocks are dealt to the XCDs in contiguous
+// runs of triangles, so the phi bricks a run gathers stay in one L2.
+// ---------------------------------------------------------------------------
+template <typename T, int ORDER>
+__device__ __forceinline__ T lagrange_at(T u, int a) {
+  T w = T(1);
+#pragma unroll
+  for (int b = 0; b <= ORDER; ++b)
+    if (b != a) w = w * (u - T(b)) / T(a - b);
+  return w;
+}
+
+template <typename T, int ORDER, bool NEARC>
+__global__ __launch_bounds__(256) void interp_implicit_kernel(
+    const cx<T>* __restrict__ phi, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+    const int32_t* __restrict__ qorigin, const T* __restrict__ qlocal, const T* __restrict__ qw,
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const T* __restrict__ val, int64_t n, int Nx, int Ny, int64_t Ng) {
+  constexpr int S = ORDER + 1, PER = S * S;
+  constexpr bool QLANES = 3 * PER <= 32;  // one lane per (point, ix, iy)
+  constexpr int LPR = QLANES ? 32 : 16;
+  static_assert(QLANES || PER == 16, "order 3 uses 16 lanes per triangle");
+  const int nb = int(gridDim.x), b = int(blockIdx.x);
+  const int lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int sub = threadIdx.x % LPR;
+  const int64_t i = (int64_t(lb) * blockDim.x + threadIdx.x) / LPR;
+  const int rhs = blockIdx.y;
+  T ar = T(0), ai = T(0);
+  if (i < n) {
+    const cx<T>* ph = phi + rhs * Ng;
+    const int64_t plane = int64_t(Nx) * Ny;
+    auto point = [&](int q, int ix, int iy) {
+      const int64_t p = 3 * i + q;
+      const T* u = qlocal + 3 * p;
+      const T wq = qw[p];
+      const T lxy = lagrange_at<T, ORDER>(u[0], ix) * lagrange_at<T, ORDER>(u[1], iy);
+      const int64_t base = int64_t(qorigin[p]) + int64_t(iy) * Nx + ix;
+#pragma unroll
+      for (int iz = 0; iz < S; ++iz) {
+        const T wgt = wq * (lxy * lagrange_at<T, ORDER>(u[2], iz));
+        const cx<T> v = ph[base + iz * plane];
+        ar += wgt * v.x;
+        ai += wgt * v.y;
+      }
+    };
+    if constexpr (QLANES) {
+      if (sub < 3 * PER) {
+        const int q = sub / PER, r = sub % PER;
+        point(q, r % S, r / S);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) point(q, sub % S, sub / S);
+    }
+    if constexpr (NEARC) {
+      const cx<T>* xr = x + rhs * n;
+      for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
+        const T v = val[k];
+        const cx<T> xv = xr[col[k]];
+        ar += v * xv.x;
+        ai += v * xv.y;
+      }
+    }
+  }
+  ar = group_sum<LPR>(ar);
+  ai = group_sum<LPR>(ai);
+  if (sub == 0 && i < n) y[rhs * n + i] = mkc<T>(ar, ai);
+}
+
+template <typename T>
+void launch_interp_implicit(const GridShape& g, const QpDevice& qp, const CsrDevice& csr,
+                            const void* phi, const void* x, void* y, int nrhs, bool do_near,
+                            hipStream_t s) {
+  const int64_t n = csr.n;
+  const int lpr = qp.order == 3 ? 16 : 32;
+  dim3 grid(unsigned((n * lpr + 255) / 256), unsigned(nrhs));
+  const cx<T>* ph = static_cast<const cx<T>*>(phi);
+  const cx<T>* xi = static_cast<const cx<T>*>(x);
+  cx<T>* yo = static_cast<cx<T>*>(y);
+  const T* lc = static_cast<const T*>(qp.local);
+  const T* w = static_cast<const T*>(qp.w);
+  const T* v = static_cast<const T*>(csr.val);
+#define AIM_II_LAUNCH(O, NR)                                                                    \
+  hipLaunchKernelGGL((interp_implicit_kernel<T, O, NR>), grid, dim3(256), 0, s, ph, xi, yo,    \
+                     qp.origin, lc, w, csr.rowptr, csr.col, v, n, g.N[0], g.N[1], g.Ng)
+  if (qp.order == 3) {
+    if (do_near) AIM_II_LAUNCH(3, true);
+    else AIM_II_LAUNCH(3, false);
+  } else if (qp.order == 2) {
+    if (do_near) AIM_II_LAUNCH(2, true);
+    else AIM_II_LAUNCH(2, false);
+  } else {
+    throw Error(AIM_ERR_STATE, "implicit interpolation is built for orders 2 and 3");
+  }
+#undef AIM_II_LAUNCH
+  AIM_HIP(hipGetLastError());
+}
+
+template void launch_interp_implicit<double>(const GridShape&, const QpDevice&, const CsrDevice&,
+                                             const void*, const void*, void*, int, bool,
+                                             hipStream_t);
+template void launch_interp_implicit<float>(const GridShape&, const QpDevice&, const CsrDevice&,
+                                            const void*, const void*, void*, int, bool,
+                                            hipStream_t);
 
 template void launch_interp_near<double>(const GridShape&, const CsrDevice&, const CsrDevice&,
                                          const void*, const void*, void*, int, bool, bool,

@@ -192,9 +192,28 @@ def test_full_size_box_array_sampled():
     p.close()
 
 
+@pytest.mark.parametrize("case", CASES)
+def test_implicit_interpolation_matches_oracle(case):
+    """Interpolation with the weights of P^T recomputed from the quadrature
+    points (schedule entry 6 = 1): stage and whole-matvec parity, both
+    precisions."""
+    w, o, p = _setup(case)
+    Nx, Ny, Nz = o.dims
+    g = I.complex_gaussian(Nx * Ny * Nz, 113, nrhs=2).reshape(2, Nz, Ny, Nx)
+    x = I.complex_gaussian(o.N, 114, nrhs=3)
+    ref_y = o.matvec(x, w.k[0])
+    for prec, dt, tol in (("c128", torch.complex128, FP64_TOL), ("c64", torch.complex64, FP32_TOL)):
+        p.set_schedule([0] * 6 + [1], prec=prec)
+        y = host(p.apply_stage("interpolate", dev(g, dt), prec=prec))
+        assert rel(y, o.interpolate(g)) <= (1e-14 if prec == "c128" else 1e-6)
+        assert rel(host(p.matvec(dev(x, dt), prec=prec)), ref_y) <= tol
+        p.set_schedule([0] * 7, prec=prec)
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_every_fft_launch_shape_matches_oracle(prec):
-    """Each launch shape of each FFT pass gives the oracle's result."""
+    """Each launch shape of each FFT pass, in every workspace layout, gives
+    the oracle's result."""
     w, o, p = _setup("boxes")
     dt = torch.complex128 if prec == "c128" else torch.complex64
     tol = FP64_TOL if prec == "c128" else FP32_TOL
@@ -202,21 +221,24 @@ def test_every_fft_launch_shape_matches_oracle(prec):
     ref = o.matvec(x, w.k[0])
     xd = dev(x, dt)
     tried = 0
-    for k in range(5):
-        for v in range(binding.FFT_SHAPES):
-            sched = [0] * 5
-            sched[k] = v
-            try:
-                p.set_schedule(sched, prec=prec)
-            except binding.AimError:
-                continue
-            tried += 1
-            assert rel(host(p.matvec(xd, prec=prec)), ref) <= tol, (k, v)
-    assert tried >= 16
+    for layout in range(binding.FFT_LAYOUTS):
+        for k in range(5):
+            for v in range(binding.FFT_SHAPES):
+                sched = [0] * 5 + [layout]
+                sched[k] = v
+                try:
+                    p.set_schedule(sched, prec=prec)
+                except binding.AimError:
+                    continue
+                tried += 1
+                assert rel(host(p.matvec(xd, prec=prec)), ref) <= tol, (k, v, layout)
+    assert tried >= 16 * binding.FFT_LAYOUTS
+    with pytest.raises(binding.AimError):
+        p.set_schedule([0] * 5 + [binding.FFT_LAYOUTS], prec=prec)
     res = p.autotune(prec=prec, nrhs=3, reps=3)
-    assert len(res["schedule"]) == 5 and all(t > 0 for t in res["pass_ms"])
+    assert len(res["schedule"]) == binding.SCHEDULE_LEN and all(t > 0 for t in res["pass_ms"])
     assert rel(host(p.matvec(xd, prec=prec)), ref) <= tol
-    p.set_schedule([0] * 5, prec=prec)
+    p.set_schedule([0] * 7, prec=prec)
 
 
 def test_captured_graph_replays_match_eager():
