@@ -270,8 +270,8 @@ aim_status aim_graph_destroy(aim_graph graph);  /* NULL is a no-op */
  * interpolation: for every workspace layout, times every available launch
  * shape (lines per workgroup x threads per line) of each pass over `reps`
  * runs with nrhs right-hand sides on hip_stream and keeps the layout with
- * the smallest sum of per-pass best times and those shapes; then times both
- * interpolation modes and keeps the faster.  The schedule is stored in the
+ * the smallest sum of per-pass best times and those shapes; then times whole
+ * matvecs in both interpolation modes and keeps the faster.  The schedule is stored in the
  * plan for this precision and returned in sched_out[AIM_SCHEDULE_LEN], the
  * chosen passes' average times (ms) in pass_ms_out[5] (either may be NULL).
  * Overwrites the plan's internal grid workspace; allocates and frees two

@@ -720,8 +720,9 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
       throw;
     }
     destroy();
-    // interpolation: assembled P^T against recomputed weights, with the near
-    // correction, on the grid workspace as phi
+    // interpolation: assembled P^T against recomputed weights, timed as whole
+    // matvecs (the mode also changes what the projection finds in cache)
+    for (int k = 0; k < 6; ++k) p->sched[pi][k] = pick[k];
     {
       const size_t vb = size_t(p->t.N) * cb * nrhs;
       void* xy = nullptr;
@@ -733,14 +734,8 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
         AIM_HIP(hipEventCreate(&e0));
         AIM_HIP(hipEventCreate(&e1));
         for (int mode = 0; mode < 2; ++mode) {
-          auto run = [&] {
-            if (dbl)
-              interp_near<double>(p, prec, grid, xy, static_cast<char*>(xy) + vb, nrhs, true,
-                                  true, s, mode);
-            else
-              interp_near<float>(p, prec, grid, xy, static_cast<char*>(xy) + vb, nrhs, true,
-                                 true, s, mode);
-          };
+          p->sched[pi][6] = mode;
+          auto run = [&] { matvec_any(p, prec, xy, static_cast<char*>(xy) + vb, nrhs, df, s); };
           run();  // warm-up
           AIM_HIP(hipEventRecord(e0, s));
           for (int r = 0; r < reps; ++r) run();

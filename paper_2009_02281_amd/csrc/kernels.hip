@@ -737,60 +737,79 @@ __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ 
                                                       const int32_t* __restrict__ col,
                                                       const T* __restrict__ val,
                                                       const int32_t* __restrict__ blk, int64_t n,
-                                                      int64_t Ng) {
+                                                      int64_t Ng, int nrhs, int rb) {
   __shared__ cx<T> prod[kProjNnz];
   __shared__ T red[2 * 256];
   const int tid = threadIdx.x;
-  const int rhs = blockIdx.y;
-  x += rhs * n;
-  q += rhs * Ng;
   const int r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
   const int k0 = rowptr[r0], k1 = rowptr[r1];
-  if (k1 - k0 > kProjNnz) {  // one long row: strided partial sums, block reduction
-    T ar = T(0), ai = T(0);
+  // rb right-hand sides per block: the block's rows of P are read from
+  // memory for the first and from cache for the others
+  const int rhs_end = min(nrhs, int(blockIdx.y + 1) * rb);
+  for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
+    const cx<T>* xr = x + rhs * n;
+    cx<T>* qr = q + rhs * Ng;
+    if (k1 - k0 > kProjNnz) {  // one long row: strided partial sums, block reduction
+      T ar = T(0), ai = T(0);
+      for (int k = k0 + tid; k < k1; k += 256) {
+        const T w = val[k];
+        const cx<T> xv = xr[col[k]];
+        ar += w * xv.x;
+        ai += w * xv.y;
+      }
+      red[tid] = ar;
+      red[256 + tid] = ai;
+      __syncthreads();
+      for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+          red[tid] += red[tid + o];
+          red[256 + tid] += red[256 + tid + o];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) qr[r0] = mkc<T>(red[0], red[256]);
+      __syncthreads();  // red is reused by the next right-hand side
+      continue;
+    }
+    // all non-zeros of the block at once (independent loads), then row sums
     for (int k = k0 + tid; k < k1; k += 256) {
       const T w = val[k];
-      const cx<T> xv = x[col[k]];
-      ar += w * xv.x;
-      ai += w * xv.y;
+      const cx<T> xv = xr[col[k]];
+      prod[k - k0] = mkc<T>(w * xv.x, w * xv.y);
     }
-    red[tid] = ar;
-    red[256 + tid] = ai;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) {
-        red[tid] += red[tid + o];
-        red[256 + tid] += red[256 + tid + o];
+    for (int r = r0 + tid; r < r1; r += 256) {
+      T ar = T(0), ai = T(0);
+      const int e = rowptr[r + 1] - k0;
+      for (int k = rowptr[r] - k0; k < e; ++k) {
+        ar += prod[k].x;
+        ai += prod[k].y;
       }
-      __syncthreads();
+      qr[r] = mkc<T>(ar, ai);
     }
-    if (tid == 0) q[r0] = mkc<T>(red[0], red[256]);
-    return;
+    __syncthreads();  // prod is reused by the next right-hand side
   }
-  // all non-zeros of the block at once (independent loads), then row sums
-  for (int k = k0 + tid; k < k1; k += 256) {
-    const T w = val[k];
-    const cx<T> xv = x[col[k]];
-    prod[k - k0] = mkc<T>(w * xv.x, w * xv.y);
-  }
-  __syncthreads();
-  for (int r = r0 + tid; r < r1; r += 256) {
-    T ar = T(0), ai = T(0);
-    const int e = rowptr[r + 1] - k0;
-    for (int k = rowptr[r] - k0; k < e; ++k) {
-      ar += prod[k].x;
-      ai += prod[k].y;
-    }
-    q[r] = mkc<T>(ar, ai);
-  }
+}
+
+// right-hand sides per block.  Sharing pays where one right-hand side's
+// matrix stream is large (it then comes from cache for the others); small
+// operators keep their tables in L2 anyway and need the parallelism, so
+// blocks serve several right-hand sides (up to 8) only when one right-hand
+// side alone fills at least 1024 workgroups.
+inline int rhs_per_block(int64_t blocks_per_rhs, int nrhs) {
+  if (blocks_per_rhs < 1024) return 1;
+  int rb = 1;
+  while (rb < 8 && 2 * rb <= nrhs) rb *= 2;
+  return rb;
 }
 
 template <typename T>
 void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, int nblk,
                     const void* x, int64_t n, void* q, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(project_kernel<T>, dim3(unsigned(nblk), unsigned(nrhs)), dim3(256), 0, s,
-                     static_cast<const cx<T>*>(x), static_cast<cx<T>*>(q), P.rowptr, P.col,
-                     static_cast<const T*>(P.val), blk, n, g.Ng);
+  const int rb = rhs_per_block(nblk, nrhs);
+  hipLaunchKernelGGL(project_kernel<T>, dim3(unsigned(nblk), unsigned((nrhs + rb - 1) / rb)),
+                     dim3(256), 0, s, static_cast<const cx<T>*>(x), static_cast<cx<T>*>(q),
+                     P.rowptr, P.col, static_cast<const T*>(P.val), blk, n, g.Ng, nrhs, rb);
   AIM_HIP(hipGetLastError());
 }
 
@@ -818,34 +837,37 @@ __global__ __launch_bounds__(256) void interp_near_kernel(
     const cx<T>* __restrict__ phi, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
     const int32_t* __restrict__ prow, const int32_t* __restrict__ pcol, const T* __restrict__ pval,
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const T* __restrict__ val, int64_t n, int64_t Ng) {
+    const T* __restrict__ val, int64_t n, int64_t Ng, int nrhs, int rb) {
   const int sub = threadIdx.x % LPR;
   const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
-  const int rhs = blockIdx.y;
-  T ar = T(0), ai = T(0);
-  if (i < n) {
-    if constexpr (INTERP) {
-      const cx<T>* ph = phi + rhs * Ng;
-      for (int k = prow[i] + sub; k < prow[i + 1]; k += LPR) {
-        const T w = pval[k];
-        const cx<T> v = ph[pcol[k]];
-        ar += w * v.x;
-        ai += w * v.y;
+  // rb right-hand sides per block; the rows are read from cache after the first
+  const int rhs_end = min(nrhs, int(blockIdx.y + 1) * rb);
+  for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
+    T ar = T(0), ai = T(0);
+    if (i < n) {
+      if constexpr (INTERP) {
+        const cx<T>* ph = phi + rhs * Ng;
+        for (int k = prow[i] + sub; k < prow[i + 1]; k += LPR) {
+          const T w = pval[k];
+          const cx<T> v = ph[pcol[k]];
+          ar += w * v.x;
+          ai += w * v.y;
+        }
+      }
+      if constexpr (NEARC) {
+        const cx<T>* xr = x + rhs * n;
+        for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
+          const T v = val[k];
+          const cx<T> xv = xr[col[k]];
+          ar += v * xv.x;
+          ai += v * xv.y;
+        }
       }
     }
-    if constexpr (NEARC) {
-      const cx<T>* xr = x + rhs * n;
-      for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
-        const T v = val[k];
-        const cx<T> xv = xr[col[k]];
-        ar += v * xv.x;
-        ai += v * xv.y;
-      }
-    }
+    ar = group_sum<LPR>(ar);
+    ai = group_sum<LPR>(ai);
+    if (sub == 0 && i < n) y[rhs * n + i] = mkc<T>(ar, ai);
   }
-  ar = group_sum<LPR>(ar);
-  ai = group_sum<LPR>(ai);
-  if (sub == 0 && i < n) y[rhs * n + i] = mkc<T>(ar, ai);
 }
 
 template <typename T>
@@ -854,7 +876,9 @@ void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice
                         bool do_near, hipStream_t s) {
   constexpr int LPR = 16;
   const int64_t n = csr.n;
-  dim3 grid(unsigned((n * LPR + 255) / 256), unsigned(nrhs));
+  const int64_t gx = (n * LPR + 255) / 256;
+  const int rb = rhs_per_block(gx, nrhs);
+  dim3 grid(unsigned(gx), unsigned((nrhs + rb - 1) / rb));
   const cx<T>* ph = static_cast<const cx<T>*>(phi);
   const cx<T>* xi = static_cast<const cx<T>*>(x);
   cx<T>* yo = static_cast<cx<T>*>(y);
@@ -862,7 +886,7 @@ void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice
   const T* v = static_cast<const T*>(csr.val);
 #define AIM_IN_LAUNCH(I, NR)                                                                  \
   hipLaunchKernelGGL((interp_near_kernel<T, LPR, I, NR>), grid, dim3(256), 0, s, ph, xi, yo,  \
-                     Pt.rowptr, Pt.col, pv, csr.rowptr, csr.col, v, n, g.Ng)
+                     Pt.rowptr, Pt.col, pv, csr.rowptr, csr.col, v, n, g.Ng, nrhs, rb)
   if (do_interp && do_near) AIM_IN_LAUNCH(true, true);
   else if (do_interp) AIM_IN_LAUNCH(true, false);
   else AIM_IN_LAUNCH(false, true);
@@ -876,9 +900,11 @@ void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice
 // w_q (Lx Ly Lz)(node) phi(node), with the tensor Lagrange weights recomputed
 // from the stored local coordinates (36 bytes per point instead of ~12 bytes
 // per merged non-zero), plus the near-field rows of C.  Order 3: 16 lanes per
-// triangle, lane = (ix, iy), looping over q and iz; order 2: 32 lanes, lane =
-// (q, ix, iy), looping over iz.  Blocks are dealt to the XCDs in contiguous
-// runs of triangles, so the phi bricks a run gathers stay in one L2.
+// triangle, lane = (ix, iy), covering the three points and iz; order 2: 32
+// lanes, lane = (q, ix, iy), covering iz.  A lane computes its weights and
+// grid offsets once and reuses them for every right-hand side of its block.
+// Blocks are dealt to the XCDs in contiguous runs of triangles, so the phi
+// bricks a run gathers stay in one L2.
 // ---------------------------------------------------------------------------
 template <typename T, int ORDER>
 __device__ __forceinline__ T lagrange_at(T u, int a) {
@@ -894,21 +920,27 @@ __global__ __launch_bounds__(256) void interp_implicit_kernel(
     const cx<T>* __restrict__ phi, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
     const int32_t* __restrict__ qorigin, const T* __restrict__ qlocal, const T* __restrict__ qw,
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const T* __restrict__ val, int64_t n, int Nx, int Ny, int64_t Ng) {
+    const T* __restrict__ val, int64_t n, int Nx, int Ny, int64_t Ng, int nrhs, int rb) {
   constexpr int S = ORDER + 1, PER = S * S;
   constexpr bool QLANES = 3 * PER <= 32;  // one lane per (point, ix, iy)
   constexpr int LPR = QLANES ? 32 : 16;
+  constexpr int NTERM = QLANES ? S : 3 * S;  // gathers per lane and right-hand side
   static_assert(QLANES || PER == 16, "order 3 uses 16 lanes per triangle");
   const int nb = int(gridDim.x), b = int(blockIdx.x);
   const int lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
   const int sub = threadIdx.x % LPR;
   const int64_t i = (int64_t(lb) * blockDim.x + threadIdx.x) / LPR;
-  const int rhs = blockIdx.y;
-  T ar = T(0), ai = T(0);
-  if (i < n) {
-    const cx<T>* ph = phi + rhs * Ng;
+  T wts[NTERM];
+  int64_t off[NTERM];
+#pragma unroll
+  for (int t = 0; t < NTERM; ++t) {
+    wts[t] = T(0);
+    off[t] = 0;
+  }
+  const bool active = i < n && (!QLANES || sub < 3 * PER);
+  if (active) {
     const int64_t plane = int64_t(Nx) * Ny;
-    auto point = [&](int q, int ix, int iy) {
+    auto point = [&](int q, int ix, int iy, int t0) {
       const int64_t p = 3 * i + q;
       const T* u = qlocal + 3 * p;
       const T wq = qw[p];
@@ -916,34 +948,45 @@ __global__ __launch_bounds__(256) void interp_implicit_kernel(
       const int64_t base = int64_t(qorigin[p]) + int64_t(iy) * Nx + ix;
 #pragma unroll
       for (int iz = 0; iz < S; ++iz) {
-        const T wgt = wq * (lxy * lagrange_at<T, ORDER>(u[2], iz));
-        const cx<T> v = ph[base + iz * plane];
-        ar += wgt * v.x;
-        ai += wgt * v.y;
+        wts[t0 + iz] = wq * (lxy * lagrange_at<T, ORDER>(u[2], iz));
+        off[t0 + iz] = base + iz * plane;
       }
     };
     if constexpr (QLANES) {
-      if (sub < 3 * PER) {
-        const int q = sub / PER, r = sub % PER;
-        point(q, r % S, r / S);
-      }
+      const int q = sub / PER, r = sub % PER;
+      point(q, r % S, r / S, 0);
     } else {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) point(q, sub % S, sub / S);
-    }
-    if constexpr (NEARC) {
-      const cx<T>* xr = x + rhs * n;
-      for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
-        const T v = val[k];
-        const cx<T> xv = xr[col[k]];
-        ar += v * xv.x;
-        ai += v * xv.y;
-      }
+      for (int q = 0; q < 3; ++q) point(q, sub % S, sub / S, q * S);
     }
   }
-  ar = group_sum<LPR>(ar);
-  ai = group_sum<LPR>(ai);
-  if (sub == 0 && i < n) y[rhs * n + i] = mkc<T>(ar, ai);
+  const int rhs_end = min(nrhs, int(blockIdx.y + 1) * rb);
+  for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
+    T ar = T(0), ai = T(0);
+    if (active) {
+      const cx<T>* ph = phi + rhs * Ng;
+#pragma unroll
+      for (int t = 0; t < NTERM; ++t) {
+        const cx<T> v = ph[off[t]];
+        ar += wts[t] * v.x;
+        ai += wts[t] * v.y;
+      }
+    }
+    if constexpr (NEARC) {
+      if (i < n) {
+        const cx<T>* xr = x + rhs * n;
+        for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
+          const T v = val[k];
+          const cx<T> xv = xr[col[k]];
+          ar += v * xv.x;
+          ai += v * xv.y;
+        }
+      }
+    }
+    ar = group_sum<LPR>(ar);
+    ai = group_sum<LPR>(ai);
+    if (sub == 0 && i < n) y[rhs * n + i] = mkc<T>(ar, ai);
+  }
 }
 
 template <typename T>
@@ -952,7 +995,9 @@ void launch_interp_implicit(const GridShape& g, const QpDevice& qp, const CsrDev
                             hipStream_t s) {
   const int64_t n = csr.n;
   const int lpr = qp.order == 3 ? 16 : 32;
-  dim3 grid(unsigned((n * lpr + 255) / 256), unsigned(nrhs));
+  const int64_t gx = (n * lpr + 255) / 256;
+  const int rb = rhs_per_block(gx, nrhs);
+  dim3 grid(unsigned(gx), unsigned((nrhs + rb - 1) / rb));
   const cx<T>* ph = static_cast<const cx<T>*>(phi);
   const cx<T>* xi = static_cast<const cx<T>*>(x);
   cx<T>* yo = static_cast<cx<T>*>(y);
@@ -961,7 +1006,8 @@ void launch_interp_implicit(const GridShape& g, const QpDevice& qp, const CsrDev
   const T* v = static_cast<const T*>(csr.val);
 #define AIM_II_LAUNCH(O, NR)                                                                    \
   hipLaunchKernelGGL((interp_implicit_kernel<T, O, NR>), grid, dim3(256), 0, s, ph, xi, yo,    \
-                     qp.origin, lc, w, csr.rowptr, csr.col, v, n, g.N[0], g.N[1], g.Ng)
+                     qp.origin, lc, w, csr.rowptr, csr.col, v, n, g.N[0], g.N[1], g.Ng, nrhs,  \
+                     rb)
   if (qp.order == 3) {
     if (do_near) AIM_II_LAUNCH(3, true);
     else AIM_II_LAUNCH(3, false);

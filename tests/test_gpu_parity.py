@@ -126,6 +126,27 @@ def test_matvec_frequency_batch():
     p.close()
 
 
+def test_many_right_hand_sides_at_many_wavenumbers():
+    """64 vectors at 8 wavenumbers, every vector against the oracle, in both
+    interpolation modes."""
+    w = I.sweep_small(nfreq=8, rhs_per_freq=8)
+    print("[gpu] 64 right-hand sides", flush=True)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     max_rhs=64)
+    freq = np.arange(64) % 8
+    x = I.complex_gaussian(o.N, 3101, nrhs=64)
+    refs = [o.matvec(x[r], w.k[freq[r]]) for r in range(64)]
+    for mode in (0, 1):
+        for prec, dt, tol in (("c128", torch.complex128, FP64_TOL),
+                              ("c64", torch.complex64, FP32_TOL)):
+            p.set_schedule([0] * 6 + [mode], prec=prec)
+            y = host(p.matvec(dev(x, dt), freq_idx=freq, prec=prec))
+            for r in range(64):
+                assert rel(y[r], refs[r]) <= tol, (mode, prec, r)
+    p.close()
+
+
 def test_projection_is_deterministic():
     w, o, p = _setup("boxes")
     x = dev(I.complex_gaussian(o.N, 105, nrhs=4))
@@ -166,6 +187,29 @@ def test_invalid_calls_raise():
     assert e.value.status == 1
     with pytest.raises(binding.AimError):
         p.matvec(x[:2], freq_idx=[0, 3])   # frequency index out of range
+
+
+def test_full_size_box_array_shared_blocks():
+    """The full-size box array with 8 right-hand sides: the projection and
+    interpolation workgroups each serve several right-hand sides (one right-
+    hand side alone fills thousands of workgroups).  Sampled rows of every
+    vector against the oracle, both precisions and interpolation modes."""
+    w = I.box_array_large()
+    print(f"[gpu] full-size box array, 8 right-hand sides", flush=True)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     max_rhs=8)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    x = I.complex_gaussian(o.N, 2101, nrhs=8)
+    rows = np.sort(np.random.default_rng(2102).choice(o.N, 16, replace=False))
+    refs = [o.matvec_rows(x[r], w.k[0], rows) for r in range(8)]
+    for mode in (0, 1):
+        for prec, dt, tol in (("c128", torch.complex128, FP64_TOL),
+                              ("c64", torch.complex64, FP32_TOL)):
+            p.set_schedule([0] * 6 + [mode], prec=prec)
+            y = host(p.matvec(dev(x, dt), prec=prec))
+            for r in range(8):
+                assert rel(y[r][rows], refs[r]) <= tol, (mode, prec, r)
+    p.close()
 
 
 def test_full_size_box_array_sampled():
