@@ -791,12 +791,21 @@ __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ 
   }
 }
 
-// right-hand sides per block.  Sharing pays where one right-hand side's
-// matrix stream is large (it then comes from cache for the others); small
-// operators keep their tables in L2 anyway and need the parallelism, so
-// blocks serve several right-hand sides (up to 8) only when one right-hand
-// side alone fills at least 1024 workgroups.
+// right-hand sides per workgroup: the largest power of two (at most 8, at
+// most nrhs) that still leaves 1024 workgroups in the launch, else 1.  Each
+// matrix entry is then loaded once and applied to that many vectors.
 inline int rhs_per_block(int64_t blocks_per_rhs, int nrhs) {
+  int rb = 1;
+  while (rb < 8 && 2 * rb <= nrhs && blocks_per_rhs * ((nrhs + 2 * rb - 1) / (2 * rb)) >= 1024)
+    rb *= 2;
+  return rb;
+}
+
+// the projection serves several right-hand sides per workgroup (its rows of
+// P then come from cache after the first) only on operators large enough that
+// one right-hand side already fills 1024 workgroups; on small ones the rows
+// are cache-resident anyway and the parallelism matters more
+inline int project_rhs_per_block(int64_t blocks_per_rhs, int nrhs) {
   if (blocks_per_rhs < 1024) return 1;
   int rb = 1;
   while (rb < 8 && 2 * rb <= nrhs) rb *= 2;
@@ -806,7 +815,7 @@ inline int rhs_per_block(int64_t blocks_per_rhs, int nrhs) {
 template <typename T>
 void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, int nblk,
                     const void* x, int64_t n, void* q, int nrhs, hipStream_t s) {
-  const int rb = rhs_per_block(nblk, nrhs);
+  const int rb = project_rhs_per_block(nblk, nrhs);
   hipLaunchKernelGGL(project_kernel<T>, dim3(unsigned(nblk), unsigned((nrhs + rb - 1) / rb)),
                      dim3(256), 0, s, static_cast<const cx<T>*>(x), static_cast<cx<T>*>(q),
                      P.rowptr, P.col, static_cast<const T*>(P.val), blk, n, g.Ng, nrhs, rb);
@@ -832,41 +841,52 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-template <typename T, int LPR, bool INTERP, bool NEARC>
+template <typename T, int LPR, bool INTERP, bool NEARC, int RB>
 __global__ __launch_bounds__(256) void interp_near_kernel(
     const cx<T>* __restrict__ phi, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
     const int32_t* __restrict__ prow, const int32_t* __restrict__ pcol, const T* __restrict__ pval,
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const T* __restrict__ val, int64_t n, int64_t Ng, int nrhs, int rb) {
+    const T* __restrict__ val, int64_t n, int64_t Ng, int nrhs) {
   const int sub = threadIdx.x % LPR;
   const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
-  // rb right-hand sides per block; the rows are read from cache after the first
-  const int rhs_end = min(nrhs, int(blockIdx.y + 1) * rb);
-  for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
-    T ar = T(0), ai = T(0);
-    if (i < n) {
-      if constexpr (INTERP) {
-        const cx<T>* ph = phi + rhs * Ng;
-        for (int k = prow[i] + sub; k < prow[i + 1]; k += LPR) {
-          const T w = pval[k];
-          const cx<T> v = ph[pcol[k]];
-          ar += w * v.x;
-          ai += w * v.y;
-        }
-      }
-      if constexpr (NEARC) {
-        const cx<T>* xr = x + rhs * n;
-        for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
-          const T v = val[k];
-          const cx<T> xv = xr[col[k]];
-          ar += v * xv.x;
-          ai += v * xv.y;
-        }
+  // RB right-hand sides per workgroup: each matrix entry is loaded once
+  const int rhs0 = int(blockIdx.y) * RB;
+  const int nr = min(RB, nrhs - rhs0);
+  T ar[RB], ai[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) ar[j] = ai[j] = T(0);
+  if (i < n) {
+    if constexpr (INTERP) {
+      for (int k = prow[i] + sub; k < prow[i + 1]; k += LPR) {
+        const T w = pval[k];
+        const int64_t c = pcol[k];
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+          if (j < nr) {
+            const cx<T> v = phi[(rhs0 + j) * Ng + c];
+            ar[j] += w * v.x;
+            ai[j] += w * v.y;
+          }
       }
     }
-    ar = group_sum<LPR>(ar);
-    ai = group_sum<LPR>(ai);
-    if (sub == 0 && i < n) y[rhs * n + i] = mkc<T>(ar, ai);
+    if constexpr (NEARC) {
+      for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
+        const T v = val[k];
+        const int64_t c = col[k];
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+          if (j < nr) {
+            const cx<T> xv = x[(rhs0 + j) * n + c];
+            ar[j] += v * xv.x;
+            ai[j] += v * xv.y;
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const T sr = group_sum<LPR>(ar[j]), si = group_sum<LPR>(ai[j]);
+    if (sub == 0 && i < n && j < nr) y[(rhs0 + j) * n + i] = mkc<T>(sr, si);
   }
 }
 
@@ -884,12 +904,20 @@ void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice
   cx<T>* yo = static_cast<cx<T>*>(y);
   const T* pv = static_cast<const T*>(Pt.val);
   const T* v = static_cast<const T*>(csr.val);
-#define AIM_IN_LAUNCH(I, NR)                                                                  \
-  hipLaunchKernelGGL((interp_near_kernel<T, LPR, I, NR>), grid, dim3(256), 0, s, ph, xi, yo,  \
-                     Pt.rowptr, Pt.col, pv, csr.rowptr, csr.col, v, n, g.Ng, nrhs, rb)
-  if (do_interp && do_near) AIM_IN_LAUNCH(true, true);
-  else if (do_interp) AIM_IN_LAUNCH(true, false);
-  else AIM_IN_LAUNCH(false, true);
+#define AIM_IN_LAUNCH(I, NR, R)                                                                  \
+  hipLaunchKernelGGL((interp_near_kernel<T, LPR, I, NR, R>), grid, dim3(256), 0, s, ph, xi, yo,  \
+                     Pt.rowptr, Pt.col, pv, csr.rowptr, csr.col, v, n, g.Ng, nrhs)
+#define AIM_IN_RB(I, NR)                         \
+  switch (rb) {                                  \
+    case 1: AIM_IN_LAUNCH(I, NR, 1); break;      \
+    case 2: AIM_IN_LAUNCH(I, NR, 2); break;      \
+    case 4: AIM_IN_LAUNCH(I, NR, 4); break;      \
+    default: AIM_IN_LAUNCH(I, NR, 8); break;     \
+  }
+  if (do_interp && do_near) AIM_IN_RB(true, true)
+  else if (do_interp) AIM_IN_RB(true, false)
+  else AIM_IN_RB(false, true)
+#undef AIM_IN_RB
 #undef AIM_IN_LAUNCH
   AIM_HIP(hipGetLastError());
 }
