@@ -334,10 +334,14 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
       const int e = t + i * NT + r * (L / R0);
       v[i * R0 + r] = (valid && e < a.Lin) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
     }
-  run_stages<T, L, NT, MODE == 1, SF, RMAX, 0>(v, sl, es, t, tw);
+  // fused z pass: the spectrum values this thread multiplies after its
+  // forward transform depend only on (kx, ky) and the element index, so they
+  // are loaded here, in flight together with the line itself
+  using Fw = Sched<L, true, RMAX>;
+  constexpr int RM = Fw::radix(Fw::NST - 1);
+  constexpr int NSP = MODE == 2 ? E : 1;
+  cx<T> spv[NSP];
   if constexpr (MODE == 2) {
-    using Fw = Sched<L, true, RMAX>;
-    constexpr int RM = Fw::radix(Fw::NST - 1);
     static_assert(RM == Sched<L, false, RMAX>::radix(0),
                   "the forward transform must end with the radix the inverse starts with");
     if (valid) {
@@ -354,8 +358,15 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
         for (int r = 0; r < RM; ++r) {
           const int e = t + i * NT + r * (L / RM);
           const int fz = e <= a.Nz ? e : a.Mz - e;
-          v[i * RM + r] = cmul(v[i * RM + r], sp[fz * zst]);
+          spv[i * RM + r] = sp[fz * zst];
         }
+    }
+  }
+  run_stages<T, L, NT, MODE == 1, SF, RMAX, 0>(v, sl, es, t, tw);
+  if constexpr (MODE == 2) {
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = cmul(v[k], spv[k]);
     }
     run_stages<T, L, NT, true, false, RMAX, 0>(v, sl, es, t, tw);
   }
