@@ -10,9 +10,11 @@
 //   out = a7 W^T + b (1x1x1, C->2)
 // with 3x3x3 "same" convolutions, 2x2x2 average pooling and nearest
 // upsampling.  Weights and activations are bfloat16; the convolutions are
-// implicit GEMMs on the 16x16x16 bf16 MFMA with fp32 accumulation (the data
-// gradient is the same GEMM with flipped, transposed weights); weight
-// gradients are fp32 reductions; master weights and Adam moments are fp32.
+// LDS-tiled implicit GEMMs on the 16x16x32 bf16 MFMA with fp32 accumulation
+// (the data gradient is the same GEMM with flipped, transposed weights); the
+// weight gradients of the 3x3x3 layers are per-tap GEMMs over positions on the
+// same MFMA, those of the 2-channel input and output layers fp32 reductions;
+// master weights and Adam moments are fp32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +24,7 @@
 #include <memory>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "aim_internal.h"
@@ -46,67 +49,109 @@ __device__ __forceinline__ void pos_xyz(int64_t p, int W, int H, int& x, int& y,
 }
 
 // ---------------------------------------------------------------------------
-// 3x3x3 convolution as implicit GEMM on MFMA: Y[p][co] = sum_{t,ci}
-// X[p + d(t)][ci] Wt[co][t][ci] (+ bias, relu).  A wavefront computes 16
-// consecutive positions for all output channels; per tap and 16-channel
-// chunk, lane l loads four bf16 of position l%16 (B operand) and four of the
-// weight row l%16 of each 16-channel output tile (A operand); the result
-// tile holds channels 4*(l/16)..+3 of position l%16.
+// 3x3x3 convolution, LDS-tiled: a workgroup computes a 16 x BY x 4 brick of
+// output positions for all output channels.  It stages the 18 x (BY+2) x 6
+// input tile (brick plus one-point halo, all CIN channels, bf16) in LDS once,
+// so every input element feeds 27 taps from LDS.  Wave w takes the brick's z
+// slice w: BY groups of 16 positions (its y rows) against TILES tiles of 16
+// output channels, so each weight load feeds BY MFMAs (BY = 2: taller
+// bricks measured slower, the larger tile costing occupancy).  K is the flattened (tap, channel) index, 27 * CIN,
+// walked in chunks of 32 on the 16x16x32 bf16 MFMA: lane l supplies
+// A[co = l % 16][k = 8 (l / 16) + i] (weights, 16 bytes from global memory)
+// and B[k][position l % 16] (16 bytes from LDS) and receives
+// C[co = 4 (l / 16) + i][position l % 16].  The tail chunk is zero-padded.
 // ---------------------------------------------------------------------------
-template <int TILES, bool OUT_BF16>
-__global__ __launch_bounds__(256) void conv3_mfma_kernel(const uint16_t* __restrict__ X, int ldx,
-                                                         int ox, int Cin, int D, int H, int W,
-                                                         const uint16_t* __restrict__ Wt,
-                                                         const float* __restrict__ bias, void* Y,
-                                                         int ldy, int oy, int relu) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t P = int64_t(D) * H * W;
-  const int64_t p0 = (int64_t(blockIdx.x) * 4 + wave) * 16;
-  if (p0 >= P) return;  // whole wavefront
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kBX = 16, kBZ = 4;                             // output brick (x, z)
+constexpr int kTX = kBX + 2, kTZ = kBZ + 2;                  // input tile (x, z)
+constexpr int conv_by(int) { return 2; }                       // output brick (y)
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
+template <int CIN, int TILES, bool OUT_BF16, int kBY = conv_by(CIN)>
+__global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restrict__ X, int ldx,
+                                                        int ox, int D, int H, int W,
+                                                        const uint16_t* __restrict__ Wt,
+                                                        const float* __restrict__ bias, void* Y,
+                                                        int ldy, int oy, int relu) {
+  constexpr int C8 = CIN / 8;
+  constexpr int kTY = kBY + 2, kTilePos = kTX * kTY * kTZ;
+  static_assert(CIN % 8 == 0, "channels in groups of 8");
+  __shared__ uint4 tile[kTilePos * C8];  // [position][channel / 8], 8 bf16 per entry
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nbx = (W + kBX - 1) / kBX, nby = (H + kBY - 1) / kBY;
+  int b = int(blockIdx.x);
+  const int bx = b % nbx;
+  b /= nbx;
+  const int by = b % nby, bz = b / nby;
+  const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+  for (int u = tid; u < kTilePos * C8; u += 256) {
+    const int c8 = u % C8, pos = u / C8;
+    const int gx = x0 + pos % kTX - 1, gy = y0 + (pos / kTX) % kTY - 1, gz = z0 + pos / (kTX * kTY) - 1;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gx >= 0 && gy >= 0 && gz >= 0 && gx < W && gy < H && gz < D)
+      v = *reinterpret_cast<const uint4*>(X + ((int64_t(gz) * H + gy) * W + gx) * ldx + ox + 8 * c8);
+    tile[u] = v;
+  }
+  __syncthreads();
   const int col = lane & 15, kg = lane >> 4;
-  const int64_t p = p0 + col;
-  const bool pv = p < P;
-  int x = 0, y = 0, z = 0;
-  if (pv) pos_xyz(p, W, H, x, y, z);
-  f32x4 acc[TILES];
+  constexpr int K = 27 * CIN, NCH = (K + 31) / 32;
+  f32x4 acc[kBY][TILES];
 #pragma unroll
-  for (int t = 0; t < TILES; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int K = 27 * Cin;
-  for (int tap = 0; tap < 27; ++tap) {
-    const int nx = x + tap % 3 - 1, ny = y + (tap / 3) % 3 - 1, nz = z + tap / 9 - 1;
-    const bool inb = pv && nx >= 0 && ny >= 0 && nz >= 0 && nx < W && ny < H && nz < D;
-    const uint16_t* xp = X + ((int64_t(nz) * H + ny) * W + nx) * ldx + ox + 4 * kg;
-    const uint16_t* wp = Wt + int64_t(col) * K + tap * Cin + 4 * kg;
-    for (int c0 = 0; c0 < Cin; c0 += 16) {
-      bf16x4 b = bf16x4{0, 0, 0, 0};
-      if (inb) b = *reinterpret_cast<const bf16x4*>(xp + c0);
+  for (int g = 0; g < kBY; ++g)
 #pragma unroll
-      for (int t = 0; t < TILES; ++t) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4*>(wp + int64_t(t) * 16 * K + c0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-      }
+    for (int t = 0; t < TILES; ++t) acc[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero = as_bf16x8(make_uint4(0u, 0u, 0u, 0u));
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * 32 + 8 * kg;
+    const bool kv = k < K;
+    const int tap = kv ? k / CIN : 0, ci = kv ? k % CIN : 0;
+    const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+    bf16x8 bv[kBY];
+#pragma unroll
+    for (int g = 0; g < kBY; ++g) {
+      const int pos = ((wave + dz) * kTY + g + dy) * kTX + col + dx;
+      bv[g] = kv ? as_bf16x8(tile[pos * C8 + ci / 8]) : zero;
+    }
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+      const bf16x8 av =
+          kv ? as_bf16x8(*reinterpret_cast<const uint4*>(Wt + int64_t(t * 16 + col) * K + k)) : zero;
+#pragma unroll
+      for (int g = 0; g < kBY; ++g)
+        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[g], acc[g][t], 0, 0, 0);
     }
   }
-  if (!pv) return;
+  const int x = x0 + col, z = z0 + wave;
 #pragma unroll
-  for (int t = 0; t < TILES; ++t) {
-    const int co = t * 16 + 4 * kg;
-    float v[4];
+  for (int g = 0; g < kBY; ++g) {
+    const int y = y0 + g;
+    if (x >= W || y >= H || z >= D) continue;
+    const int64_t p = (int64_t(z) * H + y) * W + x;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      v[i] = acc[t][i] + (bias ? bias[co + i] : 0.f);
-      if (relu) v[i] = fmaxf(v[i], 0.f);
-    }
-    if constexpr (OUT_BF16) {
-      ushort4 o;
-      o.x = f2bf(v[0]);
-      o.y = f2bf(v[1]);
-      o.z = f2bf(v[2]);
-      o.w = f2bf(v[3]);
-      *reinterpret_cast<ushort4*>(static_cast<uint16_t*>(Y) + p * ldy + oy + co) = o;
-    } else {
-      *reinterpret_cast<float4*>(static_cast<float*>(Y) + p * ldy + oy + co) =
-          make_float4(v[0], v[1], v[2], v[3]);
+    for (int t = 0; t < TILES; ++t) {
+      const int co = t * 16 + 4 * kg;
+      float v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        v[i] = acc[g][t][i] + (bias ? bias[co + i] : 0.f);
+        if (relu) v[i] = fmaxf(v[i], 0.f);
+      }
+      if constexpr (OUT_BF16) {
+        ushort4 o;
+        o.x = f2bf(v[0]);
+        o.y = f2bf(v[1]);
+        o.z = f2bf(v[2]);
+        o.w = f2bf(v[3]);
+        *reinterpret_cast<ushort4*>(static_cast<uint16_t*>(Y) + p * ldy + oy + co) = o;
+      } else {
+        *reinterpret_cast<float4*>(static_cast<float*>(Y) + p * ldy + oy + co) =
+            make_float4(v[0], v[1], v[2], v[3]);
+      }
     }
   }
 }
@@ -226,6 +271,94 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(
   }
 }
 
+// weight gradients on MFMA for bf16 X and dY with 16-multiple channels: per
+// tap, dW_t[co][ci] = sum_p dY[p][co] X[p + d(t)][ci] is a GEMM over
+// positions.  Steps of 64 positions are staged transposed in LDS
+// ([channel][position], bf16), so lane l reads its 8 consecutive positions
+// (k = 8 (l / 16) + i) of row co = l % 16 (A) and of column ci = l % 16 (B)
+// as one 16-byte word; the 16x16 output tiles (co tile, ci tile) are dealt
+// to the four waves.  Partial sums per chunk of positions, as above.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void wgrad_mfma_kernel(
+    const uint16_t* __restrict__ X, int ldx, int ox, const uint16_t* __restrict__ dY, int ldy,
+    int oy, int D, int H, int W, int64_t chunk, float* __restrict__ part) {
+  constexpr int KS = 64;                             // positions per step
+  constexpr int NTC = COUT / 16, NTI = CIN / 16, NT = NTC * NTI, NTW = (NT + 3) / 4;
+  __shared__ __attribute__((aligned(16))) uint16_t syT[COUT * KS];  // 16-byte reads below
+  __shared__ __attribute__((aligned(16))) uint16_t sxT[CIN * KS];
+  const int tap = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kg = lane >> 4;
+  const int64_t P = int64_t(D) * H * W;
+  const int64_t pb = int64_t(blockIdx.x) * chunk, pe = min(P, pb + chunk);
+  const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+  f32x4 acc[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  __shared__ int64_t src[KS];  // shifted source position of each staged position, or -1
+  for (int64_t s0 = pb; s0 < pe; s0 += KS) {
+    const int cnt = int(min(int64_t(KS), pe - s0));
+    if (tid < KS) {
+      int64_t v = -1;
+      if (tid < cnt) {
+        int x, y, z;
+        pos_xyz(s0 + tid, W, H, x, y, z);
+        const int nx = x + dx, ny = y + dy, nz = z + dz;
+        if (nx >= 0 && ny >= 0 && nz >= 0 && nx < W && ny < H && nz < D)
+          v = (int64_t(nz) * H + ny) * W + nx;
+      }
+      src[tid] = v;
+    }
+    // dY and the shifted X, 8 channels (16 bytes) per load, transposed into LDS
+    for (int i = tid; i < KS * (COUT / 8); i += 256) {
+      const int pp = i / (COUT / 8), c8 = i % (COUT / 8);
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (pp < cnt) v = *reinterpret_cast<const uint4*>(dY + (s0 + pp) * ldy + oy + 8 * c8);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) syT[(8 * c8 + j) * KS + pp] = e[j];
+    }
+    __syncthreads();
+    for (int i = tid; i < KS * (CIN / 8); i += 256) {
+      const int pp = i / (CIN / 8), c8 = i % (CIN / 8);
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      const int64_t q = src[pp];
+      if (q >= 0) v = *reinterpret_cast<const uint4*>(X + q * ldx + ox + 8 * c8);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sxT[(8 * c8 + j) * KS + pp] = e[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+      const int tt = wave + 4 * j;
+      if (tt < NT) {
+        const int tc = tt / NTI, ti = tt % NTI;
+#pragma unroll
+        for (int kc = 0; kc < KS / 32; ++kc) {
+          const int k = kc * 32 + 8 * kg;
+          const bf16x8 av = as_bf16x8(*reinterpret_cast<const uint4*>(&syT[(tc * 16 + col) * KS + k]));
+          const bf16x8 bv = as_bf16x8(*reinterpret_cast<const uint4*>(&sxT[(ti * 16 + col) * KS + k]));
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) {
+    const int tt = wave + 4 * j;
+    if (tt < NT) {
+      const int tc = tt / NTI, ti = tt % NTI;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = tc * 16 + 4 * kg + i, ci = ti * 16 + col;
+        part[(int64_t(blockIdx.x) * 27 * COUT + int64_t(co) * 27 + tap) * CIN + ci] = acc[j][i];
+      }
+    }
+  }
+}
+
 // grad[i] (+)= sum_c part[c][i]
 __global__ void reduce_chunks_kernel(const float* __restrict__ part, int nchunk, int64_t n,
                                      float* __restrict__ grad) {
@@ -237,21 +370,27 @@ __global__ void reduce_chunks_kernel(const float* __restrict__ part, int nchunk,
   }
 }
 
-// bias gradient: db[c] += sum_p dY[p][c]
+// bias gradient, first stage: part[chunk][c] = sum over the chunk's positions
+// of dY[p][c]; thread t covers channel t % C and every (256 / C)-th position
 template <typename TY>
-__global__ __launch_bounds__(256) void bgrad_kernel(const TY* __restrict__ dY, int ldy, int oy,
-                                                    int C, int64_t P, float* __restrict__ db) {
+__global__ __launch_bounds__(256) void bgrad_partial_kernel(const TY* __restrict__ dY, int ldy,
+                                                            int oy, int C, int64_t P,
+                                                            int64_t chunk,
+                                                            float* __restrict__ part) {
   __shared__ float red[256];
-  const int c = blockIdx.x;
+  const int R = 256 / C;
+  const int t = threadIdx.x, c = t % C, r = t / C;
+  const int64_t pb = int64_t(blockIdx.x) * chunk, pe = min(P, pb + chunk);
   float s = 0.f;
-  for (int64_t p = threadIdx.x; p < P; p += 256) s += ldv(dY, p * ldy + oy + c);
-  red[threadIdx.x] = s;
+  if (r < R)
+    for (int64_t p = pb + r; p < pe; p += R) s += ldv(dY, p * ldy + oy + c);
+  red[t] = s;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  if (t < C) {
+    float a = 0.f;
+    for (int q = 0; q < R; ++q) a += red[q * C + t];
+    part[int64_t(blockIdx.x) * C + t] = a;
   }
-  if (threadIdx.x == 0) db[c] += red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -571,26 +710,39 @@ struct aim_unet_s {
   void conv(const uint16_t* X, int ldx, int ox, int cin, int D, int H, int W, const uint16_t* Wt,
             const float* bias, void* Y, int ldy, int oy, int cout, bool out_bf16, bool relu,
             hipStream_t s) {
-    const int64_t P = int64_t(D) * H * W;
-    dim3 grid(unsigned((P + 63) / 64));
+    AIM_REQUIRE(ox % 8 == 0 && ldx % 8 == 0 && oy % 4 == 0 && cout % 16 == 0, AIM_ERR_STATE,
+                "channel blocks must be aligned");
+    const int by = conv_by(cin);
+    const unsigned nb = unsigned(((W + kBX - 1) / kBX) * ((H + by - 1) / by) *
+                                 ((D + kBZ - 1) / kBZ));
     const int tiles = cout / 16;
-#define AIM_CONV(T)                                                                           \
-  if (out_bf16)                                                                               \
-    hipLaunchKernelGGL((conv3_mfma_kernel<T, true>), grid, dim3(256), 0, s, X, ldx, ox, cin, D, \
-                       H, W, Wt, bias, Y, ldy, oy, relu ? 1 : 0);                              \
-  else                                                                                        \
-    hipLaunchKernelGGL((conv3_mfma_kernel<T, false>), grid, dim3(256), 0, s, X, ldx, ox, cin, D, \
-                       H, W, Wt, bias, Y, ldy, oy, relu ? 1 : 0);
-    switch (tiles) {
-      case 1: AIM_CONV(1) break;
-      case 2: AIM_CONV(2) break;
-      case 3: AIM_CONV(3) break;
-      case 4: AIM_CONV(4) break;
-      case 6: AIM_CONV(6) break;
-      default: throw aim::Error(AIM_ERR_STATE, "unsupported channel count");
-    }
+    const int rl = relu ? 1 : 0;
+#define AIM_CONV(CI, T)                                                                          \
+  if (cin == CI && tiles == T) {                                                                \
+    if (out_bf16)                                                                               \
+      hipLaunchKernelGGL((conv3_lds_kernel<CI, T, true>), dim3(nb), dim3(256), 0, s, X, ldx, ox, \
+                         D, H, W, Wt, bias, Y, ldy, oy, rl);                                     \
+    else                                                                                        \
+      hipLaunchKernelGGL((conv3_lds_kernel<CI, T, false>), dim3(nb), dim3(256), 0, s, X, ldx,   \
+                         ox, D, H, W, Wt, bias, Y, ldy, oy, rl);                                 \
+    AIM_HIP(hipGetLastError());                                                                 \
+    return;                                                                                     \
+  }
+    // the (input channels, output tiles) pairs of the network's forward and
+    // data-gradient convolutions
+    AIM_CONV(16, 1)
+    AIM_CONV(16, 2)
+    AIM_CONV(16, 3)
+    AIM_CONV(32, 1)
+    AIM_CONV(32, 2)
+    AIM_CONV(32, 4)
+    AIM_CONV(32, 6)
+    AIM_CONV(48, 1)
+    AIM_CONV(64, 2)
+    AIM_CONV(64, 4)
+    AIM_CONV(96, 2)
 #undef AIM_CONV
-    AIM_HIP(hipGetLastError());
+    throw aim::Error(AIM_ERR_STATE, "unsupported channel count");
   }
 
   template <typename TX, typename TY>
@@ -598,20 +750,55 @@ struct aim_unet_s {
              int H, int W, const Layer& L, hipStream_t s) {
     const int64_t P = int64_t(D) * H * W;
     AIM_REQUIRE(int64_t(cout) * cin <= 256 * 24, AIM_ERR_STATE, "layer too wide for wgrad");
-    int64_t nchunk = std::min<int64_t>(64, (P + kWgPos - 1) / kWgPos);
+    // chunks of positions for the partial sums: as many as the partial
+    // buffer holds (at most 1024), each at least 256 positions long
+    const int64_t entries = int64_t(cout) * L.taps * cin;
+    int64_t nchunk = std::min<int64_t>(std::min<int64_t>(1024, acts.part_n / entries),
+                                       (P + 255) / 256);
+    nchunk = std::max<int64_t>(1, nchunk);
     const int64_t chunk = (P + nchunk - 1) / nchunk;
     nchunk = (P + chunk - 1) / chunk;
-    const size_t shm = size_t(kWgPos) * (cout + cin) * sizeof(float);
-    hipLaunchKernelGGL((wgrad_partial_kernel<TX, TY>), dim3(unsigned(nchunk), L.taps), dim3(256),
-                       shm, s, X, ldx, ox, cin, dY, ldy, oy, cout, D, H, W, L.taps, chunk,
-                       acts.part);
+    bool done = false;
+    if constexpr (std::is_same_v<TX, uint16_t> && std::is_same_v<TY, uint16_t>) {
+      if (L.taps == 27) {
+#define AIM_WG(CI, CO)                                                                          \
+  if (!done && cin == CI && cout == CO) {                                                     \
+    hipLaunchKernelGGL((wgrad_mfma_kernel<CI, CO>), dim3(unsigned(nchunk), 27), dim3(256), 0, s, \
+                       X, ldx, ox, dY, ldy, oy, D, H, W, chunk, acts.part);                    \
+    done = true;                                                                              \
+  }
+        // the (input, output) channel pairs of the network's 3x3x3 layers
+        AIM_WG(16, 16)
+        AIM_WG(16, 32)
+        AIM_WG(32, 32)
+        AIM_WG(32, 64)
+        AIM_WG(64, 64)
+        AIM_WG(96, 32)
+        AIM_WG(48, 16)
+#undef AIM_WG
+      }
+    }
+    if (!done) {
+      const size_t shm = size_t(kWgPos) * (cout + cin) * sizeof(float);
+      hipLaunchKernelGGL((wgrad_partial_kernel<TX, TY>), dim3(unsigned(nchunk), L.taps),
+                         dim3(256), shm, s, X, ldx, ox, cin, dY, ldy, oy, cout, D, H, W, L.taps,
+                         chunk, acts.part);
+    }
     AIM_HIP(hipGetLastError());
     const int64_t n = int64_t(cout) * L.taps * cin;
     hipLaunchKernelGGL(reduce_chunks_kernel, dim3(gsz(n)), dim3(256), 0, s, acts.part,
                        int(nchunk), n, g + L.w_off);
     AIM_HIP(hipGetLastError());
-    hipLaunchKernelGGL((bgrad_kernel<TY>), dim3(cout), dim3(256), 0, s, dY, ldy, oy, cout, P,
-                       g + L.b_off);
+    // bias: partial sums over position chunks (the partial buffer is free
+    // again once the weight reduction above has run on this stream)
+    int64_t nb = std::min<int64_t>(std::min<int64_t>(1024, acts.part_n / cout), (P + 1023) / 1024);
+    const int64_t bchunk = (P + nb - 1) / nb;
+    nb = (P + bchunk - 1) / bchunk;
+    hipLaunchKernelGGL((bgrad_partial_kernel<TY>), dim3(unsigned(nb)), dim3(256), 0, s, dY, ldy,
+                       oy, cout, P, bchunk, acts.part);
+    AIM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(gsz(cout)), dim3(256), 0, s, acts.part, int(nb),
+                       int64_t(cout), g + L.b_off);
     AIM_HIP(hipGetLastError());
   }
 
