@@ -188,6 +188,28 @@ aim_status aim_setup_host(const aim_setup_desc* desc, aim_plan* out);
 /* Release every device and host resource of the plan (NULL is a no-op). */
 aim_status aim_destroy(aim_plan plan);
 
+/* Checkpoint of a plan: the frequency-independent host tables (the static
+ * near-field matrix A_s,NR and C = A_s,NR - A_s,P of Sec. III-A, which the
+ * paper suggests computing once and storing; P in both layouts; the
+ * near-block preconditioner), the wavenumbers, precisions, max_rhs and the
+ * tuned schedules, in one binary file with a checksum.  Works on host-only
+ * plans too.  Blocking. */
+aim_status aim_plan_save(aim_plan plan, const char* path);
+
+/* Rebuild a plan from aim_plan_save output without the host set-up: the file
+ * is read and validated completely (checksum, sizes, every index range, the
+ * row-block and cluster structure, finiteness) before any device call, then
+ * the tables are uploaded and the spectra computed as in aim_setup.  The
+ * allocator arguments have aim_setup_desc's meaning.  AIM_ERR_INVALID_ARG for
+ * an unreadable, corrupt or inconsistent file.  Blocking. */
+aim_status aim_plan_load(const char* path, aim_alloc_fn alloc, aim_free_fn free_fn,
+                         void* alloc_ctx, void* hip_stream, aim_plan* out);
+
+/* Host-only counterpart of aim_plan_load (like aim_setup_host): answers
+ * aim_plan_query and aim_export_tables; every device call on it returns
+ * AIM_ERR_STATE.  Runs without a GPU. */
+aim_status aim_plan_load_host(const char* path, aim_plan* out);
+
 aim_status aim_plan_query(aim_plan plan, aim_plan_info* info_host);
 
 /* y = A(k_f) x for nrhs right-hand sides (eq. LAIMx): projection, zero-padded

@@ -35,6 +35,7 @@ EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim
             "aim_unet_get_params", "aim_unet_set_params", "aim_unet_forward",
             "aim_unet_train_grid", "aim_unet_save", "aim_unet_load",
             "aim_plan_set_unet", "aim_log_pairs", "aim_pc_targets", "aim_pc_train_step",
+            "aim_plan_save", "aim_plan_load", "aim_plan_load_host",
             "aim_last_error", "aim_version"]
 KERNELS = ["project", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
            "interp_near"]
@@ -139,6 +140,9 @@ def load_library(path: str = LIB_PATH):
     lib.aim_pc_targets.argtypes = [vp, i32, i32, vp, vp, i32, vp, vp, dp, vp]
     lib.aim_pc_train_step.argtypes = [vp, vp, i32, vp, vp, i32, ip32, i32, C.c_double,
                                       C.c_double, C.c_double, i32, dp, vp]
+    lib.aim_plan_save.argtypes = [vp, C.c_char_p]
+    lib.aim_plan_load.argtypes = [C.c_char_p, ALLOC_FN, FREE_FN, vp, vp, C.POINTER(vp)]
+    lib.aim_plan_load_host.argtypes = [C.c_char_p, C.POINTER(vp)]
     lib.aim_last_error.restype = C.c_char_p
     lib.aim_version.restype = C.c_char_p
     for name in EXPORTED:
@@ -330,11 +334,39 @@ class Plan:
             torch.cuda.init()
             _check(lib.aim_setup(C.byref(d), _stream_ptr(stream), C.byref(self._plan)))
         self.k = kk
+        self._finish()
+
+    def _finish(self):
         info = self.info()
         self.n = int(info["n"])
         self.dims = tuple(info["dims"])
         self.n_grid = int(info["n_grid"])
-        self.max_rhs = int(max_rhs)
+        self.max_rhs = int(info["max_rhs"])
+
+    def save(self, path: str):
+        """Checkpoint of the plan's host tables and schedules (aim_plan_save)."""
+        _check(self._lib.aim_plan_save(self._plan, str(path).encode()))
+
+    @classmethod
+    def load(cls, path: str, host_only: bool = False, stream=None):
+        """Plan from a checkpoint, without the host set-up (aim_plan_load)."""
+        lib = load_library()
+        self = cls.__new__(cls)
+        self._lib = lib
+        self._plan = C.c_void_p()
+        self.host_only = host_only
+        if host_only:
+            _check(lib.aim_plan_load_host(str(path).encode(), C.byref(self._plan)))
+        else:
+            import torch
+            torch.cuda.init()
+            _check(lib.aim_plan_load(str(path).encode(), ALLOC_FN(), FREE_FN(), None,
+                                     _stream_ptr(stream), C.byref(self._plan)))
+        info = self.info()
+        self.precisions = tuple(name for name, bit in PREC.items() if info["precisions"] >> bit & 1)
+        self.k = None
+        self._finish()
+        return self
 
     # -- lifetime -------------------------------------------------------------
     def close(self):

@@ -17,6 +17,8 @@
 #include <functional>
 #include <random>
 #include <cstring>
+#include <fstream>
+#include <iterator>
 #include <memory>
 #include <string>
 #include <vector>
@@ -404,23 +406,10 @@ aim_status aim_setup_host(const aim_setup_desc* desc, aim_plan* out) {
   return AIM_OK;
 }
 
-aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out) {
-  if (!desc || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
-  *out = nullptr;
-  std::unique_ptr<aim_plan_s> p(new aim_plan_s());
-  const aim_status st = guarded([&] {
-    const aim_setup_desc& d = *desc;
-    validate_desc(d);
-    const double t0 = now_s();
-    // host work first: every validation happens before any device call
-    aim::build_host_tables(d, p->t);
-    p->nfreq = d.n_freq;
-    p->k.assign(d.k, d.k + d.n_freq);
-    p->prec = d.precisions;
-    p->max_rhs = d.max_rhs;
-    p->alloc = d.alloc;
-    p->free_fn = d.free;
-    p->actx = d.alloc_ctx;
+namespace {
+// Everything after the host tables: grid shape, uploads, workspace, spectra.
+// Shared by aim_setup and aim_plan_load.
+void init_device(aim_plan_s* p, hipStream_t hip_stream) {
     auto& g = p->g;
     for (int a = 0; a < 3; ++a) {
       g.N[a] = p->t.dims[a];
@@ -429,7 +418,7 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
     g.Ng = int64_t(g.N[0]) * g.N[1] * g.N[2];
     g.Nfold = int64_t(g.N[0] + 1) * (g.N[1] + 1) * (g.N[2] + 1);
 
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipStream_t s = hip_stream;
     p->setup_stream = s;
     const auto& t = p->t;
     const int64_t N = t.N, Nq = 3 * N;
@@ -534,6 +523,27 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
     }
     p->spectra_seconds = now_s() - ts;
     AIM_HIP(hipStreamSynchronize(s));
+}
+}  // namespace
+
+aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out) {
+  if (!desc || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  std::unique_ptr<aim_plan_s> p(new aim_plan_s());
+  const aim_status st = guarded([&] {
+    const aim_setup_desc& d = *desc;
+    validate_desc(d);
+    const double t0 = now_s();
+    // host work first: every validation happens before any device call
+    aim::build_host_tables(d, p->t);
+    p->nfreq = d.n_freq;
+    p->k.assign(d.k, d.k + d.n_freq);
+    p->prec = d.precisions;
+    p->max_rhs = d.max_rhs;
+    p->alloc = d.alloc;
+    p->free_fn = d.free;
+    p->actx = d.alloc_ctx;
+    init_device(p.get(), static_cast<hipStream_t>(hip_stream));
     p->t.setup_seconds = now_s() - t0;
   });
   if (st != AIM_OK) return st;
@@ -1556,4 +1566,319 @@ extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, aim_pc_loss ki
     for (double v : hp) loss += v;
     if (loss_host) *loss_host = loss;
   });
+}
+
+// ---------------------------------------------------------------------------
+// plan checkpoint: the frequency-independent host tables (the static near
+// field, the precorrected C, P in both layouts, the preconditioner blocks),
+// the wavenumbers and the tuned schedules, so that a later run skips the
+// host set-up.  Little-endian binary: magic, version, header, length-prefixed
+// arrays, FNV-1a 64 checksum of everything before it.  A loaded file is
+// validated completely (sizes, index ranges, block structure, finiteness)
+// before any of it reaches a device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr char kPlanMagic[8] = {'A', 'I', 'M', 'X', 'P', 'L', 'A', 'N'};
+constexpr uint32_t kPlanVersion = 1;
+
+uint64_t fnv1a(const char* d, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= uint8_t(d[i]);
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+struct Writer {
+  std::string b;
+  template <typename T>
+  void pod(const T& v) {
+    b.append(reinterpret_cast<const char*>(&v), sizeof(T));
+  }
+  template <typename T>
+  void vec(const std::vector<T>& v) {
+    pod(int64_t(v.size()));
+    if (!v.empty()) b.append(reinterpret_cast<const char*>(v.data()), v.size() * sizeof(T));
+  }
+};
+
+struct Reader {
+  const std::string& b;
+  size_t pos = 0;
+  size_t end;
+  template <typename T>
+  void pod(T& v) {
+    AIM_REQUIRE(end - pos >= sizeof(T), AIM_ERR_INVALID_ARG, "plan file truncated");
+    std::memcpy(&v, b.data() + pos, sizeof(T));
+    pos += sizeof(T);
+  }
+  template <typename T>
+  void vec(std::vector<T>& v) {
+    int64_t n = 0;
+    pod(n);
+    AIM_REQUIRE(n >= 0 && uint64_t(n) <= (end - pos) / sizeof(T), AIM_ERR_INVALID_ARG,
+                "plan file truncated or corrupt");
+    v.resize(size_t(n));
+    if (n) std::memcpy(v.data(), b.data() + pos, size_t(n) * sizeof(T));
+    pos += size_t(n) * sizeof(T);
+  }
+};
+
+template <typename V>
+void table_vectors(aim::HostTables& t, V&& f) {
+  f(t.area);
+  f(t.qp_xyz);
+  f(t.qp_w);
+  f(t.qp_start);
+  f(t.qp_local);
+  f(t.rowptr);
+  f(t.col);
+  f(t.near_static);
+  f(t.corr);
+  f(t.p_rowptr);
+  f(t.p_col);
+  f(t.p_val);
+  f(t.p_blk);
+  f(t.pt_rowptr);
+  f(t.pt_col);
+  f(t.pt_val);
+  f(t.cl_ptr);
+  f(t.cl_perm);
+  f(t.cl_blk);
+  f(t.cl_inv);
+}
+
+template <typename I>
+void check_offsets(const std::vector<I>& off, int64_t rows, const char* what) {
+  AIM_REQUIRE(int64_t(off.size()) == rows + 1 && off[0] == 0, AIM_ERR_INVALID_ARG,
+              std::string("plan file: bad offsets of ") + what);
+  for (int64_t i = 0; i < rows; ++i)
+    AIM_REQUIRE(off[i + 1] >= off[i], AIM_ERR_INVALID_ARG,
+                std::string("plan file: offsets of ") + what + " decrease");
+}
+
+template <typename I>
+void check_range(const std::vector<I>& v, int64_t hi, const char* what) {
+  for (const I x : v)
+    AIM_REQUIRE(x >= 0 && int64_t(x) < hi, AIM_ERR_INVALID_ARG,
+                std::string("plan file: index out of range in ") + what);
+}
+
+void check_finite(const std::vector<double>& v, const char* what) {
+  for (const double x : v)
+    AIM_REQUIRE(std::isfinite(x), AIM_ERR_INVALID_ARG,
+                std::string("plan file: non-finite value in ") + what);
+}
+
+// every invariant the kernels rely on
+void validate_tables(const aim::HostTables& t) {
+  const int64_t N = t.N;
+  AIM_REQUIRE(N >= 1 && N < (int64_t(1) << 31), AIM_ERR_INVALID_ARG, "plan file: bad size");
+  AIM_REQUIRE(t.order == 2 || t.order == 3, AIM_ERR_INVALID_ARG, "plan file: bad stencil order");
+  int64_t Ng = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int d = t.dims[a];
+    AIM_REQUIRE(d >= 8 && d <= 256 && (d & (d - 1)) == 0, AIM_ERR_INVALID_ARG,
+                "plan file: bad grid dimension");
+    Ng *= d;
+  }
+  AIM_REQUIRE(std::isfinite(t.h) && t.h > 0.0, AIM_ERR_INVALID_ARG, "plan file: bad spacing");
+  AIM_REQUIRE(int64_t(t.area.size()) == N && int64_t(t.qp_w.size()) == 3 * N &&
+                  int64_t(t.qp_xyz.size()) == 9 * N && int64_t(t.qp_start.size()) == 9 * N &&
+                  int64_t(t.qp_local.size()) == 9 * N,
+              AIM_ERR_INVALID_ARG, "plan file: bad quadrature tables");
+  for (int64_t q = 0; q < 3 * N; ++q)
+    for (int a = 0; a < 3; ++a) {
+      const int32_t s0 = t.qp_start[3 * q + a];
+      AIM_REQUIRE(s0 >= 0 && s0 + t.order <= t.dims[a] - 1, AIM_ERR_INVALID_ARG,
+                  "plan file: stencil outside the grid");
+    }
+  check_finite(t.area, "areas");
+  check_finite(t.qp_xyz, "quadrature points");
+  check_finite(t.qp_w, "quadrature weights");
+  check_finite(t.qp_local, "stencil coordinates");
+  // near field
+  check_offsets(t.rowptr, N, "C");
+  const int64_t nnz = t.rowptr[N];
+  AIM_REQUIRE(nnz < (int64_t(1) << 31) && int64_t(t.col.size()) == nnz &&
+                  int64_t(t.near_static.size()) == nnz && int64_t(t.corr.size()) == nnz,
+              AIM_ERR_INVALID_ARG, "plan file: bad near-field sizes");
+  check_range(t.col, N, "C columns");
+  check_finite(t.near_static, "A_s,NR");
+  check_finite(t.corr, "C");
+  // P by node, in row blocks
+  check_offsets(t.p_rowptr, Ng, "P");
+  const int64_t pn = t.p_rowptr[Ng];
+  AIM_REQUIRE(int64_t(t.p_col.size()) == pn && int64_t(t.p_val.size()) == pn,
+              AIM_ERR_INVALID_ARG, "plan file: bad P sizes");
+  check_range(t.p_col, N, "P columns");
+  check_finite(t.p_val, "P");
+  AIM_REQUIRE(t.p_blk.size() >= 2 && t.p_blk.front() == 0 && t.p_blk.back() == Ng,
+              AIM_ERR_INVALID_ARG, "plan file: bad P row blocks");
+  for (size_t b = 0; b + 1 < t.p_blk.size(); ++b) {
+    const int32_t r0 = t.p_blk[b], r1 = t.p_blk[b + 1];
+    AIM_REQUIRE(r1 > r0, AIM_ERR_INVALID_ARG, "plan file: empty P row block");
+    AIM_REQUIRE(r1 - r0 == 1 || t.p_rowptr[r1] - t.p_rowptr[r0] <= aim::kProjNnz,
+                AIM_ERR_INVALID_ARG, "plan file: P row block too long");
+  }
+  // P^T by triangle
+  check_offsets(t.pt_rowptr, N, "P^T");
+  const int64_t tn = t.pt_rowptr[N];
+  AIM_REQUIRE(int64_t(t.pt_col.size()) == tn && int64_t(t.pt_val.size()) == tn,
+              AIM_ERR_INVALID_ARG, "plan file: bad P^T sizes");
+  check_range(t.pt_col, Ng, "P^T columns");
+  check_finite(t.pt_val, "P^T");
+  // near-block preconditioner
+  AIM_REQUIRE(t.cl_ptr.size() >= 2, AIM_ERR_INVALID_ARG, "plan file: no clusters");
+  const int64_t ncl = int64_t(t.cl_ptr.size()) - 1;
+  check_offsets(t.cl_ptr, ncl, "clusters");
+  AIM_REQUIRE(t.cl_ptr[ncl] == N && int64_t(t.cl_perm.size()) == N, AIM_ERR_INVALID_ARG,
+              "plan file: clusters do not cover the mesh");
+  check_range(t.cl_perm, N, "cluster members");
+  check_offsets(t.cl_blk, ncl, "cluster blocks");
+  for (int64_t c = 0; c < ncl; ++c) {
+    const int64_t m = t.cl_ptr[c + 1] - t.cl_ptr[c];
+    AIM_REQUIRE(m >= 1 && m <= 64 && t.cl_blk[c + 1] - t.cl_blk[c] == m * m, AIM_ERR_INVALID_ARG,
+                "plan file: bad cluster block");
+  }
+  AIM_REQUIRE(int64_t(t.cl_inv.size()) == t.cl_blk[ncl], AIM_ERR_INVALID_ARG,
+              "plan file: bad cluster inverses");
+  check_finite(t.cl_inv, "cluster inverses");
+  // static self terms (the diagonal preconditioner divides by them)
+  for (int64_t i = 0; i < N; ++i) {
+    double dv = 0.0;
+    for (int64_t q = t.rowptr[i]; q < t.rowptr[i + 1]; ++q)
+      if (t.col[q] == i) dv = t.near_static[q];
+    AIM_REQUIRE(dv != 0.0, AIM_ERR_INVALID_ARG, "plan file: zero static self term");
+  }
+}
+
+// reads and validates a plan file into a fresh host-side plan
+std::unique_ptr<aim_plan_s> read_plan(const char* path) {
+  std::ifstream f(path, std::ios::binary);
+  AIM_REQUIRE(bool(f), AIM_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  std::string buf((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+  AIM_REQUIRE(buf.size() >= sizeof(kPlanMagic) + 4 + 8, AIM_ERR_INVALID_ARG,
+              "plan file truncated");
+  uint64_t stored = 0;
+  std::memcpy(&stored, buf.data() + buf.size() - 8, 8);
+  AIM_REQUIRE(stored == fnv1a(buf.data(), buf.size() - 8), AIM_ERR_INVALID_ARG,
+              "plan file checksum mismatch");
+  AIM_REQUIRE(std::memcmp(buf.data(), kPlanMagic, sizeof(kPlanMagic)) == 0, AIM_ERR_INVALID_ARG,
+              "not a plan file");
+  Reader r{buf, sizeof(kPlanMagic), buf.size() - 8};
+  uint32_t version = 0;
+  r.pod(version);
+  AIM_REQUIRE(version == kPlanVersion, AIM_ERR_INVALID_ARG, "unsupported plan file version");
+  std::unique_ptr<aim_plan_s> p(new aim_plan_s());
+  aim::HostTables& t = p->t;
+  r.pod(t.N);
+  r.pod(t.order);
+  for (int a = 0; a < 3; ++a) r.pod(t.dims[a]);
+  r.pod(t.h);
+  for (int a = 0; a < 3; ++a) r.pod(t.origin[a]);
+  r.pod(t.setup_seconds);
+  int32_t nfreq = 0, max_rhs = 0;
+  uint32_t prec = 0;
+  r.pod(nfreq);
+  r.pod(prec);
+  r.pod(max_rhs);
+  for (int pi = 0; pi < 2; ++pi)
+    for (int k = 0; k < aim::kSchedLen; ++k) r.pod(p->sched[pi][k]);
+  r.vec(p->k);
+  table_vectors(t, [&](auto& v) { r.vec(v); });
+  AIM_REQUIRE(r.pos == r.end, AIM_ERR_INVALID_ARG, "plan file has trailing data");
+  AIM_REQUIRE(nfreq >= 1 && int64_t(p->k.size()) == nfreq, AIM_ERR_INVALID_ARG,
+              "plan file: bad wavenumbers");
+  for (const double k : p->k)
+    AIM_REQUIRE(std::isfinite(k) && k > 0.0, AIM_ERR_INVALID_ARG, "plan file: bad wavenumber");
+  AIM_REQUIRE(prec != 0 && (prec & ~3u) == 0, AIM_ERR_INVALID_ARG, "plan file: bad precisions");
+  AIM_REQUIRE(max_rhs >= 1 && max_rhs <= 65535, AIM_ERR_INVALID_ARG, "plan file: bad max_rhs");
+  validate_tables(t);
+  p->nfreq = nfreq;
+  p->prec = prec;
+  p->max_rhs = max_rhs;
+  for (int a = 0; a < 3; ++a) {
+    p->g.N[a] = t.dims[a];
+    p->g.M[a] = 2 * t.dims[a];
+  }
+  p->g.Ng = int64_t(t.dims[0]) * t.dims[1] * t.dims[2];
+  p->g.Nfold = int64_t(t.dims[0] + 1) * (t.dims[1] + 1) * (t.dims[2] + 1);
+  for (int pi = 0; pi < 2; ++pi) {
+    for (int k = 0; k < 5; ++k)
+      AIM_REQUIRE(p->sched[pi][k] >= 0 && p->sched[pi][k] < aim::kFftVariants &&
+                      aim::fft_variant_ok(pi == 0, p->g.M[kPassAxis[k]], kPassCol[k],
+                                          p->sched[pi][k]),
+                  AIM_ERR_INVALID_ARG, "plan file: bad schedule");
+    AIM_REQUIRE(p->sched[pi][5] >= 0 && p->sched[pi][5] < aim::kLayouts &&
+                    (p->sched[pi][6] == 0 || p->sched[pi][6] == 1),
+                AIM_ERR_INVALID_ARG, "plan file: bad schedule");
+  }
+  p->ncl = int(t.cl_ptr.size()) - 1;
+  for (int c = 0; c < p->ncl; ++c) p->maxcl = std::max(p->maxcl, t.cl_ptr[c + 1] - t.cl_ptr[c]);
+  return p;
+}
+
+}  // namespace
+
+extern "C" aim_status aim_plan_save(aim_plan p, const char* path) {
+  if (!p || !path) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    Writer w;
+    w.b.append(kPlanMagic, sizeof(kPlanMagic));
+    w.pod(kPlanVersion);
+    aim::HostTables& t = p->t;
+    w.pod(t.N);
+    w.pod(t.order);
+    for (int a = 0; a < 3; ++a) w.pod(t.dims[a]);
+    w.pod(t.h);
+    for (int a = 0; a < 3; ++a) w.pod(t.origin[a]);
+    w.pod(t.setup_seconds);
+    w.pod(int32_t(p->nfreq));
+    w.pod(uint32_t(p->prec));
+    w.pod(int32_t(p->max_rhs));
+    for (int pi = 0; pi < 2; ++pi)
+      for (int k = 0; k < aim::kSchedLen; ++k) w.pod(int32_t(p->sched[pi][k]));
+    w.vec(p->k);
+    table_vectors(t, [&](auto& v) { w.vec(v); });
+    w.pod(fnv1a(w.b.data(), w.b.size()));
+    std::ofstream f(path, std::ios::binary | std::ios::trunc);
+    AIM_REQUIRE(bool(f), AIM_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    f.write(w.b.data(), std::streamsize(w.b.size()));
+    AIM_REQUIRE(bool(f), AIM_ERR_INVALID_ARG, std::string("write failed: ") + path);
+  });
+}
+
+extern "C" aim_status aim_plan_load_host(const char* path, aim_plan* out) {
+  if (!path || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  std::unique_ptr<aim_plan_s> p;
+  const aim_status st = guarded([&] {
+    p = read_plan(path);
+    p->host_only = true;
+  });
+  if (st != AIM_OK) return st;
+  *out = p.release();
+  return AIM_OK;
+}
+
+extern "C" aim_status aim_plan_load(const char* path, aim_alloc_fn alloc, aim_free_fn free_fn,
+                                    void* alloc_ctx, void* hip_stream, aim_plan* out) {
+  if (!path || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(AIM_ERR_INVALID_ARG, "alloc and free must be given together");
+  std::unique_ptr<aim_plan_s> p;
+  const aim_status st = guarded([&] {
+    p = read_plan(path);  // everything validated before any device call
+    p->alloc = alloc;
+    p->free_fn = free_fn;
+    p->actx = alloc_ctx;
+    init_device(p.get(), static_cast<hipStream_t>(hip_stream));
+  });
+  if (st != AIM_OK) return st;
+  *out = p.release();
+  return AIM_OK;
 }

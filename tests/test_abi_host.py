@@ -120,3 +120,35 @@ def test_null_arguments():
     assert lib.aim_setup(None, None, None) == 1
     assert lib.aim_matvec(None, 0, None, None, 1, None, None) == 1
     assert lib.aim_destroy(None) == 0
+
+
+def test_plan_checkpoint_roundtrip_and_corruption(tmp_path):
+    """aim_plan_save / aim_plan_load_host: the loaded tables equal the saved
+    ones; a flipped byte, a truncated file and a missing file are refused
+    before any device work."""
+    w = I.sphere_tiny(level=2, radius=0.5, dims=(16, 16, 16), h=0.1)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold,
+                     [5.0, 6.0], host_only=True, max_rhs=3)
+    path = tmp_path / "plan.aim"
+    p.save(path)
+    q = binding.Plan.load(path, host_only=True)
+    a, b = p.export_tables(), q.export_tables()
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+    ia, ib = p.info(), q.info()
+    for key in ("n", "n_grid", "nnz", "dims", "order", "n_freq", "max_rhs", "precisions", "h"):
+        assert ia[key] == ib[key], key
+    raw = bytearray(path.read_bytes())
+    bad = tmp_path / "bad.aim"
+    raw[len(raw) // 2] ^= 0x40
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(binding.AimError, match="checksum"):
+        binding.Plan.load(bad, host_only=True)
+    short = tmp_path / "short.aim"
+    short.write_bytes(path.read_bytes()[:100])
+    with pytest.raises(binding.AimError):
+        binding.Plan.load(short, host_only=True)
+    with pytest.raises(binding.AimError):
+        binding.Plan.load(tmp_path / "missing.aim", host_only=True)
+    p.close()
+    q.close()
