@@ -185,6 +185,26 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
  * device call on it returns AIM_ERR_STATE.  Blocking; runs without a GPU. */
 aim_status aim_setup_host(const aim_setup_desc* desc, aim_plan* out);
 
+/* A batch of geometries of uneven size (the survey's batched solve over
+ * many instances): n descriptions, each set up as by aim_setup (own grid,
+ * frequencies, tables, spectra; max_rhs of each is ignored), behind one
+ * handle.  System i belongs to instance i; its vectors are rows of length
+ * N_max = max N_i, of which the first N_i entries are used and the rest must
+ * be zero on input (b, x0) and are zero on output.  On a batch plan,
+ * aim_matvec and aim_solve take nrhs = n (freq_idx_host[i] indexes
+ * instance i's wavenumbers; all instances have at least the batch's n_freq),
+ * with the diagonal and near-block preconditioners applied per instance;
+ * stages, excitations, schedules, profiles, checkpoints and the learned
+ * preconditioner are per instance and return AIM_ERR_STATE.  The instances
+ * run one after another on the stream (one launch sequence each), not in one
+ * fused launch.  All descriptions must share one allocator.  Blocking. */
+aim_status aim_setup_batch(const aim_setup_desc* descs, int32_t n, void* hip_stream,
+                           aim_plan* out);
+
+/* Number of instances (1 for an ordinary plan) and, if n_host != NULL, each
+ * instance's number of triangles N_i (n_host has room for the count). */
+aim_status aim_batch_sizes(aim_plan plan, int32_t* count, int64_t* n_host);
+
 /* Release every device and host resource of the plan (NULL is a no-op). */
 aim_status aim_destroy(aim_plan plan);
 

@@ -35,7 +35,8 @@ EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim
             "aim_unet_get_params", "aim_unet_set_params", "aim_unet_forward",
             "aim_unet_train_grid", "aim_unet_save", "aim_unet_load",
             "aim_plan_set_unet", "aim_log_pairs", "aim_pc_targets", "aim_pc_train_step",
-            "aim_plan_save", "aim_plan_load", "aim_plan_load_host",
+            "aim_plan_save", "aim_plan_load", "aim_plan_load_host", "aim_setup_batch",
+            "aim_batch_sizes",
             "aim_last_error", "aim_version"]
 KERNELS = ["project", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
            "interp_near"]
@@ -140,6 +141,8 @@ def load_library(path: str = LIB_PATH):
     lib.aim_pc_targets.argtypes = [vp, i32, i32, vp, vp, i32, vp, vp, dp, vp]
     lib.aim_pc_train_step.argtypes = [vp, vp, i32, vp, vp, i32, ip32, i32, C.c_double,
                                       C.c_double, C.c_double, i32, dp, vp]
+    lib.aim_setup_batch.argtypes = [C.POINTER(SetupDesc), i32, vp, C.POINTER(vp)]
+    lib.aim_batch_sizes.argtypes = [vp, ip32, C.POINTER(C.c_int64)]
     lib.aim_plan_save.argtypes = [vp, C.c_char_p]
     lib.aim_plan_load.argtypes = [C.c_char_p, ALLOC_FN, FREE_FN, vp, vp, C.POINTER(vp)]
     lib.aim_plan_load_host.argtypes = [C.c_char_p, C.POINTER(vp)]
@@ -202,6 +205,51 @@ class UNet:
         h = C.c_void_p()
         _check(lib.aim_unet_load(path.encode(), C.byref(h)))
         return cls(handle=h)
+
+    @classmethod
+    def setup_batch(cls, workloads, precisions=("c128", "c64"), stream=None):
+        """One plan over several geometries of uneven size (aim_setup_batch).
+        ``workloads`` are objects with vertices, triangles, order, dims, h,
+        near_threshold and k.  Vectors are [n][N_max] with zero padding; use
+        pack/unpack."""
+        import torch
+        lib = load_library()
+        n = len(workloads)
+        descs = (SetupDesc * n)()
+        keep = []
+        for i, w in enumerate(workloads):
+            d, kp = _make_desc(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold,
+                               w.k, precisions, 1)
+            descs[i] = d
+            keep.append(kp)
+        self = cls.__new__(cls)
+        self._lib = lib
+        self._plan = C.c_void_p()
+        self.host_only = False
+        self.precisions = tuple(precisions)
+        torch.cuda.init()
+        _check(lib.aim_setup_batch(descs, n, _stream_ptr(stream), C.byref(self._plan)))
+        self.k = None
+        self._finish()
+        cnt = C.c_int32(0)
+        sizes = (C.c_int64 * n)()
+        _check(lib.aim_batch_sizes(self._plan, C.byref(cnt), sizes))
+        self.batch_sizes = [int(v) for v in sizes]
+        return self
+
+    def pack(self, vectors, dtype=None):
+        """[n][N_max] device tensor from n vectors of the instances' sizes."""
+        import torch
+        dt = dtype or torch.complex128
+        out = torch.zeros((len(self.batch_sizes), self.n), dtype=dt, device="cuda")
+        for i, v in enumerate(vectors):
+            t = torch.as_tensor(v).to(dt).to("cuda")
+            out[i, :self.batch_sizes[i]] = t.reshape(-1)
+        return out
+
+    def unpack(self, t):
+        """List of the instances' vectors from a [n][N_max] tensor."""
+        return [t[i, :m] for i, m in enumerate(self.batch_sizes)]
 
     def save(self, path: str):
         _check(self._lib.aim_unet_save(self._h, path.encode()))
@@ -298,6 +346,30 @@ class MatvecGraph:
             pass
 
 
+def _make_desc(vertices, triangles, order, dims, h, near_threshold, k, precisions, max_rhs,
+               n_threads=0):
+    """aim_setup_desc and the arrays it points into (keep them alive)."""
+    V = np.ascontiguousarray(vertices, dtype=np.float64)
+    T = np.ascontiguousarray(triangles, dtype=np.int32)
+    kk = np.ascontiguousarray(np.atleast_1d(np.asarray(k, dtype=np.float64)))
+    d = SetupDesc()
+    d.n_vertices = V.shape[0]
+    d.n_triangles = T.shape[0]
+    d.vertices = V.ctypes.data
+    d.triangles = T.ctypes.data
+    d.stencil_order = int(order)
+    for a in range(3):
+        d.grid_dims[a] = int(dims[a])
+    d.h = float(h)
+    d.near_threshold = float(near_threshold)
+    d.n_freq = kk.size
+    d.k = kk.ctypes.data
+    d.precisions = sum(1 << PREC[p] for p in precisions)
+    d.max_rhs = int(max_rhs)
+    d.n_threads = int(n_threads)
+    return d, (V, T, kk)
+
+
 class Plan:
     """An AIMx operator for one mesh, grid and frequency set (see aim_setup)."""
 
@@ -306,24 +378,9 @@ class Plan:
                  stream=None, host_only: bool = False):
         lib = load_library()
         self._lib = lib
-        V = np.ascontiguousarray(vertices, dtype=np.float64)
-        T = np.ascontiguousarray(triangles, dtype=np.int32)
-        kk = np.ascontiguousarray(np.atleast_1d(np.asarray(k, dtype=np.float64)))
-        d = SetupDesc()
-        d.n_vertices = V.shape[0]
-        d.n_triangles = T.shape[0]
-        d.vertices = V.ctypes.data
-        d.triangles = T.ctypes.data
-        d.stencil_order = int(order)
-        for a in range(3):
-            d.grid_dims[a] = int(dims[a])
-        d.h = float(h)
-        d.near_threshold = float(near_threshold)
-        d.n_freq = kk.size
-        d.k = kk.ctypes.data
-        d.precisions = sum(1 << PREC[p] for p in precisions)
-        d.max_rhs = int(max_rhs)
-        d.n_threads = int(n_threads)
+        d, keep = _make_desc(vertices, triangles, order, dims, h, near_threshold, k, precisions,
+                             max_rhs, n_threads)
+        kk = keep[2]
         self._plan = C.c_void_p()
         self.precisions = tuple(precisions)
         self.host_only = host_only
@@ -342,6 +399,51 @@ class Plan:
         self.dims = tuple(info["dims"])
         self.n_grid = int(info["n_grid"])
         self.max_rhs = int(info["max_rhs"])
+
+    @classmethod
+    def setup_batch(cls, workloads, precisions=("c128", "c64"), stream=None):
+        """One plan over several geometries of uneven size (aim_setup_batch).
+        ``workloads`` are objects with vertices, triangles, order, dims, h,
+        near_threshold and k.  Vectors are [n][N_max] with zero padding; use
+        pack/unpack."""
+        import torch
+        lib = load_library()
+        n = len(workloads)
+        descs = (SetupDesc * n)()
+        keep = []
+        for i, w in enumerate(workloads):
+            d, kp = _make_desc(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold,
+                               w.k, precisions, 1)
+            descs[i] = d
+            keep.append(kp)
+        self = cls.__new__(cls)
+        self._lib = lib
+        self._plan = C.c_void_p()
+        self.host_only = False
+        self.precisions = tuple(precisions)
+        torch.cuda.init()
+        _check(lib.aim_setup_batch(descs, n, _stream_ptr(stream), C.byref(self._plan)))
+        self.k = None
+        self._finish()
+        cnt = C.c_int32(0)
+        sizes = (C.c_int64 * n)()
+        _check(lib.aim_batch_sizes(self._plan, C.byref(cnt), sizes))
+        self.batch_sizes = [int(v) for v in sizes]
+        return self
+
+    def pack(self, vectors, dtype=None):
+        """[n][N_max] device tensor from n vectors of the instances' sizes."""
+        import torch
+        dt = dtype or torch.complex128
+        out = torch.zeros((len(self.batch_sizes), self.n), dtype=dt, device="cuda")
+        for i, v in enumerate(vectors):
+            t = torch.as_tensor(v).to(dt).to("cuda")
+            out[i, :self.batch_sizes[i]] = t.reshape(-1)
+        return out
+
+    def unpack(self, t):
+        """List of the instances' vectors from a [n][N_max] tensor."""
+        return [t[i, :m] for i, m in enumerate(self.batch_sizes)]
 
     def save(self, path: str):
         """Checkpoint of the plan's host tables and schedules (aim_plan_save)."""

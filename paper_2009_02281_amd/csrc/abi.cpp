@@ -123,6 +123,10 @@ struct aim_plan_s {
   double* d_k = nullptr;
   double* d_area = nullptr;              // triangle areas (learned preconditioner)
   // learned preconditioner (not owned) and its buffers
+  // batch of geometries (aim_setup_batch): instance i owns system i, whose
+  // vectors are the first N_i entries of a row of length t.N = max N_i
+  bool batch = false;
+  std::vector<std::unique_ptr<aim_plan_s>> inst;
   aim_unet unet = nullptr;
   aim_pc_kind unet_base = AIM_PC_DIAG;
   double unet_tau = 1.0;
@@ -252,6 +256,11 @@ void interp_near(aim_plan p, aim_precision prec, const void* phi, const void* x,
                                do_interp, do_near, s);
 }
 
+void no_batch(aim_plan p) {
+  AIM_REQUIRE(!p->batch, AIM_ERR_STATE,
+              "not available on a batch plan (use the instance plans' own set-up)");
+}
+
 void check_prec(aim_plan p, aim_precision prec) {
   AIM_REQUIRE(!p->host_only, AIM_ERR_STATE, "host-only plan has no device data");
   AIM_REQUIRE(prec == AIM_C128 || prec == AIM_C64, AIM_ERR_INVALID_ARG, "bad precision");
@@ -303,6 +312,21 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
 
 void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev = nullptr) {
+  if (p->batch) {
+    // system i through instance i; the padding of y_i stays zero
+    AIM_REQUIRE(nrhs == int(p->inst.size()) && !ev, AIM_ERR_INVALID_ARG,
+                "a batch plan applies one system per instance");
+    const size_t cb = prec == AIM_C128 ? 16 : 8;
+    const int64_t nmax = p->t.N;
+    for (int i = 0; i < nrhs; ++i) {
+      aim_plan_s* q = p->inst[i].get();
+      const char* xi = static_cast<const char*>(x) + size_t(i) * nmax * cb;
+      char* yi = static_cast<char*>(y) + size_t(i) * nmax * cb;
+      matvec_any(q, prec, xi, yi, 1, dfreq + i, s);
+      aim::launch_zero_words(yi + size_t(q->t.N) * cb, (nmax - q->t.N) * int64_t(cb / 8), s);
+    }
+    return;
+  }
   if (prec == AIM_C128)
     matvec_impl<double>(p, prec, x, y, nrhs, dfreq, s, ev);
   else
@@ -551,6 +575,77 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
   return AIM_OK;
 }
 
+aim_status aim_setup_batch(const aim_setup_desc* descs, int32_t n, void* hip_stream,
+                           aim_plan* out) {
+  if (!descs || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (n < 1 || n > 65535) return fail(AIM_ERR_INVALID_ARG, "n must be in 1..65535");
+  std::unique_ptr<aim_plan_s> b(new aim_plan_s());
+  const aim_status st = guarded([&] {
+    const double t0 = now_s();
+    // every description is validated and every host table built before any
+    // device call
+    for (int i = 0; i < n; ++i) {
+      validate_desc(descs[i]);
+      AIM_REQUIRE((descs[i].alloc == descs[0].alloc) && (descs[i].free == descs[0].free) &&
+                      (descs[i].alloc_ctx == descs[0].alloc_ctx),
+                  AIM_ERR_INVALID_ARG, "the instances of a batch share one allocator");
+    }
+    for (int i = 0; i < n; ++i) {
+      std::unique_ptr<aim_plan_s> q(new aim_plan_s());
+      const aim_setup_desc& d = descs[i];
+      aim::build_host_tables(d, q->t);
+      q->nfreq = d.n_freq;
+      q->k.assign(d.k, d.k + d.n_freq);
+      q->prec = d.precisions;
+      q->max_rhs = 1;
+      q->alloc = d.alloc;
+      q->free_fn = d.free;
+      q->actx = d.alloc_ctx;
+      b->inst.push_back(std::move(q));
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    b->batch = true;
+    b->alloc = descs[0].alloc;
+    b->free_fn = descs[0].free;
+    b->actx = descs[0].alloc_ctx;
+    b->setup_stream = s;
+    b->max_rhs = n;
+    b->prec = 3u;
+    b->nfreq = 1 << 30;
+    b->t.N = 0;
+    b->t.order = descs[0].stencil_order;
+    for (auto& q : b->inst) {
+      init_device(q.get(), s);
+      b->t.N = std::max(b->t.N, q->t.N);
+      b->prec &= q->prec;
+      b->nfreq = std::min(b->nfreq, q->nfreq);
+      b->device_bytes += q->device_bytes;
+    }
+    AIM_REQUIRE(b->prec != 0, AIM_ERR_INVALID_ARG, "the instances share no precision");
+    b->d_rhs_freq = static_cast<int32_t*>(b->dalloc(sizeof(int32_t) * n, s));
+    AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&b->h_rhs_freq), sizeof(int32_t) * n, 0));
+    AIM_HIP(hipStreamSynchronize(s));
+    b->t.setup_seconds = now_s() - t0;
+  });
+  if (st != AIM_OK) return st;
+  *out = b.release();
+  return AIM_OK;
+}
+
+aim_status aim_batch_sizes(aim_plan p, int32_t* count, int64_t* n_host) {
+  if (!p || !count) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    *count = p->batch ? int32_t(p->inst.size()) : 1;
+    if (n_host) {
+      if (p->batch)
+        for (size_t i = 0; i < p->inst.size(); ++i) n_host[i] = p->inst[i]->t.N;
+      else
+        n_host[0] = p->t.N;
+    }
+  });
+}
+
 aim_status aim_destroy(aim_plan plan) {
   return guarded([&] { delete plan; });
 }
@@ -596,6 +691,7 @@ aim_status aim_profile_matvec(aim_plan p, aim_precision prec, const void* x, voi
                               double* kernel_ms, void* hip_stream) {
   if (!p || !x || !y || !kernel_ms) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
+    no_batch(p);
     check_prec(p, prec);
     AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
     AIM_REQUIRE(reps >= 1, AIM_ERR_INVALID_ARG, "reps must be >= 1");
@@ -632,6 +728,7 @@ static const bool kPassCol[5] = {false, true, true, true, false};
 aim_status aim_set_schedule(aim_plan p, aim_precision prec, const int32_t* sched) {
   if (!p || !sched) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
+    no_batch(p);
     check_prec(p, prec);
     for (int k = 0; k < 5; ++k)
       AIM_REQUIRE(sched[k] >= 0 && sched[k] < aim::kFftVariants &&
@@ -651,6 +748,7 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
                         int32_t* sched_out, double* pass_ms_out, void* hip_stream) {
   if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
   return guarded([&] {
+    no_batch(p);
     check_prec(p, prec);
     AIM_REQUIRE(reps >= 1 && reps <= 1000, AIM_ERR_INVALID_ARG, "reps must be in 1..1000");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -788,6 +886,7 @@ aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, cons
                            void* hip_stream) {
   if (!p || !in || !out) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
+    no_batch(p);
     check_prec(p, prec);
     AIM_REQUIRE(in != out, AIM_ERR_INVALID_ARG, "in and out must not overlap");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -840,6 +939,7 @@ aim_status aim_excitation(aim_plan p, aim_rhs_kind kind, const double* params, i
                           int32_t nrhs, const int32_t* freq_idx_host, void* b, void* hip_stream) {
   if (!p || !params || !b) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
+    no_batch(p);
     AIM_REQUIRE(!p->host_only, AIM_ERR_STATE, "host-only plan has no device data");
     AIM_REQUIRE(kind == AIM_RHS_PLANE_WAVE || kind == AIM_RHS_GAUSSIAN_PATCH, AIM_ERR_INVALID_ARG,
                 "unknown excitation kind");
@@ -877,6 +977,7 @@ aim_status aim_export_tables(aim_plan p, int32_t* stencil_start, double* stencil
                              int64_t* rowptr, int32_t* col, double* val, double* near_static) {
   if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
   return guarded([&] {
+    no_batch(p);
     const auto& t = p->t;
     if (stencil_start) std::copy(t.qp_start.begin(), t.qp_start.end(), stencil_start);
     if (stencil_local) std::copy(t.qp_local.begin(), t.qp_local.end(), stencil_local);
@@ -996,6 +1097,16 @@ void ensure_unet_buffers(aim_plan p, hipStream_t s) {
 // Classical (linear) preconditioners: z = v, D^{-1} v or the near-block inverse.
 void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hipStream_t s) {
   const int64_t n = p->t.N;
+  if (p->batch) {
+    for (int i = 0; i < nrhs; ++i) {
+      aim_plan_s* q = p->inst[i].get();
+      const char* vi = static_cast<const char*>(v) + size_t(i) * n * 16;
+      char* zi = static_cast<char*>(z) + size_t(i) * n * 16;
+      apply_base(q, pc, vi, zi, 1, s);
+      aim::launch_zero_words(zi + size_t(q->t.N) * 16, (n - q->t.N) * 2, s);
+    }
+    return;
+  }
   switch (pc) {
     case AIM_PC_NONE:
       AIM_HIP(hipMemcpyAsync(z, v, size_t(n) * 16 * nrhs, hipMemcpyDeviceToDevice, s));
@@ -1039,6 +1150,7 @@ void check_unet_plan(aim_plan p) {
 // B the base preconditioner, U the network; the grid work is complex64.
 void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s) {
   AIM_REQUIRE(p->unet != nullptr, AIM_ERR_STATE, "no learned preconditioner attached");
+  AIM_REQUIRE(!p->batch, AIM_ERR_STATE, "no learned preconditioner on a batch plan");
   ensure_unet_buffers(p, s);  // before any of the buffers is read below
   const int64_t n = p->t.N, Ng = p->g.Ng;
   unet_input(p, v, nrhs, p->ug_in, s);
@@ -1377,6 +1489,7 @@ extern "C" aim_status aim_plan_set_unet(aim_plan p, aim_unet net, aim_pc_kind ba
                                         double tau) {
   if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
   return guarded([&] {
+    no_batch(p);
     AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK, AIM_ERR_INVALID_ARG,
                 "base preconditioner must be none, diag or nearblock");
     AIM_REQUIRE(std::isfinite(tau) && tau > 0.0, AIM_ERR_INVALID_ARG, "tau must be positive");
@@ -1456,6 +1569,7 @@ extern "C" aim_status aim_pc_targets(aim_plan p, aim_pc_kind base_pc, aim_pc_los
   if (!p || (npairs > 0 && (!r_pairs || !e_pairs || !grid_out || !target_out)))
     return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
+    no_batch(p);
     AIM_REQUIRE(npairs >= 0, AIM_ERR_INVALID_ARG, "npairs must be >= 0");
     AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK, AIM_ERR_INVALID_ARG,
                 "base preconditioner must be none, diag or nearblock");
@@ -1511,6 +1625,7 @@ extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, aim_pc_loss ki
   if (!p || !net || !grids || !targets || !sample_idx_host)
     return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
+    no_batch(p);
     AIM_REQUIRE(nsamples >= 1, AIM_ERR_INVALID_ARG, "nsamples must be >= 1");
     AIM_REQUIRE(std::isfinite(tau) && tau > 0.0, AIM_ERR_INVALID_ARG, "tau must be positive");
     AIM_REQUIRE(std::isfinite(lr) && lr >= 0.0, AIM_ERR_INVALID_ARG, "lr must be >= 0");
@@ -1826,6 +1941,7 @@ std::unique_ptr<aim_plan_s> read_plan(const char* path) {
 extern "C" aim_status aim_plan_save(aim_plan p, const char* path) {
   if (!p || !path) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
+    no_batch(p);
     Writer w;
     w.b.append(kPlanMagic, sizeof(kPlanMagic));
     w.pod(kPlanVersion);

@@ -209,6 +209,8 @@ void launch_resid_loss(const void* az, const void* sv, double wgt, int64_t n, vo
 // d = coef conj(y) / area
 void launch_resid_grad(const void* y, const double* area, double coef, void* d, int64_t n,
                        hipStream_t st);
+// zero n 8-byte words
+void launch_zero_words(void* p, int64_t n, hipStream_t st);
 // e = xs - e (one vector)
 void launch_pair_error(const void* xs, void* e, int64_t n, hipStream_t st);
 void unet_forward(aim_unet u, const void* in, int D, int H, int W, void* out, hipStream_t s);

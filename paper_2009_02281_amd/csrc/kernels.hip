@@ -1697,6 +1697,20 @@ void launch_resid_grad(const void* y, const double* area, double coef, void* d, 
   AIM_HIP(hipGetLastError());
 }
 
+// zero n 8-byte words (a kernel, so that captured graphs hold no memset node)
+__global__ void zero_words_kernel(uint2* p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = make_uint2(0u, 0u);
+}
+
+void launch_zero_words(void* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, st,
+                     static_cast<uint2*>(p), n);
+  AIM_HIP(hipGetLastError());
+}
+
 // e = xs - e for a logged iterate (in place): the error of the iterate
 // against the converged solution
 __global__ void pair_error_kernel(const double2* xs, double2* e, int64_t n) {

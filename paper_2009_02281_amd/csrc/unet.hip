@@ -32,7 +32,6 @@
 namespace aim {
 namespace unetk {
 
-typedef short bf16x4 __attribute__((__vector_size__(4 * sizeof(short))));
 typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
