@@ -170,3 +170,70 @@ def test_uneven_batch_of_geometries():
             tr = true_resid(o, float(w.k[0]), Xh[i, :w.n], bs[i])
             assert tr <= 2e-8, (inner, i, tr)
     bp.close()
+
+
+def exterior_field(V, T, x, k, pts):
+    """u(r) = sum_j x_j sum_q w_q G(k, |r - r_q|) with the 3-point rule."""
+    from oracle import mesh
+    from oracle.green import green_full
+    qp, wq = mesh.quad_points(V, T), mesh.quad_weights(V, T)
+    out = np.empty(len(pts), dtype=complex)
+    for i, r in enumerate(pts):
+        R = np.linalg.norm(qp - r, axis=-1)
+        out[i] = np.sum(green_full(k, R) * wq * x[:, None])
+    return out
+
+
+def test_small_sphere_solution_matches_mie_series():
+    """cfg 1: the +z plane-wave solution of the 1,280-triangle sphere, solved
+    on the GPU (complex128, and complex64 inside complex128 refinement, to
+    1e-8), radiates the sphere series' exterior field at r = 2a within the
+    discretisation error.  ka = pi is a zero of j_0: the undetermined l = 0
+    density does not radiate, so the exterior field is well defined."""
+    from oracle import mie
+    w, o, p = sphere()
+    k = float(w.k[0])
+    b = p.excitation("plane_wave", [0, 0, 1])
+    th = np.linspace(0.1, math.pi - 0.1, 9)
+    pts = np.stack([np.sin(th), 0 * th, np.cos(th)], 1) * 1.0
+    ue = mie.exterior_field_plane_wave(k, 0.5, 1.0, np.cos(th))
+    for inner in ("c128", "c64"):
+        x, res = p.solve(b, rtol=1e-8, restart=60, pc="diag", inner=inner)
+        assert res.converged[0]
+        u = exterior_field(o.V, o.T, host(x)[0], k, pts)
+        err = np.linalg.norm(u - ue) / np.linalg.norm(ue)
+        print(f"[gpu] sphere-1280 ({inner}): iters {res.iters[0]}, exterior field vs Mie {err:.2e}",
+              flush=True)
+        assert err < 3e-2
+
+
+def test_large_sphere_mixed_precision_solve_matches_mie_series():
+    """cfg 4: the radius-6 sphere (327,680 triangles, 256^3 grid): complex64
+    matvecs inside complex128 refinement with the static diagonal, to 1e-6
+    relative residual (the library's complex128 residual, checked again with
+    a fresh complex128 matvec); the exterior field at r = 2a against the
+    sphere series (ka = 12 pi, a zero of j_0; the undetermined l = 0 density
+    does not radiate)."""
+    from oracle import mie
+    w = I.sphere_large()
+    print(f"[gpu] sphere-{w.n}: setting up", flush=True)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     max_rhs=1)
+    k = float(w.k[0])
+    b = p.excitation("plane_wave", [0, 0, 1])
+    x, res = p.solve(b, rtol=1e-6, restart=60, pc="diag", inner="c64", max_iter=6000,
+                     max_refine=20)
+    print(f"[gpu] sphere-{w.n}: iters {res.iters[0]}, refinements {res.refinements[0]}, "
+          f"residual {res.rel_resid[0]:.2e}, {res.seconds:.2f} s", flush=True)
+    assert res.converged[0] and res.rel_resid[0] <= 1e-6
+    r = b - p.matvec(x)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1.05e-6
+    a = 6.0
+    th = np.linspace(0.15, math.pi - 0.15, 7)
+    pts = np.stack([np.sin(th), 0 * th, np.cos(th)], 1) * (2 * a)
+    ue = mie.exterior_field_plane_wave(k, a, 2 * a, np.cos(th))
+    u = exterior_field(w.vertices, w.triangles, host(x)[0], k, pts)
+    err = np.linalg.norm(u - ue) / np.linalg.norm(ue)
+    print(f"    exterior field vs Mie {err:.2e}", flush=True)
+    assert err < 3e-2
+    p.close()
