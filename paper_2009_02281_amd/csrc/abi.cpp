@@ -1835,7 +1835,8 @@ void validate_tables(const aim::HostTables& t) {
   for (size_t b = 0; b + 1 < t.p_blk.size(); ++b) {
     const int32_t r0 = t.p_blk[b], r1 = t.p_blk[b + 1];
     AIM_REQUIRE(r1 > r0, AIM_ERR_INVALID_ARG, "plan file: empty P row block");
-    AIM_REQUIRE(r1 - r0 == 1 || t.p_rowptr[r1] - t.p_rowptr[r0] <= aim::kProjNnz,
+    const int64_t nz = t.p_rowptr[r1] - t.p_rowptr[r0];
+    AIM_REQUIRE(r1 - r0 == 1 || nz == 0 || (nz <= aim::kProjNnz && r1 - r0 <= aim::kProjRows),
                 AIM_ERR_INVALID_ARG, "plan file: P row block too long");
   }
   // P^T by triangle

@@ -736,10 +736,13 @@ std::vector<double> twiddles64(int L) {
 // P is assembled once at set-up (the quadrature-point stencil weights of each
 // triangle merged into one row per grid node, sorted by node) and cut into
 // blocks of consecutive rows holding at most kProjNnz non-zeros.  A block
-// loads all its non-zeros at once (coalesced, independent gathers of x) into
-// LDS, then each thread sums whole rows from LDS in a fixed order, so the
+// loads all its non-zeros and row starts at once (coalesced loads, then
+// independent gathers of x, every load in flight before the first is used),
+// forms the products in LDS, then each thread sums whole rows from LDS in a
+// fixed order (four interleaved partial sums), so the
 // result is reproducible and no atomics are needed.  Nodes that no stencil
-// reaches get their zero written by the same pass.
+// reaches get their zero written by the same pass; long runs of them form
+// blocks of their own that only store zeros.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ x,
@@ -749,18 +752,28 @@ __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ 
                                                       const T* __restrict__ val,
                                                       const int32_t* __restrict__ blk, int64_t n,
                                                       int64_t Ng, int nrhs, int rb) {
+  constexpr int PER = kProjNnz / 256, RPER = kProjRows / 256 + 1;
   __shared__ cx<T> prod[kProjNnz];
-  __shared__ T red[2 * 256];
+  __shared__ union {
+    T red[2 * 256];           // long row
+    int rp[kProjRows + 1];    // row starts of the block, relative to its first non-zero
+  } sh;
   const int tid = threadIdx.x;
   const int r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
   const int k0 = rowptr[r0], k1 = rowptr[r1];
-  // rb right-hand sides per block: the block's rows of P are read from
-  // memory for the first and from cache for the others
+  // rb right-hand sides per block: the block's rows of P are read once and
+  // applied to each of them
   const int rhs_end = min(nrhs, int(blockIdx.y + 1) * rb);
-  for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
-    const cx<T>* xr = x + rhs * n;
-    cx<T>* qr = q + rhs * Ng;
-    if (k1 - k0 > kProjNnz) {  // one long row: strided partial sums, block reduction
+  if (k0 == k1) {  // nodes no stencil reaches: zeros, without reading rowptr per row
+    for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
+      cx<T>* qr = q + rhs * Ng;
+      for (int r = r0 + tid; r < r1; r += 256) qr[r] = mkc<T>(T(0), T(0));
+    }
+    return;
+  }
+  if (k1 - k0 > kProjNnz) {  // one long row: strided partial sums, block reduction
+    for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
+      const cx<T>* xr = x + rhs * n;
       T ar = T(0), ai = T(0);
       for (int k = k0 + tid; k < k1; k += 256) {
         const T w = val[k];
@@ -768,35 +781,65 @@ __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ 
         ar += w * xv.x;
         ai += w * xv.y;
       }
-      red[tid] = ar;
-      red[256 + tid] = ai;
+      sh.red[tid] = ar;
+      sh.red[256 + tid] = ai;
       __syncthreads();
       for (int o = 128; o > 0; o >>= 1) {
         if (tid < o) {
-          red[tid] += red[tid + o];
-          red[256 + tid] += red[256 + tid + o];
+          sh.red[tid] += sh.red[tid + o];
+          sh.red[256 + tid] += sh.red[256 + tid + o];
         }
         __syncthreads();
       }
-      if (tid == 0) qr[r0] = mkc<T>(red[0], red[256]);
+      if (tid == 0) q[rhs * Ng + r0] = mkc<T>(sh.red[0], sh.red[256]);
       __syncthreads();  // red is reused by the next right-hand side
-      continue;
     }
-    // all non-zeros of the block at once (independent loads), then row sums
-    for (int k = k0 + tid; k < k1; k += 256) {
-      const T w = val[k];
-      const cx<T> xv = xr[col[k]];
-      prod[k - k0] = mkc<T>(w * xv.x, w * xv.y);
+    return;
+  }
+  // the block's entries of P (PER per thread) and row starts: every load
+  // issued before any is used
+  T w[PER];
+  int c[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int k = k0 + tid + i * 256;
+    w[i] = k < k1 ? val[k] : T(0);
+    c[i] = k < k1 ? col[k] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < RPER; ++i) {
+    const int j = tid + i * 256;
+    if (j <= r1 - r0) sh.rp[j] = rowptr[r0 + j] - k0;
+  }
+  for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
+    const cx<T>* xr = x + rhs * n;
+    cx<T>* qr = q + rhs * Ng;
+    cx<T> xv[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) xv[i] = xr[c[i]];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int k = tid + i * 256;
+      if (k < k1 - k0) prod[k] = mkc<T>(w[i] * xv[i].x, w[i] * xv[i].y);
     }
     __syncthreads();
+    // row sums from LDS, four interleaved partial sums per row (fixed order)
     for (int r = r0 + tid; r < r1; r += 256) {
-      T ar = T(0), ai = T(0);
-      const int e = rowptr[r + 1] - k0;
-      for (int k = rowptr[r] - k0; k < e; ++k) {
-        ar += prod[k].x;
-        ai += prod[k].y;
+      const int e = sh.rp[r - r0 + 1];
+      int k = sh.rp[r - r0];
+      T ar[4] = {T(0), T(0), T(0), T(0)}, ai[4] = {T(0), T(0), T(0), T(0)};
+      for (; k + 4 <= e; k += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ar[u] += prod[k + u].x;
+          ai[u] += prod[k + u].y;
+        }
       }
-      qr[r] = mkc<T>(ar, ai);
+      for (int u = 0; k < e; ++k, ++u) {
+        ar[u] += prod[k].x;
+        ai[u] += prod[k].y;
+      }
+      qr[r] = mkc<T>((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
     }
     __syncthreads();  // prod is reused by the next right-hand side
   }

@@ -428,11 +428,20 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t) {
         t.p_val[fill[u]++] = t.pt_val[k];
       }
     // row blocks: consecutive rows with at most kProjNnz non-zeros and
-    // kProjRows rows; a longer row forms a block of its own
+    // kProjRows rows; a longer row forms a block of its own, and a run of at
+    // least kProjRows empty rows (nodes no stencil reaches) forms a zero
+    // block of up to kProjZeroRows rows
     t.p_blk.assign(1, 0);
     int64_t r = 0;
     while (r < Ng) {
       int64_t e = r, nz = 0;
+      while (e < Ng && e - r < kProjZeroRows && t.p_rowptr[e + 1] == t.p_rowptr[e]) ++e;
+      if (e - r >= kProjRows || e == Ng) {
+        t.p_blk.push_back(int32_t(e));
+        r = e;
+        continue;
+      }
+      e = r;
       while (e < Ng && e - r < kProjRows) {
         const int64_t len = t.p_rowptr[e + 1] - t.p_rowptr[e];
         if (e > r && nz + len > kProjNnz) break;
