@@ -274,12 +274,14 @@ aim_status aim_solve(aim_plan plan, const void* b_dev, void* x_dev, int32_t nrhs
 /* 0 project (P x), 1 x-forward FFT, 2 y-forward FFT, 3 z FFT * spectrum *
  * inverse z FFT, 4 y-inverse FFT, 5 x-inverse FFT, 6 interpolation + C x */
 
-/* Runs aim_matvec `reps` times with a HIP event recorded between every two
- * kernels on hip_stream, and returns in kernel_ms_host[AIM_N_KERNELS] the
- * average duration of each kernel in milliseconds (the stages of eq. LAIMx:
+/* Returns in kernel_ms_host[AIM_N_KERNELS] the average duration in
+ * milliseconds of each kernel of one matvec (the stages of eq. LAIMx:
  * projection, the zero-padded FFT convolution with the Toeplitz kernel, the
- * interpolation and the near-field correction).  Same arguments and errors
- * as aim_matvec (y_dev receives the product); blocking. */
+ * interpolation and the near-field correction): every kernel is launched
+ * `reps` times back to back on hip_stream between two HIP events, so the
+ * gaps between kernels are not counted.  Same arguments and errors as
+ * aim_matvec; y_dev receives the product (one ordinary matvec runs after the
+ * timed launches, which overwrite the plan's workspace); blocking. */
 aim_status aim_profile_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
                               int32_t nrhs, const int32_t* freq_idx_host, int32_t reps,
                               double* kernel_ms_host, void* hip_stream);

@@ -293,20 +293,23 @@ const int32_t* set_freq(aim_plan p, const int32_t* freq_host, int nrhs, hipStrea
 // The matvec schedule: projection, the pruned FFT convolution (five passes),
 // then interpolation fused with the near-field correction.  With ev != NULL,
 // ev[0..7] are recorded before, between and after the seven kernels.
+// With repeat > 1 (timing only) every kernel is launched `repeat` times in a
+// row, which leaves garbage in the workspace and y.
 template <typename T>
 void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
-                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev) {
+                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev, int repeat = 1) {
   const int pi = int(prec);
   void* grid = p->d_grid[pi];
   const void* spec = prec == AIM_C128 ? p->d_spec64 : p->d_spec32;
   void* const* tw = prec == AIM_C128 ? p->d_tw64 : p->d_tw32;
   if (ev) AIM_HIP(hipEventRecord(ev[0], s));
-  aim::launch_project<T>(p->g, p_dev(p, prec), p->d_pblk, p->nblk, x, p->t.N, grid, nrhs, s);
+  for (int r = 0; r < repeat; ++r)
+    aim::launch_project<T>(p->g, p_dev(p, prec), p->d_pblk, p->nblk, x, p->t.N, grid, nrhs, s);
   if (ev) AIM_HIP(hipEventRecord(ev[1], s));
   aim::launch_convolve<T>(p->g, grid, p->d_work[pi], grid, spec, dfreq, nrhs, tw, s,
-                          ev ? ev + 2 : nullptr, p->sched[pi]);
+                          ev ? ev + 2 : nullptr, p->sched[pi], repeat);
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
-  interp_near<T>(p, prec, grid, x, y, nrhs, true, true, s);
+  for (int r = 0; r < repeat; ++r) interp_near<T>(p, prec, grid, x, y, nrhs, true, true, s);
   if (ev) AIM_HIP(hipEventRecord(ev[7], s));
 }
 
@@ -697,22 +700,28 @@ aim_status aim_profile_matvec(aim_plan p, aim_precision prec, const void* x, voi
     AIM_REQUIRE(reps >= 1, AIM_ERR_INVALID_ARG, "reps must be >= 1");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
-    std::vector<hipEvent_t> ev(8 * size_t(reps), nullptr);
+    // each kernel launched reps times back to back between two events, so
+    // that the gaps between kernels do not count; an ordinary matvec first
+    // (warm-up) and last (y = A x, as the repeated kernels leave garbage)
+    std::vector<hipEvent_t> ev(8, nullptr);
     auto destroy = [&] {
       for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     };
     try {
       for (auto& e : ev) AIM_HIP(hipEventCreate(&e));
-      for (int r = 0; r < reps; ++r) matvec_any(p, prec, x, y, nrhs, df, s, &ev[8 * size_t(r)]);
+      matvec_any(p, prec, x, y, nrhs, df, s);
+      if (prec == AIM_C128)
+        matvec_impl<double>(p, prec, x, y, nrhs, df, s, ev.data(), reps);
+      else
+        matvec_impl<float>(p, prec, x, y, nrhs, df, s, ev.data(), reps);
+      matvec_any(p, prec, x, y, nrhs, df, s);
       AIM_HIP(hipStreamSynchronize(s));
-      for (int k = 0; k < AIM_N_KERNELS; ++k) kernel_ms[k] = 0.0;
-      for (int r = 0; r < reps; ++r)
-        for (int k = 0; k < AIM_N_KERNELS; ++k) {
-          float ms = 0.f;
-          AIM_HIP(hipEventElapsedTime(&ms, ev[8 * size_t(r) + k], ev[8 * size_t(r) + k + 1]));
-          kernel_ms[k] += ms / reps;
-        }
+      for (int k = 0; k < AIM_N_KERNELS; ++k) {
+        float ms = 0.f;
+        AIM_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+        kernel_ms[k] = double(ms) / reps;
+      }
     } catch (...) {
       destroy();
       throw;

@@ -123,7 +123,8 @@ template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
                      hipEvent_t* between = nullptr,  // 4 events recorded between passes
-                     const int* sched = nullptr);
+                     const int* sched = nullptr,
+                     int repeat = 1);  // each pass launched this many times (timing only)
 // whether launch shape v exists for an FFT pass of length L
 bool fft_variant_ok(bool dbl, int L, bool col, int v);
 

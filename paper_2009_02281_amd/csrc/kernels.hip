@@ -552,7 +552,7 @@ int64_t work_elems(const GridShape& g, int layout, size_t elem_bytes) {
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
-                     hipEvent_t* between, const int* sched) {
+                     hipEvent_t* between, const int* sched, int repeat) {
   static const int kDefault[kSchedLen] = {0, 0, 0, 0, 0, 0, 0};
   if (!sched) sched = kDefault;
   auto mark = [&](int i) {
@@ -582,13 +582,14 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     return a;
   };
   // x forward: rows (y, z) of q, Nx -> Mx, into A [Nz][Ny][Mx]
-  row_pass<T>(Mx, false, q, A, tw[0], Nz, Ny, Nx, Mx, int64_t(Ny) * Nx, PA, Ng, W, Nx, Mx, nrhs,
-              s, sched[0]);
+  for (int r = 0; r < repeat; ++r)
+    row_pass<T>(Mx, false, q, A, tw[0], Nz, Ny, Nx, Mx, int64_t(Ny) * Nx, PA, Ng, W, Nx, Mx,
+                nrhs, s, sched[0]);
   mark(0);
   // y forward: A [Nz][Ny][Mx] -> B [Nz][My][Mx]
   {
     const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, PA, Mx, PB, Ny, My);
-    fft_pass<T>(My, true, 0, A, B, tw[1], a, nrhs, s, sched[1]);
+    for (int r = 0; r < repeat; ++r) fft_pass<T>(My, true, 0, A, B, tw[1], a, nrhs, s, sched[1]);
   }
   mark(1);
   // z forward * spectrum * z inverse, in place on B, keeping z < Nz
@@ -603,26 +604,27 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     a.Ny = Ny;
     a.Mz = Mz;
     a.Nz = Nz;
-    fft_pass<T>(Mz, true, 2, B, B, tw[2], a, nrhs, s, sched[2]);
+    for (int r = 0; r < repeat; ++r) fft_pass<T>(Mz, true, 2, B, B, tw[2], a, nrhs, s, sched[2]);
   }
   mark(2);
   // y inverse: B [Nz][My][Mx] -> A [Nz][Ny][Mx]
   {
     const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, PB, Mx, PA, My, Ny);
-    fft_pass<T>(My, true, 1, B, A, tw[1], a, nrhs, s, sched[3]);
+    for (int r = 0; r < repeat; ++r) fft_pass<T>(My, true, 1, B, A, tw[1], a, nrhs, s, sched[3]);
   }
   mark(3);
   // x inverse: rows of A (Mx) -> phi (Nx)
-  row_pass<T>(Mx, true, A, phi, tw[0], Nz, Ny, Mx, Nx, PA, int64_t(Ny) * Nx, W, Ng, Mx, Nx, nrhs,
-              s, sched[4]);
+  for (int r = 0; r < repeat; ++r)
+    row_pass<T>(Mx, true, A, phi, tw[0], Nz, Ny, Mx, Nx, PA, int64_t(Ny) * Nx, W, Ng, Mx, Nx,
+                nrhs, s, sched[4]);
 }
 
 template void launch_convolve<double>(const GridShape&, const void*, void*, void*, const void*,
                                       const int32_t*, int, const void* const*, hipStream_t,
-                                      hipEvent_t*, const int*);
+                                      hipEvent_t*, const int*, int);
 template void launch_convolve<float>(const GridShape&, const void*, void*, void*, const void*,
                                      const int32_t*, int, const void* const*, hipStream_t,
-                                     hipEvent_t*, const int*);
+                                     hipEvent_t*, const int*, int);
 
 // ---------------------------------------------------------------------------
 // kernel spectrum: circulant embedding of G on the padded grid, full 3-D FFT,

@@ -327,3 +327,15 @@ def test_plan_checkpoint_gives_identical_matvecs(tmp_path):
     assert rel(host(q.matvec(dev(x))), o.matvec(x, w.k[0])) <= FP64_TOL
     q.close()
     p.set_schedule([0] * 7, prec="c64")
+
+
+def test_profile_matvec_times_every_kernel_and_leaves_the_product():
+    """aim_profile_matvec: seven positive kernel durations, and y_dev holds
+    the same product as an ordinary matvec (the repeated timing launches
+    overwrite the workspace first)."""
+    w, o, p = _setup("boxes")
+    x = dev(I.complex_gaussian(o.N, 171, nrhs=2))
+    y = torch.empty_like(x)
+    ms = p.profile_matvec(x, reps=4, out=y)
+    assert list(ms) == binding.KERNELS and all(v > 0 for v in ms.values())
+    assert torch.equal(y, p.matvec(x))
