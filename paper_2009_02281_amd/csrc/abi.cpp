@@ -160,8 +160,16 @@ struct aim_plan_s {
     double* nrm = nullptr;
     int32_t* idx = nullptr;
     int32_t* freq = nullptr;
-    double2* h_host = nullptr;  // pinned
-    double* nrm_host = nullptr;
+    double* nrm_host = nullptr;  // pinned
+    // device-side Givens state of a restart cycle (givens_step) and its
+    // pinned host mirrors
+    void *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+    aim::GivensState* gst = nullptr;
+    double* scale = nullptr;
+    double2* H_host = nullptr;
+    double2* g_host = nullptr;
+    aim::GivensState* gst_host = nullptr;
+    double* scale_host = nullptr;
   } sv;
 
   void* dalloc(size_t bytes, hipStream_t s) {
@@ -199,8 +207,11 @@ struct aim_plan_s {
         (void)hipFree(o.first);
     }
     if (h_rhs_freq) (void)hipHostFree(h_rhs_freq);
-    if (sv.h_host) (void)hipHostFree(sv.h_host);
     if (sv.nrm_host) (void)hipHostFree(sv.nrm_host);
+    if (sv.H_host) (void)hipHostFree(sv.H_host);
+    if (sv.g_host) (void)hipHostFree(sv.g_host);
+    if (sv.gst_host) (void)hipHostFree(sv.gst_host);
+    if (sv.scale_host) (void)hipHostFree(sv.scale_host);
   }
 };
 
@@ -1022,22 +1033,39 @@ void ensure_solver(aim_plan p, int nrhs, int m, hipStream_t s) {
   w.bp = p->dalloc(vec * R, s);
   w.xp = p->dalloc(vec * R, s);
   w.ain = p->dalloc(vec * R, s);
-  w.h = p->dalloc(size_t(16) * R * (M + 1), s);
-  w.h2 = p->dalloc(size_t(16) * R * (M + 1), s);
+  // the two Gram-Schmidt coefficient sets and the basis norms of a step
+  const size_t hb = size_t(16) * R * (M + 1);
+  w.h = p->dalloc(2 * hb + sizeof(double) * R, s);
+  w.h2 = static_cast<char*>(w.h) + hb;
   w.y = p->dalloc(size_t(16) * R * (M + 1), s);
   const int64_t nchunk = (n + 4095) / 4096;
   w.partial = p->dalloc(size_t(16) * R * (M + 1) * nchunk, s);
-  w.nrm = static_cast<double*>(p->dalloc(sizeof(double) * R, s));
+  w.nrm = reinterpret_cast<double*>(static_cast<char*>(w.h) + 2 * hb);
   w.idx = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * R, s));
   w.freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * R, s));
   if (p->prec & (1u << AIM_C64)) {
     w.c64a = p->dalloc(size_t(n) * 8 * R, s);
     w.c64b = p->dalloc(size_t(n) * 8 * R, s);
   }
-  if (w.h_host) (void)hipHostFree(w.h_host);
+  w.H = p->dalloc(size_t(16) * R * M * (M + 1), s);
+  w.cs = p->dalloc(size_t(16) * R * M, s);
+  w.sn = p->dalloc(size_t(16) * R * M, s);
+  w.g = p->dalloc(size_t(16) * R * (M + 1), s);
+  w.gst = static_cast<aim::GivensState*>(p->dalloc(sizeof(aim::GivensState) * R, s));
+  w.scale = static_cast<double*>(p->dalloc(sizeof(double) * R, s));
   if (w.nrm_host) (void)hipHostFree(w.nrm_host);
-  // two Gram-Schmidt passes of up to M+1 coefficients per system
-  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.h_host), sizeof(double2) * 2 * R * (M + 1), 0));
+  if (w.H_host) (void)hipHostFree(w.H_host);
+  if (w.g_host) (void)hipHostFree(w.g_host);
+  if (w.gst_host) (void)hipHostFree(w.gst_host);
+  if (w.scale_host) (void)hipHostFree(w.scale_host);
+  w.nrm_host = nullptr;
+  w.H_host = w.g_host = nullptr;
+  w.gst_host = nullptr;
+  w.scale_host = nullptr;
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.H_host), size_t(16) * R * M * (M + 1), 0));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.g_host), size_t(16) * R * (M + 1), 0));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.gst_host), sizeof(aim::GivensState) * R, 0));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.scale_host), sizeof(double) * R, 0));
   AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.nrm_host), sizeof(double) * R * 2, 0));
   w.nrhs = R;
   w.m = M;
@@ -1046,12 +1074,14 @@ void ensure_solver(aim_plan p, int nrhs, int m, hipStream_t s) {
 
 // Operator application used by the Krylov loop: y = A(k_f) x in the requested
 // precision on complex128 vectors (complex64 matvec through casts).  The
-// matvec runs from fixed staging buffers through a captured graph (one per
-// precision, batch width and frequency set), so each Krylov step replays the
-// seven kernels with one launch.
+// Krylov loop leaves the host only every few steps, so the host enqueues well
+// ahead of the GPU and the seven kernels are launched directly; with
+// AIM_SOLVER_GRAPHS=1 they replay instead from a captured graph (one per
+// precision, batch width and frequency set) fed through fixed staging
+// buffers, which costs a copy per step.
 bool solver_graphs_enabled() {
   const char* e = std::getenv("AIM_SOLVER_GRAPHS");
-  return !(e && e[0] == '0');
+  return e && e[0] == '1';
 }
 
 void graph_matvec(aim_plan p, aim_precision prec, const void* in, void* out, int nrhs,
@@ -1080,6 +1110,10 @@ void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, c
              hipStream_t s) {
   const int64_t cnt = p->t.N * int64_t(nrhs);
   if (prec == AIM_C128) {
+    if (!solver_graphs_enabled()) {
+      matvec_any(p, AIM_C128, x, y, nrhs, dfreq, s);
+      return;
+    }
     AIM_HIP(hipMemcpyAsync(p->sv.ain, x, size_t(cnt) * 16, hipMemcpyDeviceToDevice, s));
     graph_matvec(p, AIM_C128, p->sv.ain, y, nrhs, dfreq, s);
   } else {
@@ -1202,6 +1236,11 @@ using CycleHook = std::function<void(const void*, const void*, const std::vector
 // extending its Krylov basis once its residual estimate is below tol * scale;
 // the true residual decides convergence at every restart.  Returns per-system
 // true relative residual (w.r.t. scale) in rel.
+// Arnoldi steps between two looks of the host at the device-side GMRES state
+// (a cycle whose systems have all converged runs at most this many steps
+// too many)
+constexpr int kSyncEvery = 4;
+
 void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, void* x, int nrhs,
                  const int32_t* dfreq, const std::vector<double>& scale, double tol, int m,
                  int max_iter, bool x_is_zero, hipStream_t s, CycleStats& st,
@@ -1245,21 +1284,31 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
     const int mm = std::min(m, maxit_left);
     // V_0 = r / beta
     aim::launch_scale_inv(w.r, w.nrm, w.V, n, nrhs, n, s);
-    // Hessenberg per system on the host, Givens rotations
-    std::vector<std::vector<cplx>> H(nrhs, std::vector<cplx>((mm + 1) * mm, 0.0));
-    std::vector<std::vector<cplx>> cs(nrhs, std::vector<cplx>(mm)), sn(nrhs, std::vector<cplx>(mm));
-    std::vector<std::vector<cplx>> g(nrhs, std::vector<cplx>(mm + 1, 0.0));
-    std::vector<int> len(nrhs, 0);
-    std::vector<char> frozen(nrhs, 0);
+    // cycle state on the device: g = (beta, 0, ...), the frozen flags and the
+    // step counts; the Hessenberg columns and rotations stay there too, and
+    // the host looks at the state only every kSyncEvery steps
+    const int mc = w.m;  // column capacity of H, cs, sn, g
     for (int r = 0; r < nrhs; ++r) {
-      g[r][0] = beta[r];
-      frozen[r] = (rel[r] <= tol || active_iters[r] >= max_iter) ? 1 : 0;
+      for (int i = 0; i <= mc; ++i) w.g_host[size_t(r) * (mc + 1) + i] = make_double2(0.0, 0.0);
+      w.g_host[size_t(r) * (mc + 1)] = make_double2(beta[r], 0.0);
+      w.gst_host[r].len = 0;
+      w.gst_host[r].frozen = (rel[r] <= tol || active_iters[r] >= max_iter) ? 1 : 0;
+      w.gst_host[r].iters = active_iters[r];
+      w.gst_host[r].nonfinite = 0;
+      w.scale_host[r] = scale[r];
     }
+    AIM_HIP(hipMemcpyAsync(w.g, w.g_host, sizeof(double2) * nrhs * (mc + 1),
+                           hipMemcpyHostToDevice, s));
+    AIM_HIP(hipMemcpyAsync(w.gst, w.gst_host, sizeof(aim::GivensState) * nrhs,
+                           hipMemcpyHostToDevice, s));
+    AIM_HIP(hipMemcpyAsync(w.scale, w.scale_host, sizeof(double) * nrhs, hipMemcpyHostToDevice,
+                           s));
     int j = 0;
     for (; j < mm; ++j) {
       void* Vj = static_cast<char*>(w.V) + size_t(j) * nrhs * vec;
-      void* Zj = static_cast<char*>(w.Z) + size_t(j) * nrhs * vec;
-      apply_M(p, pc, Vj, Zj, nrhs, s);  // z_j = M(v_j)
+      // z_j = M(v_j); without a preconditioner the basis Z is V itself
+      void* Zj = pc == AIM_PC_NONE ? Vj : static_cast<char*>(w.Z) + size_t(j) * nrhs * vec;
+      if (pc != AIM_PC_NONE) apply_M(p, pc, Vj, Zj, nrhs, s);
       apply_A(p, prec, Zj, w.d, nrhs, dfreq, s);  // w.d = A z_j
       st.matvecs++;
       // classical Gram-Schmidt, twice
@@ -1270,69 +1319,55 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
       aim::launch_norms(w.d, n, nrhs, w.partial, w.nrm, s);
       aim::launch_scale_inv(w.d, w.nrm, static_cast<char*>(w.V) + size_t(j + 1) * nrhs * vec, n,
                             nrhs, n, s);
-      AIM_HIP(hipMemcpyAsync(w.h_host, w.h, sizeof(double2) * nrhs * (j + 1), hipMemcpyDeviceToHost, s));
-      AIM_HIP(hipMemcpyAsync(w.h_host + nrhs * (j + 1), w.h2, sizeof(double2) * nrhs * (j + 1),
-                             hipMemcpyDeviceToHost, s));
-      AIM_HIP(hipMemcpyAsync(w.nrm_host, w.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-      AIM_HIP(hipStreamSynchronize(s));
-      bool all_frozen = true;
-      for (int r = 0; r < nrhs; ++r) {
-        if (frozen[r]) continue;
-        auto& Hr = H[r];
-        auto Hat = [&](int i, int c) -> cplx& { return Hr[i * mm + c]; };
-        for (int i = 0; i <= j; ++i) {
-          const double2 a = w.h_host[r * (j + 1) + i];
-          const double2 c = w.h_host[nrhs * (j + 1) + r * (j + 1) + i];
-          Hat(i, j) = cplx(a.x + c.x, a.y + c.y);
+      aim::launch_givens_step(w.h, w.h2, w.nrm, nrhs, j, mc, w.H, w.cs, w.sn, w.g, w.gst, w.scale,
+                              tol, max_iter, s);
+      if ((j + 1) % kSyncEvery == 0 || j + 1 == mm) {
+        AIM_HIP(hipMemcpyAsync(w.gst_host, w.gst, sizeof(aim::GivensState) * nrhs,
+                               hipMemcpyDeviceToHost, s));
+        AIM_HIP(hipStreamSynchronize(s));
+        bool all_frozen = true;
+        for (int r = 0; r < nrhs; ++r) {
+          if (w.gst_host[r].nonfinite) throw Error(AIM_ERR_BREAKDOWN, "non-finite Arnoldi norm");
+          if (!w.gst_host[r].frozen) all_frozen = false;
         }
-        const double hn = w.nrm_host[r];
-        if (!std::isfinite(hn)) throw Error(AIM_ERR_BREAKDOWN, "non-finite Arnoldi norm");
-        Hat(j + 1, j) = hn;
-        for (int i = 0; i < j; ++i) {
-          const cplx tmp = cs[r][i] * Hat(i, j) + sn[r][i] * Hat(i + 1, j);
-          Hat(i + 1, j) = -std::conj(sn[r][i]) * Hat(i, j) + std::conj(cs[r][i]) * Hat(i + 1, j);
-          Hat(i, j) = tmp;
+        if (all_frozen) {
+          ++j;
+          break;
         }
-        const cplx a = Hat(j, j), bb = Hat(j + 1, j);
-        const double den = std::sqrt(std::norm(a) + std::norm(bb));
-        if (den == 0.0) {
-          frozen[r] = 1;
-          continue;
-        }
-        if (std::abs(a) == 0.0) {
-          cs[r][j] = 0.0;
-          sn[r][j] = 1.0;
-        } else {
-          cs[r][j] = std::abs(a) / den;
-          sn[r][j] = (a / std::abs(a)) * std::conj(bb) / den;
-        }
-        Hat(j, j) = cs[r][j] * a + sn[r][j] * bb;
-        Hat(j + 1, j) = 0.0;
-        g[r][j + 1] = -std::conj(sn[r][j]) * g[r][j];
-        g[r][j] = cs[r][j] * g[r][j];
-        len[r] = j + 1;
-        active_iters[r]++;
-        const double est = std::abs(g[r][j + 1]) / scale[r];
-        if (est <= tol || hn == 0.0 || active_iters[r] >= max_iter) frozen[r] = 1;
-        if (!frozen[r]) all_frozen = false;
-      }
-      if (all_frozen) {
-        ++j;
-        break;
       }
     }
-    // y = H^{-1} g per system, then x += Z y
+    // the cycle's columns of H and g back to the host
+    AIM_HIP(hipMemcpyAsync(w.H_host, w.H, sizeof(double2) * ((nrhs - 1) * size_t(mc) + j) * (mc + 1),
+                           hipMemcpyDeviceToHost, s));
+    AIM_HIP(hipMemcpyAsync(w.g_host, w.g, sizeof(double2) * nrhs * (mc + 1),
+                           hipMemcpyDeviceToHost, s));
+    AIM_HIP(hipMemcpyAsync(w.gst_host, w.gst, sizeof(aim::GivensState) * nrhs,
+                           hipMemcpyDeviceToHost, s));
+    AIM_HIP(hipStreamSynchronize(s));
+    std::vector<int> len(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) {
+      if (w.gst_host[r].nonfinite) throw Error(AIM_ERR_BREAKDOWN, "non-finite Arnoldi norm");
+      len[r] = w.gst_host[r].len;
+      active_iters[r] = w.gst_host[r].iters;
+    }
+    // y = H^{-1} g per system (H upper triangular after the rotations), then
+    // x += Z y
     const int nv = *std::max_element(len.begin(), len.end());
     if (nv > 0) {
       std::vector<double2> yh(size_t(nrhs) * m);
       for (auto& v : yh) v.x = v.y = 0.0;
       for (int r = 0; r < nrhs; ++r) {
         const int L = len[r];
+        auto Hat = [&](int i, int c) {
+          const double2 e = w.H_host[(size_t(r) * mc + c) * (mc + 1) + i];
+          return cplx(e.x, e.y);
+        };
         std::vector<cplx> yv(L);
         for (int i = L - 1; i >= 0; --i) {
-          cplx acc = g[r][i];
-          for (int c = i + 1; c < L; ++c) acc -= H[r][i * mm + c] * yv[c];
-          yv[i] = acc / H[r][i * mm + i];
+          const double2 gi = w.g_host[size_t(r) * (mc + 1) + i];
+          cplx acc(gi.x, gi.y);
+          for (int c = i + 1; c < L; ++c) acc -= Hat(i, c) * yv[c];
+          yv[i] = acc / Hat(i, i);
         }
         for (int i = 0; i < L; ++i) {
           yh[size_t(r) * m + i].x = yv[i].real();
@@ -1340,7 +1375,7 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
         }
       }
       AIM_HIP(hipMemcpyAsync(w.y, yh.data(), sizeof(double2) * yh.size(), hipMemcpyHostToDevice, s));
-      aim::launch_combine(w.Z, si, sr, w.y, m, nv, x, n, nrhs, s);
+      aim::launch_combine(pc == AIM_PC_NONE ? w.V : w.Z, si, sr, w.y, m, nv, x, n, nrhs, s);
       AIM_HIP(hipStreamSynchronize(s));  // yh is pageable host memory
     }
   }

@@ -172,6 +172,18 @@ void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out
 // out[r] = w[r] * (1 / nrm[r]) (0 if nrm == 0)
 void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
                       int64_t out_stride, hipStream_t s);
+// GMRES state of one system in a restart cycle (device, givens_step)
+struct GivensState {
+  int len;        // columns of H in use this cycle
+  int frozen;     // 1: takes no more steps this cycle
+  int iters;      // Krylov steps over the whole solve
+  int nonfinite;  // 1: a non-finite basis norm was met
+};
+// One Arnoldi step's Hessenberg column, Givens rotation and residual estimate
+// for every system (see givens_step_kernel)
+void launch_givens_step(const void* h, const void* h2, const double* nrm, int nrhs, int j,
+                        int mcap, void* H, void* cs, void* sn, void* g, GivensState* st,
+                        const double* scale, double tol, int max_iter, hipStream_t s);
 // x[r] += sum_i y[r][i] Z_i,r
 void launch_combine(const void* Z, int64_t si, int64_t sr, const void* y, int64_t ldy, int nv,
                     void* x, int64_t n, int nrhs, hipStream_t s);

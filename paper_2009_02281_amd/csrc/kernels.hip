@@ -172,6 +172,45 @@ struct Dft<T, 16, INV> {
   }
 };
 
+// 32 points as 4 x 8: n = 8 n1 + n2, k = k1 + 4 k2; 4-point DFTs over n1,
+// twiddles W32^(n2 k1), 8-point DFTs over n2
+constexpr double kCos32[8] = {1.0, 0.9807852804032304, 0.9238795325112867, 0.8314696123025452,
+                              0.7071067811865476, 0.5555702330196023, 0.38268343236508984,
+                              0.19509032201612833};  // cos(2 pi r / 32)
+constexpr double kSin32[8] = {0.0, 0.19509032201612825, 0.3826834323650898, 0.5555702330196022,
+                              0.7071067811865475, 0.8314696123025452, 0.9238795325112867,
+                              0.9807852804032304};   // sin(2 pi r / 32)
+template <typename T, bool INV>
+struct Dft<T, 32, INV> {
+  // a * W32^m (e^{-2 pi i m / 32} forward): the first-octant twiddle of
+  // m mod 8, then a quarter turn for each 8 in m
+  static __device__ __forceinline__ cx<T> w(cx<T> a, int m) {
+    const int r = m % 8, q = m / 8;
+    if (r != 0) a = cmul(a, mkc<T>(T(kCos32[r]), INV ? T(kSin32[r]) : -T(kSin32[r])));
+    for (int i = 0; i < q; ++i) a = rot90<T, INV>(a);
+    return a;
+  }
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    cx<T> a[8][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) {
+      cx<T> u[4] = {v[n2], v[8 + n2], v[16 + n2], v[24 + n2]};
+      Dft<T, 4, INV>::run(u);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = w(u[k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cx<T> u[8];
+#pragma unroll
+      for (int n2 = 0; n2 < 8; ++n2) u[n2] = a[n2][k1];
+      Dft<T, 8, INV>::run(u);
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) v[k1 + 4 * k2] = u[k2];
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Register-resident Stockham FFT.  A length-L line is shared by NT threads;
 // each holds E = L/NT elements in registers.  Stage s with radix R treats
@@ -395,8 +434,10 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <typename T, int L, bool COL, int V>
 struct Shape {
   static constexpr int kTL = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
-  // V 0-3: 8 elements per thread (radix-8 stages); V 4-5: 16 (radix 16)
-  static constexpr int NT = V >= 4 ? cmax(1, L / 16)
+  // V 0-3: 8 elements per thread (radix-8 stages); V 4-5: 16 (radix 16);
+  // V 6: 32 (radix 32: one exchange for L = 512 = 32 x 16)
+  static constexpr int NT = V == 6 ? cmax(1, L / 32)
+                          : V >= 4 ? cmax(1, L / 16)
                           : COL ? (V == 0 ? cmin(L / 8, 256 / kTL)
                                   : V == 1 ? cmin(L / 8, 512 / kTL)
                                   : V == 2 ? cmin(L / 8, 256 / (2 * kTL))
@@ -405,7 +446,8 @@ struct Shape {
                                   : V == 1 ? cmin(L / 8, 128)
                                   : V == 2 ? cmin(L / 8, 32)
                                            : cmin(L / 8, 64));
-  static constexpr int TL = V >= 4 ? cmax(1, (V == 4 ? 256 : 128) / NT)
+  static constexpr int TL = V == 6 ? cmax(1, 256 / NT)
+                          : V >= 4 ? cmax(1, (V == 4 ? 256 : 128) / NT)
                           : COL ? (V == 0 ? 256 / cmin(L / 8, 256 / kTL)
                                   : V == 1 ? 512 / cmin(L / 8, 512 / kTL)
                                   : V == 2 ? 256 / cmin(L / 8, 256 / (2 * kTL))
@@ -413,13 +455,14 @@ struct Shape {
                                 : (V == 3 ? 512 / NT : cmax(1, 256 / NT));
   // radix-16 stages for the 16-element shapes: one exchange fewer per
   // transform for L = 128 and 256
-  static constexpr int RMAX = V >= 4 && L >= 16 ? 16 : 8;
+  static constexpr int RMAX = V == 6 ? (L >= 32 ? 32 : 8) : V >= 4 && L >= 16 ? 16 : 8;
   static constexpr int THREADS = TL * NT;
   static constexpr size_t LDS = sizeof(cx<T>) * (COL ? size_t(L) * TL : size_t(TL) * (L + 1)) +
                                 sizeof(cx<T>) * L;
   static constexpr bool OK = THREADS >= 64 && THREADS <= 1024 && LDS <= 160 * 1024 &&
                              (TL & (TL - 1)) == 0 &&
-                             (V < 4 || (L >= 16 && (!COL || TL * sizeof(T) * 2 >= 64)));
+                             (V < 4 || (L >= 16 && (!COL || TL * sizeof(T) * 2 >= 64))) &&
+                             (V != 6 || L >= 32);
 };
 
 template <typename T, int L, bool COL, int V>
@@ -460,6 +503,8 @@ void pass_L(bool col, int mode, int variant, const void* in, void* out, const vo
     case 9: launch_shape<T, L, true, 4>(mode, i, o, w, a, nrhs, s); break;
     case 10: launch_shape<T, L, false, 5>(mode, i, o, w, a, nrhs, s); break;
     case 11: launch_shape<T, L, true, 5>(mode, i, o, w, a, nrhs, s); break;
+    case 12: launch_shape<T, L, false, 6>(mode, i, o, w, a, nrhs, s); break;
+    case 13: launch_shape<T, L, true, 6>(mode, i, o, w, a, nrhs, s); break;
     default: throw Error(AIM_ERR_INVALID_ARG, "FFT launch shape out of range");
   }
 }
@@ -494,6 +539,8 @@ bool shape_ok_L(bool col, int v) {
     case 9: return Shape<T, L, true, 4>::OK;
     case 10: return Shape<T, L, false, 5>::OK;
     case 11: return Shape<T, L, true, 5>::OK;
+    case 12: return Shape<T, L, false, 6>::OK;
+    case 13: return Shape<T, L, true, 6>::OK;
     default: return false;
   }
 }
@@ -1270,32 +1317,49 @@ void launch_block_dot(const void* V, int64_t si, int64_t sr, const void* w, int6
   AIM_HIP(hipGetLastError());
 }
 
-// w[r] -= sum_{i < nv} h[r][i] V[r][i]
-__global__ __launch_bounds__(256) void block_update_kernel(const double2* __restrict__ V,
-                                                           int64_t si, int64_t sr,
-                                                           double2* __restrict__ w,
-                                                           int64_t n, int nv,
-                                                           const double2* __restrict__ h,
-                                                           int64_t ldh) {
+// w[r] -/+= sum_{i < nv} h[r][i] V[r][i] (Gram-Schmidt update, SUB; the
+// restart update x += Z y, !SUB): one element per thread (the launch covers
+// every element, so all CUs take part), four basis vectors loaded together
+// per step; the order of the terms is fixed
+template <bool SUB>
+__global__ __launch_bounds__(128) void basis_axpy_kernel(const double2* __restrict__ V,
+                                                         int64_t si, int64_t sr,
+                                                         double2* __restrict__ w, int64_t n,
+                                                         int nv, const double2* __restrict__ h,
+                                                         int64_t ldh) {
   const int r = blockIdx.y;
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
   const double2* hr = h + int64_t(r) * ldh;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
-       k += int64_t(gridDim.x) * blockDim.x) {
-    double2 acc = w[int64_t(r) * n + k];
-    for (int i = 0; i < nv; ++i) {
-      const double2 a = V[(int64_t(i) * si + int64_t(r) * sr) * n + k];
-      const double2 c = hr[i];
-      acc.x -= c.x * a.x - c.y * a.y;
-      acc.y -= c.x * a.y + c.y * a.x;
+  const double2* vr = V + int64_t(r) * sr * n + k;
+  const int64_t vs = si * n;
+  double2 acc = w[int64_t(r) * n + k];
+  auto term = [&](double2 c, double2 a) {
+    const double re = c.x * a.x - c.y * a.y, im = c.x * a.y + c.y * a.x;
+    if (SUB) {
+      acc.x -= re;
+      acc.y -= im;
+    } else {
+      acc.x += re;
+      acc.y += im;
     }
-    w[int64_t(r) * n + k] = acc;
+  };
+  int i = 0;
+  for (; i + 4 <= nv; i += 4) {
+    double2 a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = vr[int64_t(i + u) * vs];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) term(hr[i + u], a[u]);
   }
+  for (; i < nv; ++i) term(hr[i], vr[int64_t(i) * vs]);
+  w[int64_t(r) * n + k] = acc;
 }
 
 void launch_block_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv,
                          int nrhs, const void* h, int64_t ldh, hipStream_t s) {
-  hipLaunchKernelGGL(block_update_kernel, dim3(grid_for(n, 256 * 4), nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(V), si, sr, static_cast<double2*>(w), n, nv,
+  hipLaunchKernelGGL(basis_axpy_kernel<true>, dim3(unsigned((n + 127) / 128), nrhs), dim3(128), 0,
+                     s, static_cast<const double2*>(V), si, sr, static_cast<double2*>(w), n, nv,
                      static_cast<const double2*>(h), ldh);
   AIM_HIP(hipGetLastError());
 }
@@ -1355,29 +1419,124 @@ void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, in
   AIM_HIP(hipGetLastError());
 }
 
-__global__ void combine_kernel(const double2* __restrict__ Z, int64_t si, int64_t sr,
-                               const double2* __restrict__ y, int64_t ldy, int nv,
-                               double2* __restrict__ x, int64_t n) {
-  const int r = blockIdx.y;
-  const double2* yr = y + int64_t(r) * ldy;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
-       k += int64_t(gridDim.x) * blockDim.x) {
-    double2 acc = x[int64_t(r) * n + k];
-    for (int i = 0; i < nv; ++i) {
-      const double2 a = Z[(int64_t(i) * si + int64_t(r) * sr) * n + k];
-      const double2 c = yr[i];
-      acc.x += c.x * a.x - c.y * a.y;
-      acc.y += c.x * a.y + c.y * a.x;
-    }
-    x[int64_t(r) * n + k] = acc;
+// One Arnoldi step of restarted GMRES, on the device, thread r = system r
+// (the host loop it replaces read h, h2 and the norms back every step).
+// Column j of the Hessenberg matrix is the two Gram-Schmidt passes'
+// coefficients summed, with the new basis norm below the diagonal; the
+// earlier Givens rotations are applied to it, a new rotation zeroes its
+// subdiagonal entry, and the rotated right-hand side g gives the residual
+// estimate |g_{j+1}| / scale_r.  A system that is frozen does nothing; it
+// freezes when the estimate meets tol, max_iter is reached, the norm is zero
+// (lucky breakdown), the rotation denominator is zero, or the norm is not
+// finite (flagged).  H is stored column by column, ldH = (mcap + 1) per
+// column, mcap columns per system.
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+
+constexpr int kGivensMax = 256;  // restart lengths up to this (aim_solve allows 200)
+
+__global__ __launch_bounds__(64) void givens_step_kernel(
+    const double2* __restrict__ h, const double2* __restrict__ h2, const double* __restrict__ nrm,
+    int nrhs, int j, int mcap, double2* __restrict__ H, double2* __restrict__ cs,
+    double2* __restrict__ sn, double2* __restrict__ g, GivensState* __restrict__ st,
+    const double* __restrict__ scale, double tol, int max_iter) {
+  // the column and the earlier rotations are staged in LDS by all lanes; one
+  // lane runs the (sequential) rotation chain there; all lanes write back
+  __shared__ double2 col[kGivensMax + 1], c[kGivensMax], sv[kGivensMax];
+  __shared__ int done;
+  const int r = blockIdx.x, t = threadIdx.x;
+  GivensState& q = st[r];
+  if (q.frozen) return;  // uniform over the block
+  double2* colg = H + (int64_t(r) * mcap + j) * (mcap + 1);
+  double2* cg = cs + int64_t(r) * mcap;
+  double2* sg = sn + int64_t(r) * mcap;
+  double2* gr = g + int64_t(r) * (mcap + 1);
+  const double hn = nrm[r];
+  for (int i = t; i <= j; i += 64) col[i] = zadd(h[r * (j + 1) + i], h2[r * (j + 1) + i]);
+  for (int i = t; i < j; i += 64) {
+    c[i] = cg[i];
+    sv[i] = sg[i];
   }
+  __syncthreads();
+  if (t == 0) {
+    done = 0;
+    if (!isfinite(hn)) {
+      q.nonfinite = 1;
+      q.frozen = 1;
+      done = 1;
+    } else {
+      col[j + 1] = make_double2(hn, 0.0);
+      for (int i = 0; i < j; ++i) {
+        const double2 ci = col[i], cn = col[i + 1];
+        const double2 tt = zadd(zmul(c[i], ci), zmul(sv[i], cn));
+        const double2 ns = zmul(zconj(sv[i]), ci);
+        col[i + 1] = zadd(make_double2(-ns.x, -ns.y), zmul(zconj(c[i]), cn));
+        col[i] = tt;
+      }
+      const double2 a = col[j], bb = col[j + 1];
+      const double den = sqrt((a.x * a.x + a.y * a.y) + (bb.x * bb.x + bb.y * bb.y));
+      if (den == 0.0) {
+        q.frozen = 1;
+        done = 1;
+      } else {
+        const double aa = hypot(a.x, a.y);
+        double2 cj, sj;
+        if (aa == 0.0) {
+          cj = make_double2(0.0, 0.0);
+          sj = make_double2(1.0, 0.0);
+        } else {
+          cj = make_double2(aa / den, 0.0);
+          const double2 ph = make_double2(a.x / aa, a.y / aa);
+          const double2 tt = zmul(ph, zconj(bb));
+          sj = make_double2(tt.x / den, tt.y / den);
+        }
+        c[j] = cj;
+        sv[j] = sj;
+        col[j] = zadd(zmul(cj, a), zmul(sj, bb));
+        col[j + 1] = make_double2(0.0, 0.0);
+        const double2 gj = gr[j];
+        const double2 ng = zmul(zconj(sj), gj);
+        const double2 g1 = make_double2(-ng.x, -ng.y);
+        gr[j + 1] = g1;
+        gr[j] = zmul(cj, gj);
+        q.len = j + 1;
+        q.iters += 1;
+        const double est = hypot(g1.x, g1.y) / scale[r];
+        if (est <= tol || hn == 0.0 || q.iters >= max_iter) q.frozen = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (done) return;
+  for (int i = t; i <= j + 1; i += 64) colg[i] = col[i];
+  if (t == 0) {
+    cg[j] = c[j];
+    sg[j] = sv[j];
+  }
+}
+
+void launch_givens_step(const void* h, const void* h2, const double* nrm, int nrhs, int j,
+                        int mcap, void* H, void* cs, void* sn, void* g, GivensState* st,
+                        const double* scale, double tol, int max_iter, hipStream_t s) {
+  if (mcap > kGivensMax) throw Error(AIM_ERR_INVALID_ARG, "restart length too large");
+  hipLaunchKernelGGL(givens_step_kernel, dim3(unsigned(nrhs)), dim3(64), 0, s,
+                     static_cast<const double2*>(h), static_cast<const double2*>(h2), nrm, nrhs, j,
+                     mcap, static_cast<double2*>(H), static_cast<double2*>(cs),
+                     static_cast<double2*>(sn), static_cast<double2*>(g), st, scale, tol,
+                     max_iter);
+  AIM_HIP(hipGetLastError());
 }
 
 void launch_combine(const void* Z, int64_t si, int64_t sr, const void* y, int64_t ldy, int nv,
                     void* x, int64_t n, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(combine_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(Z), si, sr, static_cast<const double2*>(y), ldy,
-                     nv, static_cast<double2*>(x), n);
+  hipLaunchKernelGGL(basis_axpy_kernel<false>, dim3(unsigned((n + 127) / 128), nrhs), dim3(128),
+                     0, s, static_cast<const double2*>(Z), si, sr, static_cast<double2*>(x), n, nv,
+                     static_cast<const double2*>(y), ldy);
   AIM_HIP(hipGetLastError());
 }
 
