@@ -140,8 +140,9 @@ typedef struct {
  * Arnoldi orthogonalisation is always complex128 on the device. */
 typedef struct {
   double rtol;               /* target relative residual (> 0)                    */
-  /* (the solver replays captured matvec graphs; set AIM_SOLVER_GRAPHS=0 in
-     the environment to launch kernels one by one instead) */
+  /* (the solver launches the matvec kernels directly and reads its GMRES
+     state back every 4 steps; AIM_SOLVER_GRAPHS=1 in the environment makes
+     it replay captured matvec graphs instead) */
   int32_t restart;           /* Krylov subspace size m (1..200)                   */
   int32_t max_iter;          /* cap on inner iterations per right-hand side       */
   int32_t max_refine;        /* cap on refinement steps (inner = AIM_C64)          */
