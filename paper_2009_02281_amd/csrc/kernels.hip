@@ -944,6 +944,40 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Lane sub of LPR lanes accumulates its share of the sparse row [k0, k1) of
+// (col, val) against RB vectors v_j = base + j * stride: entries k0 + sub,
+// k0 + sub + LPR, ... taken kRowBatch at a time, their indices and values
+// loaded together, then the RB kRowBatch gathers, so a batch costs one
+// exposed latency instead of one per entry.  The order of the sums is fixed.
+constexpr int kRowBatch = 4;
+template <typename T, int LPR, int RB>
+__device__ __forceinline__ void row_gather(int k0, int k1, int sub, const int32_t* __restrict__ col,
+                                           const T* __restrict__ val, const cx<T>* __restrict__ base,
+                                           int64_t stride, int nr, T* ar, T* ai) {
+  for (int kb = k0 + sub; kb < k1; kb += LPR * kRowBatch) {
+    T w[kRowBatch];
+    int c[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int k = kb + u * LPR;
+      w[u] = k < k1 ? val[k] : T(0);
+      c[u] = k < k1 ? col[k] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < nr) {
+        cx<T> v[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) v[u] = base[j * stride + c[u]];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          ar[j] += w[u] * v[u].x;
+          ai[j] += w[u] * v[u].y;
+        }
+      }
+  }
+}
+
 template <typename T, int LPR, bool INTERP, bool NEARC, int RB>
 __global__ __launch_bounds__(256) void interp_near_kernel(
     const cx<T>* __restrict__ phi, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
@@ -958,7 +992,14 @@ __global__ __launch_bounds__(256) void interp_near_kernel(
   T ar[RB], ai[RB];
 #pragma unroll
   for (int j = 0; j < RB; ++j) ar[j] = ai[j] = T(0);
-  if (i < n) {
+  if (RB > 1 && i < n) {  // several vectors: batched entries (see row_gather)
+    if constexpr (INTERP)
+      row_gather<T, LPR, RB>(prow[i], prow[i + 1], sub, pcol, pval, phi + rhs0 * Ng, Ng, nr, ar,
+                             ai);
+    if constexpr (NEARC)
+      row_gather<T, LPR, RB>(rowptr[i], rowptr[i + 1], sub, col, val, x + rhs0 * n, n, nr, ar,
+                             ai);
+  } else if (i < n) {
     if constexpr (INTERP) {
       for (int k = prow[i] + sub; k < prow[i + 1]; k += LPR) {
         const T w = pval[k];
