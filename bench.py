@@ -336,7 +336,7 @@ def main() -> int:
           flush=True)
     tuned = {}
     for pr in precs:
-        tuned[pr] = plan.autotune(prec=pr, nrhs=args.nrhs, reps=5)
+        tuned[pr] = plan.autotune(prec=pr, nrhs=args.nrhs, reps=10)
         print(f"[bench] autotuned FFT launch shapes ({pr}): {tuned[pr]['schedule']} "
               f"pass ms {[round(t, 4) for t in tuned[pr]['pass_ms']]}", file=sys.stderr,
               flush=True)

@@ -98,8 +98,8 @@ struct CsrDevice {
 // q = P x over row blocks of P (each block holds at most kProjNnz non-zeros
 // and kProjRows rows, or is one longer row on its own, or is a run of empty
 // rows)
-constexpr int kProjNnz = 2048;
-constexpr int kProjRows = 1024;
+constexpr int kProjNnz = 1024;
+constexpr int kProjRows = 512;
 constexpr int kProjZeroRows = 16384;  // rows of a block that only writes zeros
 template <typename T>
 void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, int nblk,
