@@ -793,7 +793,7 @@ std::vector<double> twiddles64(int L) {
 // reaches get their zero written by the same pass; long runs of them form
 // blocks of their own that only store zeros.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int PR>
 __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ x,
                                                       cx<T>* __restrict__ q,
                                                       const int32_t* __restrict__ rowptr,
@@ -802,7 +802,9 @@ __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ 
                                                       const int32_t* __restrict__ blk, int64_t n,
                                                       int64_t Ng, int nrhs, int rb) {
   constexpr int PER = kProjNnz / 256, RPER = kProjRows / 256 + 1;
-  __shared__ cx<T> prod[kProjNnz];
+  // PR right-hand sides side by side: their gathers in flight together, their
+  // products in PR slices of LDS
+  __shared__ cx<T> prod[PR * kProjNnz];
   __shared__ union {
     T red[2 * 256];           // long row
     int rp[kProjRows + 1];    // row starts of the block, relative to its first non-zero
@@ -810,8 +812,8 @@ __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ 
   const int tid = threadIdx.x;
   const int r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
   const int k0 = rowptr[r0], k1 = rowptr[r1];
-  // rb right-hand sides per block: the block's rows of P are read once and
-  // applied to each of them
+  // rb right-hand sides per block (a multiple of PR): the block's rows of P
+  // are read once and applied to each of them
   const int rhs_end = min(nrhs, int(blockIdx.y + 1) * rb);
   if (k0 == k1) {  // nodes no stencil reaches: zeros, without reading rowptr per row
     for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
@@ -860,37 +862,50 @@ __global__ __launch_bounds__(256) void project_kernel(const cx<T>* __restrict__ 
     const int j = tid + i * 256;
     if (j <= r1 - r0) sh.rp[j] = rowptr[r0 + j] - k0;
   }
-  for (int rhs = int(blockIdx.y) * rb; rhs < rhs_end; ++rhs) {
-    const cx<T>* xr = x + rhs * n;
-    cx<T>* qr = q + rhs * Ng;
-    cx<T> xv[PER];
+  const int R = r1 - r0;
+  for (int rhs0 = int(blockIdx.y) * rb; rhs0 < rhs_end; rhs0 += PR) {
+    const int nr = min(PR, rhs_end - rhs0);
+    cx<T> xv[PR][PER];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) xv[i] = xr[c[i]];
+    for (int j = 0; j < PR; ++j)
+      if (j < nr) {
+        const cx<T>* xr = x + (rhs0 + j) * n;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int k = tid + i * 256;
-      if (k < k1 - k0) prod[k] = mkc<T>(w[i] * xv[i].x, w[i] * xv[i].y);
-    }
+        for (int i = 0; i < PER; ++i) xv[j][i] = xr[c[i]];
+      }
+#pragma unroll
+    for (int j = 0; j < PR; ++j)
+      if (j < nr) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          const int k = tid + i * 256;
+          if (k < k1 - k0) prod[j * kProjNnz + k] = mkc<T>(w[i] * xv[j][i].x, w[i] * xv[j][i].y);
+        }
+      }
     __syncthreads();
-    // row sums from LDS, four interleaved partial sums per row (fixed order)
-    for (int r = r0 + tid; r < r1; r += 256) {
-      const int e = sh.rp[r - r0 + 1];
-      int k = sh.rp[r - r0];
+    // row sums from LDS, four interleaved partial sums per row (fixed order),
+    // one (row, right-hand side) pair per thread at a time
+    for (int idx = tid; idx < R * nr; idx += 256) {
+      const int j = idx / R, rr = idx - j * R;
+      const cx<T>* pj = prod + j * kProjNnz;
+      const int e = sh.rp[rr + 1];
+      int k = sh.rp[rr];
       T ar[4] = {T(0), T(0), T(0), T(0)}, ai[4] = {T(0), T(0), T(0), T(0)};
       for (; k + 4 <= e; k += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          ar[u] += prod[k + u].x;
-          ai[u] += prod[k + u].y;
+          ar[u] += pj[k + u].x;
+          ai[u] += pj[k + u].y;
         }
       }
       for (int u = 0; k < e; ++k, ++u) {
-        ar[u] += prod[k].x;
-        ai[u] += prod[k].y;
+        ar[u] += pj[k].x;
+        ai[u] += pj[k].y;
       }
-      qr[r] = mkc<T>((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
+      q[(rhs0 + j) * Ng + r0 + rr] =
+          mkc<T>((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
     }
-    __syncthreads();  // prod is reused by the next right-hand side
+    __syncthreads();  // prod is reused by the next group of right-hand sides
   }
 }
 
@@ -918,10 +933,29 @@ inline int project_rhs_per_block(int64_t blocks_per_rhs, int nrhs) {
 template <typename T>
 void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, int nblk,
                     const void* x, int64_t n, void* q, int nrhs, hipStream_t s) {
-  const int rb = project_rhs_per_block(nblk, nrhs);
-  hipLaunchKernelGGL(project_kernel<T>, dim3(unsigned(nblk), unsigned((nrhs + rb - 1) / rb)),
-                     dim3(256), 0, s, static_cast<const cx<T>*>(x), static_cast<cx<T>*>(q),
-                     P.rowptr, P.col, static_cast<const T*>(P.val), blk, n, g.Ng, nrhs, rb);
+  // large operators: rb right-hand sides one after another per workgroup; small
+  // ones with many right-hand sides: up to 4 (complex64) or 2 (complex128) side
+  // by side, while the launch keeps 1024 workgroups
+  int rb = project_rhs_per_block(nblk, nrhs), pr = 1;
+  if (rb == 1) {
+    const int pmax = sizeof(T) == 4 ? 4 : 2;
+    while (pr < pmax && 2 * pr <= nrhs && int64_t(nblk) * ((nrhs + 2 * pr - 1) / (2 * pr)) >= 1024)
+      pr *= 2;
+    rb = pr;
+  }
+  const dim3 grid(unsigned(nblk), unsigned((nrhs + rb - 1) / rb));
+  const cx<T>* xi = static_cast<const cx<T>*>(x);
+  cx<T>* qo = static_cast<cx<T>*>(q);
+  const T* v = static_cast<const T*>(P.val);
+  if (pr == 4)
+    hipLaunchKernelGGL((project_kernel<T, 4>), grid, dim3(256), 0, s, xi, qo, P.rowptr, P.col, v,
+                       blk, n, g.Ng, nrhs, rb);
+  else if (pr == 2)
+    hipLaunchKernelGGL((project_kernel<T, 2>), grid, dim3(256), 0, s, xi, qo, P.rowptr, P.col, v,
+                       blk, n, g.Ng, nrhs, rb);
+  else
+    hipLaunchKernelGGL((project_kernel<T, 1>), grid, dim3(256), 0, s, xi, qo, P.rowptr, P.col, v,
+                       blk, n, g.Ng, nrhs, rb);
   AIM_HIP(hipGetLastError());
 }
 
