@@ -410,6 +410,11 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
     run_stages<T, L, NT, true, false, RMAX, 0>(v, sl, es, t, tw);
   }
   using Sf = Sched<L, MODE == 0, RMAX>;
+  // outputs that the next pass streams (the forward passes and the y
+  // inverse) are stored non-temporally, keeping them out of the way in the
+  // caches; the in-place z pass and the x inverse, whose output the
+  // interpolation gathers, store normally (measured both ways)
+  constexpr bool kStreamOut = MODE == 0 || (MODE == 1 && COL);
   constexpr int Rf = Sf::radix(Sf::NST - 1), NBf = L / (Rf * NT);
   if (valid) {
 #pragma unroll
@@ -417,7 +422,14 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
 #pragma unroll
       for (int r = 0; r < Rf; ++r) {
         const int e = t + i * NT + r * (L / Rf);
-        if (e < a.Lout) dst[e * a.out_es] = v[i * Rf + r];
+        if (e < a.Lout) {
+          if constexpr (kStreamOut) {
+            __builtin_nontemporal_store(v[i * Rf + r].x, &dst[e * a.out_es].x);
+            __builtin_nontemporal_store(v[i * Rf + r].y, &dst[e * a.out_es].y);
+          } else {
+            dst[e * a.out_es] = v[i * Rf + r];
+          }
+        }
       }
   }
 }
