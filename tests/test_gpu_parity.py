@@ -339,3 +339,28 @@ def test_profile_matvec_times_every_kernel_and_leaves_the_product():
     ms = p.profile_matvec(x, reps=4, out=y)
     assert list(ms) == binding.KERNELS and all(v > 0 for v in ms.values())
     assert torch.equal(y, p.matvec(x))
+
+
+def test_full_size_autotuned_schedules_match_oracle():
+    """The full-size workloads in the launch configuration the benchmark
+    times: schedules picked by the autotuner (box array in both precisions,
+    the radius-6 sphere in complex64), sampled rows against the oracle."""
+    cases = [("box array", I.box_array_large, ("c128", "c64"), 2301),
+             ("sphere", I.sphere_large, ("c64",), 2401)]
+    for name, make, precs, seed in cases:
+        w = make()
+        print(f"[gpu] autotuned full size: {name} N={w.n}", flush=True)
+        o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+        x = I.complex_gaussian(o.N, seed)
+        rows = np.sort(np.random.default_rng(seed + 1).choice(o.N, 24, replace=False))
+        ref = o.matvec_rows(x, w.k[0], rows)
+        p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                         precisions=precs, max_rhs=1)
+        for prec in precs:
+            dt = torch.complex128 if prec == "c128" else torch.complex64
+            tol = FP64_TOL if prec == "c128" else FP32_TOL
+            sched = p.autotune(prec=prec, nrhs=1, reps=3)["schedule"]
+            err = rel(host(p.matvec(dev(x, dt), prec=prec)).reshape(-1)[rows], ref)
+            print(f"    {prec} schedule {sched}: {err:.2e}", flush=True)
+            assert err <= tol, (name, prec, sched)
+        p.close()
