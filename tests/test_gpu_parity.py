@@ -364,3 +364,26 @@ def test_full_size_autotuned_schedules_match_oracle():
             print(f"    {prec} schedule {sched}: {err:.2e}", flush=True)
             assert err <= tol, (name, prec, sched)
         p.close()
+
+
+def test_sweep_batch_of_512_in_benchmark_configuration():
+    """The sweep as the benchmark runs it: 512 vectors, vector r at wavenumber
+    r mod 64, in one launch per kernel with autotuned schedules; 16 sampled
+    vectors against the oracle at their own wavenumber, both precisions."""
+    w = I.sweep_small()
+    nf = len(w.k)
+    print(f"[gpu] sweep batch: N={w.n}, {nf} wavenumbers, 512 vectors", flush=True)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    freq = np.arange(512) % nf
+    x = I.complex_gaussian(o.N, 2501, nrhs=512)
+    pick = np.sort(np.random.default_rng(2502).choice(512, 16, replace=False))
+    refs = {r: o.matvec(x[r], w.k[freq[r]]) for r in pick}
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     max_rhs=512)
+    for prec, dt, tol in (("c128", torch.complex128, FP64_TOL), ("c64", torch.complex64, FP32_TOL)):
+        sched = p.autotune(prec=prec, nrhs=512, reps=2)["schedule"]
+        y = host(p.matvec(dev(x, dt), freq_idx=freq, prec=prec))
+        worst = max(rel(y[r], refs[r]) for r in pick)
+        print(f"    {prec} schedule {sched}: worst {worst:.2e}", flush=True)
+        assert worst <= tol, (prec, sched)
+    p.close()
