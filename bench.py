@@ -380,6 +380,21 @@ def main() -> int:
         "fft_schedule": {pr: tuned[pr]["schedule"] for pr in tuned},
     }
 
+    if args.workload == "sweep":
+        # the paper's cost model T = T_s + N_f T_d: T_s the frequency-independent
+        # set-up (host tables and uploads), T_d per wavenumber its kernel
+        # spectrum plus its share of the batched matvec (its vectors' share)
+        nf = len(w.k)
+        t_spec = info["spectra_seconds"] / nf
+        t_mv = ms * 1e-3 / nf
+        t_s = setup_s - info["spectra_seconds"]
+        out["cost_model"] = {"n_freq": nf, "T_s_seconds": t_s,
+                             "T_d_seconds": t_spec + t_mv,
+                             "T_d_spectrum_seconds": t_spec,
+                             "T_d_matvec_seconds": t_mv,
+                             "vectors_per_freq": args.nrhs // nf,
+                             "T_total_seconds": t_s + nf * (t_spec + t_mv)}
+
     if not args.no_profile:
         reps = max(5, min(50, args.steps))
         kms = plan.profile_matvec(x, reps=reps, prec=args.prec, out=y, freq_idx=freq)
