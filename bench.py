@@ -50,6 +50,26 @@ def algorithmic_bytes(info: dict, prec: str, nrhs: int = 1) -> dict:
     }
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """A plain device-to-device copy of nbytes (read + write), timed with HIP
+    events: the streaming bandwidth this GPU reaches, beside the nominal one."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": ms,
+            "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def make_workload(name: str):
     from paper_2009_02281_amd import inputs as I
     return {"boxarray": I.box_array_large, "sphere": I.sphere_small,
@@ -300,19 +320,7 @@ def main() -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     if args.copy_calibration:
-        nbytes = 1 << 30
-        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(5):
-            b.copy_(a)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / 5
-        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
-                          "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+        print(json.dumps(copy_bandwidth()), flush=True)
         return 0
     w = make_workload(args.workload)
     freq = None
@@ -408,7 +416,8 @@ def main() -> int:
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": load_traffic(dom, w.name, args.prec)}
+                           "traffic": load_traffic(dom, w.name, args.prec),
+                           "copy_measured_gbs": copy_bandwidth()["gbs"]}
         out["stages"] = stages
         out["matvec_alg_gbs"] = total_b / (ms * 1e-3) / 1e9
         print(f"[bench] kernels (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in kms.items()),
