@@ -131,6 +131,7 @@ struct aim_plan_s {
   aim_pc_kind unet_base = AIM_PC_DIAG;
   double unet_tau = 1.0;
   void *ug_in = nullptr, *ug_out = nullptr, *um1 = nullptr, *um2 = nullptr, *upart = nullptr;
+  void* ug_x = nullptr;  // training: the selected input grids, stacked
   double* u_s = nullptr;
   double* u_s2 = nullptr;
   void* d_work[2] = {nullptr, nullptr};  // [prec] 6 Ng per rhs
@@ -1133,6 +1134,7 @@ void ensure_unet_buffers(aim_plan p, hipStream_t s) {
   const int64_t n = p->t.N, Ng = p->g.Ng;
   p->ug_in = p->dalloc(size_t(Ng) * 8 * R, s);
   p->ug_out = p->dalloc(size_t(Ng) * 8 * R, s);
+  p->ug_x = p->dalloc(size_t(Ng) * 8 * R, s);
   p->um1 = p->dalloc(size_t(n) * 8 * R, s);
   p->um2 = p->dalloc(size_t(n) * 8 * R, s);
   const int64_t nchunk = (std::max(n, Ng) + 4095) / 4096;
@@ -1201,9 +1203,8 @@ void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s) 
   ensure_unet_buffers(p, s);  // before any of the buffers is read below
   const int64_t n = p->t.N, Ng = p->g.Ng;
   unet_input(p, v, nrhs, p->ug_in, s);
-  for (int r = 0; r < nrhs; ++r)
-    aim::unet_forward(p->unet, static_cast<char*>(p->ug_in) + size_t(r) * Ng * 8, p->g.N[2],
-                      p->g.N[1], p->g.N[0], static_cast<char*>(p->ug_out) + size_t(r) * Ng * 8, s);
+  // the nrhs grids lie one after another: one batched pass of the network
+  aim::unet_forward(p->unet, p->ug_in, nrhs, p->g.N[2], p->g.N[1], p->g.N[0], p->ug_out, s);
   interp_near<float>(p, AIM_C64, p->ug_out, nullptr, p->um2, nrhs, true, false, s);
   apply_base(p, p->unet_base, v, z, nrhs, s);
   aim::launch_unet_combine(p->um2, p->d_area, p->unet_tau, p->u_s, z, n, nrhs, s);
@@ -1693,33 +1694,48 @@ extern "C" aim_status aim_pc_train_step(aim_plan p, aim_unet net, aim_pc_loss ki
                     int64_t(16) * p->max_rhs * ((std::max(n, Ng) + 4095) / 4096),
                 AIM_ERR_INVALID_ARG, "too many samples in one step");
     double* part = static_cast<double*>(p->upart);
-    const int32_t* df = kind == AIM_LOSS_RESIDUAL ? set_freq(p, nullptr, 1, s) : nullptr;
     aim::unet_zero_grad(net, s);
     const double inv_cnt = 1.0 / (double(n) * nsamples);
-    for (int i = 0; i < nsamples; ++i) {
-      const int64_t k = sample_idx_host[i];
-      const char* g = static_cast<const char*>(grids) + size_t(k) * Ng * 8;
-      aim::unet_forward(net, g, p->g.N[2], p->g.N[1], p->g.N[0], p->ug_out, s);
-      interp_near<float>(p, AIM_C64, p->ug_out, nullptr, p->um2, 1, true, false, s);
-      const char* tk = static_cast<const char*>(targets) + size_t(k) * n * 16;
+    // groups of up to max_rhs samples, each one batched pass: the selected
+    // grids are gathered one after another (stacked along z for the network)
+    for (int i0 = 0; i0 < nsamples; i0 += p->max_rhs) {
+      const int nb = std::min(p->max_rhs, nsamples - i0);
+      for (int j = 0; j < nb; ++j)
+        AIM_HIP(hipMemcpyAsync(static_cast<char*>(p->ug_x) + size_t(j) * Ng * 8,
+                               static_cast<const char*>(grids) +
+                                   size_t(sample_idx_host[i0 + j]) * Ng * 8,
+                               size_t(Ng) * 8, hipMemcpyDeviceToDevice, s));
+      aim::unet_forward(net, p->ug_x, nb, p->g.N[2], p->g.N[1], p->g.N[0], p->ug_out, s);
+      interp_near<float>(p, AIM_C64, p->ug_out, nullptr, p->um2, nb, true, false, s);
+      auto mesh = [&](void* base, int j) { return static_cast<char*>(base) + size_t(j) * n * 8; };
+      auto target = [&](int j) {
+        return static_cast<const char*>(targets) + size_t(sample_idx_host[i0 + j]) * n * 16;
+      };
       if (kind == AIM_LOSS_ERROR) {
-        aim::launch_mesh_mse(p->um2, tk, p->d_area, 1.0 / tau, n, inv_cnt * weight, p->um1,
-                             part + size_t(i) * kParts, kParts, s);
+        for (int j = 0; j < nb; ++j)
+          aim::launch_mesh_mse(mesh(p->um2, j), target(j), p->d_area, 1.0 / tau, n,
+                               inv_cnt * weight, mesh(p->um1, j),
+                               part + size_t(i0 + j) * kParts, kParts, s);
       } else {
         // loss = weight mean |s - A z|^2, z = tau c / area; its gradient with
         // respect to c is -2 weight tau A^H (s - A z) / (area cnt)
-        aim::launch_area_scale_c64(p->um2, p->d_area, tau, p->um1, n, s);
-        matvec_any(p, AIM_C64, p->um1, p->um2, 1, df, s);
-        aim::launch_resid_loss(p->um2, tk, weight * inv_cnt, n, p->um1,
-                               part + size_t(i) * kParts, kParts, s);
-        matvec_any(p, AIM_C64, p->um1, p->um2, 1, df, s);
-        aim::launch_resid_grad(p->um2, p->d_area, -2.0 * weight * tau * inv_cnt, p->um1, n, s);
+        const int32_t* df = set_freq(p, nullptr, nb, s);
+        for (int j = 0; j < nb; ++j)
+          aim::launch_area_scale_c64(mesh(p->um2, j), p->d_area, tau, mesh(p->um1, j), n, s);
+        matvec_any(p, AIM_C64, p->um1, p->um2, nb, df, s);
+        for (int j = 0; j < nb; ++j)
+          aim::launch_resid_loss(mesh(p->um2, j), target(j), weight * inv_cnt, n,
+                                 mesh(p->um1, j), part + size_t(i0 + j) * kParts, kParts, s);
+        matvec_any(p, AIM_C64, p->um1, p->um2, nb, df, s);
+        for (int j = 0; j < nb; ++j)
+          aim::launch_resid_grad(mesh(p->um2, j), p->d_area, -2.0 * weight * tau * inv_cnt,
+                                 mesh(p->um1, j), n, s);
       }
       // d loss / d grid output = P (d loss / d mesh output), as the mesh
       // output is P^T of the grid output
       aim::launch_project<float>(p->g, p_dev(p, AIM_C64), p->d_pblk, p->nblk, p->um1, n,
-                                 p->ug_in, 1, s);
-      aim::unet_backward(net, g, p->ug_in, s);
+                                 p->ug_in, nb, s);
+      aim::unet_backward(net, p->ug_x, p->ug_in, s);
     }
     if (apply) aim::unet_adam(net, lr, s);
     std::vector<double> hp(size_t(kParts) * nsamples);

@@ -228,7 +228,9 @@ void launch_resid_grad(const void* y, const double* area, double coef, void* d, 
 void launch_zero_words(void* p, int64_t n, hipStream_t st);
 // e = xs - e (one vector)
 void launch_pair_error(const void* xs, void* e, int64_t n, hipStream_t st);
-void unet_forward(aim_unet u, const void* in, int D, int H, int W, void* out, hipStream_t s);
+// nb samples of D x H x W, stored one after another (stacked along z)
+void unet_forward(aim_unet u, const void* in, int nb, int D, int H, int W, void* out,
+                  hipStream_t s);
 void unet_backward(aim_unet u, const void* in, const void* dout, hipStream_t s);
 void unet_zero_grad(aim_unet u, hipStream_t s);
 void unet_adam(aim_unet u, double lr, hipStream_t s);

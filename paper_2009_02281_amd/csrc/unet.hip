@@ -9,7 +9,9 @@
 //   a6 = relu(conv3([up(a5), s0], 3C->C))   a7 = relu(conv3(a6, C->C))
 //   out = a7 W^T + b (1x1x1, C->2)
 // with 3x3x3 "same" convolutions, 2x2x2 average pooling and nearest
-// upsampling.  Weights and activations are bfloat16; the convolutions are
+// upsampling.  A batch of samples is stacked along z (each sample Ds planes
+// deep, Ds a multiple of 4, so pooling never mixes samples); the 3x3x3
+// kernels treat the planes of other samples as the zero padding.  Weights and activations are bfloat16; the convolutions are
 // LDS-tiled implicit GEMMs on the 16x16x32 bf16 MFMA with fp32 accumulation
 // (the data gradient is the same GEMM with flipped, transposed weights); the
 // weight gradients of the 3x3x3 layers are per-tap GEMMs over positions on the
@@ -73,7 +75,7 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
 
 template <int CIN, int TILES, bool OUT_BF16, int kBY = conv_by(CIN)>
 __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restrict__ X, int ldx,
-                                                        int ox, int D, int H, int W,
+                                                        int ox, int D, int Ds, int H, int W,
                                                         const uint16_t* __restrict__ Wt,
                                                         const float* __restrict__ bias, void* Y,
                                                         int ldy, int oy, int relu) {
@@ -99,6 +101,10 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restri
   __syncthreads();
   const int col = lane & 15, kg = lane >> 4;
   constexpr int K = 27 * CIN, NCH = (K + 31) / 32;
+  // the wave's output plane and whether its z - 1 / z + 1 neighbours lie in
+  // the same sample (a brick may straddle two samples)
+  const int zo = z0 + wave, zs = (zo / Ds) * Ds;
+  const bool lo_ok = zo - 1 >= zs, hi_ok = zo + 1 < zs + Ds;
   f32x4 acc[kBY][TILES];
 #pragma unroll
   for (int g = 0; g < kBY; ++g)
@@ -110,11 +116,12 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restri
     const bool kv = k < K;
     const int tap = kv ? k / CIN : 0, ci = kv ? k % CIN : 0;
     const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+    const bool bok = kv && (dz == 1 || (dz == 0 ? lo_ok : hi_ok));
     bf16x8 bv[kBY];
 #pragma unroll
     for (int g = 0; g < kBY; ++g) {
       const int pos = ((wave + dz) * kTY + g + dy) * kTX + col + dx;
-      bv[g] = kv ? as_bf16x8(tile[pos * C8 + ci / 8]) : zero;
+      bv[g] = bok ? as_bf16x8(tile[pos * C8 + ci / 8]) : zero;
     }
 #pragma unroll
     for (int t = 0; t < TILES; ++t) {
@@ -157,8 +164,8 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restri
 
 // first layer: 2 fp32 input channels (the complex64 grid), C outputs, relu
 template <int C>
-__global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict__ in, int D, int H,
-                                                         int W, const float* __restrict__ Wm,
+__global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict__ in, int D, int Ds,
+                                                         int H, int W, const float* __restrict__ Wm,
                                                          const float* __restrict__ bias,
                                                          uint16_t* __restrict__ Y, int ldy, int oy) {
   __shared__ float w[C * 27 * 2];
@@ -169,12 +176,13 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
   if (p >= P) return;
   int x, y, z;
   pos_xyz(p, W, H, x, y, z);
+  const int zs = (z / Ds) * Ds;  // the sample's first plane
   float acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = bias[c];
   for (int tap = 0; tap < 27; ++tap) {
     const int nx = x + tap % 3 - 1, ny = y + (tap / 3) % 3 - 1, nz = z + tap / 9 - 1;
-    if (nx < 0 || ny < 0 || nz < 0 || nx >= W || ny >= H || nz >= D) continue;
+    if (nx < 0 || ny < 0 || nz < zs || nx >= W || ny >= H || nz >= zs + Ds) continue;
     const float2 v = *reinterpret_cast<const float2*>(in + 2 * ((int64_t(nz) * H + ny) * W + nx));
     // the first layer reads bf16-rounded inputs, like every other layer
     const float v0 = bf2f(f2bf(v.x)), v1 = bf2f(f2bf(v.y));
@@ -215,7 +223,7 @@ constexpr int kWgPos = 32;  // positions staged per step
 template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void wgrad_partial_kernel(
     const TX* __restrict__ X, int ldx, int ox, int Cin, const TY* __restrict__ dY, int ldy, int oy,
-    int Cout, int D, int H, int W, int ntaps, int64_t chunk, float* __restrict__ part) {
+    int Cout, int D, int Ds, int H, int W, int ntaps, int64_t chunk, float* __restrict__ part) {
   extern __shared__ float sm[];
   float* sy = sm;                     // [kWgPos][Cout]
   float* sx = sm + kWgPos * Cout;     // [kWgPos][Cin]
@@ -241,8 +249,8 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(
       if (pp < cnt) {
         int x, y, z;
         pos_xyz(s0 + pp, W, H, x, y, z);
-        const int nx = x + dx, ny = y + dy, nz = z + dz;
-        if (nx >= 0 && ny >= 0 && nz >= 0 && nx < W && ny < H && nz < D)
+        const int nx = x + dx, ny = y + dy, nz = z + dz, zs = (z / Ds) * Ds;
+        if (nx >= 0 && ny >= 0 && nz >= zs && nx < W && ny < H && nz < zs + Ds)
           v = ldv(X, ((int64_t(nz) * H + ny) * W + nx) * ldx + ox + c);
       }
       sx[i] = v;
@@ -276,16 +284,25 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(
 // ([channel][position], bf16), so lane l reads its 8 consecutive positions
 // (k = 8 (l / 16) + i) of row co = l % 16 (A) and of column ci = l % 16 (B)
 // as one 16-byte word; the 16x16 output tiles (co tile, ci tile) are dealt
-// to the four waves.  Partial sums per chunk of positions, as above.
-template <int CIN, int COUT>
+// to the four waves.  Partial sums per chunk of positions, as above; only
+// input channels ci < CST are stored (the first layer runs on its two input
+// channels zero-padded to 16).  The blocks of the centre tap, whose staged
+// dY covers every position of the chunk once, also write the chunk's bias
+// gradient partials partb[chunk][co] = sum_p dY[p][co] (when partb is set).
+template <int CIN, int COUT, int CST = CIN>
 __global__ __launch_bounds__(256) void wgrad_mfma_kernel(
     const uint16_t* __restrict__ X, int ldx, int ox, const uint16_t* __restrict__ dY, int ldy,
-    int oy, int D, int H, int W, int64_t chunk, float* __restrict__ part) {
+    int oy, int D, int Ds, int H, int W, int64_t chunk, float* __restrict__ part,
+    float* __restrict__ partb) {
   constexpr int KS = 64;                             // positions per step
   constexpr int NTC = COUT / 16, NTI = CIN / 16, NT = NTC * NTI, NTW = (NT + 3) / 4;
+  constexpr int BR = 256 / COUT;                     // bias: threads per output channel
+  static_assert(CST <= CIN && COUT <= 256, "channel layout");
   __shared__ __attribute__((aligned(16))) uint16_t syT[COUT * KS];  // 16-byte reads below
   __shared__ __attribute__((aligned(16))) uint16_t sxT[CIN * KS];
+  __shared__ float red[256];
   const int tap = blockIdx.y;
+  const bool bias = partb != nullptr && tap == 13;   // uniform over the block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
   const int64_t P = int64_t(D) * H * W;
@@ -294,6 +311,7 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(
   f32x4 acc[NTW];
 #pragma unroll
   for (int j = 0; j < NTW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
   __shared__ int64_t src[KS];  // shifted source position of each staged position, or -1
   for (int64_t s0 = pb; s0 < pe; s0 += KS) {
     const int cnt = int(min(int64_t(KS), pe - s0));
@@ -302,8 +320,8 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(
       if (tid < cnt) {
         int x, y, z;
         pos_xyz(s0 + tid, W, H, x, y, z);
-        const int nx = x + dx, ny = y + dy, nz = z + dz;
-        if (nx >= 0 && ny >= 0 && nz >= 0 && nx < W && ny < H && nz < D)
+        const int nx = x + dx, ny = y + dy, nz = z + dz, zs = (z / Ds) * Ds;
+        if (nx >= 0 && ny >= 0 && nz >= zs && nx < W && ny < H && nz < zs + Ds)
           v = (int64_t(nz) * H + ny) * W + nx;
       }
       src[tid] = v;
@@ -327,6 +345,8 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(
 #pragma unroll
       for (int j = 0; j < 8; ++j) sxT[(8 * c8 + j) * KS + pp] = e[j];
     }
+    if (bias)  // staged positions past the chunk's end are zero
+      for (int pp = tid / COUT; pp < KS; pp += BR) bsum += bf2f(syT[(tid % COUT) * KS + pp]);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
@@ -349,24 +369,55 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(
     const int tt = wave + 4 * j;
     if (tt < NT) {
       const int tc = tt / NTI, ti = tt % NTI;
+      const int ci = ti * 16 + col;
+      if (ci < CST) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int co = tc * 16 + 4 * kg + i, ci = ti * 16 + col;
-        part[(int64_t(blockIdx.x) * 27 * COUT + int64_t(co) * 27 + tap) * CIN + ci] = acc[j][i];
+        for (int i = 0; i < 4; ++i) {
+          const int co = tc * 16 + 4 * kg + i;
+          part[(int64_t(blockIdx.x) * 27 * COUT + int64_t(co) * 27 + tap) * CST + ci] = acc[j][i];
+        }
       }
+    }
+  }
+  if (bias) {
+    red[tid] = bsum;
+    __syncthreads();
+    if (tid < COUT) {
+      float a = 0.f;
+      for (int q = 0; q < BR; ++q) a += red[q * COUT + tid];
+      partb[int64_t(blockIdx.x) * COUT + tid] = a;
     }
   }
 }
 
-// grad[i] (+)= sum_c part[c][i]
-__global__ void reduce_chunks_kernel(const float* __restrict__ part, int nchunk, int64_t n,
-                                     float* __restrict__ grad) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    float s = 0.f;
-    for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * n + i];
-    grad[i] += s;
-  }
+// grad[i] (+)= sum_c part[c][i]: a block takes 64 consecutive entries, its
+// four waves a quarter of the chunks each
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(const float* __restrict__ part,
+                                                            int nchunk, int64_t n,
+                                                            float* __restrict__ grad) {
+  __shared__ float red[4][64];
+  const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t i = int64_t(blockIdx.x) * 64 + e;
+  float s = 0.f;
+  if (i < n)
+    for (int c = q; c < nchunk; c += 4) s += part[int64_t(c) * n + i];
+  red[q][e] = s;
+  __syncthreads();
+  if (q == 0 && i < n) grad[i] += (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+}
+
+// the first layer's input for its weight gradient: the complex64 grid
+// [P][2] rounded to bf16 (as the forward pass reads it), zero-padded to 16
+// channels
+__global__ void pack_in16_kernel(const float* __restrict__ in, int64_t P,
+                                 uint16_t* __restrict__ o) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const float2 v = *reinterpret_cast<const float2*>(in + 2 * p);
+  uint4 a = make_uint4(uint32_t(f2bf(v.x)) | (uint32_t(f2bf(v.y)) << 16), 0u, 0u, 0u);
+  uint4* d = reinterpret_cast<uint4*>(o + 16 * p);
+  d[0] = a;
+  d[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // bias gradient, first stage: part[chunk][c] = sum over the chunk's positions
@@ -395,73 +446,109 @@ __global__ __launch_bounds__(256) void bgrad_partial_kernel(const TY* __restrict
 // ---------------------------------------------------------------------------
 // pooling, upsampling, masks
 // ---------------------------------------------------------------------------
-__global__ void pool_kernel(const uint16_t* __restrict__ X, int ldx, int ox, int C, int D, int H,
-                            int W, uint16_t* __restrict__ Y) {  // Y [P/8][C]
-  const int Dc = D / 2, Hc = H / 2, Wc = W / 2;
-  const int64_t n = int64_t(Dc) * Hc * Wc * C;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int c = int(i % C);
-    const int64_t q = i / C;
-    int x, y, z;
-    pos_xyz(q, Wc, Hc, x, y, z);
-    float s = 0.f;
-    for (int k = 0; k < 8; ++k) {
-      const int64_t pf = (int64_t(2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
-      s += bf2f(X[pf * ldx + ox + c]);
-    }
-    Y[q * C + c] = f2bf(s * 0.125f);
+// The elementwise kernels below take 8 consecutive channels (one 16-byte
+// bf16 word, two fp32 float4) per thread; every channel count, row stride and
+// channel offset they see is a multiple of 8, and every grid has fewer than
+// 2^31 positions.
+__device__ __forceinline__ void unpack8(uint4 v, float* f) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    f[2 * j] = __uint_as_float(w[j] << 16);
+    f[2 * j + 1] = __uint_as_float(w[j] & 0xFFFF0000u);
   }
 }
+__device__ __forceinline__ uint4 pack8(const float* f) {
+  uint32_t w[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) w[j] = uint32_t(f2bf(f[2 * j])) | (uint32_t(f2bf(f[2 * j + 1])) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+__device__ __forceinline__ void load8(const float* p, float* f) {
+  const float4 a = *reinterpret_cast<const float4*>(p), b = *reinterpret_cast<const float4*>(p + 4);
+  f[0] = a.x; f[1] = a.y; f[2] = a.z; f[3] = a.w;
+  f[4] = b.x; f[5] = b.y; f[6] = b.z; f[7] = b.w;
+}
+// fine position of child k (0..7) of coarse position (x, y, z)
+__device__ __forceinline__ int64_t child(int x, int y, int z, int k, int H, int W) {
+  return (int64_t(2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
+}
 
+// Y[q][c] = bf16(mean of X over the 8 children of coarse position q)
+__global__ void pool_kernel(const uint16_t* __restrict__ X, int ldx, int ox, int C, int D, int H,
+                            int W, uint16_t* __restrict__ Y) {  // Y [P/8][C]
+  const int Hc = H / 2, Wc = W / 2, C8 = C / 8;
+  const int n = (D / 2) * Hc * Wc * C8;
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = 8 * (i % C8), q = i / C8;
+  const int x = q % Wc, y = (q / Wc) % Hc, z = q / (Wc * Hc);
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < 8; ++k) {
+    float f[8];
+    unpack8(*reinterpret_cast<const uint4*>(X + child(x, y, z, k, H, W) * ldx + ox + c), f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += f[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] *= 0.125f;
+  *reinterpret_cast<uint4*>(Y + int64_t(q) * C + c) = pack8(s);
+}
+
+// nearest upsampling: Y[p][oy + c] = X[parent(p)][c]
 __global__ void up_kernel(const uint16_t* __restrict__ X, int C, int Dc, int Hc, int Wc,
                           uint16_t* __restrict__ Y, int ldy, int oy) {  // fine [8 Pc][ldy]
-  const int D = 2 * Dc, H = 2 * Hc, W = 2 * Wc;
-  const int64_t n = int64_t(D) * H * W * C;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int c = int(i % C);
-    const int64_t p = i / C;
-    int x, y, z;
-    pos_xyz(p, W, H, x, y, z);
-    const int64_t q = (int64_t(z / 2) * Hc + y / 2) * Wc + x / 2;
-    Y[p * ldy + oy + c] = X[q * C + c];
-  }
+  const int H = 2 * Hc, W = 2 * Wc, C8 = C / 8;
+  const int n = 2 * Dc * H * W * C8;
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = 8 * (i % C8), p = i / C8;
+  const int x = p % W, y = (p / W) % H, z = p / (W * H);
+  const int64_t q = (int64_t(z / 2) * Hc + y / 2) * Wc + x / 2;
+  *reinterpret_cast<uint4*>(Y + int64_t(p) * ldy + oy + c) =
+      *reinterpret_cast<const uint4*>(X + q * C + c);
 }
 
 // gb[p][c] = bf16(g[p][og + c]) where act[p][oa + c] > 0, else 0
 __global__ void mask_kernel(const float* __restrict__ g, int ldg, int og,
                             const uint16_t* __restrict__ act, int lda, int oa, int C, int64_t P,
                             uint16_t* __restrict__ gb) {
-  const int64_t n = P * C;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int c = int(i % C);
-    const int64_t p = i / C;
-    const float v = bf2f(act[p * lda + oa + c]) > 0.f ? g[p * ldg + og + c] : 0.f;
-    gb[i] = f2bf(v);
-  }
+  const int C8 = C / 8;
+  const int64_t n = P * C8;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = 8 * int(i % C8);
+  const int64_t p = i / C8;
+  float v[8], a[8];
+  load8(g + p * ldg + og + c, v);
+  unpack8(*reinterpret_cast<const uint4*>(act + p * lda + oa + c), a);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = a[j] > 0.f ? v[j] : 0.f;
+  *reinterpret_cast<uint4*>(gb + p * C + c) = pack8(v);
 }
 
 // coarse gb[q][c] = bf16(sum of the 8 children g[child][og + c]) masked by act[q][c] > 0
 __global__ void up_backward_kernel(const float* __restrict__ g, int ldg, int og, int C, int Dc,
                                    int Hc, int Wc, const uint16_t* __restrict__ act,
                                    uint16_t* __restrict__ gb) {
-  const int H = 2 * Hc, W = 2 * Wc;
-  const int64_t n = int64_t(Dc) * Hc * Wc * C;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int c = int(i % C);
-    const int64_t q = i / C;
-    int x, y, z;
-    pos_xyz(q, Wc, Hc, x, y, z);
-    float s = 0.f;
-    for (int k = 0; k < 8; ++k) {
-      const int64_t pf = (int64_t(2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
-      s += g[pf * ldg + og + c];
-    }
-    gb[i] = f2bf(bf2f(act[i]) > 0.f ? s : 0.f);
+  const int H = 2 * Hc, W = 2 * Wc, C8 = C / 8;
+  const int n = Dc * Hc * Wc * C8;
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = 8 * (i % C8), q = i / C8;
+  const int x = q % Wc, y = (q / Wc) % Hc, z = q / (Wc * Hc);
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < 8; ++k) {
+    float f[8];
+    load8(g + child(x, y, z, k, H, W) * ldg + og + c, f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += f[j];
   }
+  float a[8];
+  unpack8(*reinterpret_cast<const uint4*>(act + int64_t(q) * C + c), a);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] = a[j] > 0.f ? s[j] : 0.f;
+  *reinterpret_cast<uint4*>(gb + int64_t(q) * C + c) = pack8(s);
 }
 
 // fine gb[p][c] = bf16((gc[parent][c] / 8 + skip[p][os + c]) * (act[p][oa + c] > 0))
@@ -469,19 +556,20 @@ __global__ void pool_backward_kernel(const float* __restrict__ gc, int C, int D,
                                      const float* __restrict__ skip, int lds, int os,
                                      const uint16_t* __restrict__ act, int lda, int oa,
                                      uint16_t* __restrict__ gb) {
-  const int Hc = H / 2, Wc = W / 2;
-  const int64_t n = int64_t(D) * H * W * C;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int c = int(i % C);
-    const int64_t p = i / C;
-    int x, y, z;
-    pos_xyz(p, W, H, x, y, z);
-    const int64_t q = (int64_t(z / 2) * Hc + y / 2) * Wc + x / 2;
-    float v = gc[q * C + c] * 0.125f + skip[p * lds + os + c];
-    if (!(bf2f(act[p * lda + oa + c]) > 0.f)) v = 0.f;
-    gb[i] = f2bf(v);
-  }
+  const int Hc = H / 2, Wc = W / 2, C8 = C / 8;
+  const int n = D * H * W * C8;
+  const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = 8 * (i % C8), p = i / C8;
+  const int x = p % W, y = (p / W) % H, z = p / (W * H);
+  const int64_t q = (int64_t(z / 2) * Hc + y / 2) * Wc + x / 2;
+  float v[8], sk[8], a[8];
+  load8(gc + q * C + c, v);
+  load8(skip + int64_t(p) * lds + os + c, sk);
+  unpack8(*reinterpret_cast<const uint4*>(act + int64_t(p) * lda + oa + c), a);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = a[j] > 0.f ? v[j] * 0.125f + sk[j] : 0.f;
+  *reinterpret_cast<uint4*>(gb + int64_t(p) * C + c) = pack8(v);
 }
 
 // gradient through the 1x1 output layer: ga[p][c] = bf16((dout[p] W)[c]) masked by a7 > 0
@@ -562,6 +650,9 @@ __global__ void fill_kernel(float* __restrict__ p, int64_t n, float v) {
     p[i] = v;
 }
 
+// blocks of 256 threads for n elements taken 8 per thread (no grid-stride loop)
+inline unsigned gsz8(int64_t n) { return unsigned((n / 8 + 255) / 256); }
+
 inline unsigned gsz(int64_t n, int per = 256) {
   int64_t g = (n + per - 1) / per;
   return unsigned(g < 1 ? 1 : (g > 16384 ? 16384 : g));
@@ -583,13 +674,14 @@ struct Layer {
   int64_t flip_off;      // into the flipped bf16 vector (3x3x3 layers)
 };
 
-struct Acts {  // per-level activation / gradient buffers for one grid size
-  int D = 0, H = 0, W = 0;
+struct Acts {  // per-level activation / gradient buffers, reused while they fit
+  int D = 0, Ds = 0, H = 0, W = 0;  // the current batch: D = samples x Ds planes
+  int64_t cap = 0;                  // level-0 positions the buffers hold
   std::vector<void*> bufs;
   uint16_t *a0, *cat0, *p0, *a1, *cat1, *p1, *a2, *a3, *a4, *a5, *a6, *a7;
-  float *out, *gcat0, *g0, *gcat1, *g1, *g2, *part;
-  uint16_t *gb0, *gb1, *gb2;
-  int64_t part_n = 0;
+  float *out, *gcat0, *g0, *gcat1, *g1, *g2, *part, *partb;
+  uint16_t *gb0, *gb1, *gb2, *in16;
+  int64_t part_n = 0, partb_n = 0;
 };
 
 thread_local std::string g_unet_err;
@@ -659,15 +751,26 @@ struct aim_unet_s {
     }
   }
 
-  void ensure_acts(int D, int H, int W) {
-    AIM_REQUIRE(D % 4 == 0 && H % 4 == 0 && W % 4 == 0 && D >= 4 && H >= 4 && W >= 4,
+  // buffers for nb samples of Ds x H x W stacked along z
+  void ensure_acts(int nb, int Ds, int H, int W) {
+    AIM_REQUIRE(Ds % 4 == 0 && H % 4 == 0 && W % 4 == 0 && Ds >= 4 && H >= 4 && W >= 4,
                 AIM_ERR_GRID, "U-Net grid dimensions must be multiples of 4");
-    if (acts.D == D && acts.H == H && acts.W == W) return;
-    free_acts();
+    AIM_REQUIRE(nb >= 1 && int64_t(nb) * Ds * H * W < (int64_t(1) << 31) / 96, AIM_ERR_GRID,
+                "U-Net batch too large");
+    const int D = nb * Ds;
+    if (int64_t(D) * H * W > acts.cap) {
+      free_acts();
+      acts.cap = int64_t(D) * H * W;
+      alloc_acts(acts.cap);
+    }
     acts.D = D;
+    acts.Ds = Ds;
     acts.H = H;
     acts.W = W;
-    const int64_t P0 = int64_t(D) * H * W, P1 = P0 / 8, P2 = P1 / 8;
+  }
+
+  void alloc_acts(int64_t P0) {
+    const int64_t P1 = P0 / 8, P2 = P1 / 8;
     const int c0 = C, c1 = 2 * C, c2 = 4 * C;
     auto al = [&](int64_t bytes) {
       void* p = nullptr;
@@ -698,15 +801,34 @@ struct aim_unet_s {
     acts.gb0 = b16(P0 * c0);
     acts.gb1 = b16(P1 * c1);
     acts.gb2 = b16(P2 * c2);
-    // weight-gradient partials: chunks * taps * cout * cin, largest layer
-    int64_t mx = 0;
-    for (const auto& L : layers) mx = std::max<int64_t>(mx, int64_t(L.cout) * L.cin * L.taps);
-    acts.part_n = 64 * mx;
+    acts.in16 = b16(P0 * 16);
+    // two-stage gradient sums: weight partials (chunks x entries, bounded
+    // by wg_chunks) and bias partials (chunks x output channels)
+    acts.part_n = std::max<int64_t>(int64_t(1) << 21, int64_t(kMaxChunks) * 64);
     acts.part = f32(acts.part_n);
+    acts.partb_n = int64_t(kMaxChunks) * 64;
+    acts.partb = f32(acts.partb_n);
+  }
+
+  // Chunks of positions for the weight-gradient partial sums: enough blocks
+  // (chunks x taps) to fill the chip, at least four 64-position steps per
+  // chunk, and at most 2^21 partial sums (or 8 chunks) in flight.
+  static constexpr int64_t kMaxChunks = 1024;
+  static int64_t wg_chunks(int64_t P, int64_t entries, int taps) {
+    const int64_t steps = (P + 63) / 64;
+    int64_t n = std::min<int64_t>((4096 + taps - 1) / taps, std::max<int64_t>(1, steps / 4));
+    n = std::min<int64_t>(n, std::max<int64_t>(8, (int64_t(1) << 21) / entries));
+    return std::max<int64_t>(1, std::min<int64_t>(n, kMaxChunks));
+  }
+
+  void reduce(const float* part, int64_t nchunk, int64_t n, float* grad, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(unsigned((n + 63) / 64)), dim3(256), 0, s, part,
+                       int(nchunk), n, grad);
+    AIM_HIP(hipGetLastError());
   }
 
   // -- launch helpers --------------------------------------------------------
-  void conv(const uint16_t* X, int ldx, int ox, int cin, int D, int H, int W, const uint16_t* Wt,
+  void conv(const uint16_t* X, int ldx, int ox, int cin, int D, int Ds, int H, int W, const uint16_t* Wt,
             const float* bias, void* Y, int ldy, int oy, int cout, bool out_bf16, bool relu,
             hipStream_t s) {
     AIM_REQUIRE(ox % 8 == 0 && ldx % 8 == 0 && oy % 4 == 0 && cout % 16 == 0, AIM_ERR_STATE,
@@ -720,10 +842,10 @@ struct aim_unet_s {
   if (cin == CI && tiles == T) {                                                                \
     if (out_bf16)                                                                               \
       hipLaunchKernelGGL((conv3_lds_kernel<CI, T, true>), dim3(nb), dim3(256), 0, s, X, ldx, ox, \
-                         D, H, W, Wt, bias, Y, ldy, oy, rl);                                     \
+                         D, Ds, H, W, Wt, bias, Y, ldy, oy, rl);                                 \
     else                                                                                        \
       hipLaunchKernelGGL((conv3_lds_kernel<CI, T, false>), dim3(nb), dim3(256), 0, s, X, ldx,   \
-                         ox, D, H, W, Wt, bias, Y, ldy, oy, rl);                                 \
+                         ox, D, Ds, H, W, Wt, bias, Y, ldy, oy, rl);                             \
     AIM_HIP(hipGetLastError());                                                                 \
     return;                                                                                     \
   }
@@ -746,144 +868,157 @@ struct aim_unet_s {
 
   template <typename TX, typename TY>
   void wgrad(const TX* X, int ldx, int ox, int cin, const TY* dY, int ldy, int oy, int cout, int D,
-             int H, int W, const Layer& L, hipStream_t s) {
+             int Ds, int H, int W, const Layer& L, hipStream_t s) {
     const int64_t P = int64_t(D) * H * W;
-    AIM_REQUIRE(int64_t(cout) * cin <= 256 * 24, AIM_ERR_STATE, "layer too wide for wgrad");
-    // chunks of positions for the partial sums: as many as the partial
-    // buffer holds (at most 1024), each at least 256 positions long
+    AIM_REQUIRE(int64_t(cout) * cin <= 256 * 24 && cout <= 64, AIM_ERR_STATE,
+                "layer too wide for wgrad");
     const int64_t entries = int64_t(cout) * L.taps * cin;
-    int64_t nchunk = std::min<int64_t>(std::min<int64_t>(1024, acts.part_n / entries),
-                                       (P + 255) / 256);
-    nchunk = std::max<int64_t>(1, nchunk);
-    const int64_t chunk = (P + nchunk - 1) / nchunk;
+    int64_t nchunk = wg_chunks(P, entries, L.taps);
+    const int64_t chunk = ((P + 63) / 64 + nchunk - 1) / nchunk * 64;
     nchunk = (P + chunk - 1) / chunk;
+    AIM_REQUIRE(nchunk * entries <= acts.part_n && nchunk * cout <= acts.partb_n, AIM_ERR_STATE,
+                "gradient partial buffer too small");
     bool done = false;
-    if constexpr (std::is_same_v<TX, uint16_t> && std::is_same_v<TY, uint16_t>) {
+    if constexpr (std::is_same_v<TY, uint16_t>) {
       if (L.taps == 27) {
-#define AIM_WG(CI, CO)                                                                          \
-  if (!done && cin == CI && cout == CO) {                                                     \
-    hipLaunchKernelGGL((wgrad_mfma_kernel<CI, CO>), dim3(unsigned(nchunk), 27), dim3(256), 0, s, \
-                       X, ldx, ox, dY, ldy, oy, D, H, W, chunk, acts.part);                    \
+        const uint16_t* Xb;
+        int kcin = cin;
+        if constexpr (std::is_same_v<TX, float>) {
+          // the 2-channel first layer, on its bf16-rounded input padded to 16
+          AIM_REQUIRE(cin == 2 && ldx == 2 && ox == 0, AIM_ERR_STATE, "first-layer input layout");
+          hipLaunchKernelGGL(pack_in16_kernel, dim3(unsigned((P + 255) / 256)), dim3(256), 0, s, X,
+                             P, acts.in16);
+          AIM_HIP(hipGetLastError());
+          Xb = acts.in16;
+          ldx = 16;
+          kcin = 16;
+        } else {
+          Xb = X;
+        }
+#define AIM_WG(CI, CO, CS)                                                                      \
+  if (!done && kcin == CI && cin == CS && cout == CO) {                                       \
+    hipLaunchKernelGGL((wgrad_mfma_kernel<CI, CO, CS>), dim3(unsigned(nchunk), 27), dim3(256), \
+                       0, s, Xb, ldx, ox, dY, ldy, oy, D, Ds, H, W, chunk, acts.part,          \
+                       acts.partb);                                                           \
     done = true;                                                                              \
   }
-        // the (input, output) channel pairs of the network's 3x3x3 layers
-        AIM_WG(16, 16)
-        AIM_WG(16, 32)
-        AIM_WG(32, 32)
-        AIM_WG(32, 64)
-        AIM_WG(64, 64)
-        AIM_WG(96, 32)
-        AIM_WG(48, 16)
+        // the (input, output, stored input) channel triples of the 3x3x3 layers
+        AIM_WG(16, 16, 2)
+        AIM_WG(16, 16, 16)
+        AIM_WG(16, 32, 16)
+        AIM_WG(32, 32, 32)
+        AIM_WG(32, 64, 32)
+        AIM_WG(64, 64, 64)
+        AIM_WG(96, 32, 96)
+        AIM_WG(48, 16, 48)
 #undef AIM_WG
       }
     }
-    if (!done) {
-      const size_t shm = size_t(kWgPos) * (cout + cin) * sizeof(float);
-      hipLaunchKernelGGL((wgrad_partial_kernel<TX, TY>), dim3(unsigned(nchunk), L.taps),
-                         dim3(256), shm, s, X, ldx, ox, cin, dY, ldy, oy, cout, D, H, W, L.taps,
-                         chunk, acts.part);
+    if constexpr (std::is_same_v<TX, uint16_t>) {
+      if (!done) {
+        const size_t shm = size_t(kWgPos) * (cout + cin) * sizeof(float);
+        hipLaunchKernelGGL((wgrad_partial_kernel<TX, TY>), dim3(unsigned(nchunk), L.taps),
+                           dim3(256), shm, s, X, ldx, ox, cin, dY, ldy, oy, cout, D, Ds, H, W,
+                           L.taps, chunk, acts.part);
+        AIM_HIP(hipGetLastError());
+        // bias partials over the same chunks
+        hipLaunchKernelGGL((bgrad_partial_kernel<TY>), dim3(unsigned(nchunk)), dim3(256), 0, s,
+                           dY, ldy, oy, cout, P, chunk, acts.partb);
+        done = true;
+      }
     }
+    AIM_REQUIRE(done, AIM_ERR_STATE, "unsupported weight-gradient layer");
     AIM_HIP(hipGetLastError());
-    const int64_t n = int64_t(cout) * L.taps * cin;
-    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(gsz(n)), dim3(256), 0, s, acts.part,
-                       int(nchunk), n, g + L.w_off);
-    AIM_HIP(hipGetLastError());
-    // bias: partial sums over position chunks (the partial buffer is free
-    // again once the weight reduction above has run on this stream)
-    int64_t nb = std::min<int64_t>(std::min<int64_t>(1024, acts.part_n / cout), (P + 1023) / 1024);
-    const int64_t bchunk = (P + nb - 1) / nb;
-    nb = (P + bchunk - 1) / bchunk;
-    hipLaunchKernelGGL((bgrad_partial_kernel<TY>), dim3(unsigned(nb)), dim3(256), 0, s, dY, ldy,
-                       oy, cout, P, bchunk, acts.part);
-    AIM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(gsz(cout)), dim3(256), 0, s, acts.part, int(nb),
-                       int64_t(cout), g + L.b_off);
-    AIM_HIP(hipGetLastError());
+    reduce(acts.part, nchunk, entries, g + L.w_off, s);
+    reduce(acts.partb, nchunk, cout, g + L.b_off, s);
   }
 
-  // forward pass on one sample: in = complex64 grid [D][H][W] (2 fp32), out fp32 [P][2]
-  void forward(const float* in, int D, int H, int W, float* out, hipStream_t s) {
-    ensure_acts(D, H, W);
+  // forward pass on nb samples stacked along z: in = complex64 grids
+  // [nb][Ds][H][W] (2 fp32 each), out fp32 [nb Ds H W][2]
+  void forward(const float* in, int nb, int Ds, int H, int W, float* out, hipStream_t s) {
+    ensure_acts(nb, Ds, H, W);
     Acts& a = acts;
+    const int D = a.D;
     const int c0 = C, c1 = 2 * C, c2 = 4 * C;
     const int D1 = D / 2, H1 = H / 2, W1 = W / 2, D2 = D / 4, H2 = H / 4, W2 = W / 4;
+    const int Ds1 = Ds / 2, Ds2 = Ds / 4;
     const int64_t P0 = int64_t(D) * H * W, P1 = P0 / 8;
     const Layer* Ls = layers.data();
     AIM_REQUIRE(C == 16, AIM_ERR_STATE, "only base width 16 is built");
-    hipLaunchKernelGGL((conv_first_kernel<16>), dim3(gsz(P0)), dim3(256), 0, s, in, D, H, W,
+    hipLaunchKernelGGL((conv_first_kernel<16>), dim3(gsz(P0)), dim3(256), 0, s, in, D, Ds, H, W,
                        w + Ls[0].w_off, w + Ls[0].b_off, a.a0, c0, 0);
     AIM_HIP(hipGetLastError());
-    conv(a.a0, c0, 0, c0, D, H, W, wb + Ls[1].w_off, w + Ls[1].b_off, a.cat0, c1 + c0, c1, c0, true, true, s);
-    hipLaunchKernelGGL(pool_kernel, dim3(gsz(P1 * c0)), dim3(256), 0, s, a.cat0, c1 + c0, c1, c0, D, H, W, a.p0);
-    conv(a.p0, c0, 0, c0, D1, H1, W1, wb + Ls[2].w_off, w + Ls[2].b_off, a.a1, c1, 0, c1, true, true, s);
-    conv(a.a1, c1, 0, c1, D1, H1, W1, wb + Ls[3].w_off, w + Ls[3].b_off, a.cat1, c2 + c1, c2, c1, true, true, s);
-    hipLaunchKernelGGL(pool_kernel, dim3(gsz(P1 / 8 * c1)), dim3(256), 0, s, a.cat1, c2 + c1, c2, c1, D1, H1, W1, a.p1);
-    conv(a.p1, c1, 0, c1, D2, H2, W2, wb + Ls[4].w_off, w + Ls[4].b_off, a.a2, c2, 0, c2, true, true, s);
-    conv(a.a2, c2, 0, c2, D2, H2, W2, wb + Ls[5].w_off, w + Ls[5].b_off, a.a3, c2, 0, c2, true, true, s);
-    hipLaunchKernelGGL(up_kernel, dim3(gsz(P1 * c2)), dim3(256), 0, s, a.a3, c2, D2, H2, W2, a.cat1, c2 + c1, 0);
-    conv(a.cat1, c2 + c1, 0, c2 + c1, D1, H1, W1, wb + Ls[6].w_off, w + Ls[6].b_off, a.a4, c1, 0, c1, true, true, s);
-    conv(a.a4, c1, 0, c1, D1, H1, W1, wb + Ls[7].w_off, w + Ls[7].b_off, a.a5, c1, 0, c1, true, true, s);
-    hipLaunchKernelGGL(up_kernel, dim3(gsz(P0 * c1)), dim3(256), 0, s, a.a5, c1, D1, H1, W1, a.cat0, c1 + c0, 0);
-    conv(a.cat0, c1 + c0, 0, c1 + c0, D, H, W, wb + Ls[8].w_off, w + Ls[8].b_off, a.a6, c0, 0, c0, true, true, s);
-    conv(a.a6, c0, 0, c0, D, H, W, wb + Ls[9].w_off, w + Ls[9].b_off, a.a7, c0, 0, c0, true, true, s);
+    conv(a.a0, c0, 0, c0, D, Ds, H, W, wb + Ls[1].w_off, w + Ls[1].b_off, a.cat0, c1 + c0, c1, c0, true, true, s);
+    hipLaunchKernelGGL(pool_kernel, dim3(gsz8(P1 * c0)), dim3(256), 0, s, a.cat0, c1 + c0, c1, c0, D, H, W, a.p0);
+    conv(a.p0, c0, 0, c0, D1, Ds1, H1, W1, wb + Ls[2].w_off, w + Ls[2].b_off, a.a1, c1, 0, c1, true, true, s);
+    conv(a.a1, c1, 0, c1, D1, Ds1, H1, W1, wb + Ls[3].w_off, w + Ls[3].b_off, a.cat1, c2 + c1, c2, c1, true, true, s);
+    hipLaunchKernelGGL(pool_kernel, dim3(gsz8(P1 / 8 * c1)), dim3(256), 0, s, a.cat1, c2 + c1, c2, c1, D1, H1, W1, a.p1);
+    conv(a.p1, c1, 0, c1, D2, Ds2, H2, W2, wb + Ls[4].w_off, w + Ls[4].b_off, a.a2, c2, 0, c2, true, true, s);
+    conv(a.a2, c2, 0, c2, D2, Ds2, H2, W2, wb + Ls[5].w_off, w + Ls[5].b_off, a.a3, c2, 0, c2, true, true, s);
+    hipLaunchKernelGGL(up_kernel, dim3(gsz8(P1 * c2)), dim3(256), 0, s, a.a3, c2, D2, H2, W2, a.cat1, c2 + c1, 0);
+    conv(a.cat1, c2 + c1, 0, c2 + c1, D1, Ds1, H1, W1, wb + Ls[6].w_off, w + Ls[6].b_off, a.a4, c1, 0, c1, true, true, s);
+    conv(a.a4, c1, 0, c1, D1, Ds1, H1, W1, wb + Ls[7].w_off, w + Ls[7].b_off, a.a5, c1, 0, c1, true, true, s);
+    hipLaunchKernelGGL(up_kernel, dim3(gsz8(P0 * c1)), dim3(256), 0, s, a.a5, c1, D1, H1, W1, a.cat0, c1 + c0, 0);
+    conv(a.cat0, c1 + c0, 0, c1 + c0, D, Ds, H, W, wb + Ls[8].w_off, w + Ls[8].b_off, a.a6, c0, 0, c0, true, true, s);
+    conv(a.a6, c0, 0, c0, D, Ds, H, W, wb + Ls[9].w_off, w + Ls[9].b_off, a.a7, c0, 0, c0, true, true, s);
     hipLaunchKernelGGL((conv_out_kernel<16>), dim3(gsz(P0)), dim3(256), 0, s, a.a7, P0,
                        w + Ls[10].w_off, w + Ls[10].b_off, out ? out : a.out);
     AIM_HIP(hipGetLastError());
   }
 
-  // backward pass after forward(in) on the same sample; dout fp32 [P][2];
-  // gradients are added to g
+  // backward pass after forward(in) on the same batch; dout fp32 [P][2];
+  // gradients (summed over the batch) are added to g
   void backward(const float* in, const float* dout, hipStream_t s) {
     Acts& a = acts;
-    const int D = a.D, H = a.H, W = a.W;
+    const int D = a.D, H = a.H, W = a.W, Ds = a.Ds, Ds1 = Ds / 2, Ds2 = Ds / 4;
     const int c0 = C, c1 = 2 * C, c2 = 4 * C;
     const int D1 = D / 2, H1 = H / 2, W1 = W / 2, D2 = D / 4, H2 = H / 4, W2 = W / 4;
     const int64_t P0 = int64_t(D) * H * W, P1 = P0 / 8, P2 = P1 / 8;
     const Layer* Ls = layers.data();
     // output layer
-    wgrad<uint16_t, float>(a.a7, c0, 0, c0, dout, 2, 0, 2, D, H, W, Ls[10], s);
+    wgrad<uint16_t, float>(a.a7, c0, 0, c0, dout, 2, 0, 2, D, Ds, H, W, Ls[10], s);
     hipLaunchKernelGGL((out_backward_kernel<16>), dim3(gsz(P0)), dim3(256), 0, s, dout,
                        w + Ls[10].w_off, a.a7, P0, a.gb0);
     // conv9
-    wgrad<uint16_t, uint16_t>(a.a6, c0, 0, c0, a.gb0, c0, 0, c0, D, H, W, Ls[9], s);
-    conv(a.gb0, c0, 0, c0, D, H, W, wf + Ls[9].flip_off, nullptr, a.g0, c0, 0, c0, false, false, s);
-    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P0 * c0)), dim3(256), 0, s, a.g0, c0, 0, a.a6, c0, 0, c0, P0, a.gb0);
+    wgrad<uint16_t, uint16_t>(a.a6, c0, 0, c0, a.gb0, c0, 0, c0, D, Ds, H, W, Ls[9], s);
+    conv(a.gb0, c0, 0, c0, D, Ds, H, W, wf + Ls[9].flip_off, nullptr, a.g0, c0, 0, c0, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz8(P0 * c0)), dim3(256), 0, s, a.g0, c0, 0, a.a6, c0, 0, c0, P0, a.gb0);
     // conv8 (input cat0 = [up(a5) | s0])
-    wgrad<uint16_t, uint16_t>(a.cat0, c1 + c0, 0, c1 + c0, a.gb0, c0, 0, c0, D, H, W, Ls[8], s);
-    conv(a.gb0, c0, 0, c0, D, H, W, wf + Ls[8].flip_off, nullptr, a.gcat0, c1 + c0, 0, c1 + c0, false, false, s);
-    hipLaunchKernelGGL(up_backward_kernel, dim3(gsz(P1 * c1)), dim3(256), 0, s, a.gcat0, c1 + c0, 0, c1, D1, H1, W1, a.a5, a.gb1);
+    wgrad<uint16_t, uint16_t>(a.cat0, c1 + c0, 0, c1 + c0, a.gb0, c0, 0, c0, D, Ds, H, W, Ls[8], s);
+    conv(a.gb0, c0, 0, c0, D, Ds, H, W, wf + Ls[8].flip_off, nullptr, a.gcat0, c1 + c0, 0, c1 + c0, false, false, s);
+    hipLaunchKernelGGL(up_backward_kernel, dim3(gsz8(P1 * c1)), dim3(256), 0, s, a.gcat0, c1 + c0, 0, c1, D1, H1, W1, a.a5, a.gb1);
     // conv7
-    wgrad<uint16_t, uint16_t>(a.a4, c1, 0, c1, a.gb1, c1, 0, c1, D1, H1, W1, Ls[7], s);
-    conv(a.gb1, c1, 0, c1, D1, H1, W1, wf + Ls[7].flip_off, nullptr, a.g1, c1, 0, c1, false, false, s);
-    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P1 * c1)), dim3(256), 0, s, a.g1, c1, 0, a.a4, c1, 0, c1, P1, a.gb1);
+    wgrad<uint16_t, uint16_t>(a.a4, c1, 0, c1, a.gb1, c1, 0, c1, D1, Ds1, H1, W1, Ls[7], s);
+    conv(a.gb1, c1, 0, c1, D1, Ds1, H1, W1, wf + Ls[7].flip_off, nullptr, a.g1, c1, 0, c1, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz8(P1 * c1)), dim3(256), 0, s, a.g1, c1, 0, a.a4, c1, 0, c1, P1, a.gb1);
     // conv6 (input cat1 = [up(a3) | s1])
-    wgrad<uint16_t, uint16_t>(a.cat1, c2 + c1, 0, c2 + c1, a.gb1, c1, 0, c1, D1, H1, W1, Ls[6], s);
-    conv(a.gb1, c1, 0, c1, D1, H1, W1, wf + Ls[6].flip_off, nullptr, a.gcat1, c2 + c1, 0, c2 + c1, false, false, s);
-    hipLaunchKernelGGL(up_backward_kernel, dim3(gsz(P2 * c2)), dim3(256), 0, s, a.gcat1, c2 + c1, 0, c2, D2, H2, W2, a.a3, a.gb2);
+    wgrad<uint16_t, uint16_t>(a.cat1, c2 + c1, 0, c2 + c1, a.gb1, c1, 0, c1, D1, Ds1, H1, W1, Ls[6], s);
+    conv(a.gb1, c1, 0, c1, D1, Ds1, H1, W1, wf + Ls[6].flip_off, nullptr, a.gcat1, c2 + c1, 0, c2 + c1, false, false, s);
+    hipLaunchKernelGGL(up_backward_kernel, dim3(gsz8(P2 * c2)), dim3(256), 0, s, a.gcat1, c2 + c1, 0, c2, D2, H2, W2, a.a3, a.gb2);
     // conv5
-    wgrad<uint16_t, uint16_t>(a.a2, c2, 0, c2, a.gb2, c2, 0, c2, D2, H2, W2, Ls[5], s);
-    conv(a.gb2, c2, 0, c2, D2, H2, W2, wf + Ls[5].flip_off, nullptr, a.g2, c2, 0, c2, false, false, s);
-    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P2 * c2)), dim3(256), 0, s, a.g2, c2, 0, a.a2, c2, 0, c2, P2, a.gb2);
+    wgrad<uint16_t, uint16_t>(a.a2, c2, 0, c2, a.gb2, c2, 0, c2, D2, Ds2, H2, W2, Ls[5], s);
+    conv(a.gb2, c2, 0, c2, D2, Ds2, H2, W2, wf + Ls[5].flip_off, nullptr, a.g2, c2, 0, c2, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz8(P2 * c2)), dim3(256), 0, s, a.g2, c2, 0, a.a2, c2, 0, c2, P2, a.gb2);
     // conv4 (input p1)
-    wgrad<uint16_t, uint16_t>(a.p1, c1, 0, c1, a.gb2, c2, 0, c2, D2, H2, W2, Ls[4], s);
-    conv(a.gb2, c2, 0, c2, D2, H2, W2, wf + Ls[4].flip_off, nullptr, a.g2, c1, 0, c1, false, false, s);
-    hipLaunchKernelGGL(pool_backward_kernel, dim3(gsz(P1 * c1)), dim3(256), 0, s, a.g2, c1, D1, H1, W1,
+    wgrad<uint16_t, uint16_t>(a.p1, c1, 0, c1, a.gb2, c2, 0, c2, D2, Ds2, H2, W2, Ls[4], s);
+    conv(a.gb2, c2, 0, c2, D2, Ds2, H2, W2, wf + Ls[4].flip_off, nullptr, a.g2, c1, 0, c1, false, false, s);
+    hipLaunchKernelGGL(pool_backward_kernel, dim3(gsz8(P1 * c1)), dim3(256), 0, s, a.g2, c1, D1, H1, W1,
                        a.gcat1, c2 + c1, c2, a.cat1, c2 + c1, c2, a.gb1);
     // conv3
-    wgrad<uint16_t, uint16_t>(a.a1, c1, 0, c1, a.gb1, c1, 0, c1, D1, H1, W1, Ls[3], s);
-    conv(a.gb1, c1, 0, c1, D1, H1, W1, wf + Ls[3].flip_off, nullptr, a.g1, c1, 0, c1, false, false, s);
-    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P1 * c1)), dim3(256), 0, s, a.g1, c1, 0, a.a1, c1, 0, c1, P1, a.gb1);
+    wgrad<uint16_t, uint16_t>(a.a1, c1, 0, c1, a.gb1, c1, 0, c1, D1, Ds1, H1, W1, Ls[3], s);
+    conv(a.gb1, c1, 0, c1, D1, Ds1, H1, W1, wf + Ls[3].flip_off, nullptr, a.g1, c1, 0, c1, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz8(P1 * c1)), dim3(256), 0, s, a.g1, c1, 0, a.a1, c1, 0, c1, P1, a.gb1);
     // conv2 (input p0)
-    wgrad<uint16_t, uint16_t>(a.p0, c0, 0, c0, a.gb1, c1, 0, c1, D1, H1, W1, Ls[2], s);
-    conv(a.gb1, c1, 0, c1, D1, H1, W1, wf + Ls[2].flip_off, nullptr, a.g1, c0, 0, c0, false, false, s);
-    hipLaunchKernelGGL(pool_backward_kernel, dim3(gsz(P0 * c0)), dim3(256), 0, s, a.g1, c0, D, H, W,
+    wgrad<uint16_t, uint16_t>(a.p0, c0, 0, c0, a.gb1, c1, 0, c1, D1, Ds1, H1, W1, Ls[2], s);
+    conv(a.gb1, c1, 0, c1, D1, Ds1, H1, W1, wf + Ls[2].flip_off, nullptr, a.g1, c0, 0, c0, false, false, s);
+    hipLaunchKernelGGL(pool_backward_kernel, dim3(gsz8(P0 * c0)), dim3(256), 0, s, a.g1, c0, D, H, W,
                        a.gcat0, c1 + c0, c1, a.cat0, c1 + c0, c1, a.gb0);
     // conv1
-    wgrad<uint16_t, uint16_t>(a.a0, c0, 0, c0, a.gb0, c0, 0, c0, D, H, W, Ls[1], s);
-    conv(a.gb0, c0, 0, c0, D, H, W, wf + Ls[1].flip_off, nullptr, a.g0, c0, 0, c0, false, false, s);
-    hipLaunchKernelGGL(mask_kernel, dim3(gsz(P0 * c0)), dim3(256), 0, s, a.g0, c0, 0, a.a0, c0, 0, c0, P0, a.gb0);
+    wgrad<uint16_t, uint16_t>(a.a0, c0, 0, c0, a.gb0, c0, 0, c0, D, Ds, H, W, Ls[1], s);
+    conv(a.gb0, c0, 0, c0, D, Ds, H, W, wf + Ls[1].flip_off, nullptr, a.g0, c0, 0, c0, false, false, s);
+    hipLaunchKernelGGL(mask_kernel, dim3(gsz8(P0 * c0)), dim3(256), 0, s, a.g0, c0, 0, a.a0, c0, 0, c0, P0, a.gb0);
     // conv0 (fp32 input, 2 channels)
-    wgrad<float, uint16_t>(in, 2, 0, 2, a.gb0, c0, 0, c0, D, H, W, Ls[0], s);
+    wgrad<float, uint16_t>(in, 2, 0, 2, a.gb0, c0, 0, c0, D, Ds, H, W, Ls[0], s);
     AIM_HIP(hipGetLastError());
   }
 
@@ -905,8 +1040,9 @@ struct aim_unet_s {
 
 namespace aim {
 // used by the solver integration in abi.cpp
-void unet_forward(aim_unet u, const void* in, int D, int H, int W, void* out, hipStream_t s) {
-  u->forward(static_cast<const float*>(in), D, H, W, static_cast<float*>(out), s);
+void unet_forward(aim_unet u, const void* in, int nb, int D, int H, int W, void* out,
+                  hipStream_t s) {
+  u->forward(static_cast<const float*>(in), nb, D, H, W, static_cast<float*>(out), s);
 }
 void unet_backward(aim_unet u, const void* in, const void* dout, hipStream_t s) {
   u->backward(static_cast<const float*>(in), static_cast<const float*>(dout), s);
@@ -1013,10 +1149,8 @@ aim_status aim_unet_forward(aim_unet u, const void* in_dev, void* out_dev, int32
   return uguard([&] {
     AIM_REQUIRE(nbatch >= 1, AIM_ERR_INVALID_ARG, "nbatch must be >= 1");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const int64_t P = int64_t(dims[0]) * dims[1] * dims[2];
-    for (int b = 0; b < nbatch; ++b)
-      u->forward(static_cast<const float*>(in_dev) + 2 * P * b, dims[2], dims[1], dims[0],
-                 static_cast<float*>(out_dev) + 2 * P * b, s);
+    u->forward(static_cast<const float*>(in_dev), nbatch, dims[2], dims[1], dims[0],
+               static_cast<float*>(out_dev), s);
   });
 }
 
@@ -1032,25 +1166,24 @@ aim_status aim_unet_train_grid(aim_unet u, const void* in_dev, const void* targe
     constexpr int kParts = 256;
     float* dout = nullptr;
     float* part = nullptr;
-    AIM_HIP(hipMalloc(&dout, 2 * P * 4));
-    hipError_t e = hipMalloc(&part, size_t(kParts) * nbatch * 4);
+    AIM_HIP(hipMalloc(&dout, 2 * P * nbatch * 4));
+    hipError_t e = hipMalloc(&part, size_t(kParts) * 4);
     if (e != hipSuccess) {
       (void)hipFree(dout);
       AIM_HIP(e);
     }
-    std::vector<float> hp(size_t(kParts) * nbatch);
+    std::vector<float> hp(kParts);
     try {
-      for (int b = 0; b < nbatch; ++b) {
-        const float* in = static_cast<const float*>(in_dev) + 2 * P * b;
-        const float* tg = static_cast<const float*>(target_dev) + 2 * P * b;
-        u->forward(in, dims[2], dims[1], dims[0], nullptr, s);
-        // mean squared error over all entries of the batch
-        const float inv = 1.f / (float(2 * P) * float(nbatch));
-        hipLaunchKernelGGL(mse_kernel, dim3(kParts), dim3(256), 0, s, u->acts.out, tg, 2 * P,
-                           2.f * inv, inv, dout, part + size_t(kParts) * b);
-        AIM_HIP(hipGetLastError());
-        u->backward(in, dout, s);
-      }
+      // the whole batch in one pass, samples stacked along z
+      const float* in = static_cast<const float*>(in_dev);
+      const float* tg = static_cast<const float*>(target_dev);
+      u->forward(in, nbatch, dims[2], dims[1], dims[0], nullptr, s);
+      // mean squared error over all entries of the batch
+      const float inv = 1.f / (float(2 * P) * float(nbatch));
+      hipLaunchKernelGGL(mse_kernel, dim3(kParts), dim3(256), 0, s, u->acts.out, tg,
+                         2 * P * nbatch, 2.f * inv, inv, dout, part);
+      AIM_HIP(hipGetLastError());
+      u->backward(in, dout, s);
       if (apply) u->adam(lr, s);
       AIM_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * 4, hipMemcpyDeviceToHost, s));
       AIM_HIP(hipStreamSynchronize(s));

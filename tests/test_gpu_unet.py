@@ -73,6 +73,46 @@ def test_gradients_match_reference():
     net.close()
 
 
+def test_batched_forward_equals_each_sample():
+    """A batch is stacked along z; each sample's output must equal the one it
+    gets alone, bit for bit (the same products in the same order), also
+    where a 4-plane brick straddles two samples (12 planes deep: the coarsest
+    level is 3 planes per sample)."""
+    net = binding.UNet(seed=5)
+    shape = (12, 8, 16)
+    xs = [grid_c64(shape, 40 + i) for i in range(3)]
+    out = net.forward(torch.stack([to_dev(x) for x in xs]))
+    for i, x in enumerate(xs):
+        assert torch.equal(out[i], net.forward(to_dev(x))), i
+    net.close()
+
+
+def test_batched_gradients_match_reference():
+    """Loss and gradients of a batch of two: the batch mean of the oracle's
+    per-sample losses and gradients."""
+    net = binding.UNet(seed=15)
+    layers = binding.unet_params_to_layers(net.params())
+    shape = (12, 8, 8)
+    xs = [grid_c64(shape, 50 + i) for i in range(2)]
+    ts = [grid_c64(shape, 60 + i) for i in range(2)]
+    loss = net.train_grid(torch.stack([to_dev(x) for x in xs]),
+                          torch.stack([to_dev(t) for t in ts]), apply=False)
+    g = binding.unet_params_to_layers(net.grads())
+    r = ref.UNet(layers, bf16=True)
+    want_loss, want = 0.0, None
+    for x, t in zip(xs, ts):
+        want_loss += 0.5 * r.loss(x.astype(np.float64), t.astype(np.float64))
+        gi = r.backward(t.astype(np.float64))
+        gi = [(0.5 * W, 0.5 * b) for W, b in gi]
+        want = gi if want is None else [(W + a, b + c) for (W, b), (a, c) in zip(want, gi)]
+    assert loss == pytest.approx(want_loss, rel=1e-2)
+    for i, ((dW, db), (rW, rb)) in enumerate(zip(g, want)):
+        e_w, e_b = rel(dW, rW), rel(db, rb)
+        print(f"    layer {i}: dW {e_w:.2e} db {e_b:.2e}", flush=True)
+        assert e_w <= 3e-2 and e_b <= 3e-2, i
+    net.close()
+
+
 def test_training_reduces_loss_and_weights_roundtrip(tmp_path):
     net = binding.UNet(seed=21)
     shape = (8, 8, 8)
