@@ -90,13 +90,28 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restri
   b /= nbx;
   const int by = b % nby, bz = b / nby;
   const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
-  for (int u = tid; u < kTilePos * C8; u += 256) {
-    const int c8 = u % C8, pos = u / C8;
-    const int gx = x0 + pos % kTX - 1, gy = y0 + (pos / kTX) % kTY - 1, gz = z0 + pos / (kTX * kTY) - 1;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gx >= 0 && gy >= 0 && gz >= 0 && gx < W && gy < H && gz < D)
-      v = *reinterpret_cast<const uint4*>(X + ((int64_t(gz) * H + gy) * W + gx) * ldx + ox + 8 * c8);
-    tile[u] = v;
+  // stage the tile in batches of 8 loads per thread, all in flight together
+  constexpr int kTileWords = kTilePos * C8, kBatch = 8 * 256;
+  for (int u0 = 0; u0 < kTileWords; u0 += kBatch) {
+    uint4 v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int u = u0 + j * 256 + tid;
+      v[j] = make_uint4(0u, 0u, 0u, 0u);
+      if (u < kTileWords) {
+        const int c8 = u % C8, pos = u / C8;
+        const int gx = x0 + pos % kTX - 1, gy = y0 + (pos / kTX) % kTY - 1,
+                  gz = z0 + pos / (kTX * kTY) - 1;
+        if (gx >= 0 && gy >= 0 && gz >= 0 && gx < W && gy < H && gz < D)
+          v[j] = *reinterpret_cast<const uint4*>(X + ((int64_t(gz) * H + gy) * W + gx) * ldx + ox +
+                                                 8 * c8);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int u = u0 + j * 256 + tid;
+      if (u < kTileWords) tile[u] = v[j];
+    }
   }
   __syncthreads();
   const int col = lane & 15, kg = lane >> 4;
@@ -111,25 +126,47 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restri
 #pragma unroll
     for (int t = 0; t < TILES; ++t) acc[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bf16x8 zero = as_bf16x8(make_uint4(0u, 0u, 0u, 0u));
-  for (int ch = 0; ch < NCH; ++ch) {
-    const int k = ch * 32 + 8 * kg;
-    const bool kv = k < K;
-    const int tap = kv ? k / CIN : 0, ci = kv ? k % CIN : 0;
-    const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
-    const bool bok = kv && (dz == 1 || (dz == 0 ? lo_ok : hi_ok));
-    bf16x8 bv[kBY];
+  // weights stream through a ring of PF K steps held in registers: the
+  // loads for step ch + PF are issued while step ch computes (on small grids
+  // the few workgroups would otherwise wait out a load latency per step)
+  // (depth 4, or 2 where the extra registers would cost occupancy that the
+  // LDS tile leaves)
+  constexpr int PF = (TILES <= 2 || (CIN >= 64 && TILES <= 4)) ? 4 : 2;
+  auto wload = [&](int k, bf16x8* w) {
 #pragma unroll
-    for (int g = 0; g < kBY; ++g) {
-      const int pos = ((wave + dz) * kTY + g + dy) * kTX + col + dx;
-      bv[g] = bok ? as_bf16x8(tile[pos * C8 + ci / 8]) : zero;
-    }
+    for (int t = 0; t < TILES; ++t)
+      w[t] = k < K ? as_bf16x8(*reinterpret_cast<const uint4*>(Wt + int64_t(t * 16 + col) * K + k))
+                   : zero;
+  };
+  bf16x8 wq[PF][TILES];
 #pragma unroll
-    for (int t = 0; t < TILES; ++t) {
-      const bf16x8 av =
-          kv ? as_bf16x8(*reinterpret_cast<const uint4*>(Wt + int64_t(t * 16 + col) * K + k)) : zero;
+  for (int j = 0; j < PF; ++j) wload(32 * j + 8 * kg, wq[j]);
+  for (int c0 = 0; c0 < NCH; c0 += PF) {
 #pragma unroll
-      for (int g = 0; g < kBY; ++g)
-        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[g], acc[g][t], 0, 0, 0);
+    for (int j = 0; j < PF; ++j) {
+      const int ch = c0 + j;
+      if (ch < NCH) {
+        const int k = ch * 32 + 8 * kg;
+        const bool kv = k < K;
+        bf16x8 wc[TILES];
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) wc[t] = wq[j][t];
+        if (ch + PF < NCH) wload(k + 32 * PF, wq[j]);
+        const int tap = kv ? k / CIN : 0, ci = kv ? k % CIN : 0;
+        const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+        const bool bok = kv && (dz == 1 || (dz == 0 ? lo_ok : hi_ok));
+        bf16x8 bv[kBY];
+#pragma unroll
+        for (int g = 0; g < kBY; ++g) {
+          const int pos = ((wave + dz) * kTY + g + dy) * kTX + col + dx;
+          bv[g] = bok ? as_bf16x8(tile[pos * C8 + ci / 8]) : zero;
+        }
+#pragma unroll
+        for (int t = 0; t < TILES; ++t)
+#pragma unroll
+          for (int g = 0; g < kBY; ++g)
+            acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc[t], bv[g], acc[g][t], 0, 0, 0);
+      }
     }
   }
   const int x = x0 + col, z = z0 + wave;
@@ -180,12 +217,19 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
   float acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = bias[c];
+  // the 27 neighbours are loaded together (outside the sample: zero)
+  float2 nb[27];
+#pragma unroll
   for (int tap = 0; tap < 27; ++tap) {
     const int nx = x + tap % 3 - 1, ny = y + (tap / 3) % 3 - 1, nz = z + tap / 9 - 1;
-    if (nx < 0 || ny < 0 || nz < zs || nx >= W || ny >= H || nz >= zs + Ds) continue;
-    const float2 v = *reinterpret_cast<const float2*>(in + 2 * ((int64_t(nz) * H + ny) * W + nx));
+    nb[tap] = make_float2(0.f, 0.f);
+    if (nx >= 0 && ny >= 0 && nz >= zs && nx < W && ny < H && nz < zs + Ds)
+      nb[tap] = *reinterpret_cast<const float2*>(in + 2 * ((int64_t(nz) * H + ny) * W + nx));
+  }
+#pragma unroll
+  for (int tap = 0; tap < 27; ++tap) {
     // the first layer reads bf16-rounded inputs, like every other layer
-    const float v0 = bf2f(f2bf(v.x)), v1 = bf2f(f2bf(v.y));
+    const float v0 = bf2f(f2bf(nb[tap].x)), v1 = bf2f(f2bf(nb[tap].y));
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] += w[(c * 27 + tap) * 2] * v0 + w[(c * 27 + tap) * 2 + 1] * v1;
   }
