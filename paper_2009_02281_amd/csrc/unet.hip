@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(
 }
 
 // grad[i] (+)= sum_c part[c][i]: a block takes 64 consecutive entries, its
-// four waves a quarter of the chunks each
+// four waves a quarter of the chunks each, eight loads in flight per thread
 __global__ __launch_bounds__(256) void reduce_chunks_kernel(const float* __restrict__ part,
                                                             int nchunk, int64_t n,
                                                             float* __restrict__ grad) {
@@ -444,7 +444,16 @@ __global__ __launch_bounds__(256) void reduce_chunks_kernel(const float* __restr
   const int64_t i = int64_t(blockIdx.x) * 64 + e;
   float s = 0.f;
   if (i < n)
-    for (int c = q; c < nchunk; c += 4) s += part[int64_t(c) * n + i];
+    for (int c0 = q; c0 < nchunk; c0 += 32) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = c0 + 4 * j;
+        v[j] = c < nchunk ? part[int64_t(c) * n + i] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s += v[j];
+    }
   red[q][e] = s;
   __syncthreads();
   if (q == 0 && i < n) grad[i] += (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
@@ -640,8 +649,18 @@ __global__ void to_bf16_kernel(const float* __restrict__ w, int64_t n, uint16_t*
     o[i] = f2bf(w[i]);
 }
 
-__global__ void flip_kernel(const float* __restrict__ w, int Cout, int Cin,
-                            uint16_t* __restrict__ o) {
+// all flipped copies in one launch: blockIdx.y picks the layer
+struct FlipSet {
+  int n;                                  // layers
+  int cout[12], cin[12];
+  int64_t w_off[12], f_off[12];
+};
+__global__ void flip_kernel(const float* __restrict__ wall, FlipSet fs,
+                            uint16_t* __restrict__ oall) {
+  const int L = blockIdx.y;
+  const int Cout = fs.cout[L], Cin = fs.cin[L];
+  const float* w = wall + fs.w_off[L];
+  uint16_t* o = oall + fs.f_off[L];
   const int64_t n = int64_t(Cout) * 27 * Cin;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
@@ -787,12 +806,20 @@ struct aim_unet_s {
   void refresh(hipStream_t s) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3(gsz(nparam)), dim3(256), 0, s, w, nparam, wb);
     AIM_HIP(hipGetLastError());
+    FlipSet fs{};
+    int64_t mx = 0;
     for (const auto& L : layers) {
       if (L.taps != 27 || L.cin == 2) continue;
-      hipLaunchKernelGGL(flip_kernel, dim3(gsz(int64_t(L.cout) * 27 * L.cin)), dim3(256), 0, s,
-                         w + L.w_off, L.cout, L.cin, wf + L.flip_off);
-      AIM_HIP(hipGetLastError());
+      AIM_REQUIRE(fs.n < 12, AIM_ERR_STATE, "too many layers");
+      fs.cout[fs.n] = L.cout;
+      fs.cin[fs.n] = L.cin;
+      fs.w_off[fs.n] = L.w_off;
+      fs.f_off[fs.n] = L.flip_off;
+      ++fs.n;
+      mx = std::max<int64_t>(mx, int64_t(L.cout) * 27 * L.cin);
     }
+    hipLaunchKernelGGL(flip_kernel, dim3(gsz(mx), unsigned(fs.n)), dim3(256), 0, s, w, fs, wf);
+    AIM_HIP(hipGetLastError());
   }
 
   // buffers for nb samples of Ds x H x W stacked along z
