@@ -129,24 +129,62 @@ def cpu_baseline(w, x, reps: int = 3, near_rows: int = 512) -> dict:
 RESTART = 60
 
 
-def solve_leg(plan, rtol: float) -> dict:
+def cpu_gmres_leg(rtol: float) -> dict:
+    """GMRES(RESTART) to rtol for the +z plane wave on the 1,280-triangle
+    sphere: the oracle (NumPy/SciPy float64 FGMRES on this host, operator
+    set-up excluded) beside the library's complex128 solve on the GPU.  Each
+    side builds its own right-hand side."""
+    import numpy as np
+    import torch
+    from oracle import aimx, excitation, solver
+    from paper_2009_02281_amd import binding
+    w = make_workload("sphere")
+    k = float(w.k[0])
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    o.spectrum(k)
+    _ = o.C
+    b = excitation.plane_wave(w.vertices, w.triangles, k, (0.0, 0.0, 1.0))
+    t0 = time.perf_counter()
+    _, info = solver.fgmres(lambda v: o.matvec(v, k), b, tol=rtol, restart=RESTART,
+                            max_iter=4000)
+    t_cpu = time.perf_counter() - t0
+    plan = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
+    bg = plan.excitation("plane_wave", [0.0, 0.0, 1.0])
+    plan.solve(bg, rtol=1e-2, restart=RESTART, max_iter=30, raise_on_fail=False)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r = plan.solve(bg, rtol=rtol, restart=RESTART, max_iter=4000, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    plan.close()
+    return {"workload": f"{w.name} (N={w.n}, grid {list(w.dims)}, k={k})", "rtol": rtol,
+            "restart": RESTART, "cpu": {"seconds": t_cpu, "iters": int(info.iters),
+                                        "rel_resid": float(info.rel_resid),
+                                        "converged": bool(info.converged),
+                                        "cores": os.cpu_count() or 1, "kind": "oracle"},
+            "gpu": {"seconds": t_gpu, "iters": int(r.iters[0]),
+                    "rel_resid": float(r.rel_resid[0]), "converged": bool(r.converged[0]),
+                    "precision": "c128"}}
+
+
+def solve_leg(plan, rtol: float, max_iter: int = 4000,
+              pcs=("none", "diag", "nearblock")) -> dict:
     """Time to rtol for the +z plane wave: complex128 GMRES(RESTART) without
     preconditioner (the reference) against complex64-matvec GMRES inside
     complex128 refinement, each also with the static diagonal and the
     near-field block preconditioner."""
     import torch
     b = plan.excitation("plane_wave", [0.0, 0.0, 1.0])
-    runs = [("c128", "none"), ("c128", "diag"), ("c128", "nearblock"),
-            ("c64", "none"), ("c64", "diag"), ("c64", "nearblock")]
+    runs = [(inner, pc) for inner in ("c128", "c64") for pc in pcs]
     res = {}
     for inner, pc in runs:
         plan.solve(b, rtol=1e-2, restart=RESTART, max_iter=30, inner=inner, pc=pc,
                    raise_on_fail=False)                    # warm-up (workspace, graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        # max_refine 4: the complex64 runs converge in 2 refinement steps; a run
-        # that stalls stops after 4 x 4000 inner steps
-        x, r = plan.solve(b, rtol=rtol, restart=RESTART, max_iter=4000, inner=inner, pc=pc,
+        # max_refine 4: the complex64 runs converge in 2-3 refinement steps; a
+        # run that stalls stops after 4 x max_iter inner steps
+        x, r = plan.solve(b, rtol=rtol, restart=RESTART, max_iter=max_iter, inner=inner, pc=pc,
                           max_refine=4, raise_on_fail=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -157,7 +195,8 @@ def solve_leg(plan, rtol: float) -> dict:
                                 "converged": bool(r.converged[0])}
         print(f"[bench] gmres {inner}+{pc}: {dt:.3f}s iters={r.iters[0]} "
               f"resid={r.rel_resid[0]:.2e}", file=sys.stderr, flush=True)
-    return {"rtol": rtol, "rhs": "plane wave +z", "restart": RESTART, "runs": res}
+    return {"rtol": rtol, "rhs": "plane wave +z", "restart": RESTART, "max_iter": max_iter,
+            "runs": res}
 
 
 def learned_pc_leg(rtol: float) -> dict:
@@ -306,6 +345,10 @@ def main() -> int:
                     help="skip the learned-preconditioner time-to-tolerance leg")
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net throughput leg")
     ap.add_argument("--solve-rtol", type=float, default=1e-6)
+    ap.add_argument("--solve-max-iter", type=int, default=4000,
+                    help="GMRES iteration cap per solve (per refinement step in complex64)")
+    ap.add_argument("--solve-pcs", default="none,diag,nearblock",
+                    help="comma-separated preconditioners for the GMRES leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -370,6 +413,19 @@ def main() -> int:
     value = w.n * args.nrhs / (ms * 1e-3)
     print(f"[bench] {ms:.4f} ms/matvec -> {value:.4e} unknowns*matvecs/s", file=sys.stderr,
           flush=True)
+    # spread of single matvecs (events around each one; outside the timed region)
+    nsamp = max(20, min(100, args.steps))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(nsamp)]
+    for a, b in evs:
+        a.record()
+        plan.matvec(x, prec=args.prec, out=y, freq_idx=freq)
+        b.record()
+    torch.cuda.synchronize()
+    one = sorted(a.elapsed_time(b) for a, b in evs)
+    q = lambda f: one[min(nsamp - 1, int(round(f * (nsamp - 1))))]
+    spread = {"samples": nsamp, "median_ms": q(0.5), "p25_ms": q(0.25), "p75_ms": q(0.75),
+              "note": "one matvec between two events each, after the timed region"}
 
     out = {
         "metric": "AIM matvec unknowns/s",
@@ -390,6 +446,7 @@ def main() -> int:
                    "nrhs": args.nrhs, "nnz": info["nnz"],
                    "n_freq": int(len(w.k))},
         "fft_schedule": {pr: tuned[pr]["schedule"] for pr in tuned},
+        "ms_per_matvec_spread": spread,
     }
 
     if args.workload == "sweep":
@@ -428,7 +485,8 @@ def main() -> int:
               file=sys.stderr, flush=True)
 
     if not args.no_solve:
-        out["gmres"] = solve_leg(plan, args.solve_rtol)
+        out["gmres"] = solve_leg(plan, args.solve_rtol, args.solve_max_iter,
+                                 tuple(args.solve_pcs.split(",")))
     if not args.no_learned and args.workload != "sweep":
         out["learned_pc"] = learned_pc_leg(args.solve_rtol)
     if not args.no_unet and args.workload != "sweep":
@@ -440,6 +498,10 @@ def main() -> int:
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         print(f"[bench] oracle {cb['seconds_per_matvec']:.3f} s/matvec", file=sys.stderr,
               flush=True)
+        if not args.no_solve:
+            out["cpu_gmres"] = cpu_gmres_leg(args.solve_rtol)
+            print(f"[bench] GMRES on the small sphere: oracle {out['cpu_gmres']['cpu']}, "
+                  f"GPU {out['cpu_gmres']['gpu']}", file=sys.stderr, flush=True)
     plan.close()
     print(json.dumps(out), flush=True)
     return 0

@@ -84,6 +84,24 @@ def test_solve_tight_tolerance_with_refinement():
     assert res.refinements[0] >= 2
 
 
+def test_complex64_inner_solve_stops_at_its_accuracy_floor():
+    """An inner tolerance below what complex64 matvecs resolve must not spin
+    the inner solve in short restart cycles up to max_iter: it hands its
+    iterate back to the complex128 refinement, which still reaches rtol."""
+    w, o, p = sphere()
+    k = float(w.k[0])
+    b_dev = p.excitation("plane_wave", [0, 0, 1])
+    _, ref = p.solve(b_dev, rtol=1e-10, restart=30, max_iter=3000, inner="c128", pc="diag")
+    x_dev, res = p.solve(b_dev, rtol=1e-10, restart=30, max_iter=3000, inner="c64", pc="diag",
+                         inner_rtol=1e-12, max_refine=10)
+    print(f"    c128 iters={ref.iters[0]}; c64 iters={res.iters[0]} matvecs={res.matvecs[0]} "
+          f"refinements={res.refinements[0]}", flush=True)
+    assert res.converged.all()
+    assert true_resid(o, k, host(x_dev)[0], host(b_dev)[0]) <= 1.1e-10
+    # cycling at the floor would run each inner solve to its 3000 steps
+    assert res.iters[0] <= 6 * ref.iters[0] and res.matvecs[0] < 1000
+
+
 def test_batched_frequencies_and_patches():
     w = I.sweep_small(nfreq=4, rhs_per_freq=2)
     o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
