@@ -322,105 +322,135 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(
   }
 }
 
-// weight gradients on MFMA for bf16 X and dY with 16-multiple channels: per
-// tap, dW_t[co][ci] = sum_p dY[p][co] X[p + d(t)][ci] is a GEMM over
-// positions.  Steps of 64 positions are staged transposed in LDS
-// ([channel][position], bf16), so lane l reads its 8 consecutive positions
-// (k = 8 (l / 16) + i) of row co = l % 16 (A) and of column ci = l % 16 (B)
-// as one 16-byte word; the 16x16 output tiles (co tile, ci tile) are dealt
-// to the four waves.  Partial sums per chunk of positions, as above; only
-// input channels ci < CST are stored (the first layer runs on its two input
-// channels zero-padded to 16).  The blocks of the centre tap, whose staged
-// dY covers every position of the chunk once, also write the chunk's bias
-// gradient partials partb[chunk][co] = sum_p dY[p][co] (when partb is set).
+// Weight gradients of a 3x3x3 layer on MFMA for bf16 X and dY:
+//   dW[co][t][ci] = sum_p dY[p][co] X[p + d(t)][ci]
+// (p and p + d(t) in the same sample), a GEMM over positions per tap.  A
+// workgroup takes one 16-channel tile of the input (blockIdx.y) and a strided
+// set of bricks of 16 x 2 x 4 output positions, and does all 27 taps of every
+// brick, so each dY and X element is staged once per brick rather than once
+// per tap.  Per brick it stages dY transposed ([co][position], 128 positions)
+// and the input brick with its one-point halo as three x-shifted copies
+// ([shift][ci][halo row][x], copy s holding X at x + s - 1), so the operand
+// of every tap is one aligned 16-byte LDS read; channel strides carry 16
+// bytes of padding so the 16 lanes of a read hit distinct banks.  The K
+// steps are the brick's 4 z-planes (32 positions: x 0..15 of two rows); lane
+// l supplies A[co = l % 16][k = 8 (l / 16) + i] (dY) and B[k][ci = l % 16]
+// (X) and holds C[co = 4 (l / 16) + i][ci = l % 16].  Wave w does the taps
+// w, w + 4, ...  Partial sums per workgroup (part[chunk][co][t][ci], input
+// channels ci < CST only: the first layer runs on its two channels padded to
+// 16); the workgroups of the first tile also sum the bias gradient
+// partb[chunk][co] = sum_p dY[p][co] (when partb is set).
 template <int CIN, int COUT, int CST = CIN>
 __global__ __launch_bounds__(256) void wgrad_mfma_kernel(
     const uint16_t* __restrict__ X, int ldx, int ox, const uint16_t* __restrict__ dY, int ldy,
-    int oy, int D, int Ds, int H, int W, int64_t chunk, float* __restrict__ part,
+    int oy, int D, int Ds, int H, int W, int nbrick, float* __restrict__ part,
     float* __restrict__ partb) {
-  constexpr int KS = 64;                             // positions per step
-  constexpr int NTC = COUT / 16, NTI = CIN / 16, NT = NTC * NTI, NTW = (NT + 3) / 4;
-  constexpr int BR = 256 / COUT;                     // bias: threads per output channel
-  static_assert(CST <= CIN && COUT <= 256, "channel layout");
-  __shared__ __attribute__((aligned(16))) uint16_t syT[COUT * KS];  // 16-byte reads below
-  __shared__ __attribute__((aligned(16))) uint16_t sxT[CIN * KS];
+  constexpr int BX = 16, BY = 2, BZ = 4, BP = BX * BY * BZ;   // output brick
+  constexpr int RY = BY + 2, RZ = BZ + 2, ROWS = RY * RZ;     // halo rows (y, z)
+  constexpr int NTC = COUT / 16, TW = 7;                      // co tiles, taps per wave
+  constexpr int XS_CI = ROWS * BX + 8;                        // per channel, + 16 B pad
+  constexpr int XS_COPY = 16 * XS_CI;                         // one shifted copy
+  constexpr int DY_CO = BP + 8;                               // per output channel, + pad
+  constexpr int BR = 256 / COUT;                              // bias: threads per channel
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0 && CST <= CIN && COUT <= 256, "layout");
+  __shared__ __attribute__((aligned(16))) uint16_t xs[3 * XS_COPY];
+  __shared__ __attribute__((aligned(16))) uint16_t dyT[COUT * DY_CO];
   __shared__ float red[256];
-  const int tap = blockIdx.y;
-  const bool bias = partb != nullptr && tap == 13;   // uniform over the block
+  const int ti = blockIdx.y;
+  const bool bias = partb != nullptr && ti == 0;  // uniform over the block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  const int64_t P = int64_t(D) * H * W;
-  const int64_t pb = int64_t(blockIdx.x) * chunk, pe = min(P, pb + chunk);
-  const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-  f32x4 acc[NTW];
+  const int yk = kg >> 1, xk = 8 * (kg & 1);  // this lane's K positions in a step
+  const int nbx = (W + BX - 1) / BX, nby = (H + BY - 1) / BY;
+  const bf16x8 zero = as_bf16x8(make_uint4(0u, 0u, 0u, 0u));
+  f32x4 acc[TW][NTC];
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < TW; ++j)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[j][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
-  __shared__ int64_t src[KS];  // shifted source position of each staged position, or -1
-  for (int64_t s0 = pb; s0 < pe; s0 += KS) {
-    const int cnt = int(min(int64_t(KS), pe - s0));
-    if (tid < KS) {
-      int64_t v = -1;
-      if (tid < cnt) {
-        int x, y, z;
-        pos_xyz(s0 + tid, W, H, x, y, z);
-        const int nx = x + dx, ny = y + dy, nz = z + dz, zs = (z / Ds) * Ds;
-        if (nx >= 0 && ny >= 0 && nz >= zs && nx < W && ny < H && nz < zs + Ds)
-          v = (int64_t(nz) * H + ny) * W + nx;
-      }
-      src[tid] = v;
-    }
-    // dY and the shifted X, 8 channels (16 bytes) per load, transposed into LDS
-    for (int i = tid; i < KS * (COUT / 8); i += 256) {
-      const int pp = i / (COUT / 8), c8 = i % (COUT / 8);
+  for (int br = blockIdx.x; br < nbrick; br += gridDim.x) {
+    int b = br;
+    const int x0 = (b % nbx) * BX;
+    b /= nbx;
+    const int y0 = (b % nby) * BY, z0 = (b / nby) * BZ;
+    __syncthreads();  // the previous brick's operands have been read
+    // dY, 8 channels (16 bytes) per load, transposed; zero outside the grid
+    for (int u = tid; u < BP * (COUT / 8); u += 256) {
+      const int c8 = u % (COUT / 8), pp = u / (COUT / 8);
+      const int x = x0 + pp % BX, y = y0 + (pp / BX) % BY, z = z0 + pp / (BX * BY);
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (pp < cnt) v = *reinterpret_cast<const uint4*>(dY + (s0 + pp) * ldy + oy + 8 * c8);
+      if (x < W && y < H && z < D)
+        v = *reinterpret_cast<const uint4*>(dY + ((int64_t(z) * H + y) * W + x) * ldy + oy +
+                                            8 * c8);
       const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) syT[(8 * c8 + j) * KS + pp] = e[j];
+      for (int j = 0; j < 8; ++j) dyT[(8 * c8 + j) * DY_CO + pp] = e[j];
     }
-    __syncthreads();
-    for (int i = tid; i < KS * (CIN / 8); i += 256) {
-      const int pp = i / (CIN / 8), c8 = i % (CIN / 8);
+    // X, this tile's 16 channels (two 16-byte loads per position), brick plus
+    // halo, into the three shifted copies; zero outside the grid
+    for (int u = tid; u < ROWS * (BX + 2) * 2; u += 256) {
+      const int h = u & 1, q = u >> 1, xq = q % (BX + 2), row = q / (BX + 2);
+      const int gx = x0 + xq - 1, gy = y0 + row % RY - 1, gz = z0 + row / RY - 1;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      const int64_t q = src[pp];
-      if (q >= 0) v = *reinterpret_cast<const uint4*>(X + q * ldx + ox + 8 * c8);
+      if (gx >= 0 && gy >= 0 && gz >= 0 && gx < W && gy < H && gz < D)
+        v = *reinterpret_cast<const uint4*>(X + ((int64_t(gz) * H + gy) * W + gx) * ldx + ox +
+                                            16 * ti + 8 * h);
       const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sxT[(8 * c8 + j) * KS + pp] = e[j];
-    }
-    if (bias)  // staged positions past the chunk's end are zero
-      for (int pp = tid / COUT; pp < KS; pp += BR) bsum += bf2f(syT[(tid % COUT) * KS + pp]);
-    __syncthreads();
+      for (int sft = 0; sft < 3; ++sft) {
+        const int x = xq - sft;
+        if (x >= 0 && x < BX) {
 #pragma unroll
-    for (int j = 0; j < NTW; ++j) {
-      const int tt = wave + 4 * j;
-      if (tt < NT) {
-        const int tc = tt / NTI, ti = tt % NTI;
-#pragma unroll
-        for (int kc = 0; kc < KS / 32; ++kc) {
-          const int k = kc * 32 + 8 * kg;
-          const bf16x8 av = as_bf16x8(*reinterpret_cast<const uint4*>(&syT[(tc * 16 + col) * KS + k]));
-          const bf16x8 bv = as_bf16x8(*reinterpret_cast<const uint4*>(&sxT[(ti * 16 + col) * KS + k]));
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+          for (int j = 0; j < 8; ++j)
+            xs[sft * XS_COPY + (8 * h + j) * XS_CI + row * BX + x] = e[j];
         }
       }
     }
     __syncthreads();
-  }
+    if (bias)  // positions outside the grid were staged as zero
+      for (int pp = tid / COUT; pp < BP; pp += BR) bsum += bf2f(dyT[(tid % COUT) * DY_CO + pp]);
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) {
-    const int tt = wave + 4 * j;
-    if (tt < NT) {
-      const int tc = tt / NTI, ti = tt % NTI;
-      const int ci = ti * 16 + col;
-      if (ci < CST) {
+    for (int kc = 0; kc < BZ; ++kc) {
+      // the step's plane and whether its z - 1 / z + 1 neighbours lie in the
+      // same sample
+      const int z = z0 + kc, zs = (z / Ds) * Ds;
+      const bool lo_ok = z - 1 >= zs, hi_ok = z + 1 < zs + Ds;
+      bf16x8 av[NTC];
+#pragma unroll
+      for (int t = 0; t < NTC; ++t)
+        av[t] = as_bf16x8(*reinterpret_cast<const uint4*>(&dyT[(t * 16 + col) * DY_CO + kc * 32 +
+                                                              8 * kg]));
+#pragma unroll
+      for (int j = 0; j < TW; ++j) {
+        const int tap = wave + 4 * j;
+        if (tap < 27) {
+          const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+          const bool zok = dz == 1 || (dz == 0 ? lo_ok : hi_ok);
+          const int row = (kc + dz) * RY + yk + dy;
+          const bf16x8 bv =
+              zok ? as_bf16x8(*reinterpret_cast<const uint4*>(
+                        &xs[dx * XS_COPY + col * XS_CI + row * BX + xk]))
+                  : zero;
+#pragma unroll
+          for (int t = 0; t < NTC; ++t)
+            acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], bv, acc[j][t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  const int ci = 16 * ti + col;
+#pragma unroll
+  for (int j = 0; j < TW; ++j) {
+    const int tap = wave + 4 * j;
+    if (tap < 27 && ci < CST) {
+#pragma unroll
+      for (int t = 0; t < NTC; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int co = tc * 16 + 4 * kg + i;
-          part[(int64_t(blockIdx.x) * 27 * COUT + int64_t(co) * 27 + tap) * CST + ci] = acc[j][i];
+          const int co = t * 16 + 4 * kg + i;
+          part[((int64_t(blockIdx.x) * COUT + co) * 27 + tap) * CST + ci] = acc[j][t][i];
         }
-      }
     }
   }
   if (bias) {
@@ -875,15 +905,15 @@ struct aim_unet_s {
     acts.in16 = b16(P0 * 16);
     // two-stage gradient sums: weight partials (chunks x entries, bounded
     // by wg_chunks) and bias partials (chunks x output channels)
-    acts.part_n = std::max<int64_t>(int64_t(1) << 21, int64_t(kMaxChunks) * 64);
+    acts.part_n = std::max<int64_t>(int64_t(1) << 22, int64_t(kMaxChunks) * 64);
     acts.part = f32(acts.part_n);
     acts.partb_n = int64_t(kMaxChunks) * 64;
     acts.partb = f32(acts.partb_n);
   }
 
-  // Chunks of positions for the weight-gradient partial sums: enough blocks
-  // (chunks x taps) to fill the chip, at least four 64-position steps per
-  // chunk, and at most 2^21 partial sums (or 8 chunks) in flight.
+  // Chunks of positions for the partial sums of the 1x1 output layer's
+  // gradient: enough blocks to fill the chip, at least four 64-position
+  // steps per chunk, and at most 2^21 partial sums (or 8 chunks) in flight.
   static constexpr int64_t kMaxChunks = 1024;
   static int64_t wg_chunks(int64_t P, int64_t entries, int taps) {
     const int64_t steps = (P + 63) / 64;
@@ -944,11 +974,7 @@ struct aim_unet_s {
     AIM_REQUIRE(int64_t(cout) * cin <= 256 * 24 && cout <= 64, AIM_ERR_STATE,
                 "layer too wide for wgrad");
     const int64_t entries = int64_t(cout) * L.taps * cin;
-    int64_t nchunk = wg_chunks(P, entries, L.taps);
-    const int64_t chunk = ((P + 63) / 64 + nchunk - 1) / nchunk * 64;
-    nchunk = (P + chunk - 1) / chunk;
-    AIM_REQUIRE(nchunk * entries <= acts.part_n && nchunk * cout <= acts.partb_n, AIM_ERR_STATE,
-                "gradient partial buffer too small");
+    int64_t nchunk = 0;
     bool done = false;
     if constexpr (std::is_same_v<TY, uint16_t>) {
       if (L.taps == 27) {
@@ -966,11 +992,21 @@ struct aim_unet_s {
         } else {
           Xb = X;
         }
+        // bricks of 16 x 2 x 4 positions, dealt to nchunk workgroups per input
+        // tile: about 1,024 workgroups, at most 2^22 partial sums (or 16 chunks)
+        const int64_t nbrick = int64_t((W + 15) / 16) * ((H + 1) / 2) * ((D + 3) / 4);
+        const int nti = kcin / 16;
+        nchunk = std::min<int64_t>(nbrick, (1024 + nti - 1) / nti);
+        nchunk = std::max<int64_t>(1, std::min<int64_t>(
+                                          nchunk, std::max<int64_t>(16, acts.part_n / entries)));
+        AIM_REQUIRE(nchunk * entries <= acts.part_n && nchunk * cout <= acts.partb_n &&
+                        nbrick < (int64_t(1) << 31),
+                    AIM_ERR_STATE, "gradient partial buffer too small");
 #define AIM_WG(CI, CO, CS)                                                                      \
   if (!done && kcin == CI && cin == CS && cout == CO) {                                       \
-    hipLaunchKernelGGL((wgrad_mfma_kernel<CI, CO, CS>), dim3(unsigned(nchunk), 27), dim3(256), \
-                       0, s, Xb, ldx, ox, dY, ldy, oy, D, Ds, H, W, chunk, acts.part,          \
-                       acts.partb);                                                           \
+    hipLaunchKernelGGL((wgrad_mfma_kernel<CI, CO, CS>), dim3(unsigned(nchunk), CI / 16),       \
+                       dim3(256), 0, s, Xb, ldx, ox, dY, ldy, oy, D, Ds, H, W, int(nbrick),    \
+                       acts.part, acts.partb);                                                \
     done = true;                                                                              \
   }
         // the (input, output, stored input) channel triples of the 3x3x3 layers
@@ -987,6 +1023,11 @@ struct aim_unet_s {
     }
     if constexpr (std::is_same_v<TX, uint16_t>) {
       if (!done) {
+        nchunk = wg_chunks(P, entries, L.taps);
+        const int64_t chunk = ((P + 63) / 64 + nchunk - 1) / nchunk * 64;
+        nchunk = (P + chunk - 1) / chunk;
+        AIM_REQUIRE(nchunk * entries <= acts.part_n && nchunk * cout <= acts.partb_n,
+                    AIM_ERR_STATE, "gradient partial buffer too small");
         const size_t shm = size_t(kWgPos) * (cout + cin) * sizeof(float);
         hipLaunchKernelGGL((wgrad_partial_kernel<TX, TY>), dim3(unsigned(nchunk), L.taps),
                            dim3(256), shm, s, X, ldx, ox, cin, dY, ldy, oy, cout, D, Ds, H, W,
