@@ -464,14 +464,24 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(
   }
 }
 
-// grad[i] (+)= sum_c part[c][i]: a block takes 64 consecutive entries, its
-// four waves a quarter of the chunks each, eight loads in flight per thread
-__global__ __launch_bounds__(256) void reduce_chunks_kernel(const float* __restrict__ part,
-                                                            int nchunk, int64_t n,
-                                                            float* __restrict__ grad) {
+// grad[i] (+)= sum_c part[c][i] for the weights and gradb[i] (+)= sum_c
+// partb[c][i] for the biases of one layer, in one launch: a block takes 64
+// consecutive entries (the first nwb blocks the weights, the rest the
+// biases), its four waves a quarter of the chunks each, eight loads in
+// flight per thread
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(const float* __restrict__ partw,
+                                                            int nchunk, int64_t nw,
+                                                            float* __restrict__ gradw, int nwb,
+                                                            const float* __restrict__ partb,
+                                                            int64_t nbias,
+                                                            float* __restrict__ gradb) {
   __shared__ float red[4][64];
+  const bool wt = int(blockIdx.x) < nwb;
+  const float* part = wt ? partw : partb;
+  float* grad = wt ? gradw : gradb;
+  const int64_t n = wt ? nw : nbias;
   const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int64_t i = int64_t(blockIdx.x) * 64 + e;
+  const int64_t i = int64_t(wt ? blockIdx.x : blockIdx.x - nwb) * 64 + e;
   float s = 0.f;
   if (i < n)
     for (int c0 = q; c0 < nchunk; c0 += 32) {
@@ -555,6 +565,48 @@ __device__ __forceinline__ void load8(const float* p, float* f) {
 // fine position of child k (0..7) of coarse position (x, y, z)
 __device__ __forceinline__ int64_t child(int x, int y, int z, int k, int H, int W) {
   return (int64_t(2 * z + (k >> 2)) * H + 2 * y + ((k >> 1) & 1)) * W + 2 * x + (k & 1);
+}
+
+// gradient of the 1x1 output layer, first stage: per chunk of positions
+// part[chunk][co][ci] = sum_p dout[p][co] a[p][ci] and partb[chunk][co] =
+// sum_p dout[p][co] (2 outputs, C bf16 inputs), each position read once
+template <int C>
+__global__ __launch_bounds__(256) void outgrad_partial_kernel(const uint16_t* __restrict__ a,
+                                                              const float* __restrict__ dout,
+                                                              int64_t P, int64_t chunk,
+                                                              float* __restrict__ part,
+                                                              float* __restrict__ partb) {
+  constexpr int NE = 2 * C + 2;
+  __shared__ float red[NE][257];
+  float acc[NE];
+#pragma unroll
+  for (int j = 0; j < NE; ++j) acc[j] = 0.f;
+  const int64_t pb = int64_t(blockIdx.x) * chunk, pe = min(P, pb + chunk);
+  for (int64_t p = pb + threadIdx.x; p < pe; p += 256) {
+    const float2 d = *reinterpret_cast<const float2*>(dout + 2 * p);
+    float v[C];
+#pragma unroll
+    for (int c8 = 0; c8 < C / 8; ++c8)
+      unpack8(*reinterpret_cast<const uint4*>(a + p * C + 8 * c8), v + 8 * c8);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      acc[c] += d.x * v[c];
+      acc[C + c] += d.y * v[c];
+    }
+    acc[2 * C] += d.x;
+    acc[2 * C + 1] += d.y;
+  }
+#pragma unroll
+  for (int j = 0; j < NE; ++j) red[j][threadIdx.x] = acc[j];
+  __syncthreads();
+  if (threadIdx.x < NE) {
+    float t = 0.f;
+    for (int q = 0; q < 256; ++q) t += red[threadIdx.x][q];
+    if (threadIdx.x < 2 * C)
+      part[int64_t(blockIdx.x) * 2 * C + threadIdx.x] = t;
+    else
+      partb[int64_t(blockIdx.x) * 2 + threadIdx.x - 2 * C] = t;
+  }
 }
 
 // Y[q][c] = bf16(mean of X over the 8 children of coarse position q)
@@ -922,9 +974,11 @@ struct aim_unet_s {
     return std::max<int64_t>(1, std::min<int64_t>(n, kMaxChunks));
   }
 
-  void reduce(const float* part, int64_t nchunk, int64_t n, float* grad, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(unsigned((n + 63) / 64)), dim3(256), 0, s, part,
-                       int(nchunk), n, grad);
+  // weight and bias partials of one layer (nchunk chunks each) into g
+  void reduce(int64_t nchunk, int64_t nw, float* gw, int64_t nb, float* gb, hipStream_t s) {
+    const int nwb = int((nw + 63) / 64), nbb = int((nb + 63) / 64);
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(unsigned(nwb + nbb)), dim3(256), 0, s,
+                       acts.part, int(nchunk), nw, gw, nwb, acts.partb, nb, gb);
     AIM_HIP(hipGetLastError());
   }
 
@@ -1021,6 +1075,20 @@ struct aim_unet_s {
 #undef AIM_WG
       }
     }
+    if constexpr (std::is_same_v<TX, uint16_t> && std::is_same_v<TY, float>) {
+      if (!done && L.taps == 1 && cin == 16 && cout == 2 && ldx == 16 && ox == 0 && ldy == 2 &&
+          oy == 0) {
+        // the 1x1 output layer: one pass over the positions
+        nchunk = std::min<int64_t>(1024, (P + 1023) / 1024);
+        const int64_t chunk = (P + nchunk - 1) / nchunk;
+        nchunk = (P + chunk - 1) / chunk;
+        AIM_REQUIRE(nchunk * entries <= acts.part_n && nchunk * cout <= acts.partb_n,
+                    AIM_ERR_STATE, "gradient partial buffer too small");
+        hipLaunchKernelGGL((outgrad_partial_kernel<16>), dim3(unsigned(nchunk)), dim3(256), 0, s,
+                           X, dY, P, chunk, acts.part, acts.partb);
+        done = true;
+      }
+    }
     if constexpr (std::is_same_v<TX, uint16_t>) {
       if (!done) {
         nchunk = wg_chunks(P, entries, L.taps);
@@ -1041,8 +1109,7 @@ struct aim_unet_s {
     }
     AIM_REQUIRE(done, AIM_ERR_STATE, "unsupported weight-gradient layer");
     AIM_HIP(hipGetLastError());
-    reduce(acts.part, nchunk, entries, g + L.w_off, s);
-    reduce(acts.partb, nchunk, cout, g + L.b_off, s);
+    reduce(nchunk, entries, g + L.w_off, cout, g + L.b_off, s);
   }
 
   // forward pass on nb samples stacked along z: in = complex64 grids
