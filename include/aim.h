@@ -150,7 +150,14 @@ typedef struct {
   aim_pc_kind pc;            /* right preconditioner                               */
   double inner_rtol;         /* inner tolerance per refinement step (0: adaptive,
                                 0.3 rtol / current residual, kept within
-                                [3e-6, 0.1])                                      */
+                                [3e-6, 0.1]).  An inner solve also ends early
+                                at complex64's accuracy floor: after two
+                                restarts in a row at which either every system
+                                had stopped its cycle on its residual estimate
+                                yet its true residual is above the inner
+                                tolerance, or every unconverged true relative
+                                residual is below 1e-4 and fell by less than a
+                                tenth over the cycle                              */
   aim_pc_kind fallback_pc;   /* pc = AIM_PC_UNET only: preconditioner the solve
                                 continues with when the learned one is gated out
                                 (AIM_PC_NONE or AIM_PC_NEARBLOCK; 0 = none)        */
@@ -361,13 +368,17 @@ aim_status aim_unet_num_params(aim_unet net, int64_t* n);
 aim_status aim_unet_get_params(aim_unet net, float* params_host, float* grads_host);
 aim_status aim_unet_set_params(aim_unet net, const float* params_host);
 /* out = U(in) for nbatch grids (complex64 [nbatch][Nz][Ny][Nx] in and out,
- * device); dims = {Nx, Ny, Nz}; asynchronous */
+ * device); dims = {Nx, Ny, Nz}, each a multiple of 4; asynchronous.  The
+ * batch is one pass (the grids stacked along z, each sample's 3x3x3
+ * neighbourhoods ending at its own planes); each output equals the one its
+ * grid gets alone.  The network's activation buffers grow to the largest
+ * batch seen and are kept until aim_unet_destroy. */
 aim_status aim_unet_forward(aim_unet net, const void* in_dev, void* out_dev, int32_t nbatch,
                             const int32_t dims[3], void* hip_stream);
 /* One training step on grid pairs: gradients of the mean squared error
- * between U(in) and target over the batch (all on the device), then, if
- * apply != 0, one Adam step (beta 0.9/0.999, eps 1e-8) with rate lr.  The
- * loss value is returned in loss_host; blocking. */
+ * between U(in) and target over the batch (all on the device, one batched
+ * pass), then, if apply != 0, one Adam step (beta 0.9/0.999, eps 1e-8) with
+ * rate lr.  The loss value is returned in loss_host; blocking. */
 aim_status aim_unet_train_grid(aim_unet net, const void* in_dev, const void* target_dev,
                                int32_t nbatch, const int32_t dims[3], double lr, int32_t apply,
                                double* loss_host, void* hip_stream);
@@ -436,7 +447,8 @@ aim_status aim_pc_targets(aim_plan plan, aim_pc_kind base_pc, aim_pc_loss kind,
  * (and, for RESIDUAL, through A and its adjoint, complex64 products at
  * frequency index 0), the network's backward pass, then Adam with learning
  * rate lr if apply != 0.  *loss_host receives the loss before the step.
- * nsamples is limited by the plan's scratch (at least 128).  Blocking. */
+ * nsamples is limited by the plan's scratch (at least 128); the samples
+ * run in batched passes of up to the plan's max_rhs.  Blocking. */
 aim_status aim_pc_train_step(aim_plan plan, aim_unet net, aim_pc_loss kind,
                              const void* grids_dev, const void* targets_dev, int32_t npairs,
                              const int32_t* sample_idx_host, int32_t nsamples, double tau,
