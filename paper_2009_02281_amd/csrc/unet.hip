@@ -55,8 +55,11 @@ __device__ __forceinline__ void pos_xyz(int64_t p, int W, int H, int& x, int& y,
 // input tile (brick plus one-point halo, all CIN channels, bf16) in LDS once,
 // so every input element feeds 27 taps from LDS.  Wave w takes the brick's z
 // slice w: BY groups of 16 positions (its y rows) against TILES tiles of 16
-// output channels, so each weight load feeds BY MFMAs (BY = 2: taller
-// bricks measured slower, the larger tile costing occupancy).  K is the flattened (tap, channel) index, 27 * CIN,
+// output channels, so each weight load feeds BY MFMAs (BY = 4 for layers
+// with one output tile on grids that still give 1,024 workgroups: 6-7% less
+// forward time at 64^3 and 128x128x64; else 2, as taller bricks with more
+// tiles, or on small grids, cost occupancy or parallelism).  K is the
+// flattened (tap, channel) index, 27 * CIN,
 // walked in chunks of 32 on the 16x16x32 bf16 MFMA: lane l supplies
 // A[co = l % 16][k = 8 (l / 16) + i] (weights, 16 bytes from global memory)
 // and B[k][position l % 16] (16 bytes from LDS) and receives
@@ -65,7 +68,9 @@ __device__ __forceinline__ void pos_xyz(int64_t p, int W, int H, int& x, int& y,
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kBX = 16, kBZ = 4;                             // output brick (x, z)
 constexpr int kTX = kBX + 2, kTZ = kBZ + 2;                  // input tile (x, z)
-constexpr int conv_by(int) { return 2; }                       // output brick (y)
+// output brick height (y): 2 rows, or 4 (each weight fragment then feeds
+// four MFMAs) for layers with one 16-channel output tile on large grids
+constexpr int conv_by(int) { return 2; }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
   bf16x8 r;
@@ -988,21 +993,28 @@ struct aim_unet_s {
             hipStream_t s) {
     AIM_REQUIRE(ox % 8 == 0 && ldx % 8 == 0 && oy % 4 == 0 && cout % 16 == 0, AIM_ERR_STATE,
                 "channel blocks must be aligned");
-    const int by = conv_by(cin);
-    const unsigned nb = unsigned(((W + kBX - 1) / kBX) * ((H + by - 1) / by) *
-                                 ((D + kBZ - 1) / kBZ));
     const int tiles = cout / 16;
     const int rl = relu ? 1 : 0;
-#define AIM_CONV(CI, T)                                                                          \
-  if (cin == CI && tiles == T) {                                                                \
+    auto blocks = [&](int by) {
+      return unsigned(((W + kBX - 1) / kBX) * ((H + by - 1) / by) * ((D + kBZ - 1) / kBZ));
+    };
+    const bool tall = tiles == 1 && blocks(4) >= 1024;
+#define AIM_CONV_BY(CI, T, BY)                                                                  \
+  {                                                                                             \
+    const unsigned nb = blocks(BY);                                                             \
     if (out_bf16)                                                                               \
-      hipLaunchKernelGGL((conv3_lds_kernel<CI, T, true>), dim3(nb), dim3(256), 0, s, X, ldx, ox, \
-                         D, Ds, H, W, Wt, bias, Y, ldy, oy, rl);                                 \
-    else                                                                                        \
-      hipLaunchKernelGGL((conv3_lds_kernel<CI, T, false>), dim3(nb), dim3(256), 0, s, X, ldx,   \
+      hipLaunchKernelGGL((conv3_lds_kernel<CI, T, true, BY>), dim3(nb), dim3(256), 0, s, X, ldx, \
                          ox, D, Ds, H, W, Wt, bias, Y, ldy, oy, rl);                             \
+    else                                                                                        \
+      hipLaunchKernelGGL((conv3_lds_kernel<CI, T, false, BY>), dim3(nb), dim3(256), 0, s, X,    \
+                         ldx, ox, D, Ds, H, W, Wt, bias, Y, ldy, oy, rl);                        \
     AIM_HIP(hipGetLastError());                                                                 \
     return;                                                                                     \
+  }
+#define AIM_CONV(CI, T)                                                                          \
+  if (cin == CI && tiles == T) {                                                                \
+    if (T == 1 && tall) AIM_CONV_BY(CI, T, (T == 1 ? 4 : 2))                                    \
+    AIM_CONV_BY(CI, T, 2)                                                                       \
   }
     // the (input channels, output tiles) pairs of the network's forward and
     // data-gradient convolutions
@@ -1018,6 +1030,7 @@ struct aim_unet_s {
     AIM_CONV(64, 4)
     AIM_CONV(96, 2)
 #undef AIM_CONV
+#undef AIM_CONV_BY
     throw aim::Error(AIM_ERR_STATE, "unsupported channel count");
   }
 
