@@ -199,6 +199,63 @@ def solve_leg(plan, rtol: float, max_iter: int = 4000,
             "runs": res}
 
 
+def batch_leg(rtol: float) -> dict:
+    """One batched solve over 32 uneven geometries behind one plan
+    (aim_setup_batch) against the same 32 systems solved one after another
+    on their own plans: GMRES(RESTART) to rtol with the diagonal
+    preconditioner, complex64 matvecs inside complex128 refinement, a +z
+    plane wave per instance (each computed on its own plan)."""
+    import torch
+    from paper_2009_02281_amd import binding
+    from paper_2009_02281_amd import inputs as I
+    ws = I.uneven_batch()
+    t0 = time.perf_counter()
+    plans = [binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
+             for w in ws]
+    t_sep_setup = time.perf_counter() - t0
+    bs = [p.excitation("plane_wave", [0.0, 0.0, 1.0]) for p in plans]
+    t0 = time.perf_counter()
+    bp = binding.Plan.setup_batch(ws)
+    t_batch_setup = time.perf_counter() - t0
+    B = bp.pack([b[0] for b in bs])
+    opts = dict(rtol=rtol, restart=RESTART, max_iter=4000, pc="diag", inner="c64", max_refine=4,
+                raise_on_fail=False)
+    warm = dict(rtol=1e-2, restart=RESTART, max_iter=20, pc="diag", inner="c64",
+                raise_on_fail=False)
+    bp.solve(B, **warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r = bp.solve(B, **opts)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"[bench] batch of {len(ws)}: one batched solve {t_batch:.3f}s, iters "
+          f"{int(r.iters.min())}..{int(r.iters.max())}", file=sys.stderr, flush=True)
+    sep_s, sep_it, sep_ok = 0.0, [], True
+    for p, b in zip(plans, bs):
+        p.solve(b, **warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ri = p.solve(b, **opts)
+        torch.cuda.synchronize()
+        sep_s += time.perf_counter() - t0
+        sep_it.append(int(ri.iters[0]))
+        sep_ok = sep_ok and bool(ri.converged[0])
+    print(f"[bench] batch of {len(ws)}: one after another {sep_s:.3f}s", file=sys.stderr,
+          flush=True)
+    bp.close()
+    for p in plans:
+        p.close()
+    return {"instances": len(ws), "triangles_total": int(sum(w.n for w in ws)),
+            "triangles_range": [int(min(w.n for w in ws)), int(max(w.n for w in ws))],
+            "k_range": [float(min(w.k[0] for w in ws)), float(max(w.k[0] for w in ws))],
+            "grids": sorted({"x".join(map(str, w.dims)) for w in ws}),
+            "rtol": rtol, "restart": RESTART, "pc": "diag", "inner": "c64",
+            "batched": {"seconds": t_batch, "iters": r.iters.tolist(),
+                        "converged": bool(r.converged.all()), "setup_seconds": t_batch_setup},
+            "one_after_another": {"seconds": sep_s, "iters": sep_it, "converged": sep_ok,
+                                  "setup_seconds": t_sep_setup}}
+
+
 def learned_pc_leg(rtol: float) -> dict:
     """GMRES time to rtol on a held-out ellipsoid (4 plane waves, batched):
     complex128 GMRES without and with the near-block preconditioner against
@@ -347,6 +404,9 @@ def main() -> int:
     ap.add_argument("--solve-rtol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=4000,
                     help="GMRES iteration cap per solve (per refinement step in complex64)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time one batched solve over 32 uneven geometries against "
+                         "solving them one after another")
     ap.add_argument("--solve-pcs", default="none,diag,nearblock",
                     help="comma-separated preconditioners for the GMRES leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -491,6 +551,8 @@ def main() -> int:
         out["learned_pc"] = learned_pc_leg(args.solve_rtol)
     if not args.no_unet and args.workload != "sweep":
         out["unet"] = unet_leg()
+    if args.batch:
+        out["batch"] = batch_leg(args.solve_rtol)
 
     if not args.no_cpu:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)

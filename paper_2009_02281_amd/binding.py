@@ -206,51 +206,6 @@ class UNet:
         _check(lib.aim_unet_load(path.encode(), C.byref(h)))
         return cls(handle=h)
 
-    @classmethod
-    def setup_batch(cls, workloads, precisions=("c128", "c64"), stream=None):
-        """One plan over several geometries of uneven size (aim_setup_batch).
-        ``workloads`` are objects with vertices, triangles, order, dims, h,
-        near_threshold and k.  Vectors are [n][N_max] with zero padding; use
-        pack/unpack."""
-        import torch
-        lib = load_library()
-        n = len(workloads)
-        descs = (SetupDesc * n)()
-        keep = []
-        for i, w in enumerate(workloads):
-            d, kp = _make_desc(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold,
-                               w.k, precisions, 1)
-            descs[i] = d
-            keep.append(kp)
-        self = cls.__new__(cls)
-        self._lib = lib
-        self._plan = C.c_void_p()
-        self.host_only = False
-        self.precisions = tuple(precisions)
-        torch.cuda.init()
-        _check(lib.aim_setup_batch(descs, n, _stream_ptr(stream), C.byref(self._plan)))
-        self.k = None
-        self._finish()
-        cnt = C.c_int32(0)
-        sizes = (C.c_int64 * n)()
-        _check(lib.aim_batch_sizes(self._plan, C.byref(cnt), sizes))
-        self.batch_sizes = [int(v) for v in sizes]
-        return self
-
-    def pack(self, vectors, dtype=None):
-        """[n][N_max] device tensor from n vectors of the instances' sizes."""
-        import torch
-        dt = dtype or torch.complex128
-        out = torch.zeros((len(self.batch_sizes), self.n), dtype=dt, device="cuda")
-        for i, v in enumerate(vectors):
-            t = torch.as_tensor(v).to(dt).to("cuda")
-            out[i, :self.batch_sizes[i]] = t.reshape(-1)
-        return out
-
-    def unpack(self, t):
-        """List of the instances' vectors from a [n][N_max] tensor."""
-        return [t[i, :m] for i, m in enumerate(self.batch_sizes)]
-
     def save(self, path: str):
         _check(self._lib.aim_unet_save(self._h, path.encode()))
 

@@ -325,8 +325,11 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
   if (ev) AIM_HIP(hipEventRecord(ev[7], s));
 }
 
+// skip (batch plans only, may be null): systems whose product is not
+// needed (GMRES systems that have stopped); their rows of y are zeroed
 void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
-                const int32_t* dfreq, hipStream_t s, hipEvent_t* ev = nullptr) {
+                const int32_t* dfreq, hipStream_t s, hipEvent_t* ev = nullptr,
+                const char* skip = nullptr) {
   if (p->batch) {
     // system i through instance i; the padding of y_i stays zero
     AIM_REQUIRE(nrhs == int(p->inst.size()) && !ev, AIM_ERR_INVALID_ARG,
@@ -337,6 +340,10 @@ void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs
       aim_plan_s* q = p->inst[i].get();
       const char* xi = static_cast<const char*>(x) + size_t(i) * nmax * cb;
       char* yi = static_cast<char*>(y) + size_t(i) * nmax * cb;
+      if (skip && skip[i]) {
+        aim::launch_zero_words(yi, nmax * int64_t(cb / 8), s);
+        continue;
+      }
       matvec_any(q, prec, xi, yi, 1, dfreq + i, s);
       aim::launch_zero_words(yi + size_t(q->t.N) * cb, (nmax - q->t.N) * int64_t(cb / 8), s);
     }
@@ -1112,8 +1119,18 @@ void graph_matvec(aim_plan p, aim_precision prec, const void* in, void* out, int
 }
 
 void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, const int32_t* dfreq,
-             hipStream_t s) {
+             hipStream_t s, const char* skip = nullptr) {
   const int64_t cnt = p->t.N * int64_t(nrhs);
+  if (skip && p->batch) {  // direct launches, stopped instances skipped
+    if (prec == AIM_C128) {
+      matvec_any(p, AIM_C128, x, y, nrhs, dfreq, s, nullptr, skip);
+    } else {
+      aim::launch_cast_c128_to_c64(x, p->sv.c64a, cnt, s);
+      matvec_any(p, AIM_C64, p->sv.c64a, p->sv.c64b, nrhs, dfreq, s, nullptr, skip);
+      aim::launch_cast_c64_to_c128(p->sv.c64b, y, cnt, s);
+    }
+    return;
+  }
   if (prec == AIM_C128) {
     if (!solver_graphs_enabled()) {
       matvec_any(p, AIM_C128, x, y, nrhs, dfreq, s);
@@ -1249,7 +1266,12 @@ constexpr int kSyncEvery = 4;
 void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, void* x, int nrhs,
                  const int32_t* dfreq, const std::vector<double>& scale, double tol, int m,
                  int max_iter, bool x_is_zero, hipStream_t s, CycleStats& st,
-                 std::vector<double>& rel, const CycleHook* hook = nullptr, double gate = 0.0) {
+                 std::vector<double>& rel, const CycleHook* hook = nullptr, double gate = 0.0,
+                 const std::vector<double>* tols = nullptr) {
+  // per-system tolerances (tols, relative to scale) or one for all; on the
+  // device they are folded into the scales (estimate / (scale tol_r / tol)
+  // against tol)
+  auto tol_of = [&](int r) { return tols ? (*tols)[r] : tol; };
   std::vector<double> prev_rel;
   auto& w = p->sv;
   const int64_t n = p->t.N;
@@ -1261,19 +1283,20 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
   rel.assign(nrhs, 1.0);
   std::vector<double> beta(nrhs);
   bool first = true;
-  // complex64 inner solves stop at complex64's accuracy floor, which shows
-  // in two ways: a cycle whose systems all stopped on their residual
-  // estimates is followed by a true residual still above tol (the estimate
+  // complex64 inner solves stop each system at complex64's accuracy floor,
+  // which shows in two ways: the system stopped its last cycle on its
+  // residual estimate but its true residual is still above tol (the estimate
   // has run past what complex64 matvecs resolve, and further cycles are a
-  // few steps long), or every unconverged system has a true relative
-  // residual below kC64Floor that fell by less than a tenth over the last
-  // cycle (slow but genuine convergence, e.g. 1.3x per cycle on the
-  // 327,680-triangle sphere, is left alone).  After two such restarts in a
-  // row the solve returns its iterate to the refinement loop, which
-  // recomputes the residual in complex128, instead of cycling to max_iter.
+  // few steps long), or its true relative residual is below kC64Floor and
+  // fell by less than a tenth over the last cycle (slow but genuine
+  // convergence, e.g. 1.3x per cycle on the 327,680-triangle sphere, is left
+  // alone).  A system that shows either at two restarts in a row is parked
+  // (frozen for the rest of this solve); the solve returns when every system
+  // has converged, reached max_iter or been parked, and the refinement loop
+  // recomputes the residuals in complex128.
   constexpr double kC64Floor = 1e-4;
-  bool est_frozen = false;
-  int gap_cycles = 0;
+  std::vector<int> gaps(nrhs, 0);
+  std::vector<char> parked(nrhs, 0), est_stop(nrhs, 0), frozen0(nrhs, 0);
   for (;;) {
     // r = b - A x (skipped when x is known to be zero)
     if (first && x_is_zero) {
@@ -1285,28 +1308,28 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
     }
     first = false;
     norms_host(p, w.r, nrhs, s, beta);
-    bool all_done = true;
     int maxit_left = 0;
     for (int r = 0; r < nrhs; ++r) {
       rel[r] = beta[r] / scale[r];
       if (!std::isfinite(rel[r])) throw Error(AIM_ERR_BREAKDOWN, "non-finite residual");
-      if (rel[r] > tol && active_iters[r] < max_iter) all_done = false;
       maxit_left = std::max(maxit_left, max_iter - active_iters[r]);
     }
     if (gate > 0.0 && !prev_rel.empty())
       for (int r = 0; r < nrhs; ++r)
-        if (rel[r] > tol && rel[r] > gate * prev_rel[r]) throw GateFail{};
-    if (prec == AIM_C64 && !prev_rel.empty()) {
-      bool stalled = true;
+        if (rel[r] > tol_of(r) && rel[r] > gate * prev_rel[r]) throw GateFail{};
+    if (prec == AIM_C64 && !prev_rel.empty())
       for (int r = 0; r < nrhs; ++r)
-        if (rel[r] > tol && active_iters[r] < max_iter &&
-            !(rel[r] < kC64Floor && rel[r] > 0.9 * prev_rel[r]))
-          stalled = false;
-      gap_cycles = (stalled || est_frozen) ? gap_cycles + 1 : 0;
-    }
+        if (rel[r] > tol_of(r) && active_iters[r] < max_iter && !parked[r]) {
+          const bool stalled = rel[r] < kC64Floor && rel[r] > 0.9 * prev_rel[r];
+          gaps[r] = (stalled || est_stop[r]) ? gaps[r] + 1 : 0;
+          if (gaps[r] >= 2) parked[r] = 1;
+        }
+    bool all_done = true;
+    for (int r = 0; r < nrhs; ++r)
+      if (rel[r] > tol_of(r) && active_iters[r] < max_iter && !parked[r]) all_done = false;
     prev_rel = rel;
     if (hook) (*hook)(x, w.r, rel);
-    if (all_done || gap_cycles >= 2) return;
+    if (all_done) return;
     const int mm = std::min(m, maxit_left);
     // V_0 = r / beta
     aim::launch_scale_inv(w.r, w.nrm, w.V, n, nrhs, n, s);
@@ -1318,11 +1341,19 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
       for (int i = 0; i <= mc; ++i) w.g_host[size_t(r) * (mc + 1) + i] = make_double2(0.0, 0.0);
       w.g_host[size_t(r) * (mc + 1)] = make_double2(beta[r], 0.0);
       w.gst_host[r].len = 0;
-      w.gst_host[r].frozen = (rel[r] <= tol || active_iters[r] >= max_iter) ? 1 : 0;
+      w.gst_host[r].frozen =
+          (rel[r] <= tol_of(r) || active_iters[r] >= max_iter || parked[r]) ? 1 : 0;
+      frozen0[r] = w.gst_host[r].frozen;
       w.gst_host[r].iters = active_iters[r];
       w.gst_host[r].nonfinite = 0;
-      w.scale_host[r] = scale[r];
+      w.scale_host[r] = scale[r] * tol_of(r) / tol;
     }
+    // systems stopped at the cycle's start (and, from each look of the host
+    // on, those stopped since) need no matvec: on a batch plan their
+    // instances are skipped (zero product, which their frozen Givens state
+    // ignores)
+    std::vector<char> skip(nrhs);
+    for (int r = 0; r < nrhs; ++r) skip[r] = w.gst_host[r].frozen ? 1 : 0;
     AIM_HIP(hipMemcpyAsync(w.g, w.g_host, sizeof(double2) * nrhs * (mc + 1),
                            hipMemcpyHostToDevice, s));
     AIM_HIP(hipMemcpyAsync(w.gst, w.gst_host, sizeof(aim::GivensState) * nrhs,
@@ -1335,16 +1366,18 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
       // z_j = M(v_j); without a preconditioner the basis Z is V itself
       void* Zj = pc == AIM_PC_NONE ? Vj : static_cast<char*>(w.Z) + size_t(j) * nrhs * vec;
       if (pc != AIM_PC_NONE) apply_M(p, pc, Vj, Zj, nrhs, s);
-      apply_A(p, prec, Zj, w.d, nrhs, dfreq, s);  // w.d = A z_j
+      apply_A(p, prec, Zj, w.d, nrhs, dfreq, s, p->batch ? skip.data() : nullptr);  // w.d = A z_j
       st.matvecs++;
       // classical Gram-Schmidt, twice
-      aim::launch_block_dot(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h, s);
-      aim::launch_block_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.h, j + 1, s);
-      aim::launch_block_dot(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h2, s);
-      aim::launch_block_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.h2, j + 1, s);
-      aim::launch_norms(w.d, n, nrhs, w.partial, w.nrm, s);
+      // (systems frozen by the Givens step are skipped on the device; their
+      // columns past len are never used)
+      aim::launch_block_dot(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h, s, w.gst);
+      aim::launch_block_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.h, j + 1, s, w.gst);
+      aim::launch_block_dot(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h2, s, w.gst);
+      aim::launch_block_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.h2, j + 1, s, w.gst);
+      aim::launch_norms(w.d, n, nrhs, w.partial, w.nrm, s, w.gst);
       aim::launch_scale_inv(w.d, w.nrm, static_cast<char*>(w.V) + size_t(j + 1) * nrhs * vec, n,
-                            nrhs, n, s);
+                            nrhs, n, s, w.gst);
       aim::launch_givens_step(w.h, w.h2, w.nrm, nrhs, j, mc, w.H, w.cs, w.sn, w.g, w.gst, w.scale,
                               tol, max_iter, s);
       if ((j + 1) % kSyncEvery == 0 || j + 1 == mm) {
@@ -1355,6 +1388,7 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
         for (int r = 0; r < nrhs; ++r) {
           if (w.gst_host[r].nonfinite) throw Error(AIM_ERR_BREAKDOWN, "non-finite Arnoldi norm");
           if (!w.gst_host[r].frozen) all_frozen = false;
+          skip[r] = w.gst_host[r].frozen ? 1 : 0;
         }
         if (all_frozen) {
           ++j;
@@ -1371,12 +1405,12 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
                            hipMemcpyDeviceToHost, s));
     AIM_HIP(hipStreamSynchronize(s));
     std::vector<int> len(nrhs, 0);
-    est_frozen = true;
     for (int r = 0; r < nrhs; ++r) {
       if (w.gst_host[r].nonfinite) throw Error(AIM_ERR_BREAKDOWN, "non-finite Arnoldi norm");
       len[r] = w.gst_host[r].len;
       active_iters[r] = w.gst_host[r].iters;
-      if (!w.gst_host[r].frozen) est_frozen = false;
+      // stopped during this cycle on its residual estimate
+      est_stop[r] = (w.gst_host[r].frozen && !frozen0[r] && active_iters[r] < max_iter) ? 1 : 0;
     }
     // y = H^{-1} g per system (H upper triangular after the rotations), then
     // x += Z y
@@ -1483,21 +1517,26 @@ extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs
             if (rel[r] > o.rtol) done = false;
           }
           if (done || refine >= std::max(0, o.max_refine)) break;
+          // systems already at rtol get a zero inner right-hand side, so the
+          // inner solve stops them at once (and a batch plan skips them)
+          for (int r = 0; r < nrhs; ++r)
+            if (rel[r] <= o.rtol)
+              aim::launch_zero_words(static_cast<char*>(w.bp) + size_t(r) * vec, int64_t(n) * 2, s);
           std::vector<double> iscale(nrhs);
           for (int r = 0; r < nrhs; ++r) iscale[r] = rn[r] > 0.0 ? rn[r] : 1.0;
           AIM_HIP(hipMemsetAsync(w.xp, 0, vec * nrhs, s));
-          // inner tolerance: enough to reach rtol from here, but not below what
-          // complex64 matvecs can resolve (unless the caller fixed it)
-          double itol = inner_tol;
-          if (o.inner_rtol <= 0.0) {
-            double worst = 0.0;
-            for (int r = 0; r < nrhs; ++r) worst = std::max(worst, rel[r]);
-            itol = std::max(3e-6, std::min(0.1, 0.3 * o.rtol / std::max(worst, 1e-300)));
-          }
+          // inner tolerance per system: enough to reach rtol from its residual,
+          // but not below what complex64 matvecs can resolve (unless the
+          // caller fixed it)
+          std::vector<double> itols(nrhs, inner_tol);
+          if (o.inner_rtol <= 0.0)
+            for (int r = 0; r < nrhs; ++r)
+              itols[r] = std::max(3e-6, std::min(0.1, 0.3 * o.rtol / std::max(rel[r], 1e-300)));
+          const double itol = *std::min_element(itols.begin(), itols.end());
           std::vector<double> irel;
           CycleStats ist;
           gmres_batch(p, AIM_C64, use_pc, w.bp, w.xp, nrhs, df, iscale, itol, o.restart,
-                      o.max_iter, true, s, ist, irel, nullptr, use_gate);
+                      o.max_iter, true, s, ist, irel, nullptr, use_gate, &itols);
           cst.matvecs += ist.matvecs;
           for (int r = 0; r < nrhs; ++r) inf[r].iters += ist.iters[r];
           aim::launch_axpy_inplace(x, w.xp, n * int64_t(nrhs), s);

@@ -158,20 +158,6 @@ void launch_excitation(int kind, const double* qp_xyz, const double* qp_w, int64
                        const double* params, int n_params, const double* kvals,
                        const int32_t* rhs_freq, int nrhs, void* b, hipStream_t s);
 
-// Krylov helpers on complex128 [nrhs][n] vectors; vector i of system r in a
-// basis block starts at base + (i * si + r * sr) * n.
-void launch_cast_c128_to_c64(const void* in, void* out, int64_t count, hipStream_t s);
-void launch_cast_c64_to_c128(const void* in, void* out, int64_t count, hipStream_t s);
-// out[r][i] = sum_n conj(V_i,r[n]) w[r][n] for i < nv (two-stage, deterministic)
-void launch_block_dot(const void* V, int64_t si, int64_t sr, const void* w, int64_t n, int nv,
-                      int nrhs, void* partial, void* out, hipStream_t s);
-// w[r] -= sum_i h[r][i] V_i,r
-void launch_block_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv,
-                         int nrhs, const void* h, int64_t ldh, hipStream_t s);
-void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out, hipStream_t s);
-// out[r] = w[r] * (1 / nrm[r]) (0 if nrm == 0)
-void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
-                      int64_t out_stride, hipStream_t s);
 // GMRES state of one system in a restart cycle (device, givens_step)
 struct GivensState {
   int len;        // columns of H in use this cycle
@@ -179,6 +165,25 @@ struct GivensState {
   int iters;      // Krylov steps over the whole solve
   int nonfinite;  // 1: a non-finite basis norm was met
 };
+// Krylov helpers on complex128 [nrhs][n] vectors; vector i of system r in a
+// basis block starts at base + (i * si + r * sr) * n.  With gst (device, may
+// be null) the helpers skip the systems whose state is frozen: the dots and
+// norms of those are 0, their vectors are left as they are.
+void launch_cast_c128_to_c64(const void* in, void* out, int64_t count, hipStream_t s);
+void launch_cast_c64_to_c128(const void* in, void* out, int64_t count, hipStream_t s);
+// out[r][i] = sum_n conj(V_i,r[n]) w[r][n] for i < nv (two-stage, deterministic)
+void launch_block_dot(const void* V, int64_t si, int64_t sr, const void* w, int64_t n, int nv,
+                      int nrhs, void* partial, void* out, hipStream_t s,
+                      const GivensState* gst = nullptr);
+// w[r] -= sum_i h[r][i] V_i,r
+void launch_block_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv,
+                         int nrhs, const void* h, int64_t ldh, hipStream_t s,
+                         const GivensState* gst = nullptr);
+void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out, hipStream_t s,
+                  const GivensState* gst = nullptr);
+// out[r] = w[r] * (1 / nrm[r]) (0 if nrm == 0)
+void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
+                      int64_t out_stride, hipStream_t s, const GivensState* gst = nullptr);
 // One Arnoldi step's Hessenberg column, Givens rotation and residual estimate
 // for every system (see givens_step_kernel)
 void launch_givens_step(const void* h, const void* h2, const double* nrm, int nrhs, int j,

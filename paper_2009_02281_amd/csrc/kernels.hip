@@ -1358,9 +1358,14 @@ __device__ __forceinline__ double2 block_sum2(double2 v, double2* sh) {
 __global__ __launch_bounds__(256) void block_dot_kernel(const double2* __restrict__ V, int64_t si,
                                                         int64_t sr, const double2* __restrict__ w,
                                                         int64_t n, int nv, int nchunk,
-                                                        double2* partial) {
+                                                        double2* partial,
+                                                        const GivensState* __restrict__ gst) {
   __shared__ double2 sh[256];
   const int c = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
+  if (gst && gst[r].frozen) {  // uniform over the block
+    if (threadIdx.x == 0) partial[(int64_t(r) * nv + i) * nchunk + c] = make_double2(0.0, 0.0);
+    return;
+  }
   const double2* vi = V + (int64_t(i) * si + int64_t(r) * sr) * n;
   const double2* wr = w + int64_t(r) * n;
   double2 acc;
@@ -1391,11 +1396,11 @@ __global__ void reduce_partials_kernel(const double2* partial, int nchunk, int t
 }
 
 void launch_block_dot(const void* V, int64_t si, int64_t sr, const void* w, int64_t n, int nv,
-                      int nrhs, void* partial, void* out, hipStream_t s) {
+                      int nrhs, void* partial, void* out, hipStream_t s, const GivensState* gst) {
   const int nchunk = int((n + kDotChunk - 1) / kDotChunk);
   hipLaunchKernelGGL(block_dot_kernel, dim3(nchunk, nv, nrhs), dim3(256), 0, s,
                      static_cast<const double2*>(V), si, sr, static_cast<const double2*>(w), n, nv,
-                     nchunk, static_cast<double2*>(partial));
+                     nchunk, static_cast<double2*>(partial), gst);
   AIM_HIP(hipGetLastError());
   const int total = nv * nrhs;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((total + 127) / 128), dim3(128), 0, s,
@@ -1413,10 +1418,11 @@ __global__ __launch_bounds__(128) void basis_axpy_kernel(const double2* __restri
                                                          int64_t si, int64_t sr,
                                                          double2* __restrict__ w, int64_t n,
                                                          int nv, const double2* __restrict__ h,
-                                                         int64_t ldh) {
+                                                         int64_t ldh,
+                                                         const GivensState* __restrict__ gst) {
   const int r = blockIdx.y;
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= n || (gst && gst[r].frozen)) return;
   const double2* hr = h + int64_t(r) * ldh;
   const double2* vr = V + int64_t(r) * sr * n + k;
   const int64_t vs = si * n;
@@ -1444,18 +1450,24 @@ __global__ __launch_bounds__(128) void basis_axpy_kernel(const double2* __restri
 }
 
 void launch_block_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv,
-                         int nrhs, const void* h, int64_t ldh, hipStream_t s) {
+                         int nrhs, const void* h, int64_t ldh, hipStream_t s,
+                         const GivensState* gst) {
   hipLaunchKernelGGL(basis_axpy_kernel<true>, dim3(unsigned((n + 127) / 128), nrhs), dim3(128), 0,
                      s, static_cast<const double2*>(V), si, sr, static_cast<double2*>(w), n, nv,
-                     static_cast<const double2*>(h), ldh);
+                     static_cast<const double2*>(h), ldh, gst);
   AIM_HIP(hipGetLastError());
 }
 
 __global__ __launch_bounds__(256) void norm_partial_kernel(const double2* __restrict__ w,
                                                            int64_t n, int nchunk,
-                                                           double2* partial) {
+                                                           double2* partial,
+                                                           const GivensState* __restrict__ gst) {
   __shared__ double2 sh[256];
   const int c = blockIdx.x, r = blockIdx.y;
+  if (gst && gst[r].frozen) {  // uniform over the block
+    if (threadIdx.x == 0) partial[int64_t(r) * nchunk + c] = make_double2(0.0, 0.0);
+    return;
+  }
   const double2* wr = w + int64_t(r) * n;
   double2 acc;
   acc.x = 0.0;
@@ -1474,10 +1486,11 @@ __global__ void norm_finish_kernel(const double2* partial, int nchunk, int nrhs,
   out[r] = sqrt(s);
 }
 
-void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out, hipStream_t s) {
+void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out, hipStream_t s,
+                  const GivensState* gst) {
   const int nchunk = int((n + kDotChunk - 1) / kDotChunk);
   hipLaunchKernelGGL(norm_partial_kernel, dim3(nchunk, nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(w), n, nchunk, static_cast<double2*>(partial));
+                     static_cast<const double2*>(w), n, nchunk, static_cast<double2*>(partial), gst);
   AIM_HIP(hipGetLastError());
   hipLaunchKernelGGL(norm_finish_kernel, dim3((nrhs + 127) / 128), dim3(128), 0, s,
                      static_cast<const double2*>(partial), nchunk, nrhs, out);
@@ -1485,8 +1498,9 @@ void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out
 }
 
 __global__ void scale_inv_kernel(const double2* w, const double* nrm, double2* out, int64_t n,
-                                 int64_t out_stride) {
+                                 int64_t out_stride, const GivensState* __restrict__ gst) {
   const int r = blockIdx.y;
+  if (gst && gst[r].frozen) return;
   const double nv = nrm[r];
   const double sc = nv > 0.0 ? 1.0 / nv : 0.0;
   for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
@@ -1499,10 +1513,10 @@ __global__ void scale_inv_kernel(const double2* w, const double* nrm, double2* o
 }
 
 void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
-                      int64_t out_stride, hipStream_t s) {
+                      int64_t out_stride, hipStream_t s, const GivensState* gst) {
   hipLaunchKernelGGL(scale_inv_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, s,
                      static_cast<const double2*>(w), nrm, static_cast<double2*>(out), n,
-                     out_stride);
+                     out_stride, gst);
   AIM_HIP(hipGetLastError());
 }
 
@@ -1623,7 +1637,7 @@ void launch_combine(const void* Z, int64_t si, int64_t sr, const void* y, int64_
                     void* x, int64_t n, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(basis_axpy_kernel<false>, dim3(unsigned((n + 127) / 128), nrhs), dim3(128),
                      0, s, static_cast<const double2*>(Z), si, sr, static_cast<double2*>(x), n, nv,
-                     static_cast<const double2*>(y), ldy);
+                     static_cast<const double2*>(y), ldy, nullptr);
   AIM_HIP(hipGetLastError());
 }
 

@@ -292,3 +292,56 @@ def learned_pc_geometries(count: int, seed: int = 5004, level: int = 3,
         out.append(Workload(f"ellipsoid-{seed}-{i}", V, T, 2, (16, 16, 16), 0.1, 2.0,
                             np.array([k]), seed, extra={"radii": radii}))
     return out
+
+
+def _pow2_at_least(v: float, lo: int = 32, hi: int = 128) -> int:
+    p = lo
+    while p < v and p < hi:
+        p *= 2
+    return p
+
+
+def uneven_batch(count: int = 32, seed: int = 5003, n_range=(5000, 120000)) -> list:
+    """Uneven geometries for one batched solve.  Each instance draws a kind
+    (icosphere of level 4-6, a box, or a 2x2 to 4x4 box array), a wavenumber
+    k ~ U[2 pi, 6 pi] and is meshed at about a tenth of its wavelength,
+    keeping 5k-120k triangles (draws outside the range are redrawn).  Grids
+    are a power of two per axis (32-128 points, so 64-256 padded) with the
+    spacing the library would derive for them, 2nd-order stencils and a 2h
+    near threshold."""
+    rng = np.random.default_rng(seed)
+    # mean edge of a unit-radius icosphere per level
+    unit_edge = {}
+    out = []
+    while len(out) < count:
+        kind = int(rng.integers(3))
+        k = float(rng.uniform(2 * math.pi, 6 * math.pi))
+        lam = 2 * math.pi / k
+        edge = lam / 10
+        if kind == 0:
+            level = int(rng.integers(4, 7))
+            if level not in unit_edge:
+                V1, T1 = icosphere(level, 1.0)
+                e = np.linalg.norm(V1[T1[:, 1]] - V1[T1[:, 0]], axis=1)
+                unit_edge[level] = float(e.mean())
+            V, T = icosphere(level, edge / unit_edge[level])
+            name = f"sphere-L{level}"
+        elif kind == 1:
+            size = rng.uniform(2.0, 8.0, size=3) * lam
+            V, T = box_surface(np.zeros(3), size, edge)
+            name = "box"
+        else:
+            nx, ny = (int(v) for v in rng.integers(2, 5, size=2))
+            a, c = rng.uniform(1.0, 2.0) * lam, rng.uniform(2.0, 4.0) * lam
+            V, T = box_array(nx, ny, size=(a, a, c), gap=0.5 * lam, jitter=0.05 * lam,
+                             edge=edge, seed=int(rng.integers(1 << 30)))
+            name = f"boxarray-{nx}x{ny}"
+        if not (n_range[0] <= T.shape[0] <= n_range[1]):
+            continue
+        ext = V.max(axis=0) - V.min(axis=0)
+        dims = tuple(_pow2_at_least(ext[a] / edge + 6) for a in range(3))
+        h = derived_spacing(V, dims)
+        i = len(out)
+        out.append(Workload(f"{name}-{T.shape[0]}", V, T, 2, dims, h, 2.0, np.array([k]),
+                            seed * 100 + i, extra={"kind": name, "edge": edge}))
+    return out
