@@ -177,6 +177,8 @@ def test_uneven_batch_of_geometries():
             assert not np.any(yi[w.n:]), (prec, i)
     bs = [excitation.plane_wave(o.V, o.T, float(w.k[0])) for w, o in zip(ws, oracles)]
     B = bp.pack(bs)
+    solo = [binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
+            for w in ws]
     for inner in ("c128", "c64"):
         X, res = bp.solve(B, rtol=1e-8, restart=40, pc="nearblock", inner=inner)
         print(f"    batch solve ({inner}): iters {res.iters.tolist()} {res.seconds * 1e3:.1f} ms",
@@ -187,6 +189,13 @@ def test_uneven_batch_of_geometries():
             assert not np.any(Xh[i, w.n:])
             tr = true_resid(o, float(w.k[0]), Xh[i, :w.n], bs[i])
             assert tr <= 2e-8, (inner, i, tr)
+            # each system takes the steps it takes alone: stopped systems are
+            # skipped, and tolerances and refinement targets are per system
+            _, ri = solo[i].solve(torch.from_numpy(bs[i][None]).cuda(), rtol=1e-8, restart=40,
+                                  pc="nearblock", inner=inner)
+            assert int(ri.iters[0]) == int(res.iters[i]), (inner, i, ri.iters[0], res.iters[i])
+    for q in solo:
+        q.close()
     bp.close()
 
 
