@@ -446,8 +446,10 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <typename T, int L, bool COL, int V>
 struct Shape {
   static constexpr int kTL = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
-  // V 0-3: 8 elements per thread (radix-8 stages); V 4-5: 16 (radix 16);
-  // V 6: 32 (radix 32: one exchange for L = 512 = 32 x 16)
+  // V 0-3: 8 elements per thread (radix-8 stages); V 4-5 and 7: 16 (radix 16;
+  // V 7 with 512 threads, e.g. 16 lines of complex64 at L = 512, i.e.
+  // 128-byte column rows); V 6: 32 (radix 32: one exchange for L = 512 =
+  // 32 x 16)
   static constexpr int NT = V == 6 ? cmax(1, L / 32)
                           : V >= 4 ? cmax(1, L / 16)
                           : COL ? (V == 0 ? cmin(L / 8, 256 / kTL)
@@ -459,7 +461,7 @@ struct Shape {
                                   : V == 2 ? cmin(L / 8, 32)
                                            : cmin(L / 8, 64));
   static constexpr int TL = V == 6 ? cmax(1, 256 / NT)
-                          : V >= 4 ? cmax(1, (V == 4 ? 256 : 128) / NT)
+                          : V >= 4 ? cmax(1, (V == 4 ? 256 : V == 5 ? 128 : 512) / NT)
                           : COL ? (V == 0 ? 256 / cmin(L / 8, 256 / kTL)
                                   : V == 1 ? 512 / cmin(L / 8, 512 / kTL)
                                   : V == 2 ? 256 / cmin(L / 8, 256 / (2 * kTL))
@@ -517,6 +519,8 @@ void pass_L(bool col, int mode, int variant, const void* in, void* out, const vo
     case 11: launch_shape<T, L, true, 5>(mode, i, o, w, a, nrhs, s); break;
     case 12: launch_shape<T, L, false, 6>(mode, i, o, w, a, nrhs, s); break;
     case 13: launch_shape<T, L, true, 6>(mode, i, o, w, a, nrhs, s); break;
+    case 14: launch_shape<T, L, false, 7>(mode, i, o, w, a, nrhs, s); break;
+    case 15: launch_shape<T, L, true, 7>(mode, i, o, w, a, nrhs, s); break;
     default: throw Error(AIM_ERR_INVALID_ARG, "FFT launch shape out of range");
   }
 }
@@ -553,6 +557,8 @@ bool shape_ok_L(bool col, int v) {
     case 11: return Shape<T, L, true, 5>::OK;
     case 12: return Shape<T, L, false, 6>::OK;
     case 13: return Shape<T, L, true, 6>::OK;
+    case 14: return Shape<T, L, false, 7>::OK;
+    case 15: return Shape<T, L, true, 7>::OK;
     default: return false;
   }
 }
