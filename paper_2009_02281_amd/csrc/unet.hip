@@ -84,9 +84,12 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restri
                                                         const uint16_t* __restrict__ Wt,
                                                         const float* __restrict__ bias, void* Y,
                                                         int ldy, int oy, int relu) {
-  constexpr int C8 = CIN / 8;
+  // the input channels are staged in CS parts of CH channels (two for 64 and
+  // more, so the tile takes 28-41 KB of LDS instead of 55-83 KB and more
+  // workgroups fit on a CU); the K walk covers one part after the other
+  constexpr int CS = CIN >= 64 ? 2 : 1, CH = CIN / CS, C8 = CH / 8;
   constexpr int kTY = kBY + 2, kTilePos = kTX * kTY * kTZ;
-  static_assert(CIN % 8 == 0, "channels in groups of 8");
+  static_assert(CH % 8 == 0, "channels in groups of 8");
   __shared__ uint4 tile[kTilePos * C8];  // [position][channel / 8], 8 bf16 per entry
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nbx = (W + kBX - 1) / kBX, nby = (H + kBY - 1) / kBY;
@@ -95,32 +98,8 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restri
   b /= nbx;
   const int by = b % nby, bz = b / nby;
   const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
-  // stage the tile in batches of 8 loads per thread, all in flight together
-  constexpr int kTileWords = kTilePos * C8, kBatch = 8 * 256;
-  for (int u0 = 0; u0 < kTileWords; u0 += kBatch) {
-    uint4 v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int u = u0 + j * 256 + tid;
-      v[j] = make_uint4(0u, 0u, 0u, 0u);
-      if (u < kTileWords) {
-        const int c8 = u % C8, pos = u / C8;
-        const int gx = x0 + pos % kTX - 1, gy = y0 + (pos / kTX) % kTY - 1,
-                  gz = z0 + pos / (kTX * kTY) - 1;
-        if (gx >= 0 && gy >= 0 && gz >= 0 && gx < W && gy < H && gz < D)
-          v[j] = *reinterpret_cast<const uint4*>(X + ((int64_t(gz) * H + gy) * W + gx) * ldx + ox +
-                                                 8 * c8);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int u = u0 + j * 256 + tid;
-      if (u < kTileWords) tile[u] = v[j];
-    }
-  }
-  __syncthreads();
   const int col = lane & 15, kg = lane >> 4;
-  constexpr int K = 27 * CIN, NCH = (K + 31) / 32;
+  constexpr int K = 27 * CIN, KH = 27 * CH, NCH = (KH + 31) / 32;
   // the wave's output plane and whether its z - 1 / z + 1 neighbours lie in
   // the same sample (a brick may straddle two samples)
   const int zo = z0 + wave, zs = (zo / Ds) * Ds;
@@ -136,41 +115,72 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const uint16_t* __restri
   // the few workgroups would otherwise wait out a load latency per step)
   // (depth 4, or 2 where the extra registers would cost occupancy that the
   // LDS tile leaves)
-  constexpr int PF = (TILES <= 2 || (CIN >= 64 && TILES <= 4)) ? 4 : 2;
-  auto wload = [&](int k, bf16x8* w) {
+  constexpr int PF = CS > 1 ? 2 : TILES <= 2 ? 4 : 2;
+#pragma unroll 1
+  for (int part = 0; part < CS; ++part) {
+    if (part > 0) __syncthreads();  // the previous part's tile has been read
+    // stage the tile in batches of 8 loads per thread, all in flight together
+    constexpr int kTileWords = kTilePos * C8, kBatch = 8 * 256;
+    for (int u0 = 0; u0 < kTileWords; u0 += kBatch) {
+      uint4 v[8];
 #pragma unroll
-    for (int t = 0; t < TILES; ++t)
-      w[t] = k < K ? as_bf16x8(*reinterpret_cast<const uint4*>(Wt + int64_t(t * 16 + col) * K + k))
-                   : zero;
-  };
-  bf16x8 wq[PF][TILES];
-#pragma unroll
-  for (int j = 0; j < PF; ++j) wload(32 * j + 8 * kg, wq[j]);
-  for (int c0 = 0; c0 < NCH; c0 += PF) {
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-      const int ch = c0 + j;
-      if (ch < NCH) {
-        const int k = ch * 32 + 8 * kg;
-        const bool kv = k < K;
-        bf16x8 wc[TILES];
-#pragma unroll
-        for (int t = 0; t < TILES; ++t) wc[t] = wq[j][t];
-        if (ch + PF < NCH) wload(k + 32 * PF, wq[j]);
-        const int tap = kv ? k / CIN : 0, ci = kv ? k % CIN : 0;
-        const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
-        const bool bok = kv && (dz == 1 || (dz == 0 ? lo_ok : hi_ok));
-        bf16x8 bv[kBY];
-#pragma unroll
-        for (int g = 0; g < kBY; ++g) {
-          const int pos = ((wave + dz) * kTY + g + dy) * kTX + col + dx;
-          bv[g] = bok ? as_bf16x8(tile[pos * C8 + ci / 8]) : zero;
+      for (int j = 0; j < 8; ++j) {
+        const int u = u0 + j * 256 + tid;
+        v[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (u < kTileWords) {
+          const int c8 = u % C8, pos = u / C8;
+          const int gx = x0 + pos % kTX - 1, gy = y0 + (pos / kTX) % kTY - 1,
+                    gz = z0 + pos / (kTX * kTY) - 1;
+          if (gx >= 0 && gy >= 0 && gz >= 0 && gx < W && gy < H && gz < D)
+            v[j] = *reinterpret_cast<const uint4*>(X + ((int64_t(gz) * H + gy) * W + gx) * ldx +
+                                                   ox + part * CH + 8 * c8);
         }
+      }
 #pragma unroll
-        for (int t = 0; t < TILES; ++t)
+      for (int j = 0; j < 8; ++j) {
+        const int u = u0 + j * 256 + tid;
+        if (u < kTileWords) tile[u] = v[j];
+      }
+    }
+    __syncthreads();
+    // K step index kp within the part: tap kp / CH, channel part * CH + kp % CH
+    auto wload = [&](int kp, bf16x8* w) {
+      const int tp = kp / CH, k = tp * CIN + part * CH + (kp - tp * CH);
 #pragma unroll
-          for (int g = 0; g < kBY; ++g)
-            acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc[t], bv[g], acc[g][t], 0, 0, 0);
+      for (int t = 0; t < TILES; ++t)
+        w[t] = kp < KH
+                   ? as_bf16x8(*reinterpret_cast<const uint4*>(Wt + int64_t(t * 16 + col) * K + k))
+                   : zero;
+    };
+    bf16x8 wq[PF][TILES];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) wload(32 * j + 8 * kg, wq[j]);
+    for (int c0 = 0; c0 < NCH; c0 += PF) {
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        const int ch = c0 + j;
+        if (ch < NCH) {
+          const int kp = ch * 32 + 8 * kg;
+          const bool kv = kp < KH;
+          bf16x8 wc[TILES];
+#pragma unroll
+          for (int t = 0; t < TILES; ++t) wc[t] = wq[j][t];
+          if (ch + PF < NCH) wload(kp + 32 * PF, wq[j]);
+          const int tap = kv ? kp / CH : 0, ci = kv ? kp % CH : 0;
+          const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+          const bool bok = kv && (dz == 1 || (dz == 0 ? lo_ok : hi_ok));
+          bf16x8 bv[kBY];
+#pragma unroll
+          for (int g = 0; g < kBY; ++g) {
+            const int pos = ((wave + dz) * kTY + g + dy) * kTX + col + dx;
+            bv[g] = bok ? as_bf16x8(tile[pos * C8 + ci / 8]) : zero;
+          }
+#pragma unroll
+          for (int t = 0; t < TILES; ++t)
+#pragma unroll
+            for (int g = 0; g < kBY; ++g)
+              acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc[t], bv[g], acc[g][t], 0, 0, 0);
+        }
       }
     }
   }
