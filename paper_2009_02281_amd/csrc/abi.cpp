@@ -1371,13 +1371,17 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
       // classical Gram-Schmidt, twice
       // (systems frozen by the Givens step are skipped on the device; their
       // columns past len are never used)
-      aim::launch_block_dot(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h, s, w.gst);
-      aim::launch_block_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.h, j + 1, s, w.gst);
-      aim::launch_block_dot(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h2, s, w.gst);
-      aim::launch_block_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.h2, j + 1, s, w.gst);
-      aim::launch_norms(w.d, n, nrhs, w.partial, w.nrm, s, w.gst);
-      aim::launch_scale_inv(w.d, w.nrm, static_cast<char*>(w.V) + size_t(j + 1) * nrhs * vec, n,
-                            nrhs, n, s, w.gst);
+      // (the updates sum the dot partials themselves and the scaling the
+      // norm partials, so no reduction launches; the coefficients h, h2 and
+      // the norm land in w.h, w.h2 and w.nrm for the Givens step)
+      aim::launch_block_dot_partials(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, s, w.gst);
+      aim::launch_gs_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h, s, w.gst);
+      aim::launch_block_dot_partials(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, s, w.gst);
+      aim::launch_gs_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h2, s, w.gst);
+      aim::launch_norm_partials(w.d, n, nrhs, w.partial, s, w.gst);
+      aim::launch_scale_norm(w.d, w.partial, w.nrm,
+                             static_cast<char*>(w.V) + size_t(j + 1) * nrhs * vec, n, nrhs, n, s,
+                             w.gst);
       aim::launch_givens_step(w.h, w.h2, w.nrm, nrhs, j, mc, w.H, w.cs, w.sn, w.g, w.gst, w.scale,
                               tol, max_iter, s);
       if ((j + 1) % kSyncEvery == 0 || j + 1 == mm) {

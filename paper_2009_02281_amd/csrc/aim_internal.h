@@ -171,16 +171,26 @@ struct GivensState {
 // norms of those are 0, their vectors are left as they are.
 void launch_cast_c128_to_c64(const void* in, void* out, int64_t count, hipStream_t s);
 void launch_cast_c64_to_c128(const void* in, void* out, int64_t count, hipStream_t s);
-// out[r][i] = sum_n conj(V_i,r[n]) w[r][n] for i < nv (two-stage, deterministic)
-void launch_block_dot(const void* V, int64_t si, int64_t sr, const void* w, int64_t n, int nv,
-                      int nrhs, void* partial, void* out, hipStream_t s,
-                      const GivensState* gst = nullptr);
-// w[r] -= sum_i h[r][i] V_i,r
-void launch_block_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv,
-                         int nrhs, const void* h, int64_t ldh, hipStream_t s,
-                         const GivensState* gst = nullptr);
 void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out, hipStream_t s,
                   const GivensState* gst = nullptr);
+// One Arnoldi step without reduction launches: the partials of
+// conj(V_i,r) . w[r] over chunks of positions (launch_block_dot_partials)
+// feed the Gram-Schmidt update w[r] -= sum_i h[r][i] V_i,r directly
+// (launch_gs_update, which also stores h in h_out[r][i]), and the norm
+// partials (launch_norm_partials) feed the scaling w[r] / ||w[r]|| directly
+// (launch_scale_norm, which also stores the norms in nrm_out); partials are
+// summed in chunk order (deterministic).
+void launch_block_dot_partials(const void* V, int64_t si, int64_t sr, const void* w, int64_t n,
+                               int nv, int nrhs, void* partial, hipStream_t s,
+                               const GivensState* gst = nullptr);
+void launch_gs_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv, int nrhs,
+                      const void* partial, void* h_out, hipStream_t s,
+                      const GivensState* gst = nullptr);
+void launch_norm_partials(const void* w, int64_t n, int nrhs, void* partial, hipStream_t s,
+                          const GivensState* gst = nullptr);
+void launch_scale_norm(const void* w, const void* partial, double* nrm_out, void* out, int64_t n,
+                       int nrhs, int64_t out_stride, hipStream_t s,
+                       const GivensState* gst = nullptr);
 // out[r] = w[r] * (1 / nrm[r]) (0 if nrm == 0)
 void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
                       int64_t out_stride, hipStream_t s, const GivensState* gst = nullptr);

@@ -1387,36 +1387,8 @@ __global__ __launch_bounds__(256) void block_dot_kernel(const double2* __restric
   if (threadIdx.x == 0) partial[(int64_t(r) * nv + i) * nchunk + c] = s;
 }
 
-__global__ void reduce_partials_kernel(const double2* partial, int nchunk, int total,
-                                       double2* out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  double2 s;
-  s.x = 0.0;
-  s.y = 0.0;
-  for (int c = 0; c < nchunk; ++c) {
-    s.x += partial[int64_t(idx) * nchunk + c].x;
-    s.y += partial[int64_t(idx) * nchunk + c].y;
-  }
-  out[idx] = s;
-}
-
-void launch_block_dot(const void* V, int64_t si, int64_t sr, const void* w, int64_t n, int nv,
-                      int nrhs, void* partial, void* out, hipStream_t s, const GivensState* gst) {
-  const int nchunk = int((n + kDotChunk - 1) / kDotChunk);
-  hipLaunchKernelGGL(block_dot_kernel, dim3(nchunk, nv, nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(V), si, sr, static_cast<const double2*>(w), n, nv,
-                     nchunk, static_cast<double2*>(partial), gst);
-  AIM_HIP(hipGetLastError());
-  const int total = nv * nrhs;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((total + 127) / 128), dim3(128), 0, s,
-                     static_cast<const double2*>(partial), nchunk, total,
-                     static_cast<double2*>(out));
-  AIM_HIP(hipGetLastError());
-}
-
-// w[r] -/+= sum_{i < nv} h[r][i] V[r][i] (Gram-Schmidt update, SUB; the
-// restart update x += Z y, !SUB): one element per thread (the launch covers
+// w[r] -/+= sum_{i < nv} h[r][i] V[r][i] (SUB: a Gram-Schmidt update; !SUB:
+// the restart update x += Z y): one element per thread (the launch covers
 // every element, so all CUs take part), four basis vectors loaded together
 // per step; the order of the terms is fixed
 template <bool SUB>
@@ -1455,12 +1427,80 @@ __global__ __launch_bounds__(128) void basis_axpy_kernel(const double2* __restri
   w[int64_t(r) * n + k] = acc;
 }
 
-void launch_block_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv,
-                         int nrhs, const void* h, int64_t ldh, hipStream_t s,
-                         const GivensState* gst) {
-  hipLaunchKernelGGL(basis_axpy_kernel<true>, dim3(unsigned((n + 127) / 128), nrhs), dim3(128), 0,
-                     s, static_cast<const double2*>(V), si, sr, static_cast<double2*>(w), n, nv,
-                     static_cast<const double2*>(h), ldh, gst);
+// One Arnoldi step's Gram-Schmidt update straight from the dot partials:
+// h[r][i] = sum_c part[(r nv + i) nchunk + c] is summed by every workgroup
+// into LDS (chunks in order, so every workgroup has the same value to the
+// bit), then w[r] -= sum_i h[r][i] V_i,r as in basis_axpy_kernel; workgroup
+// 0 of each system also stores h in h_out for the Givens step.  No separate
+// reduction launch.
+constexpr int kMaxBasis = 256;
+int dot_chunks(int64_t n) { return int((n + kDotChunk - 1) / kDotChunk); }
+
+__global__ __launch_bounds__(128) void gs_update_kernel(const double2* __restrict__ V, int64_t si,
+                                                        int64_t sr, double2* __restrict__ w,
+                                                        int64_t n, int nv,
+                                                        const double2* __restrict__ part,
+                                                        int nchunk, double2* __restrict__ h_out,
+                                                        const GivensState* __restrict__ gst) {
+  __shared__ double2 hs[kMaxBasis];
+  const int r = blockIdx.y;
+  if (gst && gst[r].frozen) return;  // uniform over the block
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    const double2* pp = part + (int64_t(r) * nv + i) * nchunk;
+    double2 sum = make_double2(0.0, 0.0);
+    for (int c0 = 0; c0 < nchunk; c0 += 8) {  // loads in flight together, sums in order
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = c0 + u < nchunk ? pp[c0 + u] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < nchunk) {
+          sum.x += v[u].x;
+          sum.y += v[u].y;
+        }
+    }
+    hs[i] = sum;
+    if (blockIdx.x == 0) h_out[int64_t(r) * nv + i] = sum;
+  }
+  __syncthreads();
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double2* vr = V + int64_t(r) * sr * n + k;
+  const int64_t vs = si * n;
+  double2 acc = w[int64_t(r) * n + k];
+  auto term = [&](double2 c, double2 a) {
+    acc.x -= c.x * a.x - c.y * a.y;
+    acc.y -= c.x * a.y + c.y * a.x;
+  };
+  int i = 0;
+  for (; i + 4 <= nv; i += 4) {
+    double2 a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = vr[int64_t(i + u) * vs];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) term(hs[i + u], a[u]);
+  }
+  for (; i < nv; ++i) term(hs[i], vr[int64_t(i) * vs]);
+  w[int64_t(r) * n + k] = acc;
+}
+
+void launch_block_dot_partials(const void* V, int64_t si, int64_t sr, const void* w, int64_t n,
+                               int nv, int nrhs, void* partial, hipStream_t s,
+                               const GivensState* gst) {
+  const int nchunk = dot_chunks(n);
+  hipLaunchKernelGGL(block_dot_kernel, dim3(nchunk, nv, nrhs), dim3(256), 0, s,
+                     static_cast<const double2*>(V), si, sr, static_cast<const double2*>(w), n, nv,
+                     nchunk, static_cast<double2*>(partial), gst);
+  AIM_HIP(hipGetLastError());
+}
+
+void launch_gs_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv, int nrhs,
+                      const void* partial, void* h_out, hipStream_t s, const GivensState* gst) {
+  AIM_REQUIRE(nv <= kMaxBasis, AIM_ERR_INVALID_ARG, "Krylov basis too large");
+  hipLaunchKernelGGL(gs_update_kernel, dim3(unsigned((n + 127) / 128), nrhs), dim3(128), 0, s,
+                     static_cast<const double2*>(V), si, sr, static_cast<double2*>(w), n, nv,
+                     static_cast<const double2*>(partial), dot_chunks(n),
+                     static_cast<double2*>(h_out), gst);
   AIM_HIP(hipGetLastError());
 }
 
@@ -1516,6 +1556,58 @@ __global__ void scale_inv_kernel(const double2* w, const double* nrm, double2* o
     v.y *= sc;
     out[int64_t(r) * out_stride + k] = v;
   }
+}
+
+// out[r] = w[r] / ||w[r]|| with the norm summed from norm_partial_kernel's
+// partials by every workgroup (chunks in order, as norm_finish_kernel sums
+// them: the same value to the bit); workgroup 0 of each system stores it in
+// nrm_out for the Givens step.  No separate finishing launch.
+__global__ void scale_norm_kernel(const double2* w, const double2* __restrict__ part, int nchunk,
+                                  double* __restrict__ nrm_out, double2* out, int64_t n,
+                                  int64_t out_stride, const GivensState* __restrict__ gst) {
+  __shared__ double nrm_s;
+  const int r = blockIdx.y;
+  if (gst && gst[r].frozen) return;  // uniform over the block
+  if (threadIdx.x == 0) {
+    const double2* pp = part + int64_t(r) * nchunk;
+    double sum = 0.0;
+    for (int c0 = 0; c0 < nchunk; c0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = c0 + u < nchunk ? pp[c0 + u].x : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < nchunk) sum += v[u];
+    }
+    nrm_s = sqrt(sum);
+    if (blockIdx.x == 0) nrm_out[r] = nrm_s;
+  }
+  __syncthreads();
+  const double nv = nrm_s;
+  const double sc = nv > 0.0 ? 1.0 / nv : 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    double2 v = w[int64_t(r) * n + k];
+    v.x *= sc;
+    v.y *= sc;
+    out[int64_t(r) * out_stride + k] = v;
+  }
+}
+
+void launch_norm_partials(const void* w, int64_t n, int nrhs, void* partial, hipStream_t s,
+                          const GivensState* gst) {
+  hipLaunchKernelGGL(norm_partial_kernel, dim3(dot_chunks(n), nrhs), dim3(256), 0, s,
+                     static_cast<const double2*>(w), n, dot_chunks(n),
+                     static_cast<double2*>(partial), gst);
+  AIM_HIP(hipGetLastError());
+}
+
+void launch_scale_norm(const void* w, const void* partial, double* nrm_out, void* out, int64_t n,
+                       int nrhs, int64_t out_stride, hipStream_t s, const GivensState* gst) {
+  hipLaunchKernelGGL(scale_norm_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, s,
+                     static_cast<const double2*>(w), static_cast<const double2*>(partial),
+                     dot_chunks(n), nrm_out, static_cast<double2*>(out), n, out_stride, gst);
+  AIM_HIP(hipGetLastError());
 }
 
 void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
