@@ -248,8 +248,17 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] += w[(c * 27 + tap) * 2] * v0 + w[(c * 27 + tap) * 2 + 1] * v1;
   }
+  // the C bf16 outputs as 16-byte words (the row stride and offset are
+  // multiples of 8 channels)
+  static_assert(C % 8 == 0, "outputs in groups of 8");
+  uint32_t wv[C / 2];
 #pragma unroll
-  for (int c = 0; c < C; ++c) Y[p * ldy + oy + c] = f2bf(fmaxf(acc[c], 0.f));
+  for (int c = 0; c < C; c += 2)
+    wv[c / 2] = uint32_t(f2bf(fmaxf(acc[c], 0.f))) | (uint32_t(f2bf(fmaxf(acc[c + 1], 0.f))) << 16);
+  uint4* dst = reinterpret_cast<uint4*>(Y + p * ldy + oy);
+#pragma unroll
+  for (int q = 0; q < C / 8; ++q)
+    dst[q] = make_uint4(wv[4 * q], wv[4 * q + 1], wv[4 * q + 2], wv[4 * q + 3]);
 }
 
 // 1x1 output layer: out[p][2] = a[p][:] W^T + b (fp32)
@@ -1147,6 +1156,7 @@ struct aim_unet_s {
     const int64_t P0 = int64_t(D) * H * W, P1 = P0 / 8;
     const Layer* Ls = layers.data();
     AIM_REQUIRE(C == 16, AIM_ERR_STATE, "only base width 16 is built");
+    AIM_REQUIRE(c0 % 8 == 0, AIM_ERR_STATE, "first-layer outputs go out as 16-byte words");
     hipLaunchKernelGGL((conv_first_kernel<16>), dim3(gsz(P0)), dim3(256), 0, s, in, D, Ds, H, W,
                        w + Ls[0].w_off, w + Ls[0].b_off, a.a0, c0, 0);
     AIM_HIP(hipGetLastError());
