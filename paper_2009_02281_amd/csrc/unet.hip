@@ -736,13 +736,21 @@ template <int C>
 __global__ void out_backward_kernel(const float* __restrict__ dout, const float* __restrict__ Wm,
                                     const uint16_t* __restrict__ act, int64_t P,
                                     uint16_t* __restrict__ ga) {
+  static_assert(C % 8 == 0, "channels in 16-byte words");
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  const float d0 = dout[2 * p], d1 = dout[2 * p + 1];
+  const float2 d = *reinterpret_cast<const float2*>(dout + 2 * p);
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const float v = d0 * bf2f(f2bf(Wm[c])) + d1 * bf2f(f2bf(Wm[C + c]));
-    ga[p * C + c] = f2bf(bf2f(act[p * C + c]) > 0.f ? v : 0.f);
+  for (int c8 = 0; c8 < C / 8; ++c8) {
+    float a[8], v[8];
+    unpack8(*reinterpret_cast<const uint4*>(act + p * C + 8 * c8), a);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = 8 * c8 + j;
+      const float g = d.x * bf2f(f2bf(Wm[c])) + d.y * bf2f(f2bf(Wm[C + c]));
+      v[j] = a[j] > 0.f ? g : 0.f;
+    }
+    *reinterpret_cast<uint4*>(ga + p * C + 8 * c8) = pack8(v);
   }
 }
 
