@@ -326,7 +326,8 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
 }
 
 // skip (batch plans only, may be null): systems whose product is not
-// needed (GMRES systems that have stopped); their rows of y are zeroed
+// needed (GMRES systems that have stopped); their rows of y are left as they
+// are, and the caller must not read them
 void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev = nullptr,
                 const char* skip = nullptr) {
@@ -340,10 +341,7 @@ void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs
       aim_plan_s* q = p->inst[i].get();
       const char* xi = static_cast<const char*>(x) + size_t(i) * nmax * cb;
       char* yi = static_cast<char*>(y) + size_t(i) * nmax * cb;
-      if (skip && skip[i]) {
-        aim::launch_zero_words(yi, nmax * int64_t(cb / 8), s);
-        continue;
-      }
+      if (skip && skip[i]) continue;
       matvec_any(q, prec, xi, yi, 1, dfreq + i, s);
       aim::launch_zero_words(yi + size_t(q->t.N) * cb, (nmax - q->t.N) * int64_t(cb / 8), s);
     }
@@ -1350,8 +1348,8 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
     }
     // systems stopped at the cycle's start (and, from each look of the host
     // on, those stopped since) need no matvec: on a batch plan their
-    // instances are skipped (zero product, which their frozen Givens state
-    // ignores)
+    // instances are skipped, and the Krylov kernels and the Givens step never
+    // read their rows of the product (they exit on the frozen flag)
     std::vector<char> skip(nrhs);
     for (int r = 0; r < nrhs; ++r) skip[r] = w.gst_host[r].frozen ? 1 : 0;
     AIM_HIP(hipMemcpyAsync(w.g, w.g_host, sizeof(double2) * nrhs * (mc + 1),
