@@ -414,7 +414,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; the multi-GPU design is "
+        print("bench.py: this benchmark measures one GPU only; the multi-GPU design is "
               "described, not run (use --gpus 1)", file=sys.stderr)
         return 2
 

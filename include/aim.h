@@ -193,8 +193,8 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
  * device call on it returns AIM_ERR_STATE.  Blocking; runs without a GPU. */
 aim_status aim_setup_host(const aim_setup_desc* desc, aim_plan* out);
 
-/* A batch of geometries of uneven size (the survey's batched solve over
- * many instances): n descriptions, each set up as by aim_setup (own grid,
+/* A batch of geometries of uneven size (one batched solve over many
+ * instances): n descriptions, each set up as by aim_setup (own grid,
  * frequencies, tables, spectra; max_rhs of each is ignored), behind one
  * handle.  System i belongs to instance i; its vectors are rows of length
  * N_max = max N_i, of which the first N_i entries are used and the rest must

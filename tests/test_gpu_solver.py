@@ -1,7 +1,7 @@
 """GPU tests of aim_solve through the C ABI: restarted GMRES in complex128,
 complex128 iterative refinement around complex64 matvecs, the static
 diagonal and near-block preconditioners, batched frequencies, and the
-failure paths.  Solutions are judged with the oracle's operator (the true
+failure paths.  Solutions are checked with the oracle's operator (the true
 residual) and against a direct solve of the oracle's assembled matrix."""
 import math
 
