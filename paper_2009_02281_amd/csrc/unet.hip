@@ -11,12 +11,14 @@
 // with 3x3x3 "same" convolutions, 2x2x2 average pooling and nearest
 // upsampling.  A batch of samples is stacked along z (each sample Ds planes
 // deep, Ds a multiple of 4, so pooling never mixes samples); the 3x3x3
-// kernels treat the planes of other samples as the zero padding.  Weights and activations are bfloat16; the convolutions are
-// LDS-tiled implicit GEMMs on the 16x16x32 bf16 MFMA with fp32 accumulation
-// (the data gradient is the same GEMM with flipped, transposed weights); the
-// weight gradients of the 3x3x3 layers are per-tap GEMMs over positions on the
-// same MFMA, those of the 2-channel input and output layers fp32 reductions;
-// master weights and Adam moments are fp32.
+// kernels treat the planes of other samples as the zero padding.  Weights
+// and activations are bfloat16; the convolutions are LDS-tiled implicit GEMMs
+// on the 16x16x32 bf16 MFMA with fp32 accumulation (the data gradient is the
+// same GEMM with flipped, transposed weights); the weight gradients of the
+// 3x3x3 layers (the 2-channel input layer on its input padded to 16
+// channels) are GEMMs over bricks of positions, all 27 taps per workgroup, on
+// the same MFMA, the 1x1 output layer's a one-pass fp32 reduction, all summed
+// in two deterministic stages; master weights and Adam moments are fp32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -283,69 +285,6 @@ __global__ void conv_out_kernel(const uint16_t* __restrict__ a, int64_t P,
 // weight gradients: dW[co][t][ci] (+)= sum_p dY[p][co] X[p + d(t)][ci],
 // computed per chunk of positions (two-stage, deterministic)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float ldv(const uint16_t* p, int64_t i) { return bf2f(p[i]); }
-__device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
-
-constexpr int kWgPos = 32;  // positions staged per step
-
-template <typename TX, typename TY>
-__global__ __launch_bounds__(256) void wgrad_partial_kernel(
-    const TX* __restrict__ X, int ldx, int ox, int Cin, const TY* __restrict__ dY, int ldy, int oy,
-    int Cout, int D, int Ds, int H, int W, int ntaps, int64_t chunk, float* __restrict__ part) {
-  extern __shared__ float sm[];
-  float* sy = sm;                     // [kWgPos][Cout]
-  float* sx = sm + kWgPos * Cout;     // [kWgPos][Cin]
-  const int tap = blockIdx.y;
-  const int64_t P = int64_t(D) * H * W;
-  const int64_t pb = int64_t(blockIdx.x) * chunk, pe = min(P, pb + chunk);
-  const int dx = ntaps == 1 ? 0 : tap % 3 - 1, dy = ntaps == 1 ? 0 : (tap / 3) % 3 - 1,
-            dz = ntaps == 1 ? 0 : tap / 9 - 1;
-  const int nent = Cout * Cin;
-  constexpr int kMaxPer = 24;  // Cout * Cin <= 256 * 24
-  float acc[kMaxPer];
-#pragma unroll
-  for (int j = 0; j < kMaxPer; ++j) acc[j] = 0.f;
-  for (int64_t s0 = pb; s0 < pe; s0 += kWgPos) {
-    const int cnt = int(min(int64_t(kWgPos), pe - s0));
-    for (int i = threadIdx.x; i < kWgPos * Cout; i += 256) {
-      const int pp = i / Cout, c = i % Cout;
-      sy[i] = pp < cnt ? ldv(dY, (s0 + pp) * ldy + oy + c) : 0.f;
-    }
-    for (int i = threadIdx.x; i < kWgPos * Cin; i += 256) {
-      const int pp = i / Cin, c = i % Cin;
-      float v = 0.f;
-      if (pp < cnt) {
-        int x, y, z;
-        pos_xyz(s0 + pp, W, H, x, y, z);
-        const int nx = x + dx, ny = y + dy, nz = z + dz, zs = (z / Ds) * Ds;
-        if (nx >= 0 && ny >= 0 && nz >= zs && nx < W && ny < H && nz < zs + Ds)
-          v = ldv(X, ((int64_t(nz) * H + ny) * W + nx) * ldx + ox + c);
-      }
-      sx[i] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kMaxPer; ++j) {
-      const int e = threadIdx.x + j * 256;
-      if (e < nent) {
-        const int co = e / Cin, ci = e % Cin;
-        float a = acc[j];
-        for (int pp = 0; pp < kWgPos; ++pp) a += sy[pp * Cout + co] * sx[pp * Cin + ci];
-        acc[j] = a;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < kMaxPer; ++j) {
-    const int e = threadIdx.x + j * 256;
-    if (e < nent) {
-      const int co = e / Cin, ci = e % Cin;
-      part[(int64_t(blockIdx.x) * ntaps * Cout + int64_t(co) * ntaps + tap) * Cin + ci] = acc[j];
-    }
-  }
-}
-
 // Weight gradients of a 3x3x3 layer on MFMA for bf16 X and dY:
 //   dW[co][t][ci] = sum_p dY[p][co] X[p + d(t)][ci]
 // (p and p + d(t) in the same sample), a GEMM over positions per tap.  A
@@ -537,28 +476,6 @@ __global__ void pack_in16_kernel(const float* __restrict__ in, int64_t P,
   d[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// bias gradient, first stage: part[chunk][c] = sum over the chunk's positions
-// of dY[p][c]; thread t covers channel t % C and every (256 / C)-th position
-template <typename TY>
-__global__ __launch_bounds__(256) void bgrad_partial_kernel(const TY* __restrict__ dY, int ldy,
-                                                            int oy, int C, int64_t P,
-                                                            int64_t chunk,
-                                                            float* __restrict__ part) {
-  __shared__ float red[256];
-  const int R = 256 / C;
-  const int t = threadIdx.x, c = t % C, r = t / C;
-  const int64_t pb = int64_t(blockIdx.x) * chunk, pe = min(P, pb + chunk);
-  float s = 0.f;
-  if (r < R)
-    for (int64_t p = pb + r; p < pe; p += R) s += ldv(dY, p * ldy + oy + c);
-  red[t] = s;
-  __syncthreads();
-  if (t < C) {
-    float a = 0.f;
-    for (int q = 0; q < R; ++q) a += red[q * C + t];
-    part[int64_t(blockIdx.x) * C + t] = a;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // pooling, upsampling, masks
@@ -987,24 +904,16 @@ struct aim_unet_s {
     acts.gb1 = b16(P1 * c1);
     acts.gb2 = b16(P2 * c2);
     acts.in16 = b16(P0 * 16);
-    // two-stage gradient sums: weight partials (chunks x entries, bounded
-    // by wg_chunks) and bias partials (chunks x output channels)
+    // two-stage gradient sums: weight partials (chunks x entries, at most
+    // 2^22) and bias partials (chunks x output channels)
     acts.part_n = std::max<int64_t>(int64_t(1) << 22, int64_t(kMaxChunks) * 64);
     acts.part = f32(acts.part_n);
     acts.partb_n = int64_t(kMaxChunks) * 64;
     acts.partb = f32(acts.partb_n);
   }
 
-  // Chunks of positions for the partial sums of the 1x1 output layer's
-  // gradient: enough blocks to fill the chip, at least four 64-position
-  // steps per chunk, and at most 2^21 partial sums (or 8 chunks) in flight.
+  // at most this many chunks of positions per gradient reduction
   static constexpr int64_t kMaxChunks = 1024;
-  static int64_t wg_chunks(int64_t P, int64_t entries, int taps) {
-    const int64_t steps = (P + 63) / 64;
-    int64_t n = std::min<int64_t>((4096 + taps - 1) / taps, std::max<int64_t>(1, steps / 4));
-    n = std::min<int64_t>(n, std::max<int64_t>(8, (int64_t(1) << 21) / entries));
-    return std::max<int64_t>(1, std::min<int64_t>(n, kMaxChunks));
-  }
 
   // weight and bias partials of one layer (nchunk chunks each) into g
   void reduce(int64_t nchunk, int64_t nw, float* gw, int64_t nb, float* gb, hipStream_t s) {
@@ -1126,24 +1035,6 @@ struct aim_unet_s {
                     AIM_ERR_STATE, "gradient partial buffer too small");
         hipLaunchKernelGGL((outgrad_partial_kernel<16>), dim3(unsigned(nchunk)), dim3(256), 0, s,
                            X, dY, P, chunk, acts.part, acts.partb);
-        done = true;
-      }
-    }
-    if constexpr (std::is_same_v<TX, uint16_t>) {
-      if (!done) {
-        nchunk = wg_chunks(P, entries, L.taps);
-        const int64_t chunk = ((P + 63) / 64 + nchunk - 1) / nchunk * 64;
-        nchunk = (P + chunk - 1) / chunk;
-        AIM_REQUIRE(nchunk * entries <= acts.part_n && nchunk * cout <= acts.partb_n,
-                    AIM_ERR_STATE, "gradient partial buffer too small");
-        const size_t shm = size_t(kWgPos) * (cout + cin) * sizeof(float);
-        hipLaunchKernelGGL((wgrad_partial_kernel<TX, TY>), dim3(unsigned(nchunk), L.taps),
-                           dim3(256), shm, s, X, ldx, ox, cin, dY, ldy, oy, cout, D, Ds, H, W,
-                           L.taps, chunk, acts.part);
-        AIM_HIP(hipGetLastError());
-        // bias partials over the same chunks
-        hipLaunchKernelGGL((bgrad_partial_kernel<TY>), dim3(unsigned(nchunk)), dim3(256), 0, s,
-                           dY, ldy, oy, cout, P, chunk, acts.partb);
         done = true;
       }
     }
