@@ -7,9 +7,13 @@ by the kernel spectrum, inverse FFT, interpolation and the sparse near-field
 correction -- all in the library's HIP kernels.  Inputs are resident in HBM
 when the timed region starts.
 
-Default workload: the 4x4 array of 1x1x4-wavelength conductor boxes
-(57,600 triangles, 3rd-order stencils, 128x128x64 grid zero-padded to
-256x256x128, near threshold 3h, k = 2 pi), complex128.  Prints one JSON line.
+Default workload: the largest single-GPU operator, a radius-6 sphere meshed
+as a level-7 icosphere (327,680 triangles, 2nd-order stencils, 256^3 grid
+zero-padded to 512^3, near threshold 2h, k = 2 pi), complex128.  The same
+line carries, as extra keys, the complex64 figure on that operator, the
+512-vector frequency sweep (64 wavenumbers x 8 right-hand sides on the
+1,280-triangle sphere) and the 57,600-triangle box array.  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -95,34 +99,61 @@ def load_traffic(kernel: str, workload: str, prec: str):
     return ent.get("bytes_per_launch")
 
 
+def host_threads() -> int:
+    """Threads the oracle may use: the CPUs this process may run on, at most
+    16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(w, x, reps: int = 3, near_rows: int = 512) -> dict:
     """The oracle (NumPy/SciPy float64) timed on this host: the whole far part
-    plus the near-field correction on a row sample, scaled to all rows."""
+    (projection, zero-padded FFT convolution over the full padded grid,
+    interpolation) plus the near-field correction on a row sample, scaled to
+    all rows -- an estimate of one full oracle matvec.  Median of ``reps``
+    runs with the host's threads, then one run with a single thread (the
+    paper's own set-up ran single-threaded)."""
     import numpy as np
     import scipy.sparse as sp
     from oracle import aimx
+    threads = host_threads()
+    aimx.FFT_WORKERS = threads
     o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
     k = float(w.k[0])
     o.spectrum(k)
     rows = np.sort(np.random.default_rng(5).choice(o.N, min(near_rows, o.N), replace=False))
     r, c, v = o.correction_rows(rows)
     Cs = sp.csr_matrix((v, (r, c)), shape=(o.N, o.N))
-    t_far, t_near = [], []
-    for _ in range(reps):
+
+    def once():
         t0 = time.perf_counter()
         o.far(x, k)
         t1 = time.perf_counter()
         Cs @ x
         t2 = time.perf_counter()
-        t_far.append(t1 - t0)
-        t_near.append(t2 - t1)
-    t = min(t_far) + min(t_near) * o.N / rows.size
-    cores = os.cpu_count() or 1
-    return {"value": o.N / t, "unit": "unknowns*matvecs/s", "cores": cores, "kind": "oracle",
-            "sample": (f"one matvec of the same workload: full far part (P x, scipy.fft "
-                       f"over the 256x256x128 padded grid with {cores} workers, P^T), "
-                       f"near correction on {rows.size} sampled rows scaled by "
-                       f"{o.N}/{rows.size}; best of {reps}; oracle set-up excluded"),
+        return t1 - t0, t2 - t1
+
+    runs = [once() for _ in range(reps)]
+    t_far = sorted(a for a, _ in runs)[reps // 2]
+    t_near = sorted(b for _, b in runs)[reps // 2]
+    t = t_far + t_near * o.N / rows.size
+    aimx.FFT_WORKERS = 1
+    f1, n1 = once()
+    aimx.FFT_WORKERS = -1
+    t1 = f1 + n1 * o.N / rows.size
+    padded = "x".join(str(2 * d) for d in w.dims)
+    return {"value": o.N / t, "unit": "unknowns*matvecs/s", "cores": threads,
+            "kind": "estimate",
+            "sample": (f"one oracle matvec of the same workload, estimated: the full far part "
+                       f"(P x, scipy.fft over the {padded} padded grid with {threads} "
+                       f"workers, P^T) timed whole, the near correction timed on "
+                       f"{rows.size} sampled rows and scaled by {o.N}/{rows.size}; median "
+                       f"of {reps}; oracle set-up excluded"),
+            "single_thread": {"value": o.N / t1, "unit": "unknowns*matvecs/s", "cores": 1,
+                              "seconds_per_matvec": t1, "runs": 1},
             "seconds_per_matvec": t}
 
 
@@ -385,12 +416,63 @@ def unet_leg(dims=(64, 64, 64), reps: int = 20) -> dict:
                     "it also holds host synchronisation for the loss", **res}
 
 
+def time_matvecs(plan, x, y, prec: str, steps: int, warmup: int, freq=None) -> float:
+    """ms per matvec call, back to back between two events on the stream the
+    library launches on (torch's current stream)."""
+    import torch
+    for _ in range(warmup):
+        plan.matvec(x, prec=prec, out=y, freq_idx=freq)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        plan.matvec(x, prec=prec, out=y, freq_idx=freq)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def extra_workload(name: str, precs, steps: int, warmup: int) -> dict:
+    """Throughput of another workload (its own plan, autotuned schedules) in
+    the given precisions: the sweep runs all 512 vectors per launch, vector r
+    at wavenumber r mod 64; the others one vector."""
+    import numpy as np
+    import torch
+    from paper_2009_02281_amd import binding
+    from paper_2009_02281_amd import inputs as I
+    w = make_workload(name)
+    freq, nrhs = None, 1
+    if name == "sweep":
+        nrhs = 8 * len(w.k)
+        freq = np.arange(nrhs) % len(w.k)
+    plan = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                        precisions=precs, max_rhs=nrhs)
+    info = plan.info()
+    xh = I.complex_gaussian(w.n, w.seed_base + 1, nrhs=nrhs)
+    res = {"workload": w.name, "triangles": w.n, "grid": list(w.dims), "nrhs": nrhs,
+           "n_freq": int(len(w.k))}
+    for pr in precs:
+        plan.autotune(prec=pr, nrhs=nrhs, reps=5)
+        dt = torch.complex128 if pr == "c128" else torch.complex64
+        x = torch.from_numpy(xh).to(dt).cuda()
+        y = torch.empty_like(x)
+        ms = time_matvecs(plan, x, y, pr, steps, warmup, freq)
+        ab = sum(algorithmic_bytes(info, pr, nrhs).values())
+        res[pr] = {"ms_per_launch": ms, "unknowns_matvecs_per_s": w.n * nrhs / (ms * 1e-3),
+                   "alg_gbs": ab / (ms * 1e-3) / 1e9}
+        print(f"[bench] extra {w.name} {pr}: {ms:.4f} ms per launch of {nrhs} -> "
+              f"{res[pr]['unknowns_matvecs_per_s']:.4e} unknowns*matvecs/s", file=sys.stderr,
+              flush=True)
+    plan.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="boxarray",
+    ap.add_argument("--workload", default="sphere-large",
                     choices=["boxarray", "sphere", "sphere-large", "sweep"])
     ap.add_argument("--prec", default="c128", choices=["c128", "c64"])
     ap.add_argument("--nrhs", type=int, default=0,
@@ -401,13 +483,15 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner time-to-tolerance leg")
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net throughput leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other precision and the extra workloads (sweep, box array)")
     ap.add_argument("--solve-rtol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=4000,
                     help="GMRES iteration cap per solve (per refinement step in complex64)")
     ap.add_argument("--batch", action="store_true",
                     help="also time one batched solve over 32 uneven geometries against "
                          "solving them one after another")
-    ap.add_argument("--solve-pcs", default="none,diag,nearblock",
+    ap.add_argument("--solve-pcs", default="none,diag",
                     help="comma-separated preconditioners for the GMRES leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -438,10 +522,11 @@ def main() -> int:
         args.no_solve = True
         args.no_cpu = True
     args.nrhs = args.nrhs or 1
+    other = "c64" if args.prec == "c128" else "c128"
     print(f"[bench] workload {w.name}: N={w.n} dims={w.dims} order={w.order} "
           f"prec={args.prec} nrhs={args.nrhs}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    precs = ("c128", "c64") if not args.no_solve else (args.prec,)
+    precs = (args.prec,) if (args.no_solve and args.no_extra) else ("c128", "c64")
     plan = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
                         precisions=precs, max_rhs=args.nrhs)
     setup_s = time.perf_counter() - t0
@@ -460,16 +545,7 @@ def main() -> int:
     x = torch.from_numpy(xh).to(dtype).cuda()
     y = torch.empty_like(x)
 
-    for _ in range(args.warmup):
-        plan.matvec(x, prec=args.prec, out=y, freq_idx=freq)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(args.steps):
-        plan.matvec(x, prec=args.prec, out=y, freq_idx=freq)
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
+    ms = time_matvecs(plan, x, y, args.prec, args.steps, args.warmup, freq)
     value = w.n * args.nrhs / (ms * 1e-3)
     print(f"[bench] {ms:.4f} ms/matvec -> {value:.4e} unknowns*matvecs/s", file=sys.stderr,
           flush=True)
@@ -531,7 +607,9 @@ def main() -> int:
         dom = max(kms, key=kms.get)
         achieved = ab[dom] / (kms[dom] * 1e-3) / 1e9
         stages = {k: {"ms": kms[k], "alg_bytes": ab[k],
-                      "gbs": ab[k] / (kms[k] * 1e-3) / 1e9 if kms[k] > 0 else None}
+                      "gbs": ab[k] / (kms[k] * 1e-3) / 1e9 if kms[k] > 0 else None,
+                      "frac": ab[k] / (kms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS if kms[k] > 0
+                      else None}
                   for k in kms}
         total_b = sum(ab.values())
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
@@ -544,9 +622,34 @@ def main() -> int:
         print(f"[bench] kernels (ms): " + ", ".join(f"{k}={v:.4f}" for k, v in kms.items()),
               file=sys.stderr, flush=True)
 
+    if not args.no_extra and args.workload != "sweep":
+        xo = torch.from_numpy(xh).to(torch.complex64 if other == "c64" else torch.complex128).cuda()
+        yo = torch.empty_like(xo)
+        mso = time_matvecs(plan, xo, yo, other, args.steps, args.warmup, freq)
+        extra = {other: {"workload": w.name, "ms_per_step": mso,
+                         "unknowns_matvecs_per_s": w.n * args.nrhs / (mso * 1e-3)}}
+        if not args.no_profile:
+            ko = plan.profile_matvec(xo, reps=max(5, min(50, args.steps)), prec=other, out=yo,
+                                     freq_idx=freq)
+            abo = algorithmic_bytes(info, other, args.nrhs)
+            extra[other]["stages"] = {k: {"ms": ko[k], "gbs": abo[k] / (ko[k] * 1e-3) / 1e9,
+                                          "frac": abo[k] / (ko[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                      for k in ko}
+        print(f"[bench] {w.name} {other}: {mso:.4f} ms/matvec -> "
+              f"{extra[other]['unknowns_matvecs_per_s']:.4e}", file=sys.stderr, flush=True)
+        del xo, yo
+        out["extra"] = extra
+
     if not args.no_solve:
         out["gmres"] = solve_leg(plan, args.solve_rtol, args.solve_max_iter,
                                  tuple(args.solve_pcs.split(",")))
+    if not args.no_extra and args.workload != "sweep":
+        plan.close()
+        plan = None
+        torch.cuda.empty_cache()
+        out["extra"]["sweep"] = extra_workload("sweep", ("c128", "c64"), 20, 3)
+        if args.workload != "boxarray":
+            out["extra"]["boxarray"] = extra_workload("boxarray", ("c128", "c64"), 50, 5)
     if not args.no_learned and args.workload != "sweep":
         out["learned_pc"] = learned_pc_leg(args.solve_rtol)
     if not args.no_unet and args.workload != "sweep":
@@ -557,14 +660,17 @@ def main() -> int:
     if not args.no_cpu:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)
         cb = cpu_baseline(w, xh[0] if xh.ndim == 2 else xh)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-        print(f"[bench] oracle {cb['seconds_per_matvec']:.3f} s/matvec", file=sys.stderr,
-              flush=True)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                  "single_thread")}
+        print(f"[bench] oracle {cb['seconds_per_matvec']:.3f} s/matvec "
+              f"({cb['cores']} threads), {cb['single_thread']['seconds_per_matvec']:.3f} s "
+              f"single-threaded", file=sys.stderr, flush=True)
         if not args.no_solve:
             out["cpu_gmres"] = cpu_gmres_leg(args.solve_rtol)
             print(f"[bench] GMRES on the small sphere: oracle {out['cpu_gmres']['cpu']}, "
                   f"GPU {out['cpu_gmres']['gpu']}", file=sys.stderr, flush=True)
-    plan.close()
+    if plan is not None:
+        plan.close()
     print(json.dumps(out), flush=True)
     return 0
 

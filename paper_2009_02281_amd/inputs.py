@@ -301,14 +301,46 @@ def _pow2_at_least(v: float, lo: int = 32, hi: int = 128) -> int:
     return p
 
 
+def sphere_resonance_margin(ka: float) -> float:
+    """min over n <= ka + 5 of (ka)^2 |j_n(ka)| |h_n(ka)|.  The interior
+    Dirichlet problem of a sphere of radius a resonates where j_n(ka) = 0;
+    this measure is about |sin(ka - n pi/2)| for n well below ka and tends to
+    zero at a resonance, so a draw with a small margin is rejected."""
+    from scipy.special import spherical_jn, spherical_yn
+    n = np.arange(int(ka + 5) + 1)
+    j = spherical_jn(n, ka)
+    y = spherical_yn(n, ka)
+    return float(np.min(ka * ka * np.abs(j) * np.hypot(j, y)))
+
+
+def box_resonance_gap(k: float, size) -> float:
+    """Distance from k to the nearest interior Dirichlet wavenumber of a box
+    with sides ``size`` (pi sqrt((l/a)^2 + (m/b)^2 + (n/c)^2), l, m, n >= 1),
+    relative to the mean spacing of those wavenumbers near k (Weyl's law:
+    about 2 pi^2 / (volume k^2)).  Small values mean a near-resonant draw."""
+    a, b, c = (float(v) for v in size)
+    lmax = [int(k * v / math.pi) + 2 for v in (a, b, c)]
+    l = np.arange(1, lmax[0] + 1)[:, None, None] / a
+    m = np.arange(1, lmax[1] + 1)[None, :, None] / b
+    n = np.arange(1, lmax[2] + 1)[None, None, :] / c
+    km = math.pi * np.sqrt(l * l + m * m + n * n)
+    spacing = 2 * math.pi ** 2 / (a * b * c * k * k)
+    return float(np.min(np.abs(km - k)) / spacing)
+
+
 def uneven_batch(count: int = 32, seed: int = 5003, n_range=(5000, 120000)) -> list:
     """Uneven geometries for one batched solve.  Each instance draws a kind
     (icosphere of level 4-6, a box, or a 2x2 to 4x4 box array), a wavenumber
-    k ~ U[2 pi, 6 pi] and is meshed at about a tenth of its wavelength,
-    keeping 5k-120k triangles (draws outside the range are redrawn).  Grids
-    are a power of two per axis (32-128 points, so 64-256 padded) with the
-    spacing the library would derive for them, 2nd-order stencils and a 2h
-    near threshold."""
+    k ~ U[2 pi, 6 pi] and an edge length ~ U[lambda/12, lambda/8], and is
+    meshed at that edge, keeping 5k-120k triangles (draws outside the range
+    are redrawn).  A sphere's radius follows from its level and edge, so ka
+    varies continuously; draws near an interior resonance of the closed
+    surface, where the single-layer operator is nearly singular, are redrawn:
+    spheres need ``sphere_resonance_margin(ka) >= 0.15``, boxes (and each box
+    of an array) ``box_resonance_gap >= 0.3`` of the local mode spacing.
+    Grids are a power of two per axis (32-128 points, so 64-256 padded) with
+    the spacing the library would derive for them, 2nd-order stencils and a
+    2h near threshold."""
     rng = np.random.default_rng(seed)
     # mean edge of a unit-radius icosphere per level
     unit_edge = {}
@@ -317,24 +349,32 @@ def uneven_batch(count: int = 32, seed: int = 5003, n_range=(5000, 120000)) -> l
         kind = int(rng.integers(3))
         k = float(rng.uniform(2 * math.pi, 6 * math.pi))
         lam = 2 * math.pi / k
-        edge = lam / 10
+        edge = lam / float(rng.uniform(8.0, 12.0))
         if kind == 0:
             level = int(rng.integers(4, 7))
             if level not in unit_edge:
                 V1, T1 = icosphere(level, 1.0)
                 e = np.linalg.norm(V1[T1[:, 1]] - V1[T1[:, 0]], axis=1)
                 unit_edge[level] = float(e.mean())
-            V, T = icosphere(level, edge / unit_edge[level])
+            radius = edge / unit_edge[level]
+            if sphere_resonance_margin(k * radius) < 0.15:
+                continue
+            V, T = icosphere(level, radius)
             name = f"sphere-L{level}"
         elif kind == 1:
             size = rng.uniform(2.0, 8.0, size=3) * lam
+            if box_resonance_gap(k, size) < 0.3:
+                continue
             V, T = box_surface(np.zeros(3), size, edge)
             name = "box"
         else:
             nx, ny = (int(v) for v in rng.integers(2, 5, size=2))
             a, c = rng.uniform(1.0, 2.0) * lam, rng.uniform(2.0, 4.0) * lam
+            bseed = int(rng.integers(1 << 30))
+            if box_resonance_gap(k, (a, a, c)) < 0.3:
+                continue
             V, T = box_array(nx, ny, size=(a, a, c), gap=0.5 * lam, jitter=0.05 * lam,
-                             edge=edge, seed=int(rng.integers(1 << 30)))
+                             edge=edge, seed=bseed)
             name = f"boxarray-{nx}x{ny}"
         if not (n_range[0] <= T.shape[0] <= n_range[1]):
             continue

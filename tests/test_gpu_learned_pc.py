@@ -312,7 +312,10 @@ def test_train_on_other_geometries_then_solve_held_out():
         its[pc] = (int(res.iters[0]), bool(res.fallback_used[0]), res.seconds)
         assert res.converged[0], pc
     print("[gpu] held-out iterations: " + ", ".join(
-        f"{k}={v[0]}{' (fallback)' if v[1] else ''} {v[2] * 1e3:.1f} ms" for k, v in its.items()),
-        flush=True)
+        f"{k}={v[0]}{' (fallback)' if v[1] else ''} {v[2] * 1e3:.1f} ms" for k, v in its.items())
+        + f"; unet/diag iteration ratio {its['unet'][0] / its['diag'][0]:.2f}", flush=True)
+    # the network itself carried the solve: the gate never switched to the
+    # fallback (its benefit against diag is measured and reported, not pinned)
+    assert not its["unet"][1]
     p.set_unet(None)
     net.close()

@@ -343,16 +343,18 @@ def test_profile_matvec_times_every_kernel_and_leaves_the_product():
 
 def test_full_size_autotuned_schedules_match_oracle():
     """The full-size workloads in the launch configuration the benchmark
-    times: schedules picked by the autotuner (box array in both precisions,
-    the radius-6 sphere in complex64), sampled rows against the oracle."""
+    times: schedules picked by the autotuner (box array and the radius-6
+    sphere, each in both precisions), 64 sampled rows against the oracle --
+    for the sphere this covers the complex128 schedules at L = 512 and the
+    256^3 projection and interpolation that the refinement's residual uses."""
     cases = [("box array", I.box_array_large, ("c128", "c64"), 2301),
-             ("sphere", I.sphere_large, ("c64",), 2401)]
+             ("sphere", I.sphere_large, ("c128", "c64"), 2401)]
     for name, make, precs, seed in cases:
         w = make()
         print(f"[gpu] autotuned full size: {name} N={w.n}", flush=True)
         o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
         x = I.complex_gaussian(o.N, seed)
-        rows = np.sort(np.random.default_rng(seed + 1).choice(o.N, 24, replace=False))
+        rows = np.sort(np.random.default_rng(seed + 1).choice(o.N, 64, replace=False))
         ref = o.matvec_rows(x, w.k[0], rows)
         p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
                          precisions=precs, max_rhs=1)

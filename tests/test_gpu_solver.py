@@ -236,30 +236,43 @@ def test_small_sphere_solution_matches_mie_series():
 
 def test_large_sphere_mixed_precision_solve_matches_mie_series():
     """cfg 4: the radius-6 sphere (327,680 triangles, 256^3 grid): complex64
-    matvecs inside complex128 refinement with the static diagonal, to 1e-6
-    relative residual (the library's complex128 residual, checked again with
-    a fresh complex128 matvec); the exterior field at r = 2a against the
-    sphere series (ka = 12 pi, a zero of j_0; the undetermined l = 0 density
-    does not radiate)."""
-    from oracle import mie
+    matvecs inside complex128 refinement with the static diagonal, to the
+    1e-9 relative residual target (which passes through 1e-6).  The
+    residual is checked three ways: the library's own complex128 residual, a
+    fresh complex128 matvec, and the oracle's rows of b - A x on 64 sampled
+    rows (independent of the library).  The exterior field at r = 2a is
+    compared with the sphere series (ka = 12 pi, a zero of j_0; the
+    undetermined l = 0 density does not radiate)."""
+    from oracle import aimx, mie
     w = I.sphere_large()
     print(f"[gpu] sphere-{w.n}: setting up", flush=True)
     p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
                      max_rhs=1)
     k = float(w.k[0])
     b = p.excitation("plane_wave", [0, 0, 1])
-    x, res = p.solve(b, rtol=1e-6, restart=60, pc="diag", inner="c64", max_iter=6000,
+    x, res = p.solve(b, rtol=1e-9, restart=60, pc="diag", inner="c64", max_iter=12000,
                      max_refine=20)
     print(f"[gpu] sphere-{w.n}: iters {res.iters[0]}, refinements {res.refinements[0]}, "
           f"residual {res.rel_resid[0]:.2e}, {res.seconds:.2f} s", flush=True)
-    assert res.converged[0] and res.rel_resid[0] <= 1e-6
+    assert res.converged[0] and res.rel_resid[0] <= 1e-9
     r = b - p.matvec(x)
-    assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1.05e-6
+    rr = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    assert rr <= 1.05e-9
+    xh, bh = host(x)[0], host(b)[0]
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    rows = np.sort(np.random.default_rng(4409).choice(o.N, 64, replace=False))
+    ro = bh[rows] - o.matvec_rows(xh, k, rows)
+    # rows of a residual of relative norm <= 1e-9: the sampled part is of
+    # the same size relative to the sampled b (a factor 10 of slack)
+    samp = float(np.linalg.norm(ro) / np.linalg.norm(bh[rows]))
+    print(f"    residual: library {res.rel_resid[0]:.2e}, fresh matvec {rr:.2e}, "
+          f"oracle rows {samp:.2e}", flush=True)
+    assert samp <= 1e-8
     a = 6.0
     th = np.linspace(0.15, math.pi - 0.15, 7)
     pts = np.stack([np.sin(th), 0 * th, np.cos(th)], 1) * (2 * a)
     ue = mie.exterior_field_plane_wave(k, a, 2 * a, np.cos(th))
-    u = exterior_field(w.vertices, w.triangles, host(x)[0], k, pts)
+    u = exterior_field(w.vertices, w.triangles, xh, k, pts)
     err = np.linalg.norm(u - ue) / np.linalg.norm(ue)
     print(f"    exterior field vs Mie {err:.2e}", flush=True)
     assert err < 3e-2

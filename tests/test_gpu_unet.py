@@ -137,3 +137,44 @@ def test_training_reduces_loss_and_weights_roundtrip(tmp_path):
     assert torch.equal(net.forward(X), net2.forward(X))
     net.close()
     net2.close()
+
+
+def test_64cubed_forward_and_gradients_match_reference():
+    """One 64^3 grid, the size the benchmark's U-Net leg times.  At this size
+    the full-resolution layers with 16 output channels give at least 1,024
+    four-row bricks, so the four-row ("tall") convolution variants run, for
+    the forward pass and for the data gradients, together with the weight
+    gradient kernels of every layer at this size.  The calls are the ones
+    the benchmark makes (forward of one grid; a training step of one grid),
+    so every kernel variant it times is compared here with the oracle."""
+    net = binding.UNet(seed=31)
+    rng = np.random.default_rng(32)
+    flat = net.params()
+    off = 0
+    for W, b in binding.unet_params_to_layers(flat):
+        off += W.size
+        flat[off:off + b.size] = 0.05 * rng.standard_normal(b.size)
+        off += b.size
+    net.set_params(flat)
+    layers = binding.unet_params_to_layers(flat)
+    shape = (64, 64, 64)
+    x = grid_c64(shape, 33)
+    t = grid_c64(shape, 34)
+    print(f"[gpu] unet 64^3 forward + gradients", flush=True)
+    out = net.forward(to_dev(x)).cpu().numpy()
+    out = np.stack([out.real, out.imag], axis=-1)
+    r = ref.UNet(layers, bf16=True)
+    want = r.forward(x.astype(np.float64))
+    err = rel(out, want)
+    print(f"    forward rel err {err:.2e}", flush=True)
+    assert err <= 1e-2
+    loss = net.train_grid(to_dev(x), to_dev(t), apply=False)
+    g = binding.unet_params_to_layers(net.grads())
+    want_loss = r.loss(x.astype(np.float64), t.astype(np.float64))
+    gw = r.backward(t.astype(np.float64))
+    assert loss == pytest.approx(want_loss, rel=1e-2)
+    for i, ((dW, db), (rW, rb)) in enumerate(zip(g, gw)):
+        e_w, e_b = rel(dW, rW), rel(db, rb)
+        print(f"    layer {i}: dW {e_w:.2e} db {e_b:.2e}", flush=True)
+        assert e_w <= 3e-2 and e_b <= 3e-2, i
+    net.close()
