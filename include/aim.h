@@ -313,7 +313,7 @@ aim_status aim_graph_destroy(aim_graph graph);  /* NULL is a no-op */
  * which keeps the strided z lines from falling on one memory channel), then
  * the interpolation mode (0: the assembled P^T; 1: the weights of P^T
  * recomputed from the quadrature points' stencil coordinates). */
-#define AIM_FFT_SHAPES 8
+#define AIM_FFT_SHAPES 12
 #define AIM_FFT_LAYOUTS 4
 #define AIM_SCHEDULE_LEN 7
 

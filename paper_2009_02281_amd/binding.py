@@ -22,7 +22,7 @@ STATUS = {0: "AIM_OK", 1: "AIM_ERR_INVALID_ARG", 2: "AIM_ERR_GEOMETRY", 3: "AIM_
 PREC = {"c128": 0, "c64": 1}
 PC = {"none": 0, "diag": 1, "nearblock": 2, "unet": 3}
 LOSS = {"error": 0, "residual": 1}
-FFT_SHAPES = 8          # AIM_FFT_SHAPES
+FFT_SHAPES = 12         # AIM_FFT_SHAPES
 FFT_LAYOUTS = 4         # AIM_FFT_LAYOUTS
 SCHEDULE_LEN = 7        # AIM_SCHEDULE_LEN: five pass shapes, the layout, the interpolation mode
 STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc": 4}

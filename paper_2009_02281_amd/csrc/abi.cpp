@@ -747,10 +747,6 @@ aim_status aim_profile_matvec(aim_plan p, aim_precision prec, const void* x, voi
   });
 }
 
-// the five FFT passes: (length index into g.M, column pass?)
-static const int kPassAxis[5] = {0, 1, 2, 1, 0};
-static const bool kPassCol[5] = {false, true, true, true, false};
-
 aim_status aim_set_schedule(aim_plan p, aim_precision prec, const int32_t* sched) {
   if (!p || !sched) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
@@ -758,8 +754,7 @@ aim_status aim_set_schedule(aim_plan p, aim_precision prec, const int32_t* sched
     check_prec(p, prec);
     for (int k = 0; k < 5; ++k)
       AIM_REQUIRE(sched[k] >= 0 && sched[k] < aim::kFftVariants &&
-                      aim::fft_variant_ok(prec == AIM_C128, p->g.M[kPassAxis[k]], kPassCol[k],
-                                          sched[k]),
+                      aim::fft_variant_ok(prec == AIM_C128, p->g, k, sched[k]),
                   AIM_ERR_INVALID_ARG, "launch shape not available for this pass");
     AIM_REQUIRE(sched[5] >= 0 && sched[5] < aim::kLayouts, AIM_ERR_INVALID_ARG,
                 "workspace layout out of range");
@@ -783,11 +778,24 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
     const bool dbl = prec == AIM_C128;
     const size_t cb = dbl ? 16 : 8;
     void* grid = p->d_grid[pi];
-    AIM_HIP(hipMemsetAsync(grid, 0, size_t(p->g.Ng) * cb * nrhs, s));
+    // a pseudo-random input grid (timings on zeros run at a higher clock),
+    // convolved into a buffer of its own so that every timed pass sees the
+    // same values
+    aim::launch_pattern(grid, p->g.Ng * nrhs, dbl, s);
+    void* phi = nullptr;
+    {
+      const hipError_t e = hipMalloc(&phi, size_t(p->g.Ng) * cb * nrhs);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw aim::Error(AIM_ERR_OOM, "autotune: no memory for the output grid");
+      }
+    }
     std::vector<hipEvent_t> ev(6 * size_t(reps), nullptr);
     auto destroy = [&] {
       for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(phi);
     };
     double best[5], lbest[5];
     int pick[aim::kSchedLen], lpick[5];
@@ -805,7 +813,7 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
           int sch[aim::kSchedLen];
           bool any = false;
           for (int k = 0; k < 5; ++k) {
-            const bool ok = aim::fft_variant_ok(dbl, p->g.M[kPassAxis[k]], kPassCol[k], v);
+            const bool ok = aim::fft_variant_ok(dbl, p->g, k, v);
             sch[k] = ok ? v : 0;
             any = any || ok;
           }
@@ -816,10 +824,10 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
             hipEvent_t* e = &ev[6 * size_t(std::max(r, 0))];
             if (r >= 0) AIM_HIP(hipEventRecord(e[0], s));
             if (dbl)
-              aim::launch_convolve<double>(p->g, grid, p->d_work[pi], grid, p->d_spec64, df, nrhs,
+              aim::launch_convolve<double>(p->g, grid, p->d_work[pi], phi, p->d_spec64, df, nrhs,
                                            p->d_tw64, s, r >= 0 ? e + 1 : nullptr, sch);
             else
-              aim::launch_convolve<float>(p->g, grid, p->d_work[pi], grid, p->d_spec32, df, nrhs,
+              aim::launch_convolve<float>(p->g, grid, p->d_work[pi], phi, p->d_spec32, df, nrhs,
                                           p->d_tw32, s, r >= 0 ? e + 1 : nullptr, sch);
             if (r >= 0) AIM_HIP(hipEventRecord(e[5], s));
           }
@@ -864,7 +872,7 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
       hipEvent_t e0 = nullptr, e1 = nullptr;
       double tm[2] = {0.0, 0.0};
       try {
-        AIM_HIP(hipMemsetAsync(xy, 0, 2 * vb, s));
+        aim::launch_pattern(xy, p->t.N * nrhs, dbl, s);
         AIM_HIP(hipEventCreate(&e0));
         AIM_HIP(hipEventCreate(&e1));
         // three rounds alternating the modes, best time of each: one round
@@ -2053,8 +2061,7 @@ std::unique_ptr<aim_plan_s> read_plan(const char* path) {
   for (int pi = 0; pi < 2; ++pi) {
     for (int k = 0; k < 5; ++k)
       AIM_REQUIRE(p->sched[pi][k] >= 0 && p->sched[pi][k] < aim::kFftVariants &&
-                      aim::fft_variant_ok(pi == 0, p->g.M[kPassAxis[k]], kPassCol[k],
-                                          p->sched[pi][k]),
+                      aim::fft_variant_ok(pi == 0, p->g, k, p->sched[pi][k]),
                   AIM_ERR_INVALID_ARG, "plan file: bad schedule");
     AIM_REQUIRE(p->sched[pi][5] >= 0 && p->sched[pi][5] < aim::kLayouts &&
                     (p->sched[pi][6] == 0 || p->sched[pi][6] == 1),

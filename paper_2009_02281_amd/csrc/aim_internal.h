@@ -111,6 +111,9 @@ void launch_project(const GridShape& g, const CsrDevice& P, const int32_t* blk, 
 // sched[5] selects the launch shape of the x-forward, y-forward, z, y-inverse
 // and x-inverse passes (NULL: shape 0 everywhere).
 constexpr int kFftVariants = AIM_FFT_SHAPES;
+// shapes below this serve every pass (one set of lines per workgroup); the
+// rest are persistent shapes of the fused z pass
+constexpr int kFftShapesPerLine = 8;
 // schedule = launch shape of each of the five FFT passes, the work layout,
 // and the interpolation mode (0: assembled P^T, 1: recomputed weights)
 constexpr int kSchedLen = 7;
@@ -125,8 +128,9 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
                      hipEvent_t* between = nullptr,  // 4 events recorded between passes
                      const int* sched = nullptr,
                      int repeat = 1);  // each pass launched this many times (timing only)
-// whether launch shape v exists for an FFT pass of length L
-bool fft_variant_ok(bool dbl, int L, bool col, int v);
+// whether launch shape v exists for FFT pass `pass` (0 x forward, 1 y
+// forward, 2 fused z, 3 y inverse, 4 x inverse) of the grid g
+bool fft_variant_ok(bool dbl, const GridShape& g, int pass, int v);
 
 // y = P^T phi + C x: rows of P^T (by triangle) and of C, one group of lanes
 // per triangle
@@ -241,6 +245,9 @@ void launch_resid_grad(const void* y, const double* area, double coef, void* d, 
                        hipStream_t st);
 // zero n 8-byte words
 void launch_zero_words(void* p, int64_t n, hipStream_t st);
+// n complex values (complex128 if dbl, else complex64) of a fixed pseudo-random
+// pattern, modulus <= 1 (timing input)
+void launch_pattern(void* p, int64_t n, bool dbl, hipStream_t st);
 // e = xs - e (one vector)
 void launch_pair_error(const void* xs, void* e, int64_t n, hipStream_t st);
 // nb samples of D x H x W, stored one after another (stacked along z)

@@ -16,6 +16,7 @@
 //                  rows of the real CSR near-field correction, one pass over y.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -576,7 +577,228 @@ bool fft_shape_ok(int L, bool col, int v) {
   }
 }
 
-bool fft_variant_ok(bool dbl, int L, bool col, int v) {
+// ---------------------------------------------------------------------------
+// Fused z pass, persistent and software-pipelined (z-pass shapes 8 and up).
+// A set is TL adjacent z lines (kx .. kx+TL-1 of one row ky).  Each workgroup
+// walks a strided list of sets and, while it transforms one set, has the
+// loads of the next one in flight, so the memory pipe keeps streaming during
+// the butterflies and LDS exchanges (a workgroup of the one-set-per-launch
+// kernel above leaves it idle for that time).  The twiddle table is loaded
+// once per workgroup, after the first set's loads are issued.  The pass
+// length L = Mz = 2 Nz is fixed at compile time: the forward transform reads
+// only z < L/2 (the rest is the zero padding) and the inverse stores only
+// z < L/2.  Sets are dealt to XCDs in contiguous runs, rows in the order 0,
+// 1, My-1, 2, My-2, ... so that rows sharing a folded spectrum plane run on
+// the same XCD (as in the kernel above).
+// ---------------------------------------------------------------------------
+struct ZconvArgs {
+  int64_t es;  // element stride along z (plane pitch of the work grid)
+  int64_t bs;  // per right-hand-side stride of the work grid
+  const void* spec;
+  int64_t spec_fs;  // per-frequency stride of the folded spectrum
+  const int32_t* rhs_freq;
+  int Mx, Nx, My, Ny, Nz;
+  int nsets;  // Mx My / TL
+};
+
+template <typename T, int L, int TL, int NT, int RMAX>
+__global__ __launch_bounds__(TL* NT) void zconv_kernel(cx<T>* B, const cx<T>* __restrict__ twg,
+                                                       ZconvArgs a) {
+  constexpr int E = L / NT, NTH = TL * NT;
+  static_assert(RMAX <= E, "a thread must hold a whole butterfly");
+  __shared__ cx<T> s[L * TL];
+  __shared__ cx<T> tw[L];
+  const int tid = threadIdx.x;
+  const int l = tid & (TL - 1), t = tid / TL;
+  B += int64_t(blockIdx.y) * a.bs;
+  const cx<T>* spec =
+      static_cast<const cx<T>*>(a.spec) + int64_t(a.rhs_freq[blockIdx.y]) * a.spec_fs;
+  // sets first, first + step, ... below last
+  const int G = int(gridDim.x), b = int(blockIdx.x);
+  int first = b, step = G, last = a.nsets;
+  if (G % 8 == 0 && a.nsets % 8 == 0) {
+    const int per = a.nsets / 8;
+    first = (b % 8) * per + b / 8;
+    step = G / 8;
+    last = (b % 8 + 1) * per;
+  }
+  const int nbx = a.Mx / TL, hy = a.My / 2;
+  auto row_of = [&](int si) {
+    const int rowpos = si / nbx;
+    return rowpos == 0 ? 0
+         : rowpos == a.My - 1 ? hy
+         : (rowpos & 1) ? (rowpos + 1) / 2 : a.My - rowpos / 2;
+  };
+  auto col_of = [&](int si) { return (si % nbx) * TL + l; };
+  // first forward stage: radix R0 over elements t + i NT + r L/R0; those
+  // with r >= R0/2 lie in the zero padding
+  using Fw = Sched<L, true, RMAX>;
+  using Iv = Sched<L, false, RMAX>;
+  constexpr int R0 = Fw::radix(0), NB0 = L / (R0 * NT), RH = R0 / 2;
+  constexpr int RM = Fw::radix(Fw::NST - 1);
+  static_assert(RM == Iv::radix(0),
+                "the forward transform must end with the radix the inverse starts with");
+  constexpr int Rf = Iv::radix(Iv::NST - 1), NBf = L / (Rf * NT);
+  cx<T> nx[NB0 * RH];
+  auto load = [&](int si) {
+    const cx<T>* src = B + int64_t(row_of(si)) * a.Mx + col_of(si);
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < RH; ++r) nx[i * RH + r] = src[int64_t(t + i * NT + r * (L / R0)) * a.es];
+  };
+  int si = first;
+  if (si < last) load(si);
+  for (int m = tid; m < L; m += NTH) tw[m] = twg[m];
+  __syncthreads();
+  cx<T>* sl = s + l;
+  for (; si < last; si += step) {
+    cx<T> v[E];
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[i * R0 + r] = r < RH ? nx[i * RH + r] : mkc<T>(T(0), T(0));
+    const int ky = row_of(si), kx = col_of(si);
+    // this set's spectrum values (needed after the forward transform), then
+    // the next set's loads: both in flight during the forward transform
+    cx<T> spv[E];
+    {
+      const int fx = kx <= a.Nx ? kx : a.Mx - kx;
+      const int fy = ky <= a.Ny ? ky : a.My - ky;
+      const cx<T>* sp = spec + int64_t(fy) * (a.Nz + 1) * (a.Nx + 1) + fx;
+      const int64_t zst = int64_t(a.Nx + 1);
+#pragma unroll
+      for (int i = 0; i < L / (RM * NT); ++i)
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+          const int e = t + i * NT + r * (L / RM);
+          const int fz = e <= a.Nz ? e : L - e;
+          spv[i * RM + r] = sp[fz * zst];
+        }
+    }
+    // (the last set reloads itself, unused: no branch, so the waits on these
+    // loads are counted exactly)
+    load(si + step < last ? si + step : si);
+    run_stages<T, L, NT, false, true, RMAX, 0>(v, sl, TL, t, tw);
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = cmul(v[k], spv[k]);
+    run_stages<T, L, NT, true, false, RMAX, 0>(v, sl, TL, t, tw);
+    cx<T>* dst = B + int64_t(ky) * a.Mx + kx;
+#pragma unroll
+    for (int i = 0; i < NBf; ++i)
+#pragma unroll
+      for (int r = 0; r < Rf / 2; ++r)
+        dst[int64_t(t + i * NT + r * (L / Rf)) * a.es] = v[i * Rf + r];
+  }
+}
+
+// z-pass shapes 8 .. 8 + kZconvShapes - 1 (lines per set TL, threads per
+// line NT, largest radix)
+template <typename T, int L, int V>
+struct ZShape {
+  static constexpr int kTL = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
+  // V 0: radix 8, 8 elements per thread where the 512-thread cap allows;
+  // V 1: radix 16, 256 threads; V 2: radix 16, 512 threads; V 3: radix 8,
+  // 256 threads (short lines: more lines per set, at most 64, so that a
+  // workgroup has at least one wave)
+  static constexpr int NT = V == 0 ? cmin(L / 8, 512 / kTL)
+                          : V == 1 ? cmax(1, L / 16)
+                          : V == 2 ? cmax(1, L / 16)
+                                   : cmin(L / 8, 256 / kTL);
+  static constexpr int TL = V == 1 ? cmin(64, cmax(kTL, 256 / NT))
+                          : V == 2 ? cmin(64, cmax(kTL, 512 / NT))
+                                   : cmin(64, cmax(kTL, 64 / NT));
+  static constexpr int RMAX = (V == 1 || V == 2) && L >= 16 ? 16 : 8;
+  static constexpr int THREADS = TL * NT;
+  static constexpr size_t LDS = sizeof(cx<T>) * (size_t(L) * TL + L);
+  static constexpr bool OK = L >= 16 && L / NT >= RMAX && THREADS >= 64 && THREADS <= 1024 &&
+                             LDS <= 160 * 1024;
+};
+
+template <typename T, int L, int V>
+void launch_zshape(cx<T>* B, const cx<T>* w, ZconvArgs a, int nrhs, hipStream_t s) {
+  using S = ZShape<T, L, V>;
+  if constexpr (!S::OK) {
+    throw Error(AIM_ERR_INVALID_ARG, "z-pass shape not available for this length");
+  } else {
+    AIM_REQUIRE(a.Mx % S::TL == 0 && a.My % 2 == 0, AIM_ERR_INVALID_ARG,
+                "z-pass shape needs the padded x length to be a multiple of its lines per set");
+    a.nsets = int(int64_t(a.Mx) * a.My / S::TL);
+    auto kern = zconv_kernel<T, L, S::TL, S::NT, S::RMAX>;
+    // one wave of workgroups: as many as can be resident on the device
+    static int resident = 0;
+    if (resident == 0) {
+      int dev = 0, ncu = 0, per = 0;
+      AIM_HIP(hipGetDevice(&dev));
+      AIM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      AIM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, S::THREADS, 0));
+      resident = std::max(8, (ncu * std::max(per, 1)) / 8 * 8);
+    }
+    const int G = std::min(resident, a.nsets);
+    hipLaunchKernelGGL(kern, dim3(unsigned(G), unsigned(nrhs)), dim3(S::THREADS), 0, s, B, w, a);
+  }
+}
+
+template <typename T, int L>
+void zconv_L(int v, cx<T>* B, const cx<T>* w, const ZconvArgs& a, int nrhs, hipStream_t s) {
+  switch (v) {
+    case 0: launch_zshape<T, L, 0>(B, w, a, nrhs, s); break;
+    case 1: launch_zshape<T, L, 1>(B, w, a, nrhs, s); break;
+    case 2: launch_zshape<T, L, 2>(B, w, a, nrhs, s); break;
+    case 3: launch_zshape<T, L, 3>(B, w, a, nrhs, s); break;
+    default: throw Error(AIM_ERR_INVALID_ARG, "z-pass shape out of range");
+  }
+}
+
+template <typename T>
+void zconv(int L, int v, void* B, const void* tw, const ZconvArgs& a, int nrhs, hipStream_t s) {
+  cx<T>* b = static_cast<cx<T>*>(B);
+  const cx<T>* w = static_cast<const cx<T>*>(tw);
+  switch (L) {
+    case 16: zconv_L<T, 16>(v, b, w, a, nrhs, s); break;
+    case 32: zconv_L<T, 32>(v, b, w, a, nrhs, s); break;
+    case 64: zconv_L<T, 64>(v, b, w, a, nrhs, s); break;
+    case 128: zconv_L<T, 128>(v, b, w, a, nrhs, s); break;
+    case 256: zconv_L<T, 256>(v, b, w, a, nrhs, s); break;
+    case 512: zconv_L<T, 512>(v, b, w, a, nrhs, s); break;
+    default: throw Error(AIM_ERR_GRID, "unsupported FFT length");
+  }
+  AIM_HIP(hipGetLastError());
+}
+
+template <typename T, int L>
+bool zshape_ok_L(int v, int Mx) {
+  switch (v) {
+    case 0: return ZShape<T, L, 0>::OK && Mx % ZShape<T, L, 0>::TL == 0;
+    case 1: return ZShape<T, L, 1>::OK && Mx % ZShape<T, L, 1>::TL == 0;
+    case 2: return ZShape<T, L, 2>::OK && Mx % ZShape<T, L, 2>::TL == 0;
+    case 3: return ZShape<T, L, 3>::OK && Mx % ZShape<T, L, 3>::TL == 0;
+    default: return false;
+  }
+}
+
+template <typename T>
+bool zshape_ok(int L, int v, int Mx) {
+  switch (L) {
+    case 16: return zshape_ok_L<T, 16>(v, Mx);
+    case 32: return zshape_ok_L<T, 32>(v, Mx);
+    case 64: return zshape_ok_L<T, 64>(v, Mx);
+    case 128: return zshape_ok_L<T, 128>(v, Mx);
+    case 256: return zshape_ok_L<T, 256>(v, Mx);
+    case 512: return zshape_ok_L<T, 512>(v, Mx);
+    default: return false;
+  }
+}
+
+bool fft_variant_ok(bool dbl, const GridShape& g, int pass, int v) {
+  static const int axis[5] = {0, 1, 2, 1, 0};
+  const int L = g.M[axis[pass]];
+  if (v >= kFftShapesPerLine) {  // persistent shapes: the fused z pass only
+    if (pass != 2 || v >= kFftVariants) return false;
+    return dbl ? zshape_ok<double>(L, v - kFftShapesPerLine, g.M[0])
+               : zshape_ok<float>(L, v - kFftShapesPerLine, g.M[0]);
+  }
+  const bool col = pass >= 1 && pass <= 3;
   return dbl ? fft_shape_ok<double>(L, col, v) : fft_shape_ok<float>(L, col, v);
 }
 
@@ -669,7 +891,24 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     a.Ny = Ny;
     a.Mz = Mz;
     a.Nz = Nz;
-    for (int r = 0; r < repeat; ++r) fft_pass<T>(Mz, true, 2, B, B, tw[2], a, nrhs, s, sched[2]);
+    if (sched[2] >= kFftShapesPerLine) {
+      ZconvArgs z{};
+      z.es = PB;
+      z.bs = W;
+      z.spec = spec;
+      z.spec_fs = g.Nfold;
+      z.rhs_freq = rhs_freq;
+      z.Mx = Mx;
+      z.Nx = Nx;
+      z.My = My;
+      z.Ny = Ny;
+      z.Nz = Nz;
+      for (int r = 0; r < repeat; ++r)
+        zconv<T>(Mz, sched[2] - kFftShapesPerLine, B, tw[2], z, nrhs, s);
+    } else {
+      for (int r = 0; r < repeat; ++r)
+        fft_pass<T>(Mz, true, 2, B, B, tw[2], a, nrhs, s, sched[2]);
+    }
   }
   mark(2);
   // y inverse: B [Nz][My][Mx] -> A [Nz][Ny][Mx]
@@ -2111,6 +2350,33 @@ void launch_zero_words(void* p, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, st,
                      static_cast<uint2*>(p), n);
+  AIM_HIP(hipGetLastError());
+}
+
+// n complex values of modulus <= 1 from a hash of the index (timing input:
+// the clock under load depends on the data, and zeros flatter the kernels)
+template <typename T>
+__global__ void pattern_kernel(cx<T>* p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    uint64_t h = uint64_t(i) * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 32;
+    const T re = T(int32_t(uint32_t(h))) * T(3.3e-10);
+    const T im = T(int32_t(uint32_t(h >> 32))) * T(3.3e-10);
+    p[i] = mkc<T>(re, im);
+  }
+}
+
+void launch_pattern(void* p, int64_t n, bool dbl, hipStream_t st) {
+  if (n <= 0) return;
+  if (dbl)
+    hipLaunchKernelGGL(pattern_kernel<double>, dim3(grid_for(n, 1024)), dim3(256), 0, st,
+                       static_cast<double2*>(p), n);
+  else
+    hipLaunchKernelGGL(pattern_kernel<float>, dim3(grid_for(n, 1024)), dim3(256), 0, st,
+                       static_cast<float2*>(p), n);
   AIM_HIP(hipGetLastError());
 }
 
