@@ -250,6 +250,25 @@ aim_status aim_plan_query(aim_plan plan, aim_plan_info* info_host);
 aim_status aim_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
                       int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream);
 
+/* aim_matvec for callers that cannot allocate device memory during the call
+ * or at all after set-up (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same operator, arguments, kernels and
+ * results as aim_matvec; the projection grid and the convolution workspace
+ * live in a fixed device array of the library (AIM_STATIC_SCRATCH_BYTES =
+ * 64 MiB, held on each device that uses it until the process ends) instead
+ * of the plan's workspace.  The call allocates nothing; the first call on a
+ * device looks up that device's copy of the array.  Nothing in the array
+ * needs clearing (every element is written before it is read).  All calls on
+ * one device share the array: calls that overlap in time on one device (two
+ * streams, two threads, two plans) race and give undefined results.  Not for
+ * batch plans (AIM_ERR_STATE).  Errors as aim_matvec, plus
+ * AIM_ERR_INVALID_ARG when nrhs vectors need more than the array holds:
+ * 16 (complex128) or 8 (complex64) bytes per vector times (Ng + the
+ * workspace, about 6 Ng), e.g. at most 2 complex128 vectors on a 64^3 grid. */
+#define AIM_STATIC_SCRATCH_BYTES (64u << 20)
+aim_status aim_matvec_static(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
+                             int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream);
+
 /* One stage of the matvec, for stage-level checks (see aim_stage for the
  * shapes).  Same rules as aim_matvec; grids are unpadded [nrhs][Nz][Ny][Nx]. */
 aim_status aim_apply_stage(aim_plan plan, aim_precision prec, aim_stage stage,

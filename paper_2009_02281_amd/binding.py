@@ -28,7 +28,8 @@ SCHEDULE_LEN = 7        # AIM_SCHEDULE_LEN: five pass shapes, the layout, the in
 STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc": 4}
 RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
-EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec", "aim_apply_stage",
+EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec",
+            "aim_matvec_static", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
             "aim_autotune", "aim_set_schedule", "aim_matvec_capture", "aim_graph_launch",
             "aim_graph_destroy", "aim_unet_create", "aim_unet_destroy", "aim_unet_num_params",
@@ -110,6 +111,7 @@ def load_library(path: str = LIB_PATH):
     lib.aim_destroy.argtypes = [vp]
     lib.aim_plan_query.argtypes = [vp, C.POINTER(PlanInfo)]
     lib.aim_matvec.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
+    lib.aim_matvec_static.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
     lib.aim_apply_stage.argtypes = [vp, i32, i32, vp, vp, i32, ip32, vp]
     lib.aim_excitation.argtypes = [vp, i32, C.POINTER(C.c_double), i32, i32, ip32, vp, vp]
     lib.aim_solve.argtypes = [vp, vp, vp, i32, ip32, C.POINTER(SolveOpts),
@@ -497,6 +499,20 @@ class Plan:
         _, fp = _freq_arg(freq_idx, nrhs)
         _check(self._lib.aim_matvec(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
                                     C.c_void_p(y.data_ptr()), nrhs, fp, _stream_ptr(stream)))
+        return y
+
+    def matvec_static(self, x, freq_idx=None, prec: str = "c128", out=None, stream=None):
+        """y = A(k_f) x through aim_matvec_static (no allocation in the call:
+        scratch in the library's fixed device array)."""
+        import torch
+        self._check_vec(x, prec, self.n, "x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        self._check_vec(y, prec, self.n, "out")
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_matvec_static(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
+                                           C.c_void_p(y.data_ptr()), nrhs, fp,
+                                           _stream_ptr(stream)))
         return y
 
     def profile_matvec(self, x, reps: int = 10, freq_idx=None, prec: str = "c128", out=None,

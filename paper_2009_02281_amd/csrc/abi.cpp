@@ -307,18 +307,22 @@ const int32_t* set_freq(aim_plan p, const int32_t* freq_host, int nrhs, hipStrea
 // ev[0..7] are recorded before, between and after the seven kernels.
 // With repeat > 1 (timing only) every kernel is launched `repeat` times in a
 // row, which leaves garbage in the workspace and y.
+// grid and work (both null: the plan's own) hold the projection grid and
+// the convolution workspace of nrhs vectors.
 template <typename T>
 void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
-                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev, int repeat = 1) {
+                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev, int repeat = 1,
+                 void* grid = nullptr, void* work = nullptr) {
   const int pi = int(prec);
-  void* grid = p->d_grid[pi];
+  if (!grid) grid = p->d_grid[pi];
+  if (!work) work = p->d_work[pi];
   const void* spec = prec == AIM_C128 ? p->d_spec64 : p->d_spec32;
   void* const* tw = prec == AIM_C128 ? p->d_tw64 : p->d_tw32;
   if (ev) AIM_HIP(hipEventRecord(ev[0], s));
   for (int r = 0; r < repeat; ++r)
     aim::launch_project<T>(p->g, p_dev(p, prec), p->d_pblk, p->nblk, x, p->t.N, grid, nrhs, s);
   if (ev) AIM_HIP(hipEventRecord(ev[1], s));
-  aim::launch_convolve<T>(p->g, grid, p->d_work[pi], grid, spec, dfreq, nrhs, tw, s,
+  aim::launch_convolve<T>(p->g, grid, work, grid, spec, dfreq, nrhs, tw, s,
                           ev ? ev + 2 : nullptr, p->sched[pi], repeat);
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
   for (int r = 0; r < repeat; ++r) interp_near<T>(p, prec, grid, x, y, nrhs, true, true, s);
@@ -703,6 +707,39 @@ aim_status aim_matvec(aim_plan p, aim_precision prec, const void* x, void* y, in
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
     matvec_any(p, prec, x, y, nrhs, df, s);
+  });
+}
+
+aim_status aim_matvec_static(aim_plan p, aim_precision prec, const void* x, void* y,
+                             int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream) {
+  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    no_batch(p);
+    check_prec(p, prec);
+    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+    AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+                "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+    // the projection grid, then the convolution workspace in the plan's
+    // layout, each starting on a 256-byte boundary
+    const int pi = int(prec);
+    const size_t cb = prec == AIM_C128 ? 16 : 8;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t grid_b = up(size_t(p->g.Ng) * cb * nrhs);
+    const size_t work_b = up(size_t(aim::work_elems(p->g, p->sched[pi][5], cb)) * cb * nrhs);
+    AIM_REQUIRE(grid_b + work_b <= aim::kStaticScratchBytes, AIM_ERR_INVALID_ARG,
+                "aim_matvec_static: " + std::to_string(nrhs) + " vectors on this grid need " +
+                    std::to_string(grid_b + work_b) + " bytes of scratch; the limit is " +
+                    std::to_string(aim::kStaticScratchBytes) + " (use aim_matvec)");
+    char* base = static_cast<char*>(aim::static_scratch());
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    // every scratch element is written before it is read (the projection
+    // writes all grid nodes, each FFT pass every element the next one
+    // reads), so nothing is cleared
+    if (prec == AIM_C128)
+      matvec_impl<double>(p, prec, x, y, nrhs, df, s, nullptr, 1, base, base + grid_b);
+    else
+      matvec_impl<float>(p, prec, x, y, nrhs, df, s, nullptr, 1, base, base + grid_b);
   });
 }
 

@@ -245,6 +245,11 @@ void launch_resid_grad(const void* y, const double* area, double coef, void* d, 
                        hipStream_t st);
 // zero n 8-byte words
 void launch_zero_words(void* p, int64_t n, hipStream_t st);
+// bytes of the fixed device array behind the no-allocation matvec
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+// device address of that array on the current device (looked up once per
+// device with it current); throws on failure
+void* static_scratch();
 // n complex values (complex128 if dbl, else complex64) of a fixed pseudo-random
 // pattern, modulus <= 1 (timing input)
 void launch_pattern(void* p, int64_t n, bool dbl, hipStream_t st);

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "aim_internal.h"
@@ -2351,6 +2352,33 @@ void launch_zero_words(void* p, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, st,
                      static_cast<uint2*>(p), n);
   AIM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch for the matvec variant that allocates nothing: the
+// projection grid and the convolution workspace of one call.  The array is
+// part of the code object, so each device that loads the library holds its
+// own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (the array's
+// name in host code is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+void* static_scratch() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  AIM_HIP(hipGetDevice(&dev));
+  AIM_REQUIRE(dev >= 0 && dev < kMaxDevices, AIM_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    AIM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    AIM_REQUIRE(ptr != nullptr, AIM_ERR_DEVICE, "no device address for the static scratch");
+    addr[dev] = ptr;
+  }
+  return addr[dev];
 }
 
 // n complex values of modulus <= 1 from a hash of the index (timing input:
