@@ -130,6 +130,9 @@ typedef struct {
   int64_t device_bytes;      /* device memory held by the plan                    */
   int32_t n_clusters;        /* near-block preconditioner clusters                */
   int32_t max_cluster;       /* largest cluster                                    */
+  double near_seconds;       /* part of set-up spent on A_s,NR and C               */
+  int32_t near_on_device;    /* 1: A_s,NR and C were computed on the device        */
+  int32_t reserved;
 } aim_plan_info;
 
 /* Solver options (aim_solve).  rtol is the relative residual
@@ -178,12 +181,16 @@ typedef struct {
 } aim_solve_info;
 
 /* Build a plan: validates the mesh and grid on the host (before any device
- * call), computes quadrature points (3-point rule), stencils, the near list,
- * the static near-field matrix by closed-form integration of 1/R (Sec. III-A,
- * change (a) of the AIMx recipe) and its precorrection, uploads the tables
- * and computes one kernel spectrum per wavenumber on the device.
+ * call), computes quadrature points (3-point rule), stencils and the near
+ * list on the host, then the static near-field matrix by closed-form
+ * integration of 1/R (Sec. III-A, change (a) of the AIMx recipe) and its
+ * precorrection on the device (one thread per near pair; the one-time
+ * static fill of Sec. VI), uploads the tables and computes one kernel
+ * spectrum per wavenumber on the device.
  * Errors: AIM_ERR_INVALID_ARG, AIM_ERR_GEOMETRY, AIM_ERR_GRID, AIM_ERR_OOM,
- * AIM_ERR_DEVICE.  Blocking. */
+ * AIM_ERR_DEVICE.  A singular near-field preconditioner block (degenerate
+ * geometry) is reported as AIM_ERR_GEOMETRY after the device fill.
+ * Blocking. */
 aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out);
 
 /* Host-only variant of aim_setup: builds and validates every

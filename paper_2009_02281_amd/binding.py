@@ -73,6 +73,7 @@ class PlanInfo(C.Structure):
         ("origin", C.c_double * 3), ("setup_seconds", C.c_double),
         ("spectra_seconds", C.c_double), ("device_bytes", C.c_int64),
         ("n_clusters", C.c_int32), ("max_cluster", C.c_int32),
+        ("near_seconds", C.c_double), ("near_on_device", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -455,7 +456,8 @@ class Plan:
             "precisions": pi.precisions, "h": pi.h, "origin": list(pi.origin),
             "setup_seconds": pi.setup_seconds, "spectra_seconds": pi.spectra_seconds,
             "device_bytes": pi.device_bytes, "n_clusters": pi.n_clusters,
-            "max_cluster": pi.max_cluster,
+            "max_cluster": pi.max_cluster, "near_seconds": pi.near_seconds,
+            "near_on_device": bool(pi.near_on_device),
         }
 
     def export_tables(self) -> dict:

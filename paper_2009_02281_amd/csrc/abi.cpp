@@ -106,6 +106,7 @@ struct aim_plan_s {
   int32_t* d_ptcol = nullptr;
   double* d_ptval64 = nullptr;
   float* d_ptval32 = nullptr;
+  bool near_on_device = false;  // A_s,NR and C computed by the device fill
   int32_t* d_rowptr = nullptr;
   int32_t* d_col = nullptr;
   double* d_val64 = nullptr;
@@ -455,6 +456,19 @@ aim_status aim_setup_host(const aim_setup_desc* desc, aim_plan* out) {
 }
 
 namespace {
+// The static near entries and C on the device (copied back into the host
+// tables), then the preconditioner's cluster inverses from them.
+void fill_near_device(aim_plan_s* p, const aim_setup_desc& d, hipStream_t s) {
+  const double t0 = now_s();
+  {
+    aim::NearDevice nd(p->t, d.vertices, d.triangles, d.alloc, d.free, d.alloc_ctx, s);
+    nd.fill_static(p->t.near_static, p->t.corr, s);
+  }
+  p->t.near_seconds = now_s() - t0;
+  p->near_on_device = true;
+  aim::build_cluster_inverses(p->t, aim::setup_threads(d));
+}
+
 // Everything after the host tables: grid shape, uploads, workspace, spectra.
 // Shared by aim_setup and aim_plan_load.
 void init_device(aim_plan_s* p, hipStream_t hip_stream) {
@@ -583,7 +597,7 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
     validate_desc(d);
     const double t0 = now_s();
     // host work first: every validation happens before any device call
-    aim::build_host_tables(d, p->t);
+    aim::build_host_tables(d, p->t, false);
     p->nfreq = d.n_freq;
     p->k.assign(d.k, d.k + d.n_freq);
     p->prec = d.precisions;
@@ -591,6 +605,7 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
     p->alloc = d.alloc;
     p->free_fn = d.free;
     p->actx = d.alloc_ctx;
+    fill_near_device(p.get(), d, static_cast<hipStream_t>(hip_stream));
     init_device(p.get(), static_cast<hipStream_t>(hip_stream));
     p->t.setup_seconds = now_s() - t0;
   });
@@ -618,7 +633,7 @@ aim_status aim_setup_batch(const aim_setup_desc* descs, int32_t n, void* hip_str
     for (int i = 0; i < n; ++i) {
       std::unique_ptr<aim_plan_s> q(new aim_plan_s());
       const aim_setup_desc& d = descs[i];
-      aim::build_host_tables(d, q->t);
+      aim::build_host_tables(d, q->t, false);
       q->nfreq = d.n_freq;
       q->k.assign(d.k, d.k + d.n_freq);
       q->prec = d.precisions;
@@ -639,7 +654,9 @@ aim_status aim_setup_batch(const aim_setup_desc* descs, int32_t n, void* hip_str
     b->nfreq = 1 << 30;
     b->t.N = 0;
     b->t.order = descs[0].stencil_order;
-    for (auto& q : b->inst) {
+    for (int i = 0; i < n; ++i) {
+      auto& q = b->inst[size_t(i)];
+      fill_near_device(q.get(), descs[i], s);
       init_device(q.get(), s);
       b->t.N = std::max(b->t.N, q->t.N);
       b->prec &= q->prec;
@@ -695,6 +712,9 @@ aim_status aim_plan_query(aim_plan p, aim_plan_info* info) {
     o.device_bytes = p->device_bytes;
     o.n_clusters = p->ncl;
     o.max_cluster = p->maxcl;
+    o.near_seconds = p->t.near_seconds;
+    o.near_on_device = p->near_on_device ? 1 : 0;
+    o.reserved = 0;
   });
 }
 

@@ -69,10 +69,21 @@ struct HostTables {
   std::vector<int64_t> cl_blk;      // [ncl+1] offsets into cl_inv
   std::vector<double> cl_inv;       // dense inverse blocks, row-major
   double setup_seconds = 0.0;
+  double near_seconds = 0.0;        // the static near fill (host or device)
 };
 
-// Builds every host table; throws aim::Error on invalid input.
-void build_host_tables(const aim_setup_desc& d, HostTables& t);
+// Builds every host table; throws aim::Error on invalid input.  With
+// near_on_host false the static near entries, C and the cluster inverses
+// are left out (every validation still happens here): the caller fills
+// near_static and corr (on the device) and then calls
+// build_cluster_inverses.
+void build_host_tables(const aim_setup_desc& d, HostTables& t, bool near_on_host = true);
+// A_s,NR and C on the near list, on the host
+void fill_near_host(HostTables& t, const double* V, const int32_t* T, int nthreads);
+// dense inverses of A_s,NR over the preconditioner clusters
+void build_cluster_inverses(HostTables& t, int nthreads);
+// host threads for set-up (the descriptor's n_threads, else all cores)
+int setup_threads(const aim_setup_desc& d);
 
 // Closed-form integral of 1/|r - r'| over the triangle (a, b, c).
 double triangle_inv_r(const double r[3], const double a[3], const double b[3],
@@ -261,6 +272,39 @@ void unet_forward(aim_unet u, const void* in, int nb, int D, int H, int W, void*
 void unet_backward(aim_unet u, const void* in, const void* dout, hipStream_t s);
 void unet_zero_grad(aim_unet u, hipStream_t s);
 void unet_adam(aim_unet u, double lr, hipStream_t s);
+
+// Near-field tables on the device (nearfield.hip).  Uploads the geometry and
+// the near list once; fills the static near entries A_s,NR and the AIMx
+// correction C = A_s,NR - A_s,P (copied back to the host), and, per
+// wavenumber, the complex correction A_NR(k) - A_P(k) of the conventional
+// AIM into a caller's device buffer of nnz complex128 values.
+class NearDevice {
+ public:
+  NearDevice(const HostTables& t, const double* V, const int32_t* T, aim_alloc_fn alloc,
+             aim_free_fn free_fn, void* ctx, hipStream_t s);
+  ~NearDevice();
+  NearDevice(const NearDevice&) = delete;
+  NearDevice& operator=(const NearDevice&) = delete;
+  void fill_static(std::vector<double>& near_static, std::vector<double>& corr, hipStream_t s);
+  void set_static(const std::vector<double>& near_static, hipStream_t s);
+  void fill_conventional(double k, void* out_dev, hipStream_t s);
+  int64_t nnz() const { return nnz_; }
+
+ private:
+  void* get(size_t bytes);
+  void release();
+  int64_t N_, nnz_;
+  int order_;
+  double h_;
+  aim_alloc_fn alloc_;
+  aim_free_fn free_;
+  void* ctx_;
+  hipStream_t stream_;
+  std::vector<void*> bufs_;
+  void *tri_ = nullptr, *qp_ = nullptr, *qw_ = nullptr, *qstart_ = nullptr, *qlocal_ = nullptr,
+       *rowptr_ = nullptr, *col_ = nullptr, *static_ = nullptr;
+  bool have_static_ = false;
+};
 
 // Twiddle table exp(-2 pi i m / L), m < L, in complex128 (and complex64).
 std::vector<double> twiddles64(int L);

@@ -1,0 +1,413 @@
+// Near-field set-up on the device.
+//
+// AIMx (Sec. III-A): for every pair (i, j) of the near list, the static
+// Galerkin entry A_s,NR[i, j] of the kernel 1/(4 pi R) (eq. hgfs) and the
+// correction C = A_s,NR - A_s,P with the precorrection A_s,P = W H_s,NR P of
+// eq. aimLPs (grid kernel 1/(4 pi R), self term 0 per eq. Hsmm).  These are
+// the one-time static fill of the cost model of Sec. VI; they do not depend
+// on the frequency.
+//
+// Conventional AIM (Sec. II-B, eqs. aimL, aimLFR, aimLP), for comparison:
+// per wavenumber k the complex near correction A_NR(k) - A_P(k), where the
+// near entries of the full kernel e^{-jkR}/(4 pi R) are the static entries
+// above plus the smooth remainder G_d = (e^{-jkR} - 1)/(4 pi R) integrated by
+// the 3 x 3 point rule, and A_P(k) = W H_NR(k) P uses the grid kernel
+// G(k, R) with the same self term -jk/(4 pi) as the far-field H (eq. Hmm), so
+// the self terms cancel.
+//
+// One thread per near pair.  The Galerkin entry uses the 3-point rule on the
+// testing triangle and the closed-form integral of 1/R over the source
+// triangle, written here as edge integrals plus the solid angle the triangle
+// subtends (van Oosterom and Strackee, IEEE Trans. Biomed. Eng. 30(2), 1983):
+//
+//   int_T dS'/R = sum_i P0_i int_{edge i} dl/R  -  |h| Omega,
+//
+// which follows from div_s[(rho' - rho)/R] = 1/R + h^2/R^3 in the plane of T
+// (h the height of r above it, P0_i the in-plane distance from the foot of
+// r to edge i, positive on the inner side) and int_T |h|/R^3 dS' = Omega.
+// The entry is symmetrised, (M_ij + M_ji)/2, so the matrix is exactly
+// symmetric.  The precorrection is evaluated per quadrature-point pair as
+// the separable correlation of the two stencils' 1-D Lagrange weights
+// against the grid kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "aim_internal.h"
+
+namespace aim {
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kInvFourPi = 1.0 / (4.0 * kPi);
+
+struct P3 {
+  double x, y, z;
+};
+__device__ __forceinline__ P3 sub(P3 a, P3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double dot(P3 a, P3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ P3 cross(P3 a, P3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ P3 scale(P3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ double len(P3 a) { return sqrt(dot(a, a)); }
+
+// integral of dl / sqrt(l^2 + R0^2) from lm to lp (lm <= lp), with R = the
+// distances of the endpoints, free of cancellation: the integrand is even in
+// l, so a segment behind the foot is mirrored, and a segment across it uses
+// (R + l)(R - l) = R0^2
+__device__ double edge_integral(double lm, double lp, double Rm, double Rp, double R0sq) {
+  if (lm >= 0.0) return log((Rp + lp) / (Rm + lm));
+  if (lp <= 0.0) return log((Rm - lm) / (Rp - lp));
+  return log((Rp + lp) * (Rm - lm) / R0sq);
+}
+
+// solid angle of triangle (A, B, C) seen from the origin, in [0, 2 pi)
+__device__ double solid_angle(P3 A, P3 B, P3 C) {
+  const double a = len(A), b = len(B), c = len(C);
+  const double num = fabs(dot(A, cross(B, C)));
+  const double den = a * b * c + dot(A, B) * c + dot(A, C) * b + dot(B, C) * a;
+  return 2.0 * atan2(num, den);
+}
+
+// integral over triangle v[0..2] of 1 / |r - r'| dS'
+__device__ double inv_r_integral(P3 r, const P3* v) {
+  const P3 nn = cross(sub(v[1], v[0]), sub(v[2], v[0]));
+  const double twice_area = len(nn);
+  const P3 n = scale(nn, 1.0 / twice_area);
+  const double h = dot(sub(r, v[0]), n);
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const P3 p = v[e], q = v[(e + 1) % 3];
+    const P3 d = sub(q, p);
+    const double L = len(d);
+    const P3 u = scale(d, 1.0 / L);       // edge direction, counter-clockwise about n
+    const P3 m = cross(u, n);             // outward in-plane normal of the edge
+    const P3 pr = sub(p, r), qr = sub(q, r);
+    const double P0 = dot(pr, m);
+    if (fabs(P0) <= 1e-15 * L) continue;  // foot on the edge line: the term vanishes
+    const double lm = dot(pr, u), lp = dot(qr, u);
+    acc += P0 * edge_integral(lm, lp, len(pr), len(qr), P0 * P0 + h * h);
+  }
+  // finite for every r (0 at a vertex), so no guard: the term is 0 in the plane
+  acc -= fabs(h) * solid_angle(sub(v[0], r), sub(v[1], r), sub(v[2], r));
+  return acc;
+}
+
+struct NearArgs {
+  const double* tri;       // [N][3][3] corners
+  const double* qp;        // [3N][3] quadrature points
+  const double* qw;        // [3N] weights (area / 3)
+  const int32_t* qstart;   // [3N][3] stencil start per axis
+  const double* qlocal;    // [3N][3] local coordinate t - s per axis
+  const int64_t* rowptr;   // [N+1] near list
+  const int32_t* col;      // [nnz]
+  int64_t N, nnz;
+  double h;                // grid spacing
+  double k;                // wavenumber (conventional AIM only)
+};
+
+__device__ int64_t row_of(const int64_t* rowptr, int64_t N, int64_t p) {
+  int64_t lo = 0, hi = N;  // rowptr[lo] <= p < rowptr[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) / 2;
+    if (rowptr[mid] <= p) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int ORDER>
+__device__ __forceinline__ void lagrange(double u, double* w) {
+#pragma unroll
+  for (int a = 0; a <= ORDER; ++a) {
+    double v = 1.0;
+#pragma unroll
+    for (int b = 0; b <= ORDER; ++b)
+      if (b != a) v *= (u - double(b)) / double(a - b);
+    w[a] = v;
+  }
+}
+
+__device__ double galerkin_static(const NearArgs& a, int64_t i, int64_t j) {
+  P3 v[3];
+  for (int c = 0; c < 3; ++c)
+    v[c] = {a.tri[9 * j + 3 * c], a.tri[9 * j + 3 * c + 1], a.tri[9 * j + 3 * c + 2]};
+  double s = 0.0;
+  for (int p = 0; p < 3; ++p) {
+    const int64_t q = 3 * i + p;
+    const P3 r = {a.qp[3 * q], a.qp[3 * q + 1], a.qp[3 * q + 2]};
+    s += a.qw[q] * inv_r_integral(r, v);
+  }
+  return s * kInvFourPi;
+}
+
+// grid kernel at the integer offset (x, y, z): static 1/(4 pi R) with 0 at
+// the origin, or (DYN) e^{-jkR}/(4 pi R) with -jk/(4 pi) at the origin
+template <bool DYN>
+struct GridKernel;
+template <>
+struct GridKernel<false> {
+  using V = double;
+  static __device__ V zero() { return 0.0; }
+  static __device__ V at(int x, int y, int z, double h, double) {
+    const int q = x * x + y * y + z * z;
+    return q == 0 ? 0.0 : kInvFourPi / (h * sqrt(double(q)));
+  }
+  static __device__ V fma(double w, V v, V acc) { return acc + w * v; }
+};
+template <>
+struct GridKernel<true> {
+  using V = double2;
+  static __device__ V zero() { return make_double2(0.0, 0.0); }
+  static __device__ V at(int x, int y, int z, double h, double k) {
+    const int q = x * x + y * y + z * z;
+    if (q == 0) return make_double2(0.0, -k * kInvFourPi);
+    const double R = h * sqrt(double(q));
+    double sn, cs;
+    sincos(k * R, &sn, &cs);
+    const double s = kInvFourPi / R;
+    return make_double2(cs * s, -sn * s);
+  }
+  static __device__ V fma(double w, V v, V acc) {
+    return make_double2(acc.x + w * v.x, acc.y + w * v.y);
+  }
+};
+
+// sum over quadrature-point pairs of w_a w_b sum_{u, v} L_u(r_a) H(u - v) L_v(r_b)
+template <bool DYN, int ORDER>
+__device__ typename GridKernel<DYN>::V precorrection(const NearArgs& a, int64_t i, int64_t j) {
+  using GK = GridKernel<DYN>;
+  constexpr int n = ORDER, S = n + 1, W = 2 * n + 1;
+  typename GK::V pc = GK::zero();
+  for (int p = 0; p < 3; ++p) {
+    const int64_t qa = 3 * i + p;
+    double li[3][S];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) lagrange<ORDER>(a.qlocal[3 * qa + ax], li[ax]);
+    for (int q = 0; q < 3; ++q) {
+      const int64_t qb = 3 * j + q;
+      // per axis: offset of the stencil starts and the correlation of the
+      // two weight vectors, K[d + n] = sum_{alpha - beta = d} l_a l_b
+      int d0[3];
+      double K[3][W];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        double lj[S];
+        lagrange<ORDER>(a.qlocal[3 * qb + ax], lj);
+        d0[ax] = a.qstart[3 * qa + ax] - a.qstart[3 * qb + ax];
+#pragma unroll
+        for (int d = 0; d < W; ++d) K[ax][d] = 0.0;
+#pragma unroll
+        for (int al = 0; al < S; ++al)
+#pragma unroll
+          for (int be = 0; be < S; ++be) K[ax][al - be + n] += li[ax][al] * lj[be];
+      }
+      typename GK::V acc = GK::zero();
+      for (int dz = 0; dz < W; ++dz)
+        for (int dy = 0; dy < W; ++dy) {
+          const double kyz = K[2][dz] * K[1][dy];
+          typename GK::V row = GK::zero();
+#pragma unroll
+          for (int dx = 0; dx < W; ++dx)
+            row = GK::fma(K[0][dx],
+                          GK::at(d0[0] + dx - n, d0[1] + dy - n, d0[2] + dz - n, a.h, a.k), row);
+          acc = GK::fma(kyz, row, acc);
+        }
+      pc = GK::fma(a.qw[qa] * a.qw[qb], acc, pc);
+    }
+  }
+  return pc;
+}
+
+template <int ORDER>
+__global__ __launch_bounds__(128) void near_static_kernel(NearArgs a, double* near_static,
+                                                          double* corr) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.nnz) return;
+  const int64_t i = row_of(a.rowptr, a.N, p), j = a.col[p];
+  // (i, j) and (j, i) evaluate the same expression (pair in ascending order,
+  // since the compiler may fuse a product into either sum), so the matrix
+  // is symmetric to the bit
+  const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+  const double m = 0.5 * (galerkin_static(a, lo, hi) + galerkin_static(a, hi, lo));
+  near_static[p] = m;
+  corr[p] = m - precorrection<false, ORDER>(a, i, j);
+}
+
+// conventional AIM: A_NR(k) - A_P(k) from the static entries
+template <int ORDER>
+__global__ __launch_bounds__(128) void near_dynamic_kernel(NearArgs a, const double* near_static,
+                                                           double2* out) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.nnz) return;
+  const int64_t i = row_of(a.rowptr, a.N, p), j = a.col[p];
+  // smooth remainder by the 3 x 3 point rule, G_d = (e^{-jkR} - 1)/(4 pi R)
+  // written as (-2 sin^2(kR/2) - j sin(kR))/(4 pi R), -jk/(4 pi) at R = 0
+  double dr = 0.0, di = 0.0;
+  for (int s = 0; s < 3; ++s)
+    for (int t = 0; t < 3; ++t) {
+      const int64_t qa = 3 * i + s, qb = 3 * j + t;
+      const P3 ra = {a.qp[3 * qa], a.qp[3 * qa + 1], a.qp[3 * qa + 2]};
+      const P3 rb = {a.qp[3 * qb], a.qp[3 * qb + 1], a.qp[3 * qb + 2]};
+      const double R = len(sub(ra, rb));
+      const double w = a.qw[qa] * a.qw[qb];
+      if (R == 0.0) {
+        di -= w * a.k * kInvFourPi;
+      } else {
+        double sn, cs;
+        sincos(0.5 * a.k * R, &sn, &cs);
+        const double s2 = 2.0 * sn * cs;  // sin(kR)
+        dr -= w * 2.0 * sn * sn * kInvFourPi / R;
+        di -= w * s2 * kInvFourPi / R;
+      }
+    }
+  const double2 pc = precorrection<true, ORDER>(a, i, j);
+  out[p] = make_double2(near_static[p] + dr - pc.x, di - pc.y);
+}
+
+unsigned blocks_for(int64_t n) { return unsigned((n + 127) / 128); }
+
+}  // namespace
+
+void* NearDevice::get(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void* p = nullptr;
+  if (alloc_) {
+    p = alloc_(bytes, stream_, ctx_);
+    AIM_REQUIRE(p != nullptr, AIM_ERR_OOM, "device allocator returned NULL");
+  } else {
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(AIM_ERR_OOM, "near-field tables: device allocation failed");
+    }
+  }
+  bufs_.push_back(p);
+  return p;
+}
+
+template <typename T>
+static void* put(void* dst, const std::vector<T>& v, hipStream_t s) {
+  if (!v.empty())
+    AIM_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return dst;
+}
+
+NearDevice::NearDevice(const HostTables& t, const double* V, const int32_t* T,
+                       aim_alloc_fn alloc, aim_free_fn free_fn, void* ctx, hipStream_t s)
+    : N_(t.N), nnz_(t.rowptr.empty() ? 0 : t.rowptr[t.N]), order_(t.order), h_(t.h),
+      alloc_(alloc), free_(free_fn), ctx_(ctx), stream_(s) {
+  try {
+    std::vector<double> tri(9 * size_t(N_));
+    for (int64_t j = 0; j < N_; ++j)
+      for (int c = 0; c < 3; ++c)
+        for (int ax = 0; ax < 3; ++ax) tri[9 * j + 3 * c + ax] = V[3 * int64_t(T[3 * j + c]) + ax];
+    tri_ = put(get(tri.size() * 8), tri, s);
+    qp_ = put(get(t.qp_xyz.size() * 8), t.qp_xyz, s);
+    qw_ = put(get(t.qp_w.size() * 8), t.qp_w, s);
+    qstart_ = put(get(t.qp_start.size() * 4), t.qp_start, s);
+    qlocal_ = put(get(t.qp_local.size() * 8), t.qp_local, s);
+    rowptr_ = put(get(t.rowptr.size() * 8), t.rowptr, s);
+    col_ = put(get(t.col.size() * 4), t.col, s);
+    static_ = get(size_t(nnz_) * 8);
+    AIM_HIP(hipStreamSynchronize(s));  // the host vectors above are temporaries
+  } catch (...) {
+    release();
+    throw;
+  }
+}
+
+void NearDevice::release() {
+  (void)hipStreamSynchronize(stream_);
+  for (void* p : bufs_) {
+    if (alloc_)
+      free_(p, stream_, ctx_);
+    else
+      (void)hipFree(p);
+  }
+  bufs_.clear();
+}
+
+NearDevice::~NearDevice() { release(); }
+
+static NearArgs make_args(const void* tri, const void* qp, const void* qw, const void* qstart,
+                          const void* qlocal, const void* rowptr, const void* col, int64_t N,
+                          int64_t nnz, double h, double k) {
+  NearArgs a{};
+  a.tri = static_cast<const double*>(tri);
+  a.qp = static_cast<const double*>(qp);
+  a.qw = static_cast<const double*>(qw);
+  a.qstart = static_cast<const int32_t*>(qstart);
+  a.qlocal = static_cast<const double*>(qlocal);
+  a.rowptr = static_cast<const int64_t*>(rowptr);
+  a.col = static_cast<const int32_t*>(col);
+  a.N = N;
+  a.nnz = nnz;
+  a.h = h;
+  a.k = k;
+  return a;
+}
+
+void NearDevice::fill_static(std::vector<double>& near_static, std::vector<double>& corr,
+                             hipStream_t s) {
+  const NearArgs a = make_args(tri_, qp_, qw_, qstart_, qlocal_, rowptr_, col_, N_, nnz_, h_,
+                               0.0);
+  void* cr = nullptr;
+  if (nnz_ > 0) {
+    const hipError_t e = hipMalloc(&cr, size_t(nnz_) * 8);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(AIM_ERR_OOM, "near-field set-up: device allocation failed");
+    }
+  }
+  try {
+    near_static.resize(nnz_);
+    corr.resize(nnz_);
+    if (nnz_ > 0) {
+      if (order_ == 2)
+        hipLaunchKernelGGL(near_static_kernel<2>, dim3(blocks_for(nnz_)), dim3(128), 0, s, a,
+                           static_cast<double*>(static_), static_cast<double*>(cr));
+      else
+        hipLaunchKernelGGL(near_static_kernel<3>, dim3(blocks_for(nnz_)), dim3(128), 0, s, a,
+                           static_cast<double*>(static_), static_cast<double*>(cr));
+      AIM_HIP(hipGetLastError());
+      AIM_HIP(hipMemcpyAsync(near_static.data(), static_, size_t(nnz_) * 8,
+                             hipMemcpyDeviceToHost, s));
+      AIM_HIP(hipMemcpyAsync(corr.data(), cr, size_t(nnz_) * 8, hipMemcpyDeviceToHost, s));
+    }
+    AIM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    if (cr) (void)hipFree(cr);
+    throw;
+  }
+  if (cr) (void)hipFree(cr);
+  have_static_ = true;
+}
+
+void NearDevice::set_static(const std::vector<double>& near_static, hipStream_t s) {
+  AIM_REQUIRE(int64_t(near_static.size()) == nnz_, AIM_ERR_INVALID_ARG,
+              "static near entries do not match the near list");
+  put(static_, near_static, s);
+  AIM_HIP(hipStreamSynchronize(s));
+  have_static_ = true;
+}
+
+void NearDevice::fill_conventional(double k, void* out_dev, hipStream_t s) {
+  AIM_REQUIRE(have_static_, AIM_ERR_STATE, "static near field not on the device");
+  const NearArgs a = make_args(tri_, qp_, qw_, qstart_, qlocal_, rowptr_, col_, N_, nnz_, h_, k);
+  if (nnz_ > 0) {
+    if (order_ == 2)
+      hipLaunchKernelGGL(near_dynamic_kernel<2>, dim3(blocks_for(nnz_)), dim3(128), 0, s, a,
+                         static_cast<const double*>(static_), static_cast<double2*>(out_dev));
+    else
+      hipLaunchKernelGGL(near_dynamic_kernel<3>, dim3(blocks_for(nnz_)), dim3(128), 0, s, a,
+                         static_cast<const double*>(static_), static_cast<double2*>(out_dev));
+    AIM_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace aim

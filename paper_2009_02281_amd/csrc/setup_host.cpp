@@ -139,8 +139,154 @@ double triangle_inv_r(const double r[3], const double a[3], const double b[3], c
   return total;
 }
 
+// A_s,NR and C = A_s,NR - A_s,P on the near list (host).
+void fill_near_host(HostTables& t, const double* V, const int32_t* T, int nthreads) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t N = t.N;
+  const int64_t nnz = t.rowptr[N];
+  const double h = t.h;
+  const int n = t.order, S = n + 1, W = 2 * n + 1;
+  std::vector<double> lw(3 * N * 3 * S);  // [qp][axis][a]
+  for (int64_t p = 0; p < 3 * N; ++p)
+    for (int ax = 0; ax < 3; ++ax) lagrange(t.qp_local[3 * p + ax], n, &lw[(3 * p + ax) * S]);
+  // -- static near field A_s,NR ----------------------------------------------
+  auto Mij = [&](int64_t i, int64_t j) {  // sum_p (A_i/3) Phi_j(r_ip)
+    const double* a = V + 3 * T[3 * j];
+    const double* b = V + 3 * T[3 * j + 1];
+    const double* c = V + 3 * T[3 * j + 2];
+    double s = 0.0;
+    for (int p = 0; p < 3; ++p)
+      s += t.qp_w[3 * i + p] * (triangle_inv_r(&t.qp_xyz[3 * (3 * i + p)], a, b, c) / kFourPi);
+    return s;
+  };
+  t.near_static.resize(nnz);
+  parallel_for(N, nthreads, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+        const int64_t j = t.col[p];
+        t.near_static[p] = 0.5 * (Mij(i, j) + Mij(j, i));
+      }
+  });
+
+  // -- precorrection A_s,P and the correction C ------------------------------
+  // 1/|d| table over squared integer distances
+  int dmax = 0;
+  for (int64_t i = 0; i < N; ++i)
+    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+      const int64_t j = t.col[p];
+      for (int q1 = 0; q1 < 3; ++q1)
+        for (int q2 = 0; q2 < 3; ++q2)
+          for (int ax = 0; ax < 3; ++ax)
+            dmax = std::max(dmax, std::abs(t.qp_start[3 * (3 * i + q1) + ax] -
+                                           t.qp_start[3 * (3 * j + q2) + ax]) + n);
+    }
+  const int64_t d2max = 3 * int64_t(dmax) * dmax;
+  std::vector<double> hs(d2max + 1);
+  hs[0] = 0.0;  // H_s self term (eq. Hsmm)
+  for (int64_t q = 1; q <= d2max; ++q) hs[q] = 1.0 / (kFourPi * h * std::sqrt(double(q)));
+  t.corr.resize(nnz);
+  parallel_for(N, nthreads, [&](int64_t b, int64_t e) {
+    std::vector<double> K(3 * W);
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+        const int64_t j = t.col[p];
+        double pc = 0.0;
+        for (int q1 = 0; q1 < 3; ++q1)
+          for (int q2 = 0; q2 < 3; ++q2) {
+            const int64_t a1 = 3 * i + q1, a2 = 3 * j + q2;
+            int d0[3];
+            for (int ax = 0; ax < 3; ++ax) {
+              d0[ax] = t.qp_start[3 * a1 + ax] - t.qp_start[3 * a2 + ax];
+              const double* la = &lw[(3 * a1 + ax) * S];
+              const double* lb = &lw[(3 * a2 + ax) * S];
+              double* k = &K[ax * W];
+              for (int dd = 0; dd < W; ++dd) k[dd] = 0.0;
+              for (int al = 0; al < S; ++al)
+                for (int be = 0; be < S; ++be) k[al - be + n] += la[al] * lb[be];
+            }
+            double acc = 0.0;
+            for (int dz = 0; dz < W; ++dz) {
+              const int64_t z = d0[2] + dz - n;
+              for (int dy = 0; dy < W; ++dy) {
+                const int64_t y = d0[1] + dy - n;
+                const double kyz = K[2 * W + dz] * K[W + dy];
+                const int64_t yz2 = y * y + z * z;
+                double accx = 0.0;
+                for (int dx = 0; dx < W; ++dx) {
+                  const int64_t x = d0[0] + dx - n;
+                  accx += K[dx] * hs[x * x + yz2];
+                }
+                acc += kyz * accx;
+              }
+            }
+            pc += t.qp_w[a1] * t.qp_w[a2] * acc;
+          }
+        t.corr[p] = t.near_static[p] - pc;
+      }
+  });
+
+  t.near_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Dense inverses of A_s,NR over the preconditioner clusters (needs the
+// static near entries).
+void build_cluster_inverses(HostTables& t, int nthreads) {
+  const int64_t ncl = int64_t(t.cl_ptr.size()) - 1;
+  t.cl_inv.assign(t.cl_blk[ncl], 0.0);
+  parallel_for(ncl, nthreads, [&](int64_t b, int64_t e) {
+    std::vector<double> A, I;
+    for (int64_t c = b; c < e; ++c) {
+      const int64_t o = t.cl_ptr[c], m = t.cl_ptr[c + 1] - o;
+      A.assign(m * m, 0.0);
+      I.assign(m * m, 0.0);
+      for (int64_t r = 0; r < m; ++r) {
+        const int32_t i = t.cl_perm[o + r];
+        I[r * m + r] = 1.0;
+        for (int64_t cc = 0; cc < m; ++cc) {
+          const int32_t j = t.cl_perm[o + cc];
+          const auto beg = t.col.begin() + t.rowptr[i], end = t.col.begin() + t.rowptr[i + 1];
+          const auto it = std::lower_bound(beg, end, j);
+          if (it != end && *it == j) A[r * m + cc] = t.near_static[it - t.col.begin()];
+        }
+      }
+      // Gauss-Jordan with partial pivoting
+      for (int64_t k = 0; k < m; ++k) {
+        int64_t piv = k;
+        for (int64_t r = k + 1; r < m; ++r)
+          if (std::fabs(A[r * m + k]) > std::fabs(A[piv * m + k])) piv = r;
+        AIM_REQUIRE(A[piv * m + k] != 0.0, AIM_ERR_GEOMETRY, "singular near-field block");
+        if (piv != k)
+          for (int64_t cc = 0; cc < m; ++cc) {
+            std::swap(A[k * m + cc], A[piv * m + cc]);
+            std::swap(I[k * m + cc], I[piv * m + cc]);
+          }
+        const double inv = 1.0 / A[k * m + k];
+        for (int64_t cc = 0; cc < m; ++cc) {
+          A[k * m + cc] *= inv;
+          I[k * m + cc] *= inv;
+        }
+        for (int64_t r = 0; r < m; ++r) {
+          if (r == k) continue;
+          const double f = A[r * m + k];
+          if (f == 0.0) continue;
+          for (int64_t cc = 0; cc < m; ++cc) {
+            A[r * m + cc] -= f * A[k * m + cc];
+            I[r * m + cc] -= f * I[k * m + cc];
+          }
+        }
+      }
+      std::copy(I.begin(), I.end(), t.cl_inv.begin() + t.cl_blk[c]);
+    }
+  });
+
+}
+
+int setup_threads(const aim_setup_desc& d) {
+  return d.n_threads > 0 ? d.n_threads : int(std::max(1u, std::thread::hardware_concurrency()));
+}
+
 // ---------------------------------------------------------------------------
-void build_host_tables(const aim_setup_desc& d, HostTables& t) {
+void build_host_tables(const aim_setup_desc& d, HostTables& t, bool near_on_host) {
   const auto t0 = std::chrono::steady_clock::now();
   AIM_REQUIRE(d.n_vertices >= 3 && d.n_triangles >= 1, AIM_ERR_INVALID_ARG,
               "need at least 3 vertices and 1 triangle");
@@ -162,8 +308,7 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t) {
   for (int64_t i = 0; i < 3 * N; ++i)
     AIM_REQUIRE(T[i] >= 0 && T[i] < NV, AIM_ERR_GEOMETRY, "triangle vertex index out of range");
 
-  const int nthreads = d.n_threads > 0 ? d.n_threads
-                                       : std::max(1u, std::thread::hardware_concurrency());
+  const int nthreads = setup_threads(d);
   t.N = N;
   t.order = d.stencil_order;
   for (int a = 0; a < 3; ++a) t.dims[a] = d.grid_dims[a];
@@ -287,85 +432,11 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t) {
   nbrs.clear();
   nbrs.shrink_to_fit();
 
-  // -- static near field A_s,NR ----------------------------------------------
-  auto Mij = [&](int64_t i, int64_t j) {  // sum_p (A_i/3) Phi_j(r_ip)
-    const double* a = V + 3 * T[3 * j];
-    const double* b = V + 3 * T[3 * j + 1];
-    const double* c = V + 3 * T[3 * j + 2];
-    double s = 0.0;
-    for (int p = 0; p < 3; ++p)
-      s += t.qp_w[3 * i + p] * (triangle_inv_r(&t.qp_xyz[3 * (3 * i + p)], a, b, c) / kFourPi);
-    return s;
-  };
-  t.near_static.resize(nnz);
-  parallel_for(N, nthreads, [&](int64_t b, int64_t e) {
-    for (int64_t i = b; i < e; ++i)
-      for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
-        const int64_t j = t.col[p];
-        t.near_static[p] = 0.5 * (Mij(i, j) + Mij(j, i));
-      }
-  });
-
-  // -- precorrection A_s,P and the correction C ------------------------------
-  const int n = t.order, S = n + 1, W = 2 * n + 1;
+  const int n = t.order, S = n + 1;
   std::vector<double> lw(3 * N * 3 * S);  // [qp][axis][a]
   for (int64_t p = 0; p < 3 * N; ++p)
     for (int ax = 0; ax < 3; ++ax) lagrange(t.qp_local[3 * p + ax], n, &lw[(3 * p + ax) * S]);
-  // 1/|d| table over squared integer distances
-  int dmax = 0;
-  for (int64_t i = 0; i < N; ++i)
-    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
-      const int64_t j = t.col[p];
-      for (int q1 = 0; q1 < 3; ++q1)
-        for (int q2 = 0; q2 < 3; ++q2)
-          for (int ax = 0; ax < 3; ++ax)
-            dmax = std::max(dmax, std::abs(t.qp_start[3 * (3 * i + q1) + ax] -
-                                           t.qp_start[3 * (3 * j + q2) + ax]) + n);
-    }
-  const int64_t d2max = 3 * int64_t(dmax) * dmax;
-  std::vector<double> hs(d2max + 1);
-  hs[0] = 0.0;  // H_s self term (eq. Hsmm)
-  for (int64_t q = 1; q <= d2max; ++q) hs[q] = 1.0 / (kFourPi * h * std::sqrt(double(q)));
-  t.corr.resize(nnz);
-  parallel_for(N, nthreads, [&](int64_t b, int64_t e) {
-    std::vector<double> K(3 * W);
-    for (int64_t i = b; i < e; ++i)
-      for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
-        const int64_t j = t.col[p];
-        double pc = 0.0;
-        for (int q1 = 0; q1 < 3; ++q1)
-          for (int q2 = 0; q2 < 3; ++q2) {
-            const int64_t a1 = 3 * i + q1, a2 = 3 * j + q2;
-            int d0[3];
-            for (int ax = 0; ax < 3; ++ax) {
-              d0[ax] = t.qp_start[3 * a1 + ax] - t.qp_start[3 * a2 + ax];
-              const double* la = &lw[(3 * a1 + ax) * S];
-              const double* lb = &lw[(3 * a2 + ax) * S];
-              double* k = &K[ax * W];
-              for (int dd = 0; dd < W; ++dd) k[dd] = 0.0;
-              for (int al = 0; al < S; ++al)
-                for (int be = 0; be < S; ++be) k[al - be + n] += la[al] * lb[be];
-            }
-            double acc = 0.0;
-            for (int dz = 0; dz < W; ++dz) {
-              const int64_t z = d0[2] + dz - n;
-              for (int dy = 0; dy < W; ++dy) {
-                const int64_t y = d0[1] + dy - n;
-                const double kyz = K[2 * W + dz] * K[W + dy];
-                const int64_t yz2 = y * y + z * z;
-                double accx = 0.0;
-                for (int dx = 0; dx < W; ++dx) {
-                  const int64_t x = d0[0] + dx - n;
-                  accx += K[dx] * hs[x * x + yz2];
-                }
-                acc += kyz * accx;
-              }
-            }
-            pc += t.qp_w[a1] * t.qp_w[a2] * acc;
-          }
-        t.corr[p] = t.near_static[p] - pc;
-      }
-  });
+  if (near_on_host) fill_near_host(t, V, T, nthreads);
 
   // -- projection matrix P (merged per triangle) -------------------------------
   {
@@ -496,52 +567,7 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t) {
     const int64_t m = leaves[c].second - leaves[c].first;
     t.cl_blk[c + 1] = t.cl_blk[c] + m * m;
   }
-  t.cl_inv.assign(t.cl_blk[ncl], 0.0);
-  parallel_for(ncl, nthreads, [&](int64_t b, int64_t e) {
-    std::vector<double> A, I;
-    for (int64_t c = b; c < e; ++c) {
-      const int64_t o = t.cl_ptr[c], m = t.cl_ptr[c + 1] - o;
-      A.assign(m * m, 0.0);
-      I.assign(m * m, 0.0);
-      for (int64_t r = 0; r < m; ++r) {
-        const int32_t i = t.cl_perm[o + r];
-        I[r * m + r] = 1.0;
-        for (int64_t cc = 0; cc < m; ++cc) {
-          const int32_t j = t.cl_perm[o + cc];
-          const auto beg = t.col.begin() + t.rowptr[i], end = t.col.begin() + t.rowptr[i + 1];
-          const auto it = std::lower_bound(beg, end, j);
-          if (it != end && *it == j) A[r * m + cc] = t.near_static[it - t.col.begin()];
-        }
-      }
-      // Gauss-Jordan with partial pivoting
-      for (int64_t k = 0; k < m; ++k) {
-        int64_t piv = k;
-        for (int64_t r = k + 1; r < m; ++r)
-          if (std::fabs(A[r * m + k]) > std::fabs(A[piv * m + k])) piv = r;
-        AIM_REQUIRE(A[piv * m + k] != 0.0, AIM_ERR_GEOMETRY, "singular near-field block");
-        if (piv != k)
-          for (int64_t cc = 0; cc < m; ++cc) {
-            std::swap(A[k * m + cc], A[piv * m + cc]);
-            std::swap(I[k * m + cc], I[piv * m + cc]);
-          }
-        const double inv = 1.0 / A[k * m + k];
-        for (int64_t cc = 0; cc < m; ++cc) {
-          A[k * m + cc] *= inv;
-          I[k * m + cc] *= inv;
-        }
-        for (int64_t r = 0; r < m; ++r) {
-          if (r == k) continue;
-          const double f = A[r * m + k];
-          if (f == 0.0) continue;
-          for (int64_t cc = 0; cc < m; ++cc) {
-            A[r * m + cc] -= f * A[k * m + cc];
-            I[r * m + cc] -= f * I[k * m + cc];
-          }
-        }
-      }
-      std::copy(I.begin(), I.end(), t.cl_inv.begin() + t.cl_blk[c]);
-    }
-  });
+  if (near_on_host) build_cluster_inverses(t, nthreads);
 
   t.setup_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
