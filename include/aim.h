@@ -276,6 +276,27 @@ aim_status aim_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void
 aim_status aim_matvec_static(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
                              int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream);
 
+/* Conventional AIM on the same plan (Sec. II-B, eqs. aimL, aimLFR, aimLP),
+ * the method AIMx is measured against: per wavenumber the complex near
+ * correction C(k) = A_NR(k) - A_P(k) is rebuilt, where A_NR(k) holds the
+ * near-region Galerkin entries of e^{-jkR}/(4 pi R) (the plan's static
+ * entries plus the smooth remainder (e^{-jkR} - 1)/(4 pi R) by the 3 x 3
+ * point rule) and A_P(k) = W H_NR(k) P uses the grid kernel of H(k) with its
+ * self term -jk/(4 pi), so that it cancels.  The far operator W H(k) P is
+ * the AIMx one.
+ * aim_conventional_fill computes C(k_f) on the device for wavenumber
+ * freq_idx (one thread per near pair; asynchronous on hip_stream; the plan
+ * keeps one wavenumber at a time, in complex128 and, if built, complex64).
+ * aim_matvec_conventional: y = W H(k_f) P x + C(k_f) x for nrhs vectors, all
+ * at that wavenumber (same layouts and rules as aim_matvec; AIM_ERR_STATE
+ * before any fill).  aim_conventional_export copies C(k_f) to the host as
+ * [nnz][2] doubles in the order of the near list (aim_export_tables);
+ * blocking.  Not for batch plans. */
+aim_status aim_conventional_fill(aim_plan plan, int32_t freq_idx, void* hip_stream);
+aim_status aim_matvec_conventional(aim_plan plan, aim_precision prec, const void* x_dev,
+                                   void* y_dev, int32_t nrhs, void* hip_stream);
+aim_status aim_conventional_export(aim_plan plan, double* vals_host, void* hip_stream);
+
 /* One stage of the matvec, for stage-level checks (see aim_stage for the
  * shapes).  Same rules as aim_matvec; grids are unpadded [nrhs][Nz][Ny][Nx]. */
 aim_status aim_apply_stage(aim_plan plan, aim_precision prec, aim_stage stage,

@@ -29,7 +29,8 @@ STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc":
 RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec",
-            "aim_matvec_static", "aim_apply_stage",
+            "aim_matvec_static", "aim_conventional_fill", "aim_matvec_conventional",
+            "aim_conventional_export", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
             "aim_autotune", "aim_set_schedule", "aim_matvec_capture", "aim_graph_launch",
             "aim_graph_destroy", "aim_unet_create", "aim_unet_destroy", "aim_unet_num_params",
@@ -112,6 +113,9 @@ def load_library(path: str = LIB_PATH):
     lib.aim_destroy.argtypes = [vp]
     lib.aim_plan_query.argtypes = [vp, C.POINTER(PlanInfo)]
     lib.aim_matvec.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
+    lib.aim_conventional_fill.argtypes = [vp, i32, vp]
+    lib.aim_matvec_conventional.argtypes = [vp, i32, vp, vp, i32, vp]
+    lib.aim_conventional_export.argtypes = [vp, C.POINTER(C.c_double), vp]
     lib.aim_matvec_static.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
     lib.aim_apply_stage.argtypes = [vp, i32, i32, vp, vp, i32, ip32, vp]
     lib.aim_excitation.argtypes = [vp, i32, C.POINTER(C.c_double), i32, i32, ip32, vp, vp]
@@ -516,6 +520,33 @@ class Plan:
                                            C.c_void_p(y.data_ptr()), nrhs, fp,
                                            _stream_ptr(stream)))
         return y
+
+    def conventional_fill(self, freq_idx: int = 0, stream=None):
+        """Conventional AIM: builds the complex near correction of wavenumber
+        ``freq_idx`` on the device (aim_conventional_fill)."""
+        _check(self._lib.aim_conventional_fill(self._plan, int(freq_idx), _stream_ptr(stream)))
+
+    def matvec_conventional(self, x, prec: str = "c128", out=None, stream=None):
+        """y = W H(k) P x + C(k) x with the last filled conventional
+        correction."""
+        import torch
+        self._check_vec(x, prec, self.n, "x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        self._check_vec(y, prec, self.n, "out")
+        _check(self._lib.aim_matvec_conventional(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
+                                                 C.c_void_p(y.data_ptr()), nrhs,
+                                                 _stream_ptr(stream)))
+        return y
+
+    def conventional_values(self, stream=None) -> np.ndarray:
+        """The filled conventional correction, complex128 [nnz] in near-list
+        order."""
+        nnz = int(self.info()["nnz"])
+        out = np.empty(2 * nnz, dtype=np.float64)
+        _check(self._lib.aim_conventional_export(
+            self._plan, out.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)))
+        return out.view(np.complex128)
 
     def profile_matvec(self, x, reps: int = 10, freq_idx=None, prec: str = "c128", out=None,
                        stream=None) -> dict:

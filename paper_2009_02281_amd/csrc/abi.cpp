@@ -142,6 +142,12 @@ struct aim_plan_s {
   int32_t* d_rhs_freq = nullptr;          // [max_rhs]
   int32_t* h_rhs_freq = nullptr;          // pinned staging
   std::vector<int32_t> cur_freq;          // what d_rhs_freq holds
+  // conventional AIM (aim_conventional_fill): complex near correction of
+  // wavenumber conv_freq, complex128 and complex64 copies
+  std::unique_ptr<aim::NearDevice> conv_nd;
+  void* d_conv64 = nullptr;
+  void* d_conv32 = nullptr;
+  int conv_freq = -1;
 
   // captured matvec graphs used by the solver, keyed by (prec, nrhs, in, out, freq)
   struct GraphKey {
@@ -200,6 +206,7 @@ struct aim_plan_s {
   ~aim_plan_s() {
     if (host_only) return;
     graphs.clear();
+    conv_nd.reset();
     if (setup_stream) (void)hipStreamSynchronize(setup_stream);
     (void)hipDeviceSynchronize();
     for (auto& o : owned) {
@@ -310,10 +317,11 @@ const int32_t* set_freq(aim_plan p, const int32_t* freq_host, int nrhs, hipStrea
 // row, which leaves garbage in the workspace and y.
 // grid and work (both null: the plan's own) hold the projection grid and
 // the convolution workspace of nrhs vectors.
+// With near false the near correction C x is left out (y = W H P x).
 template <typename T>
 void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
                  const int32_t* dfreq, hipStream_t s, hipEvent_t* ev, int repeat = 1,
-                 void* grid = nullptr, void* work = nullptr) {
+                 void* grid = nullptr, void* work = nullptr, bool near = true) {
   const int pi = int(prec);
   if (!grid) grid = p->d_grid[pi];
   if (!work) work = p->d_work[pi];
@@ -326,7 +334,7 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
   aim::launch_convolve<T>(p->g, grid, work, grid, spec, dfreq, nrhs, tw, s,
                           ev ? ev + 2 : nullptr, p->sched[pi], repeat);
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
-  for (int r = 0; r < repeat; ++r) interp_near<T>(p, prec, grid, x, y, nrhs, true, true, s);
+  for (int r = 0; r < repeat; ++r) interp_near<T>(p, prec, grid, x, y, nrhs, true, near, s);
   if (ev) AIM_HIP(hipEventRecord(ev[7], s));
 }
 
@@ -760,6 +768,65 @@ aim_status aim_matvec_static(aim_plan p, aim_precision prec, const void* x, void
       matvec_impl<double>(p, prec, x, y, nrhs, df, s, nullptr, 1, base, base + grid_b);
     else
       matvec_impl<float>(p, prec, x, y, nrhs, df, s, nullptr, 1, base, base + grid_b);
+  });
+}
+
+aim_status aim_conventional_fill(aim_plan p, int32_t freq_idx, void* hip_stream) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    no_batch(p);
+    AIM_REQUIRE(!p->host_only, AIM_ERR_STATE, "host-only plan has no device data");
+    AIM_REQUIRE(freq_idx >= 0 && freq_idx < p->nfreq, AIM_ERR_INVALID_ARG,
+                "frequency index out of range");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int64_t nnz = int64_t(p->t.col.size());
+    if (!p->conv_nd) {
+      p->conv_nd.reset(
+          new aim::NearDevice(p->t, nullptr, nullptr, p->alloc, p->free_fn, p->actx, s));
+      p->conv_nd->set_static(p->t.near_static, s);
+    }
+    if (!p->d_conv64) p->d_conv64 = p->dalloc(size_t(nnz) * 16, s);
+    if ((p->prec & (1u << AIM_C64)) && !p->d_conv32) p->d_conv32 = p->dalloc(size_t(nnz) * 8, s);
+    p->conv_freq = -1;
+    p->conv_nd->fill_conventional(p->k[freq_idx], p->d_conv64, s);
+    if (p->d_conv32) aim::launch_cast_c128_to_c64(p->d_conv64, p->d_conv32, nnz, s);
+    p->conv_freq = freq_idx;
+  });
+}
+
+aim_status aim_matvec_conventional(aim_plan p, aim_precision prec, const void* x, void* y,
+                                   int32_t nrhs, void* hip_stream) {
+  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    no_batch(p);
+    check_prec(p, prec);
+    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+    AIM_REQUIRE(p->conv_freq >= 0, AIM_ERR_STATE,
+                "no conventional near correction: call aim_conventional_fill first");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+                "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+    const std::vector<int32_t> fr(size_t(nrhs), p->conv_freq);
+    const int32_t* df = set_freq(p, fr.data(), nrhs, s);
+    // W H(k) P x, then the complex near correction of the same wavenumber
+    if (prec == AIM_C128) {
+      matvec_impl<double>(p, prec, x, y, nrhs, df, s, nullptr, 1, nullptr, nullptr, false);
+      aim::launch_near_complex<double>(p->d_rowptr, p->d_col, p->d_conv64, x, y, p->t.N, nrhs, s);
+    } else {
+      matvec_impl<float>(p, prec, x, y, nrhs, df, s, nullptr, 1, nullptr, nullptr, false);
+      aim::launch_near_complex<float>(p->d_rowptr, p->d_col, p->d_conv32, x, y, p->t.N, nrhs, s);
+    }
+  });
+}
+
+aim_status aim_conventional_export(aim_plan p, double* vals_host, void* hip_stream) {
+  if (!p || !vals_host) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    AIM_REQUIRE(p->conv_freq >= 0, AIM_ERR_STATE, "no conventional near correction filled");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t nnz = p->t.col.size();
+    if (nnz) AIM_HIP(hipMemcpyAsync(vals_host, p->d_conv64, nnz * 16, hipMemcpyDeviceToHost, s));
+    AIM_HIP(hipStreamSynchronize(s));
   });
 }
 

@@ -143,6 +143,11 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
 // forward, 2 fused z, 3 y inverse, 4 x inverse) of the grid g
 bool fft_variant_ok(bool dbl, const GridShape& g, int pass, int v);
 
+// y += Cc x with a complex CSR matrix (values complex128 or complex64 like
+// the vectors): the near correction of the conventional AIM
+template <typename T>
+void launch_near_complex(const int32_t* rowptr, const int32_t* col, const void* val,
+                         const void* x, void* y, int64_t n, int nrhs, hipStream_t s);
 // y = P^T phi + C x: rows of P^T (by triangle) and of C, one group of lanes
 // per triangle
 // quadrature-point stencil records (implicit interpolation)
@@ -277,7 +282,8 @@ void unet_adam(aim_unet u, double lr, hipStream_t s);
 // the near list once; fills the static near entries A_s,NR and the AIMx
 // correction C = A_s,NR - A_s,P (copied back to the host), and, per
 // wavenumber, the complex correction A_NR(k) - A_P(k) of the conventional
-// AIM into a caller's device buffer of nnz complex128 values.
+// AIM into a caller's device buffer of nnz complex128 values.  V and T may be
+// null when only the conventional fill is wanted (after set_static).
 class NearDevice {
  public:
   NearDevice(const HostTables& t, const double* V, const int32_t* T, aim_alloc_fn alloc,

@@ -1326,6 +1326,52 @@ __global__ __launch_bounds__(256) void interp_near_kernel(
   }
 }
 
+// y += Cc x for a complex CSR matrix: LPR lanes per row, fixed summation
+// order, one vector per blockIdx.y
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void near_complex_kernel(const int32_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ col,
+                                                           const cx<T>* __restrict__ val,
+                                                           const cx<T>* __restrict__ x,
+                                                           cx<T>* __restrict__ y, int64_t n) {
+  const int sub = threadIdx.x % LPR;
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
+  const int64_t off = int64_t(blockIdx.y) * n;
+  T ar = T(0), ai = T(0);
+  if (i < n) {
+    for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
+      const cx<T> c = val[k];
+      const cx<T> v = x[off + col[k]];
+      ar += c.x * v.x - c.y * v.y;
+      ai += c.x * v.y + c.y * v.x;
+    }
+  }
+  ar = group_sum<LPR>(ar);
+  ai = group_sum<LPR>(ai);
+  if (sub == 0 && i < n) {
+    cx<T> o = y[off + i];
+    o.x += ar;
+    o.y += ai;
+    y[off + i] = o;
+  }
+}
+
+template <typename T>
+void launch_near_complex(const int32_t* rowptr, const int32_t* col, const void* val,
+                         const void* x, void* y, int64_t n, int nrhs, hipStream_t s) {
+  constexpr int LPR = 8;
+  const dim3 grid(unsigned((n * LPR + 255) / 256), unsigned(nrhs));
+  hipLaunchKernelGGL((near_complex_kernel<T, LPR>), grid, dim3(256), 0, s, rowptr, col,
+                     static_cast<const cx<T>*>(val), static_cast<const cx<T>*>(x),
+                     static_cast<cx<T>*>(y), n);
+  AIM_HIP(hipGetLastError());
+}
+
+template void launch_near_complex<double>(const int32_t*, const int32_t*, const void*,
+                                          const void*, void*, int64_t, int, hipStream_t);
+template void launch_near_complex<float>(const int32_t*, const int32_t*, const void*, const void*,
+                                         void*, int64_t, int, hipStream_t);
+
 template <typename T>
 void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice& csr,
                         const void* phi, const void* x, void* y, int nrhs, bool do_interp,

@@ -301,11 +301,14 @@ NearDevice::NearDevice(const HostTables& t, const double* V, const int32_t* T,
     : N_(t.N), nnz_(t.rowptr.empty() ? 0 : t.rowptr[t.N]), order_(t.order), h_(t.h),
       alloc_(alloc), free_(free_fn), ctx_(ctx), stream_(s) {
   try {
-    std::vector<double> tri(9 * size_t(N_));
-    for (int64_t j = 0; j < N_; ++j)
-      for (int c = 0; c < 3; ++c)
-        for (int ax = 0; ax < 3; ++ax) tri[9 * j + 3 * c + ax] = V[3 * int64_t(T[3 * j + c]) + ax];
-    tri_ = put(get(tri.size() * 8), tri, s);
+    if (V && T) {  // corners: only the static fill needs them
+      std::vector<double> tri(9 * size_t(N_));
+      for (int64_t j = 0; j < N_; ++j)
+        for (int c = 0; c < 3; ++c)
+          for (int ax = 0; ax < 3; ++ax)
+            tri[9 * j + 3 * c + ax] = V[3 * int64_t(T[3 * j + c]) + ax];
+      tri_ = put(get(tri.size() * 8), tri, s);
+    }
     qp_ = put(get(t.qp_xyz.size() * 8), t.qp_xyz, s);
     qw_ = put(get(t.qp_w.size() * 8), t.qp_w, s);
     qstart_ = put(get(t.qp_start.size() * 4), t.qp_start, s);
@@ -353,6 +356,7 @@ static NearArgs make_args(const void* tri, const void* qp, const void* qw, const
 
 void NearDevice::fill_static(std::vector<double>& near_static, std::vector<double>& corr,
                              hipStream_t s) {
+  AIM_REQUIRE(tri_ != nullptr, AIM_ERR_STATE, "near-field tables built without the mesh");
   const NearArgs a = make_args(tri_, qp_, qw_, qstart_, qlocal_, rowptr_, col_, N_, nnz_, h_,
                                0.0);
   void* cr = nullptr;
