@@ -467,6 +467,70 @@ def extra_workload(name: str, precs, steps: int, warmup: int) -> dict:
     return res
 
 
+def conventional_leg(plan, w, nrhs: int = 8, reps: int = 10) -> dict:
+    """Conventional AIM against AIMx on one plan (Sec. II-B against Sec. III;
+    the per-wavenumber cost of the sweep comparison of Sec. VI): the
+    conventional method rebuilds its complex near correction for every
+    wavenumber (here on the device, median of the fills timed with events),
+    AIMx only its kernel spectrum; both then apply the same far operator."""
+    import numpy as np
+    import torch
+    from paper_2009_02281_amd import inputs as I
+    info = plan.info()
+    nf = int(len(w.k))
+    fills = []
+    for f in range(min(nf, 5)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        plan.conventional_fill(f)
+        b.record()
+        torch.cuda.synchronize()
+        fills.append(a.elapsed_time(b))
+    fill_ms = sorted(fills)[len(fills) // 2]
+    nr = min(nrhs, int(info["max_rhs"]))
+    x = torch.from_numpy(I.complex_gaussian(w.n, w.seed_base + 7, nrhs=nr)).cuda()
+    y = torch.empty_like(x)
+    f_last = min(nf, 5) - 1
+    ms_aimx = time_matvecs(plan, x, y, "c128", reps, 2, np.full(nr, f_last))
+    for _ in range(2):
+        plan.matvec_conventional(x, out=y)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        plan.matvec_conventional(x, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    ms_conv = a.elapsed_time(b) / reps
+    spec_ms = 1e3 * info["spectra_seconds"] / nf
+    res = {"workload": w.name, "triangles": w.n, "near_pairs": int(info["nnz"]), "n_freq": nf,
+           "static_fill_seconds_once": info["near_seconds"],
+           "per_freq_ms": {"aimx_spectrum": spec_ms, "conventional_spectrum_plus_near_fill":
+                           spec_ms + fill_ms, "conventional_near_fill": fill_ms},
+           "matvec_ms": {"vectors": nr, "aimx": ms_aimx, "conventional": ms_conv},
+           "note": "complex128; the conventional near fill is per wavenumber, the AIMx static "
+                   "fill once per geometry"}
+    print(f"[bench] conventional AIM on {w.name}: near fill {fill_ms:.2f} ms per wavenumber "
+          f"(AIMx: spectrum {spec_ms:.2f} ms), matvec x{nr} {ms_conv:.3f} ms vs AIMx "
+          f"{ms_aimx:.3f} ms", file=sys.stderr, flush=True)
+    return res
+
+
+def host_near_seconds(w) -> dict:
+    """The same static near fill on the host (a host-only plan of the
+    workload), for comparison with the device fill."""
+    from paper_2009_02281_amd import binding
+    t0 = time.perf_counter()
+    hp = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                      host_only=True)
+    total = time.perf_counter() - t0
+    hi = hp.info()
+    hp.close()
+    return {"host_setup_seconds": total, "host_near_fill_seconds": hi["near_seconds"],
+            "host_threads": host_threads()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,7 +595,8 @@ def main() -> int:
                         precisions=precs, max_rhs=args.nrhs)
     setup_s = time.perf_counter() - t0
     info = plan.info()
-    print(f"[bench] setup {setup_s:.2f}s (host tables {info['setup_seconds']:.2f}s, "
+    print(f"[bench] setup {setup_s:.2f}s (tables {info['setup_seconds']:.2f}s, static near "
+          f"fill {'device' if info['near_on_device'] else 'host'} {info['near_seconds']:.3f}s, "
           f"spectra {info['spectra_seconds']:.3f}s), nnz={info['nnz']}", file=sys.stderr,
           flush=True)
     tuned = {}
@@ -583,7 +648,15 @@ def main() -> int:
                    "n_freq": int(len(w.k))},
         "fft_schedule": {pr: tuned[pr]["schedule"] for pr in tuned},
         "ms_per_matvec_spread": spread,
+        "setup": {"seconds": setup_s, "static_near_fill_seconds": info["near_seconds"],
+                  "static_near_fill_on_device": info["near_on_device"],
+                  "spectra_seconds": info["spectra_seconds"]},
     }
+    if not args.no_extra:
+        out["setup"].update(host_near_seconds(w))
+        print(f"[bench] host near fill {out['setup']['host_near_fill_seconds']:.3f}s "
+              f"({out['setup']['host_threads']} threads) vs device "
+              f"{info['near_seconds']:.3f}s", file=sys.stderr, flush=True)
 
     if args.workload == "sweep":
         # the paper's cost model T = T_s + N_f T_d: T_s the frequency-independent
@@ -643,11 +716,18 @@ def main() -> int:
     if not args.no_solve:
         out["gmres"] = solve_leg(plan, args.solve_rtol, args.solve_max_iter,
                                  tuple(args.solve_pcs.split(",")))
+    if not args.no_extra and args.workload != "sweep" and args.nrhs <= plan.info()["max_rhs"]:
+        out["conventional"] = {w.name: conventional_leg(plan, w, nrhs=args.nrhs)}
     if not args.no_extra and args.workload != "sweep":
         plan.close()
         plan = None
         torch.cuda.empty_cache()
         out["extra"]["sweep"] = extra_workload("sweep", ("c128", "c64"), 20, 3)
+        ws = make_workload("sweep")
+        sp = binding.Plan(ws.vertices, ws.triangles, ws.order, ws.dims, ws.h, ws.near_threshold,
+                          ws.k, precisions=("c128",), max_rhs=8)
+        out["conventional"][ws.name] = conventional_leg(sp, ws, nrhs=8)
+        sp.close()
         if args.workload != "boxarray":
             out["extra"]["boxarray"] = extra_workload("boxarray", ("c128", "c64"), 50, 5)
     if not args.no_learned and args.workload != "sweep":
