@@ -332,11 +332,11 @@ aim_status aim_solve(aim_plan plan, const void* b_dev, void* x_dev, int32_t nrhs
 /* Returns in kernel_ms_host[AIM_N_KERNELS] the average duration in
  * milliseconds of each kernel of one matvec (the stages of eq. LAIMx:
  * projection, the zero-padded FFT convolution with the Toeplitz kernel, the
- * interpolation and the near-field correction): every kernel is launched
- * `reps` times back to back on hip_stream between two HIP events, so the
- * gaps between kernels are not counted.  Same arguments and errors as
- * aim_matvec; y_dev receives the product (one ordinary matvec runs after the
- * timed launches, which overwrite the plan's workspace); blocking. */
+ * interpolation and the near-field correction): `reps` ordinary matvecs run
+ * back to back on hip_stream with a HIP event recorded before, between and
+ * after their seven kernels, and each kernel's average is taken over the
+ * intervals it spans.  Same arguments and errors as aim_matvec; y_dev
+ * receives the product; blocking. */
 aim_status aim_profile_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
                               int32_t nrhs, const int32_t* freq_idx_host, int32_t reps,
                               double* kernel_ms_host, void* hip_stream);

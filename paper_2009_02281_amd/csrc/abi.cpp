@@ -838,13 +838,13 @@ aim_status aim_profile_matvec(aim_plan p, aim_precision prec, const void* x, voi
     no_batch(p);
     check_prec(p, prec);
     AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
-    AIM_REQUIRE(reps >= 1, AIM_ERR_INVALID_ARG, "reps must be >= 1");
+    AIM_REQUIRE(reps >= 1 && reps <= 1000, AIM_ERR_INVALID_ARG, "reps must be in 1..1000");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
-    // each kernel launched reps times back to back between two events, so
-    // that the gaps between kernels do not count; an ordinary matvec first
-    // (warm-up) and last (y = A x, as the repeated kernels leave garbage)
-    std::vector<hipEvent_t> ev(8, nullptr);
+    // reps ordinary matvecs after one warm-up, events before, between and
+    // after the seven kernels of each (the queue stays full, so an interval
+    // is its kernel's duration)
+    std::vector<hipEvent_t> ev(8 * size_t(reps), nullptr);
     auto destroy = [&] {
       for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
@@ -852,16 +852,21 @@ aim_status aim_profile_matvec(aim_plan p, aim_precision prec, const void* x, voi
     try {
       for (auto& e : ev) AIM_HIP(hipEventCreate(&e));
       matvec_any(p, prec, x, y, nrhs, df, s);
-      if (prec == AIM_C128)
-        matvec_impl<double>(p, prec, x, y, nrhs, df, s, ev.data(), reps);
-      else
-        matvec_impl<float>(p, prec, x, y, nrhs, df, s, ev.data(), reps);
-      matvec_any(p, prec, x, y, nrhs, df, s);
+      for (int r = 0; r < reps; ++r) {
+        if (prec == AIM_C128)
+          matvec_impl<double>(p, prec, x, y, nrhs, df, s, ev.data() + 8 * size_t(r));
+        else
+          matvec_impl<float>(p, prec, x, y, nrhs, df, s, ev.data() + 8 * size_t(r));
+      }
       AIM_HIP(hipStreamSynchronize(s));
       for (int k = 0; k < AIM_N_KERNELS; ++k) {
-        float ms = 0.f;
-        AIM_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
-        kernel_ms[k] = double(ms) / reps;
+        double tot = 0.0;
+        for (int r = 0; r < reps; ++r) {
+          float ms = 0.f;
+          AIM_HIP(hipEventElapsedTime(&ms, ev[8 * size_t(r) + k], ev[8 * size_t(r) + k + 1]));
+          tot += double(ms);
+        }
+        kernel_ms[k] = tot / reps;
       }
     } catch (...) {
       destroy();

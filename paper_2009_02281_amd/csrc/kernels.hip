@@ -87,37 +87,53 @@ __device__ __forceinline__ cx<T> rot90(cx<T> a) {  // * (-i) forward, * (+i) inv
   return INV ? mkc<T>(-a.y, a.x) : mkc<T>(a.y, -a.x);
 }
 
-template <typename T, int R, bool INV>
+// HALF_IN: the upper half of the inputs (v[R/2] .. v[R-1]) is zero and is
+// not read, which drops the butterflies that would only add zeros (the first
+// forward stage of a zero-padded line).
+template <typename T, int R, bool INV, bool HALF_IN = false>
 struct Dft;
 
-template <typename T, bool INV>
-struct Dft<T, 2, INV> {
+template <typename T, bool INV, bool HALF_IN>
+struct Dft<T, 2, INV, HALF_IN> {
   static __device__ __forceinline__ void run(cx<T>* v) {
     const cx<T> a = v[0];
-    v[0] = cadd(a, v[1]);
-    v[1] = csub(a, v[1]);
+    if constexpr (HALF_IN) {
+      v[1] = a;
+    } else {
+      v[0] = cadd(a, v[1]);
+      v[1] = csub(a, v[1]);
+    }
   }
 };
 
-template <typename T, bool INV>
-struct Dft<T, 4, INV> {
+template <typename T, bool INV, bool HALF_IN>
+struct Dft<T, 4, INV, HALF_IN> {
   static __device__ __forceinline__ void run(cx<T>* v) {
-    const cx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    const cx<T> t2 = cadd(v[1], v[3]), t3 = rot90<T, INV>(csub(v[1], v[3]));
-    v[0] = cadd(t0, t2);
-    v[2] = csub(t0, t2);
-    v[1] = cadd(t1, t3);
-    v[3] = csub(t1, t3);
+    if constexpr (HALF_IN) {
+      const cx<T> a0 = v[0], a1 = v[1], r = rot90<T, INV>(a1);
+      v[0] = cadd(a0, a1);
+      v[2] = csub(a0, a1);
+      v[1] = cadd(a0, r);
+      v[3] = csub(a0, r);
+    } else {
+      const cx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+      const cx<T> t2 = cadd(v[1], v[3]), t3 = rot90<T, INV>(csub(v[1], v[3]));
+      v[0] = cadd(t0, t2);
+      v[2] = csub(t0, t2);
+      v[1] = cadd(t1, t3);
+      v[3] = csub(t1, t3);
+    }
   }
 };
 
-template <typename T, bool INV>
-struct Dft<T, 8, INV> {
+template <typename T, bool INV, bool HALF_IN>
+struct Dft<T, 8, INV, HALF_IN> {
   static __device__ __forceinline__ void run(cx<T>* v) {
+    // even and odd inputs; with HALF_IN only their first two are non-zero
     cx<T> e[4] = {v[0], v[2], v[4], v[6]};
     cx<T> o[4] = {v[1], v[3], v[5], v[7]};
-    Dft<T, 4, INV>::run(e);
-    Dft<T, 4, INV>::run(o);
+    Dft<T, 4, INV, HALF_IN>::run(e);
+    Dft<T, 4, INV, HALF_IN>::run(o);
     const T r2 = T(0.70710678118654752440);
     // o1 *= w8, o2 *= w8^2, o3 *= w8^3 with w8 = e^{-/+ i pi/4}
     const cx<T> a = o[1], c = o[3];
@@ -139,8 +155,8 @@ struct Dft<T, 8, INV> {
 
 // 16 points as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2; 4-point DFTs over n1,
 // twiddles W16^(n2 k1), 4-point DFTs over n2
-template <typename T, bool INV>
-struct Dft<T, 16, INV> {
+template <typename T, bool INV, bool HALF_IN>
+struct Dft<T, 16, INV, HALF_IN> {
   static __device__ __forceinline__ cx<T> tw(cx<T> a, T c, T sf) {  // a * (c + i sf), sf forward
     return cmul(a, mkc<T>(c, INV ? -sf : sf));
   }
@@ -151,7 +167,7 @@ struct Dft<T, 16, INV> {
 #pragma unroll
     for (int n2 = 0; n2 < 4; ++n2) {
       cx<T> u[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
-      Dft<T, 4, INV>::run(u);
+      Dft<T, 4, INV, HALF_IN>::run(u);  // inputs n < 8: n1 < 2
 #pragma unroll
       for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = u[k1];
     }
@@ -182,8 +198,8 @@ constexpr double kCos32[8] = {1.0, 0.9807852804032304, 0.9238795325112867, 0.831
 constexpr double kSin32[8] = {0.0, 0.19509032201612825, 0.3826834323650898, 0.5555702330196022,
                               0.7071067811865475, 0.8314696123025452, 0.9238795325112867,
                               0.9807852804032304};   // sin(2 pi r / 32)
-template <typename T, bool INV>
-struct Dft<T, 32, INV> {
+template <typename T, bool INV, bool HALF_IN>
+struct Dft<T, 32, INV, HALF_IN> {
   // a * W32^m (e^{-2 pi i m / 32} forward): the first-octant twiddle of
   // m mod 8, then a quarter turn for each 8 in m
   static __device__ __forceinline__ cx<T> w(cx<T> a, int m) {
@@ -197,7 +213,7 @@ struct Dft<T, 32, INV> {
 #pragma unroll
     for (int n2 = 0; n2 < 8; ++n2) {
       cx<T> u[4] = {v[n2], v[8 + n2], v[16 + n2], v[24 + n2]};
-      Dft<T, 4, INV>::run(u);
+      Dft<T, 4, INV, HALF_IN>::run(u);  // inputs n < 16: n1 < 2
 #pragma unroll
       for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = w(u[k1], n2 * k1);
     }
@@ -244,7 +260,7 @@ struct Sched {
   }
 };
 
-template <typename T, int L, int NT, bool INV, int R, int LGNS>
+template <typename T, int L, int NT, bool INV, int R, int LGNS, bool HALF_IN = false>
 __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* tw) {
   constexpr int NB = L / (R * NT);
   static_assert(NB >= 1, "too many threads per line for this radix");
@@ -260,7 +276,7 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* tw) 
         v[i * R + r] = cmul(v[i * R + r], w);
       }
     }
-    Dft<T, R, INV>::run(v + i * R);
+    Dft<T, R, INV, HALF_IN>::run(v + i * R);
   }
 }
 
@@ -285,11 +301,13 @@ __device__ __forceinline__ void exchange(cx<T>* v, cx<T>* s, int es, int t) {
   __syncthreads();
 }
 
-template <typename T, int L, int NT, bool INV, bool SF, int RMAX, int ST>
+// HALF_IN: the second half of the line is zero (a zero-padded forward
+// transform); only the first stage sees that
+template <typename T, int L, int NT, bool INV, bool SF, int RMAX, int ST, bool HALF_IN = false>
 __device__ __forceinline__ void run_stages(cx<T>* v, cx<T>* s, int es, int t, const cx<T>* tw) {
   using Sc = Sched<L, SF, RMAX>;
   constexpr int R = Sc::radix(ST), LG = Sc::lgns(ST);
-  stage_compute<T, L, NT, INV, R, LG>(v, t, tw);
+  stage_compute<T, L, NT, INV, R, LG, HALF_IN && ST == 0>(v, t, tw);
   if constexpr (ST + 1 < Sc::NST) {
     exchange<T, L, NT, R, LG, Sc::radix(ST + 1)>(v, s, es, t);
     run_stages<T, L, NT, INV, SF, RMAX, ST + 1>(v, s, es, t, tw);
@@ -303,6 +321,10 @@ __device__ __forceinline__ void run_stages(cx<T>* v, cx<T>* s, int es, int t, co
 // rows of TL elements); row passes (x) have lg_nli = log2(rows per plane),
 // p0 = row pitch, os = plane pitch and es = 1.
 // MODE 0: forward, 1: inverse, 2: forward * spectrum then inverse.
+// HALF (the convolution's passes): a forward transform reads only the first
+// half of its line (the rest is the zero padding, known at compile time, so
+// the first stage skips it) and an inverse transform keeps only the first
+// half; otherwise (the kernel spectrum) whole lines, Lin and Lout elements.
 // ---------------------------------------------------------------------------
 struct PassArgs {
   int64_t nlines;
@@ -318,7 +340,7 @@ struct PassArgs {
   int Mx, Nx, My, Ny, Mz, Nz;
 };
 
-template <typename T, int L, int TL, int NT, int MODE, bool COL, int RMAX>
+template <typename T, int L, int TL, int NT, int MODE, bool COL, int RMAX, bool HALF>
 __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>* out,
                                                           const cx<T>* __restrict__ twg,
                                                           PassArgs a) {
@@ -330,7 +352,6 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
   const int rhs = blockIdx.y;
   in += rhs * a.in_bs;
   out += rhs * a.out_bs;
-  for (int m = tid; m < L; m += NTH) tw[m] = twg[m];
   const int l = COL ? (tid & (TL - 1)) : (tid / NT);
   const int t = COL ? (tid / TL) : (tid & (NT - 1));
   int64_t line0 = int64_t(blockIdx.x) * TL;
@@ -361,9 +382,9 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
   cx<T>* dst = out + lo * a.out_os + li * a.out_p0;
   cx<T>* sl = COL ? s + l : s + l * (L + 1);
   const int es = COL ? TL : 1;
-  __syncthreads();
 
   constexpr bool SF = MODE != 1;
+  constexpr bool HALF_IN = HALF && MODE != 1, HALF_OUT = HALF && MODE != 0;
   static_assert(RMAX <= E, "a thread must hold a whole butterfly");
   using S0 = Sched<L, SF, RMAX>;
   constexpr int R0 = S0::radix(0), NB0 = L / (R0 * NT);
@@ -373,7 +394,10 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const int e = t + i * NT + r * (L / R0);
-      v[i * R0 + r] = (valid && e < a.Lin) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
+      if constexpr (HALF_IN)  // e < L/2 exactly when r < R0/2
+        v[i * R0 + r] = (valid && r < R0 / 2) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
+      else
+        v[i * R0 + r] = (valid && e < a.Lin) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
     }
   // fused z pass: the spectrum values this thread multiplies after its
   // forward transform depend only on (kx, ky) and the element index, so they
@@ -403,7 +427,11 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
         }
     }
   }
-  run_stages<T, L, NT, MODE == 1, SF, RMAX, 0>(v, sl, es, t, tw);
+  // the twiddle table after the line and spectrum loads, so that their
+  // latencies overlap
+  for (int m = tid; m < L; m += NTH) tw[m] = twg[m];
+  __syncthreads();
+  run_stages<T, L, NT, MODE == 1, SF, RMAX, 0, HALF_IN>(v, sl, es, t, tw);
   if constexpr (MODE == 2) {
     if (valid) {
 #pragma unroll
@@ -424,7 +452,7 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
 #pragma unroll
       for (int r = 0; r < Rf; ++r) {
         const int e = t + i * NT + r * (L / Rf);
-        if (e < a.Lout) {
+        if (HALF_OUT ? r < Rf / 2 : e < a.Lout) {  // e < L/2 exactly when r < Rf/2
           if constexpr (kStreamOut) {
             __builtin_nontemporal_store(v[i * Rf + r].x, &dst[e * a.out_es].x);
             __builtin_nontemporal_store(v[i * Rf + r].y, &dst[e * a.out_es].y);
@@ -489,12 +517,16 @@ void launch_shape(int mode, const cx<T>* i, cx<T>* o, const cx<T>* w, const Pass
     throw Error(AIM_ERR_INVALID_ARG, "FFT launch shape not available for this length");
   } else {
     dim3 grid(unsigned((a.nlines + S::TL - 1) / S::TL), unsigned(nrhs));
+    AIM_REQUIRE(mode == 2 ? (a.Lin == L / 2 && a.Lout == L / 2)
+                          : mode == 0 ? (a.Lin == L / 2 && a.Lout == L)
+                                      : (a.Lin == L && a.Lout == L / 2),
+                AIM_ERR_INVALID_ARG, "convolution FFT pass: lines must be half zero padding");
     if (mode == 0)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 0, COL, S::RMAX>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 0, COL, S::RMAX, true>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
     else if (mode == 1)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 1, COL, S::RMAX>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 1, COL, S::RMAX, true>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
     else if constexpr (COL)
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 2, COL, S::RMAX>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 2, COL, S::RMAX, true>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
     else
       throw Error(AIM_ERR_INVALID_ARG, "row passes have no spectral multiply");
   }
@@ -537,6 +569,38 @@ void fft_pass(int L, bool col, int mode, const void* in, void* out, const void* 
     case 128: pass_L<T, 128>(col, mode, variant, in, out, tw, a, nrhs, s); break;
     case 256: pass_L<T, 256>(col, mode, variant, in, out, tw, a, nrhs, s); break;
     case 512: pass_L<T, 512>(col, mode, variant, in, out, tw, a, nrhs, s); break;
+    default: throw Error(AIM_ERR_GRID, "unsupported FFT length");
+  }
+  AIM_HIP(hipGetLastError());
+}
+
+// whole-line forward transform (the kernel spectrum), launch shape 0
+template <typename T, int L, bool COL>
+void full_forward_L(const void* in, void* out, const void* tw, const PassArgs& a, hipStream_t s) {
+  using S = Shape<T, L, COL, 0>;
+  static_assert(S::OK, "shape 0 exists for every length");
+  dim3 grid(unsigned((a.nlines + S::TL - 1) / S::TL), 1u);
+  hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 0, COL, S::RMAX, false>), grid,
+                     dim3(S::THREADS), 0, s, static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out),
+                     static_cast<const cx<T>*>(tw), a);
+}
+
+template <typename T>
+void fft_full_forward(int L, bool col, const void* in, void* out, const void* tw,
+                      const PassArgs& a, hipStream_t s) {
+  switch (L * 2 + (col ? 1 : 0)) {
+    case 32: full_forward_L<T, 16, false>(in, out, tw, a, s); break;
+    case 33: full_forward_L<T, 16, true>(in, out, tw, a, s); break;
+    case 64: full_forward_L<T, 32, false>(in, out, tw, a, s); break;
+    case 65: full_forward_L<T, 32, true>(in, out, tw, a, s); break;
+    case 128: full_forward_L<T, 64, false>(in, out, tw, a, s); break;
+    case 129: full_forward_L<T, 64, true>(in, out, tw, a, s); break;
+    case 256: full_forward_L<T, 128, false>(in, out, tw, a, s); break;
+    case 257: full_forward_L<T, 128, true>(in, out, tw, a, s); break;
+    case 512: full_forward_L<T, 256, false>(in, out, tw, a, s); break;
+    case 513: full_forward_L<T, 256, true>(in, out, tw, a, s); break;
+    case 1024: full_forward_L<T, 512, false>(in, out, tw, a, s); break;
+    case 1025: full_forward_L<T, 512, true>(in, out, tw, a, s); break;
     default: throw Error(AIM_ERR_GRID, "unsupported FFT length");
   }
   AIM_HIP(hipGetLastError());
@@ -680,7 +744,7 @@ __global__ __launch_bounds__(TL* NT) void zconv_kernel(cx<T>* B, const cx<T>* __
     // (the last set reloads itself, unused: no branch, so the waits on these
     // loads are counted exactly)
     load(si + step < last ? si + step : si);
-    run_stages<T, L, NT, false, true, RMAX, 0>(v, sl, TL, t, tw);
+    run_stages<T, L, NT, false, true, RMAX, 0, true>(v, sl, TL, t, tw);
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = cmul(v[k], spv[k]);
     run_stages<T, L, NT, true, false, RMAX, 0>(v, sl, TL, t, tw);
@@ -998,8 +1062,16 @@ void launch_spectrum(const GridShape& g, double k, double h, void* full_work, vo
   hipLaunchKernelGGL(green_sample_kernel, dim3(4096), dim3(256), 0, s, F, Nx, Ny, Nz, k, h);
   AIM_HIP(hipGetLastError());
   const int64_t Np = int64_t(Mx) * My * Mz;
-  row_pass<double>(Mx, false, F, F, tw64[0], Mz, My, Mx, Mx, int64_t(My) * Mx,
-                   int64_t(My) * Mx, 0, 0, Mx, Mx, 1, s);
+  {  // rows (y, z) of the whole padded grid
+    PassArgs a{};
+    a.nlines = int64_t(Mz) * My;
+    a.lg_nli = ilog2(My);
+    a.in_es = a.out_es = 1;
+    a.in_os = a.out_os = int64_t(My) * Mx;
+    a.in_p0 = a.out_p0 = Mx;
+    a.Lin = a.Lout = Mx;
+    fft_full_forward<double>(Mx, false, F, F, tw64[0], a, s);
+  }
   {
     PassArgs a{};
     a.nlines = int64_t(Mx) * Mz;
@@ -1008,7 +1080,7 @@ void launch_spectrum(const GridShape& g, double k, double h, void* full_work, vo
     a.in_es = a.out_es = Mx;
     a.in_os = a.out_os = int64_t(My) * Mx;
     a.Lin = a.Lout = My;
-    fft_pass<double>(My, true, 0, F, F, tw64[1], a, 1, s);
+    fft_full_forward<double>(My, true, F, F, tw64[1], a, s);
   }
   {
     PassArgs a{};
@@ -1018,7 +1090,7 @@ void launch_spectrum(const GridShape& g, double k, double h, void* full_work, vo
     a.in_es = a.out_es = int64_t(My) * Mx;
     a.in_os = a.out_os = Mx;
     a.Lin = a.Lout = Mz;
-    fft_pass<double>(Mz, true, 0, F, F, tw64[2], a, 1, s);
+    fft_full_forward<double>(Mz, true, F, F, tw64[2], a, s);
   }
   hipLaunchKernelGGL(fold_spectrum_kernel, dim3(2048), dim3(256), 0, s, F,
                      static_cast<double2*>(spec64), static_cast<float2*>(spec32), Nx, Ny, Nz,
