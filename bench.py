@@ -555,7 +555,7 @@ def main() -> int:
     ap.add_argument("--batch", action="store_true",
                     help="also time one batched solve over 32 uneven geometries against "
                          "solving them one after another")
-    ap.add_argument("--solve-pcs", default="none,diag",
+    ap.add_argument("--solve-pcs", default="none,diag,nearblock",
                     help="comma-separated preconditioners for the GMRES leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")

@@ -59,13 +59,23 @@ typedef enum {
   AIM_PC_NONE = 0,       /* unpreconditioned                                      */
   AIM_PC_DIAG = 1,       /* 1 / diag(A_s,NR): the frequency-independent diagonal
                             preconditioner of Sec. III-A ("Preconditioning")     */
-  AIM_PC_NEARBLOCK = 2,  /* block-Jacobi on spatial clusters of A_s,NR: the
-                            near-region/block choice of the same section, built
-                            from static entries only                             */
-  AIM_PC_UNET = 3        /* learned grid preconditioner attached with
+  AIM_PC_NEARBLOCK = 2,  /* block-Jacobi on spatial clusters (recursive
+                            coordinate bisection to at most 64 triangles) of the
+                            full-kernel Galerkin matrix at each right-hand
+                            side's wavenumber: the static near entries A_s,NR
+                            with the dynamic part added (3 x 3 point rule), as
+                            the same section suggests for near-region/block
+                            preconditioners (built and inverted on the device
+                            once per wavenumber used)                            */
+  AIM_PC_UNET = 3,       /* learned grid preconditioner attached with
                             aim_plan_set_unet, applied inside flexible GMRES
                             (right preconditioning with stored Z), gated, with
                             aim_solve_opts.fallback_pc as its fallback             */
+  AIM_PC_NEARBLOCK_STATIC = 4 /* the same clusters with the static entries
+                            A_s,NR only (frequency independent; the form that
+                            section expects to be less effective: over clusters
+                            a sizeable fraction of a wavelength wide it can
+                            stall GMRES)                                         */
 } aim_pc_kind;
 
 typedef enum {
@@ -73,9 +83,12 @@ typedef enum {
   AIM_STAGE_CONVOLVE = 1,    /* q[nrhs][Ng]           -> phi[nrhs][Ng] (phi = H(k) q)  */
   AIM_STAGE_INTERPOLATE = 2, /* phi[nrhs][Ng]         -> y[nrhs][N]   (y = P^T phi)    */
   AIM_STAGE_NEAR = 3,        /* x[nrhs][N]            -> y[nrhs][N]   (y = C x)        */
-  AIM_STAGE_LEARNED_PC = 4   /* x[nrhs][N] complex128 -> y[nrhs][N] complex128,
+  AIM_STAGE_LEARNED_PC = 4,  /* x[nrhs][N] complex128 -> y[nrhs][N] complex128,
                                 y = M(x) of the attached network (aim_plan_set_unet);
                                 prec must be AIM_C128                             */
+  AIM_STAGE_NEARBLOCK_PC = 5 /* x[nrhs][N] complex128 -> y[nrhs][N] complex128,
+                                y = B_k^{-1} x of AIM_PC_NEARBLOCK at each vector's
+                                wavenumber; prec must be AIM_C128                 */
 } aim_stage;
 
 typedef enum { AIM_RHS_PLANE_WAVE = 0, AIM_RHS_GAUSSIAN_PATCH = 1 } aim_rhs_kind;
@@ -275,6 +288,12 @@ aim_status aim_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void
 #define AIM_STATIC_SCRATCH_BYTES (64u << 20)
 aim_status aim_matvec_static(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
                              int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream);
+
+/* The near-block preconditioner's clusters: cl_ptr_host[n_clusters + 1]
+ * offsets into cl_perm_host[N], the triangles of cluster c being
+ * cl_perm_host[cl_ptr_host[c] .. cl_ptr_host[c+1]) (n_clusters from
+ * aim_plan_query).  Host-only plans too. */
+aim_status aim_export_clusters(aim_plan plan, int32_t* cl_ptr_host, int32_t* cl_perm_host);
 
 /* Conventional AIM on the same plan (Sec. II-B, eqs. aimL, aimLFR, aimLP),
  * the method AIMx is measured against: per wavenumber the complex near

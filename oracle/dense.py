@@ -55,3 +55,38 @@ def dense_matvec(V, T, k: float, x, near_static, rows=None) -> np.ndarray:
     for s in range(0, rows.size, chunk):
         y[s:s + chunk] = dense_rows(V, T, k, rows[s:s + chunk], near_static) @ x
     return y
+
+
+def cluster_block(V, T, k: float, members, near_static) -> np.ndarray:
+    """The block of D over a set of triangles (rows and columns ``members``):
+    the near-region/block preconditioner of Sec. III-A built from the full
+    kernel, i.e. the static near entries with the dynamic part added."""
+    members = np.asarray(members, dtype=np.int64)
+    qp = _mesh.quad_points(V, T)
+    w = _mesh.quad_weights(V, T)
+    d = qp[members][:, None, :, None, :] - qp[members][None, :, None, :, :]
+    R = np.linalg.norm(d, axis=-1)                        # [m, m, 3, 3]
+    ww = w[members][:, None, :, None] * w[members][None, :, None, :]
+    dyn = np.sum(ww * green_dynamic(k, R), axis=(2, 3))
+    with np.errstate(divide="ignore"):
+        st = np.sum(ww * np.where(R > 0, green_static(np.where(R > 0, R, 1.0)), 0.0),
+                    axis=(2, 3))
+    ns = near_static.tocsr()
+    for a, i in enumerate(members):
+        row = ns.getrow(int(i))
+        pos = {int(c): v for c, v in zip(row.indices, row.data)}
+        for b, j in enumerate(members):
+            if int(j) in pos:
+                st[a, b] = pos[int(j)]
+    return dyn + st
+
+
+def nearblock_apply(V, T, k: float, clusters, near_static, x) -> np.ndarray:
+    """z = B^{-1} x with B block diagonal over ``clusters`` (lists of
+    triangle indices), each block the cluster_block."""
+    x = np.asarray(x, dtype=np.complex128)
+    z = np.zeros_like(x)
+    for members in clusters:
+        B = cluster_block(V, T, k, members, near_static)
+        z[..., members] = np.linalg.solve(B, x[..., members].T).T
+    return z

@@ -20,17 +20,18 @@ STATUS = {0: "AIM_OK", 1: "AIM_ERR_INVALID_ARG", 2: "AIM_ERR_GEOMETRY", 3: "AIM_
           4: "AIM_ERR_OOM", 5: "AIM_ERR_DEVICE", 6: "AIM_ERR_NOT_CONVERGED",
           7: "AIM_ERR_BREAKDOWN", 8: "AIM_ERR_STATE"}
 PREC = {"c128": 0, "c64": 1}
-PC = {"none": 0, "diag": 1, "nearblock": 2, "unet": 3}
+PC = {"none": 0, "diag": 1, "nearblock": 2, "unet": 3, "nearblock_static": 4}
 LOSS = {"error": 0, "residual": 1}
 FFT_SHAPES = 12         # AIM_FFT_SHAPES
 FFT_LAYOUTS = 4         # AIM_FFT_LAYOUTS
 SCHEDULE_LEN = 7        # AIM_SCHEDULE_LEN: five pass shapes, the layout, the interpolation mode
-STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc": 4}
+STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc": 4,
+         "nearblock_pc": 5}
 RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec",
             "aim_matvec_static", "aim_conventional_fill", "aim_matvec_conventional",
-            "aim_conventional_export", "aim_apply_stage",
+            "aim_conventional_export", "aim_export_clusters", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
             "aim_autotune", "aim_set_schedule", "aim_matvec_capture", "aim_graph_launch",
             "aim_graph_destroy", "aim_unet_create", "aim_unet_destroy", "aim_unet_num_params",
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     lib.aim_plan_query.argtypes = [vp, C.POINTER(PlanInfo)]
     lib.aim_matvec.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
     lib.aim_conventional_fill.argtypes = [vp, i32, vp]
+    lib.aim_export_clusters.argtypes = [vp, ip32, ip32]
     lib.aim_matvec_conventional.argtypes = [vp, i32, vp, vp, i32, vp]
     lib.aim_conventional_export.argtypes = [vp, C.POINTER(C.c_double), vp]
     lib.aim_matvec_static.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
@@ -521,6 +523,16 @@ class Plan:
                                            _stream_ptr(stream)))
         return y
 
+    def export_clusters(self):
+        """The near-block preconditioner's clusters: a list of index arrays."""
+        info = self.info()
+        ptr = np.empty(int(info["n_clusters"]) + 1, dtype=np.int32)
+        perm = np.empty(int(info["n"]), dtype=np.int32)
+        _check(self._lib.aim_export_clusters(self._plan,
+                                             ptr.ctypes.data_as(C.POINTER(C.c_int32)),
+                                             perm.ctypes.data_as(C.POINTER(C.c_int32))))
+        return [perm[ptr[c]:ptr[c + 1]].copy() for c in range(len(ptr) - 1)]
+
     def conventional_fill(self, freq_idx: int = 0, stream=None):
         """Conventional AIM: builds the complex near correction of wavenumber
         ``freq_idx`` on the device (aim_conventional_fill)."""
@@ -617,7 +629,7 @@ class Plan:
         import torch
         Nx, Ny, Nz = self.dims
         nrhs = inp.shape[0] if inp.dim() in (2, 4) else 1
-        if stage in ("project", "near", "learned_pc"):
+        if stage in ("project", "near", "learned_pc", "nearblock_pc"):
             self._check_vec(inp, prec, self.n, "input")
         else:
             self._check_vec(inp.reshape(nrhs, -1), prec, self.n_grid, "input grid")

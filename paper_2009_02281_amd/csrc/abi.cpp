@@ -145,6 +145,10 @@ struct aim_plan_s {
   // conventional AIM (aim_conventional_fill): complex near correction of
   // wavenumber conv_freq, complex128 and complex64 copies
   std::unique_ptr<aim::NearDevice> conv_nd;
+  // near-block preconditioner: complex128 inverses of the clusters'
+  // full-kernel blocks, one set per wavenumber (built on first use)
+  void* d_clinv_k = nullptr;
+  std::vector<char> clinv_built;
   void* d_conv64 = nullptr;
   void* d_conv32 = nullptr;
   int conv_freq = -1;
@@ -771,6 +775,19 @@ aim_status aim_matvec_static(aim_plan p, aim_precision prec, const void* x, void
   });
 }
 
+namespace {
+aim::NearDevice& near_device(aim_plan p, hipStream_t s);
+}  // namespace
+
+aim_status aim_export_clusters(aim_plan p, int32_t* cl_ptr, int32_t* cl_perm) {
+  if (!p || !cl_ptr || !cl_perm) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    no_batch(p);
+    std::copy(p->t.cl_ptr.begin(), p->t.cl_ptr.end(), cl_ptr);
+    std::copy(p->t.cl_perm.begin(), p->t.cl_perm.end(), cl_perm);
+  });
+}
+
 aim_status aim_conventional_fill(aim_plan p, int32_t freq_idx, void* hip_stream) {
   if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
   return guarded([&] {
@@ -780,15 +797,11 @@ aim_status aim_conventional_fill(aim_plan p, int32_t freq_idx, void* hip_stream)
                 "frequency index out of range");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const int64_t nnz = int64_t(p->t.col.size());
-    if (!p->conv_nd) {
-      p->conv_nd.reset(
-          new aim::NearDevice(p->t, nullptr, nullptr, p->alloc, p->free_fn, p->actx, s));
-      p->conv_nd->set_static(p->t.near_static, s);
-    }
+    aim::NearDevice& nd = near_device(p, s);
     if (!p->d_conv64) p->d_conv64 = p->dalloc(size_t(nnz) * 16, s);
     if ((p->prec & (1u << AIM_C64)) && !p->d_conv32) p->d_conv32 = p->dalloc(size_t(nnz) * 8, s);
     p->conv_freq = -1;
-    p->conv_nd->fill_conventional(p->k[freq_idx], p->d_conv64, s);
+    nd.fill_conventional(p->k[freq_idx], p->d_conv64, s);
     if (p->d_conv32) aim::launch_cast_c128_to_c64(p->d_conv64, p->d_conv32, nnz, s);
     p->conv_freq = freq_idx;
   });
@@ -1044,7 +1057,12 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
 }
 
 namespace {
-void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s);
+void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, const int32_t* dfreq,
+                   hipStream_t s);
+void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs,
+                const int32_t* dfreq, hipStream_t s);
+void ensure_nearblock(aim_plan p, int f, hipStream_t s);
+void ensure_nearblock_for(aim_plan p, const int32_t* freq_host, int nrhs, hipStream_t s);
 void check_unet_plan(aim_plan p);
 }  // namespace
 
@@ -1094,7 +1112,14 @@ aim_status aim_apply_stage(aim_plan p, aim_precision prec, aim_stage stage, cons
         AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
                     "nrhs must be in 1..max_rhs");
         check_unet_plan(p);
-        apply_unet_pc(p, in, out, nrhs, s);
+        if (p->unet_base == AIM_PC_NEARBLOCK) ensure_nearblock_for(p, freq_idx_host, nrhs, s);
+        apply_unet_pc(p, in, out, nrhs, df, s);
+        break;
+      case AIM_STAGE_NEARBLOCK_PC:
+        AIM_REQUIRE(d, AIM_ERR_INVALID_ARG,
+                    "the near-block preconditioner maps complex128 vectors (prec = AIM_C128)");
+        ensure_nearblock_for(p, freq_idx_host, nrhs, s);
+        apply_base(p, AIM_PC_NEARBLOCK, in, out, nrhs, df, s);
         break;
       default:
         throw Error(AIM_ERR_INVALID_ARG, "unknown stage");
@@ -1295,15 +1320,52 @@ void ensure_unet_buffers(aim_plan p, hipStream_t s) {
   p->u_s2 = static_cast<double*>(p->dalloc(sizeof(double) * R, s));
 }
 
-// Classical (linear) preconditioners: z = v, D^{-1} v or the near-block inverse.
-void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hipStream_t s) {
+// Near-field tables on the device without the mesh (the static entries
+// uploaded), for the conventional fill and the near-block blocks.
+aim::NearDevice& near_device(aim_plan p, hipStream_t s) {
+  if (!p->conv_nd) {
+    p->conv_nd.reset(
+        new aim::NearDevice(p->t, nullptr, nullptr, p->alloc, p->free_fn, p->actx, s));
+    p->conv_nd->set_static(p->t.near_static, s);
+  }
+  return *p->conv_nd;
+}
+
+// Builds the near-block inverses of wavenumber index f if they are missing.
+void ensure_nearblock(aim_plan p, int f, hipStream_t s) {
+  AIM_REQUIRE(f >= 0 && f < p->nfreq, AIM_ERR_INVALID_ARG, "frequency index out of range");
+  const int64_t per = p->t.cl_blk.back();  // complex values per wavenumber
+  if (!p->d_clinv_k) {
+    p->d_clinv_k = p->dalloc(size_t(per) * 16 * p->nfreq, s);
+    p->clinv_built.assign(p->nfreq, 0);
+  }
+  if (p->clinv_built[f]) return;
+  near_device(p, s).fill_cluster_inverses(
+      p->k[f], p->d_clptr, p->d_clperm, p->d_clblk, p->ncl, p->maxcl,
+      static_cast<char*>(p->d_clinv_k) + size_t(f) * per * 16, s);
+  p->clinv_built[f] = 1;
+}
+
+// ... for the wavenumbers of nrhs systems (freq_host null: all index 0); a
+// batch plan's system i is its instance i
+void ensure_nearblock_for(aim_plan p, const int32_t* freq_host, int nrhs, hipStream_t s) {
+  for (int r = 0; r < nrhs; ++r) {
+    const int f = freq_host ? freq_host[r] : 0;
+    ensure_nearblock(p->batch ? p->inst[size_t(r)].get() : p, f, s);
+  }
+}
+
+// Classical (linear) preconditioners: z = v, D^{-1} v or a near-block
+// inverse; dfreq (device) holds each system's wavenumber index.
+void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs,
+                const int32_t* dfreq, hipStream_t s) {
   const int64_t n = p->t.N;
   if (p->batch) {
     for (int i = 0; i < nrhs; ++i) {
       aim_plan_s* q = p->inst[i].get();
       const char* vi = static_cast<const char*>(v) + size_t(i) * n * 16;
       char* zi = static_cast<char*>(z) + size_t(i) * n * 16;
-      apply_base(q, pc, vi, zi, 1, s);
+      apply_base(q, pc, vi, zi, 1, dfreq + i, s);
       aim::launch_zero_words(zi + size_t(q->t.N) * 16, (n - q->t.N) * 2, s);
     }
     return;
@@ -1316,6 +1378,11 @@ void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hi
       aim::launch_diag_pc(v, p->d_dinv, z, n, nrhs, s);
       break;
     case AIM_PC_NEARBLOCK:
+      AIM_REQUIRE(p->d_clinv_k != nullptr, AIM_ERR_STATE, "near-block inverses not built");
+      aim::launch_block_pc_complex(v, z, p->d_clptr, p->d_clperm, p->d_clblk, p->d_clinv_k,
+                                   p->t.cl_blk.back(), dfreq, p->ncl, p->maxcl, n, nrhs, s);
+      break;
+    case AIM_PC_NEARBLOCK_STATIC:
       aim::launch_block_pc(v, z, p->d_clptr, p->d_clperm, p->d_clblk, p->d_clinv, p->ncl, p->maxcl,
                            n, nrhs, s);
       break;
@@ -1349,7 +1416,8 @@ void check_unet_plan(aim_plan p) {
 // Learned preconditioner (a nonlinear map, so the solve is flexible GMRES):
 //   z = B v + tau ||v|| (P^T U(g)) / area,   g = unet_input(v),
 // B the base preconditioner, U the network; the grid work is complex64.
-void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s) {
+void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, const int32_t* dfreq,
+                   hipStream_t s) {
   AIM_REQUIRE(p->unet != nullptr, AIM_ERR_STATE, "no learned preconditioner attached");
   AIM_REQUIRE(!p->batch, AIM_ERR_STATE, "no learned preconditioner on a batch plan");
   ensure_unet_buffers(p, s);  // before any of the buffers is read below
@@ -1358,15 +1426,16 @@ void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, hipStream_t s) 
   // the nrhs grids lie one after another: one batched pass of the network
   aim::unet_forward(p->unet, p->ug_in, nrhs, p->g.N[2], p->g.N[1], p->g.N[0], p->ug_out, s);
   interp_near<float>(p, AIM_C64, p->ug_out, nullptr, p->um2, nrhs, true, false, s);
-  apply_base(p, p->unet_base, v, z, nrhs, s);
+  apply_base(p, p->unet_base, v, z, nrhs, dfreq, s);
   aim::launch_unet_combine(p->um2, p->d_area, p->unet_tau, p->u_s, z, n, nrhs, s);
 }
 
-void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, hipStream_t s) {
+void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, const int32_t* dfreq,
+             hipStream_t s) {
   if (pc == AIM_PC_UNET)
-    apply_unet_pc(p, v, z, nrhs, s);
+    apply_unet_pc(p, v, z, nrhs, dfreq, s);
   else
-    apply_base(p, pc, v, z, nrhs, s);
+    apply_base(p, pc, v, z, nrhs, dfreq, s);
 }
 
 void norms_host(aim_plan p, const void* v, int nrhs, hipStream_t s, std::vector<double>& out) {
@@ -1500,7 +1569,7 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
       void* Vj = static_cast<char*>(w.V) + size_t(j) * nrhs * vec;
       // z_j = M(v_j); without a preconditioner the basis Z is V itself
       void* Zj = pc == AIM_PC_NONE ? Vj : static_cast<char*>(w.Z) + size_t(j) * nrhs * vec;
-      if (pc != AIM_PC_NONE) apply_M(p, pc, Vj, Zj, nrhs, s);
+      if (pc != AIM_PC_NONE) apply_M(p, pc, Vj, Zj, nrhs, dfreq, s);
       apply_A(p, prec, Zj, w.d, nrhs, dfreq, s, p->batch ? skip.data() : nullptr);  // w.d = A z_j
       st.matvecs++;
       // classical Gram-Schmidt, twice
@@ -1594,10 +1663,11 @@ extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs
     AIM_REQUIRE(o.rtol > 0.0 && std::isfinite(o.rtol), AIM_ERR_INVALID_ARG, "rtol must be positive");
     AIM_REQUIRE(o.restart >= 1 && o.restart <= 200, AIM_ERR_INVALID_ARG, "restart must be in 1..200");
     AIM_REQUIRE(o.max_iter >= 1, AIM_ERR_INVALID_ARG, "max_iter must be >= 1");
-    AIM_REQUIRE(o.pc >= AIM_PC_NONE && o.pc <= AIM_PC_UNET, AIM_ERR_INVALID_ARG,
+    AIM_REQUIRE(o.pc >= AIM_PC_NONE && o.pc <= AIM_PC_NEARBLOCK_STATIC, AIM_ERR_INVALID_ARG,
                 "unknown preconditioner");
-    AIM_REQUIRE(o.fallback_pc >= AIM_PC_NONE && o.fallback_pc <= AIM_PC_NEARBLOCK,
-                AIM_ERR_INVALID_ARG, "fallback preconditioner must be none, diag or nearblock");
+    AIM_REQUIRE(o.fallback_pc >= AIM_PC_NONE && o.fallback_pc <= AIM_PC_NEARBLOCK_STATIC &&
+                    o.fallback_pc != AIM_PC_UNET,
+                AIM_ERR_INVALID_ARG, "fallback preconditioner must be a classical one");
     AIM_REQUIRE(o.pc != AIM_PC_UNET || p->unet != nullptr, AIM_ERR_STATE,
                 "no learned preconditioner attached (aim_plan_set_unet)");
     check_prec(p, AIM_C128);
@@ -1606,6 +1676,10 @@ extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs
     const double t0 = now_s();
     const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
     ensure_solver(p, nrhs, o.restart, s);
+    // full-kernel near-block inverses at the systems' wavenumbers, if used
+    if (o.pc == AIM_PC_NEARBLOCK || o.fallback_pc == AIM_PC_NEARBLOCK ||
+        (o.pc == AIM_PC_UNET && p->unet_base == AIM_PC_NEARBLOCK))
+      ensure_nearblock_for(p, freq_idx_host, nrhs, s);
     auto& w = p->sv;
     const int64_t n = p->t.N;
     const size_t vec = size_t(n) * 16;
@@ -1740,8 +1814,9 @@ extern "C" aim_status aim_plan_set_unet(aim_plan p, aim_unet net, aim_pc_kind ba
   if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
   return guarded([&] {
     no_batch(p);
-    AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK, AIM_ERR_INVALID_ARG,
-                "base preconditioner must be none, diag or nearblock");
+    AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK_STATIC &&
+                    base_pc != AIM_PC_UNET,
+                AIM_ERR_INVALID_ARG, "base preconditioner must be a classical one");
     AIM_REQUIRE(std::isfinite(tau) && tau > 0.0, AIM_ERR_INVALID_ARG, "tau must be positive");
     if (net) check_unet_plan(p);
     p->unet = net;
@@ -1821,8 +1896,9 @@ extern "C" aim_status aim_pc_targets(aim_plan p, aim_pc_kind base_pc, aim_pc_los
   return guarded([&] {
     no_batch(p);
     AIM_REQUIRE(npairs >= 0, AIM_ERR_INVALID_ARG, "npairs must be >= 0");
-    AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK, AIM_ERR_INVALID_ARG,
-                "base preconditioner must be none, diag or nearblock");
+    AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK_STATIC &&
+                    base_pc != AIM_PC_UNET,
+                AIM_ERR_INVALID_ARG, "base preconditioner must be a classical one");
     AIM_REQUIRE(kind == AIM_LOSS_ERROR || kind == AIM_LOSS_RESIDUAL, AIM_ERR_INVALID_ARG,
                 "unknown loss kind");
     check_unet_plan(p);
@@ -1840,7 +1916,10 @@ extern "C" aim_status aim_pc_targets(aim_plan p, aim_pc_kind base_pc, aim_pc_los
       char* tg = static_cast<char*>(target_out) + size_t(k0) * vec;
       unet_input(p, rr, nb, static_cast<char*>(grid_out) + size_t(k0) * Ng * 8, s);
       void* br = p->sv.w;
-      apply_base(p, base_pc, rr, br, nb, s);  // B r
+      // the pairs are logged at wavenumber index 0
+      const int32_t* df0 = set_freq(p, nullptr, nb, s);
+      if (base_pc == AIM_PC_NEARBLOCK) ensure_nearblock(p, 0, s);
+      apply_base(p, base_pc, rr, br, nb, df0, s);  // B r
       if (kind == AIM_LOSS_RESIDUAL) {
         // s = (r - A B r) / ||r||: what is left of the normalised residual
         // after the base preconditioner's step

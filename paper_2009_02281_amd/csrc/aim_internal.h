@@ -230,6 +230,12 @@ void launch_diag_pc(const void* v, const double* dinv, void* z, int64_t n, int n
 void launch_block_pc(const void* v, void* z, const int32_t* cl_ptr, const int32_t* cl_perm,
                      const int64_t* cl_blk, const double* cl_inv, int ncl, int max_cl,
                      int64_t n, int nrhs, hipStream_t s);
+// the same with complex128 block inverses, one set per wavenumber
+// (freq_stride values apart), vector r taking the set rhs_freq[r] (device)
+void launch_block_pc_complex(const void* v, void* z, const int32_t* cl_ptr,
+                             const int32_t* cl_perm, const int64_t* cl_blk, const void* cl_inv,
+                             int64_t freq_stride, const int32_t* rhs_freq, int ncl, int max_cl,
+                             int64_t n, int nrhs, hipStream_t s);
 // gather/scatter of whole right-hand-side rows: dst[r] = src[idx[r]] (or reverse)
 void launch_gather_rows(const void* src, void* dst, const int32_t* idx, int64_t n, int nrhs,
                         bool scatter, hipStream_t s);
@@ -294,6 +300,12 @@ class NearDevice {
   void fill_static(std::vector<double>& near_static, std::vector<double>& corr, hipStream_t s);
   void set_static(const std::vector<double>& near_static, hipStream_t s);
   void fill_conventional(double k, void* out_dev, hipStream_t s);
+  // inverses of the clusters' blocks of the full-kernel Galerkin matrix at
+  // wavenumber k (complex128, row-major, at cl_blk offsets; device arrays);
+  // throws AIM_ERR_GEOMETRY for a singular block
+  void fill_cluster_inverses(double k, const int32_t* cl_ptr, const int32_t* cl_perm,
+                             const int64_t* cl_blk, int ncl, int max_cluster, void* out_dev,
+                             hipStream_t s);
   int64_t nnz() const { return nnz_; }
 
  private:

@@ -2168,6 +2168,42 @@ __global__ __launch_bounds__(64) void block_pc_kernel(const double2* __restrict_
   }
 }
 
+// complex block inverses: vector r uses the set of wavenumber rhs_freq[r],
+// stored freq_stride complex values after the previous one
+__global__ __launch_bounds__(64) void block_pc_complex_kernel(
+    const double2* __restrict__ v, double2* __restrict__ z, const int32_t* __restrict__ cl_ptr,
+    const int32_t* __restrict__ perm, const int64_t* __restrict__ cl_blk,
+    const double2* __restrict__ inv, int64_t freq_stride, const int32_t* __restrict__ rhs_freq,
+    int64_t n) {
+  __shared__ double2 sv[64];
+  const int c = blockIdx.x, r = blockIdx.y, a = threadIdx.x;
+  const int o = cl_ptr[c], m = cl_ptr[c + 1] - o;
+  const double2* vr = v + int64_t(r) * n;
+  if (a < m) sv[a] = vr[perm[o + a]];
+  __syncthreads();
+  if (a < m) {
+    const double2* row = inv + int64_t(rhs_freq[r]) * freq_stride + cl_blk[c] + int64_t(a) * m;
+    double ar = 0.0, ai = 0.0;
+    for (int b = 0; b < m; ++b) {
+      const double2 w = row[b], x = sv[b];
+      ar += w.x * x.x - w.y * x.y;
+      ai += w.x * x.y + w.y * x.x;
+    }
+    z[int64_t(r) * n + perm[o + a]] = make_double2(ar, ai);
+  }
+}
+
+void launch_block_pc_complex(const void* v, void* z, const int32_t* cl_ptr,
+                             const int32_t* cl_perm, const int64_t* cl_blk, const void* cl_inv,
+                             int64_t freq_stride, const int32_t* rhs_freq, int ncl, int max_cl,
+                             int64_t n, int nrhs, hipStream_t s) {
+  AIM_REQUIRE(max_cl <= 64, AIM_ERR_STATE, "cluster larger than 64");
+  hipLaunchKernelGGL(block_pc_complex_kernel, dim3(ncl, nrhs), dim3(64), 0, s,
+                     static_cast<const double2*>(v), static_cast<double2*>(z), cl_ptr, cl_perm,
+                     cl_blk, static_cast<const double2*>(cl_inv), freq_stride, rhs_freq, n);
+  AIM_HIP(hipGetLastError());
+}
+
 void launch_block_pc(const void* v, void* z, const int32_t* cl_ptr, const int32_t* cl_perm,
                      const int64_t* cl_blk, const double* cl_inv, int ncl, int max_cl, int64_t n,
                      int nrhs, hipStream_t s) {

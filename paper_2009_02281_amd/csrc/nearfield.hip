@@ -270,6 +270,133 @@ __global__ __launch_bounds__(128) void near_dynamic_kernel(NearArgs a, const dou
 
 unsigned blocks_for(int64_t n) { return unsigned((n + 127) / 128); }
 
+// Galerkin entry of the full kernel by the 3 x 3 point rule, split as the
+// dense reference does: the smooth remainder G_d = G - G_s for every pair
+// and, for pairs outside the near list, the static kernel too (pairs in the
+// near list take their directly integrated static entry instead)
+__device__ double2 pair_rule(const NearArgs& a, int64_t i, int64_t j, bool with_static) {
+  double re = 0.0, im = 0.0;
+  for (int s = 0; s < 3; ++s)
+    for (int t = 0; t < 3; ++t) {
+      const int64_t qa = 3 * i + s, qb = 3 * j + t;
+      const P3 ra = {a.qp[3 * qa], a.qp[3 * qa + 1], a.qp[3 * qa + 2]};
+      const P3 rb = {a.qp[3 * qb], a.qp[3 * qb + 1], a.qp[3 * qb + 2]};
+      const double R = len(sub(ra, rb));
+      const double w = a.qw[qa] * a.qw[qb];
+      if (R == 0.0) {
+        im -= w * a.k * kInvFourPi;
+      } else {
+        double sn, cs;
+        sincos(0.5 * a.k * R, &sn, &cs);
+        re -= w * 2.0 * sn * sn * kInvFourPi / R;
+        im -= w * 2.0 * sn * cs * kInvFourPi / R;
+        if (with_static) re += w * kInvFourPi / R;
+      }
+    }
+  return make_double2(re, im);
+}
+
+// position of j in the sorted near-list row i, or -1
+__device__ int64_t near_index(const NearArgs& a, int64_t i, int64_t j) {
+  int64_t lo = a.rowptr[i], hi = a.rowptr[i + 1];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    const int64_t c = a.col[mid];
+    if (c == j) return mid;
+    if (c < j) lo = mid + 1;
+    else hi = mid;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ double2 cmul2(double2 x, double2 y) {
+  return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+}
+
+// One workgroup per cluster: the block of the full-kernel Galerkin matrix
+// over the cluster's triangles, then its inverse by Gauss-Jordan elimination
+// with partial pivoting in LDS.  A zero pivot sets *singular.
+constexpr int kMaxBlock = 64;
+__global__ __launch_bounds__(256) void cluster_block_kernel(NearArgs a, const double* near_static,
+                                                            const int32_t* cl_ptr,
+                                                            const int32_t* perm,
+                                                            const int64_t* cl_blk, double2* inv,
+                                                            int* singular) {
+  __shared__ double2 A[kMaxBlock * kMaxBlock];
+  __shared__ double2 B[kMaxBlock * kMaxBlock];
+  __shared__ double2 f[kMaxBlock];
+  __shared__ double mag[kMaxBlock];
+  __shared__ int arg[kMaxBlock];
+  const int c = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int o = cl_ptr[c], m = cl_ptr[c + 1] - o;
+  for (int e = tid; e < m * m; e += nt) {
+    const int r = e / m, q = e - r * m;
+    const int64_t i = perm[o + r], j = perm[o + q];
+    const int64_t pn = near_index(a, i, j);
+    double2 v = pair_rule(a, i, j, pn < 0);
+    if (pn >= 0) v.x += near_static[pn];
+    A[e] = v;
+    B[e] = make_double2(r == q ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int kk = 0; kk < m; ++kk) {
+    // pivot: the row at or below kk with the largest |A[r][kk]|
+    if (tid < kMaxBlock) {
+      const int r = kk + tid;
+      mag[tid] = r < m ? A[r * m + kk].x * A[r * m + kk].x + A[r * m + kk].y * A[r * m + kk].y : -1.0;
+      arg[tid] = r;
+    }
+    __syncthreads();
+    for (int w = kMaxBlock / 2; w > 0; w >>= 1) {
+      if (tid < w && (mag[tid + w] > mag[tid] ||
+                      (mag[tid + w] == mag[tid] && arg[tid + w] < arg[tid]))) {
+        mag[tid] = mag[tid + w];
+        arg[tid] = arg[tid + w];
+      }
+      __syncthreads();
+    }
+    const int pr = arg[0];
+    if (mag[0] <= 0.0) {
+      if (tid == 0) *singular = 1;
+      return;  // uniform: every thread reads the same mag[0]
+    }
+    if (pr != kk)
+      for (int q = tid; q < m; q += nt) {
+        const double2 t1 = A[kk * m + q], t2 = B[kk * m + q];
+        A[kk * m + q] = A[pr * m + q];
+        B[kk * m + q] = B[pr * m + q];
+        A[pr * m + q] = t1;
+        B[pr * m + q] = t2;
+      }
+    __syncthreads();
+    // scale the pivot row by 1 / pivot (every thread reads the pivot before
+    // any thread rewrites the row)
+    const double2 pv = A[kk * m + kk];
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    const double2 ip = make_double2(pv.x / den, -pv.y / den);
+    __syncthreads();
+    for (int q = tid; q < m; q += nt) {
+      A[kk * m + q] = cmul2(A[kk * m + q], ip);
+      B[kk * m + q] = cmul2(B[kk * m + q], ip);
+    }
+    __syncthreads();
+    // eliminate column kk from every other row
+    for (int r = tid; r < m; r += nt) f[r] = A[r * m + kk];
+    __syncthreads();
+    for (int e = tid; e < m * m; e += nt) {
+      const int r = e / m, q = e - r * m;
+      if (r == kk) continue;
+      const double2 fr = f[r];
+      const double2 ak = A[kk * m + q], bk = B[kk * m + q];
+      A[e] = make_double2(A[e].x - (fr.x * ak.x - fr.y * ak.y), A[e].y - (fr.x * ak.y + fr.y * ak.x));
+      B[e] = make_double2(B[e].x - (fr.x * bk.x - fr.y * bk.y), B[e].y - (fr.x * bk.y + fr.y * bk.x));
+    }
+    __syncthreads();
+  }
+  double2* out = inv + cl_blk[c];
+  for (int e = tid; e < m * m; e += nt) out[e] = B[e];
+}
+
 }  // namespace
 
 void* NearDevice::get(size_t bytes) {
@@ -398,6 +525,34 @@ void NearDevice::set_static(const std::vector<double>& near_static, hipStream_t 
   put(static_, near_static, s);
   AIM_HIP(hipStreamSynchronize(s));
   have_static_ = true;
+}
+
+void NearDevice::fill_cluster_inverses(double k, const int32_t* cl_ptr, const int32_t* cl_perm,
+                                       const int64_t* cl_blk, int ncl, int max_cluster,
+                                       void* out_dev, hipStream_t s) {
+  AIM_REQUIRE(have_static_, AIM_ERR_STATE, "static near field not on the device");
+  AIM_REQUIRE(max_cluster <= kMaxBlock, AIM_ERR_INVALID_ARG, "cluster larger than 64 triangles");
+  const NearArgs a = make_args(tri_, qp_, qw_, qstart_, qlocal_, rowptr_, col_, N_, nnz_, h_, k);
+  int* flag = nullptr;
+  AIM_HIP(hipMalloc(&flag, sizeof(int)));
+  int h_flag = 0;
+  try {
+    AIM_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    if (ncl > 0) {
+      hipLaunchKernelGGL(cluster_block_kernel, dim3(unsigned(ncl)), dim3(256), 0, s, a,
+                         static_cast<const double*>(static_), cl_ptr, cl_perm, cl_blk,
+                         static_cast<double2*>(out_dev), flag);
+      AIM_HIP(hipGetLastError());
+    }
+    AIM_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    AIM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(flag);
+    throw;
+  }
+  (void)hipFree(flag);
+  AIM_REQUIRE(h_flag == 0, AIM_ERR_GEOMETRY, "singular near-field preconditioner block");
 }
 
 void NearDevice::fill_conventional(double k, void* out_dev, hipStream_t s) {

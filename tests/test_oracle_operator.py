@@ -292,3 +292,19 @@ def test_gmres_small_dense_textbook():
         x, info = solver.fgmres(lambda v: A @ v, b, tol=1e-12, restart=m, max_iter=400)
         assert info.converged
         assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_cluster_block_is_the_dense_reference_restricted_to_the_cluster():
+    """The near-block preconditioner's block (full kernel: static near
+    entries plus the dynamic part) equals the dense reference matrix on the
+    cluster's rows and columns, and is complex symmetric."""
+    from oracle.dense import cluster_block, dense_rows
+    w = I.sphere_tiny(level=2, dims=(16, 16, 16), h=0.1)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, 0.25)
+    ns = o.static_near_matrix()
+    members = np.array([3, 7, 11, 40, 41, 100, 200])
+    k = 6.0
+    B = cluster_block(o.V, o.T, k, members, ns)
+    D = dense_rows(o.V, o.T, k, members, ns)[:, members]
+    assert np.max(np.abs(B - D)) <= 1e-14 * np.max(np.abs(D))
+    assert np.max(np.abs(B - B.T)) <= 1e-14 * np.max(np.abs(B))
