@@ -230,12 +230,13 @@ def solve_leg(plan, rtol: float, max_iter: int = 4000,
             "runs": res}
 
 
-def batch_leg(rtol: float) -> dict:
+def batch_leg(rtol: float, pcs=("diag", "nearblock")) -> dict:
     """One batched solve over 32 uneven geometries behind one plan
-    (aim_setup_batch) against the same 32 systems solved one after another
-    on their own plans: GMRES(RESTART) to rtol with the diagonal
-    preconditioner, complex64 matvecs inside complex128 refinement, a +z
-    plane wave per instance (each computed on its own plan)."""
+    (aim_setup_batch; the instances' matvecs run concurrently on the plan's
+    worker streams) against the same 32 systems solved one after another on
+    their own plans: GMRES(RESTART) to rtol, complex64 matvecs inside
+    complex128 refinement, a +z plane wave per instance (each computed on its
+    own plan), for each preconditioner in pcs."""
     import torch
     from paper_2009_02281_amd import binding
     from paper_2009_02281_amd import inputs as I
@@ -249,42 +250,47 @@ def batch_leg(rtol: float) -> dict:
     bp = binding.Plan.setup_batch(ws)
     t_batch_setup = time.perf_counter() - t0
     B = bp.pack([b[0] for b in bs])
-    opts = dict(rtol=rtol, restart=RESTART, max_iter=4000, pc="diag", inner="c64", max_refine=4,
-                raise_on_fail=False)
-    warm = dict(rtol=1e-2, restart=RESTART, max_iter=20, pc="diag", inner="c64",
-                raise_on_fail=False)
-    bp.solve(B, **warm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, r = bp.solve(B, **opts)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    print(f"[bench] batch of {len(ws)}: one batched solve {t_batch:.3f}s, iters "
-          f"{int(r.iters.min())}..{int(r.iters.max())}", file=sys.stderr, flush=True)
-    sep_s, sep_it, sep_ok = 0.0, [], True
-    for p, b in zip(plans, bs):
-        p.solve(b, **warm)
+    out = {"instances": len(ws), "triangles_total": int(sum(w.n for w in ws)),
+           "triangles_range": [int(min(w.n for w in ws)), int(max(w.n for w in ws))],
+           "k_range": [float(min(w.k[0] for w in ws)), float(max(w.k[0] for w in ws))],
+           "grids": sorted({"x".join(map(str, w.dims)) for w in ws}),
+           "rtol": rtol, "restart": RESTART, "inner": "c64",
+           "setup_seconds": {"batched": t_batch_setup, "one_after_another": t_sep_setup},
+           "runs": {}}
+    for pc in pcs:
+        opts = dict(rtol=rtol, restart=RESTART, max_iter=4000, pc=pc, inner="c64", max_refine=4,
+                    raise_on_fail=False)
+        warm = dict(rtol=1e-2, restart=RESTART, max_iter=20, pc=pc, inner="c64",
+                    raise_on_fail=False)
+        bp.solve(B, **warm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, ri = p.solve(b, **opts)
+        _, r = bp.solve(B, **opts)
         torch.cuda.synchronize()
-        sep_s += time.perf_counter() - t0
-        sep_it.append(int(ri.iters[0]))
-        sep_ok = sep_ok and bool(ri.converged[0])
-    print(f"[bench] batch of {len(ws)}: one after another {sep_s:.3f}s", file=sys.stderr,
-          flush=True)
+        t_batch = time.perf_counter() - t0
+        print(f"[bench] batch of {len(ws)} ({pc}): one batched solve {t_batch:.3f}s, iters "
+              f"{int(r.iters.min())}..{int(r.iters.max())}, converged {int(r.converged.sum())}",
+              file=sys.stderr, flush=True)
+        sep_s, sep_it, sep_conv = 0.0, [], 0
+        for p, b in zip(plans, bs):
+            p.solve(b, **warm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, ri = p.solve(b, **opts)
+            torch.cuda.synchronize()
+            sep_s += time.perf_counter() - t0
+            sep_it.append(int(ri.iters[0]))
+            sep_conv += int(ri.converged[0])
+        print(f"[bench] batch of {len(ws)} ({pc}): one after another {sep_s:.3f}s, converged "
+              f"{sep_conv}", file=sys.stderr, flush=True)
+        out["runs"][pc] = {"batched": {"seconds": t_batch, "iters": r.iters.tolist(),
+                                       "converged": int(r.converged.sum())},
+                           "one_after_another": {"seconds": sep_s, "iters": sep_it,
+                                                 "converged": sep_conv}}
     bp.close()
     for p in plans:
         p.close()
-    return {"instances": len(ws), "triangles_total": int(sum(w.n for w in ws)),
-            "triangles_range": [int(min(w.n for w in ws)), int(max(w.n for w in ws))],
-            "k_range": [float(min(w.k[0] for w in ws)), float(max(w.k[0] for w in ws))],
-            "grids": sorted({"x".join(map(str, w.dims)) for w in ws}),
-            "rtol": rtol, "restart": RESTART, "pc": "diag", "inner": "c64",
-            "batched": {"seconds": t_batch, "iters": r.iters.tolist(),
-                        "converged": bool(r.converged.all()), "setup_seconds": t_batch_setup},
-            "one_after_another": {"seconds": sep_s, "iters": sep_it, "converged": sep_ok,
-                                  "setup_seconds": t_sep_setup}}
+    return out
 
 
 def learned_pc_leg(rtol: float) -> dict:

@@ -128,6 +128,11 @@ struct aim_plan_s {
   // vectors are the first N_i entries of a row of length t.N = max N_i
   bool batch = false;
   std::vector<std::unique_ptr<aim_plan_s>> inst;
+  // worker streams of a batch plan: the instances' matvecs and
+  // preconditioner applications run on them concurrently (default priority)
+  std::vector<hipStream_t> workers;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
   aim_unet unet = nullptr;
   aim_pc_kind unet_base = AIM_PC_DIAG;
   double unet_tau = 1.0;
@@ -219,6 +224,10 @@ struct aim_plan_s {
       else
         (void)hipFree(o.first);
     }
+    for (hipStream_t w : workers) (void)hipStreamSynchronize(w);
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (hipStream_t w : workers) (void)hipStreamDestroy(w);
     if (h_rhs_freq) (void)hipHostFree(h_rhs_freq);
     if (sv.nrm_host) (void)hipHostFree(sv.nrm_host);
     if (sv.H_host) (void)hipHostFree(sv.H_host);
@@ -345,6 +354,34 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
 // skip (batch plans only, may be null): systems whose product is not
 // needed (GMRES systems that have stopped); their rows of y are left as they
 // are, and the caller must not read them
+// Runs fn(i, stream) for the instances i of a batch plan that are not
+// skipped, dealt round robin to the plan's worker streams after the work
+// already queued on s and before the work queued on s afterwards (on s
+// itself, one after another, while s is being captured into a graph).
+template <typename F>
+void batch_fork(aim_plan p, int n, const char* skip, hipStream_t s, F&& fn) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  AIM_HIP(hipStreamIsCapturing(s, &cap));
+  if (p->workers.empty() || cap != hipStreamCaptureStatusNone) {
+    for (int i = 0; i < n; ++i)
+      if (!(skip && skip[i])) fn(i, s);
+    return;
+  }
+  const int W = int(p->workers.size());
+  AIM_HIP(hipEventRecord(p->fork_ev, s));
+  for (int w = 0; w < W; ++w) AIM_HIP(hipStreamWaitEvent(p->workers[w], p->fork_ev, 0));
+  int next = 0;
+  for (int i = 0; i < n; ++i) {
+    if (skip && skip[i]) continue;
+    fn(i, p->workers[next % W]);
+    ++next;
+  }
+  for (int w = 0; w < W; ++w) {
+    AIM_HIP(hipEventRecord(p->join_ev[w], p->workers[w]));
+    AIM_HIP(hipStreamWaitEvent(s, p->join_ev[w], 0));
+  }
+}
+
 void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev = nullptr,
                 const char* skip = nullptr) {
@@ -354,14 +391,13 @@ void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs
                 "a batch plan applies one system per instance");
     const size_t cb = prec == AIM_C128 ? 16 : 8;
     const int64_t nmax = p->t.N;
-    for (int i = 0; i < nrhs; ++i) {
+    batch_fork(p, nrhs, skip, s, [&](int i, hipStream_t si) {
       aim_plan_s* q = p->inst[i].get();
       const char* xi = static_cast<const char*>(x) + size_t(i) * nmax * cb;
       char* yi = static_cast<char*>(y) + size_t(i) * nmax * cb;
-      if (skip && skip[i]) continue;
-      matvec_any(q, prec, xi, yi, 1, dfreq + i, s);
-      aim::launch_zero_words(yi + size_t(q->t.N) * cb, (nmax - q->t.N) * int64_t(cb / 8), s);
-    }
+      matvec_any(q, prec, xi, yi, 1, dfreq + i, si);
+      aim::launch_zero_words(yi + size_t(q->t.N) * cb, (nmax - q->t.N) * int64_t(cb / 8), si);
+    });
     return;
   }
   if (prec == AIM_C128)
@@ -677,6 +713,18 @@ aim_status aim_setup_batch(const aim_setup_desc* descs, int32_t n, void* hip_str
     }
     AIM_REQUIRE(b->prec != 0, AIM_ERR_INVALID_ARG, "the instances share no precision");
     b->d_rhs_freq = static_cast<int32_t*>(b->dalloc(sizeof(int32_t) * n, s));
+    // worker streams for the instances' concurrent matvecs (as many as the
+    // device has hardware queues by default)
+    constexpr int kWorkers = 4;
+    for (int w = 0; w < kWorkers && w < n; ++w) {
+      hipStream_t ws = nullptr;
+      AIM_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+      b->workers.push_back(ws);
+      hipEvent_t e = nullptr;
+      AIM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->join_ev.push_back(e);
+    }
+    AIM_HIP(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
     AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&b->h_rhs_freq), sizeof(int32_t) * n, 0));
     AIM_HIP(hipStreamSynchronize(s));
     b->t.setup_seconds = now_s() - t0;
@@ -1361,13 +1409,13 @@ void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs,
                 const int32_t* dfreq, hipStream_t s) {
   const int64_t n = p->t.N;
   if (p->batch) {
-    for (int i = 0; i < nrhs; ++i) {
+    batch_fork(p, nrhs, nullptr, s, [&](int i, hipStream_t si) {
       aim_plan_s* q = p->inst[i].get();
       const char* vi = static_cast<const char*>(v) + size_t(i) * n * 16;
       char* zi = static_cast<char*>(z) + size_t(i) * n * 16;
-      apply_base(q, pc, vi, zi, 1, dfreq + i, s);
-      aim::launch_zero_words(zi + size_t(q->t.N) * 16, (n - q->t.N) * 2, s);
-    }
+      apply_base(q, pc, vi, zi, 1, dfreq + i, si);
+      aim::launch_zero_words(zi + size_t(q->t.N) * 16, (n - q->t.N) * 2, si);
+    });
     return;
   }
   switch (pc) {
