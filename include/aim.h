@@ -289,6 +289,18 @@ aim_status aim_matvec(aim_plan plan, aim_precision prec, const void* x_dev, void
 aim_status aim_matvec_static(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
                              int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream);
 
+/* The linear-term modification of Sec. III-A ("Modification for Increased
+ * Accuracy", eqs. linterm and Lmatdecomplin): with on != 0, every matvec and
+ * solve of the plan adds k^2 D x, where D is the real diagonal
+ * A_lin[i, i] - (W H_lin P)[i, i] of G_lin = -R/(8 pi): the linear Taylor term
+ * of the dynamic kernel integrated directly where a basis function overlaps
+ * itself (3-point outer rule, closed-form inner integral), minus what the
+ * grid already gives for it.  D is computed by aim_setup's device near fill
+ * (AIM_ERR_STATE on plans without it: host-only or loaded from a file).
+ * Off by default.  aim_export_lin_diag copies D ([N] doubles) to the host. */
+aim_status aim_set_lin_term(aim_plan plan, int32_t on);
+aim_status aim_export_lin_diag(aim_plan plan, double* d_host);
+
 /* The near-block preconditioner's clusters: cl_ptr_host[n_clusters + 1]
  * offsets into cl_perm_host[N], the triangles of cluster c being
  * cl_perm_host[cl_ptr_host[c] .. cl_ptr_host[c+1]) (n_clusters from

@@ -90,3 +90,17 @@ def nearblock_apply(V, T, k: float, clusters, near_static, x) -> np.ndarray:
         B = cluster_block(V, T, k, members, near_static)
         z[..., members] = np.linalg.solve(B, x[..., members].T).T
     return z
+
+
+def self_lin_correction(V, T, k: float) -> np.ndarray:
+    """Change of the dense reference's self entries when their linear
+    dynamic term k^2 G_lin = -k^2 R/(8 pi) (eq. linterm) is integrated
+    directly (closed-form inner integral) instead of by the 3 x 3 point rule
+    (the accuracy modification of Sec. III-A): per triangle,
+    k^2 (A_lin[i, i] - sum_p sum_q (A_i/3)^2 G_lin(|r_ip - r_iq|))."""
+    from .lin import lin_self
+    qp = _mesh.quad_points(V, T)
+    w = _mesh.quad_weights(V, T)
+    R = np.linalg.norm(qp[:, :, None, :] - qp[:, None, :, :], axis=-1)   # [N, 3, 3]
+    rule = np.sum(w[:, :, None] * w[:, None, :] * (-R / (8.0 * np.pi)), axis=(1, 2))
+    return (k * k) * (lin_self(V, T) - rule)

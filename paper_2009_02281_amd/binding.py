@@ -31,7 +31,8 @@ RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec",
             "aim_matvec_static", "aim_conventional_fill", "aim_matvec_conventional",
-            "aim_conventional_export", "aim_export_clusters", "aim_apply_stage",
+            "aim_conventional_export", "aim_export_clusters", "aim_set_lin_term",
+            "aim_export_lin_diag", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
             "aim_autotune", "aim_set_schedule", "aim_matvec_capture", "aim_graph_launch",
             "aim_graph_destroy", "aim_unet_create", "aim_unet_destroy", "aim_unet_num_params",
@@ -116,6 +117,8 @@ def load_library(path: str = LIB_PATH):
     lib.aim_matvec.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
     lib.aim_conventional_fill.argtypes = [vp, i32, vp]
     lib.aim_export_clusters.argtypes = [vp, ip32, ip32]
+    lib.aim_set_lin_term.argtypes = [vp, i32]
+    lib.aim_export_lin_diag.argtypes = [vp, C.POINTER(C.c_double)]
     lib.aim_matvec_conventional.argtypes = [vp, i32, vp, vp, i32, vp]
     lib.aim_conventional_export.argtypes = [vp, C.POINTER(C.c_double), vp]
     lib.aim_matvec_static.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
@@ -522,6 +525,17 @@ class Plan:
                                            C.c_void_p(y.data_ptr()), nrhs, fp,
                                            _stream_ptr(stream)))
         return y
+
+    def set_lin_term(self, on: bool = True):
+        """Adds (or removes) the linear-term modification k^2 D x to every
+        matvec and solve of the plan (aim_set_lin_term)."""
+        _check(self._lib.aim_set_lin_term(self._plan, 1 if on else 0))
+
+    def lin_diagonal(self) -> np.ndarray:
+        """The linear-term diagonal D, float64 [N]."""
+        out = np.empty(int(self.info()["n"]), dtype=np.float64)
+        _check(self._lib.aim_export_lin_diag(self._plan, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def export_clusters(self):
         """The near-block preconditioner's clusters: a list of index arrays."""

@@ -122,6 +122,8 @@ struct aim_plan_s {
   void* d_tw64[3] = {nullptr, nullptr, nullptr};
   void* d_tw32[3] = {nullptr, nullptr, nullptr};
   double* d_k = nullptr;
+  double* d_lin = nullptr;               // linear-term diagonal D (may be absent)
+  bool lin_on = false;                   // matvecs add k^2 D x
   double* d_area = nullptr;              // triangle areas (learned preconditioner)
   // learned preconditioner (not owned) and its buffers
   // batch of geometries (aim_setup_batch): instance i owns system i, whose
@@ -348,6 +350,7 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
                           ev ? ev + 2 : nullptr, p->sched[pi], repeat);
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
   for (int r = 0; r < repeat; ++r) interp_near<T>(p, prec, grid, x, y, nrhs, true, near, s);
+  if (near && p->lin_on) aim::launch_lin_term<T>(p->d_lin, p->d_k, dfreq, x, y, p->t.N, nrhs, s);
   if (ev) AIM_HIP(hipEventRecord(ev[7], s));
 }
 
@@ -510,7 +513,7 @@ void fill_near_device(aim_plan_s* p, const aim_setup_desc& d, hipStream_t s) {
   const double t0 = now_s();
   {
     aim::NearDevice nd(p->t, d.vertices, d.triangles, d.alloc, d.free, d.alloc_ctx, s);
-    nd.fill_static(p->t.near_static, p->t.corr, s);
+    nd.fill_static(p->t.near_static, p->t.corr, p->t.lin_diag, s);
   }
   p->t.near_seconds = now_s() - t0;
   p->near_on_device = true;
@@ -590,6 +593,7 @@ void init_device(aim_plan_s* p, hipStream_t hip_stream) {
       p->d_clinv = p->upload(t.cl_inv, s);
     }
     p->d_k = p->upload(p->k, s);
+    if (!t.lin_diag.empty()) p->d_lin = p->upload(t.lin_diag, s);
     p->d_area = p->upload(t.area, s);
     // twiddles per axis
     for (int a = 0; a < 3; ++a) {
@@ -826,6 +830,31 @@ aim_status aim_matvec_static(aim_plan p, aim_precision prec, const void* x, void
 namespace {
 aim::NearDevice& near_device(aim_plan p, hipStream_t s);
 }  // namespace
+
+aim_status aim_set_lin_term(aim_plan p, int32_t on) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    auto set = [&](aim_plan q) {
+      AIM_REQUIRE(!on || q->d_lin != nullptr, AIM_ERR_STATE,
+                  "no linear-term diagonal in this plan (computed by the device set-up only)");
+      q->lin_on = on != 0;
+    };
+    if (p->batch)
+      for (auto& q : p->inst) set(q.get());
+    else
+      set(p);
+    p->lin_on = on != 0;
+  });
+}
+
+aim_status aim_export_lin_diag(aim_plan p, double* d_host) {
+  if (!p || !d_host) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    no_batch(p);
+    AIM_REQUIRE(!p->t.lin_diag.empty(), AIM_ERR_STATE, "no linear-term diagonal in this plan");
+    std::copy(p->t.lin_diag.begin(), p->t.lin_diag.end(), d_host);
+  });
+}
 
 aim_status aim_export_clusters(aim_plan p, int32_t* cl_ptr, int32_t* cl_perm) {
   if (!p || !cl_ptr || !cl_perm) return fail(AIM_ERR_INVALID_ARG, "null argument");

@@ -70,6 +70,9 @@ struct HostTables {
   std::vector<double> cl_inv;       // dense inverse blocks, row-major
   double setup_seconds = 0.0;
   double near_seconds = 0.0;        // the static near fill (host or device)
+  // diagonal D of the linear-term modification (k^2 D added to C); empty
+  // when not computed (host-only and loaded plans)
+  std::vector<double> lin_diag;
 };
 
 // Builds every host table; throws aim::Error on invalid input.  With
@@ -267,6 +270,10 @@ void launch_resid_grad(const void* y, const double* area, double coef, void* d, 
                        hipStream_t st);
 // zero n 8-byte words
 void launch_zero_words(void* p, int64_t n, hipStream_t st);
+// y[r] += k_{f_r}^2 D x[r] (the linear-term modification), f_r = rhs_freq[r]
+template <typename T>
+void launch_lin_term(const double* D, const double* k, const int32_t* rhs_freq, const void* x,
+                     void* y, int64_t n, int nrhs, hipStream_t s);
 // bytes of the fixed device array behind the no-allocation matvec
 constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 // device address of that array on the current device (looked up once per
@@ -297,7 +304,9 @@ class NearDevice {
   ~NearDevice();
   NearDevice(const NearDevice&) = delete;
   NearDevice& operator=(const NearDevice&) = delete;
-  void fill_static(std::vector<double>& near_static, std::vector<double>& corr, hipStream_t s);
+  // also the diagonal of the linear-term modification (lin_diag, N values)
+  void fill_static(std::vector<double>& near_static, std::vector<double>& corr,
+                   std::vector<double>& lin_diag, hipStream_t s);
   void set_static(const std::vector<double>& near_static, hipStream_t s);
   void fill_conventional(double k, void* out_dev, hipStream_t s);
   // inverses of the clusters' blocks of the full-kernel Galerkin matrix at

@@ -2494,6 +2494,38 @@ void launch_resid_grad(const void* y, const double* area, double coef, void* d, 
   AIM_HIP(hipGetLastError());
 }
 
+// y[r][i] += k_{f_r}^2 D_i x[r][i]
+template <typename T>
+__global__ void lin_term_kernel(const double* __restrict__ D, const double* __restrict__ k,
+                                const int32_t* __restrict__ rhs_freq, const cx<T>* __restrict__ x,
+                                cx<T>* __restrict__ y, int64_t n) {
+  const int r = blockIdx.y;
+  const double kr = k[rhs_freq[r]];
+  const T k2 = T(kr * kr);
+  const int64_t off = int64_t(r) * n;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const T d = k2 * T(D[i]);
+    const cx<T> xv = x[off + i];
+    cx<T> yv = y[off + i];
+    yv.x += d * xv.x;
+    yv.y += d * xv.y;
+    y[off + i] = yv;
+  }
+}
+
+template <typename T>
+void launch_lin_term(const double* D, const double* k, const int32_t* rhs_freq, const void* x,
+                     void* y, int64_t n, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(lin_term_kernel<T>, dim3(grid_for(n, 1024), unsigned(nrhs)), dim3(256), 0, s,
+                     D, k, rhs_freq, static_cast<const cx<T>*>(x), static_cast<cx<T>*>(y), n);
+  AIM_HIP(hipGetLastError());
+}
+template void launch_lin_term<double>(const double*, const double*, const int32_t*, const void*,
+                                      void*, int64_t, int, hipStream_t);
+template void launch_lin_term<float>(const double*, const double*, const int32_t*, const void*,
+                                     void*, int64_t, int, hipStream_t);
+
 // zero n 8-byte words (a kernel, so that captured graphs hold no memset node)
 __global__ void zero_words_kernel(uint2* p, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;

@@ -96,6 +96,32 @@ __device__ double inv_r_integral(P3 r, const P3* v) {
   return acc;
 }
 
+// integral over triangle v[0..2] of |r - r'| dS': in the plane of T,
+// div_s[(rho' - rho) R] = 3R - h^2/R gives (1/3)[sum_i P0_i int_{edge i} R dl
+// + h^2 int_T dS'/R], with int R dl = [l R + R0^2 ln(l + R)]/2
+__device__ double r_integral(P3 r, const P3* v) {
+  const P3 nn = cross(sub(v[1], v[0]), sub(v[2], v[0]));
+  const P3 n = scale(nn, 1.0 / len(nn));
+  const double h = dot(sub(r, v[0]), n);
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const P3 p = v[e], q = v[(e + 1) % 3];
+    const P3 d = sub(q, p);
+    const double L = len(d);
+    const P3 u = scale(d, 1.0 / L);
+    const P3 m = cross(u, n);
+    const P3 pr = sub(p, r), qr = sub(q, r);
+    const double P0 = dot(pr, m);
+    if (fabs(P0) <= 1e-15 * L) continue;
+    const double lm = dot(pr, u), lp = dot(qr, u), Rm = len(pr), Rp = len(qr);
+    const double R0sq = P0 * P0 + h * h;
+    acc += P0 * 0.5 * (lp * Rp - lm * Rm + R0sq * edge_integral(lm, lp, Rm, Rp, R0sq));
+  }
+  if (h != 0.0) acc += h * h * inv_r_integral(r, v);
+  return acc / 3.0;
+}
+
 struct NearArgs {
   const double* tri;       // [N][3][3] corners
   const double* qp;        // [3N][3] quadrature points
@@ -145,11 +171,22 @@ __device__ double galerkin_static(const NearArgs& a, int64_t i, int64_t j) {
 }
 
 // grid kernel at the integer offset (x, y, z): static 1/(4 pi R) with 0 at
-// the origin, or (DYN) e^{-jkR}/(4 pi R) with -jk/(4 pi) at the origin
-template <bool DYN>
+// the origin (kind 0), e^{-jkR}/(4 pi R) with -jk/(4 pi) at the origin (kind
+// 1), or the linear term G_lin = -R/(8 pi), 0 at the origin (kind 2)
+template <int KIND>
 struct GridKernel;
 template <>
-struct GridKernel<false> {
+struct GridKernel<2> {
+  using V = double;
+  static __device__ V zero() { return 0.0; }
+  static __device__ V at(int x, int y, int z, double h, double) {
+    const int q = x * x + y * y + z * z;
+    return -0.5 * kInvFourPi * h * sqrt(double(q));
+  }
+  static __device__ V fma(double w, V v, V acc) { return acc + w * v; }
+};
+template <>
+struct GridKernel<0> {
   using V = double;
   static __device__ V zero() { return 0.0; }
   static __device__ V at(int x, int y, int z, double h, double) {
@@ -159,7 +196,7 @@ struct GridKernel<false> {
   static __device__ V fma(double w, V v, V acc) { return acc + w * v; }
 };
 template <>
-struct GridKernel<true> {
+struct GridKernel<1> {
   using V = double2;
   static __device__ V zero() { return make_double2(0.0, 0.0); }
   static __device__ V at(int x, int y, int z, double h, double k) {
@@ -177,9 +214,9 @@ struct GridKernel<true> {
 };
 
 // sum over quadrature-point pairs of w_a w_b sum_{u, v} L_u(r_a) H(u - v) L_v(r_b)
-template <bool DYN, int ORDER>
-__device__ typename GridKernel<DYN>::V precorrection(const NearArgs& a, int64_t i, int64_t j) {
-  using GK = GridKernel<DYN>;
+template <int KIND, int ORDER>
+__device__ typename GridKernel<KIND>::V precorrection(const NearArgs& a, int64_t i, int64_t j) {
+  using GK = GridKernel<KIND>;
   constexpr int n = ORDER, S = n + 1, W = 2 * n + 1;
   typename GK::V pc = GK::zero();
   for (int p = 0; p < 3; ++p) {
@@ -222,6 +259,25 @@ __device__ typename GridKernel<DYN>::V precorrection(const NearArgs& a, int64_t 
   return pc;
 }
 
+// diagonal of the linear-term modification (Sec. III-A): per triangle,
+// A_lin[i, i] - (W H_lin P)[i, i] with G_lin = -R/(8 pi) integrated directly
+// (3-point outer rule, closed-form inner integral)
+template <int ORDER>
+__global__ __launch_bounds__(128) void lin_diag_kernel(NearArgs a, double* out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  P3 v[3];
+  for (int c = 0; c < 3; ++c)
+    v[c] = {a.tri[9 * i + 3 * c], a.tri[9 * i + 3 * c + 1], a.tri[9 * i + 3 * c + 2]};
+  double s = 0.0;
+  for (int p = 0; p < 3; ++p) {
+    const int64_t q = 3 * i + p;
+    const P3 r = {a.qp[3 * q], a.qp[3 * q + 1], a.qp[3 * q + 2]};
+    s += a.qw[q] * r_integral(r, v);
+  }
+  out[i] = -0.5 * kInvFourPi * s - precorrection<2, ORDER>(a, i, i);
+}
+
 template <int ORDER>
 __global__ __launch_bounds__(128) void near_static_kernel(NearArgs a, double* near_static,
                                                           double* corr) {
@@ -234,7 +290,7 @@ __global__ __launch_bounds__(128) void near_static_kernel(NearArgs a, double* ne
   const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
   const double m = 0.5 * (galerkin_static(a, lo, hi) + galerkin_static(a, hi, lo));
   near_static[p] = m;
-  corr[p] = m - precorrection<false, ORDER>(a, i, j);
+  corr[p] = m - precorrection<0, ORDER>(a, i, j);
 }
 
 // conventional AIM: A_NR(k) - A_P(k) from the static entries
@@ -264,7 +320,7 @@ __global__ __launch_bounds__(128) void near_dynamic_kernel(NearArgs a, const dou
         di -= w * s2 * kInvFourPi / R;
       }
     }
-  const double2 pc = precorrection<true, ORDER>(a, i, j);
+  const double2 pc = precorrection<1, ORDER>(a, i, j);
   out[p] = make_double2(near_static[p] + dr - pc.x, di - pc.y);
 }
 
@@ -482,13 +538,13 @@ static NearArgs make_args(const void* tri, const void* qp, const void* qw, const
 }
 
 void NearDevice::fill_static(std::vector<double>& near_static, std::vector<double>& corr,
-                             hipStream_t s) {
+                             std::vector<double>& lin_diag, hipStream_t s) {
   AIM_REQUIRE(tri_ != nullptr, AIM_ERR_STATE, "near-field tables built without the mesh");
   const NearArgs a = make_args(tri_, qp_, qw_, qstart_, qlocal_, rowptr_, col_, N_, nnz_, h_,
                                0.0);
   void* cr = nullptr;
-  if (nnz_ > 0) {
-    const hipError_t e = hipMalloc(&cr, size_t(nnz_) * 8);
+  {
+    const hipError_t e = hipMalloc(&cr, size_t(nnz_ + N_) * 8);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       throw Error(AIM_ERR_OOM, "near-field set-up: device allocation failed");
@@ -497,6 +553,16 @@ void NearDevice::fill_static(std::vector<double>& near_static, std::vector<doubl
   try {
     near_static.resize(nnz_);
     corr.resize(nnz_);
+    lin_diag.resize(N_);
+    double* ld = static_cast<double*>(cr) + nnz_;
+    if (N_ > 0) {
+      if (order_ == 2)
+        hipLaunchKernelGGL(lin_diag_kernel<2>, dim3(blocks_for(N_)), dim3(128), 0, s, a, ld);
+      else
+        hipLaunchKernelGGL(lin_diag_kernel<3>, dim3(blocks_for(N_)), dim3(128), 0, s, a, ld);
+      AIM_HIP(hipGetLastError());
+      AIM_HIP(hipMemcpyAsync(lin_diag.data(), ld, size_t(N_) * 8, hipMemcpyDeviceToHost, s));
+    }
     if (nnz_ > 0) {
       if (order_ == 2)
         hipLaunchKernelGGL(near_static_kernel<2>, dim3(blocks_for(nnz_)), dim3(128), 0, s, a,
