@@ -237,6 +237,7 @@ def batch_leg(rtol: float, pcs=("diag", "nearblock")) -> dict:
     their own plans: GMRES(RESTART) to rtol, complex64 matvecs inside
     complex128 refinement, a +z plane wave per instance (each computed on its
     own plan), for each preconditioner in pcs."""
+    import numpy as np
     import torch
     from paper_2009_02281_amd import binding
     from paper_2009_02281_amd import inputs as I
@@ -254,6 +255,7 @@ def batch_leg(rtol: float, pcs=("diag", "nearblock")) -> dict:
            "triangles_range": [int(min(w.n for w in ws)), int(max(w.n for w in ws))],
            "k_range": [float(min(w.k[0] for w in ws)), float(max(w.k[0] for w in ws))],
            "grids": sorted({"x".join(map(str, w.dims)) for w in ws}),
+           "kinds": [w.extra["kind"] for w in ws], "k": [float(w.k[0]) for w in ws],
            "rtol": rtol, "restart": RESTART, "inner": "c64",
            "setup_seconds": {"batched": t_batch_setup, "one_after_another": t_sep_setup},
            "runs": {}}
@@ -284,7 +286,9 @@ def batch_leg(rtol: float, pcs=("diag", "nearblock")) -> dict:
         print(f"[bench] batch of {len(ws)} ({pc}): one after another {sep_s:.3f}s, converged "
               f"{sep_conv}", file=sys.stderr, flush=True)
         out["runs"][pc] = {"batched": {"seconds": t_batch, "iters": r.iters.tolist(),
-                                       "converged": int(r.converged.sum())},
+                                       "converged": int(r.converged.sum()),
+                                       "unconverged": [int(i) for i in
+                                                       np.nonzero(~r.converged)[0]]},
                            "one_after_another": {"seconds": sep_s, "iters": sep_it,
                                                  "converged": sep_conv}}
     bp.close()

@@ -130,6 +130,7 @@ struct aim_plan_s {
   // vectors are the first N_i entries of a row of length t.N = max N_i
   bool batch = false;
   std::vector<std::unique_ptr<aim_plan_s>> inst;
+  int32_t* d_inst_rows = nullptr;  // [instances] N_i: the Krylov kernels skip the padding
   // worker streams of a batch plan: the instances' matvecs and
   // preconditioner applications run on them concurrently (default priority)
   std::vector<hipStream_t> workers;
@@ -360,12 +361,16 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
 // Runs fn(i, stream) for the instances i of a batch plan that are not
 // skipped, dealt round robin to the plan's worker streams after the work
 // already queued on s and before the work queued on s afterwards (on s
-// itself, one after another, while s is being captured into a graph).
+// itself, one after another, while s is being captured into a graph or when
+// at most one instance runs).
 template <typename F>
 void batch_fork(aim_plan p, int n, const char* skip, hipStream_t s, F&& fn) {
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   AIM_HIP(hipStreamIsCapturing(s, &cap));
-  if (p->workers.empty() || cap != hipStreamCaptureStatusNone) {
+  int running = 0;
+  for (int i = 0; i < n; ++i) running += (skip && skip[i]) ? 0 : 1;
+  // one running instance: no fork and join
+  if (p->workers.empty() || cap != hipStreamCaptureStatusNone || running <= 1) {
     for (int i = 0; i < n; ++i)
       if (!(skip && skip[i])) fn(i, s);
     return;
@@ -717,6 +722,11 @@ aim_status aim_setup_batch(const aim_setup_desc* descs, int32_t n, void* hip_str
     }
     AIM_REQUIRE(b->prec != 0, AIM_ERR_INVALID_ARG, "the instances share no precision");
     b->d_rhs_freq = static_cast<int32_t*>(b->dalloc(sizeof(int32_t) * n, s));
+    {
+      std::vector<int32_t> rows(n);
+      for (int i = 0; i < n; ++i) rows[i] = int32_t(b->inst[size_t(i)]->t.N);
+      b->d_inst_rows = b->upload(rows, s);
+    }
     // worker streams for the instances' concurrent matvecs (as many as the
     // device has hardware queues by default)
     constexpr int kWorkers = 4;
@@ -1137,7 +1147,7 @@ namespace {
 void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, const int32_t* dfreq,
                    hipStream_t s);
 void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs,
-                const int32_t* dfreq, hipStream_t s);
+                const int32_t* dfreq, hipStream_t s, const char* skip = nullptr);
 void ensure_nearblock(aim_plan p, int f, hipStream_t s);
 void ensure_nearblock_for(aim_plan p, const int32_t* freq_host, int nrhs, hipStream_t s);
 void check_unet_plan(aim_plan p);
@@ -1361,11 +1371,22 @@ void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, c
   if (skip && p->batch) {  // direct launches, stopped instances skipped
     if (prec == AIM_C128) {
       matvec_any(p, AIM_C128, x, y, nrhs, dfreq, s, nullptr, skip);
-    } else {
-      aim::launch_cast_c128_to_c64(x, p->sv.c64a, cnt, s);
-      matvec_any(p, AIM_C64, p->sv.c64a, p->sv.c64b, nrhs, dfreq, s, nullptr, skip);
-      aim::launch_cast_c64_to_c128(p->sv.c64b, y, cnt, s);
+      return;
     }
+    // complex64 matvecs: each running instance casts its own rows, so the
+    // stopped ones cost nothing
+    const int64_t nmax = p->t.N;
+    batch_fork(p, nrhs, skip, s, [&](int i, hipStream_t si) {
+      aim_plan_s* q = p->inst[i].get();
+      const int64_t ni = q->t.N, off = int64_t(i) * nmax;
+      void* a = static_cast<char*>(p->sv.c64a) + size_t(off) * 8;
+      void* b2 = static_cast<char*>(p->sv.c64b) + size_t(off) * 8;
+      char* yi = static_cast<char*>(y) + size_t(off) * 16;
+      aim::launch_cast_c128_to_c64(static_cast<const char*>(x) + size_t(off) * 16, a, ni, si);
+      matvec_any(q, AIM_C64, a, b2, 1, dfreq + i, si);
+      aim::launch_cast_c64_to_c128(b2, yi, ni, si);
+      aim::launch_zero_words(yi + size_t(ni) * 16, (nmax - ni) * 2, si);
+    });
     return;
   }
   if (prec == AIM_C128) {
@@ -1434,11 +1455,13 @@ void ensure_nearblock_for(aim_plan p, const int32_t* freq_host, int nrhs, hipStr
 
 // Classical (linear) preconditioners: z = v, D^{-1} v or a near-block
 // inverse; dfreq (device) holds each system's wavenumber index.
+// skip (batch plans only, may be null): systems whose result is not needed
+// (GMRES systems that have stopped); their rows of z are left as they are
 void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs,
-                const int32_t* dfreq, hipStream_t s) {
+                const int32_t* dfreq, hipStream_t s, const char* skip) {
   const int64_t n = p->t.N;
   if (p->batch) {
-    batch_fork(p, nrhs, nullptr, s, [&](int i, hipStream_t si) {
+    batch_fork(p, nrhs, skip, s, [&](int i, hipStream_t si) {
       aim_plan_s* q = p->inst[i].get();
       const char* vi = static_cast<const char*>(v) + size_t(i) * n * 16;
       char* zi = static_cast<char*>(z) + size_t(i) * n * 16;
@@ -1508,11 +1531,11 @@ void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, const int32_t* 
 }
 
 void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, const int32_t* dfreq,
-             hipStream_t s) {
+             hipStream_t s, const char* skip = nullptr) {
   if (pc == AIM_PC_UNET)
     apply_unet_pc(p, v, z, nrhs, dfreq, s);
   else
-    apply_base(p, pc, v, z, nrhs, dfreq, s);
+    apply_base(p, pc, v, z, nrhs, dfreq, s, skip);
 }
 
 void norms_host(aim_plan p, const void* v, int nrhs, hipStream_t s, std::vector<double>& out) {
@@ -1559,6 +1582,9 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
   const size_t vec = size_t(n) * 16;
   // basis layout [i][r][n]: the i-th vectors of all systems are contiguous
   const int64_t si = nrhs, sr = 1;
+  // a batch of uneven geometries: each system's Krylov vectors use only its
+  // own N_i rows (the padding stays as it is and is never read)
+  const int32_t* rows = p->batch ? p->d_inst_rows : nullptr;
   std::vector<int>& active_iters = st.iters;
   active_iters.assign(nrhs, 0);
   rel.assign(nrhs, 1.0);
@@ -1613,7 +1639,7 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
     if (all_done) return;
     const int mm = std::min(m, maxit_left);
     // V_0 = r / beta
-    aim::launch_scale_inv(w.r, w.nrm, w.V, n, nrhs, n, s);
+    aim::launch_scale_inv(w.r, w.nrm, w.V, n, nrhs, n, s, nullptr, rows);
     // cycle state on the device: g = (beta, 0, ...), the frozen flags and the
     // step counts; the Hessenberg columns and rotations stay there too, and
     // the host looks at the state only every kSyncEvery steps
@@ -1646,7 +1672,7 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
       void* Vj = static_cast<char*>(w.V) + size_t(j) * nrhs * vec;
       // z_j = M(v_j); without a preconditioner the basis Z is V itself
       void* Zj = pc == AIM_PC_NONE ? Vj : static_cast<char*>(w.Z) + size_t(j) * nrhs * vec;
-      if (pc != AIM_PC_NONE) apply_M(p, pc, Vj, Zj, nrhs, dfreq, s);
+      if (pc != AIM_PC_NONE) apply_M(p, pc, Vj, Zj, nrhs, dfreq, s, p->batch ? skip.data() : nullptr);
       apply_A(p, prec, Zj, w.d, nrhs, dfreq, s, p->batch ? skip.data() : nullptr);  // w.d = A z_j
       st.matvecs++;
       // classical Gram-Schmidt, twice
@@ -1655,14 +1681,14 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
       // (the updates sum the dot partials themselves and the scaling the
       // norm partials, so no reduction launches; the coefficients h, h2 and
       // the norm land in w.h, w.h2 and w.nrm for the Givens step)
-      aim::launch_block_dot_partials(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, s, w.gst);
-      aim::launch_gs_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h, s, w.gst);
-      aim::launch_block_dot_partials(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, s, w.gst);
-      aim::launch_gs_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h2, s, w.gst);
-      aim::launch_norm_partials(w.d, n, nrhs, w.partial, s, w.gst);
+      aim::launch_block_dot_partials(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, s, w.gst, rows);
+      aim::launch_gs_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h, s, w.gst, rows);
+      aim::launch_block_dot_partials(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, s, w.gst, rows);
+      aim::launch_gs_update(w.V, si, sr, w.d, n, j + 1, nrhs, w.partial, w.h2, s, w.gst, rows);
+      aim::launch_norm_partials(w.d, n, nrhs, w.partial, s, w.gst, rows);
       aim::launch_scale_norm(w.d, w.partial, w.nrm,
                              static_cast<char*>(w.V) + size_t(j + 1) * nrhs * vec, n, nrhs, n, s,
-                             w.gst);
+                             w.gst, rows);
       aim::launch_givens_step(w.h, w.h2, w.nrm, nrhs, j, mc, w.H, w.cs, w.sn, w.g, w.gst, w.scale,
                               tol, max_iter, s);
       if ((j + 1) % kSyncEvery == 0 || j + 1 == mm) {
@@ -1722,7 +1748,8 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
         }
       }
       AIM_HIP(hipMemcpyAsync(w.y, yh.data(), sizeof(double2) * yh.size(), hipMemcpyHostToDevice, s));
-      aim::launch_combine(pc == AIM_PC_NONE ? w.V : w.Z, si, sr, w.y, m, nv, x, n, nrhs, s);
+      aim::launch_combine(pc == AIM_PC_NONE ? w.V : w.Z, si, sr, w.y, m, nv, x, n, nrhs, w.gst, s,
+                          rows);
       AIM_HIP(hipStreamSynchronize(s));  // yh is pageable host memory
     }
   }

@@ -202,29 +202,35 @@ void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out
 // (launch_gs_update, which also stores h in h_out[r][i]), and the norm
 // partials (launch_norm_partials) feed the scaling w[r] / ||w[r]|| directly
 // (launch_scale_norm, which also stores the norms in nrm_out); partials are
-// summed in chunk order (deterministic).
+// summed in chunk order (deterministic).  rows (device, may be null): system
+// r uses only its first rows[r] <= n entries (the systems of a batch of
+// uneven geometries, padded to n); the rest of its vectors is neither read
+// nor written.
 void launch_block_dot_partials(const void* V, int64_t si, int64_t sr, const void* w, int64_t n,
                                int nv, int nrhs, void* partial, hipStream_t s,
-                               const GivensState* gst = nullptr);
+                               const GivensState* gst = nullptr, const int32_t* rows = nullptr);
 void launch_gs_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv, int nrhs,
                       const void* partial, void* h_out, hipStream_t s,
-                      const GivensState* gst = nullptr);
+                      const GivensState* gst = nullptr, const int32_t* rows = nullptr);
 void launch_norm_partials(const void* w, int64_t n, int nrhs, void* partial, hipStream_t s,
-                          const GivensState* gst = nullptr);
+                          const GivensState* gst = nullptr, const int32_t* rows = nullptr);
 void launch_scale_norm(const void* w, const void* partial, double* nrm_out, void* out, int64_t n,
                        int nrhs, int64_t out_stride, hipStream_t s,
-                       const GivensState* gst = nullptr);
+                       const GivensState* gst = nullptr, const int32_t* rows = nullptr);
 // out[r] = w[r] * (1 / nrm[r]) (0 if nrm == 0)
 void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
-                      int64_t out_stride, hipStream_t s, const GivensState* gst = nullptr);
+                      int64_t out_stride, hipStream_t s, const GivensState* gst = nullptr,
+                      const int32_t* rows = nullptr);
 // One Arnoldi step's Hessenberg column, Givens rotation and residual estimate
 // for every system (see givens_step_kernel)
 void launch_givens_step(const void* h, const void* h2, const double* nrm, int nrhs, int j,
                         int mcap, void* H, void* cs, void* sn, void* g, GivensState* st,
                         const double* scale, double tol, int max_iter, hipStream_t s);
-// x[r] += sum_i y[r][i] Z_i,r
+// x[r] += sum_{i < len_r} y[r][i] Z_i,r with len_r the system's basis length
+// in st (at most nv), over the first rows[r] entries (all n if rows is null)
 void launch_combine(const void* Z, int64_t si, int64_t sr, const void* y, int64_t ldy, int nv,
-                    void* x, int64_t n, int nrhs, hipStream_t s);
+                    void* x, int64_t n, int nrhs, const GivensState* st, hipStream_t s,
+                    const int32_t* rows = nullptr);
 // r = b - r   (in place on r)
 void launch_residual(const void* b, void* r, int64_t count, hipStream_t s);
 void launch_axpy_inplace(void* x, const void* d, int64_t count, hipStream_t s);

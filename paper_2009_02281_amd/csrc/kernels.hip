@@ -1723,10 +1723,13 @@ __global__ __launch_bounds__(256) void block_dot_kernel(const double2* __restric
                                                         int64_t sr, const double2* __restrict__ w,
                                                         int64_t n, int nv, int nchunk,
                                                         double2* partial,
-                                                        const GivensState* __restrict__ gst) {
+                                                        const GivensState* __restrict__ gst,
+                                                        const int32_t* __restrict__ rows) {
   __shared__ double2 sh[256];
   const int c = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
-  if (gst && gst[r].frozen) {  // uniform over the block
+  const int64_t nr = rows ? int64_t(rows[r]) : n;
+  // frozen systems and chunks past the system's rows (uniform over the block)
+  if ((gst && gst[r].frozen) || int64_t(c) * kDotChunk >= nr) {
     if (threadIdx.x == 0) partial[(int64_t(r) * nv + i) * nchunk + c] = make_double2(0.0, 0.0);
     return;
   }
@@ -1735,7 +1738,7 @@ __global__ __launch_bounds__(256) void block_dot_kernel(const double2* __restric
   double2 acc;
   acc.x = 0.0;
   acc.y = 0.0;
-  const int64_t b = int64_t(c) * kDotChunk, e = min(n, b + kDotChunk);
+  const int64_t b = int64_t(c) * kDotChunk, e = min(nr, b + kDotChunk);
   for (int64_t k = b + threadIdx.x; k < e; k += 256) {
     const double2 a = vi[k], x = wr[k];
     acc.x += a.x * x.x + a.y * x.y;
@@ -1745,8 +1748,9 @@ __global__ __launch_bounds__(256) void block_dot_kernel(const double2* __restric
   if (threadIdx.x == 0) partial[(int64_t(r) * nv + i) * nchunk + c] = s;
 }
 
-// w[r] -/+= sum_{i < nv} h[r][i] V[r][i] (SUB: a Gram-Schmidt update; !SUB:
-// the restart update x += Z y): one element per thread (the launch covers
+// w[r] -/+= sum_{i < nv_r} h[r][i] V[r][i] (SUB: a Gram-Schmidt update; !SUB:
+// the restart update x += Z y), nv_r = min(nv, gst[r].len) when the cycle
+// state is given, else nv: one element per thread (the launch covers
 // every element, so all CUs take part), four basis vectors loaded together
 // per step; the order of the terms is fixed
 template <bool SUB>
@@ -1755,10 +1759,14 @@ __global__ __launch_bounds__(128) void basis_axpy_kernel(const double2* __restri
                                                          double2* __restrict__ w, int64_t n,
                                                          int nv, const double2* __restrict__ h,
                                                          int64_t ldh,
-                                                         const GivensState* __restrict__ gst) {
+                                                         const GivensState* __restrict__ gst,
+                                                         const int32_t* __restrict__ rows) {
   const int r = blockIdx.y;
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= n || (gst && gst[r].frozen)) return;
+  if (k >= (rows ? int64_t(rows[r]) : n)) return;
+  // each system's own basis length: columns past it may never have been
+  // written (systems stopped before or during the cycle)
+  if (gst) nv = min(nv, gst[r].len);
   const double2* hr = h + int64_t(r) * ldh;
   const double2* vr = V + int64_t(r) * sr * n + k;
   const int64_t vs = si * n;
@@ -1799,10 +1807,15 @@ __global__ __launch_bounds__(128) void gs_update_kernel(const double2* __restric
                                                         int64_t n, int nv,
                                                         const double2* __restrict__ part,
                                                         int nchunk, double2* __restrict__ h_out,
-                                                        const GivensState* __restrict__ gst) {
+                                                        const GivensState* __restrict__ gst,
+                                                        const int32_t* __restrict__ rows) {
   __shared__ double2 hs[kMaxBasis];
   const int r = blockIdx.y;
+  const int64_t nr = rows ? int64_t(rows[r]) : n;
   if (gst && gst[r].frozen) return;  // uniform over the block
+  // workgroups past the system's rows (uniform); workgroup 0 always stays,
+  // it stores h
+  if (blockIdx.x > 0 && int64_t(blockIdx.x) * blockDim.x >= nr) return;
   for (int i = threadIdx.x; i < nv; i += blockDim.x) {
     const double2* pp = part + (int64_t(r) * nv + i) * nchunk;
     double2 sum = make_double2(0.0, 0.0);
@@ -1822,7 +1835,7 @@ __global__ __launch_bounds__(128) void gs_update_kernel(const double2* __restric
   }
   __syncthreads();
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= nr) return;
   const double2* vr = V + int64_t(r) * sr * n + k;
   const int64_t vs = si * n;
   double2 acc = w[int64_t(r) * n + k];
@@ -1844,31 +1857,34 @@ __global__ __launch_bounds__(128) void gs_update_kernel(const double2* __restric
 
 void launch_block_dot_partials(const void* V, int64_t si, int64_t sr, const void* w, int64_t n,
                                int nv, int nrhs, void* partial, hipStream_t s,
-                               const GivensState* gst) {
+                               const GivensState* gst, const int32_t* rows) {
   const int nchunk = dot_chunks(n);
   hipLaunchKernelGGL(block_dot_kernel, dim3(nchunk, nv, nrhs), dim3(256), 0, s,
                      static_cast<const double2*>(V), si, sr, static_cast<const double2*>(w), n, nv,
-                     nchunk, static_cast<double2*>(partial), gst);
+                     nchunk, static_cast<double2*>(partial), gst, rows);
   AIM_HIP(hipGetLastError());
 }
 
 void launch_gs_update(const void* V, int64_t si, int64_t sr, void* w, int64_t n, int nv, int nrhs,
-                      const void* partial, void* h_out, hipStream_t s, const GivensState* gst) {
+                      const void* partial, void* h_out, hipStream_t s, const GivensState* gst,
+                      const int32_t* rows) {
   AIM_REQUIRE(nv <= kMaxBasis, AIM_ERR_INVALID_ARG, "Krylov basis too large");
   hipLaunchKernelGGL(gs_update_kernel, dim3(unsigned((n + 127) / 128), nrhs), dim3(128), 0, s,
                      static_cast<const double2*>(V), si, sr, static_cast<double2*>(w), n, nv,
                      static_cast<const double2*>(partial), dot_chunks(n),
-                     static_cast<double2*>(h_out), gst);
+                     static_cast<double2*>(h_out), gst, rows);
   AIM_HIP(hipGetLastError());
 }
 
 __global__ __launch_bounds__(256) void norm_partial_kernel(const double2* __restrict__ w,
                                                            int64_t n, int nchunk,
                                                            double2* partial,
-                                                           const GivensState* __restrict__ gst) {
+                                                           const GivensState* __restrict__ gst,
+                                                           const int32_t* __restrict__ rows) {
   __shared__ double2 sh[256];
   const int c = blockIdx.x, r = blockIdx.y;
-  if (gst && gst[r].frozen) {  // uniform over the block
+  const int64_t nr = rows ? int64_t(rows[r]) : n;
+  if ((gst && gst[r].frozen) || int64_t(c) * kDotChunk >= nr) {  // uniform over the block
     if (threadIdx.x == 0) partial[int64_t(r) * nchunk + c] = make_double2(0.0, 0.0);
     return;
   }
@@ -1876,7 +1892,7 @@ __global__ __launch_bounds__(256) void norm_partial_kernel(const double2* __rest
   double2 acc;
   acc.x = 0.0;
   acc.y = 0.0;
-  const int64_t b = int64_t(c) * kDotChunk, e = min(n, b + kDotChunk);
+  const int64_t b = int64_t(c) * kDotChunk, e = min(nr, b + kDotChunk);
   for (int64_t k = b + threadIdx.x; k < e; k += 256) acc.x += wr[k].x * wr[k].x + wr[k].y * wr[k].y;
   const double2 s = block_sum2(acc, sh);
   if (threadIdx.x == 0) partial[int64_t(r) * nchunk + c] = s;
@@ -1894,7 +1910,8 @@ void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out
                   const GivensState* gst) {
   const int nchunk = int((n + kDotChunk - 1) / kDotChunk);
   hipLaunchKernelGGL(norm_partial_kernel, dim3(nchunk, nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(w), n, nchunk, static_cast<double2*>(partial), gst);
+                     static_cast<const double2*>(w), n, nchunk, static_cast<double2*>(partial), gst,
+                     nullptr);
   AIM_HIP(hipGetLastError());
   hipLaunchKernelGGL(norm_finish_kernel, dim3((nrhs + 127) / 128), dim3(128), 0, s,
                      static_cast<const double2*>(partial), nchunk, nrhs, out);
@@ -1902,12 +1919,14 @@ void launch_norms(const void* w, int64_t n, int nrhs, void* partial, double* out
 }
 
 __global__ void scale_inv_kernel(const double2* w, const double* nrm, double2* out, int64_t n,
-                                 int64_t out_stride, const GivensState* __restrict__ gst) {
+                                 int64_t out_stride, const GivensState* __restrict__ gst,
+                                 const int32_t* __restrict__ rows) {
   const int r = blockIdx.y;
   if (gst && gst[r].frozen) return;
+  const int64_t nr = rows ? int64_t(rows[r]) : n;
   const double nv = nrm[r];
   const double sc = nv > 0.0 ? 1.0 / nv : 0.0;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < nr;
        k += int64_t(gridDim.x) * blockDim.x) {
     double2 v = w[int64_t(r) * n + k];
     v.x *= sc;
@@ -1922,10 +1941,12 @@ __global__ void scale_inv_kernel(const double2* w, const double* nrm, double2* o
 // nrm_out for the Givens step.  No separate finishing launch.
 __global__ void scale_norm_kernel(const double2* w, const double2* __restrict__ part, int nchunk,
                                   double* __restrict__ nrm_out, double2* out, int64_t n,
-                                  int64_t out_stride, const GivensState* __restrict__ gst) {
+                                  int64_t out_stride, const GivensState* __restrict__ gst,
+                                  const int32_t* __restrict__ rows) {
   __shared__ double nrm_s;
   const int r = blockIdx.y;
   if (gst && gst[r].frozen) return;  // uniform over the block
+  const int64_t nr = rows ? int64_t(rows[r]) : n;
   if (threadIdx.x == 0) {
     const double2* pp = part + int64_t(r) * nchunk;
     double sum = 0.0;
@@ -1943,7 +1964,7 @@ __global__ void scale_norm_kernel(const double2* w, const double2* __restrict__ 
   __syncthreads();
   const double nv = nrm_s;
   const double sc = nv > 0.0 ? 1.0 / nv : 0.0;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < nr;
        k += int64_t(gridDim.x) * blockDim.x) {
     double2 v = w[int64_t(r) * n + k];
     v.x *= sc;
@@ -1953,26 +1974,28 @@ __global__ void scale_norm_kernel(const double2* w, const double2* __restrict__ 
 }
 
 void launch_norm_partials(const void* w, int64_t n, int nrhs, void* partial, hipStream_t s,
-                          const GivensState* gst) {
+                          const GivensState* gst, const int32_t* rows) {
   hipLaunchKernelGGL(norm_partial_kernel, dim3(dot_chunks(n), nrhs), dim3(256), 0, s,
                      static_cast<const double2*>(w), n, dot_chunks(n),
-                     static_cast<double2*>(partial), gst);
+                     static_cast<double2*>(partial), gst, rows);
   AIM_HIP(hipGetLastError());
 }
 
 void launch_scale_norm(const void* w, const void* partial, double* nrm_out, void* out, int64_t n,
-                       int nrhs, int64_t out_stride, hipStream_t s, const GivensState* gst) {
+                       int nrhs, int64_t out_stride, hipStream_t s, const GivensState* gst,
+                       const int32_t* rows) {
   hipLaunchKernelGGL(scale_norm_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, s,
                      static_cast<const double2*>(w), static_cast<const double2*>(partial),
-                     dot_chunks(n), nrm_out, static_cast<double2*>(out), n, out_stride, gst);
+                     dot_chunks(n), nrm_out, static_cast<double2*>(out), n, out_stride, gst, rows);
   AIM_HIP(hipGetLastError());
 }
 
 void launch_scale_inv(const void* w, const double* nrm, void* out, int64_t n, int nrhs,
-                      int64_t out_stride, hipStream_t s, const GivensState* gst) {
+                      int64_t out_stride, hipStream_t s, const GivensState* gst,
+                      const int32_t* rows) {
   hipLaunchKernelGGL(scale_inv_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, s,
                      static_cast<const double2*>(w), nrm, static_cast<double2*>(out), n,
-                     out_stride, gst);
+                     out_stride, gst, rows);
   AIM_HIP(hipGetLastError());
 }
 
@@ -2090,10 +2113,11 @@ void launch_givens_step(const void* h, const void* h2, const double* nrm, int nr
 }
 
 void launch_combine(const void* Z, int64_t si, int64_t sr, const void* y, int64_t ldy, int nv,
-                    void* x, int64_t n, int nrhs, hipStream_t s) {
+                    void* x, int64_t n, int nrhs, const GivensState* gst, hipStream_t s,
+                    const int32_t* rows) {
   hipLaunchKernelGGL(basis_axpy_kernel<false>, dim3(unsigned((n + 127) / 128), nrhs), dim3(128),
                      0, s, static_cast<const double2*>(Z), si, sr, static_cast<double2*>(x), n, nv,
-                     static_cast<const double2*>(y), ldy, nullptr);
+                     static_cast<const double2*>(y), ldy, gst, rows);
   AIM_HIP(hipGetLastError());
 }
 
