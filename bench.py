@@ -230,7 +230,7 @@ def solve_leg(plan, rtol: float, max_iter: int = 4000,
             "runs": res}
 
 
-def batch_leg(rtol: float, pcs=("diag", "nearblock")) -> dict:
+def batch_leg(rtol: float, pcs=("diag", "nearblock"), restart: int = RESTART) -> dict:
     """One batched solve over 32 uneven geometries behind one plan
     (aim_setup_batch; the instances' matvecs run concurrently on the plan's
     worker streams) against the same 32 systems solved one after another on
@@ -256,13 +256,13 @@ def batch_leg(rtol: float, pcs=("diag", "nearblock")) -> dict:
            "k_range": [float(min(w.k[0] for w in ws)), float(max(w.k[0] for w in ws))],
            "grids": sorted({"x".join(map(str, w.dims)) for w in ws}),
            "kinds": [w.extra["kind"] for w in ws], "k": [float(w.k[0]) for w in ws],
-           "rtol": rtol, "restart": RESTART, "inner": "c64",
+           "rtol": rtol, "restart": restart, "inner": "c64",
            "setup_seconds": {"batched": t_batch_setup, "one_after_another": t_sep_setup},
            "runs": {}}
     for pc in pcs:
-        opts = dict(rtol=rtol, restart=RESTART, max_iter=4000, pc=pc, inner="c64", max_refine=4,
+        opts = dict(rtol=rtol, restart=restart, max_iter=4000, pc=pc, inner="c64", max_refine=4,
                     raise_on_fail=False)
-        warm = dict(rtol=1e-2, restart=RESTART, max_iter=20, pc=pc, inner="c64",
+        warm = dict(rtol=1e-2, restart=restart, max_iter=20, pc=pc, inner="c64",
                     raise_on_fail=False)
         bp.solve(B, **warm)
         torch.cuda.synchronize()
@@ -565,6 +565,8 @@ def main() -> int:
     ap.add_argument("--batch", action="store_true",
                     help="also time one batched solve over 32 uneven geometries against "
                          "solving them one after another")
+    ap.add_argument("--batch-restart", type=int, default=200,
+                    help="GMRES restart length of the batch leg")
     ap.add_argument("--solve-pcs", default="none,diag,nearblock",
                     help="comma-separated preconditioners for the GMRES leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -745,7 +747,7 @@ def main() -> int:
     if not args.no_unet and args.workload != "sweep":
         out["unet"] = unet_leg()
     if args.batch:
-        out["batch"] = batch_leg(args.solve_rtol)
+        out["batch"] = batch_leg(args.solve_rtol, restart=args.batch_restart)
 
     if not args.no_cpu:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)

@@ -390,11 +390,13 @@ void batch_fork(aim_plan p, int n, const char* skip, hipStream_t s, F&& fn) {
   }
 }
 
+// pad (batch plans): zero the padding rows of y (the GMRES loop, whose
+// Krylov kernels never read them, leaves them as they are)
 void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs,
                 const int32_t* dfreq, hipStream_t s, hipEvent_t* ev = nullptr,
-                const char* skip = nullptr) {
+                const char* skip = nullptr, bool pad = true) {
   if (p->batch) {
-    // system i through instance i; the padding of y_i stays zero
+    // system i through instance i; the padding of y_i zeroed
     AIM_REQUIRE(nrhs == int(p->inst.size()) && !ev, AIM_ERR_INVALID_ARG,
                 "a batch plan applies one system per instance");
     const size_t cb = prec == AIM_C128 ? 16 : 8;
@@ -404,7 +406,7 @@ void matvec_any(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs
       const char* xi = static_cast<const char*>(x) + size_t(i) * nmax * cb;
       char* yi = static_cast<char*>(y) + size_t(i) * nmax * cb;
       matvec_any(q, prec, xi, yi, 1, dfreq + i, si);
-      aim::launch_zero_words(yi + size_t(q->t.N) * cb, (nmax - q->t.N) * int64_t(cb / 8), si);
+      if (pad) aim::launch_zero_words(yi + size_t(q->t.N) * cb, (nmax - q->t.N) * int64_t(cb / 8), si);
     });
     return;
   }
@@ -1368,9 +1370,9 @@ void graph_matvec(aim_plan p, aim_precision prec, const void* in, void* out, int
 void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, const int32_t* dfreq,
              hipStream_t s, const char* skip = nullptr) {
   const int64_t cnt = p->t.N * int64_t(nrhs);
-  if (skip && p->batch) {  // direct launches, stopped instances skipped
+  if (skip && p->batch) {  // direct launches, stopped instances skipped, padding left
     if (prec == AIM_C128) {
-      matvec_any(p, AIM_C128, x, y, nrhs, dfreq, s, nullptr, skip);
+      matvec_any(p, AIM_C128, x, y, nrhs, dfreq, s, nullptr, skip, false);
       return;
     }
     // complex64 matvecs: each running instance casts its own rows, so the
@@ -1385,7 +1387,6 @@ void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, c
       aim::launch_cast_c128_to_c64(static_cast<const char*>(x) + size_t(off) * 16, a, ni, si);
       matvec_any(q, AIM_C64, a, b2, 1, dfreq + i, si);
       aim::launch_cast_c64_to_c128(b2, yi, ni, si);
-      aim::launch_zero_words(yi + size_t(ni) * 16, (nmax - ni) * 2, si);
     });
     return;
   }
@@ -1456,7 +1457,8 @@ void ensure_nearblock_for(aim_plan p, const int32_t* freq_host, int nrhs, hipStr
 // Classical (linear) preconditioners: z = v, D^{-1} v or a near-block
 // inverse; dfreq (device) holds each system's wavenumber index.
 // skip (batch plans only, may be null): systems whose result is not needed
-// (GMRES systems that have stopped); their rows of z are left as they are
+// (GMRES systems that have stopped); their rows of z are left as they are,
+// and so is the padding of every row (only the GMRES loop passes skip)
 void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs,
                 const int32_t* dfreq, hipStream_t s, const char* skip) {
   const int64_t n = p->t.N;
@@ -1466,7 +1468,7 @@ void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs,
       const char* vi = static_cast<const char*>(v) + size_t(i) * n * 16;
       char* zi = static_cast<char*>(z) + size_t(i) * n * 16;
       apply_base(q, pc, vi, zi, 1, dfreq + i, si);
-      aim::launch_zero_words(zi + size_t(q->t.N) * 16, (n - q->t.N) * 2, si);
+      if (!skip) aim::launch_zero_words(zi + size_t(q->t.N) * 16, (n - q->t.N) * 2, si);
     });
     return;
   }
