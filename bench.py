@@ -297,6 +297,108 @@ def batch_leg(rtol: float, pcs=("diag", "nearblock"), restart: int = RESTART) ->
     return out
 
 
+def batch_learned_leg(rtol: float, restart: int = 200, pairs: int = 20000,
+                      epochs: int = 3) -> dict:
+    """The learned preconditioner at the uneven batch's scale.  Pairs are
+    logged from plain complex128 GMRES(12) to 1e-8 on uneven training
+    geometries of their own seed (5004; spheres, boxes and box arrays of
+    5k-25k triangles, grids from 32^3 to 128x64x64, eight plane waves each), the
+    network is trained on them with the residual loss over the diagonal
+    preconditioner, and the 32-instance batch (seed 5003) is then solved in
+    one batched solve with pc=unet (complex64 matvecs in complex128
+    refinement, diagonal base and fallback) against the classical batched
+    runs.  Reported whichever way it falls."""
+    import numpy as np
+    import torch
+    from paper_2009_02281_amd import binding
+    from paper_2009_02281_amd import inputs as I
+    rng = np.random.default_rng(5006)
+
+    def dirs(n):
+        d = rng.standard_normal((n, 3))
+        return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+    train = I.uneven_batch(count=24, seed=5004, n_range=(5000, 25000))
+    per = max(1, pairs // len(train))
+    t0 = time.perf_counter()
+    data, err2, res2, count, skipped = [], 0.0, 0.0, 0, 0
+    for w in train:
+        p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                         max_rhs=8)
+        try:
+            r, e, _ = p.log_pairs(p.excitation("plane_wave", dirs(8)), rtol=1e-8, restart=12,
+                                  max_iter=4000, max_pairs=per)
+        except binding.AimError as err:
+            if err.status != 6:  # not converged: its errors e_t would be inexact
+                raise
+            skipped += 1
+            p.close()
+            continue
+        grids, ts, sums = p.pc_targets(r, e, base_pc="diag", loss="residual")
+        del r, e
+        data.append((p, grids, ts))
+        err2, res2, count = err2 + sums[0], res2 + sums[1], count + grids.shape[0] * p.n
+    torch.cuda.synchronize()
+    t_log = time.perf_counter() - t0
+    npairs = sum(d[1].shape[0] for d in data)
+    print(f"[bench] batch learned: {npairs} pairs from {len(data)} geometries ({skipped} "
+          f"skipped: plain GMRES did not converge) in {t_log:.1f}s", file=sys.stderr, flush=True)
+    tau, weight = math.sqrt(err2 / count), count / res2
+    net = binding.UNet(seed=61)
+    order_rng = np.random.default_rng(62)
+    t0 = time.perf_counter()
+    loss = []
+    for _ in range(epochs):
+        tot, nb = 0.0, 0
+        for gi in order_rng.permutation(len(data)):
+            p, grids, ts = data[gi]
+            idx = order_rng.permutation(grids.shape[0])
+            for s0 in range(0, len(idx), 8):
+                tot += p.pc_train_step(net, grids, ts, idx[s0:s0 + 8], tau=tau, weight=weight,
+                                       loss="residual", lr=1e-3)
+                nb += 1
+        loss.append(tot / nb)
+        print(f"[bench] batch learned: epoch loss {loss[-1]:.4f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ngeom = len(data)
+    for p, _, _ in data:
+        p.close()
+    del data
+    ws = I.uneven_batch()
+    solo = [binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
+            for w in ws]
+    bs = [q.excitation("plane_wave", [0.0, 0.0, 1.0])[0] for q in solo]
+    for q in solo:
+        q.close()
+    bp = binding.Plan.setup_batch(ws)
+    bp.set_unet(net, base_pc="diag", tau=tau)
+    B = bp.pack(bs)
+    runs = {}
+    for inner, pc in (("c128", "none"), ("c128", "diag"), ("c64", "diag"), ("c64", "unet")):
+        opts = dict(rtol=rtol, restart=restart, max_iter=10000, pc=pc, inner=inner,
+                    max_refine=4, fallback_pc="diag", raise_on_fail=False)
+        bp.solve(B, **dict(opts, rtol=1e-2, max_iter=20))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, r = bp.solve(B, **opts)
+        torch.cuda.synchronize()
+        runs[f"{inner}+{pc}"] = {"seconds": time.perf_counter() - t0,
+                                 "iters_max": int(r.iters.max()),
+                                 "iters_sum": int(r.iters.sum()),
+                                 "converged": int(r.converged.sum()),
+                                 "fallback_used": bool(r.fallback_used.any())}
+        print(f"[bench] batch learned {inner}+{pc}: {runs[f'{inner}+{pc}']}", file=sys.stderr,
+              flush=True)
+    bp.set_unet(None)
+    bp.close()
+    net.close()
+    return {"rtol": rtol, "restart": restart, "training_geometries": ngeom,
+            "training_geometries_skipped": skipped,
+            "training_pairs": npairs, "log_seconds": t_log, "train_seconds": t_train,
+            "epochs": epochs, "train_loss": loss, "tau": tau, "instances": len(ws), "runs": runs}
+
+
 def learned_pc_leg(rtol: float) -> dict:
     """GMRES time to rtol on a held-out ellipsoid (4 plane waves, batched):
     complex128 GMRES without and with the near-block preconditioner against
@@ -562,9 +664,12 @@ def main() -> int:
     ap.add_argument("--solve-rtol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=4000,
                     help="GMRES iteration cap per solve (per refinement step in complex64)")
-    ap.add_argument("--batch", action="store_true",
-                    help="also time one batched solve over 32 uneven geometries against "
-                         "solving them one after another")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched solve over 32 uneven geometries (against solving "
+                         "them one after another)")
+    ap.add_argument("--no-batch-learned", action="store_true",
+                    help="skip training the learned preconditioner on pairs from uneven "
+                         "training geometries and solving the 32-instance batch with it")
     ap.add_argument("--batch-restart", type=int, default=200,
                     help="GMRES restart length of the batch leg")
     ap.add_argument("--solve-pcs", default="none,diag,nearblock",
@@ -746,8 +851,18 @@ def main() -> int:
         out["learned_pc"] = learned_pc_leg(args.solve_rtol)
     if not args.no_unet and args.workload != "sweep":
         out["unet"] = unet_leg()
-    if args.batch:
-        out["batch"] = batch_leg(args.solve_rtol, restart=args.batch_restart)
+    # the uneven batch (classical preconditioners, then the learned one);
+    # a failure there is recorded and does not cost the main line
+    for key, on, leg in (("batch", not args.no_batch, batch_leg),
+                         ("batch_learned", not args.no_batch_learned, batch_learned_leg)):
+        if not on:
+            continue
+        try:
+            out[key] = leg(args.solve_rtol, restart=args.batch_restart)
+        except Exception as err:  # noqa: BLE001 - reported in the JSON line
+            out[key] = {"error": f"{type(err).__name__}: {err}"}
+            print(f"[bench] {key} leg failed: {err}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         print("[bench] timing the oracle on the host ...", file=sys.stderr, flush=True)

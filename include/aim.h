@@ -488,7 +488,10 @@ typedef enum { AIM_LOSS_ERROR = 0, AIM_LOSS_RESIDUAL = 1 } aim_pc_loss;
 /* Attach (net != NULL) or detach (net == NULL) a network.  base_pc is B
  * (AIM_PC_NONE, AIM_PC_DIAG or AIM_PC_NEARBLOCK) and tau > 0 the target scale
  * used in training.  The plan keeps the pointer, not a copy: the network
- * must outlive its use by aim_solve.  Blocking. */
+ * must outlive its use by aim_solve.  On a batch plan (aim_setup_batch) every
+ * instance applies the network on its own grid, one instance after another
+ * (the network's buffers are shared); every instance's grid must meet the
+ * network's conditions.  Blocking. */
 aim_status aim_plan_set_unet(aim_plan plan, aim_unet net, aim_pc_kind base_pc, double tau);
 
 /* Solve A x = b with plain restarted GMRES (complex128, no preconditioner,

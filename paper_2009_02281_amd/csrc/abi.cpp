@@ -1147,7 +1147,7 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
 
 namespace {
 void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, const int32_t* dfreq,
-                   hipStream_t s);
+                   hipStream_t s, const char* skip = nullptr);
 void apply_base(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs,
                 const int32_t* dfreq, hipStream_t s, const char* skip = nullptr);
 void ensure_nearblock(aim_plan p, int f, hipStream_t s);
@@ -1518,10 +1518,24 @@ void check_unet_plan(aim_plan p) {
 // Learned preconditioner (a nonlinear map, so the solve is flexible GMRES):
 //   z = B v + tau ||v|| (P^T U(g)) / area,   g = unet_input(v),
 // B the base preconditioner, U the network; the grid work is complex64.
+// On a batch plan each instance applies the network on its own grid, one
+// instance after another on s (the network's activation buffers are shared);
+// skip as in apply_base.
 void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, const int32_t* dfreq,
-                   hipStream_t s) {
+                   hipStream_t s, const char* skip) {
   AIM_REQUIRE(p->unet != nullptr, AIM_ERR_STATE, "no learned preconditioner attached");
-  AIM_REQUIRE(!p->batch, AIM_ERR_STATE, "no learned preconditioner on a batch plan");
+  if (p->batch) {
+    const int64_t n = p->t.N;
+    for (int i = 0; i < nrhs; ++i) {
+      if (skip && skip[i]) continue;
+      aim_plan_s* q = p->inst[size_t(i)].get();
+      const char* vi = static_cast<const char*>(v) + size_t(i) * n * 16;
+      char* zi = static_cast<char*>(z) + size_t(i) * n * 16;
+      apply_unet_pc(q, vi, zi, 1, dfreq + i, s);
+      if (!skip) aim::launch_zero_words(zi + size_t(q->t.N) * 16, (n - q->t.N) * 2, s);
+    }
+    return;
+  }
   ensure_unet_buffers(p, s);  // before any of the buffers is read below
   const int64_t n = p->t.N, Ng = p->g.Ng;
   unet_input(p, v, nrhs, p->ug_in, s);
@@ -1535,7 +1549,7 @@ void apply_unet_pc(aim_plan p, const void* v, void* z, int nrhs, const int32_t* 
 void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, const int32_t* dfreq,
              hipStream_t s, const char* skip = nullptr) {
   if (pc == AIM_PC_UNET)
-    apply_unet_pc(p, v, z, nrhs, dfreq, s);
+    apply_unet_pc(p, v, z, nrhs, dfreq, s, skip);
   else
     apply_base(p, pc, v, z, nrhs, dfreq, s, skip);
 }
@@ -1919,12 +1933,22 @@ extern "C" aim_status aim_plan_set_unet(aim_plan p, aim_unet net, aim_pc_kind ba
                                         double tau) {
   if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
   return guarded([&] {
-    no_batch(p);
     AIM_REQUIRE(base_pc >= AIM_PC_NONE && base_pc <= AIM_PC_NEARBLOCK_STATIC &&
                     base_pc != AIM_PC_UNET,
                 AIM_ERR_INVALID_ARG, "base preconditioner must be a classical one");
     AIM_REQUIRE(std::isfinite(tau) && tau > 0.0, AIM_ERR_INVALID_ARG, "tau must be positive");
-    if (net) check_unet_plan(p);
+    // a batch plan: every instance applies the same network on its own grid
+    std::vector<aim_plan_s*> targets;
+    if (p->batch)
+      for (auto& q : p->inst) targets.push_back(q.get());
+    for (aim_plan_s* q : targets)
+      if (net) check_unet_plan(q);
+    if (!p->batch && net) check_unet_plan(p);
+    for (aim_plan_s* q : targets) {
+      q->unet = net;
+      q->unet_base = base_pc;
+      q->unet_tau = tau;
+    }
     p->unet = net;
     p->unet_base = base_pc;
     p->unet_tau = tau;
