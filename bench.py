@@ -579,6 +579,38 @@ def extra_workload(name: str, precs, steps: int, warmup: int) -> dict:
     return res
 
 
+def dlp_leg(plan, w, reps: int = 20) -> dict:
+    """The double-layer operator under AIMx (Sec. III-B) on the same plan:
+    its one-time tables (near values on the device, one spectrum of the
+    gradient channels' radial factor per wavenumber) and the per-call time
+    of K x against the single-layer matvec A x (complex128, one vector)."""
+    import torch
+    from paper_2009_02281_amd import inputs as I
+    x = torch.from_numpy(I.complex_gaussian(w.n, w.seed_base + 9)).cuda()
+    y = torch.empty_like(x)
+    t0 = time.perf_counter()
+    plan.matvec_dlp(x, out=y)
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    for _ in range(2):
+        plan.matvec_dlp(x, out=y)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        plan.matvec_dlp(x, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    res = {"workload": w.name, "first_call_seconds": first, "ms_per_matvec": ms,
+           "unknowns_matvecs_per_s": w.n / (ms * 1e-3),
+           "note": "complex128; three gradient channels as six convolutions with one even "
+                   "kernel; the first call builds the tables"}
+    print(f"[bench] double layer on {w.name}: {ms:.3f} ms per matvec (first call "
+          f"{first:.2f}s)", file=sys.stderr, flush=True)
+    return res
+
+
 def conventional_leg(plan, w, nrhs: int = 8, reps: int = 10) -> dict:
     """Conventional AIM against AIMx on one plan (Sec. II-B against Sec. III;
     the per-wavenumber cost of the sweep comparison of Sec. VI): the
@@ -835,6 +867,8 @@ def main() -> int:
                                  tuple(args.solve_pcs.split(",")))
     if not args.no_extra and args.workload != "sweep" and args.nrhs <= plan.info()["max_rhs"]:
         out["conventional"] = {w.name: conventional_leg(plan, w, nrhs=args.nrhs)}
+        if args.nrhs == 1:
+            out["dlp"] = dlp_leg(plan, w)
     if not args.no_extra and args.workload != "sweep":
         plan.close()
         plan = None

@@ -328,6 +328,35 @@ aim_status aim_matvec_conventional(aim_plan plan, aim_precision prec, const void
                                    void* y_dev, int32_t nrhs, void* hip_stream);
 aim_status aim_conventional_export(aim_plan plan, double* vals_host, void* hip_stream);
 
+/* The double-layer potential operator under AIMx (Sec. III-B, eqs. opK,
+ * ghgf, KAIMx, gH00), in the scalar setting of the plan: one
+ * piecewise-constant density per flat triangle, Galerkin testing, kernel
+ * dG/dn' = n_j.(r - r') (1 + jkR) e^{-jkR} / (4 pi R^3) (n_j the unit normal
+ * (b - a) x (c - a) of the source triangle), so
+ *   y_i = sum_j x_j int_{T_i} int_{T_j} dG/dn'(r, r') dS' dS
+ * with the self pairs in the principal-value sense (0 for flat triangles;
+ * the jump term +-x/2 of a closed surface is the caller's).  Evaluated as
+ * K_s,NR - K_s,P + W H_grad(k) P^(K): the static near entries (inner
+ * integral in closed form through the solid angle, 3-point outer rule) and
+ * their precorrection on the plan's near list, and three gradient channels
+ * n_a x through the plan's projection, the grid samples of dG/dr'_a (self
+ * term 0 per component: eq. gH00 gives a scalar for this vector kernel, and
+ * 0 is the symmetric value) and interpolation.  x_dev, y_dev: [nrhs][N]
+ * complex128 device buffers (caller-owned, not overlapping), freq_idx_host
+ * [nrhs] indices into the plan's wavenumbers (NULL: all 0).  The first call
+ * builds the operator's tables on the device (normals, the near values, one
+ * spectrum per wavenumber, buffers for max_rhs products: about 6 max_rhs
+ * times the matvec's workspace); needs the complex128 tables and the mesh
+ * (AIM_ERR_STATE on loaded or host-only plans).  Asynchronous after that
+ * first call.  Not on batch plans. */
+aim_status aim_matvec_dlp(aim_plan plan, const void* x_dev, void* y_dev, int32_t nrhs,
+                          const int32_t* freq_idx_host, void* hip_stream);
+/* The double-layer near values on the near list (aim_export_tables order):
+ * K_s,NR into near_host[nnz] and C_K = K_s,NR - K_s,P into corr_host[nnz]
+ * (either may be NULL).  Builds the tables if needed.  Blocking. */
+aim_status aim_dlp_export(aim_plan plan, double* near_host, double* corr_host,
+                          void* hip_stream);
+
 /* One stage of the matvec, for stage-level checks (see aim_stage for the
  * shapes).  Same rules as aim_matvec; grids are unpadded [nrhs][Nz][Ny][Nx]. */
 aim_status aim_apply_stage(aim_plan plan, aim_precision prec, aim_stage stage,

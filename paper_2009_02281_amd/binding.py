@@ -31,7 +31,8 @@ RHS = {"plane_wave": 0, "gaussian_patch": 1}
 
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec",
             "aim_matvec_static", "aim_conventional_fill", "aim_matvec_conventional",
-            "aim_conventional_export", "aim_export_clusters", "aim_set_lin_term",
+            "aim_conventional_export", "aim_matvec_dlp", "aim_dlp_export",
+            "aim_export_clusters", "aim_set_lin_term",
             "aim_export_lin_diag", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
             "aim_autotune", "aim_set_schedule", "aim_matvec_capture", "aim_graph_launch",
@@ -121,6 +122,8 @@ def load_library(path: str = LIB_PATH):
     lib.aim_export_lin_diag.argtypes = [vp, C.POINTER(C.c_double)]
     lib.aim_matvec_conventional.argtypes = [vp, i32, vp, vp, i32, vp]
     lib.aim_conventional_export.argtypes = [vp, C.POINTER(C.c_double), vp]
+    lib.aim_matvec_dlp.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), vp]
+    lib.aim_dlp_export.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
     lib.aim_matvec_static.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
     lib.aim_apply_stage.argtypes = [vp, i32, i32, vp, vp, i32, ip32, vp]
     lib.aim_excitation.argtypes = [vp, i32, C.POINTER(C.c_double), i32, i32, ip32, vp, vp]
@@ -573,6 +576,29 @@ class Plan:
         _check(self._lib.aim_conventional_export(
             self._plan, out.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)))
         return out.view(np.complex128)
+
+    def matvec_dlp(self, x, freq_idx=None, out=None, stream=None):
+        """y = K x, the double-layer operator under AIMx (complex128)."""
+        import torch
+        self._check_vec(x, "c128", self.n, "x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        self._check_vec(y, "c128", self.n, "out")
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_matvec_dlp(self._plan, C.c_void_p(x.data_ptr()),
+                                        C.c_void_p(y.data_ptr()), nrhs, fp,
+                                        _stream_ptr(stream)))
+        return y
+
+    def dlp_values(self, stream=None):
+        """(K_s,NR, C_K) of the double-layer operator on the near list."""
+        nnz = int(self.info()["nnz"])
+        near = np.empty(max(nnz, 1), dtype=np.float64)
+        corr = np.empty(max(nnz, 1), dtype=np.float64)
+        _check(self._lib.aim_dlp_export(self._plan, near.ctypes.data_as(C.POINTER(C.c_double)),
+                                        corr.ctypes.data_as(C.POINTER(C.c_double)),
+                                        _stream_ptr(stream)))
+        return near[:nnz], corr[:nnz]
 
     def profile_matvec(self, x, reps: int = 10, freq_idx=None, prec: str = "c128", out=None,
                        stream=None) -> dict:

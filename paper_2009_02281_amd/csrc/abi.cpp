@@ -160,6 +160,20 @@ struct aim_plan_s {
   void* d_conv64 = nullptr;
   void* d_conv32 = nullptr;
   int conv_freq = -1;
+  // double-layer operator (aim_matvec_dlp), built on first use
+  bool dlp_ready = false;
+  double* d_dlp_nrm = nullptr;     // [N][3] unit normals
+  double* d_dlp_corr = nullptr;    // [nnz] C_K = K_s,NR - K_s,P on the near list
+  void* d_dlp_spec = nullptr;      // [nfreq] folded spectra of the radial factor F
+  void* d_dlp_src = nullptr;       // [3 max_rhs][N] channel sources n_a x
+  void* d_dlp_grid = nullptr;      // [6 max_rhs][Ng] channel grids and moments
+  void* d_dlp_work = nullptr;      // convolution workspace of 6 max_rhs grids
+  void* d_dlp_phi = nullptr;       // [max_rhs][Ng] combined potential
+  int32_t* d_dlp_freq = nullptr;   // [6 max_rhs] spectrum index per grid
+  int32_t* h_dlp_freq = nullptr;   // pinned staging
+  std::vector<int32_t> dlp_cur_freq;
+  std::vector<double> dlp_near, dlp_corr;  // host copies (aim_dlp_export)
+  double dlp_seconds = 0.0;
 
   // captured matvec graphs used by the solver, keyed by (prec, nrhs, in, out, freq)
   struct GraphKey {
@@ -232,6 +246,7 @@ struct aim_plan_s {
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (hipStream_t w : workers) (void)hipStreamDestroy(w);
     if (h_rhs_freq) (void)hipHostFree(h_rhs_freq);
+    if (h_dlp_freq) (void)hipHostFree(h_dlp_freq);
     if (sv.nrm_host) (void)hipHostFree(sv.nrm_host);
     if (sv.H_host) (void)hipHostFree(sv.H_host);
     if (sv.g_host) (void)hipHostFree(sv.g_host);
@@ -918,6 +933,121 @@ aim_status aim_matvec_conventional(aim_plan p, aim_precision prec, const void* x
       matvec_impl<float>(p, prec, x, y, nrhs, df, s, nullptr, 1, nullptr, nullptr, false);
       aim::launch_near_complex<float>(p->d_rowptr, p->d_col, p->d_conv32, x, y, p->t.N, nrhs, s);
     }
+  });
+}
+
+namespace {
+// The double-layer operator's tables (Sec. III-B): unit normals, C_K on the
+// near list (device fill), the folded spectra of the radial factor F for
+// every wavenumber of the plan, and the buffers of max_rhs products.
+void ensure_dlp(aim_plan p, hipStream_t s) {
+  if (p->dlp_ready) return;
+  AIM_REQUIRE(p->t.corners.size() == 9 * size_t(p->t.N), AIM_ERR_STATE,
+              "the double-layer operator needs the mesh (not kept by loaded plans)");
+  const double t0 = now_s();
+  const auto& t = p->t;
+  const int64_t N = t.N;
+  std::vector<double> nrm(3 * size_t(N));
+  for (int64_t j = 0; j < N; ++j) {
+    const double* c = &t.corners[9 * j];
+    const double e1[3] = {c[3] - c[0], c[4] - c[1], c[5] - c[2]};
+    const double e2[3] = {c[6] - c[0], c[7] - c[1], c[8] - c[2]};
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                         e1[0] * e2[1] - e1[1] * e2[0]};
+    const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int a = 0; a < 3; ++a) nrm[3 * j + a] = n[a] / l;
+  }
+  {
+    aim::NearDevice nd(t, nullptr, nullptr, p->alloc, p->free_fn, p->actx, s);
+    nd.fill_dlp(nrm, p->dlp_near, p->dlp_corr, s);
+  }
+  const auto& g = p->g;
+  const int R = p->max_rhs;
+  p->d_dlp_nrm = p->upload(nrm, s);
+  p->d_dlp_corr = p->upload(p->dlp_corr.empty() ? std::vector<double>(1, 0.0) : p->dlp_corr, s);
+  p->d_dlp_spec = p->dalloc(size_t(g.Nfold) * 16 * p->nfreq, s);
+  p->d_dlp_src = p->dalloc(size_t(3) * R * N * 16, s);
+  p->d_dlp_grid = p->dalloc(size_t(6) * R * g.Ng * 16, s);
+  p->d_dlp_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 6 * R, s);
+  p->d_dlp_phi = p->dalloc(size_t(R) * g.Ng * 16, s);
+  p->d_dlp_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 6 * R, s));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_dlp_freq), sizeof(int32_t) * 6 * R, 0));
+  void* full = nullptr;
+  AIM_HIP(hipMalloc(&full, size_t(8) * g.Ng * 16));
+  try {
+    for (int f = 0; f < p->nfreq; ++f)
+      aim::launch_spectrum(g, p->k[f], t.h, full,
+                           static_cast<char*>(p->d_dlp_spec) + size_t(f) * g.Nfold * 16, nullptr,
+                           p->d_tw64, s, 1);
+    AIM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(full);
+    throw;
+  }
+  AIM_HIP(hipFree(full));
+  p->dlp_cur_freq.clear();
+  p->dlp_ready = true;
+  p->dlp_seconds = now_s() - t0;
+}
+}  // namespace
+
+aim_status aim_matvec_dlp(aim_plan p, const void* x, void* y, int32_t nrhs,
+                          const int32_t* freq_idx_host, void* hip_stream) {
+  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    no_batch(p);
+    check_prec(p, AIM_C128);
+    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+    AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+                "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::vector<int32_t> fr(size_t(nrhs), 0);
+    for (int r = 0; r < nrhs; ++r) {
+      if (freq_idx_host) {
+        AIM_REQUIRE(freq_idx_host[r] >= 0 && freq_idx_host[r] < p->nfreq, AIM_ERR_INVALID_ARG,
+                    "frequency index out of range");
+        fr[r] = freq_idx_host[r];
+      }
+    }
+    ensure_dlp(p, s);
+    // one spectrum index per grid: the six grids of right-hand side r all use
+    // its wavenumber
+    std::vector<int32_t> f6(size_t(6) * nrhs);
+    for (int c = 0; c < 6; ++c)
+      for (int r = 0; r < nrhs; ++r) f6[size_t(c) * nrhs + r] = fr[r];
+    if (f6 != p->dlp_cur_freq) {
+      AIM_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed a copy
+      std::memcpy(p->h_dlp_freq, f6.data(), f6.size() * sizeof(int32_t));
+      AIM_HIP(hipMemcpyAsync(p->d_dlp_freq, p->h_dlp_freq, f6.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s));
+      p->dlp_cur_freq = f6;
+    }
+    const int64_t N = p->t.N;
+    aim::launch_dlp_sources(x, p->d_dlp_nrm, p->d_dlp_src, N, nrhs, s);
+    aim::launch_project<double>(p->g, p_dev(p, AIM_C128), p->d_pblk, p->nblk, p->d_dlp_src, N,
+                                p->d_dlp_grid, 3 * nrhs, s);
+    aim::launch_dlp_moments(p->g, p->d_dlp_grid, nrhs, s);
+    aim::launch_convolve<double>(p->g, p->d_dlp_grid, p->d_dlp_work, p->d_dlp_grid,
+                                 p->d_dlp_spec, p->d_dlp_freq, 6 * nrhs, p->d_tw64, s, nullptr,
+                                 p->sched[0]);
+    aim::launch_dlp_combine(p->g, p->d_dlp_grid, p->d_dlp_phi, nrhs, s);
+    aim::CsrDevice kc = csr_dev(p, AIM_C128);
+    kc.val = p->d_dlp_corr;
+    aim::launch_interp_near<double>(p->g, pt_dev(p, AIM_C128), kc, p->d_dlp_phi, x, y, nrhs,
+                                    true, true, s);
+  });
+}
+
+aim_status aim_dlp_export(aim_plan p, double* near_host, double* corr_host, void* hip_stream) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    no_batch(p);
+    check_prec(p, AIM_C128);
+    ensure_dlp(p, static_cast<hipStream_t>(hip_stream));
+    const size_t nnz = p->t.col.size();
+    if (near_host && nnz) std::memcpy(near_host, p->dlp_near.data(), nnz * 8);
+    if (corr_host && nnz) std::memcpy(corr_host, p->dlp_corr.data(), nnz * 8);
   });
 }
 

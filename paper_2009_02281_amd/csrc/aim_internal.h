@@ -44,6 +44,7 @@ struct HostTables {
   double h = 0.0;
   double origin[3] = {0, 0, 0};
   std::vector<double> area;         // [N]
+  std::vector<double> corners;      // [N][3][3] triangle corners (empty on loaded plans)
   std::vector<double> qp_xyz;       // [3N][3] quadrature points
   std::vector<double> qp_w;         // [3N] weights area/3
   std::vector<int32_t> qp_start;    // [3N][3] stencil start per axis
@@ -173,9 +174,22 @@ void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice
                         bool do_near, hipStream_t s);
 
 // Kernel spectrum for one wavenumber: fills the folded, scaled spectrum
-// (complex128) and optionally its complex64 rounding.
+// (complex128) and optionally its complex64 rounding.  kind 0: the grid
+// kernel G(k, R) with self term -jk/(4 pi); kind 1: the radial factor
+// F(R) = h (1 + jkR) e^{-jkR} / (4 pi R^3) of the double layer's gradient
+// channels (dG/dr'_a = (u_a - v_a) F), 0 at the origin.
 void launch_spectrum(const GridShape& g, double k, double h, void* full_work, void* spec64,
-                     void* spec32, const void* const* tw64, hipStream_t s);
+                     void* spec32, const void* const* tw64, hipStream_t s, int kind = 0);
+// double-layer operator, complex128: xs[a][r] = n_a x[r] (three channels);
+// grids[0 .. 3 nrhs) hold the channels' projections q_a, and the moments
+// (u_a - c_a) q_a are written to grids[3 nrhs .. 6 nrhs), c the grid centre;
+// then phi[r] = sum_a (u_a - c_a) F*q_a - F*((v_a - c_a) q_a) from the six
+// convolved grids
+void launch_dlp_sources(const void* x, const double* nrm, void* xs, int64_t n, int nrhs,
+                        hipStream_t s);
+void launch_dlp_moments(const GridShape& g, void* grids, int nrhs, hipStream_t s);
+void launch_dlp_combine(const GridShape& g, const void* grids, void* phi, int nrhs,
+                        hipStream_t s);
 
 void launch_excitation(int kind, const double* qp_xyz, const double* qp_w, int64_t n,
                        const double* params, int n_params, const double* kvals,
@@ -315,6 +329,10 @@ class NearDevice {
                    std::vector<double>& lin_diag, hipStream_t s);
   void set_static(const std::vector<double>& near_static, hipStream_t s);
   void fill_conventional(double k, void* out_dev, hipStream_t s);
+  // double-layer operator (Sec. III-B): K_s,NR and C_K = K_s,NR - K_s,P on
+  // the near list, for the unit normals nrm [N][3]
+  void fill_dlp(const std::vector<double>& nrm, std::vector<double>& near_out,
+                std::vector<double>& corr_out, hipStream_t s);
   // inverses of the clusters' blocks of the full-kernel Galerkin matrix at
   // wavenumber k (complex128, row-major, at cl_blk offsets; device arrays);
   // throws AIM_ERR_GEOMETRY for a singular block

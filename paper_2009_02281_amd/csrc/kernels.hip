@@ -1000,7 +1000,8 @@ template void launch_convolve<float>(const GridShape&, const void*, void*, void*
 // folded to its (Nx+1)(Ny+1)(Nz+1) distinct entries (the embedding is even in
 // every axis), scaled by 1/(Mx My Mz) and stored [fy][fz][fx]
 // ---------------------------------------------------------------------------
-__global__ void green_sample_kernel(double2* c, int Nx, int Ny, int Nz, double k, double h) {
+__global__ void green_sample_kernel(double2* c, int Nx, int Ny, int Nz, double k, double h,
+                                    int kind) {
   const int Mx = 2 * Nx, My = 2 * Ny, Mz = 2 * Nz;
   const int64_t total = int64_t(Mx) * My * Mz;
   for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
@@ -1017,7 +1018,17 @@ __global__ void green_sample_kernel(double2* c, int Nx, int Ny, int Nz, double k
       const double dz = iz < Nz ? iz : iz - Mz;
       const double d2 = dx * dx + dy * dy + dz * dz;
       const double inv4pi = 0.07957747154594766788;  // 1/(4 pi)
-      if (d2 == 0.0) {
+      if (kind == 1) {
+        // h (1 + jkR) e^{-jkR} / (4 pi R^3), 0 at the origin
+        if (d2 != 0.0) {
+          const double R = h * sqrt(d2);
+          double sn, cs;
+          sincos(k * R, &sn, &cs);
+          const double a = h * inv4pi / (R * R * R), kr = k * R;
+          v.x = (cs + kr * sn) * a;
+          v.y = (kr * cs - sn) * a;
+        }
+      } else if (d2 == 0.0) {
         v.y = -k * inv4pi;  // -jk/(4 pi): modified self term
       } else {
         const double R = h * sqrt(d2);
@@ -1055,11 +1066,12 @@ __global__ void fold_spectrum_kernel(const double2* full, double2* s64, float2* 
 }
 
 void launch_spectrum(const GridShape& g, double k, double h, void* full_work, void* spec64,
-                     void* spec32, const void* const* tw64, hipStream_t s) {
+                     void* spec32, const void* const* tw64, hipStream_t s, int kind) {
   const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
   double2* F = static_cast<double2*>(full_work);
-  hipLaunchKernelGGL(green_sample_kernel, dim3(4096), dim3(256), 0, s, F, Nx, Ny, Nz, k, h);
+  hipLaunchKernelGGL(green_sample_kernel, dim3(4096), dim3(256), 0, s, F, Nx, Ny, Nz, k, h,
+                     kind);
   AIM_HIP(hipGetLastError());
   const int64_t Np = int64_t(Mx) * My * Mz;
   {  // rows (y, z) of the whole padded grid
@@ -2561,6 +2573,88 @@ void launch_zero_words(void* p, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, st,
                      static_cast<uint2*>(p), n);
+  AIM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// double-layer operator (Sec. III-B, eq. KAIMx): the far product
+// W sum_a H_grad,a P diag(n_a) x with the odd channel kernels
+// H_grad,a(u, v) = (u_a - v_a) F(|u - v|), F radial.  Since
+//   sum_v (u_a - v_a) F(u - v) q(v) = (u_a - c_a) (F * q)(u) - (F * ((v_a - c_a) q))(u)
+// for any centre c, the three channels run as six convolutions with the one
+// even kernel F through the pruned FFT path (the centre keeps the two terms'
+// magnitudes, and so the cancellation between them, small).
+// ---------------------------------------------------------------------------
+__global__ void dlp_sources_kernel(const double2* __restrict__ x, const double* __restrict__ nrm,
+                                   double2* __restrict__ xs, int64_t n, int nrhs) {
+  const int r = blockIdx.y;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 v = x[int64_t(r) * n + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double w = nrm[3 * i + a];
+      xs[(int64_t(a) * nrhs + r) * n + i] = make_double2(w * v.x, w * v.y);
+    }
+  }
+}
+
+void launch_dlp_sources(const void* x, const double* nrm, void* xs, int64_t n, int nrhs,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(dlp_sources_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, s,
+                     static_cast<const double2*>(x), nrm, static_cast<double2*>(xs), n, nrhs);
+  AIM_HIP(hipGetLastError());
+}
+
+__global__ void dlp_moments_kernel(double2* __restrict__ g, int Nx, int Ny, int64_t Ng,
+                                   int nrhs, double cx, double cy, double cz) {
+  const int ch = blockIdx.y;  // a nrhs + r
+  const int a = ch / nrhs;
+  const double c = a == 0 ? cx : a == 1 ? cy : cz;
+  const double2* q = g + int64_t(ch) * Ng;
+  double2* m = g + int64_t(3 * nrhs + ch) * Ng;
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
+       u += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t ix = u % Nx, iy = (u / Nx) % Ny, iz = u / (int64_t(Nx) * Ny);
+    const double d = double(a == 0 ? ix : a == 1 ? iy : iz) - c;
+    const double2 v = q[u];
+    m[u] = make_double2(d * v.x, d * v.y);
+  }
+}
+
+void launch_dlp_moments(const GridShape& g, void* grids, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(dlp_moments_kernel, dim3(grid_for(g.Ng, 1024), 3 * nrhs), dim3(256), 0, s,
+                     static_cast<double2*>(grids), g.N[0], g.N[1], g.Ng, nrhs,
+                     0.5 * (g.N[0] - 1), 0.5 * (g.N[1] - 1), 0.5 * (g.N[2] - 1));
+  AIM_HIP(hipGetLastError());
+}
+
+__global__ void dlp_combine_kernel(const double2* __restrict__ g, double2* __restrict__ phi,
+                                   int Nx, int Ny, int64_t Ng, int nrhs, double cx, double cy,
+                                   double cz) {
+  const int r = blockIdx.y;
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
+       u += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t ix = u % Nx, iy = (u / Nx) % Ny, iz = u / (int64_t(Nx) * Ny);
+    const double d[3] = {double(ix) - cx, double(iy) - cy, double(iz) - cz};
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double2 f = g[(int64_t(a) * nrhs + r) * Ng + u];
+      const double2 m = g[(int64_t(3 + a) * nrhs + r) * Ng + u];
+      re += d[a] * f.x - m.x;
+      im += d[a] * f.y - m.y;
+    }
+    phi[int64_t(r) * Ng + u] = make_double2(re, im);
+  }
+}
+
+void launch_dlp_combine(const GridShape& g, const void* grids, void* phi, int nrhs,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(dlp_combine_kernel, dim3(grid_for(g.Ng, 1024), nrhs), dim3(256), 0, s,
+                     static_cast<const double2*>(grids), static_cast<double2*>(phi), g.N[0],
+                     g.N[1], g.Ng, nrhs, 0.5 * (g.N[0] - 1), 0.5 * (g.N[1] - 1),
+                     0.5 * (g.N[2] - 1));
   AIM_HIP(hipGetLastError());
 }
 

@@ -213,6 +213,27 @@ struct GridKernel<1> {
   }
 };
 
+// the double layer's static gradient channels (Sec. III-B): component a is
+// h d_a / (4 pi R^3), R = h |d|, 0 at the origin (kind 3)
+struct Vec3d {
+  double x, y, z;
+};
+template <>
+struct GridKernel<3> {
+  using V = Vec3d;
+  static __device__ V zero() { return {0.0, 0.0, 0.0}; }
+  static __device__ V at(int x, int y, int z, double h, double) {
+    const int q = x * x + y * y + z * z;
+    if (q == 0) return {0.0, 0.0, 0.0};
+    const double R = h * sqrt(double(q));
+    const double f = kInvFourPi * h / (R * R * R);
+    return {f * x, f * y, f * z};
+  }
+  static __device__ V fma(double w, V v, V acc) {
+    return {acc.x + w * v.x, acc.y + w * v.y, acc.z + w * v.z};
+  }
+};
+
 // sum over quadrature-point pairs of w_a w_b sum_{u, v} L_u(r_a) H(u - v) L_v(r_b)
 template <int KIND, int ORDER>
 __device__ typename GridKernel<KIND>::V precorrection(const NearArgs& a, int64_t i, int64_t j) {
@@ -291,6 +312,40 @@ __global__ __launch_bounds__(128) void near_static_kernel(NearArgs a, double* ne
   const double m = 0.5 * (galerkin_static(a, lo, hi) + galerkin_static(a, hi, lo));
   near_static[p] = m;
   corr[p] = m - precorrection<0, ORDER>(a, i, j);
+}
+
+// double-layer operator (Sec. III-B): K_s,NR[i, j] = sum_p w_ip (1/4 pi)
+// int_{T_j} n_j.(r_ip - r') / R^3 dS' and C_K = K_s,NR - K_s,P.  The inner
+// integral is h / |h| times the solid angle T_j subtends at r_ip (h its
+// height above the plane of T_j along n_j; 0 in the plane, to rounding: the
+// principal value of the self pairs); the precorrection dots the static gradient
+// channels' grid product with n_j.
+template <int ORDER>
+__global__ __launch_bounds__(128) void dlp_near_kernel(NearArgs a, const double* nrm,
+                                                       double* near_out, double* corr) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.nnz) return;
+  const int64_t i = row_of(a.rowptr, a.N, p), j = a.col[p];
+  P3 v[3];
+  for (int c = 0; c < 3; ++c)
+    v[c] = {a.tri[9 * j + 3 * c], a.tri[9 * j + 3 * c + 1], a.tri[9 * j + 3 * c + 2]};
+  const P3 n = {nrm[3 * j], nrm[3 * j + 1], nrm[3 * j + 2]};
+  // heights below 1e-14 of the triangle's size are rounding: the point is in
+  // the plane (where the solid angle jumps by 4 pi)
+  const double hmin = 1e-14 * sqrt(len(cross(sub(v[1], v[0]), sub(v[2], v[0]))));
+  double s = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    const int64_t qi = 3 * i + q;
+    const P3 r = {a.qp[3 * qi], a.qp[3 * qi + 1], a.qp[3 * qi + 2]};
+    const double h = dot(sub(r, v[0]), n);
+    if (fabs(h) <= hmin) continue;
+    const double om = solid_angle(sub(v[0], r), sub(v[1], r), sub(v[2], r));
+    s += a.qw[qi] * (h > 0.0 ? om : -om);
+  }
+  s *= kInvFourPi;
+  near_out[p] = s;
+  const Vec3d pc = precorrection<3, ORDER>(a, i, j);
+  corr[p] = s - (pc.x * n.x + pc.y * n.y + pc.z * n.z);
 }
 
 // conventional AIM: A_NR(k) - A_P(k) from the static entries
@@ -484,13 +539,15 @@ NearDevice::NearDevice(const HostTables& t, const double* V, const int32_t* T,
     : N_(t.N), nnz_(t.rowptr.empty() ? 0 : t.rowptr[t.N]), order_(t.order), h_(t.h),
       alloc_(alloc), free_(free_fn), ctx_(ctx), stream_(s) {
   try {
-    if (V && T) {  // corners: only the static fill needs them
+    if (V && T) {  // corners: only the static and double-layer fills need them
       std::vector<double> tri(9 * size_t(N_));
       for (int64_t j = 0; j < N_; ++j)
         for (int c = 0; c < 3; ++c)
           for (int ax = 0; ax < 3; ++ax)
             tri[9 * j + 3 * c + ax] = V[3 * int64_t(T[3 * j + c]) + ax];
       tri_ = put(get(tri.size() * 8), tri, s);
+    } else if (t.corners.size() == 9 * size_t(N_)) {
+      tri_ = put(get(t.corners.size() * 8), t.corners, s);
     }
     qp_ = put(get(t.qp_xyz.size() * 8), t.qp_xyz, s);
     qw_ = put(get(t.qp_w.size() * 8), t.qp_w, s);
@@ -535,6 +592,32 @@ static NearArgs make_args(const void* tri, const void* qp, const void* qw, const
   a.h = h;
   a.k = k;
   return a;
+}
+
+void NearDevice::fill_dlp(const std::vector<double>& nrm, std::vector<double>& near_out,
+                          std::vector<double>& corr_out, hipStream_t s) {
+  AIM_REQUIRE(tri_ != nullptr, AIM_ERR_STATE, "near-field tables built without the mesh");
+  AIM_REQUIRE(nrm.size() == 3 * size_t(N_), AIM_ERR_INVALID_ARG, "one normal per triangle");
+  const NearArgs a = make_args(tri_, qp_, qw_, qstart_, qlocal_, rowptr_, col_, N_, nnz_, h_,
+                               0.0);
+  near_out.assign(nnz_, 0.0);
+  corr_out.assign(nnz_, 0.0);
+  if (nnz_ == 0) return;
+  void* buf = get(size_t(2 * nnz_ + 3 * N_) * 8);
+  double* nd = static_cast<double*>(buf);
+  double* cd = nd + nnz_;
+  double* nr = cd + nnz_;
+  AIM_HIP(hipMemcpyAsync(nr, nrm.data(), size_t(3 * N_) * 8, hipMemcpyHostToDevice, s));
+  if (order_ == 2)
+    hipLaunchKernelGGL(dlp_near_kernel<2>, dim3(blocks_for(nnz_)), dim3(128), 0, s, a, nr, nd,
+                       cd);
+  else
+    hipLaunchKernelGGL(dlp_near_kernel<3>, dim3(blocks_for(nnz_)), dim3(128), 0, s, a, nr, nd,
+                       cd);
+  AIM_HIP(hipGetLastError());
+  AIM_HIP(hipMemcpyAsync(near_out.data(), nd, size_t(nnz_) * 8, hipMemcpyDeviceToHost, s));
+  AIM_HIP(hipMemcpyAsync(corr_out.data(), cd, size_t(nnz_) * 8, hipMemcpyDeviceToHost, s));
+  AIM_HIP(hipStreamSynchronize(s));
 }
 
 void NearDevice::fill_static(std::vector<double>& near_static, std::vector<double>& corr,

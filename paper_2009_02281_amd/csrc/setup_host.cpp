@@ -337,6 +337,7 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t, bool near_on_host
                                     {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0},
                                     {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0}};
   t.area.resize(N);
+  t.corners.resize(9 * N);
   t.qp_xyz.resize(9 * N);
   t.qp_w.resize(3 * N);
   t.qp_start.resize(9 * N);
@@ -354,7 +355,12 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t, bool near_on_host
     AIM_REQUIRE(std::isfinite(A) && A > 1e-14 * diag * diag, AIM_ERR_GEOMETRY,
                 "zero-area triangle " + std::to_string(j));
     t.area[j] = A;
-    for (int a2 = 0; a2 < 3; ++a2) cent[3 * j + a2] = (a[a2] + b[a2] + c[a2]) / 3.0;
+    for (int a2 = 0; a2 < 3; ++a2) {
+      cent[3 * j + a2] = (a[a2] + b[a2] + c[a2]) / 3.0;
+      t.corners[9 * j + a2] = a[a2];
+      t.corners[9 * j + 3 + a2] = b[a2];
+      t.corners[9 * j + 6 + a2] = c[a2];
+    }
     for (int q = 0; q < 3; ++q) {
       const int64_t p = 3 * j + q;
       t.qp_w[p] = A / 3.0;
