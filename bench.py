@@ -604,7 +604,7 @@ def dlp_leg(plan, w, reps: int = 20) -> dict:
     ms = a.elapsed_time(b) / reps
     res = {"workload": w.name, "first_call_seconds": first, "ms_per_matvec": ms,
            "unknowns_matvecs_per_s": w.n / (ms * 1e-3),
-           "note": "complex128; three gradient channels as six convolutions with one even "
+           "note": "complex128; three gradient channels as four convolutions with one even "
                    "kernel; the first call builds the tables"}
     print(f"[bench] double layer on {w.name}: {ms:.3f} ms per matvec (first call "
           f"{first:.2f}s)", file=sys.stderr, flush=True)

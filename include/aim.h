@@ -345,7 +345,7 @@ aim_status aim_conventional_export(aim_plan plan, double* vals_host, void* hip_s
  * complex128 device buffers (caller-owned, not overlapping), freq_idx_host
  * [nrhs] indices into the plan's wavenumbers (NULL: all 0).  The first call
  * builds the operator's tables on the device (normals, the near values, one
- * spectrum per wavenumber, buffers for max_rhs products: about 6 max_rhs
+ * spectrum per wavenumber, buffers for max_rhs products: about 4 max_rhs
  * times the matvec's workspace); needs the complex128 tables and the mesh
  * (AIM_ERR_STATE on loaded or host-only plans).  Asynchronous after that
  * first call.  Not on batch plans. */

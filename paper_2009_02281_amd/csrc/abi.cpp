@@ -166,10 +166,10 @@ struct aim_plan_s {
   double* d_dlp_corr = nullptr;    // [nnz] C_K = K_s,NR - K_s,P on the near list
   void* d_dlp_spec = nullptr;      // [nfreq] folded spectra of the radial factor F
   void* d_dlp_src = nullptr;       // [3 max_rhs][N] channel sources n_a x
-  void* d_dlp_grid = nullptr;      // [6 max_rhs][Ng] channel grids and moments
-  void* d_dlp_work = nullptr;      // convolution workspace of 6 max_rhs grids
+  void* d_dlp_grid = nullptr;      // [4 max_rhs][Ng] channel grids and moment sums
+  void* d_dlp_work = nullptr;      // convolution workspace of 4 max_rhs grids
   void* d_dlp_phi = nullptr;       // [max_rhs][Ng] combined potential
-  int32_t* d_dlp_freq = nullptr;   // [6 max_rhs] spectrum index per grid
+  int32_t* d_dlp_freq = nullptr;   // [4 max_rhs] spectrum index per grid
   int32_t* h_dlp_freq = nullptr;   // pinned staging
   std::vector<int32_t> dlp_cur_freq;
   std::vector<double> dlp_near, dlp_corr;  // host copies (aim_dlp_export)
@@ -967,11 +967,11 @@ void ensure_dlp(aim_plan p, hipStream_t s) {
   p->d_dlp_corr = p->upload(p->dlp_corr.empty() ? std::vector<double>(1, 0.0) : p->dlp_corr, s);
   p->d_dlp_spec = p->dalloc(size_t(g.Nfold) * 16 * p->nfreq, s);
   p->d_dlp_src = p->dalloc(size_t(3) * R * N * 16, s);
-  p->d_dlp_grid = p->dalloc(size_t(6) * R * g.Ng * 16, s);
-  p->d_dlp_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 6 * R, s);
+  p->d_dlp_grid = p->dalloc(size_t(4) * R * g.Ng * 16, s);
+  p->d_dlp_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 4 * R, s);
   p->d_dlp_phi = p->dalloc(size_t(R) * g.Ng * 16, s);
-  p->d_dlp_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 6 * R, s));
-  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_dlp_freq), sizeof(int32_t) * 6 * R, 0));
+  p->d_dlp_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 4 * R, s));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_dlp_freq), sizeof(int32_t) * 4 * R, 0));
   void* full = nullptr;
   AIM_HIP(hipMalloc(&full, size_t(8) * g.Ng * 16));
   try {
@@ -1011,10 +1011,10 @@ aim_status aim_matvec_dlp(aim_plan p, const void* x, void* y, int32_t nrhs,
       }
     }
     ensure_dlp(p, s);
-    // one spectrum index per grid: the six grids of right-hand side r all use
+    // one spectrum index per grid: the four grids of right-hand side r all use
     // its wavenumber
-    std::vector<int32_t> f6(size_t(6) * nrhs);
-    for (int c = 0; c < 6; ++c)
+    std::vector<int32_t> f6(size_t(4) * nrhs);
+    for (int c = 0; c < 4; ++c)
       for (int r = 0; r < nrhs; ++r) f6[size_t(c) * nrhs + r] = fr[r];
     if (f6 != p->dlp_cur_freq) {
       AIM_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed a copy
@@ -1029,7 +1029,7 @@ aim_status aim_matvec_dlp(aim_plan p, const void* x, void* y, int32_t nrhs,
                                 p->d_dlp_grid, 3 * nrhs, s);
     aim::launch_dlp_moments(p->g, p->d_dlp_grid, nrhs, s);
     aim::launch_convolve<double>(p->g, p->d_dlp_grid, p->d_dlp_work, p->d_dlp_grid,
-                                 p->d_dlp_spec, p->d_dlp_freq, 6 * nrhs, p->d_tw64, s, nullptr,
+                                 p->d_dlp_spec, p->d_dlp_freq, 4 * nrhs, p->d_tw64, s, nullptr,
                                  p->sched[0]);
     aim::launch_dlp_combine(p->g, p->d_dlp_grid, p->d_dlp_phi, nrhs, s);
     aim::CsrDevice kc = csr_dev(p, AIM_C128);

@@ -181,10 +181,10 @@ void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice
 void launch_spectrum(const GridShape& g, double k, double h, void* full_work, void* spec64,
                      void* spec32, const void* const* tw64, hipStream_t s, int kind = 0);
 // double-layer operator, complex128: xs[a][r] = n_a x[r] (three channels);
-// grids[0 .. 3 nrhs) hold the channels' projections q_a, and the moments
-// (u_a - c_a) q_a are written to grids[3 nrhs .. 6 nrhs), c the grid centre;
-// then phi[r] = sum_a (u_a - c_a) F*q_a - F*((v_a - c_a) q_a) from the six
-// convolved grids
+// grids[0 .. 3 nrhs) hold the channels' projections q_a, and the moment sum
+// m = sum_a (v_a - c_a) q_a is written to grids[3 nrhs .. 4 nrhs), c the grid
+// centre; then phi[r] = sum_a (u_a - c_a) F*q_a - F*m from the four convolved
+// grids
 void launch_dlp_sources(const void* x, const double* nrm, void* xs, int64_t n, int nrhs,
                         hipStream_t s);
 void launch_dlp_moments(const GridShape& g, void* grids, int nrhs, hipStream_t s);

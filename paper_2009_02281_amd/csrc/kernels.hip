@@ -2581,9 +2581,11 @@ void launch_zero_words(void* p, int64_t n, hipStream_t st) {
 // W sum_a H_grad,a P diag(n_a) x with the odd channel kernels
 // H_grad,a(u, v) = (u_a - v_a) F(|u - v|), F radial.  Since
 //   sum_v (u_a - v_a) F(u - v) q(v) = (u_a - c_a) (F * q)(u) - (F * ((v_a - c_a) q))(u)
-// for any centre c, the three channels run as six convolutions with the one
-// even kernel F through the pruned FFT path (the centre keeps the two terms'
-// magnitudes, and so the cancellation between them, small).
+// for any centre c, and the second terms of the three channels add up before
+// the convolution: four convolutions with the one even kernel F through the
+// pruned FFT path, F*q_a for a = x, y, z and F*m with m = sum_a (v_a - c_a) q_a
+// (the centre keeps the two terms' magnitudes, and so the cancellation
+// between them, small).
 // ---------------------------------------------------------------------------
 __global__ void dlp_sources_kernel(const double2* __restrict__ x, const double* __restrict__ nrm,
                                    double2* __restrict__ xs, int64_t n, int nrhs) {
@@ -2608,22 +2610,25 @@ void launch_dlp_sources(const void* x, const double* nrm, void* xs, int64_t n, i
 
 __global__ void dlp_moments_kernel(double2* __restrict__ g, int Nx, int Ny, int64_t Ng,
                                    int nrhs, double cx, double cy, double cz) {
-  const int ch = blockIdx.y;  // a nrhs + r
-  const int a = ch / nrhs;
-  const double c = a == 0 ? cx : a == 1 ? cy : cz;
-  const double2* q = g + int64_t(ch) * Ng;
-  double2* m = g + int64_t(3 * nrhs + ch) * Ng;
+  const int r = blockIdx.y;
+  double2* m = g + int64_t(3 * nrhs + r) * Ng;
   for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
        u += int64_t(gridDim.x) * blockDim.x) {
     const int64_t ix = u % Nx, iy = (u / Nx) % Ny, iz = u / (int64_t(Nx) * Ny);
-    const double d = double(a == 0 ? ix : a == 1 ? iy : iz) - c;
-    const double2 v = q[u];
-    m[u] = make_double2(d * v.x, d * v.y);
+    const double d[3] = {double(ix) - cx, double(iy) - cy, double(iz) - cz};
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double2 v = g[(int64_t(a) * nrhs + r) * Ng + u];
+      re += d[a] * v.x;
+      im += d[a] * v.y;
+    }
+    m[u] = make_double2(re, im);
   }
 }
 
 void launch_dlp_moments(const GridShape& g, void* grids, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(dlp_moments_kernel, dim3(grid_for(g.Ng, 1024), 3 * nrhs), dim3(256), 0, s,
+  hipLaunchKernelGGL(dlp_moments_kernel, dim3(grid_for(g.Ng, 1024), nrhs), dim3(256), 0, s,
                      static_cast<double2*>(grids), g.N[0], g.N[1], g.Ng, nrhs,
                      0.5 * (g.N[0] - 1), 0.5 * (g.N[1] - 1), 0.5 * (g.N[2] - 1));
   AIM_HIP(hipGetLastError());
@@ -2637,13 +2642,13 @@ __global__ void dlp_combine_kernel(const double2* __restrict__ g, double2* __res
        u += int64_t(gridDim.x) * blockDim.x) {
     const int64_t ix = u % Nx, iy = (u / Nx) % Ny, iz = u / (int64_t(Nx) * Ny);
     const double d[3] = {double(ix) - cx, double(iy) - cy, double(iz) - cz};
-    double re = 0.0, im = 0.0;
+    const double2 m = g[(int64_t(3) * nrhs + r) * Ng + u];
+    double re = -m.x, im = -m.y;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double2 f = g[(int64_t(a) * nrhs + r) * Ng + u];
-      const double2 m = g[(int64_t(3 + a) * nrhs + r) * Ng + u];
-      re += d[a] * f.x - m.x;
-      im += d[a] * f.y - m.y;
+      re += d[a] * f.x;
+      im += d[a] * f.y;
     }
     phi[int64_t(r) * Ng + u] = make_double2(re, im);
   }
