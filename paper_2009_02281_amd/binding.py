@@ -340,16 +340,50 @@ def _make_desc(vertices, triangles, order, dims, h, near_threshold, k, precision
     return d, (V, T, kk)
 
 
+class TorchAllocator:
+    """Device memory for a plan from PyTorch's caching allocator, passed to
+    aim_setup as its allocator callbacks (aim_alloc_fn / aim_free_fn).  Counts
+    the live blocks so a caller can see that everything came back."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.live = {}
+        self.calls = 0
+        self._alloc = ALLOC_FN(self._do_alloc)
+        self._free = FREE_FN(self._do_free)
+
+    def _do_alloc(self, nbytes, stream, ctx):
+        try:
+            ptr = int(self._torch.cuda.caching_allocator_alloc(max(int(nbytes), 1)))
+        except Exception:  # noqa: BLE001 - the library reports AIM_ERR_OOM for NULL
+            return None
+        self.live[ptr] = int(nbytes)
+        self.calls += 1
+        return ptr
+
+    def _do_free(self, ptr, stream, ctx):
+        if ptr:
+            self.live.pop(int(ptr), None)
+            self._torch.cuda.caching_allocator_delete(int(ptr))
+
+
 class Plan:
     """An AIMx operator for one mesh, grid and frequency set (see aim_setup)."""
 
     def __init__(self, vertices, triangles, order: int, dims, h: float, near_threshold: float,
                  k, precisions=("c128", "c64"), max_rhs: int = 1, n_threads: int = 0,
-                 stream=None, host_only: bool = False):
+                 stream=None, host_only: bool = False, allocator=None):
+        """``allocator``: None (the library's own hipMalloc) or a
+        TorchAllocator, which the plan keeps until it is closed."""
         lib = load_library()
         self._lib = lib
         d, keep = _make_desc(vertices, triangles, order, dims, h, near_threshold, k, precisions,
                              max_rhs, n_threads)
+        self._allocator = allocator
+        if allocator is not None:
+            d.alloc = allocator._alloc
+            d.free = allocator._free
         kk = keep[2]
         self._plan = C.c_void_p()
         self.precisions = tuple(precisions)

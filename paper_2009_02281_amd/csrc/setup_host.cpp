@@ -88,55 +88,59 @@ inline void lagrange(double u, int order, double* out) {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// closed-form 1/R over a flat triangle (edge-sum form; Wilton et al. 1984)
-// ---------------------------------------------------------------------------
+// Integral over the triangle (a, b, c) of 1/|r - r'| dS': the in-plane
+// divergence identity div_s[(rho' - rho)/R] = 1/R + h^2/R^3 turns it into
+// edge integrals, sum_i P0_i int_{edge i} dl/R, minus |h| times the solid
+// angle the triangle subtends at r (van Oosterom and Strackee, 1983) -- the
+// form the device fill uses.  The edge logarithm is written without
+// cancellation on either side of the foot point.
 double triangle_inv_r(const double r[3], const double a[3], const double b[3], const double c[3]) {
   const double* v[3] = {a, b, c};
-  double e1[3], e2[3], n[3];
+  double e1[3], e2[3], nn[3];
   sub3(b, a, e1);
   sub3(c, a, e2);
-  cross3(e1, e2, n);
-  const double area2 = norm3(n);
-  for (double& x : n) x /= area2;
-  const double size = std::sqrt(area2);
+  cross3(e1, e2, nn);
+  const double tw = norm3(nn);
+  const double n[3] = {nn[0] / tw, nn[1] / tw, nn[2] / tw};
   double ra[3];
   sub3(r, a, ra);
   const double h = dot3(ra, n);
-  const double ah = std::fabs(h);
-  double rho[3] = {r[0] - h * n[0], r[1] - h * n[1], r[2] - h * n[2]};
-  double total = 0.0;
-  for (int i = 0; i < 3; ++i) {
-    const double* pm = v[i];
-    const double* pp = v[(i + 1) % 3];
-    double e[3];
-    sub3(pp, pm, e);
-    const double le = norm3(e);
-    double lhat[3] = {e[0] / le, e[1] / le, e[2] / le};
-    double uhat[3];
-    cross3(lhat, n, uhat);  // outward in-plane normal of the edge
-    double dpp[3], dpm[3];
-    sub3(pp, rho, dpp);
-    sub3(pm, rho, dpm);
-    const double lp = dot3(dpp, lhat);
-    const double lm = dot3(dpm, lhat);
-    const double P0 = dot3(dpm, uhat);  // > 0 when rho is on the inner side
-    const double R0sq = P0 * P0 + h * h;
-    double rp[3], rm[3];
-    sub3(r, pp, rp);
-    sub3(r, pm, rm);
-    const double Rp = norm3(rp);
-    const double Rm = norm3(rm);
-    if (std::fabs(P0) > 1e-14 * size) {
-      // R + l without cancellation: R0^2 / (R - l) when l < 0
-      const double num = lp >= 0.0 ? Rp + lp : R0sq / (Rp - lp);
-      const double den = lm >= 0.0 ? Rm + lm : R0sq / (Rm - lm);
-      total += P0 * std::log(num / den);
-      if (ah > 1e-14 * size)
-        total -= ah * (std::atan(P0 * lp / (R0sq + ah * Rp)) - std::atan(P0 * lm / (R0sq + ah * Rm)));
-    }
+  double acc = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    const double* p = v[e];
+    const double* q = v[(e + 1) % 3];
+    double d[3];
+    sub3(q, p, d);
+    const double L = norm3(d);
+    const double u[3] = {d[0] / L, d[1] / L, d[2] / L};  // counter-clockwise about n
+    double m[3];
+    cross3(u, n, m);  // outward in-plane normal of the edge
+    double pr[3], qr[3];
+    sub3(p, r, pr);
+    sub3(q, r, qr);
+    const double P0 = dot3(pr, m);
+    if (std::fabs(P0) <= 1e-15 * L) continue;  // foot on the edge line: no term
+    const double lm = dot3(pr, u), lp = dot3(qr, u);
+    const double Rm = norm3(pr), Rp = norm3(qr), R0sq = P0 * P0 + h * h;
+    double lg;
+    if (lm >= 0.0)
+      lg = std::log((Rp + lp) / (Rm + lm));
+    else if (lp <= 0.0)
+      lg = std::log((Rm - lm) / (Rp - lp));  // the segment mirrored through the foot
+    else
+      lg = std::log((Rp + lp) * (Rm - lm) / R0sq);  // (R + l)(R - l) = R0^2
+    acc += P0 * lg;
   }
-  return total;
+  double A[3], B[3], Cv[3], bc[3];
+  sub3(a, r, A);
+  sub3(b, r, B);
+  sub3(c, r, Cv);
+  cross3(B, Cv, bc);
+  const double la = norm3(A), lb = norm3(B), lc = norm3(Cv);
+  const double num = std::fabs(dot3(A, bc));
+  const double den = la * lb * lc + dot3(A, B) * lc + dot3(A, Cv) * lb + dot3(B, Cv) * la;
+  acc -= std::fabs(h) * 2.0 * std::atan2(num, den);
+  return acc;
 }
 
 // A_s,NR and C = A_s,NR - A_s,P on the near list (host).

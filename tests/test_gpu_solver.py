@@ -300,3 +300,45 @@ def test_large_sphere_mixed_precision_solve_matches_mie_series():
     print(f"    exterior field vs Mie {err:.2e}", flush=True)
     assert err < 3e-2
     p.close()
+
+
+def test_solver_graph_replay_matches_direct_launches(monkeypatch):
+    """With AIM_SOLVER_GRAPHS=1 the solver replays captured matvec graphs
+    (one per operand pair, replayed every step); iterations and solutions
+    equal those of direct launches, in complex128 and with complex64 inner
+    solves."""
+    w = I.sphere_small()
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
+    b = p.excitation("plane_wave", [0.0, 0.0, 1.0])
+    for inner in ("c128", "c64"):
+        monkeypatch.delenv("AIM_SOLVER_GRAPHS", raising=False)
+        x0, r0 = p.solve(b, rtol=1e-8, restart=30, pc="diag", inner=inner)
+        monkeypatch.setenv("AIM_SOLVER_GRAPHS", "1")
+        x1, r1 = p.solve(b, rtol=1e-8, restart=30, pc="diag", inner=inner)
+        monkeypatch.delenv("AIM_SOLVER_GRAPHS")
+        assert r0.converged.all() and r1.converged.all()
+        assert r1.iters.tolist() == r0.iters.tolist(), inner
+        assert torch.equal(x0, x1), inner
+    p.close()
+
+
+def test_plan_with_the_callers_allocator():
+    """Every table and workspace of a plan built with the caller's
+    allocator (PyTorch's caching allocator through aim_alloc_fn) comes from
+    it and goes back on destroy; its matvecs and solves equal those of a
+    plan that allocates for itself."""
+    w = I.sphere_small()
+    alloc = binding.TorchAllocator()
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     allocator=alloc)
+    q = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
+    assert alloc.calls > 10 and len(alloc.live) > 10
+    x = torch.from_numpy(I.complex_gaussian(p.n, 77)).cuda()
+    assert torch.equal(p.matvec(x), q.matvec(x))
+    b = p.excitation("plane_wave", [0.0, 0.0, 1.0])
+    xa, ra = p.solve(b, rtol=1e-8, restart=30, pc="nearblock")
+    xb, rb = q.solve(b, rtol=1e-8, restart=30, pc="nearblock")
+    assert ra.iters.tolist() == rb.iters.tolist() and torch.equal(xa, xb)
+    p.close()
+    q.close()
+    assert not alloc.live
