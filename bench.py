@@ -301,8 +301,8 @@ def batch_learned_leg(rtol: float, restart: int = 200, pairs: int = 20000,
                       epochs: int = 3) -> dict:
     """The learned preconditioner at the uneven batch's scale.  Pairs are
     logged from plain complex128 GMRES(12) to 1e-8 on uneven training
-    geometries of their own seed (5004; spheres, boxes and box arrays of
-    5k-25k triangles, grids from 32^3 to 128x64x64, eight plane waves each), the
+    geometries of their own seed (5004; 40 spheres, boxes and box arrays of
+    5k-16k triangles, grids from 32^3 to 64x128x32, eight plane waves each), the
     network is trained on them with the residual loss over the diagonal
     preconditioner, and the 32-instance batch (seed 5003) is then solved in
     one batched solve with pc=unet (complex64 matvecs in complex128
@@ -318,7 +318,7 @@ def batch_learned_leg(rtol: float, restart: int = 200, pairs: int = 20000,
         d = rng.standard_normal((n, 3))
         return d / np.linalg.norm(d, axis=1, keepdims=True)
 
-    train = I.uneven_batch(count=24, seed=5004, n_range=(5000, 25000))
+    train = I.uneven_batch(count=40, seed=5004, n_range=(5000, 16000))
     per = max(1, pairs // len(train))
     t0 = time.perf_counter()
     data, err2, res2, count, skipped = [], 0.0, 0.0, 0, 0
