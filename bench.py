@@ -298,7 +298,7 @@ def batch_leg(rtol: float, pcs=("diag", "nearblock"), restart: int = RESTART) ->
 
 
 def batch_learned_leg(rtol: float, restart: int = 200, pairs: int = 20000,
-                      epochs: int = 3) -> dict:
+                      epochs: int = 8) -> dict:
     """The learned preconditioner at the uneven batch's scale.  Pairs are
     logged from plain complex128 GMRES(12) to 1e-8 on uneven training
     geometries of their own seed (5004; 40 spheres, boxes and box arrays of
@@ -349,15 +349,20 @@ def batch_learned_leg(rtol: float, restart: int = 200, pairs: int = 20000,
     t0 = time.perf_counter()
     loss = []
     for _ in range(epochs):
-        tot, nb = 0.0, 0
-        for gi in order_rng.permutation(len(data)):
-            p, grids, ts = data[gi]
+        # batches of eight pairs of one geometry (their grids share a shape),
+        # the batches of all geometries shuffled together: consecutive steps
+        # from one geometry overfit it and undo the previous ones
+        batches = []
+        for gi, (p, grids, ts) in enumerate(data):
             idx = order_rng.permutation(grids.shape[0])
-            for s0 in range(0, len(idx), 8):
-                tot += p.pc_train_step(net, grids, ts, idx[s0:s0 + 8], tau=tau, weight=weight,
-                                       loss="residual", lr=1e-3)
-                nb += 1
-        loss.append(tot / nb)
+            batches += [(gi, idx[s0:s0 + 8]) for s0 in range(0, len(idx), 8)]
+        tot = 0.0
+        for bi in order_rng.permutation(len(batches)):
+            gi, idx = batches[bi]
+            p, grids, ts = data[gi]
+            tot += p.pc_train_step(net, grids, ts, idx, tau=tau, weight=weight,
+                                   loss="residual", lr=1e-3)
+        loss.append(tot / max(1, len(batches)))
         print(f"[bench] batch learned: epoch loss {loss[-1]:.4f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
