@@ -497,40 +497,45 @@ def unet_flops(P0: int, C: int = 16) -> float:
     return f + 2 * c0 * 2 * P0
 
 
-def unet_leg(dims=(64, 64, 64), reps: int = 20) -> dict:
+def unet_leg(dims=(64, 64, 64), reps: int = 20, batches=(1, 8)) -> dict:
     """Forward pass and training step (forward + backward + Adam) of the
-    learned preconditioner's network on one grid, timed with events on the
-    stream the kernels run on; bf16 MFMA roofline."""
+    learned preconditioner's network on one grid and on a batch of grids
+    (stacked along z, one pass), timed with events on the stream the kernels
+    run on; bf16 MFMA roofline."""
     import numpy as np
     import torch
     from paper_2009_02281_amd import binding
     net = binding.UNet(seed=1)
     nx, ny, nz = dims
-    g = torch.from_numpy((np.random.default_rng(7).standard_normal((nz, ny, nx, 2)))
-                         .astype(np.float32)).view(torch.complex64)[..., 0].contiguous().cuda()
-    t = torch.zeros_like(g)
     P0 = nx * ny * nz
     res = {}
-    for name, fn, mult in (("forward", lambda: net.forward(g), 1.0),
-                           ("train_step", lambda: net.train_grid(g, t, lr=1e-4), 3.0)):
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / reps
-        tf = mult * unet_flops(P0) / (ms * 1e-3) / 1e12
-        res[name] = {"ms": ms, "tflops": tf, "frac_bf16_peak": tf / MFMA_BF16_PEAK_TFLOPS}
-        print(f"[bench] unet {name} {list(dims)}: {ms:.3f} ms, {tf:.1f} TFLOP/s", file=sys.stderr,
-              flush=True)
+    for nb in batches:
+        g = torch.from_numpy((np.random.default_rng(7).standard_normal((nb, nz, ny, nx, 2)))
+                             .astype(np.float32)).view(torch.complex64)[..., 0].contiguous().cuda()
+        t = torch.zeros_like(g)
+        for name, fn, mult in (("forward", lambda: net.forward(g), 1.0),
+                               ("train_step", lambda: net.train_grid(g, t, lr=1e-4), 3.0)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            tf = mult * nb * unet_flops(P0) / (ms * 1e-3) / 1e12
+            key = name if nb == 1 else f"{name}_batch{nb}"
+            res[key] = {"ms": ms, "tflops": tf, "frac_bf16_peak": tf / MFMA_BF16_PEAK_TFLOPS}
+            print(f"[bench] unet {key} {list(dims)}: {ms:.3f} ms, {tf:.1f} TFLOP/s",
+                  file=sys.stderr, flush=True)
+        del g, t
     net.close()
     return {"grid": list(dims), "flops_forward": unet_flops(P0),
             "note": "train_step counted as 3x the forward flops (data and weight gradients); "
-                    "it also holds host synchronisation for the loss", **res}
+                    "it also holds host synchronisation for the loss; _batchN: N grids in one "
+                    "pass", **res}
 
 
 def time_matvecs(plan, x, y, prec: str, steps: int, warmup: int, freq=None) -> float:
