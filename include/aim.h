@@ -357,6 +357,46 @@ aim_status aim_matvec_dlp(aim_plan plan, const void* x_dev, void* y_dev, int32_t
 aim_status aim_dlp_export(aim_plan plan, double* near_host, double* corr_host,
                           void* hip_stream);
 
+/* The electric-field integral operator on RWG functions under AIMx (Sec.
+ * II-A, eq. EFIEdis; Sec. II-B, eqs. aimLFR and LAIMx; the static split of
+ * Sec. III-A), the factor -j omega mu left out:
+ *   Z_mn = int int f_m(r).f_n(r') G dS' dS
+ *          - k^-2 int int (div f_m)(r) (div' f_n)(r') G dS' dS,
+ * evaluated as C_A - k^-2 C_phi + sum_{c=x,y,z} P_c^T H(k) P_c
+ * - k^-2 P_q^T H(k) P_q: three Cartesian current channels and one charge
+ * channel through the plan's grid, stencils and spectrum H(k) (self term
+ * -jk/(4 pi)), and the real static corrections C_A = A_s,NR - A_s,P and
+ * C_phi likewise (kernel 1/(4 pi R), inner integrals int 1/R and int r'/R in
+ * closed form, 3-point outer rule, symmetrised; precorrection through H_s
+ * with self term 0).  One function per edge shared by two triangles T+, T-
+ * (T+ the lower triangle index), numbered in ascending order of the edge's
+ * (smaller, larger) vertex index pair: f = l/(2A+) (r - p+) on T+ and
+ * l/(2A-) (p- - r) on T-, p+- the vertices opposite the edge; edges of one
+ * triangle carry none (open surfaces), an edge of three or more triangles is
+ * AIM_ERR_GEOMETRY.  Two functions are near when a triangle of one is in the
+ * near list of a triangle of the other.
+ * aim_efie_setup builds the tables (functions, near list and point
+ * projection on the host threads of the plan's descriptor, the near pairs'
+ * integrals on the device; blocking) and returns the number of functions,
+ * the near-list length and the build time (each pointer may be NULL); the
+ * other two calls build them on first use.  Needs the complex128 tables and
+ * the mesh (AIM_ERR_STATE on loaded, host-only or batch plans); the device
+ * buffers hold 4 max_rhs point-source vectors, grids and convolution
+ * workspaces.
+ * aim_matvec_efie: y = Z(k_f) x, x_dev and y_dev [nrhs][n_rwg] complex128
+ * device buffers (caller-owned, not overlapping), freq_idx_host [nrhs]
+ * indices into the plan's wavenumbers (NULL: all 0); asynchronous on
+ * hip_stream.
+ * aim_efie_export copies to the host, each pointer optional: tri_rwg [N][3]
+ * (function on the edge opposite vertex e of triangle t, -1 none), the near
+ * list rowptr [n_rwg + 1] and col [nnz], and C_A, C_phi [nnz]; blocking. */
+aim_status aim_efie_setup(aim_plan plan, int64_t* n_rwg, int64_t* nnz, double* seconds,
+                          void* hip_stream);
+aim_status aim_matvec_efie(aim_plan plan, const void* x_dev, void* y_dev, int32_t nrhs,
+                           const int32_t* freq_idx_host, void* hip_stream);
+aim_status aim_efie_export(aim_plan plan, int32_t* tri_rwg, int32_t* rowptr, int32_t* col,
+                           double* ca, double* cphi, void* hip_stream);
+
 /* One stage of the matvec, for stage-level checks (see aim_stage for the
  * shapes).  Same rules as aim_matvec; grids are unpadded [nrhs][Nz][Ny][Nx]. */
 aim_status aim_apply_stage(aim_plan plan, aim_precision prec, aim_stage stage,

@@ -32,6 +32,7 @@ RHS = {"plane_wave": 0, "gaussian_patch": 1}
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec",
             "aim_matvec_static", "aim_conventional_fill", "aim_matvec_conventional",
             "aim_conventional_export", "aim_matvec_dlp", "aim_dlp_export",
+            "aim_efie_setup", "aim_matvec_efie", "aim_efie_export",
             "aim_export_clusters", "aim_set_lin_term",
             "aim_export_lin_diag", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
@@ -124,6 +125,12 @@ def load_library(path: str = LIB_PATH):
     lib.aim_conventional_export.argtypes = [vp, C.POINTER(C.c_double), vp]
     lib.aim_matvec_dlp.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), vp]
     lib.aim_dlp_export.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
+    lib.aim_efie_setup.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double), vp]
+    lib.aim_matvec_efie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), vp]
+    lib.aim_efie_export.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), vp]
     lib.aim_matvec_static.argtypes = [vp, i32, vp, vp, i32, ip32, vp]
     lib.aim_apply_stage.argtypes = [vp, i32, i32, vp, vp, i32, ip32, vp]
     lib.aim_excitation.argtypes = [vp, i32, C.POINTER(C.c_double), i32, i32, ip32, vp, vp]
@@ -633,6 +640,47 @@ class Plan:
                                         corr.ctypes.data_as(C.POINTER(C.c_double)),
                                         _stream_ptr(stream)))
         return near[:nnz], corr[:nnz]
+
+    def efie_setup(self, stream=None) -> dict:
+        """Builds the RWG EFIE tables; returns the number of functions, the
+        near-list length and the build time."""
+        n, nnz, sec = C.c_int64(), C.c_int64(), C.c_double()
+        _check(self._lib.aim_efie_setup(self._plan, C.byref(n), C.byref(nnz), C.byref(sec),
+                                        _stream_ptr(stream)))
+        return {"n_rwg": int(n.value), "nnz": int(nnz.value), "seconds": float(sec.value)}
+
+    def matvec_efie(self, x, freq_idx=None, out=None, stream=None):
+        """y = Z x, the RWG EFIE operator under AIMx (complex128, x of
+        [n_rwg] or [nrhs, n_rwg])."""
+        import torch
+        n = self.efie_setup(stream)["n_rwg"]
+        self._check_vec(x, "c128", n, "x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        self._check_vec(y, "c128", n, "out")
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_matvec_efie(self._plan, C.c_void_p(x.data_ptr()),
+                                         C.c_void_p(y.data_ptr()), nrhs, fp,
+                                         _stream_ptr(stream)))
+        return y
+
+    def efie_tables(self, stream=None) -> dict:
+        """The RWG numbering (tri_rwg [N, 3]), the RWG near list and C_A,
+        C_phi on it."""
+        info = self.efie_setup(stream)
+        n, nnz = info["n_rwg"], info["nnz"]
+        tri = np.empty((self.n, 3), dtype=np.int32)
+        rowptr = np.empty(n + 1, dtype=np.int32)
+        col = np.empty(max(nnz, 1), dtype=np.int32)
+        ca = np.empty(max(nnz, 1), dtype=np.float64)
+        cphi = np.empty(max(nnz, 1), dtype=np.float64)
+        I32, F64 = C.POINTER(C.c_int32), C.POINTER(C.c_double)
+        _check(self._lib.aim_efie_export(self._plan, tri.ctypes.data_as(I32),
+                                         rowptr.ctypes.data_as(I32), col.ctypes.data_as(I32),
+                                         ca.ctypes.data_as(F64), cphi.ctypes.data_as(F64),
+                                         _stream_ptr(stream)))
+        return {"tri_rwg": tri, "rowptr": rowptr, "col": col[:nnz], "ca": ca[:nnz],
+                "cphi": cphi[:nnz]}
 
     def profile_matvec(self, x, reps: int = 10, freq_idx=None, prec: str = "c128", out=None,
                        stream=None) -> dict:

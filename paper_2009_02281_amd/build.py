@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libaimx.so")
 
-SOURCES = ["kernels.hip", "unet.hip", "nearfield.hip", "setup_host.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "unet.hip", "nearfield.hip", "setup_host.cpp", "efie_host.cpp", "efie.hip", "abi.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -174,6 +174,27 @@ struct aim_plan_s {
   std::vector<int32_t> dlp_cur_freq;
   std::vector<double> dlp_near, dlp_corr;  // host copies (aim_dlp_export)
   double dlp_seconds = 0.0;
+  // RWG EFIE (aim_efie_setup, aim_matvec_efie), built on first use
+  int host_threads = 1;            // set-up threads of the descriptor
+  bool efie_ready = false;
+  aim::EfieTables efie;            // host tables (aim_efie_export)
+  double* d_efie_vals = nullptr;   // [N][3][3][4] channel values at the points
+  int32_t* d_efie_trirwg = nullptr;
+  int32_t* d_efie_te = nullptr;    // [n][4]
+  int32_t* d_efie_rowptr = nullptr;
+  int32_t* d_efie_col = nullptr;
+  double* d_efie_ca = nullptr;
+  double* d_efie_cphi = nullptr;
+  aim::CsrDevice efie_p{}, efie_pt{};  // point projection by node / by point
+  int32_t* d_efie_pblk = nullptr;
+  int efie_nblk = 0;
+  void* d_efie_src = nullptr;      // [4 max_rhs][3N] point sources, then potentials
+  void* d_efie_grid = nullptr;     // [4 max_rhs][Ng]
+  void* d_efie_work = nullptr;     // convolution workspace of 4 max_rhs grids
+  int32_t* d_efie_freq = nullptr;  // [4 max_rhs] spectrum index per grid
+  int32_t* h_efie_freq = nullptr;  // pinned staging
+  std::vector<int32_t> efie_cur_freq;
+  double efie_seconds = 0.0;
 
   // captured matvec graphs used by the solver, keyed by (prec, nrhs, in, out, freq)
   struct GraphKey {
@@ -247,6 +268,7 @@ struct aim_plan_s {
     for (hipStream_t w : workers) (void)hipStreamDestroy(w);
     if (h_rhs_freq) (void)hipHostFree(h_rhs_freq);
     if (h_dlp_freq) (void)hipHostFree(h_dlp_freq);
+    if (h_efie_freq) (void)hipHostFree(h_efie_freq);
     if (sv.nrm_host) (void)hipHostFree(sv.nrm_host);
     if (sv.H_host) (void)hipHostFree(sv.H_host);
     if (sv.g_host) (void)hipHostFree(sv.g_host);
@@ -673,6 +695,7 @@ aim_status aim_setup(const aim_setup_desc* desc, void* hip_stream, aim_plan* out
     // host work first: every validation happens before any device call
     aim::build_host_tables(d, p->t, false);
     p->nfreq = d.n_freq;
+    p->host_threads = aim::setup_threads(d);
     p->k.assign(d.k, d.k + d.n_freq);
     p->prec = d.precisions;
     p->max_rhs = d.max_rhs;
@@ -1048,6 +1071,145 @@ aim_status aim_dlp_export(aim_plan p, double* near_host, double* corr_host, void
     const size_t nnz = p->t.col.size();
     if (near_host && nnz) std::memcpy(near_host, p->dlp_near.data(), nnz * 8);
     if (corr_host && nnz) std::memcpy(corr_host, p->dlp_corr.data(), nnz * 8);
+  });
+}
+
+namespace {
+// The RWG EFIE's tables: functions, near list and point projection on the
+// host, the triangle pairs' inner integrals and point precorrections on the
+// device, C_A and C_phi assembled on the host, then the uploads and the
+// buffers of max_rhs products.
+void ensure_efie(aim_plan p, hipStream_t s) {
+  if (p->efie_ready) return;
+  const double t0 = now_s();
+  const auto& t = p->t;
+  aim::EfieTables& e = p->efie;
+  aim::build_efie_tables(t, e, p->host_threads);
+  {
+    std::vector<double> pv;
+    {
+      aim::NearDevice nd(t, nullptr, nullptr, p->alloc, p->free_fn, p->actx, s);
+      nd.fill_efie_pairs(e.pair_rowptr, e.pair_col, pv, s);
+    }
+    aim::assemble_efie_near(t, e, pv, p->host_threads);
+  }
+  // the pair list only feeds the assembly
+  std::vector<int64_t>().swap(e.pair_rowptr);
+  std::vector<int32_t>().swap(e.pair_col);
+  const auto& g = p->g;
+  const int R = p->max_rhs;
+  const int64_t P = 3 * t.N;
+  p->d_efie_vals = p->upload(e.vals, s);
+  p->d_efie_trirwg = p->upload(e.tri_rwg, s);
+  p->d_efie_te = p->upload(e.rwg_te.empty() ? std::vector<int32_t>(4, 0) : e.rwg_te, s);
+  p->d_efie_rowptr = p->upload(e.rowptr, s);
+  p->d_efie_col = p->upload(e.col.empty() ? std::vector<int32_t>(1, 0) : e.col, s);
+  p->d_efie_ca = p->upload(e.ca.empty() ? std::vector<double>(1, 0.0) : e.ca, s);
+  p->d_efie_cphi = p->upload(e.cphi.empty() ? std::vector<double>(1, 0.0) : e.cphi, s);
+  p->efie_p.rowptr = p->upload(e.p_rowptr, s);
+  p->efie_p.col = p->upload(e.p_col, s);
+  p->efie_p.val = p->upload(e.p_val, s);
+  p->efie_p.n = g.Ng;
+  p->d_efie_pblk = p->upload(e.p_blk, s);
+  p->efie_nblk = int(e.p_blk.size()) - 1;
+  p->efie_pt.rowptr = p->upload(e.pt_rowptr, s);
+  p->efie_pt.col = p->upload(e.pt_col, s);
+  p->efie_pt.val = p->upload(e.pt_val, s);
+  p->efie_pt.n = P;
+  p->d_efie_src = p->dalloc(size_t(4) * R * P * 16, s);
+  p->d_efie_grid = p->dalloc(size_t(4) * R * g.Ng * 16, s);
+  p->d_efie_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 4 * R, s);
+  p->d_efie_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 4 * R, s));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_efie_freq), sizeof(int32_t) * 4 * R, 0));
+  AIM_HIP(hipStreamSynchronize(s));  // the host vectors feed the uploads
+  // the device copies serve the products; the host keeps what the export returns
+  for (auto* v : {&e.vals, &e.p_val, &e.pt_val}) std::vector<double>().swap(*v);
+  for (auto* v : {&e.p_rowptr, &e.p_col, &e.p_blk, &e.pt_rowptr, &e.pt_col})
+    std::vector<int32_t>().swap(*v);
+  p->efie_cur_freq.clear();
+  p->efie_ready = true;
+  p->efie_seconds = now_s() - t0;
+}
+
+void efie_checks(aim_plan p) {
+  no_batch(p);
+  check_prec(p, AIM_C128);
+  AIM_REQUIRE(!p->host_only, AIM_ERR_STATE, "host-only plan");
+}
+}  // namespace
+
+aim_status aim_efie_setup(aim_plan p, int64_t* n_rwg, int64_t* nnz, double* seconds,
+                          void* hip_stream) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    efie_checks(p);
+    ensure_efie(p, static_cast<hipStream_t>(hip_stream));
+    if (n_rwg) *n_rwg = p->efie.n;
+    if (nnz) *nnz = int64_t(p->efie.col.size());
+    if (seconds) *seconds = p->efie_seconds;
+  });
+}
+
+aim_status aim_matvec_efie(aim_plan p, const void* x, void* y, int32_t nrhs,
+                           const int32_t* freq_idx_host, void* hip_stream) {
+  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    efie_checks(p);
+    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+    AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+                "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::vector<int32_t> fr(size_t(nrhs), 0);
+    for (int r = 0; r < nrhs; ++r) {
+      if (freq_idx_host) {
+        AIM_REQUIRE(freq_idx_host[r] >= 0 && freq_idx_host[r] < p->nfreq, AIM_ERR_INVALID_ARG,
+                    "frequency index out of range");
+        fr[r] = freq_idx_host[r];
+      }
+    }
+    ensure_efie(p, s);
+    // grid c nrhs + r (channel c of right-hand side r) takes r's wavenumber;
+    // the first nrhs entries double as the test kernel's per-vector index
+    std::vector<int32_t> f4(size_t(4) * nrhs);
+    for (int c = 0; c < 4; ++c)
+      for (int r = 0; r < nrhs; ++r) f4[size_t(c) * nrhs + r] = fr[r];
+    if (f4 != p->efie_cur_freq) {
+      AIM_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed a copy
+      std::memcpy(p->h_efie_freq, f4.data(), f4.size() * sizeof(int32_t));
+      AIM_HIP(hipMemcpyAsync(p->d_efie_freq, p->h_efie_freq, f4.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s));
+      p->efie_cur_freq = f4;
+    }
+    const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
+    aim::launch_efie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
+    aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
+                                p->d_efie_grid, 4 * nrhs, s);
+    aim::launch_convolve<double>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid,
+                                 p->d_spec64, p->d_efie_freq, 4 * nrhs, p->d_tw64, s, nullptr,
+                                 p->sched[0]);
+    aim::CsrDevice none{};
+    none.n = P;  // interpolation only: the near rows are the test kernel's
+    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_efie_grid, nullptr,
+                                    p->d_efie_src, 4 * nrhs, true, false, s);
+    aim::launch_efie_test(p->d_efie_src, p->d_efie_vals, p->d_efie_te, p->d_efie_rowptr,
+                          p->d_efie_col, p->d_efie_ca, p->d_efie_cphi, p->d_k, p->d_efie_freq, x,
+                          y, N, n, nrhs, s);
+  });
+}
+
+aim_status aim_efie_export(aim_plan p, int32_t* tri_rwg, int32_t* rowptr, int32_t* col,
+                           double* ca, double* cphi, void* hip_stream) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    efie_checks(p);
+    ensure_efie(p, static_cast<hipStream_t>(hip_stream));
+    const auto& e = p->efie;
+    const size_t nnz = e.col.size();
+    if (tri_rwg) std::memcpy(tri_rwg, e.tri_rwg.data(), e.tri_rwg.size() * 4);
+    if (rowptr) std::memcpy(rowptr, e.rowptr.data(), e.rowptr.size() * 4);
+    if (col && nnz) std::memcpy(col, e.col.data(), nnz * 4);
+    if (ca && nnz) std::memcpy(ca, e.ca.data(), nnz * 8);
+    if (cphi && nnz) std::memcpy(cphi, e.cphi.data(), nnz * 8);
   });
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -45,6 +46,7 @@ struct HostTables {
   double origin[3] = {0, 0, 0};
   std::vector<double> area;         // [N]
   std::vector<double> corners;      // [N][3][3] triangle corners (empty on loaded plans)
+  std::vector<int32_t> tri_idx;     // [N][3] vertex indices (empty on loaded plans)
   std::vector<double> qp_xyz;       // [3N][3] quadrature points
   std::vector<double> qp_w;         // [3N] weights area/3
   std::vector<int32_t> qp_start;    // [3N][3] stencil start per axis
@@ -88,6 +90,50 @@ void fill_near_host(HostTables& t, const double* V, const int32_t* T, int nthrea
 void build_cluster_inverses(HostTables& t, int nthreads);
 // host threads for set-up (the descriptor's n_threads, else all cores)
 int setup_threads(const aim_setup_desc& d);
+// fn(begin, end) over chunks of [0, n) on nthreads host threads
+void parallel_ranges(int64_t n, int nthreads, const std::function<void(int64_t, int64_t)>& fn);
+// Lagrange weights of the points 0..order at the local coordinate u
+void lagrange_host(double u, int order, double* out);
+// Row blocks of a CSR matrix for launch_project (see kProjNnz)
+std::vector<int32_t> row_blocks(const std::vector<int32_t>& rowptr);
+
+// ---------------------------------------------------------------------------
+// RWG EFIE (Sec. II-A, eq. EFIEdis; Sec. II-B, eq. LAIMx): the operator
+// L^A - k^-2 L^phi on RWG functions, with three Cartesian current channels
+// and one charge channel projected from the quadrature points and convolved
+// with the same spectrum H(k); C_A and C_phi are the static near corrections
+// of the two parts (real, frequency independent)
+// ---------------------------------------------------------------------------
+// doubles per triangle pair (i, j) from the device fill: the integrals over
+// T_j of 1/R [3] and r'/R [3][3] at the three points of T_i, then the
+// point-pair precorrections sum_{u,v} L_u(r_iq) H_s(u - v) L_v(r_jq') [3][3]
+constexpr int kEfiePairVals = 21;
+struct EfieTables {
+  int64_t n = 0;                      // RWG functions (interior edges)
+  std::vector<int32_t> tri_rwg;       // [N][3] function on the edge opposite vertex e, or -1
+  std::vector<double> sgn_len;        // [N][3] +-length (+ on the function's T+), 0 if none
+  std::vector<int32_t> rwg_te;        // [n][4] (T+, its edge, T-, its edge)
+  std::vector<double> vals;           // [N][3 points][3 edges][4]: w_q f(r_q), w_q div f
+  std::vector<int64_t> pair_rowptr;   // [N+1] triangle pairs needed by the near corrections
+  std::vector<int32_t> pair_col;
+  std::vector<int32_t> rowptr;        // [n+1] RWG near list, columns ascending
+  std::vector<int32_t> col;
+  std::vector<double> ca, cphi;       // C_A, C_phi on the RWG near list
+  // point projection Lambda_u(r_p) (no weights), p = 3t + q: by grid node
+  // (columns = points) and by point (columns = nodes)
+  std::vector<int32_t> p_rowptr, p_col, p_blk;
+  std::vector<double> p_val;
+  std::vector<int32_t> pt_rowptr, pt_col;
+  std::vector<double> pt_val;
+};
+// RWG functions (numbered by their edges' sorted vertex pairs, T+ the
+// triangle of lower index), the RWG near list (some triangle of one near
+// some triangle of the other), the triangle pairs it needs and the point
+// projection; throws AIM_ERR_GEOMETRY for an edge of more than two triangles
+void build_efie_tables(const HostTables& t, EfieTables& e, int nthreads);
+// C_A and C_phi from the pair values (kEfiePairVals per entry of the pair list)
+void assemble_efie_near(const HostTables& t, EfieTables& e, const std::vector<double>& pv,
+                        int nthreads);
 
 // Closed-form integral of 1/|r - r'| over the triangle (a, b, c).
 double triangle_inv_r(const double r[3], const double a[3], const double b[3],
@@ -190,6 +236,19 @@ void launch_dlp_sources(const void* x, const double* nrm, void* xs, int64_t n, i
 void launch_dlp_moments(const GridShape& g, void* grids, int nrhs, hipStream_t s);
 void launch_dlp_combine(const GridShape& g, const void* grids, void* phi, int nrhs,
                         hipStream_t s);
+
+// RWG EFIE, complex128: src[c][r][3t + q] = sum_e vals[t][q][e][c] x[r][tri_rwg[t][e]]
+// (c = x, y, z, charge; x is [nrhs][nrwg]); then, from the interpolated
+// channel potentials psi (same layout), y[r][n] = sum over the function's
+// two triangles and their points of the current channels' dot product minus
+// k_r^-2 times the charge channel, plus (C_A - k_r^-2 C_phi) x[r], with
+// k_r = kv[rhs_freq[r]]
+void launch_efie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
+                         int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
+void launch_efie_test(const void* psi, const double* vals, const int32_t* rwg_te,
+                      const int32_t* rowptr, const int32_t* col, const double* ca,
+                      const double* cphi, const double* kv, const int32_t* rhs_freq,
+                      const void* x, void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
 
 void launch_excitation(int kind, const double* qp_xyz, const double* qp_w, int64_t n,
                        const double* params, int n_params, const double* kvals,
@@ -333,6 +392,10 @@ class NearDevice {
   // the near list, for the unit normals nrm [N][3]
   void fill_dlp(const std::vector<double>& nrm, std::vector<double>& near_out,
                 std::vector<double>& corr_out, hipStream_t s);
+  // RWG EFIE: kEfiePairVals values per triangle pair of the CSR list
+  // (rowptr [N+1], col), see EfieTables
+  void fill_efie_pairs(const std::vector<int64_t>& rowptr, const std::vector<int32_t>& col,
+                       std::vector<double>& out, hipStream_t s);
   // inverses of the clusters' blocks of the full-kernel Galerkin matrix at
   // wavenumber k (complex128, row-major, at cl_blk offsets; device arrays);
   // throws AIM_ERR_GEOMETRY for a singular block

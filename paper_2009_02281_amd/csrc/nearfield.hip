@@ -122,6 +122,35 @@ __device__ double r_integral(P3 r, const P3* v) {
   return acc / 3.0;
 }
 
+// integral over triangle v[0..2] of r' / |r - r'| dS' (a vector), given
+// s1 = the integral of 1/|r - r'|: with rho the foot of r in the plane,
+// grad_s' R = (rho' - rho)/R, so the gradient theorem over T gives
+// rho s1 + sum_i m_i int_{edge i} R dl (m_i the outward in-plane edge normal)
+__device__ P3 rvec_r_integral(P3 r, const P3* v, double s1) {
+  const P3 nn = cross(sub(v[1], v[0]), sub(v[2], v[0]));
+  const P3 n = scale(nn, 1.0 / len(nn));
+  const double h = dot(sub(r, v[0]), n);
+  const P3 rho = sub(r, scale(n, h));
+  P3 acc = scale(rho, s1);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const P3 p = v[e], q = v[(e + 1) % 3];
+    const P3 d = sub(q, p);
+    const double L = len(d);
+    const P3 u = scale(d, 1.0 / L);
+    const P3 m = cross(u, n);
+    const P3 pr = sub(p, r), qr = sub(q, r);
+    const double P0 = dot(pr, m);
+    const double lm = dot(pr, u), lp = dot(qr, u), Rm = len(pr), Rp = len(qr);
+    const double R0sq = P0 * P0 + h * h;
+    // on the edge's line R0^2 ln(...) vanishes
+    const double lg = R0sq <= (1e-14 * L) * (1e-14 * L) ? 0.0 : edge_integral(lm, lp, Rm, Rp, R0sq);
+    const double t = 0.5 * (lp * Rp - lm * Rm + R0sq * lg);
+    acc = {acc.x + t * m.x, acc.y + t * m.y, acc.z + t * m.z};
+  }
+  return acc;
+}
+
 struct NearArgs {
   const double* tri;       // [N][3][3] corners
   const double* qp;        // [3N][3] quadrature points
@@ -234,47 +263,52 @@ struct GridKernel<3> {
   }
 };
 
+// sum_{u, v} L_u(r_qa) H(u - v) L_v(r_qb) for the quadrature points qa, qb
+template <int KIND, int ORDER>
+__device__ typename GridKernel<KIND>::V point_pair(const NearArgs& a, int64_t qa, int64_t qb) {
+  using GK = GridKernel<KIND>;
+  constexpr int n = ORDER, S = n + 1, W = 2 * n + 1;
+  // per axis: offset of the stencil starts and the correlation of the two
+  // weight vectors, K[d + n] = sum_{alpha - beta = d} l_a l_b
+  int d0[3];
+  double K[3][W];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    double li[S], lj[S];
+    lagrange<ORDER>(a.qlocal[3 * qa + ax], li);
+    lagrange<ORDER>(a.qlocal[3 * qb + ax], lj);
+    d0[ax] = a.qstart[3 * qa + ax] - a.qstart[3 * qb + ax];
+#pragma unroll
+    for (int d = 0; d < W; ++d) K[ax][d] = 0.0;
+#pragma unroll
+    for (int al = 0; al < S; ++al)
+#pragma unroll
+      for (int be = 0; be < S; ++be) K[ax][al - be + n] += li[al] * lj[be];
+  }
+  typename GK::V acc = GK::zero();
+  for (int dz = 0; dz < W; ++dz)
+    for (int dy = 0; dy < W; ++dy) {
+      const double kyz = K[2][dz] * K[1][dy];
+      typename GK::V row = GK::zero();
+#pragma unroll
+      for (int dx = 0; dx < W; ++dx)
+        row = GK::fma(K[0][dx],
+                      GK::at(d0[0] + dx - n, d0[1] + dy - n, d0[2] + dz - n, a.h, a.k), row);
+      acc = GK::fma(kyz, row, acc);
+    }
+  return acc;
+}
+
 // sum over quadrature-point pairs of w_a w_b sum_{u, v} L_u(r_a) H(u - v) L_v(r_b)
 template <int KIND, int ORDER>
 __device__ typename GridKernel<KIND>::V precorrection(const NearArgs& a, int64_t i, int64_t j) {
   using GK = GridKernel<KIND>;
-  constexpr int n = ORDER, S = n + 1, W = 2 * n + 1;
   typename GK::V pc = GK::zero();
   for (int p = 0; p < 3; ++p) {
     const int64_t qa = 3 * i + p;
-    double li[3][S];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) lagrange<ORDER>(a.qlocal[3 * qa + ax], li[ax]);
     for (int q = 0; q < 3; ++q) {
       const int64_t qb = 3 * j + q;
-      // per axis: offset of the stencil starts and the correlation of the
-      // two weight vectors, K[d + n] = sum_{alpha - beta = d} l_a l_b
-      int d0[3];
-      double K[3][W];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        double lj[S];
-        lagrange<ORDER>(a.qlocal[3 * qb + ax], lj);
-        d0[ax] = a.qstart[3 * qa + ax] - a.qstart[3 * qb + ax];
-#pragma unroll
-        for (int d = 0; d < W; ++d) K[ax][d] = 0.0;
-#pragma unroll
-        for (int al = 0; al < S; ++al)
-#pragma unroll
-          for (int be = 0; be < S; ++be) K[ax][al - be + n] += li[ax][al] * lj[be];
-      }
-      typename GK::V acc = GK::zero();
-      for (int dz = 0; dz < W; ++dz)
-        for (int dy = 0; dy < W; ++dy) {
-          const double kyz = K[2][dz] * K[1][dy];
-          typename GK::V row = GK::zero();
-#pragma unroll
-          for (int dx = 0; dx < W; ++dx)
-            row = GK::fma(K[0][dx],
-                          GK::at(d0[0] + dx - n, d0[1] + dy - n, d0[2] + dz - n, a.h, a.k), row);
-          acc = GK::fma(kyz, row, acc);
-        }
-      pc = GK::fma(a.qw[qa] * a.qw[qb], acc, pc);
+      pc = GK::fma(a.qw[qa] * a.qw[qb], point_pair<KIND, ORDER>(a, qa, qb), pc);
     }
   }
   return pc;
@@ -346,6 +380,35 @@ __global__ __launch_bounds__(128) void dlp_near_kernel(NearArgs a, const double*
   near_out[p] = s;
   const Vec3d pc = precorrection<3, ORDER>(a, i, j);
   corr[p] = s - (pc.x * n.x + pc.y * n.y + pc.z * n.z);
+}
+
+// RWG EFIE (Sec. II-A, II-B): for the pair (i, j) of the triangle pair
+// list, the static inner integrals over T_j at the three points r_iq of
+// T_i, int 1/R and int r'/R, and the nine point-pair precorrections
+// sum_{u, v} L_u(r_iq) H_s(u - v) L_v(r_jq') (no quadrature weights); the
+// host combines them into the functions' C_A and C_phi
+template <int ORDER>
+__global__ __launch_bounds__(128) void efie_pair_kernel(NearArgs a, double* out) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.nnz) return;
+  const int64_t i = row_of(a.rowptr, a.N, p), j = a.col[p];
+  P3 v[3];
+  for (int c = 0; c < 3; ++c)
+    v[c] = {a.tri[9 * j + 3 * c], a.tri[9 * j + 3 * c + 1], a.tri[9 * j + 3 * c + 2]};
+  double* o = out + int64_t(kEfiePairVals) * p;
+  for (int q = 0; q < 3; ++q) {
+    const int64_t qi = 3 * i + q;
+    const P3 r = {a.qp[3 * qi], a.qp[3 * qi + 1], a.qp[3 * qi + 2]};
+    const double s1 = inv_r_integral(r, v);
+    const P3 sv = rvec_r_integral(r, v, s1);
+    o[q] = s1;
+    o[3 + 3 * q] = sv.x;
+    o[4 + 3 * q] = sv.y;
+    o[5 + 3 * q] = sv.z;
+  }
+  for (int q = 0; q < 3; ++q)
+    for (int q2 = 0; q2 < 3; ++q2)
+      o[12 + 3 * q + q2] = point_pair<0, ORDER>(a, 3 * i + q, 3 * j + q2);
 }
 
 // conventional AIM: A_NR(k) - A_P(k) from the static entries
@@ -617,6 +680,28 @@ void NearDevice::fill_dlp(const std::vector<double>& nrm, std::vector<double>& n
   AIM_HIP(hipGetLastError());
   AIM_HIP(hipMemcpyAsync(near_out.data(), nd, size_t(nnz_) * 8, hipMemcpyDeviceToHost, s));
   AIM_HIP(hipMemcpyAsync(corr_out.data(), cd, size_t(nnz_) * 8, hipMemcpyDeviceToHost, s));
+  AIM_HIP(hipStreamSynchronize(s));
+}
+
+void NearDevice::fill_efie_pairs(const std::vector<int64_t>& rowptr,
+                                 const std::vector<int32_t>& col, std::vector<double>& out,
+                                 hipStream_t s) {
+  AIM_REQUIRE(tri_ != nullptr, AIM_ERR_STATE, "near-field tables built without the mesh");
+  AIM_REQUIRE(rowptr.size() == size_t(N_) + 1 && int64_t(col.size()) == rowptr[N_],
+              AIM_ERR_INVALID_ARG, "pair list does not match the mesh");
+  const int64_t np = int64_t(col.size());
+  out.assign(size_t(kEfiePairVals) * np, 0.0);
+  if (np == 0) return;
+  void* rp = put(get(rowptr.size() * 8), rowptr, s);
+  void* cp = put(get(col.size() * 4), col, s);
+  double* od = static_cast<double*>(get(out.size() * 8));
+  const NearArgs a = make_args(tri_, qp_, qw_, qstart_, qlocal_, rp, cp, N_, np, h_, 0.0);
+  if (order_ == 2)
+    hipLaunchKernelGGL(efie_pair_kernel<2>, dim3(blocks_for(np)), dim3(128), 0, s, a, od);
+  else
+    hipLaunchKernelGGL(efie_pair_kernel<3>, dim3(blocks_for(np)), dim3(128), 0, s, a, od);
+  AIM_HIP(hipGetLastError());
+  AIM_HIP(hipMemcpyAsync(out.data(), od, out.size() * 8, hipMemcpyDeviceToHost, s));
   AIM_HIP(hipStreamSynchronize(s));
 }
 

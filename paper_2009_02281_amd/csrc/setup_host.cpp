@@ -88,6 +88,12 @@ inline void lagrange(double u, int order, double* out) {
 
 }  // namespace
 
+void parallel_ranges(int64_t n, int nthreads, const std::function<void(int64_t, int64_t)>& fn) {
+  parallel_for(n, nthreads, fn);
+}
+
+void lagrange_host(double u, int order, double* out) { lagrange(u, order, out); }
+
 // Integral over the triangle (a, b, c) of 1/|r - r'| dS': the in-plane
 // divergence identity div_s[(rho' - rho)/R] = 1/R + h^2/R^3 turns it into
 // edge integrals, sum_i P0_i int_{edge i} dl/R, minus |h| times the solid
@@ -141,6 +147,36 @@ double triangle_inv_r(const double r[3], const double a[3], const double b[3], c
   const double den = la * lb * lc + dot3(A, B) * lc + dot3(A, Cv) * lb + dot3(B, Cv) * la;
   acc -= std::fabs(h) * 2.0 * std::atan2(num, den);
   return acc;
+}
+
+// Row blocks of a CSR matrix for the projection kernel: consecutive rows
+// with at most kProjNnz non-zeros and kProjRows rows; a longer row forms a
+// block of its own, and a run of at least kProjRows empty rows (nodes no
+// stencil reaches) forms a zero block of up to kProjZeroRows rows.
+std::vector<int32_t> row_blocks(const std::vector<int32_t>& rowptr) {
+  const int64_t Ng = int64_t(rowptr.size()) - 1;
+  std::vector<int32_t> blk(1, 0);
+  int64_t r = 0;
+  while (r < Ng) {
+    int64_t e = r, nz = 0;
+    while (e < Ng && e - r < kProjZeroRows && rowptr[e + 1] == rowptr[e]) ++e;
+    if (e - r >= kProjRows || e == Ng) {
+      blk.push_back(int32_t(e));
+      r = e;
+      continue;
+    }
+    e = r;
+    while (e < Ng && e - r < kProjRows) {
+      const int64_t len = rowptr[e + 1] - rowptr[e];
+      if (e > r && nz + len > kProjNnz) break;
+      nz += len;
+      ++e;
+      if (nz > kProjNnz) break;  // a single long row
+    }
+    blk.push_back(int32_t(e));
+    r = e;
+  }
+  return blk;
 }
 
 // A_s,NR and C = A_s,NR - A_s,P on the near list (host).
@@ -342,6 +378,7 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t, bool near_on_host
                                     {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0}};
   t.area.resize(N);
   t.corners.resize(9 * N);
+  t.tri_idx.assign(T, T + 3 * N);
   t.qp_xyz.resize(9 * N);
   t.qp_w.resize(3 * N);
   t.qp_start.resize(9 * N);
@@ -508,31 +545,7 @@ void build_host_tables(const aim_setup_desc& d, HostTables& t, bool near_on_host
         t.p_col[fill[u]] = int32_t(j);
         t.p_val[fill[u]++] = t.pt_val[k];
       }
-    // row blocks: consecutive rows with at most kProjNnz non-zeros and
-    // kProjRows rows; a longer row forms a block of its own, and a run of at
-    // least kProjRows empty rows (nodes no stencil reaches) forms a zero
-    // block of up to kProjZeroRows rows
-    t.p_blk.assign(1, 0);
-    int64_t r = 0;
-    while (r < Ng) {
-      int64_t e = r, nz = 0;
-      while (e < Ng && e - r < kProjZeroRows && t.p_rowptr[e + 1] == t.p_rowptr[e]) ++e;
-      if (e - r >= kProjRows || e == Ng) {
-        t.p_blk.push_back(int32_t(e));
-        r = e;
-        continue;
-      }
-      e = r;
-      while (e < Ng && e - r < kProjRows) {
-        const int64_t len = t.p_rowptr[e + 1] - t.p_rowptr[e];
-        if (e > r && nz + len > kProjNnz) break;
-        nz += len;
-        ++e;
-        if (nz > kProjNnz) break;  // a single long row
-      }
-      t.p_blk.push_back(int32_t(e));
-      r = e;
-    }
+    t.p_blk = row_blocks(t.p_rowptr);
   }
 
   // -- near-block preconditioner clusters (recursive coordinate bisection) ----

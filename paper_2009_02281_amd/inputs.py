@@ -253,6 +253,17 @@ def sphere_large(level: int = 7) -> Workload:
                     np.array([2 * math.pi]), 4000)
 
 
+def efie_sphere(level: int = 6) -> Workload:
+    """Radius-6 icosphere (81,920 triangles, 122,880 RWG functions at level
+    6), 128^3 grid (h about lambda/10), 2nd-order stencil, near threshold 2h,
+    k = 2*pi: the RWG EFIE's measured size."""
+    V, T = icosphere(level, 6.0)
+    dims = (128, 128, 128)
+    h = derived_spacing(V, dims)
+    return Workload(f"sphere-{T.shape[0]}-rwg", V, T, 2, dims, h, 2.0,
+                    np.array([2 * math.pi]), 4100)
+
+
 def sphere_tiny(level: int = 1, radius: float = 0.5, dims=(8, 8, 8), h: float = 0.2,
                 k: float = 2 * math.pi) -> Workload:
     """Very small sphere for brute-force checks (80 triangles at level 1)."""
