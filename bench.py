@@ -621,6 +621,54 @@ def dlp_leg(plan, w, reps: int = 20) -> dict:
     return res
 
 
+def efie_leg(reps: int = 20) -> dict:
+    """The RWG EFIE under AIMx (Sec. II-A, II-B) on the 81,920-triangle
+    sphere (122,880 functions, 128^3 grid): the tables' build time and the
+    per-call time of Z x (four channel grids through one spectrum, complex128)
+    for one and four vectors, beside the scalar single-layer product A x on the
+    same plan (one grid)."""
+    import torch
+    from paper_2009_02281_amd import binding
+    from paper_2009_02281_amd import inputs as I
+    w = I.efie_sphere()
+    t0 = time.perf_counter()
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     precisions=("c128",), max_rhs=4)
+    plan_s = time.perf_counter() - t0
+    info = p.efie_setup()
+
+    def timed(fn, x, y):
+        for _ in range(2):
+            fn(x, out=y)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn(x, out=y)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {"workload": w.name, "triangles": int(w.triangles.shape[0]), "n_rwg": info["n_rwg"],
+           "rwg_near_nnz": info["nnz"], "plan_seconds": plan_s,
+           "efie_tables_seconds": info["seconds"]}
+    for nrhs in (1, 4):
+        x = torch.from_numpy(I.complex_gaussian(info["n_rwg"], w.seed_base + nrhs,
+                                                nrhs=nrhs)).cuda()
+        ms = timed(p.matvec_efie, x, torch.empty_like(x))
+        res[f"nrhs{nrhs}"] = {"ms_per_call": ms, "ms_per_vector": ms / nrhs,
+                              "unknowns_matvecs_per_s": info["n_rwg"] * nrhs / (ms * 1e-3)}
+        print(f"[bench] EFIE on {w.name}: {nrhs} vector(s) {ms:.3f} ms per call",
+              file=sys.stderr, flush=True)
+    xs = torch.from_numpy(I.complex_gaussian(p.n, w.seed_base)).cuda()
+    res["scalar_ms_per_matvec"] = timed(p.matvec, xs, torch.empty_like(xs))
+    res["note"] = ("complex128; three current channels and one charge channel projected from "
+                   "the quadrature points and convolved with the plan's spectrum; the scalar "
+                   "product on the same plan convolves one grid")
+    p.close()
+    return res
+
+
 def conventional_leg(plan, w, nrhs: int = 8, reps: int = 10) -> dict:
     """Conventional AIM against AIMx on one plan (Sec. II-B against Sec. III;
     the per-wavenumber cost of the sweep comparison of Sec. VI): the
@@ -701,6 +749,10 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner time-to-tolerance leg")
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net throughput leg")
+    ap.add_argument("--no-efie", action="store_true",
+                    help="skip the RWG EFIE leg (81,920-triangle sphere)")
+    ap.add_argument("--efie-only", action="store_true",
+                    help="only run the RWG EFIE leg (--steps products per timing)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other precision and the extra workloads (sweep, box array)")
     ap.add_argument("--solve-rtol", type=float, default=1e-6)
@@ -735,6 +787,9 @@ def main() -> int:
         return 1
     if args.copy_calibration:
         print(json.dumps(copy_bandwidth()), flush=True)
+        return 0
+    if args.efie_only:
+        print(json.dumps({"efie": efie_leg(reps=args.steps)}), flush=True)
         return 0
     w = make_workload(args.workload)
     freq = None
@@ -891,6 +946,9 @@ def main() -> int:
         sp.close()
         if args.workload != "boxarray":
             out["extra"]["boxarray"] = extra_workload("boxarray", ("c128", "c64"), 50, 5)
+        if not args.no_efie:
+            out["efie"] = efie_leg()
+            torch.cuda.empty_cache()
     if not args.no_learned and args.workload != "sweep":
         out["learned_pc"] = learned_pc_leg(args.solve_rtol)
     if not args.no_unet and args.workload != "sweep":

@@ -183,8 +183,7 @@ struct aim_plan_s {
   int32_t* d_efie_te = nullptr;    // [n][4]
   int32_t* d_efie_rowptr = nullptr;
   int32_t* d_efie_col = nullptr;
-  double* d_efie_ca = nullptr;
-  double* d_efie_cphi = nullptr;
+  double* d_efie_cc = nullptr;     // [nnz][2] (C_A, C_phi)
   aim::CsrDevice efie_p{}, efie_pt{};  // point projection by node / by point
   int32_t* d_efie_pblk = nullptr;
   int efie_nblk = 0;
@@ -1104,8 +1103,15 @@ void ensure_efie(aim_plan p, hipStream_t s) {
   p->d_efie_te = p->upload(e.rwg_te.empty() ? std::vector<int32_t>(4, 0) : e.rwg_te, s);
   p->d_efie_rowptr = p->upload(e.rowptr, s);
   p->d_efie_col = p->upload(e.col.empty() ? std::vector<int32_t>(1, 0) : e.col, s);
-  p->d_efie_ca = p->upload(e.ca.empty() ? std::vector<double>(1, 0.0) : e.ca, s);
-  p->d_efie_cphi = p->upload(e.cphi.empty() ? std::vector<double>(1, 0.0) : e.cphi, s);
+  {
+    std::vector<double> cc(2 * std::max<size_t>(e.ca.size(), 1), 0.0);
+    for (size_t j = 0; j < e.ca.size(); ++j) {
+      cc[2 * j] = e.ca[j];
+      cc[2 * j + 1] = e.cphi[j];
+    }
+    p->d_efie_cc = p->upload(cc, s);
+    AIM_HIP(hipStreamSynchronize(s));  // cc is a temporary
+  }
   p->efie_p.rowptr = p->upload(e.p_rowptr, s);
   p->efie_p.col = p->upload(e.p_col, s);
   p->efie_p.val = p->upload(e.p_val, s);
@@ -1192,8 +1198,8 @@ aim_status aim_matvec_efie(aim_plan p, const void* x, void* y, int32_t nrhs,
     aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_efie_grid, nullptr,
                                     p->d_efie_src, 4 * nrhs, true, false, s);
     aim::launch_efie_test(p->d_efie_src, p->d_efie_vals, p->d_efie_te, p->d_efie_rowptr,
-                          p->d_efie_col, p->d_efie_ca, p->d_efie_cphi, p->d_k, p->d_efie_freq, x,
-                          y, N, n, nrhs, s);
+                          p->d_efie_col, p->d_efie_cc, p->d_k, p->d_efie_freq, x, y, N, n, nrhs,
+                          s);
   });
 }
 

@@ -242,13 +242,13 @@ void launch_dlp_combine(const GridShape& g, const void* grids, void* phi, int nr
 // channel potentials psi (same layout), y[r][n] = sum over the function's
 // two triangles and their points of the current channels' dot product minus
 // k_r^-2 times the charge channel, plus (C_A - k_r^-2 C_phi) x[r], with
-// k_r = kv[rhs_freq[r]]
+// k_r = kv[rhs_freq[r]] and cc [nnz][2] = (C_A, C_phi) interleaved
 void launch_efie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
 void launch_efie_test(const void* psi, const double* vals, const int32_t* rwg_te,
-                      const int32_t* rowptr, const int32_t* col, const double* ca,
-                      const double* cphi, const double* kv, const int32_t* rhs_freq,
-                      const void* x, void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
+                      const int32_t* rowptr, const int32_t* col, const double* cc,
+                      const double* kv, const int32_t* rhs_freq, const void* x, void* y,
+                      int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
 
 void launch_excitation(int kind, const double* qp_xyz, const double* qp_w, int64_t n,
                        const double* params, int n_params, const double* kvals,

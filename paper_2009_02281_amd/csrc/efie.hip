@@ -10,8 +10,8 @@
 // operator (the point stencils in place of the merged triangle stencils).
 // Both kernels here are gathers over small fixed fan-ins: a point reads the
 // three functions of its triangle, a function the six points of its two
-// triangles and its near-list row; every output is written once, so the
-// result does not depend on the launch shape.
+// triangles and its near-list row; every output is written once, with a
+// fixed summation order.
 #include <hip/hip_runtime.h>
 
 #include "aim_internal.h"
@@ -60,51 +60,78 @@ __global__ __launch_bounds__(256) void efie_sources_kernel(
 
 // y[r][n]: the function's channel values at the six points of its triangles
 // against the interpolated potentials (current channels minus k^-2 times the
-// charge channel), plus its near-list row of C_A - k^-2 C_phi
+// charge channel), plus its near-list row of C_A - k^-2 C_phi.  LPR lanes
+// per function: lanes 0..5 take one point each (T+ then T-, three points
+// each), every lane strides over the near row; a fixed butterfly across the
+// LPR lanes sums them.  RB right-hand sides per workgroup, so each near entry
+// and channel value is loaded once for all of them.
+template <int LPR, int RB>
 __global__ __launch_bounds__(256) void efie_test_kernel(
     const double2* __restrict__ psi, const double* __restrict__ vals,
     const int32_t* __restrict__ rwg_te, const int32_t* __restrict__ rowptr,
-    const int32_t* __restrict__ col, const double* __restrict__ ca,
-    const double* __restrict__ cphi, const double* __restrict__ kv,
-    const int32_t* __restrict__ rhs_freq, const double2* __restrict__ x, double2* __restrict__ y,
-    int64_t N, int64_t nrwg, int nrhs) {
-  const int r = blockIdx.y;
+    const int32_t* __restrict__ col, const double2* __restrict__ cc,
+    const double* __restrict__ kv, const int32_t* __restrict__ rhs_freq,
+    const double2* __restrict__ x, double2* __restrict__ y, int64_t N, int64_t nrwg, int nrhs) {
+  const int sub = threadIdx.x % LPR;
+  const int64_t n = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
+  const int r0 = int(blockIdx.y) * RB;
+  const int nr = min(RB, nrhs - r0);
   const int64_t P = 3 * N;
-  const double k = kv[rhs_freq[r]];
-  const double ik2 = 1.0 / (k * k);
-  const double2* pa = psi + int64_t(r) * P;  // channel c at pa + c nrhs P
-  const int64_t cs = int64_t(nrhs) * P;
-  const double2* xr = x + int64_t(r) * nrwg;
-  for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < nrwg;
-       n += int64_t(gridDim.x) * blockDim.x) {
-    double ar = 0.0, ai = 0.0, qr = 0.0, qi = 0.0;
+  const int64_t cs = int64_t(nrhs) * P;  // channel stride of psi
+  double ar[RB], ai[RB], qr[RB], qi[RB];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
+  for (int j = 0; j < RB; ++j) ar[j] = ai[j] = qr[j] = qi[j] = 0.0;
+  if (n < nrwg) {
+    if (sub < 6) {
+      const int side = sub >= 3 ? 1 : 0, q = sub - 3 * side;
       const int64_t t = rwg_te[4 * n + 2 * side];
       const int e = rwg_te[4 * n + 2 * side + 1];
+      const double* v = vals + 36 * t + 12 * q + 4 * e;
+      const double v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+      const double2* base = psi + int64_t(r0) * P + 3 * t + q;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const double* v = vals + 36 * t + 12 * q + 4 * e;
-        const int64_t p = 3 * t + q;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double2 ph = pa[c * cs + p];
-          ar += v[c] * ph.x;
-          ai += v[c] * ph.y;
+      for (int j = 0; j < RB; ++j)
+        if (j < nr) {
+          const double2* b = base + int64_t(j) * P;
+          const double2 p0 = b[0], p1 = b[cs], p2 = b[2 * cs], p3 = b[3 * cs];
+          ar[j] = v0 * p0.x + v1 * p1.x + v2 * p2.x;
+          ai[j] = v0 * p0.y + v1 * p1.y + v2 * p2.y;
+          qr[j] = v3 * p3.x;
+          qi[j] = v3 * p3.y;
         }
-        const double2 ph = pa[3 * cs + p];
-        qr += v[3] * ph.x;
-        qi += v[3] * ph.y;
+    }
+    const double2* xr = x + int64_t(r0) * nrwg;
+    for (int32_t k = rowptr[n] + sub; k < rowptr[n + 1]; k += LPR) {
+      const double2 c = cc[k];
+      const int64_t m = col[k];
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+        if (j < nr) {
+          const double2 xv = xr[int64_t(j) * nrwg + m];
+          ar[j] += c.x * xv.x;
+          ai[j] += c.x * xv.y;
+          qr[j] += c.y * xv.x;
+          qi[j] += c.y * xv.y;
+        }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RB; ++j)
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+      ar[j] += __shfl_xor(ar[j], o, LPR);
+      ai[j] += __shfl_xor(ai[j], o, LPR);
+      qr[j] += __shfl_xor(qr[j], o, LPR);
+      qi[j] += __shfl_xor(qi[j], o, LPR);
+    }
+  if (sub == 0 && n < nrwg) {
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < nr) {
+        const double k = kv[rhs_freq[r0 + j]];
+        const double ik2 = 1.0 / (k * k);
+        y[int64_t(r0 + j) * nrwg + n] = make_double2(ar[j] - ik2 * qr[j], ai[j] - ik2 * qi[j]);
       }
-    }
-    for (int32_t j = rowptr[n]; j < rowptr[n + 1]; ++j) {
-      const double2 xv = xr[col[j]];
-      ar += ca[j] * xv.x;
-      ai += ca[j] * xv.y;
-      qr += cphi[j] * xv.x;
-      qi += cphi[j] * xv.y;
-    }
-    y[int64_t(r) * nrwg + n] = make_double2(ar - ik2 * qr, ai - ik2 * qi);
   }
 }
 
@@ -119,14 +146,30 @@ void launch_efie_sources(const void* x, const double* vals, const int32_t* tri_r
 }
 
 void launch_efie_test(const void* psi, const double* vals, const int32_t* rwg_te,
-                      const int32_t* rowptr, const int32_t* col, const double* ca,
-                      const double* cphi, const double* kv, const int32_t* rhs_freq,
-                      const void* x, void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
+                      const int32_t* rowptr, const int32_t* col, const double* cc,
+                      const double* kv, const int32_t* rhs_freq, const void* x, void* y,
+                      int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
   if (nrwg == 0) return;
-  hipLaunchKernelGGL(efie_test_kernel, dim3(blocks(nrwg), nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(psi), vals, rwg_te, rowptr, col, ca, cphi, kv,
-                     rhs_freq, static_cast<const double2*>(x), static_cast<double2*>(y), N, nrwg,
-                     nrhs);
+  constexpr int LPR = 16;
+  const int64_t gx = (nrwg * LPR + 255) / 256;
+  // several right-hand sides per workgroup while 1024 workgroups remain
+  int rb = 1;
+  while (rb < 8 && 2 * rb <= nrhs && gx * ((nrhs + 2 * rb - 1) / (2 * rb)) >= 1024) rb *= 2;
+  const dim3 grid(unsigned(gx), unsigned((nrhs + rb - 1) / rb));
+  const double2* ps = static_cast<const double2*>(psi);
+  const double2* c2 = reinterpret_cast<const double2*>(cc);
+  const double2* xi = static_cast<const double2*>(x);
+  double2* yo = static_cast<double2*>(y);
+#define AIM_EFIE_TEST(R)                                                                       \
+  hipLaunchKernelGGL((efie_test_kernel<LPR, R>), grid, dim3(256), 0, s, ps, vals, rwg_te,     \
+                     rowptr, col, c2, kv, rhs_freq, xi, yo, N, nrwg, nrhs)
+  switch (rb) {
+    case 1: AIM_EFIE_TEST(1); break;
+    case 2: AIM_EFIE_TEST(2); break;
+    case 4: AIM_EFIE_TEST(4); break;
+    default: AIM_EFIE_TEST(8); break;
+  }
+#undef AIM_EFIE_TEST
   AIM_HIP(hipGetLastError());
 }
 
