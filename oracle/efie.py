@@ -255,18 +255,20 @@ def static_near(rwg: Rwg, rows, cols, cache=None):
     return outa, outp
 
 
-def channel_projections(rwg: Rwg, aim: AimOracle):
+def channel_projections(rwg: Rwg, aim: AimOracle, vals=None):
     """P_c, c = x, y, z, q (sparse Ng x n_rwg): sum over the functions'
-    quadrature points of w_q g_c(r_q) Lambda_u(r_q)."""
+    quadrature points of w_q g_c(r_q) Lambda_u(r_q); vals [N, 3, 3, C]
+    replaces the channel values (default rwg.point_values())."""
     V, T = rwg.V, rwg.T
     qp = _mesh.quad_points(V, T).reshape(-1, 3)
     s, u = stencil_start(qp, aim.origin, aim.h, aim.order, aim.dims)
     L = lagrange_weights(u, aim.order)                  # [Nq, 3, n+1]
-    vals = rwg.point_values()                           # [N, 3, 3, 4]
+    if vals is None:
+        vals = rwg.point_values()                       # [N, 3, 3, 4]
     N = T.shape[0]
     S = aim.order + 1
     out = []
-    for c in range(4):
+    for c in range(vals.shape[-1]):
         rr, cc, vv = [], [], []
         for e in range(3):
             fn = np.repeat(rwg.tri_rwg[:, e], 3)        # per point
