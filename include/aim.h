@@ -397,6 +397,37 @@ aim_status aim_matvec_efie(aim_plan plan, const void* x_dev, void* y_dev, int32_
 aim_status aim_efie_export(aim_plan plan, int32_t* tri_rwg, int32_t* rowptr, int32_t* col,
                            double* ca, double* cphi, void* hip_stream);
 
+/* The double-layer operator on RWG functions under AIMx (Sec. III-B, eqs.
+ * opK, ghgf, KAIMx, gH00; the K block of the discrete CFIE, eq. CFIEdis),
+ * with Galerkin RWG testing:
+ *   K_mn = int f_m(r) . [ n(r) x int grad G(r, r') x f_n(r') dS' ] dS,
+ *   grad G = -(r - r') (1 + jkR) e^{-jkR} / (4 pi R^3),
+ * n the unit normal (b - a) x (c - a) of the testing triangle, in the
+ * principal-value sense (a flat triangle's own contribution at its points
+ * is normal to it and drops out); the residue of the surface limit is a
+ * multiple of the Gram matrix G_mn = int f_m . f_n, so the call applies
+ *   y = (K(k_f) + gram_coef G) x
+ * (for the exterior MFIE n x H_inc = J/2 - n x K_PV J, -(K - G/2) is
+ * gram_coef = -1/2 with the sign of y flipped).  Evaluated as
+ * K_s,NR - K_s,P + W H_grad(k) P on the RWG functions, near list, point
+ * projection and wavenumbers of the EFIE above: three current channels
+ * w_q f(r_q), their moments (u - c) x J on the grid, six convolutions with
+ * the radial factor of grad G (self term 0 per component: eq. gH00 gives a
+ * scalar for this vector kernel), the field combined on the grid and
+ * interpolated, tested with w_q f_m(r_q) x n; static entries from the
+ * closed form of int (r - r')/R^3 over a triangle and the 3-point outer
+ * rule, precorrection with the grid's static gradient samples.  x_dev,
+ * y_dev [nrhs][n_rwg] complex128 (caller-owned, not overlapping);
+ * freq_idx_host as for aim_matvec_efie.  The first call builds the EFIE's
+ * tables if needed, then its own (blocking); asynchronous after that.
+ * aim_mfie_export copies C_K = K_s,NR - K_s,P and G on the RWG near list
+ * (order of aim_efie_export) to the host, and the build time; each pointer
+ * optional; blocking.  Same plan requirements as the EFIE. */
+aim_status aim_matvec_mfie(aim_plan plan, const void* x_dev, void* y_dev, int32_t nrhs,
+                           const int32_t* freq_idx_host, double gram_coef, void* hip_stream);
+aim_status aim_mfie_export(aim_plan plan, double* ck_host, double* gram_host, double* seconds,
+                           void* hip_stream);
+
 /* One stage of the matvec, for stage-level checks (see aim_stage for the
  * shapes).  Same rules as aim_matvec; grids are unpadded [nrhs][Nz][Ny][Nx]. */
 aim_status aim_apply_stage(aim_plan plan, aim_precision prec, aim_stage stage,

@@ -178,20 +178,26 @@ class MfieOracle:
         o = self.o
         Nx, Ny, _ = o.dims
         kern = grad_kernel(0.0, o.h, True)                  # = -grad G_s on the grid
-        Wc = [w.tocsc() for w in self.Wt]
-        Jc = [j.tocsc() for j in self.J]
+        if not hasattr(self, "_csc"):
+            self._csc = ([w.tocsc() for w in self.Wt], [j.tocsc() for j in self.J], {}, {})
+        Wc, Jc, wcache, jcache = self._csc
 
-        def nodes(mats, j):
-            idx = np.unique(np.concatenate([m.indices[m.indptr[j]:m.indptr[j + 1]]
-                                            for m in mats]))
-            vals = np.stack([np.asarray(m[idx, j].todense()).ravel() for m in mats], axis=1)
-            xyz = np.stack([idx % Nx, (idx // Nx) % Ny, idx // (Nx * Ny)], axis=1)
-            return xyz.astype(np.float64), vals
+        def nodes(mats, j, cache):
+            if j not in cache:
+                parts = [(m.indices[m.indptr[j]:m.indptr[j + 1]], m.data[m.indptr[j]:m.indptr[j + 1]])
+                         for m in mats]
+                idx = np.unique(np.concatenate([ii for ii, _ in parts]))
+                vals = np.zeros((idx.size, len(mats)))
+                for c, (ii, dd) in enumerate(parts):
+                    vals[np.searchsorted(idx, ii), c] = dd
+                xyz = np.stack([idx % Nx, (idx // Nx) % Ny, idx // (Nx * Ny)], axis=1)
+                cache[j] = (xyz.astype(np.float64), vals)
+            return cache[j]
 
         out = np.empty(len(rows))
         for t, (m, n) in enumerate(zip(rows, cols)):
-            xm, wm = nodes(Wc, int(m))
-            xn, jn = nodes(Jc, int(n))
+            xm, wm = nodes(Wc, int(m), wcache)
+            xn, jn = nodes(Jc, int(n), jcache)
             H = -kern(xm[:, None, :] - xn[None, :, :]).real  # grad G_s samples
             Vf = np.cross(H, jn[None, :, :]).sum(axis=1)       # [nm, 3]
             out[t] = float(np.sum(wm * Vf))

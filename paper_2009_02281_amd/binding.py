@@ -32,7 +32,8 @@ RHS = {"plane_wave": 0, "gaussian_patch": 1}
 EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim_matvec",
             "aim_matvec_static", "aim_conventional_fill", "aim_matvec_conventional",
             "aim_conventional_export", "aim_matvec_dlp", "aim_dlp_export",
-            "aim_efie_setup", "aim_matvec_efie", "aim_efie_export",
+            "aim_efie_setup", "aim_matvec_efie", "aim_efie_export", "aim_matvec_mfie",
+            "aim_mfie_export",
             "aim_export_clusters", "aim_set_lin_term",
             "aim_export_lin_diag", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
@@ -128,6 +129,9 @@ def load_library(path: str = LIB_PATH):
     lib.aim_efie_setup.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double), vp]
     lib.aim_matvec_efie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), vp]
+    lib.aim_matvec_mfie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
+    lib.aim_mfie_export.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), vp]
     lib.aim_efie_export.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), vp]
@@ -663,6 +667,33 @@ class Plan:
                                          C.c_void_p(y.data_ptr()), nrhs, fp,
                                          _stream_ptr(stream)))
         return y
+
+    def matvec_mfie(self, x, freq_idx=None, gram_coef: float = 0.0, out=None, stream=None):
+        """y = (K + gram_coef G) x, the RWG double layer under AIMx
+        (complex128, x of [n_rwg] or [nrhs, n_rwg])."""
+        import torch
+        n = self.efie_setup(stream)["n_rwg"]
+        self._check_vec(x, "c128", n, "x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        self._check_vec(y, "c128", n, "out")
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_matvec_mfie(self._plan, C.c_void_p(x.data_ptr()),
+                                         C.c_void_p(y.data_ptr()), nrhs, fp,
+                                         float(gram_coef), _stream_ptr(stream)))
+        return y
+
+    def mfie_values(self, stream=None) -> dict:
+        """C_K and the Gram entries on the RWG near list, and the build time."""
+        nnz = self.efie_setup(stream)["nnz"]
+        ck = np.empty(max(nnz, 1), dtype=np.float64)
+        gr = np.empty(max(nnz, 1), dtype=np.float64)
+        sec = C.c_double()
+        F64 = C.POINTER(C.c_double)
+        _check(self._lib.aim_mfie_export(self._plan, ck.ctypes.data_as(F64),
+                                         gr.ctypes.data_as(F64), C.byref(sec),
+                                         _stream_ptr(stream)))
+        return {"ck": ck[:nnz], "gram": gr[:nnz], "seconds": float(sec.value)}
 
     def efie_tables(self, stream=None) -> dict:
         """The RWG numbering (tri_rwg [N, 3]), the RWG near list and C_A,

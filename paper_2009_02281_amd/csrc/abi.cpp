@@ -194,6 +194,17 @@ struct aim_plan_s {
   int32_t* h_efie_freq = nullptr;  // pinned staging
   std::vector<int32_t> efie_cur_freq;
   double efie_seconds = 0.0;
+  // RWG double layer (aim_matvec_mfie), built on first use on the EFIE's tables
+  bool mfie_ready = false;
+  std::vector<double> mfie_ck;      // [nnz][2] (C_K, Gram) on the RWG near list
+  double* d_mfie_ck = nullptr;
+  double* d_mfie_nrm = nullptr;     // [N][3] unit normals
+  void* d_mfie_grid = nullptr;      // [6 max_rhs][Ng] currents, moments, then the field
+  void* d_mfie_work = nullptr;      // convolution workspace of 6 max_rhs grids
+  int32_t* d_mfie_freq = nullptr;   // [6 max_rhs]
+  int32_t* h_mfie_freq = nullptr;   // pinned staging
+  std::vector<int32_t> mfie_cur_freq;
+  double mfie_seconds = 0.0;
 
   // captured matvec graphs used by the solver, keyed by (prec, nrhs, in, out, freq)
   struct GraphKey {
@@ -268,6 +279,7 @@ struct aim_plan_s {
     if (h_rhs_freq) (void)hipHostFree(h_rhs_freq);
     if (h_dlp_freq) (void)hipHostFree(h_dlp_freq);
     if (h_efie_freq) (void)hipHostFree(h_efie_freq);
+    if (h_mfie_freq) (void)hipHostFree(h_mfie_freq);
     if (sv.nrm_host) (void)hipHostFree(sv.nrm_host);
     if (sv.H_host) (void)hipHostFree(sv.H_host);
     if (sv.g_host) (void)hipHostFree(sv.g_host);
@@ -959,6 +971,29 @@ aim_status aim_matvec_conventional(aim_plan p, aim_precision prec, const void* x
 }
 
 namespace {
+// The folded spectra of the gradient kernels' radial factor F (Sec. III-B)
+// for every wavenumber of the plan, shared by both double-layer operators.
+void ensure_grad_spectra(aim_plan p, hipStream_t s) {
+  if (p->d_dlp_spec) return;
+  const auto& g = p->g;
+  void* spec = p->dalloc(size_t(g.Nfold) * 16 * p->nfreq, s);
+  void* full = nullptr;
+  AIM_HIP(hipMalloc(&full, size_t(8) * g.Ng * 16));
+  try {
+    for (int f = 0; f < p->nfreq; ++f)
+      aim::launch_spectrum(g, p->k[f], p->t.h, full,
+                           static_cast<char*>(spec) + size_t(f) * g.Nfold * 16, nullptr,
+                           p->d_tw64, s, 1);
+    AIM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(full);
+    throw;
+  }
+  AIM_HIP(hipFree(full));
+  p->d_dlp_spec = spec;
+}
+
 // The double-layer operator's tables (Sec. III-B): unit normals, C_K on the
 // near list (device fill), the folded spectra of the radial factor F for
 // every wavenumber of the plan, and the buffers of max_rhs products.
@@ -987,27 +1022,13 @@ void ensure_dlp(aim_plan p, hipStream_t s) {
   const int R = p->max_rhs;
   p->d_dlp_nrm = p->upload(nrm, s);
   p->d_dlp_corr = p->upload(p->dlp_corr.empty() ? std::vector<double>(1, 0.0) : p->dlp_corr, s);
-  p->d_dlp_spec = p->dalloc(size_t(g.Nfold) * 16 * p->nfreq, s);
+  ensure_grad_spectra(p, s);
   p->d_dlp_src = p->dalloc(size_t(3) * R * N * 16, s);
   p->d_dlp_grid = p->dalloc(size_t(4) * R * g.Ng * 16, s);
   p->d_dlp_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 4 * R, s);
   p->d_dlp_phi = p->dalloc(size_t(R) * g.Ng * 16, s);
   p->d_dlp_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 4 * R, s));
   AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_dlp_freq), sizeof(int32_t) * 4 * R, 0));
-  void* full = nullptr;
-  AIM_HIP(hipMalloc(&full, size_t(8) * g.Ng * 16));
-  try {
-    for (int f = 0; f < p->nfreq; ++f)
-      aim::launch_spectrum(g, p->k[f], t.h, full,
-                           static_cast<char*>(p->d_dlp_spec) + size_t(f) * g.Nfold * 16, nullptr,
-                           p->d_tw64, s, 1);
-    AIM_HIP(hipStreamSynchronize(s));
-  } catch (...) {
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(full);
-    throw;
-  }
-  AIM_HIP(hipFree(full));
   p->dlp_cur_freq.clear();
   p->dlp_ready = true;
   p->dlp_seconds = now_s() - t0;
@@ -1088,13 +1109,10 @@ void ensure_efie(aim_plan p, hipStream_t s) {
     std::vector<double> pv;
     {
       aim::NearDevice nd(t, nullptr, nullptr, p->alloc, p->free_fn, p->actx, s);
-      nd.fill_efie_pairs(e.pair_rowptr, e.pair_col, pv, s);
+      nd.fill_rwg_pairs(0, e.pair_rowptr, e.pair_col, pv, s);
     }
     aim::assemble_efie_near(t, e, pv, p->host_threads);
   }
-  // the pair list only feeds the assembly
-  std::vector<int64_t>().swap(e.pair_rowptr);
-  std::vector<int32_t>().swap(e.pair_col);
   const auto& g = p->g;
   const int R = p->max_rhs;
   const int64_t P = 3 * t.N;
@@ -1128,8 +1146,9 @@ void ensure_efie(aim_plan p, hipStream_t s) {
   p->d_efie_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 4 * R, s));
   AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_efie_freq), sizeof(int32_t) * 4 * R, 0));
   AIM_HIP(hipStreamSynchronize(s));  // the host vectors feed the uploads
-  // the device copies serve the products; the host keeps what the export returns
-  for (auto* v : {&e.vals, &e.p_val, &e.pt_val}) std::vector<double>().swap(*v);
+  // the device copies serve the products; the host keeps what the export and
+  // the double layer's assembly need (channel values, pair list)
+  for (auto* v : {&e.p_val, &e.pt_val}) std::vector<double>().swap(*v);
   for (auto* v : {&e.p_rowptr, &e.p_col, &e.p_blk, &e.pt_rowptr, &e.pt_col})
     std::vector<int32_t>().swap(*v);
   p->efie_cur_freq.clear();
@@ -1200,6 +1219,113 @@ aim_status aim_matvec_efie(aim_plan p, const void* x, void* y, int32_t nrhs,
     aim::launch_efie_test(p->d_efie_src, p->d_efie_vals, p->d_efie_te, p->d_efie_rowptr,
                           p->d_efie_col, p->d_efie_cc, p->d_k, p->d_efie_freq, x, y, N, n, nrhs,
                           s);
+  });
+}
+
+namespace {
+// The RWG double layer's tables on top of the EFIE's: the triangle pairs'
+// static gradient integrals and grid sums on the device, C_K and the Gram
+// entries assembled on the host, the normals and max_rhs buffers.
+void ensure_mfie(aim_plan p, hipStream_t s) {
+  if (p->mfie_ready) return;
+  ensure_efie(p, s);
+  const double t0 = now_s();
+  const auto& t = p->t;
+  const auto& e = p->efie;
+  {
+    std::vector<double> pv;
+    {
+      aim::NearDevice nd(t, nullptr, nullptr, p->alloc, p->free_fn, p->actx, s);
+      nd.fill_rwg_pairs(1, e.pair_rowptr, e.pair_col, pv, s);
+    }
+    aim::assemble_mfie_near(t, e, pv, p->mfie_ck, p->host_threads);
+  }
+  std::vector<double> nrm(3 * size_t(t.N));
+  for (int64_t j = 0; j < t.N; ++j) {
+    const double* c = &t.corners[9 * j];
+    const double e1[3] = {c[3] - c[0], c[4] - c[1], c[5] - c[2]};
+    const double e2[3] = {c[6] - c[0], c[7] - c[1], c[8] - c[2]};
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                         e1[0] * e2[1] - e1[1] * e2[0]};
+    const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int a = 0; a < 3; ++a) nrm[3 * j + a] = n[a] / l;
+  }
+  const auto& g = p->g;
+  const int R = p->max_rhs;
+  p->d_mfie_ck = p->upload(p->mfie_ck, s);
+  p->d_mfie_nrm = p->upload(nrm, s);
+  ensure_grad_spectra(p, s);
+  p->d_mfie_grid = p->dalloc(size_t(6) * R * g.Ng * 16, s);
+  p->d_mfie_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 6 * R, s);
+  p->d_mfie_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 6 * R, s));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_mfie_freq), sizeof(int32_t) * 6 * R, 0));
+  AIM_HIP(hipStreamSynchronize(s));  // nrm feeds an upload
+  p->mfie_cur_freq.clear();
+  p->mfie_ready = true;
+  p->mfie_seconds = now_s() - t0;
+}
+}  // namespace
+
+aim_status aim_matvec_mfie(aim_plan p, const void* x, void* y, int32_t nrhs,
+                           const int32_t* freq_idx_host, double gram_coef, void* hip_stream) {
+  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    efie_checks(p);
+    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+    AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+                "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+    AIM_REQUIRE(std::isfinite(gram_coef), AIM_ERR_INVALID_ARG, "gram_coef must be finite");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::vector<int32_t> fr(size_t(nrhs), 0);
+    for (int r = 0; r < nrhs; ++r) {
+      if (freq_idx_host) {
+        AIM_REQUIRE(freq_idx_host[r] >= 0 && freq_idx_host[r] < p->nfreq, AIM_ERR_INVALID_ARG,
+                    "frequency index out of range");
+        fr[r] = freq_idx_host[r];
+      }
+    }
+    ensure_mfie(p, s);
+    std::vector<int32_t> f6(size_t(6) * nrhs);
+    for (int c = 0; c < 6; ++c)
+      for (int r = 0; r < nrhs; ++r) f6[size_t(c) * nrhs + r] = fr[r];
+    if (f6 != p->mfie_cur_freq) {
+      AIM_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed a copy
+      std::memcpy(p->h_mfie_freq, f6.data(), f6.size() * sizeof(int32_t));
+      AIM_HIP(hipMemcpyAsync(p->d_mfie_freq, p->h_mfie_freq, f6.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s));
+      p->mfie_cur_freq = f6;
+    }
+    const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
+    aim::launch_mfie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
+    aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
+                                p->d_mfie_grid, 3 * nrhs, s);
+    aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, false, s);
+    aim::launch_convolve<double>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid,
+                                 p->d_dlp_spec, p->d_mfie_freq, 6 * nrhs, p->d_tw64, s, nullptr,
+                                 p->sched[0]);
+    aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, true, s);
+    aim::CsrDevice none{};
+    none.n = P;
+    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
+                                    p->d_efie_src, 3 * nrhs, true, false, s);
+    aim::launch_mfie_test(p->d_efie_src, p->d_efie_vals, p->d_mfie_nrm, p->d_efie_te,
+                          p->d_efie_rowptr, p->d_efie_col, p->d_mfie_ck, gram_coef, x, y, N, n,
+                          nrhs, s);
+  });
+}
+
+aim_status aim_mfie_export(aim_plan p, double* ck_host, double* gram_host, double* seconds,
+                           void* hip_stream) {
+  if (!p) return fail(AIM_ERR_INVALID_ARG, "null plan");
+  return guarded([&] {
+    efie_checks(p);
+    ensure_mfie(p, static_cast<hipStream_t>(hip_stream));
+    const size_t nnz = p->efie.col.size();
+    for (size_t j = 0; j < nnz; ++j) {
+      if (ck_host) ck_host[j] = p->mfie_ck[2 * j];
+      if (gram_host) gram_host[j] = p->mfie_ck[2 * j + 1];
+    }
+    if (seconds) *seconds = p->mfie_seconds;
   });
 }
 

@@ -108,6 +108,10 @@ std::vector<int32_t> row_blocks(const std::vector<int32_t>& rowptr);
 // T_j of 1/R [3] and r'/R [3][3] at the three points of T_i, then the
 // point-pair precorrections sum_{u,v} L_u(r_iq) H_s(u - v) L_v(r_jq') [3][3]
 constexpr int kEfiePairVals = 21;
+// doubles per triangle pair for the double layer: int_{T_j} (r - r')/R^3
+// [3 points][3] at the points of T_i, then the point-pair sums of the static
+// grid samples h (u - v)/(4 pi R^3) [3][3][3]
+constexpr int kMfiePairVals = 36;
 struct EfieTables {
   int64_t n = 0;                      // RWG functions (interior edges)
   std::vector<int32_t> tri_rwg;       // [N][3] function on the edge opposite vertex e, or -1
@@ -134,6 +138,12 @@ void build_efie_tables(const HostTables& t, EfieTables& e, int nthreads);
 // C_A and C_phi from the pair values (kEfiePairVals per entry of the pair list)
 void assemble_efie_near(const HostTables& t, EfieTables& e, const std::vector<double>& pv,
                         int nthreads);
+// RWG double layer (Sec. III-B, eq. KAIMx): on the RWG near list, C_K =
+// K_s,NR - K_s,P of K_mn = f_m . (n x K f_n) and the Gram matrix
+// G_mn = int f_m . f_n, interleaved as ck [nnz][2], from the pair values
+// (kMfiePairVals per entry of the pair list)
+void assemble_mfie_near(const HostTables& t, const EfieTables& e, const std::vector<double>& pv,
+                        std::vector<double>& ck, int nthreads);
 
 // Closed-form integral of 1/|r - r'| over the triangle (a, b, c).
 double triangle_inv_r(const double r[3], const double a[3], const double b[3],
@@ -249,6 +259,21 @@ void launch_efie_test(const void* psi, const double* vals, const int32_t* rwg_te
                       const int32_t* rowptr, const int32_t* col, const double* cc,
                       const double* kv, const int32_t* rhs_freq, const void* x, void* y,
                       int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
+
+// RWG double layer, complex128: the three current channels of x at the
+// points (src[a][r][p], as launch_efie_sources without the charge); the
+// grid moments M = (u - c) x J (combine false: grids [3 nrhs, 6 nrhs) from
+// [0, 3 nrhs)) or, after the convolutions with the radial factor F, the field
+// V = -[(u - c) x (F * J) - F * M] into grids [0, 3 nrhs) (combine true); then
+// y[r][m] = sum over the function's points of (w f_m x n) . V(r_q) plus its
+// near row of (C_K + beta G), ck [nnz][2] = (C_K, G) interleaved
+void launch_mfie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
+                         int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
+void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s);
+void launch_mfie_test(const void* psi, const double* vals, const double* nrm,
+                      const int32_t* rwg_te, const int32_t* rowptr, const int32_t* col,
+                      const double* ck, double beta, const void* x, void* y, int64_t N,
+                      int64_t nrwg, int nrhs, hipStream_t s);
 
 void launch_excitation(int kind, const double* qp_xyz, const double* qp_w, int64_t n,
                        const double* params, int n_params, const double* kvals,
@@ -392,10 +417,11 @@ class NearDevice {
   // the near list, for the unit normals nrm [N][3]
   void fill_dlp(const std::vector<double>& nrm, std::vector<double>& near_out,
                 std::vector<double>& corr_out, hipStream_t s);
-  // RWG EFIE: kEfiePairVals values per triangle pair of the CSR list
-  // (rowptr [N+1], col), see EfieTables
-  void fill_efie_pairs(const std::vector<int64_t>& rowptr, const std::vector<int32_t>& col,
-                       std::vector<double>& out, hipStream_t s);
+  // RWG operators: per triangle pair of the CSR list (rowptr [N+1], col),
+  // kEfiePairVals values (kind 0, the EFIE) or kMfiePairVals (kind 1, the
+  // double layer), see EfieTables and assemble_mfie_near
+  void fill_rwg_pairs(int kind, const std::vector<int64_t>& rowptr,
+                      const std::vector<int32_t>& col, std::vector<double>& out, hipStream_t s);
   // inverses of the clusters' blocks of the full-kernel Galerkin matrix at
   // wavenumber k (complex128, row-major, at cl_blk offsets; device arrays);
   // throws AIM_ERR_GEOMETRY for a singular block

@@ -1,5 +1,6 @@
-// Device kernels of the RWG EFIE under AIMx (Sec. II-A, eq. EFIEdis; Sec.
-// II-B, eq. LAIMx), complex128.  One product y = Z x runs
+// Device kernels of the RWG operators under AIMx, complex128: the EFIE (Sec.
+// II-A, eq. EFIEdis; Sec. II-B, eq. LAIMx) and the double layer (Sec. III-B,
+// eq. KAIMx).  One EFIE product y = Z x runs
 //
 //   efie_sources -> projection of 4 nrhs point-source vectors (the current
 //   channels x, y, z and the charge channel) -> convolution of the 4 nrhs
@@ -8,6 +9,10 @@
 //
 // with the projection, convolution and interpolation kernels of the scalar
 // operator (the point stencils in place of the merged triangle stencils).
+// The double layer's product runs three current channels through the same
+// projection, the moments (u - c) x J on the grid, six convolutions with the
+// radial factor of grad G, the field combined on the grid, interpolation of
+// its three components and mfie_test.
 // Both kernels here are gathers over small fixed fan-ins: a point reads the
 // three functions of its triangle, a function the six points of its two
 // triangles and its near-list row; every output is written once, with a
@@ -28,6 +33,7 @@ unsigned blocks(int64_t cnt, int per = 256) {
 
 // src[c][r][p] for the point p = 3t + q: sum over the triangle's three edges
 // of the function's channel value at the point times its coefficient
+template <int C>
 __global__ __launch_bounds__(256) void efie_sources_kernel(
     const double2* __restrict__ x, const double* __restrict__ vals,
     const int32_t* __restrict__ tri_rwg, double2* __restrict__ src, int64_t N, int64_t nrwg,
@@ -38,23 +44,23 @@ __global__ __launch_bounds__(256) void efie_sources_kernel(
        p += int64_t(gridDim.x) * blockDim.x) {
     const int64_t t = p / 3;
     const double* v = vals + 36 * t + 12 * (p - 3 * t);
-    double2 acc[4];
+    double2 acc[C];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = make_double2(0.0, 0.0);
+    for (int c = 0; c < C; ++c) acc[c] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       const int32_t n = tri_rwg[3 * t + e];
       if (n < 0) continue;
       const double2 xv = x[int64_t(r) * nrwg + n];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < C; ++c) {
         const double w = v[4 * e + c];
         acc[c].x += w * xv.x;
         acc[c].y += w * xv.y;
       }
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) src[(int64_t(c) * nrhs + r) * P + p] = acc[c];
+    for (int c = 0; c < C; ++c) src[(int64_t(c) * nrhs + r) * P + p] = acc[c];
   }
 }
 
@@ -135,11 +141,166 @@ __global__ __launch_bounds__(256) void efie_test_kernel(
   }
 }
 
+// The double layer's grid stages (Sec. III-B, eq. KAIMx) in grid index
+// units about the grid centre c: with the radial factor F of the kernel
+// spectrum, grad G(r_u - r_v) = -(u - v) F(u - v), so the field
+// V(u) = sum_v grad G(r_u - r_v) x J(v) is -[(u - c) x (F * J)(u) - (F * M)(u)]
+// with the moments M(v) = (v - c) x J(v).  Grids: J_a of vector r at
+// a nrhs + r, M_a at (3 + a) nrhs + r; V overwrites J.
+__global__ __launch_bounds__(256) void mfie_moments_kernel(double2* __restrict__ g, int Nx, int Ny,
+                                                           int64_t Ng, int nrhs, double cx,
+                                                           double cy, double cz) {
+  const int r = blockIdx.y;
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
+       u += int64_t(gridDim.x) * blockDim.x) {
+    const double dx = double(u % Nx) - cx, dy = double((u / Nx) % Ny) - cy,
+                 dz = double(u / (int64_t(Nx) * Ny)) - cz;
+    const double2 jx = g[int64_t(r) * Ng + u], jy = g[int64_t(nrhs + r) * Ng + u],
+                  jz = g[int64_t(2 * nrhs + r) * Ng + u];
+    g[int64_t(3 * nrhs + r) * Ng + u] = make_double2(dy * jz.x - dz * jy.x, dy * jz.y - dz * jy.y);
+    g[int64_t(4 * nrhs + r) * Ng + u] = make_double2(dz * jx.x - dx * jz.x, dz * jx.y - dx * jz.y);
+    g[int64_t(5 * nrhs + r) * Ng + u] = make_double2(dx * jy.x - dy * jx.x, dx * jy.y - dy * jx.y);
+  }
+}
+
+__global__ __launch_bounds__(256) void mfie_combine_kernel(double2* __restrict__ g, int Nx, int Ny,
+                                                           int64_t Ng, int nrhs, double cx,
+                                                           double cy, double cz) {
+  const int r = blockIdx.y;
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
+       u += int64_t(gridDim.x) * blockDim.x) {
+    const double dx = double(u % Nx) - cx, dy = double((u / Nx) % Ny) - cy,
+                 dz = double(u / (int64_t(Nx) * Ny)) - cz;
+    double2* a0 = g + int64_t(r) * Ng + u;
+    double2* a1 = g + int64_t(nrhs + r) * Ng + u;
+    double2* a2 = g + int64_t(2 * nrhs + r) * Ng + u;
+    const double2 ax = *a0, ay = *a1, az = *a2;
+    const double2 bx = g[int64_t(3 * nrhs + r) * Ng + u], by = g[int64_t(4 * nrhs + r) * Ng + u],
+                  bz = g[int64_t(5 * nrhs + r) * Ng + u];
+    *a0 = make_double2(bx.x - (dy * az.x - dz * ay.x), bx.y - (dy * az.y - dz * ay.y));
+    *a1 = make_double2(by.x - (dz * ax.x - dx * az.x), by.y - (dz * ax.y - dx * az.y));
+    *a2 = make_double2(bz.x - (dx * ay.x - dy * ax.x), bz.y - (dx * ay.y - dy * ax.y));
+  }
+}
+
+// y[r][m]: t_q . V(r_q) over the six points of the function, t_q =
+// w_q f_m(r_q) x n of its triangle, plus its near row of C_K + beta G.
+// Lanes as in efie_test_kernel.
+template <int LPR, int RB>
+__global__ __launch_bounds__(256) void mfie_test_kernel(
+    const double2* __restrict__ psi, const double* __restrict__ vals,
+    const double* __restrict__ nrm, const int32_t* __restrict__ rwg_te,
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double2* __restrict__ ck, double beta, const double2* __restrict__ x,
+    double2* __restrict__ y, int64_t N, int64_t nrwg, int nrhs) {
+  const int sub = threadIdx.x % LPR;
+  const int64_t n = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
+  const int r0 = int(blockIdx.y) * RB;
+  const int nr = min(RB, nrhs - r0);
+  const int64_t P = 3 * N;
+  const int64_t cs = int64_t(nrhs) * P;
+  double yr[RB], yi[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) yr[j] = yi[j] = 0.0;
+  if (n < nrwg) {
+    if (sub < 6) {
+      const int side = sub >= 3 ? 1 : 0, q = sub - 3 * side;
+      const int64_t t = rwg_te[4 * n + 2 * side];
+      const int e = rwg_te[4 * n + 2 * side + 1];
+      const double* v = vals + 36 * t + 12 * q + 4 * e;
+      const double* nn = nrm + 3 * t;
+      const double t0 = v[1] * nn[2] - v[2] * nn[1], t1 = v[2] * nn[0] - v[0] * nn[2],
+                   t2 = v[0] * nn[1] - v[1] * nn[0];
+      const double2* base = psi + int64_t(r0) * P + 3 * t + q;
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+        if (j < nr) {
+          const double2* b = base + int64_t(j) * P;
+          const double2 p0 = b[0], p1 = b[cs], p2 = b[2 * cs];
+          yr[j] = t0 * p0.x + t1 * p1.x + t2 * p2.x;
+          yi[j] = t0 * p0.y + t1 * p1.y + t2 * p2.y;
+        }
+    }
+    const double2* xr = x + int64_t(r0) * nrwg;
+    for (int32_t k = rowptr[n] + sub; k < rowptr[n + 1]; k += LPR) {
+      const double2 c = ck[k];
+      const double w = c.x + beta * c.y;
+      const int64_t m = col[k];
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+        if (j < nr) {
+          const double2 xv = xr[int64_t(j) * nrwg + m];
+          yr[j] += w * xv.x;
+          yi[j] += w * xv.y;
+        }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RB; ++j)
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+      yr[j] += __shfl_xor(yr[j], o, LPR);
+      yi[j] += __shfl_xor(yi[j], o, LPR);
+    }
+  if (sub == 0 && n < nrwg) {
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < nr) y[int64_t(r0 + j) * nrwg + n] = make_double2(yr[j], yi[j]);
+  }
+}
+
 }  // namespace
+
+void launch_mfie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
+                         int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(efie_sources_kernel<3>, dim3(blocks(3 * N), nrhs), dim3(256), 0, s,
+                     static_cast<const double2*>(x), vals, tri_rwg, static_cast<double2*>(src),
+                     N, nrwg, nrhs);
+  AIM_HIP(hipGetLastError());
+}
+
+void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s) {
+  const double cx = 0.5 * (g.N[0] - 1), cy = 0.5 * (g.N[1] - 1), cz = 0.5 * (g.N[2] - 1);
+  double2* gp = static_cast<double2*>(grids);
+  if (combine)
+    hipLaunchKernelGGL(mfie_combine_kernel, dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s, gp,
+                       g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
+  else
+    hipLaunchKernelGGL(mfie_moments_kernel, dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s, gp,
+                       g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
+  AIM_HIP(hipGetLastError());
+}
+
+void launch_mfie_test(const void* psi, const double* vals, const double* nrm,
+                      const int32_t* rwg_te, const int32_t* rowptr, const int32_t* col,
+                      const double* ck, double beta, const void* x, void* y, int64_t N,
+                      int64_t nrwg, int nrhs, hipStream_t s) {
+  if (nrwg == 0) return;
+  constexpr int LPR = 16;
+  const int64_t gx = (nrwg * LPR + 255) / 256;
+  int rb = 1;
+  while (rb < 8 && 2 * rb <= nrhs && gx * ((nrhs + 2 * rb - 1) / (2 * rb)) >= 1024) rb *= 2;
+  const dim3 grid(unsigned(gx), unsigned((nrhs + rb - 1) / rb));
+  const double2* ps = static_cast<const double2*>(psi);
+  const double2* c2 = reinterpret_cast<const double2*>(ck);
+  const double2* xi = static_cast<const double2*>(x);
+  double2* yo = static_cast<double2*>(y);
+#define AIM_MFIE_TEST(R)                                                                       \
+  hipLaunchKernelGGL((mfie_test_kernel<LPR, R>), grid, dim3(256), 0, s, ps, vals, nrm, rwg_te, \
+                     rowptr, col, c2, beta, xi, yo, N, nrwg, nrhs)
+  switch (rb) {
+    case 1: AIM_MFIE_TEST(1); break;
+    case 2: AIM_MFIE_TEST(2); break;
+    case 4: AIM_MFIE_TEST(4); break;
+    default: AIM_MFIE_TEST(8); break;
+  }
+#undef AIM_MFIE_TEST
+  AIM_HIP(hipGetLastError());
+}
 
 void launch_efie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(efie_sources_kernel, dim3(blocks(3 * N), nrhs), dim3(256), 0, s,
+  hipLaunchKernelGGL(efie_sources_kernel<4>, dim3(blocks(3 * N), nrhs), dim3(256), 0, s,
                      static_cast<const double2*>(x), vals, tri_rwg, static_cast<double2*>(src),
                      N, nrwg, nrhs);
   AIM_HIP(hipGetLastError());

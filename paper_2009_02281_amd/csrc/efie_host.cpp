@@ -287,4 +287,81 @@ void assemble_efie_near(const HostTables& t, EfieTables& e, const std::vector<do
   });
 }
 
+// The double layer's near values.  With t_q = w_q f_m(r_q) x n_m (n_m the
+// testing triangle's unit normal), f_m . (n_m x V) = t_q . V, and for
+// f_n = s l/(2A) (r' - p) on its triangle,
+//   int grad G_s x f_n dS' = -(s l/(2A)) (1/4 pi) g(r) x (r - p),
+// g(r) = int (r - r')/R^3 dS' (the pair values); the precorrection is
+// sum over point pairs of t_q . (H_s x J_q') with H_s = -(the pair's grid
+// sums) the static samples of grad G and J_q' = w f_n(r_q'); the Gram
+// entries come from triangles the two functions share.
+void assemble_mfie_near(const HostTables& t, const EfieTables& e, const std::vector<double>& pv,
+                        std::vector<double>& ck, int nthreads) {
+  const int64_t n = e.n, N = t.N;
+  AIM_REQUIRE(pv.size() == size_t(kMfiePairVals) * e.pair_col.size(), AIM_ERR_STATE,
+              "pair values do not match the pair list");
+  AIM_REQUIRE(e.vals.size() == 36 * size_t(N), AIM_ERR_STATE, "channel values not kept");
+  std::vector<double> nrm(3 * size_t(N));
+  for (int64_t j = 0; j < N; ++j) {
+    const double* c = &t.corners[9 * j];
+    const double e1[3] = {c[3] - c[0], c[4] - c[1], c[5] - c[2]};
+    const double e2[3] = {c[6] - c[0], c[7] - c[1], c[8] - c[2]};
+    const double v[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                         e1[0] * e2[1] - e1[1] * e2[0]};
+    const double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int a = 0; a < 3; ++a) nrm[3 * j + a] = v[a] / l;
+  }
+  auto cross = [](const double* a, const double* b, double* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+  };
+  ck.assign(2 * std::max<size_t>(e.col.size(), 1), 0.0);
+  parallel_ranges(n, nthreads, [&](int64_t b0, int64_t b1) {
+    for (int64_t m = b0; m < b1; ++m)
+      for (int32_t p = e.rowptr[m]; p < e.rowptr[m + 1]; ++p) {
+        const int32_t nn = e.col[p];
+        double sk = 0.0, pk = 0.0, gr = 0.0;
+        for (int sm = 0; sm < 2; ++sm) {
+          const int32_t tm = e.rwg_te[4 * m + 2 * sm], em = e.rwg_te[4 * m + 2 * sm + 1];
+          double tv[3][3];  // t_q of the testing function on tm
+          for (int q = 0; q < 3; ++q) cross(&e.vals[36 * size_t(tm) + 12 * q + 4 * em],
+                                            &nrm[3 * size_t(tm)], tv[q]);
+          for (int sn = 0; sn < 2; ++sn) {
+            const int32_t tn = e.rwg_te[4 * size_t(nn) + 2 * sn];
+            const int32_t en = e.rwg_te[4 * size_t(nn) + 2 * sn + 1];
+            const int64_t idx = find_in_row(e.pair_rowptr, e.pair_col, tm, tn);
+            AIM_REQUIRE(idx >= 0, AIM_ERR_STATE, "triangle pair missing from the pair list");
+            const double* v = &pv[size_t(kMfiePairVals) * idx];
+            const double sl = e.sgn_len[3 * size_t(tn) + en];
+            const double coef = -sl / (2.0 * t.area[tn]) / kFourPi;
+            const double* fr = &t.corners[9 * size_t(tn) + 3 * en];
+            for (int q = 0; q < 3; ++q) {
+              const double* r = &t.qp_xyz[3 * (3 * size_t(tm) + q)];
+              const double rp[3] = {r[0] - fr[0], r[1] - fr[1], r[2] - fr[2]};
+              double gx[3];
+              cross(v + 3 * q, rp, gx);
+              sk += coef * (tv[q][0] * gx[0] + tv[q][1] * gx[1] + tv[q][2] * gx[2]);
+              for (int q2 = 0; q2 < 3; ++q2) {
+                const double* hs = v + 9 + 3 * (3 * q + q2);
+                const double* jn = &e.vals[36 * size_t(tn) + 12 * q2 + 4 * en];
+                double hj[3];
+                cross(hs, jn, hj);  // (-H_s) x J
+                pk -= tv[q][0] * hj[0] + tv[q][1] * hj[1] + tv[q][2] * hj[2];
+              }
+            }
+            if (tm == tn)
+              for (int q = 0; q < 3; ++q) {
+                const double* fm = &e.vals[36 * size_t(tm) + 12 * q + 4 * em];
+                const double* fn = &e.vals[36 * size_t(tm) + 12 * q + 4 * en];
+                gr += (fm[0] * fn[0] + fm[1] * fn[1] + fm[2] * fn[2]) / t.qp_w[3 * size_t(tm) + q];
+              }
+          }
+        }
+        ck[2 * size_t(p)] = sk - pk;
+        ck[2 * size_t(p) + 1] = gr;
+      }
+  });
+}
+
 }  // namespace aim

@@ -151,6 +151,36 @@ __device__ P3 rvec_r_integral(P3 r, const P3* v, double s1) {
   return acc;
 }
 
+// integral over triangle v[0..2] of (r - r') / |r - r'|^3 dS' (a vector):
+// the in-plane part is the gradient theorem for grad_s' (1/R) over T, the
+// sum over the edges of the outward in-plane normal m_i times int dl/R; the
+// normal part is n sign(h) times the solid angle T subtends at r, 0 for
+// heights below hmin (in the plane: the principal value)
+__device__ P3 grad_inv_r_integral(P3 r, const P3* v) {
+  const P3 nn = cross(sub(v[1], v[0]), sub(v[2], v[0]));
+  const double tw = len(nn);
+  const P3 n = scale(nn, 1.0 / tw);
+  const double h = dot(sub(r, v[0]), n);
+  P3 acc = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const P3 p = v[e], q = v[(e + 1) % 3];
+    const P3 d = sub(q, p);
+    const P3 u = scale(d, 1.0 / len(d));
+    const P3 m = cross(u, n);
+    const P3 pr = sub(p, r), qr = sub(q, r);
+    const double P0 = dot(pr, m);
+    const double f = edge_integral(dot(pr, u), dot(qr, u), len(pr), len(qr), P0 * P0 + h * h);
+    acc = {acc.x + f * m.x, acc.y + f * m.y, acc.z + f * m.z};
+  }
+  if (fabs(h) > 1e-14 * sqrt(tw)) {
+    const double om = solid_angle(sub(v[0], r), sub(v[1], r), sub(v[2], r));
+    const double sn = h > 0.0 ? om : -om;
+    acc = {acc.x + sn * n.x, acc.y + sn * n.y, acc.z + sn * n.z};
+  }
+  return acc;
+}
+
 struct NearArgs {
   const double* tri;       // [N][3][3] corners
   const double* qp;        // [3N][3] quadrature points
@@ -409,6 +439,36 @@ __global__ __launch_bounds__(128) void efie_pair_kernel(NearArgs a, double* out)
   for (int q = 0; q < 3; ++q)
     for (int q2 = 0; q2 < 3; ++q2)
       o[12 + 3 * q + q2] = point_pair<0, ORDER>(a, 3 * i + q, 3 * j + q2);
+}
+
+// RWG double layer (Sec. III-B): for the pair (i, j) of the triangle pair
+// list, int_{T_j} (r - r')/R^3 dS' at the three points of T_i, then the
+// point-pair sums sum_{u, v} L_u(r_iq) h (u - v) / (4 pi R^3) L_v(r_jq')
+// (the static samples of -grad G, three components each)
+template <int ORDER>
+__global__ __launch_bounds__(128) void mfie_pair_kernel(NearArgs a, double* out) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.nnz) return;
+  const int64_t i = row_of(a.rowptr, a.N, p), j = a.col[p];
+  P3 v[3];
+  for (int c = 0; c < 3; ++c)
+    v[c] = {a.tri[9 * j + 3 * c], a.tri[9 * j + 3 * c + 1], a.tri[9 * j + 3 * c + 2]};
+  double* o = out + int64_t(kMfiePairVals) * p;
+  for (int q = 0; q < 3; ++q) {
+    const int64_t qi = 3 * i + q;
+    const P3 g = grad_inv_r_integral({a.qp[3 * qi], a.qp[3 * qi + 1], a.qp[3 * qi + 2]}, v);
+    o[3 * q] = g.x;
+    o[3 * q + 1] = g.y;
+    o[3 * q + 2] = g.z;
+  }
+  for (int q = 0; q < 3; ++q)
+    for (int q2 = 0; q2 < 3; ++q2) {
+      const Vec3d w = point_pair<3, ORDER>(a, 3 * i + q, 3 * j + q2);
+      double* d = o + 9 + 3 * (3 * q + q2);
+      d[0] = w.x;
+      d[1] = w.y;
+      d[2] = w.z;
+    }
 }
 
 // conventional AIM: A_NR(k) - A_P(k) from the static entries
@@ -683,23 +743,32 @@ void NearDevice::fill_dlp(const std::vector<double>& nrm, std::vector<double>& n
   AIM_HIP(hipStreamSynchronize(s));
 }
 
-void NearDevice::fill_efie_pairs(const std::vector<int64_t>& rowptr,
-                                 const std::vector<int32_t>& col, std::vector<double>& out,
-                                 hipStream_t s) {
+void NearDevice::fill_rwg_pairs(int kind, const std::vector<int64_t>& rowptr,
+                                const std::vector<int32_t>& col, std::vector<double>& out,
+                                hipStream_t s) {
   AIM_REQUIRE(tri_ != nullptr, AIM_ERR_STATE, "near-field tables built without the mesh");
   AIM_REQUIRE(rowptr.size() == size_t(N_) + 1 && int64_t(col.size()) == rowptr[N_],
               AIM_ERR_INVALID_ARG, "pair list does not match the mesh");
+  AIM_REQUIRE(kind == 0 || kind == 1, AIM_ERR_INVALID_ARG, "pair kind");
+  const int per = kind == 0 ? kEfiePairVals : kMfiePairVals;
   const int64_t np = int64_t(col.size());
-  out.assign(size_t(kEfiePairVals) * np, 0.0);
+  out.assign(size_t(per) * np, 0.0);
   if (np == 0) return;
   void* rp = put(get(rowptr.size() * 8), rowptr, s);
   void* cp = put(get(col.size() * 4), col, s);
   double* od = static_cast<double*>(get(out.size() * 8));
   const NearArgs a = make_args(tri_, qp_, qw_, qstart_, qlocal_, rp, cp, N_, np, h_, 0.0);
-  if (order_ == 2)
-    hipLaunchKernelGGL(efie_pair_kernel<2>, dim3(blocks_for(np)), dim3(128), 0, s, a, od);
-  else
-    hipLaunchKernelGGL(efie_pair_kernel<3>, dim3(blocks_for(np)), dim3(128), 0, s, a, od);
+  if (kind == 0) {
+    if (order_ == 2)
+      hipLaunchKernelGGL(efie_pair_kernel<2>, dim3(blocks_for(np)), dim3(128), 0, s, a, od);
+    else
+      hipLaunchKernelGGL(efie_pair_kernel<3>, dim3(blocks_for(np)), dim3(128), 0, s, a, od);
+  } else {
+    if (order_ == 2)
+      hipLaunchKernelGGL(mfie_pair_kernel<2>, dim3(blocks_for(np)), dim3(128), 0, s, a, od);
+    else
+      hipLaunchKernelGGL(mfie_pair_kernel<3>, dim3(blocks_for(np)), dim3(128), 0, s, a, od);
+  }
   AIM_HIP(hipGetLastError());
   AIM_HIP(hipMemcpyAsync(out.data(), od, out.size() * 8, hipMemcpyDeviceToHost, s));
   AIM_HIP(hipStreamSynchronize(s));
