@@ -622,11 +622,11 @@ def dlp_leg(plan, w, reps: int = 20) -> dict:
 
 
 def efie_leg(reps: int = 20) -> dict:
-    """The RWG EFIE under AIMx (Sec. II-A, II-B) on the 81,920-triangle
-    sphere (122,880 functions, 128^3 grid): the tables' build time and the
-    per-call time of Z x (four channel grids through one spectrum, complex128)
-    for one and four vectors, beside the scalar single-layer product A x on the
-    same plan (one grid)."""
+    """The RWG operators under AIMx on the 81,920-triangle sphere (122,880
+    functions, 128^3 grid): the tables' build times and the per-call times of
+    the EFIE Z x (Sec. II-A, II-B), the double layer (K - G/2) x and the
+    combined field of eq. CFIEAIMx (Sec. III-B), complex128, for one and four
+    vectors, beside the scalar single-layer product A x on the same plan."""
     import torch
     from paper_2009_02281_amd import binding
     from paper_2009_02281_amd import inputs as I
@@ -652,19 +652,30 @@ def efie_leg(reps: int = 20) -> dict:
     res = {"workload": w.name, "triangles": int(w.triangles.shape[0]), "n_rwg": info["n_rwg"],
            "rwg_near_nnz": info["nnz"], "plan_seconds": plan_s,
            "efie_tables_seconds": info["seconds"]}
+    ops = (("efie", p.matvec_efie), ("mfie", lambda x, out: p.matvec_mfie(x, gram_coef=-0.5,
+                                                                          out=out)),
+           ("cfie", lambda x, out: p.matvec_cfie(x, gram_coef=-0.5, out=out)))
+    x1 = torch.from_numpy(I.complex_gaussian(info["n_rwg"], w.seed_base + 1)).cuda()
+    p.matvec_mfie(x1, out=torch.empty_like(x1))      # builds the double layer's tables
+    res["mfie_tables_seconds"] = p.mfie_values()["seconds"]
     for nrhs in (1, 4):
         x = torch.from_numpy(I.complex_gaussian(info["n_rwg"], w.seed_base + nrhs,
                                                 nrhs=nrhs)).cuda()
-        ms = timed(p.matvec_efie, x, torch.empty_like(x))
-        res[f"nrhs{nrhs}"] = {"ms_per_call": ms, "ms_per_vector": ms / nrhs,
-                              "unknowns_matvecs_per_s": info["n_rwg"] * nrhs / (ms * 1e-3)}
-        print(f"[bench] EFIE on {w.name}: {nrhs} vector(s) {ms:.3f} ms per call",
-              file=sys.stderr, flush=True)
+        for name, fn in ops:
+            ms = timed(fn, x, torch.empty_like(x))
+            key = f"nrhs{nrhs}" if name == "efie" else f"{name}_nrhs{nrhs}"
+            res[key] = {"ms_per_call": ms, "ms_per_vector": ms / nrhs,
+                        "unknowns_matvecs_per_s": info["n_rwg"] * nrhs / (ms * 1e-3)}
+            print(f"[bench] {name} on {w.name}: {nrhs} vector(s) {ms:.3f} ms per call",
+                  file=sys.stderr, flush=True)
     xs = torch.from_numpy(I.complex_gaussian(p.n, w.seed_base)).cuda()
     res["scalar_ms_per_matvec"] = timed(p.matvec, xs, torch.empty_like(xs))
-    res["note"] = ("complex128; three current channels and one charge channel projected from "
-                   "the quadrature points and convolved with the plan's spectrum; the scalar "
-                   "product on the same plan convolves one grid")
+    res["note"] = ("complex128; EFIE: three current channels and one charge channel projected "
+                   "from the quadrature points and convolved with the plan's spectrum (4 grids "
+                   "per vector); double layer (K - G/2): three current channels and their grid "
+                   "moments convolved with the radial factor of grad G (6 grids); combined "
+                   "field: one projection, 10 grids; the scalar product on the same plan "
+                   "convolves one grid")
     p.close()
     return res
 
@@ -750,7 +761,7 @@ def main() -> int:
                     help="skip the learned-preconditioner time-to-tolerance leg")
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net throughput leg")
     ap.add_argument("--no-efie", action="store_true",
-                    help="skip the RWG EFIE leg (81,920-triangle sphere)")
+                    help="skip the RWG operators' leg (81,920-triangle sphere)")
     ap.add_argument("--efie-only", action="store_true",
                     help="only run the RWG EFIE leg (--steps products per timing)")
     ap.add_argument("--no-extra", action="store_true",

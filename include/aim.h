@@ -428,6 +428,19 @@ aim_status aim_matvec_mfie(aim_plan plan, const void* x_dev, void* y_dev, int32_
 aim_status aim_mfie_export(aim_plan plan, double* ck_host, double* gram_host, double* seconds,
                            void* hip_stream);
 
+/* The AIMx-accelerated combined-field operator of eq. CFIEAIMx (Sec. III-B;
+ * the discrete CFIE, eq. CFIEdis), with its common factor -j omega mu0 left
+ * out:
+ *   y = Z(k_f) x - (j / k_f) (K(k_f) + gram_coef G) x,
+ * Z the EFIE operator of aim_matvec_efie and K, G those of aim_matvec_mfie
+ * (-(j/k) K is the term -(j/k0) K of eq. CFIEAIMx; gram_coef places the
+ * residue of the surface limit).  One projection of the four channels
+ * serves both operators: the double layer takes its three current grids
+ * from it.  Arguments and rules as for aim_matvec_mfie; the first call
+ * builds both operators' tables and a [3 max_rhs][3N] field buffer. */
+aim_status aim_matvec_cfie(aim_plan plan, const void* x_dev, void* y_dev, int32_t nrhs,
+                           const int32_t* freq_idx_host, double gram_coef, void* hip_stream);
+
 /* One stage of the matvec, for stage-level checks (see aim_stage for the
  * shapes).  Same rules as aim_matvec; grids are unpadded [nrhs][Nz][Ny][Nx]. */
 aim_status aim_apply_stage(aim_plan plan, aim_precision prec, aim_stage stage,

@@ -33,7 +33,7 @@ EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim
             "aim_matvec_static", "aim_conventional_fill", "aim_matvec_conventional",
             "aim_conventional_export", "aim_matvec_dlp", "aim_dlp_export",
             "aim_efie_setup", "aim_matvec_efie", "aim_efie_export", "aim_matvec_mfie",
-            "aim_mfie_export",
+            "aim_mfie_export", "aim_matvec_cfie",
             "aim_export_clusters", "aim_set_lin_term",
             "aim_export_lin_diag", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH):
                                    C.POINTER(C.c_double), vp]
     lib.aim_matvec_efie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), vp]
     lib.aim_matvec_mfie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
+    lib.aim_matvec_cfie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
     lib.aim_mfie_export.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), vp]
     lib.aim_efie_export.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -679,6 +680,21 @@ class Plan:
         self._check_vec(y, "c128", n, "out")
         _, fp = _freq_arg(freq_idx, nrhs)
         _check(self._lib.aim_matvec_mfie(self._plan, C.c_void_p(x.data_ptr()),
+                                         C.c_void_p(y.data_ptr()), nrhs, fp,
+                                         float(gram_coef), _stream_ptr(stream)))
+        return y
+
+    def matvec_cfie(self, x, freq_idx=None, gram_coef: float = 0.0, out=None, stream=None):
+        """y = Z x - (j/k)(K + gram_coef G) x, the combined-field operator
+        (complex128, x of [n_rwg] or [nrhs, n_rwg])."""
+        import torch
+        n = self.efie_setup(stream)["n_rwg"]
+        self._check_vec(x, "c128", n, "x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        self._check_vec(y, "c128", n, "out")
+        _, fp = _freq_arg(freq_idx, nrhs)
+        _check(self._lib.aim_matvec_cfie(self._plan, C.c_void_p(x.data_ptr()),
                                          C.c_void_p(y.data_ptr()), nrhs, fp,
                                          float(gram_coef), _stream_ptr(stream)))
         return y

@@ -203,6 +203,7 @@ struct aim_plan_s {
   void* d_mfie_work = nullptr;      // convolution workspace of 6 max_rhs grids
   int32_t* d_mfie_freq = nullptr;   // [6 max_rhs]
   int32_t* h_mfie_freq = nullptr;   // pinned staging
+  void* d_cfie_psi = nullptr;       // [3 max_rhs][3N] the double layer's field (combined call)
   std::vector<int32_t> mfie_cur_freq;
   double mfie_seconds = 0.0;
 
@@ -1175,36 +1176,51 @@ aim_status aim_efie_setup(aim_plan p, int64_t* n_rwg, int64_t* nnz, double* seco
   });
 }
 
+namespace {
+// per-vector spectrum indices, validated (NULL: all 0)
+std::vector<int32_t> freq_list(aim_plan p, int nrhs, const int32_t* freq_idx_host) {
+  std::vector<int32_t> fr(size_t(nrhs), 0);
+  for (int r = 0; r < nrhs && freq_idx_host; ++r) {
+    AIM_REQUIRE(freq_idx_host[r] >= 0 && freq_idx_host[r] < p->nfreq, AIM_ERR_INVALID_ARG,
+                "frequency index out of range");
+    fr[r] = freq_idx_host[r];
+  }
+  return fr;
+}
+
+// one spectrum index per grid, `channels` blocks of nrhs grids that all take
+// their vector's wavenumber (the first block doubles as the per-vector
+// index); copied to the device only when it changes
+void stage_freq(const std::vector<int32_t>& fr, int channels, std::vector<int32_t>& cur,
+                int32_t* h, int32_t* d, hipStream_t s) {
+  const size_t nrhs = fr.size();
+  std::vector<int32_t> f(size_t(channels) * nrhs);
+  for (int c = 0; c < channels; ++c)
+    for (size_t r = 0; r < nrhs; ++r) f[size_t(c) * nrhs + r] = fr[r];
+  if (f == cur) return;
+  AIM_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed a copy
+  std::memcpy(h, f.data(), f.size() * sizeof(int32_t));
+  AIM_HIP(hipMemcpyAsync(d, h, f.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  cur = f;
+}
+
+void check_rwg_call(aim_plan p, const void* x, const void* y, int nrhs) {
+  efie_checks(p);
+  AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
+  AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+              "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+}
+}  // namespace
+
 aim_status aim_matvec_efie(aim_plan p, const void* x, void* y, int32_t nrhs,
                            const int32_t* freq_idx_host, void* hip_stream) {
   if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
-    efie_checks(p);
-    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
-    AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
-                "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+    check_rwg_call(p, x, y, nrhs);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    std::vector<int32_t> fr(size_t(nrhs), 0);
-    for (int r = 0; r < nrhs; ++r) {
-      if (freq_idx_host) {
-        AIM_REQUIRE(freq_idx_host[r] >= 0 && freq_idx_host[r] < p->nfreq, AIM_ERR_INVALID_ARG,
-                    "frequency index out of range");
-        fr[r] = freq_idx_host[r];
-      }
-    }
+    const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
     ensure_efie(p, s);
-    // grid c nrhs + r (channel c of right-hand side r) takes r's wavenumber;
-    // the first nrhs entries double as the test kernel's per-vector index
-    std::vector<int32_t> f4(size_t(4) * nrhs);
-    for (int c = 0; c < 4; ++c)
-      for (int r = 0; r < nrhs; ++r) f4[size_t(c) * nrhs + r] = fr[r];
-    if (f4 != p->efie_cur_freq) {
-      AIM_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed a copy
-      std::memcpy(p->h_efie_freq, f4.data(), f4.size() * sizeof(int32_t));
-      AIM_HIP(hipMemcpyAsync(p->d_efie_freq, p->h_efie_freq, f4.size() * sizeof(int32_t),
-                             hipMemcpyHostToDevice, s));
-      p->efie_cur_freq = f4;
-    }
+    stage_freq(fr, 4, p->efie_cur_freq, p->h_efie_freq, p->d_efie_freq, s);
     const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
     aim::launch_efie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
     aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
@@ -1216,9 +1232,9 @@ aim_status aim_matvec_efie(aim_plan p, const void* x, void* y, int32_t nrhs,
     none.n = P;  // interpolation only: the near rows are the test kernel's
     aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_efie_grid, nullptr,
                                     p->d_efie_src, 4 * nrhs, true, false, s);
-    aim::launch_efie_test(p->d_efie_src, p->d_efie_vals, p->d_efie_te, p->d_efie_rowptr,
-                          p->d_efie_col, p->d_efie_cc, p->d_k, p->d_efie_freq, x, y, N, n, nrhs,
-                          s);
+    aim::launch_rwg_test(true, false, p->d_efie_src, nullptr, p->d_efie_vals, nullptr,
+                         p->d_efie_te, p->d_efie_rowptr, p->d_efie_col, p->d_efie_cc, nullptr,
+                         0.0, p->d_k, p->d_efie_freq, x, y, N, n, nrhs, s);
   });
 }
 
@@ -1264,53 +1280,78 @@ void ensure_mfie(aim_plan p, hipStream_t s) {
   p->mfie_ready = true;
   p->mfie_seconds = now_s() - t0;
 }
+
+// moments, the six convolutions with the radial factor, the field
+void mfie_grid_stages(aim_plan p, int nrhs, hipStream_t s) {
+  aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, false, s);
+  aim::launch_convolve<double>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid,
+                               p->d_dlp_spec, p->d_mfie_freq, 6 * nrhs, p->d_tw64, s, nullptr,
+                               p->sched[0]);
+  aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, true, s);
+}
 }  // namespace
 
 aim_status aim_matvec_mfie(aim_plan p, const void* x, void* y, int32_t nrhs,
                            const int32_t* freq_idx_host, double gram_coef, void* hip_stream) {
   if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
-    efie_checks(p);
-    AIM_REQUIRE(x != y, AIM_ERR_INVALID_ARG, "x and y must not overlap");
-    AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
-                "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+    check_rwg_call(p, x, y, nrhs);
     AIM_REQUIRE(std::isfinite(gram_coef), AIM_ERR_INVALID_ARG, "gram_coef must be finite");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    std::vector<int32_t> fr(size_t(nrhs), 0);
-    for (int r = 0; r < nrhs; ++r) {
-      if (freq_idx_host) {
-        AIM_REQUIRE(freq_idx_host[r] >= 0 && freq_idx_host[r] < p->nfreq, AIM_ERR_INVALID_ARG,
-                    "frequency index out of range");
-        fr[r] = freq_idx_host[r];
-      }
-    }
+    const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
     ensure_mfie(p, s);
-    std::vector<int32_t> f6(size_t(6) * nrhs);
-    for (int c = 0; c < 6; ++c)
-      for (int r = 0; r < nrhs; ++r) f6[size_t(c) * nrhs + r] = fr[r];
-    if (f6 != p->mfie_cur_freq) {
-      AIM_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed a copy
-      std::memcpy(p->h_mfie_freq, f6.data(), f6.size() * sizeof(int32_t));
-      AIM_HIP(hipMemcpyAsync(p->d_mfie_freq, p->h_mfie_freq, f6.size() * sizeof(int32_t),
-                             hipMemcpyHostToDevice, s));
-      p->mfie_cur_freq = f6;
-    }
+    stage_freq(fr, 6, p->mfie_cur_freq, p->h_mfie_freq, p->d_mfie_freq, s);
     const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
     aim::launch_mfie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
     aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
                                 p->d_mfie_grid, 3 * nrhs, s);
-    aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, false, s);
+    mfie_grid_stages(p, nrhs, s);
+    aim::CsrDevice none{};
+    none.n = P;
+    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
+                                    p->d_efie_src, 3 * nrhs, true, false, s);
+    aim::launch_rwg_test(false, true, nullptr, p->d_efie_src, p->d_efie_vals, p->d_mfie_nrm,
+                         p->d_efie_te, p->d_efie_rowptr, p->d_efie_col, nullptr, p->d_mfie_ck,
+                         gram_coef, p->d_k, p->d_mfie_freq, x, y, N, n, nrhs, s);
+  });
+}
+
+aim_status aim_matvec_cfie(aim_plan p, const void* x, void* y, int32_t nrhs,
+                           const int32_t* freq_idx_host, double gram_coef, void* hip_stream) {
+  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    check_rwg_call(p, x, y, nrhs);
+    AIM_REQUIRE(std::isfinite(gram_coef), AIM_ERR_INVALID_ARG, "gram_coef must be finite");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
+    ensure_mfie(p, s);
+    if (!p->d_cfie_psi) p->d_cfie_psi = p->dalloc(size_t(3) * p->max_rhs * 3 * p->t.N * 16, s);
+    stage_freq(fr, 4, p->efie_cur_freq, p->h_efie_freq, p->d_efie_freq, s);
+    stage_freq(fr, 6, p->mfie_cur_freq, p->h_mfie_freq, p->d_mfie_freq, s);
+    const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
+    // one projection of the four channels serves both operators: the
+    // double layer takes the three current grids from it
+    aim::launch_efie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
+    aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
+                                p->d_efie_grid, 4 * nrhs, s);
+    aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, false, s, p->d_efie_grid);
+    aim::launch_convolve<double>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid,
+                                 p->d_spec64, p->d_efie_freq, 4 * nrhs, p->d_tw64, s, nullptr,
+                                 p->sched[0]);
     aim::launch_convolve<double>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid,
                                  p->d_dlp_spec, p->d_mfie_freq, 6 * nrhs, p->d_tw64, s, nullptr,
                                  p->sched[0]);
     aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, true, s);
     aim::CsrDevice none{};
     none.n = P;
+    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_efie_grid, nullptr,
+                                    p->d_efie_src, 4 * nrhs, true, false, s);
     aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
-                                    p->d_efie_src, 3 * nrhs, true, false, s);
-    aim::launch_mfie_test(p->d_efie_src, p->d_efie_vals, p->d_mfie_nrm, p->d_efie_te,
-                          p->d_efie_rowptr, p->d_efie_col, p->d_mfie_ck, gram_coef, x, y, N, n,
-                          nrhs, s);
+                                    p->d_cfie_psi, 3 * nrhs, true, false, s);
+    aim::launch_rwg_test(true, true, p->d_efie_src, p->d_cfie_psi, p->d_efie_vals,
+                         p->d_mfie_nrm, p->d_efie_te, p->d_efie_rowptr, p->d_efie_col,
+                         p->d_efie_cc, p->d_mfie_ck, gram_coef, p->d_k, p->d_efie_freq, x, y, N,
+                         n, nrhs, s);
   });
 }
 

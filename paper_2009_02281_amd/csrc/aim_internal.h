@@ -255,11 +255,6 @@ void launch_dlp_combine(const GridShape& g, const void* grids, void* phi, int nr
 // k_r = kv[rhs_freq[r]] and cc [nnz][2] = (C_A, C_phi) interleaved
 void launch_efie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
-void launch_efie_test(const void* psi, const double* vals, const int32_t* rwg_te,
-                      const int32_t* rowptr, const int32_t* col, const double* cc,
-                      const double* kv, const int32_t* rhs_freq, const void* x, void* y,
-                      int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
-
 // RWG double layer, complex128: the three current channels of x at the
 // points (src[a][r][p], as launch_efie_sources without the charge); the
 // grid moments M = (u - c) x J (combine false: grids [3 nrhs, 6 nrhs) from
@@ -269,11 +264,16 @@ void launch_efie_test(const void* psi, const double* vals, const int32_t* rwg_te
 // near row of (C_K + beta G), ck [nnz][2] = (C_K, G) interleaved
 void launch_mfie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
-void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s);
-void launch_mfie_test(const void* psi, const double* vals, const double* nrm,
-                      const int32_t* rwg_te, const int32_t* rowptr, const int32_t* col,
-                      const double* ck, double beta, const void* x, void* y, int64_t N,
-                      int64_t nrwg, int nrhs, hipStream_t s);
+void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s,
+                         const void* j_in = nullptr);  // currents from other grids (copied)
+// y for the EFIE (efie), the double layer (mfie) or the combined field of
+// eq. CFIEAIMx (both: y = y_E - (j/k_r) y_M), from psi_e [4][nrhs][3N] and
+// psi_m [3][nrhs][3N]; cc = (C_A, C_phi), ck = (C_K, G) interleaved
+void launch_rwg_test(bool efie, bool mfie, const void* psi_e, const void* psi_m,
+                     const double* vals, const double* nrm, const int32_t* rwg_te,
+                     const int32_t* rowptr, const int32_t* col, const double* cc,
+                     const double* ck, double beta, const double* kv, const int32_t* rhs_freq,
+                     const void* x, void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
 
 void launch_excitation(int kind, const double* qp_xyz, const double* qp_w, int64_t n,
                        const double* params, int n_params, const double* kvals,

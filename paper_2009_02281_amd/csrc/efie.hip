@@ -64,99 +64,27 @@ __global__ __launch_bounds__(256) void efie_sources_kernel(
   }
 }
 
-// y[r][n]: the function's channel values at the six points of its triangles
-// against the interpolated potentials (current channels minus k^-2 times the
-// charge channel), plus its near-list row of C_A - k^-2 C_phi.  LPR lanes
-// per function: lanes 0..5 take one point each (T+ then T-, three points
-// each), every lane strides over the near row; a fixed butterfly across the
-// LPR lanes sums them.  RB right-hand sides per workgroup, so each near entry
-// and channel value is loaded once for all of them.
-template <int LPR, int RB>
-__global__ __launch_bounds__(256) void efie_test_kernel(
-    const double2* __restrict__ psi, const double* __restrict__ vals,
-    const int32_t* __restrict__ rwg_te, const int32_t* __restrict__ rowptr,
-    const int32_t* __restrict__ col, const double2* __restrict__ cc,
-    const double* __restrict__ kv, const int32_t* __restrict__ rhs_freq,
-    const double2* __restrict__ x, double2* __restrict__ y, int64_t N, int64_t nrwg, int nrhs) {
-  const int sub = threadIdx.x % LPR;
-  const int64_t n = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
-  const int r0 = int(blockIdx.y) * RB;
-  const int nr = min(RB, nrhs - r0);
-  const int64_t P = 3 * N;
-  const int64_t cs = int64_t(nrhs) * P;  // channel stride of psi
-  double ar[RB], ai[RB], qr[RB], qi[RB];
-#pragma unroll
-  for (int j = 0; j < RB; ++j) ar[j] = ai[j] = qr[j] = qi[j] = 0.0;
-  if (n < nrwg) {
-    if (sub < 6) {
-      const int side = sub >= 3 ? 1 : 0, q = sub - 3 * side;
-      const int64_t t = rwg_te[4 * n + 2 * side];
-      const int e = rwg_te[4 * n + 2 * side + 1];
-      const double* v = vals + 36 * t + 12 * q + 4 * e;
-      const double v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
-      const double2* base = psi + int64_t(r0) * P + 3 * t + q;
-#pragma unroll
-      for (int j = 0; j < RB; ++j)
-        if (j < nr) {
-          const double2* b = base + int64_t(j) * P;
-          const double2 p0 = b[0], p1 = b[cs], p2 = b[2 * cs], p3 = b[3 * cs];
-          ar[j] = v0 * p0.x + v1 * p1.x + v2 * p2.x;
-          ai[j] = v0 * p0.y + v1 * p1.y + v2 * p2.y;
-          qr[j] = v3 * p3.x;
-          qi[j] = v3 * p3.y;
-        }
-    }
-    const double2* xr = x + int64_t(r0) * nrwg;
-    for (int32_t k = rowptr[n] + sub; k < rowptr[n + 1]; k += LPR) {
-      const double2 c = cc[k];
-      const int64_t m = col[k];
-#pragma unroll
-      for (int j = 0; j < RB; ++j)
-        if (j < nr) {
-          const double2 xv = xr[int64_t(j) * nrwg + m];
-          ar[j] += c.x * xv.x;
-          ai[j] += c.x * xv.y;
-          qr[j] += c.y * xv.x;
-          qi[j] += c.y * xv.y;
-        }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < RB; ++j)
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) {
-      ar[j] += __shfl_xor(ar[j], o, LPR);
-      ai[j] += __shfl_xor(ai[j], o, LPR);
-      qr[j] += __shfl_xor(qr[j], o, LPR);
-      qi[j] += __shfl_xor(qi[j], o, LPR);
-    }
-  if (sub == 0 && n < nrwg) {
-#pragma unroll
-    for (int j = 0; j < RB; ++j)
-      if (j < nr) {
-        const double k = kv[rhs_freq[r0 + j]];
-        const double ik2 = 1.0 / (k * k);
-        y[int64_t(r0 + j) * nrwg + n] = make_double2(ar[j] - ik2 * qr[j], ai[j] - ik2 * qi[j]);
-      }
-  }
-}
-
 // The double layer's grid stages (Sec. III-B, eq. KAIMx) in grid index
 // units about the grid centre c: with the radial factor F of the kernel
 // spectrum, grad G(r_u - r_v) = -(u - v) F(u - v), so the field
 // V(u) = sum_v grad G(r_u - r_v) x J(v) is -[(u - c) x (F * J)(u) - (F * M)(u)]
 // with the moments M(v) = (v - c) x J(v).  Grids: J_a of vector r at
 // a nrhs + r, M_a at (3 + a) nrhs + r; V overwrites J.
-__global__ __launch_bounds__(256) void mfie_moments_kernel(double2* __restrict__ g, int Nx, int Ny,
-                                                           int64_t Ng, int nrhs, double cx,
-                                                           double cy, double cz) {
+__global__ __launch_bounds__(256) void mfie_moments_kernel(const double2* j_in, double2* g, int Nx,
+                                                           int Ny, int64_t Ng, int nrhs,
+                                                           double cx, double cy, double cz) {
   const int r = blockIdx.y;
   for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
        u += int64_t(gridDim.x) * blockDim.x) {
     const double dx = double(u % Nx) - cx, dy = double((u / Nx) % Ny) - cy,
                  dz = double(u / (int64_t(Nx) * Ny)) - cz;
-    const double2 jx = g[int64_t(r) * Ng + u], jy = g[int64_t(nrhs + r) * Ng + u],
-                  jz = g[int64_t(2 * nrhs + r) * Ng + u];
+    const double2 jx = j_in[int64_t(r) * Ng + u], jy = j_in[int64_t(nrhs + r) * Ng + u],
+                  jz = j_in[int64_t(2 * nrhs + r) * Ng + u];
+    if (j_in != g) {  // the currents come from another set of grids: copy them
+      g[int64_t(r) * Ng + u] = jx;
+      g[int64_t(nrhs + r) * Ng + u] = jy;
+      g[int64_t(2 * nrhs + r) * Ng + u] = jz;
+    }
     g[int64_t(3 * nrhs + r) * Ng + u] = make_double2(dy * jz.x - dz * jy.x, dy * jz.y - dz * jy.y);
     g[int64_t(4 * nrhs + r) * Ng + u] = make_double2(dz * jx.x - dx * jz.x, dz * jx.y - dx * jz.y);
     g[int64_t(5 * nrhs + r) * Ng + u] = make_double2(dx * jy.x - dy * jx.x, dx * jy.y - dy * jx.y);
@@ -183,55 +111,91 @@ __global__ __launch_bounds__(256) void mfie_combine_kernel(double2* __restrict__
   }
 }
 
-// y[r][m]: t_q . V(r_q) over the six points of the function, t_q =
-// w_q f_m(r_q) x n of its triangle, plus its near row of C_K + beta G.
-// Lanes as in efie_test_kernel.
-template <int LPR, int RB>
-__global__ __launch_bounds__(256) void mfie_test_kernel(
-    const double2* __restrict__ psi, const double* __restrict__ vals,
-    const double* __restrict__ nrm, const int32_t* __restrict__ rwg_te,
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const double2* __restrict__ ck, double beta, const double2* __restrict__ x,
-    double2* __restrict__ y, int64_t N, int64_t nrwg, int nrhs) {
+// y[r][n] for the EFIE (E), the double layer (M) or their combination of
+// eq. CFIEAIMx (both): over the six points of the function (T+ then T-,
+// three points each) its channel values against the interpolated fields --
+// EFIE: sum_c (w f_c) psi_c - k^-2 (w div f) psi_q; double layer:
+// (w f x n) . V -- plus its near row: (C_A - k^-2 C_phi) x and
+// (C_K + beta G) x.  Combined: y = y_E - (j/k) y_M.  LPR lanes per function:
+// lanes 0..5 take one point each, every lane strides over the near row, a
+// fixed butterfly sums them (fixed order: deterministic).  RB right-hand
+// sides per workgroup, so each near entry and channel value is loaded once.
+template <int LPR, int RB, bool E, bool M>
+__global__ __launch_bounds__(256) void rwg_test_kernel(
+    const double2* __restrict__ psi_e, const double2* __restrict__ psi_m,
+    const double* __restrict__ vals, const double* __restrict__ nrm,
+    const int32_t* __restrict__ rwg_te, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ col, const double2* __restrict__ cc,
+    const double2* __restrict__ ck, double beta, const double* __restrict__ kv,
+    const int32_t* __restrict__ rhs_freq, const double2* __restrict__ x, double2* __restrict__ y,
+    int64_t N, int64_t nrwg, int nrhs) {
   const int sub = threadIdx.x % LPR;
   const int64_t n = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
   const int r0 = int(blockIdx.y) * RB;
   const int nr = min(RB, nrhs - r0);
   const int64_t P = 3 * N;
-  const int64_t cs = int64_t(nrhs) * P;
-  double yr[RB], yi[RB];
+  const int64_t cs = int64_t(nrhs) * P;  // channel stride of psi_e and psi_m
+  double ar[RB], ai[RB], qr[RB], qi[RB], mr[RB], mi[RB];
 #pragma unroll
-  for (int j = 0; j < RB; ++j) yr[j] = yi[j] = 0.0;
+  for (int j = 0; j < RB; ++j) ar[j] = ai[j] = qr[j] = qi[j] = mr[j] = mi[j] = 0.0;
   if (n < nrwg) {
     if (sub < 6) {
       const int side = sub >= 3 ? 1 : 0, q = sub - 3 * side;
       const int64_t t = rwg_te[4 * n + 2 * side];
       const int e = rwg_te[4 * n + 2 * side + 1];
       const double* v = vals + 36 * t + 12 * q + 4 * e;
-      const double* nn = nrm + 3 * t;
-      const double t0 = v[1] * nn[2] - v[2] * nn[1], t1 = v[2] * nn[0] - v[0] * nn[2],
-                   t2 = v[0] * nn[1] - v[1] * nn[0];
-      const double2* base = psi + int64_t(r0) * P + 3 * t + q;
+      const double v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+      const int64_t off = int64_t(r0) * P + 3 * t + q;
+      if constexpr (E) {
 #pragma unroll
-      for (int j = 0; j < RB; ++j)
-        if (j < nr) {
-          const double2* b = base + int64_t(j) * P;
-          const double2 p0 = b[0], p1 = b[cs], p2 = b[2 * cs];
-          yr[j] = t0 * p0.x + t1 * p1.x + t2 * p2.x;
-          yi[j] = t0 * p0.y + t1 * p1.y + t2 * p2.y;
-        }
+        for (int j = 0; j < RB; ++j)
+          if (j < nr) {
+            const double2* b = psi_e + off + int64_t(j) * P;
+            const double2 p0 = b[0], p1 = b[cs], p2 = b[2 * cs], p3 = b[3 * cs];
+            ar[j] = v0 * p0.x + v1 * p1.x + v2 * p2.x;
+            ai[j] = v0 * p0.y + v1 * p1.y + v2 * p2.y;
+            qr[j] = v3 * p3.x;
+            qi[j] = v3 * p3.y;
+          }
+      }
+      if constexpr (M) {
+        const double* nn = nrm + 3 * t;
+        const double t0 = v1 * nn[2] - v2 * nn[1], t1 = v2 * nn[0] - v0 * nn[2],
+                     t2 = v0 * nn[1] - v1 * nn[0];
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+          if (j < nr) {
+            const double2* b = psi_m + off + int64_t(j) * P;
+            const double2 p0 = b[0], p1 = b[cs], p2 = b[2 * cs];
+            mr[j] = t0 * p0.x + t1 * p1.x + t2 * p2.x;
+            mi[j] = t0 * p0.y + t1 * p1.y + t2 * p2.y;
+          }
+      }
     }
     const double2* xr = x + int64_t(r0) * nrwg;
     for (int32_t k = rowptr[n] + sub; k < rowptr[n + 1]; k += LPR) {
-      const double2 c = ck[k];
-      const double w = c.x + beta * c.y;
       const int64_t m = col[k];
+      double2 c = make_double2(0.0, 0.0);
+      double w = 0.0;
+      if constexpr (E) c = cc[k];
+      if constexpr (M) {
+        const double2 d = ck[k];
+        w = d.x + beta * d.y;
+      }
 #pragma unroll
       for (int j = 0; j < RB; ++j)
         if (j < nr) {
           const double2 xv = xr[int64_t(j) * nrwg + m];
-          yr[j] += w * xv.x;
-          yi[j] += w * xv.y;
+          if constexpr (E) {
+            ar[j] += c.x * xv.x;
+            ai[j] += c.x * xv.y;
+            qr[j] += c.y * xv.x;
+            qi[j] += c.y * xv.y;
+          }
+          if constexpr (M) {
+            mr[j] += w * xv.x;
+            mi[j] += w * xv.y;
+          }
         }
     }
   }
@@ -239,13 +203,38 @@ __global__ __launch_bounds__(256) void mfie_test_kernel(
   for (int j = 0; j < RB; ++j)
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) {
-      yr[j] += __shfl_xor(yr[j], o, LPR);
-      yi[j] += __shfl_xor(yi[j], o, LPR);
+      if constexpr (E) {
+        ar[j] += __shfl_xor(ar[j], o, LPR);
+        ai[j] += __shfl_xor(ai[j], o, LPR);
+        qr[j] += __shfl_xor(qr[j], o, LPR);
+        qi[j] += __shfl_xor(qi[j], o, LPR);
+      }
+      if constexpr (M) {
+        mr[j] += __shfl_xor(mr[j], o, LPR);
+        mi[j] += __shfl_xor(mi[j], o, LPR);
+      }
     }
   if (sub == 0 && n < nrwg) {
 #pragma unroll
     for (int j = 0; j < RB; ++j)
-      if (j < nr) y[int64_t(r0 + j) * nrwg + n] = make_double2(yr[j], yi[j]);
+      if (j < nr) {
+        double yr = 0.0, yi = 0.0;
+        if constexpr (E) {
+          const double k = kv[rhs_freq[r0 + j]];
+          const double ik2 = 1.0 / (k * k);
+          yr = ar[j] - ik2 * qr[j];
+          yi = ai[j] - ik2 * qi[j];
+          if constexpr (M) {  // - (j/k)(mr + j mi) = (mi - j mr)/k
+            const double ik = 1.0 / k;
+            yr += ik * mi[j];
+            yi -= ik * mr[j];
+          }
+        } else {
+          yr = mr[j];
+          yi = mi[j];
+        }
+        y[int64_t(r0 + j) * nrwg + n] = make_double2(yr, yi);
+      }
   }
 }
 
@@ -259,42 +248,17 @@ void launch_mfie_sources(const void* x, const double* vals, const int32_t* tri_r
   AIM_HIP(hipGetLastError());
 }
 
-void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s) {
+void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s,
+                         const void* j_in) {
   const double cx = 0.5 * (g.N[0] - 1), cy = 0.5 * (g.N[1] - 1), cz = 0.5 * (g.N[2] - 1);
   double2* gp = static_cast<double2*>(grids);
+  const double2* jp = j_in ? static_cast<const double2*>(j_in) : gp;
   if (combine)
     hipLaunchKernelGGL(mfie_combine_kernel, dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s, gp,
                        g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
   else
-    hipLaunchKernelGGL(mfie_moments_kernel, dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s, gp,
-                       g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
-  AIM_HIP(hipGetLastError());
-}
-
-void launch_mfie_test(const void* psi, const double* vals, const double* nrm,
-                      const int32_t* rwg_te, const int32_t* rowptr, const int32_t* col,
-                      const double* ck, double beta, const void* x, void* y, int64_t N,
-                      int64_t nrwg, int nrhs, hipStream_t s) {
-  if (nrwg == 0) return;
-  constexpr int LPR = 16;
-  const int64_t gx = (nrwg * LPR + 255) / 256;
-  int rb = 1;
-  while (rb < 8 && 2 * rb <= nrhs && gx * ((nrhs + 2 * rb - 1) / (2 * rb)) >= 1024) rb *= 2;
-  const dim3 grid(unsigned(gx), unsigned((nrhs + rb - 1) / rb));
-  const double2* ps = static_cast<const double2*>(psi);
-  const double2* c2 = reinterpret_cast<const double2*>(ck);
-  const double2* xi = static_cast<const double2*>(x);
-  double2* yo = static_cast<double2*>(y);
-#define AIM_MFIE_TEST(R)                                                                       \
-  hipLaunchKernelGGL((mfie_test_kernel<LPR, R>), grid, dim3(256), 0, s, ps, vals, nrm, rwg_te, \
-                     rowptr, col, c2, beta, xi, yo, N, nrwg, nrhs)
-  switch (rb) {
-    case 1: AIM_MFIE_TEST(1); break;
-    case 2: AIM_MFIE_TEST(2); break;
-    case 4: AIM_MFIE_TEST(4); break;
-    default: AIM_MFIE_TEST(8); break;
-  }
-#undef AIM_MFIE_TEST
+    hipLaunchKernelGGL(mfie_moments_kernel, dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s, jp,
+                       gp, g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
   AIM_HIP(hipGetLastError());
 }
 
@@ -306,31 +270,41 @@ void launch_efie_sources(const void* x, const double* vals, const int32_t* tri_r
   AIM_HIP(hipGetLastError());
 }
 
-void launch_efie_test(const void* psi, const double* vals, const int32_t* rwg_te,
-                      const int32_t* rowptr, const int32_t* col, const double* cc,
-                      const double* kv, const int32_t* rhs_freq, const void* x, void* y,
-                      int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
+void launch_rwg_test(bool efie, bool mfie, const void* psi_e, const void* psi_m,
+                     const double* vals, const double* nrm, const int32_t* rwg_te,
+                     const int32_t* rowptr, const int32_t* col, const double* cc,
+                     const double* ck, double beta, const double* kv, const int32_t* rhs_freq,
+                     const void* x, void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
   if (nrwg == 0) return;
+  AIM_REQUIRE(efie || mfie, AIM_ERR_INVALID_ARG, "no operator selected");
   constexpr int LPR = 16;
   const int64_t gx = (nrwg * LPR + 255) / 256;
   // several right-hand sides per workgroup while 1024 workgroups remain
   int rb = 1;
   while (rb < 8 && 2 * rb <= nrhs && gx * ((nrhs + 2 * rb - 1) / (2 * rb)) >= 1024) rb *= 2;
   const dim3 grid(unsigned(gx), unsigned((nrhs + rb - 1) / rb));
-  const double2* ps = static_cast<const double2*>(psi);
+  const double2* pe = static_cast<const double2*>(psi_e);
+  const double2* pm = static_cast<const double2*>(psi_m);
   const double2* c2 = reinterpret_cast<const double2*>(cc);
+  const double2* k2 = reinterpret_cast<const double2*>(ck);
   const double2* xi = static_cast<const double2*>(x);
   double2* yo = static_cast<double2*>(y);
-#define AIM_EFIE_TEST(R)                                                                       \
-  hipLaunchKernelGGL((efie_test_kernel<LPR, R>), grid, dim3(256), 0, s, ps, vals, rwg_te,     \
-                     rowptr, col, c2, kv, rhs_freq, xi, yo, N, nrwg, nrhs)
-  switch (rb) {
-    case 1: AIM_EFIE_TEST(1); break;
-    case 2: AIM_EFIE_TEST(2); break;
-    case 4: AIM_EFIE_TEST(4); break;
-    default: AIM_EFIE_TEST(8); break;
+#define AIM_RWG_TEST(R, E, M)                                                                  \
+  hipLaunchKernelGGL((rwg_test_kernel<LPR, R, E, M>), grid, dim3(256), 0, s, pe, pm, vals,    \
+                     nrm, rwg_te, rowptr, col, c2, k2, beta, kv, rhs_freq, xi, yo, N, nrwg,   \
+                     nrhs)
+#define AIM_RWG_RB(E, M)                      \
+  switch (rb) {                               \
+    case 1: AIM_RWG_TEST(1, E, M); break;     \
+    case 2: AIM_RWG_TEST(2, E, M); break;     \
+    case 4: AIM_RWG_TEST(4, E, M); break;     \
+    default: AIM_RWG_TEST(8, E, M); break;    \
   }
-#undef AIM_EFIE_TEST
+  if (efie && mfie) AIM_RWG_RB(true, true)
+  else if (efie) AIM_RWG_RB(true, false)
+  else AIM_RWG_RB(false, true)
+#undef AIM_RWG_RB
+#undef AIM_RWG_TEST
   AIM_HIP(hipGetLastError());
 }
 

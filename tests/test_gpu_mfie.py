@@ -108,6 +108,35 @@ def test_large_sphere_sampled_rows():
     p.close()
 
 
+def test_combined_field_operator():
+    """eq. CFIEAIMx: Z x - (j/k)(K + beta G) x from one call, against the two
+    oracles on sampled rows, several vectors at two wavenumbers."""
+    w = I.sphere_tiny(level=2, dims=(16, 16, 16), h=0.1)
+    ks = [2 * math.pi, 8.5]
+    print("[gpu] combined field, sphere-320", flush=True)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    e = efie.EfieOracle(o)
+    m = mfie.MfieOracle(e)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, ks,
+                     max_rhs=3, precisions=("c128",))
+    x = I.complex_gaussian(m.n, 76, nrhs=3)
+    freq = [1, 0, 1]
+    y = p.matvec_cfie(torch.from_numpy(x).cuda(), freq_idx=freq, gram_coef=-0.5).cpu().numpy()
+    rows = np.arange(0, m.n, 6)
+    for r in range(3):
+        k = ks[freq[r]]
+        ref = e.matvec_rows(x[r], k, rows) - 1j / k * m.matvec_rows(x[r], k, rows, -0.5)
+        assert np.max(np.abs(y[r][rows] - ref)) <= TOL_Y * np.max(np.abs(ref)), r
+    # the separate operators' calls agree with the combined one on every row
+    xe = torch.from_numpy(x).cuda()
+    ye = p.matvec_efie(xe, freq_idx=freq).cpu().numpy()
+    ym = p.matvec_mfie(xe, freq_idx=freq, gram_coef=-0.5).cpu().numpy()
+    kk = np.array([ks[f] for f in freq])[:, None]
+    comb = ye - 1j / kk * ym
+    assert np.max(np.abs(y - comb)) <= 1e-13 * np.max(np.abs(comb))
+    p.close()
+
+
 def test_needs_the_mesh(tmp_path):
     w = I.sphere_tiny()
     p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
