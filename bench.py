@@ -85,9 +85,10 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str, prec: str):
+def load_traffic(kernel: str, workload: str, prec: str, schedule=None):
     """HBM bytes per launch from the committed rocprofv3 counter runs, only if
-    they were taken on the current kernel source."""
+    they were taken on the current kernel source and, for an FFT pass, with
+    the same launch shape of that pass and the same workspace layout."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -96,6 +97,12 @@ def load_traffic(kernel: str, workload: str, prec: str):
     ent = rec.get(f"{workload}/{prec}/{kernel}")
     if not ent or ent.get("kernel_sha") != kernel_sha():
         return None
+    passes = ["fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv"]
+    if kernel in passes and schedule is not None:
+        k = passes.index(kernel)
+        for taken in (ent.get("schedule"), ent.get("schedule_write")):
+            if taken is None or taken[k] != schedule[k] or taken[5] != schedule[5]:
+                return None
     return ent.get("bytes_per_launch")
 
 
@@ -913,7 +920,8 @@ def main() -> int:
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": load_traffic(dom, w.name, args.prec),
+                           "traffic": load_traffic(dom, w.name, args.prec,
+                                                   out["fft_schedule"].get(args.prec)),
                            "copy_measured_gbs": copy_bandwidth()["gbs"]}
         out["stages"] = stages
         out["matvec_alg_gbs"] = total_b / (ms * 1e-3) / 1e9

@@ -1544,7 +1544,9 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
         }
         double total = 0.0;
         for (int k = 0; k < 5; ++k) total += lbest[k];
-        if (total < best_total) {
+        // a later layout has to be 2% faster to win: layouts within timing
+        // noise of each other keep the earlier one, so repeated tunings agree
+        if (total < (layout == 0 ? 1.0 : 0.98) * best_total) {
           best_total = total;
           for (int k = 0; k < 5; ++k) {
             best[k] = lbest[k];
