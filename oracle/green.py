@@ -92,6 +92,43 @@ def interpolation_bound(theta0: float, thetan: float, n: int, samples: int = 200
     return (thetan - theta0) ** (n + 1) / math.factorial(n + 1) * dmax
 
 
+def grad_dynamic_theta(theta):
+    """The radial factor of grad G_d in the normalised coordinate theta = k r:
+    grad G_d(k, r) = k^2 r^ f(theta), f(theta) = -[(1 + j theta) e^{-j theta} - 1]
+    / (4 pi theta^2) (eqs. ghgf and ghgfd); its limit at 0 is -1/(8 pi)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    out = np.empty(theta.shape, dtype=np.complex128)
+    zero = theta == 0.0
+    t = np.where(zero, 1.0, theta)
+    val = -((1.0 + 1j * t) * np.exp(-1j * t) - 1.0) / (FOUR_PI * t * t)
+    out[...] = np.where(zero, -1.0 / (2.0 * FOUR_PI), val)
+    return out
+
+
+def grad_dynamic_theta_derivative(theta, m: int):
+    """m-th derivative of f (eq. Dghgf with m = n+1): Leibniz' rule on
+    u(theta) theta^{-2} with u = (1 + j theta) e^{-j theta} - 1, whose l-th
+    derivative is -delta_l + (-j)^l e^{-j theta} (1 + j theta - l), and
+    (theta^{-2})^{(m-l)} = (-m-1+l)_{m-l} theta^{-(m+2-l)} (Pochhammer)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    e = np.exp(-1j * theta)
+    acc = np.zeros(theta.shape, dtype=np.complex128)
+    for l in range(m + 1):
+        a, poch = -m - 1 + l, 1.0
+        for i in range(m - l):
+            poch *= a + i
+        ul = (-1j) ** l * e * (1.0 + 1j * theta - l) - (1.0 if l == 0 else 0.0)
+        acc = acc + math.comb(m, l) * poch / theta ** (m + 2 - l) * ul
+    return -acc / FOUR_PI
+
+
+def grad_interpolation_bound(theta0: float, thetan: float, n: int, samples: int = 2001):
+    """B_n of eq. Lbounds for the radial factor of grad G_d."""
+    xi = np.linspace(theta0, thetan, samples)
+    dmax = np.max(np.abs(grad_dynamic_theta_derivative(xi, n + 1)))
+    return (thetan - theta0) ** (n + 1) / math.factorial(n + 1) * dmax
+
+
 def lagrange_interpolate(xs, fs, x):
     """Lagrange polynomial through (xs[q], fs[q]) evaluated at x
     (the interpolant of Sec. IV-A)."""

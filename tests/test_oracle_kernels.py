@@ -104,6 +104,56 @@ def test_interpolation_error_below_bound(spl):
     assert worst < {10: 2e-3, 20: 3e-4, 30: 1e-4}[spl]
 
 
+# -- the same analysis for grad G_d (Sec. IV-A, eq. Dghgf)
+
+def test_grad_dynamic_factor_and_its_derivatives():
+    """f(theta) of grad G_d = k^2 r^ f(k r) against the full gradient minus the
+    static one, its limit at 0, and eq. Dghgf against arbitrary-precision
+    differentiation (mpmath, 40 digits)."""
+    mpmath = pytest.importorskip("mpmath")
+    k = 3.7
+    for r in (0.01, 0.3, 1.7):
+        th = k * r
+        full = -(1 + 1j * k * r) * np.exp(-1j * k * r) / (4 * math.pi * r * r)
+        static = -1.0 / (4 * math.pi * r * r)
+        assert k * k * complex(green.grad_dynamic_theta(th)) == pytest.approx(full - static,
+                                                                               rel=1e-9)
+    small = complex(green.grad_dynamic_theta(1e-3))   # -1/(8 pi) + j theta/(12 pi) + ...
+    assert small.real == pytest.approx(-1 / (8 * math.pi), rel=1e-5)
+    assert small.imag == pytest.approx(1e-3 / (12 * math.pi), rel=1e-2)
+    mpmath.mp.dps = 40
+
+    def f(t):
+        return -((1 + 1j * t) * mpmath.exp(-1j * t) - 1) / (4 * mpmath.pi * t * t)
+    for m in (1, 2, 3, 4):
+        for th in (0.4, 1.3, 5.0, 11.0):
+            ref = complex(mpmath.diff(f, mpmath.mpf(th), m))
+            got = complex(green.grad_dynamic_theta_derivative(th, m))
+            assert abs(got - ref) <= 1e-9 * abs(ref), (m, th)
+
+
+@pytest.mark.parametrize("spl", [10, 20, 30])
+def test_grad_interpolation_error_below_bound(spl):
+    """Lagrange interpolation of grad G_d's radial factor on n+1 samples at
+    ``spl`` samples per wavelength stays below B_n (eq. Dghgf in eq. Lbounds),
+    also inside the near region, and shrinks with refinement (Sec. IV-A)."""
+    n = 2
+    dth = 2 * math.pi / spl
+    worst = 0.0
+    for theta in np.linspace(0.05, 3 * math.pi, 240):
+        s0 = math.floor(theta / dth - (n - 1) / 2.0)
+        xs = dth * (s0 + np.arange(n + 1))
+        if xs[0] <= 0:
+            xs = xs - xs[0] + 1e-3 * dth
+        fs = green.grad_dynamic_theta(xs)
+        err = abs(green.lagrange_interpolate(xs, fs, theta) - green.grad_dynamic_theta(theta))
+        lo, hi = min(xs[0], theta), max(xs[-1], theta)
+        assert err <= green.grad_interpolation_bound(lo, hi, n, samples=201)
+        worst = max(worst, err)
+    print(f"grad G_d interpolation, {spl} samples per wavelength: worst {worst:.2e}")
+    assert worst < {10: 5e-4, 20: 1e-4, 30: 3e-5}[spl]
+
+
 # -- quadrature
 
 def test_three_point_rule_exact_to_degree_two():
