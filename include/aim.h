@@ -502,8 +502,10 @@ aim_status aim_graph_destroy(aim_graph graph);  /* NULL is a no-op */
  * every transform length), then the layout of the convolution workspace
  * (0 .. AIM_FFT_LAYOUTS-1: 0, 1, 4 or 12 KiB of padding after every z plane,
  * which keeps the strided z lines from falling on one memory channel), then
- * the interpolation mode (0: the assembled P^T; 1: the weights of P^T
- * recomputed from the quadrature points' stencil coordinates). */
+ * the stage modes 0..3: bit 0 the interpolation (0: the assembled P^T; 1:
+ * the weights of P^T recomputed from the quadrature points' stencil
+ * coordinates), bit 1 the projection (0: its own kernel writing the grid q;
+ * 1: computed inside the x forward FFT pass, so q never goes to memory). */
 #define AIM_FFT_SHAPES 12
 #define AIM_FFT_LAYOUTS 4
 #define AIM_SCHEDULE_LEN 7
@@ -514,7 +516,7 @@ aim_status aim_graph_destroy(aim_graph graph);  /* NULL is a no-op */
  * shape (lines per workgroup x threads per line) of each pass over `reps`
  * runs with nrhs right-hand sides on hip_stream and keeps the layout with
  * the smallest sum of per-pass best times and those shapes; then times whole
- * matvecs in both interpolation modes and keeps the faster.  The schedule is stored in the
+ * matvecs in the four stage modes and keeps the fastest.  The schedule is stored in the
  * plan for this precision and returned in sched_out[AIM_SCHEDULE_LEN], the
  * chosen passes' average times (ms) in pass_ms_out[5] (either may be NULL).
  * Overwrites the plan's internal grid workspace; allocates and frees two

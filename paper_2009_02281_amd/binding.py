@@ -24,7 +24,7 @@ PC = {"none": 0, "diag": 1, "nearblock": 2, "unet": 3, "nearblock_static": 4}
 LOSS = {"error": 0, "residual": 1}
 FFT_SHAPES = 12         # AIM_FFT_SHAPES
 FFT_LAYOUTS = 4         # AIM_FFT_LAYOUTS
-SCHEDULE_LEN = 7        # AIM_SCHEDULE_LEN: five pass shapes, the layout, the interpolation mode
+SCHEDULE_LEN = 7        # AIM_SCHEDULE_LEN: five pass shapes, the layout, the stage modes
 STAGE = {"project": 0, "convolve": 1, "interpolate": 2, "near": 3, "learned_pc": 4,
          "nearblock_pc": 5}
 RHS = {"plane_wave": 0, "gaussian_patch": 1}
@@ -762,7 +762,7 @@ class Plan:
         With ``cache_path`` a JSON file keyed by (grid, precision, nrhs,
         gfx950) is read first and updated after tuning."""
         import json
-        key = f"gfx950|{'x'.join(map(str, self.dims))}|{prec}|nrhs={nrhs}|s{SCHEDULE_LEN}"
+        key = f"gfx950|{'x'.join(map(str, self.dims))}|{prec}|nrhs={nrhs}|s{SCHEDULE_LEN}m4"
         cache = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as f:

@@ -332,7 +332,7 @@ aim::QpDevice qp_dev(aim_plan p, aim_precision prec) {
 template <typename T>
 void interp_near(aim_plan p, aim_precision prec, const void* phi, const void* x, void* y,
                  int nrhs, bool do_interp, bool do_near, hipStream_t s, int mode = -1) {
-  if (mode < 0) mode = p->sched[int(prec)][6];
+  if (mode < 0) mode = p->sched[int(prec)][6] & aim::kModeImplicitInterp;
   if (do_interp && mode == 1)
     aim::launch_interp_implicit<T>(p->g, qp_dev(p, prec), csr_dev(p, prec), phi, x, y, nrhs,
                                    do_near, s);
@@ -392,12 +392,17 @@ void matvec_impl(aim_plan p, aim_precision prec, const void* x, void* y, int nrh
   if (!work) work = p->d_work[pi];
   const void* spec = prec == AIM_C128 ? p->d_spec64 : p->d_spec32;
   void* const* tw = prec == AIM_C128 ? p->d_tw64 : p->d_tw32;
+  // the projection runs on its own, or inside the x forward pass (stage mode
+  // bit 1; its time then counts in that pass)
+  const bool fused = (p->sched[pi][6] & aim::kModeFusedProject) != 0;
+  const aim::CsrDevice P = p_dev(p, prec);
   if (ev) AIM_HIP(hipEventRecord(ev[0], s));
-  for (int r = 0; r < repeat; ++r)
-    aim::launch_project<T>(p->g, p_dev(p, prec), p->d_pblk, p->nblk, x, p->t.N, grid, nrhs, s);
+  for (int r = 0; r < repeat && !fused; ++r)
+    aim::launch_project<T>(p->g, P, p->d_pblk, p->nblk, x, p->t.N, grid, nrhs, s);
   if (ev) AIM_HIP(hipEventRecord(ev[1], s));
   aim::launch_convolve<T>(p->g, grid, work, grid, spec, dfreq, nrhs, tw, s,
-                          ev ? ev + 2 : nullptr, p->sched[pi], repeat);
+                          ev ? ev + 2 : nullptr, p->sched[pi], repeat, fused ? &P : nullptr, x,
+                          p->t.N);
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
   for (int r = 0; r < repeat; ++r) interp_near<T>(p, prec, grid, x, y, nrhs, true, near, s);
   if (near && p->lin_on) aim::launch_lin_term<T>(p->d_lin, p->d_k, dfreq, x, y, p->t.N, nrhs, s);
@@ -1454,8 +1459,8 @@ aim_status aim_set_schedule(aim_plan p, aim_precision prec, const int32_t* sched
                   AIM_ERR_INVALID_ARG, "launch shape not available for this pass");
     AIM_REQUIRE(sched[5] >= 0 && sched[5] < aim::kLayouts, AIM_ERR_INVALID_ARG,
                 "workspace layout out of range");
-    AIM_REQUIRE(sched[6] == 0 || sched[6] == 1, AIM_ERR_INVALID_ARG,
-                "interpolation mode must be 0 or 1");
+    AIM_REQUIRE(sched[6] >= 0 && sched[6] <= 3, AIM_ERR_INVALID_ARG,
+                "stage modes must be in 0..3");
     for (int k = 0; k < aim::kSchedLen; ++k) p->sched[int(prec)][k] = sched[k];
     p->graphs.clear();
   });
@@ -1568,16 +1573,18 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
       void* xy = nullptr;
       AIM_HIP(hipMalloc(&xy, 2 * vb));
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      double tm[2] = {0.0, 0.0};
+      double tm[4] = {0.0, 0.0, 0.0, 0.0};
       try {
         aim::launch_pattern(xy, p->t.N * nrhs, dbl, s);
         AIM_HIP(hipEventCreate(&e0));
         AIM_HIP(hipEventCreate(&e1));
-        // three rounds alternating the modes, best time of each: one round
-        // alone flips between modes within a few percent of each other
-        tm[0] = tm[1] = 1e300;
+        // three rounds alternating the four stage modes (interpolation from
+        // the assembled P^T or recomputed weights, projection on its own or
+        // fused into the x forward pass), best time of each: one round alone
+        // flips between modes within a few percent of each other
+        tm[0] = tm[1] = tm[2] = tm[3] = 1e300;
         for (int round = 0; round < 3; ++round)
-          for (int mode = 0; mode < 2; ++mode) {
+          for (int mode = 0; mode < 4; ++mode) {
             p->sched[pi][6] = mode;
             auto run = [&] { matvec_any(p, prec, xy, static_cast<char*>(xy) + vb, nrhs, df, s); };
             run();  // warm-up
@@ -1600,7 +1607,9 @@ aim_status aim_autotune(aim_plan p, aim_precision prec, int32_t nrhs, int32_t re
       (void)hipEventDestroy(e1);
       AIM_HIP(hipStreamSynchronize(s));
       AIM_HIP(hipFree(xy));
-      pick[6] = tm[1] < tm[0] ? 1 : 0;
+      pick[6] = 0;
+      for (int mode = 1; mode < 4; ++mode)
+        if (tm[mode] < tm[pick[6]]) pick[6] = mode;
     }
     for (int k = 0; k < aim::kSchedLen; ++k) {
       p->sched[pi][k] = pick[k];
@@ -2869,7 +2878,7 @@ std::unique_ptr<aim_plan_s> read_plan(const char* path) {
                       aim::fft_variant_ok(pi == 0, p->g, k, p->sched[pi][k]),
                   AIM_ERR_INVALID_ARG, "plan file: bad schedule");
     AIM_REQUIRE(p->sched[pi][5] >= 0 && p->sched[pi][5] < aim::kLayouts &&
-                    (p->sched[pi][6] == 0 || p->sched[pi][6] == 1),
+                    p->sched[pi][6] >= 0 && p->sched[pi][6] <= 3,
                 AIM_ERR_INVALID_ARG, "plan file: bad schedule");
   }
   p->ncl = int(t.cl_ptr.size()) - 1;

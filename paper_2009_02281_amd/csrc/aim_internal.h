@@ -186,8 +186,10 @@ constexpr int kFftVariants = AIM_FFT_SHAPES;
 // rest are persistent shapes of the fused z pass
 constexpr int kFftShapesPerLine = 8;
 // schedule = launch shape of each of the five FFT passes, the work layout,
-// and the interpolation mode (0: assembled P^T, 1: recomputed weights)
+// and the stage modes: bit 0 the interpolation (0: assembled P^T, 1:
+// recomputed weights), bit 1 the projection fused into the x forward pass
 constexpr int kSchedLen = 7;
+constexpr int kModeImplicitInterp = 1, kModeFusedProject = 2;
 constexpr int kLayouts = AIM_FFT_LAYOUTS;
 // bytes added to every z plane of the convolution work grid, per layout
 constexpr int64_t kLayoutPadBytes[kLayouts] = {0, 1024, 4096, 12288};
@@ -198,7 +200,10 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
                      hipEvent_t* between = nullptr,  // 4 events recorded between passes
                      const int* sched = nullptr,
-                     int repeat = 1);  // each pass launched this many times (timing only)
+                     int repeat = 1,  // each pass launched this many times (timing only)
+                     // with P: q is not read; the x forward pass computes its
+                     // lines as q = P x (x [nrhs][n]) itself
+                     const CsrDevice* P = nullptr, const void* x = nullptr, int64_t n = 0);
 // whether launch shape v exists for FFT pass `pass` (0 x forward, 1 y
 // forward, 2 fused z, 3 y inverse, 4 x inverse) of the grid g
 bool fft_variant_ok(bool dbl, const GridShape& g, int pass, int v);

@@ -320,7 +320,16 @@ __device__ __forceinline__ void run_stages(cx<T>* v, cx<T>* s, int es, int t, co
 // and p0 = 1 so that consecutive lines are consecutive x positions (coalesced
 // rows of TL elements); row passes (x) have lg_nli = log2(rows per plane),
 // p0 = row pitch, os = plane pitch and es = 1.
-// MODE 0: forward, 1: inverse, 2: forward * spectrum then inverse.
+// MODE 0: forward, 1: inverse, 2: forward * spectrum then inverse, 3: the x
+// forward pass with its input lines computed as the projection q = P x.
+//
+// MODE 3: a workgroup's TL lines are TL * (L/2) consecutive grid nodes, i.e.
+// consecutive rows of P sorted by node, so their entries form one contiguous
+// range.  The range is streamed in chunks through the LDS line buffer as the
+// products w x[col] (coalesced entry loads, the x gathers of 256 or more
+// threads in flight together), and every thread sums, in entry order, the
+// rows of the elements it then transforms: the projected values never go
+// to memory, and the result does not depend on the chunking.
 // HALF (the convolution's passes): a forward transform reads only the first
 // half of its line (the rest is the zero padding, known at compile time, so
 // the first stage skips it) and an inverse transform keeps only the first
@@ -338,6 +347,13 @@ struct PassArgs {
   int64_t spec_fs;        // per-frequency stride of the folded spectrum
   const int32_t* rhs_freq;
   int Mx, Nx, My, Ny, Mz, Nz;
+  // projection fused into the x forward pass (MODE 3): P by grid node and
+  // the mesh vector x ([nrhs][px_bs])
+  const int32_t* prow;
+  const int32_t* pcol;
+  const void* pval;
+  const void* px;
+  int64_t px_bs;
 };
 
 template <typename T, int L, int TL, int NT, int MODE, bool COL, int RMAX, bool HALF>
@@ -348,9 +364,10 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
   constexpr int NTH = TL * NT;
   __shared__ cx<T> s[COL ? L * TL : TL * (L + 1)];
   __shared__ cx<T> tw[L];
+  __shared__ int32_t rp[MODE == 3 ? TL * (L / 2) + 1 : 1];
   const int tid = threadIdx.x;
   const int rhs = blockIdx.y;
-  in += rhs * a.in_bs;
+  if constexpr (MODE != 3) in += rhs * a.in_bs;
   out += rhs * a.out_bs;
   const int l = COL ? (tid & (TL - 1)) : (tid / NT);
   const int t = COL ? (tid / TL) : (tid & (NT - 1));
@@ -378,27 +395,78 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
   const bool valid = line < a.nlines;
   const int64_t mask = (int64_t(1) << a.lg_nli) - 1;
   const int64_t li = line & mask, lo = line >> a.lg_nli;
-  const cx<T>* src = in + lo * a.in_os + li * a.in_p0;
+  const cx<T>* src = MODE == 3 ? nullptr : in + lo * a.in_os + li * a.in_p0;
   cx<T>* dst = out + lo * a.out_os + li * a.out_p0;
   cx<T>* sl = COL ? s + l : s + l * (L + 1);
   const int es = COL ? TL : 1;
 
+  constexpr bool FWD = MODE == 0 || MODE == 3;
   constexpr bool SF = MODE != 1;
-  constexpr bool HALF_IN = HALF && MODE != 1, HALF_OUT = HALF && MODE != 0;
+  constexpr bool HALF_IN = HALF && MODE != 1, HALF_OUT = HALF && !FWD;
   static_assert(RMAX <= E, "a thread must hold a whole butterfly");
+  static_assert(MODE != 3 || (!COL && HALF), "the fused projection feeds the x forward pass");
   using S0 = Sched<L, SF, RMAX>;
   constexpr int R0 = S0::radix(0), NB0 = L / (R0 * NT);
   cx<T> v[E];
+  if constexpr (MODE == 3) {
+    constexpr int NX = L / 2;
+    const int64_t u0 = line0 * NX, ng = a.nlines * NX;
+    for (int i = tid; i <= TL * NX; i += NTH)
+      rp[i] = a.prow[u0 + i < ng ? u0 + i : ng];
 #pragma unroll
-  for (int i = 0; i < NB0; ++i)
+    for (int k = 0; k < E; ++k) v[k] = mkc<T>(T(0), T(0));
+    __syncthreads();
+    const T* pv = static_cast<const T*>(a.pval);
+    const cx<T>* xr = static_cast<const cx<T>*>(a.px) + rhs * a.px_bs;
+    const int32_t k0 = rp[0], k1 = rp[TL * NX];
+    constexpr int CH = TL * (L + 1);
+    for (int32_t cb = k0; cb < k1; cb += CH) {
+      const int32_t ce = k1 - cb < CH ? k1 : cb + CH;
+      for (int32_t k = cb + tid; k < ce; k += NTH) {
+        const T w = pv[k];
+        const cx<T> xv = xr[a.pcol[k]];
+        s[k - cb] = mkc<T>(w * xv.x, w * xv.y);
+      }
+      __syncthreads();
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int e = t + i * NT + r * (L / R0);
-      if constexpr (HALF_IN)  // e < L/2 exactly when r < R0/2
-        v[i * R0 + r] = (valid && r < R0 / 2) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
-      else
-        v[i * R0 + r] = (valid && e < a.Lin) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0 / 2; ++r) {  // the nonzero half: e < L/2
+          const int lr = l * NX + t + i * NT + r * (L / R0);
+          const int32_t b0 = rp[lr] > cb ? rp[lr] : cb, b1 = rp[lr + 1] < ce ? rp[lr + 1] : ce;
+          // four independent partial sums (four LDS reads in flight), then
+          // combined in a fixed order
+          T ax[4] = {T(0), T(0), T(0), T(0)}, ay[4] = {T(0), T(0), T(0), T(0)};
+          int32_t k = b0;
+          for (; k + 4 <= b1; k += 4)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              ax[j] += s[k + j - cb].x;
+              ay[j] += s[k + j - cb].y;
+            }
+          for (int j = 0; k < b1; ++k, ++j) {
+            ax[j] += s[k - cb].x;
+            ay[j] += s[k - cb].y;
+          }
+          cx<T> acc = v[i * R0 + r];
+          acc.x += (ax[0] + ax[1]) + (ax[2] + ax[3]);
+          acc.y += (ay[0] + ay[1]) + (ay[2] + ay[3]);
+          v[i * R0 + r] = acc;
+        }
+      __syncthreads();
     }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int e = t + i * NT + r * (L / R0);
+        if constexpr (HALF_IN)  // e < L/2 exactly when r < R0/2
+          v[i * R0 + r] = (valid && r < R0 / 2) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
+        else
+          v[i * R0 + r] = (valid && e < a.Lin) ? src[e * a.in_es] : mkc<T>(T(0), T(0));
+      }
+  }
   // fused z pass: the spectrum values this thread multiplies after its
   // forward transform depend only on (kx, ky) and the element index, so they
   // are loaded here, in flight together with the line itself
@@ -439,12 +507,12 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
     }
     run_stages<T, L, NT, true, false, RMAX, 0>(v, sl, es, t, tw);
   }
-  using Sf = Sched<L, MODE == 0, RMAX>;
+  using Sf = Sched<L, FWD, RMAX>;
   // outputs that the next pass streams (the forward passes and the y
   // inverse) are stored non-temporally, keeping them out of the way in the
   // caches; the in-place z pass and the x inverse, whose output the
   // interpolation gathers, store normally (measured both ways)
-  constexpr bool kStreamOut = MODE == 0 || (MODE == 1 && COL);
+  constexpr bool kStreamOut = FWD || (MODE == 1 && COL);
   constexpr int Rf = Sf::radix(Sf::NST - 1), NBf = L / (Rf * NT);
   if (valid) {
 #pragma unroll
@@ -518,10 +586,15 @@ void launch_shape(int mode, const cx<T>* i, cx<T>* o, const cx<T>* w, const Pass
   } else {
     dim3 grid(unsigned((a.nlines + S::TL - 1) / S::TL), unsigned(nrhs));
     AIM_REQUIRE(mode == 2 ? (a.Lin == L / 2 && a.Lout == L / 2)
-                          : mode == 0 ? (a.Lin == L / 2 && a.Lout == L)
-                                      : (a.Lin == L && a.Lout == L / 2),
+                          : (mode == 0 || mode == 3) ? (a.Lin == L / 2 && a.Lout == L)
+                                                     : (a.Lin == L && a.Lout == L / 2),
                 AIM_ERR_INVALID_ARG, "convolution FFT pass: lines must be half zero padding");
-    if (mode == 0)
+    if (mode == 3) {
+      if constexpr (!COL)
+        hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 3, false, S::RMAX, true>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
+      else
+        throw Error(AIM_ERR_INVALID_ARG, "the fused projection is a row pass");
+    } else if (mode == 0)
       hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 0, COL, S::RMAX, true>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
     else if (mode == 1)
       hipLaunchKernelGGL((fft_pass_kernel<T, L, S::TL, S::NT, 1, COL, S::RMAX, true>), grid, dim3(S::THREADS), 0, s, i, o, w, a);
@@ -873,7 +946,8 @@ template <typename T>
 void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_t nplanes,
               int rows, int64_t in_ls, int64_t out_ls, int64_t in_ps, int64_t out_ps,
               int64_t in_bs, int64_t out_bs, int Lin, int Lout, int nrhs, hipStream_t s,
-              int variant = 0) {
+              int variant = 0, const CsrDevice* P = nullptr, const void* x = nullptr,
+              int64_t n = 0) {
   PassArgs a{};
   a.nlines = nplanes * rows;
   a.lg_nli = ilog2(rows);
@@ -886,7 +960,16 @@ void row_pass(int L, bool inv, const void* in, void* out, const void* tw, int64_
   a.out_bs = out_bs;
   a.Lin = Lin;
   a.Lout = Lout;
-  fft_pass<T>(L, false, inv ? 1 : 0, in, out, tw, a, nrhs, s, variant);
+  if (P) {  // the input lines are q = P x, computed in the pass
+    AIM_REQUIRE(!inv && in_ls == Lin && in_ps == int64_t(rows) * Lin, AIM_ERR_INVALID_ARG,
+                "the fused projection reads unpadded grid rows");
+    a.prow = P->rowptr;
+    a.pcol = P->col;
+    a.pval = P->val;
+    a.px = x;
+    a.px_bs = n;
+  }
+  fft_pass<T>(L, false, P ? 3 : (inv ? 1 : 0), in, out, tw, a, nrhs, s, variant);
 }
 
 // ---------------------------------------------------------------------------
@@ -904,7 +987,8 @@ int64_t work_elems(const GridShape& g, int layout, size_t elem_bytes) {
 template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
-                     hipEvent_t* between, const int* sched, int repeat) {
+                     hipEvent_t* between, const int* sched, int repeat, const CsrDevice* P,
+                     const void* x, int64_t n) {
   static const int kDefault[kSchedLen] = {0, 0, 0, 0, 0, 0, 0};
   if (!sched) sched = kDefault;
   auto mark = [&](int i) {
@@ -936,7 +1020,7 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
   // x forward: rows (y, z) of q, Nx -> Mx, into A [Nz][Ny][Mx]
   for (int r = 0; r < repeat; ++r)
     row_pass<T>(Mx, false, q, A, tw[0], Nz, Ny, Nx, Mx, int64_t(Ny) * Nx, PA, Ng, W, Nx, Mx,
-                nrhs, s, sched[0]);
+                nrhs, s, sched[0], P, x, n);
   mark(0);
   // y forward: A [Nz][Ny][Mx] -> B [Nz][My][Mx]
   {
@@ -990,10 +1074,12 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
 
 template void launch_convolve<double>(const GridShape&, const void*, void*, void*, const void*,
                                       const int32_t*, int, const void* const*, hipStream_t,
-                                      hipEvent_t*, const int*, int);
+                                      hipEvent_t*, const int*, int, const CsrDevice*,
+                                      const void*, int64_t);
 template void launch_convolve<float>(const GridShape&, const void*, void*, void*, const void*,
                                      const int32_t*, int, const void* const*, hipStream_t,
-                                     hipEvent_t*, const int*, int);
+                                     hipEvent_t*, const int*, int, const CsrDevice*, const void*,
+                                     int64_t);
 
 // ---------------------------------------------------------------------------
 // kernel spectrum: circulant embedding of G on the padded grid, full 3-D FFT,

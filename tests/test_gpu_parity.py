@@ -128,8 +128,9 @@ def test_matvec_frequency_batch():
 
 def test_many_right_hand_sides_at_many_wavenumbers():
     """61 vectors at 8 wavenumbers (workgroups serve several vectors each,
-    the last one fewer), every vector against the oracle, in both
-    interpolation modes."""
+    the last one fewer), every vector against the oracle, in the four stage
+    modes (both interpolations, the projection on its own or fused into the
+    x forward pass)."""
     w = I.sweep_small(nfreq=8, rhs_per_freq=8)
     print("[gpu] 64 right-hand sides", flush=True)
     o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
@@ -139,7 +140,7 @@ def test_many_right_hand_sides_at_many_wavenumbers():
     freq = np.arange(nv) % 8
     x = I.complex_gaussian(o.N, 3101, nrhs=nv)
     refs = [o.matvec(x[r], w.k[freq[r]]) for r in range(nv)]
-    for mode in (0, 1):
+    for mode in (0, 1, 2, 3):
         for prec, dt, tol in (("c128", torch.complex128, FP64_TOL),
                               ("c64", torch.complex64, FP32_TOL)):
             p.set_schedule([0] * 6 + [mode], prec=prec)
@@ -158,6 +159,11 @@ def test_projection_is_deterministic():
     ya = p.matvec(x)
     yb = p.matvec(x)
     assert torch.equal(ya, yb)
+    p.set_schedule([0] * 6 + [2])        # projection inside the x forward pass
+    yf = p.matvec(x)
+    assert torch.equal(yf, p.matvec(x))
+    assert rel(host(yf), host(ya)) <= 1e-14
+    p.set_schedule([0] * 7)
 
 
 def test_operator_symmetry_on_gpu():
@@ -194,8 +200,8 @@ def test_invalid_calls_raise():
 def test_full_size_box_array_shared_blocks():
     """The full-size box array with 7 right-hand sides: the projection and
     interpolation workgroups each serve several right-hand sides.  Sampled
-    rows of every vector against the oracle, both precisions and
-    interpolation modes."""
+    rows of every vector against the oracle, both precisions and the four
+    stage modes."""
     w = I.box_array_large()
     print("[gpu] full-size box array, 7 right-hand sides", flush=True)
     p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
@@ -204,7 +210,7 @@ def test_full_size_box_array_shared_blocks():
     x = I.complex_gaussian(o.N, 2101, nrhs=7)   # 4 + 3 vectors per workgroup
     rows = np.sort(np.random.default_rng(2102).choice(o.N, 16, replace=False))
     refs = [o.matvec_rows(x[r], w.k[0], rows) for r in range(7)]
-    for mode in (0, 1):
+    for mode in (0, 1, 2, 3):
         for prec, dt, tol in (("c128", torch.complex128, FP64_TOL),
                               ("c64", torch.complex64, FP32_TOL)):
             p.set_schedule([0] * 6 + [mode], prec=prec)
@@ -278,6 +284,9 @@ def test_every_fft_launch_shape_matches_oracle(prec):
                     continue
                 tried += 1
                 assert rel(host(p.matvec(xd, prec=prec)), ref) <= tol, (k, v, layout)
+                if k == 0:           # the same x forward shape with the projection fused
+                    p.set_schedule(sched + [2], prec=prec)
+                    assert rel(host(p.matvec(xd, prec=prec)), ref) <= tol, (v, layout, "fused")
     assert tried >= 16 * binding.FFT_LAYOUTS
     with pytest.raises(binding.AimError):
         p.set_schedule([0] * 5 + [binding.FFT_LAYOUTS], prec=prec)
