@@ -780,6 +780,9 @@ def main() -> int:
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net throughput leg")
     ap.add_argument("--no-efie", action="store_true",
                     help="skip the RWG operators' leg (81,920-triangle sphere)")
+    ap.add_argument("--schedule", default="",
+                    help="comma-separated schedule (seven integers) to install instead of "
+                         "autotuning the timed precision")
     ap.add_argument("--efie-only", action="store_true",
                     help="only run the RWG EFIE leg (--steps products per timing)")
     ap.add_argument("--no-extra", action="store_true",
@@ -844,6 +847,14 @@ def main() -> int:
           flush=True)
     tuned = {}
     for pr in precs:
+        if args.schedule and pr == args.prec:
+            # a given schedule (e.g. the one a profiled run picked) instead of
+            # tuning, so that counter runs time the same launches
+            sched = [int(v) for v in args.schedule.split(",")]
+            plan.set_schedule(sched, prec=pr)
+            tuned[pr] = {"schedule": sched, "pass_ms": [], "given": True}
+            print(f"[bench] given schedule ({pr}): {sched}", file=sys.stderr, flush=True)
+            continue
         tuned[pr] = plan.autotune(prec=pr, nrhs=args.nrhs, reps=10)
         print(f"[bench] autotuned FFT launch shapes ({pr}): {tuned[pr]['schedule']} "
               f"pass ms {[round(t, 4) for t in tuned[pr]['pass_ms']]}", file=sys.stderr,
