@@ -378,3 +378,25 @@ def dense_rows(rwg: Rwg, k: float, rows, cache=None) -> np.ndarray:
                     acc += np.sum((ff - dd / (k * k)) * Gd)
             out[a, n] += acc
     return out
+
+
+def plane_wave_tested(rwg: Rwg, k: float, direction, pol, field: str = "E") -> np.ndarray:
+    """The incident plane wave E = pol e^{-jk d.r} (d the unit direction)
+    tested with the RWG functions by the 3-point rule: field "E" gives
+    <f_m, E>; field "H" gives <f_m, n x (d x E)> = eta0 <f_m, n x H>
+    (H = d x E / eta0, n the unit normal of each triangle)."""
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    p = np.asarray(pol, dtype=np.float64)
+    qp = _mesh.quad_points(rwg.V, rwg.T)
+    vals = rwg.point_values()
+    nrm = _mesh.unit_normals(rwg.V, rwg.T)
+    out = np.zeros(rwg.n, dtype=np.complex128)
+    for t in range(rwg.T.shape[0]):
+        vec = p if field == "E" else np.cross(nrm[t], np.cross(d, p))
+        ph = np.exp(-1j * k * (qp[t] @ d))
+        for e in range(3):
+            m = rwg.tri_rwg[t, e]
+            if m >= 0:
+                out[m] += np.sum((vals[t, :, e, :3] @ vec) * ph)
+    return out

@@ -19,6 +19,7 @@ import math
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from paper_2009_02281_amd import inputs as I
 from oracle import aimx, dlp, efie, mesh, mfie
@@ -214,3 +215,60 @@ def test_accelerated_operator_against_dense_reference():
     print(f"K against the dense matrix: h = 0.1: {errs[0]:.2e}, h = 0.05: {errs[1]:.2e}")
     assert errs[0] <= 0.05
     assert errs[1] < 0.5 * errs[0]
+
+
+def test_plane_wave_vectors_at_zero_frequency():
+    """At k = 0 the tested field is pol . int f_m, which is exact under the
+    3-point rule: int_T (r - p) = A (c - p), so int f_m = (l/2)[(c+ - p+) +
+    (p- - c-)]."""
+    w = I.sphere_tiny(level=1)
+    rwg = efie.Rwg(w.vertices, w.triangles)
+    pol = np.array([0.3, -0.7, 0.2])
+    b = efie.plane_wave_tested(rwg, 0.0, [0, 0, 1], pol)
+    cen = mesh.centroids(rwg.V, rwg.T)
+    for m in range(rwg.n):
+        tp, tm = rwg.tp[m], rwg.tm[m]
+        ep = int(np.nonzero(rwg.tri_rwg[tp] == m)[0][0])
+        em = int(np.nonzero(rwg.tri_rwg[tm] == m)[0][0])
+        pp, pm = rwg.V[rwg.T[tp, ep]], rwg.V[rwg.T[tm, em]]
+        ref = 0.5 * rwg.length[m] * ((cen[tp] - pp) + (pm - cen[tm])) @ pol
+        assert b[m] == pytest.approx(ref, rel=1e-12, abs=1e-15)
+
+
+def test_magnetic_and_electric_field_equations_agree_on_a_sphere():
+    """Physics fixes the signs: for a plane wave on a closed sphere, the
+    tested MFIE (G/2 - K) J = <f, n x H_inc> (K the principal value, residue
+    -G/2) and the tested EFIE j k Z J = <f, E_inc> (eta0 = 1) give the same
+    current, up to the MFIE's discretisation error (5% here); the other
+    sign choices of K and the residue miss by far more."""
+    k = 2 * math.pi * 0.8
+    w = I.sphere_tiny(level=2, dims=(16, 16, 16), h=0.1, k=k)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    e = efie.EfieOracle(o)
+    m = mfie.MfieOracle(e)
+    n = e.n
+    Z = np.zeros((n, n), complex)
+    K = np.zeros((n, n), complex)
+    CA, CP = e.corrections()
+    CK = sp.csr_matrix((m.correction_values(m.rows, m.cols), (m.rows, m.cols)), shape=(n, n))
+    G = sp.csr_matrix((m.gram(m.rows, m.cols), (m.rows, m.cols)), shape=(n, n)).toarray()
+    for j in range(n):
+        x = np.zeros(n, complex)
+        x[j] = 1.0
+        Z[:, j] = e.far(x, k) + CA @ x - CP @ x / k ** 2
+        K[:, j] = m.far(x, k) + CK @ x
+    d, pol = [0, 0, 1], [1, 0, 0]
+    bE = efie.plane_wave_tested(e.rwg, k, d, pol, "E")
+    bH = efie.plane_wave_tested(e.rwg, k, d, pol, "H")
+    JE = np.linalg.solve(Z, bE / (1j * k))
+    errs = {}
+    for sgn in (1, -1):
+        for beta in (-0.5, 0.5):
+            JM = np.linalg.solve(-sgn * (K + beta * G), bH)
+            errs[(sgn, beta)] = np.linalg.norm(JM - JE) / np.linalg.norm(JE)
+    print("MFIE against EFIE:", {k2: round(v, 3) for k2, v in errs.items()})
+    assert errs[(1, -0.5)] < 0.08
+    assert min(v for k2, v in errs.items() if k2 != (1, -0.5)) > 0.5
+    # the combined field Z + (j/k)(K - G/2) with (bE + bH)/(jk) gives the same current
+    JC = np.linalg.solve(Z + 1j / k * (K - 0.5 * G), (bE + bH) / (1j * k))
+    assert np.linalg.norm(JC - JE) / np.linalg.norm(JE) < 0.05
