@@ -407,8 +407,9 @@ aim_status aim_efie_export(aim_plan plan, int32_t* tri_rwg, int32_t* rowptr, int
  * is normal to it and drops out); the residue of the surface limit is a
  * multiple of the Gram matrix G_mn = int f_m . f_n, so the call applies
  *   y = (K(k_f) + gram_coef G) x
- * (for the exterior MFIE n x H_inc = J/2 - n x K_PV J, -(K - G/2) is
- * gram_coef = -1/2 with the sign of y flipped).  Evaluated as
+ * (the MFIE J/2 - n x K_PV J = n x H_inc of a closed surface, tested with
+ * f_m, is (G/2 - K) J = <f_m, n x H_inc>: gram_coef = -1/2 with the sign of
+ * y flipped).  Evaluated as
  * K_s,NR - K_s,P + W H_grad(k) P on the RWG functions, near list, point
  * projection and wavenumbers of the EFIE above: three current channels
  * w_q f(r_q), their moments (u - c) x J on the grid, six convolutions with
@@ -429,17 +430,44 @@ aim_status aim_mfie_export(aim_plan plan, double* ck_host, double* gram_host, do
                            void* hip_stream);
 
 /* The AIMx-accelerated combined-field operator of eq. CFIEAIMx (Sec. III-B;
- * the discrete CFIE, eq. CFIEdis), with its common factor -j omega mu0 left
- * out:
- *   y = Z(k_f) x - (j / k_f) (K(k_f) + gram_coef G) x,
- * Z the EFIE operator of aim_matvec_efie and K, G those of aim_matvec_mfie
- * (-(j/k) K is the term -(j/k0) K of eq. CFIEAIMx; gram_coef places the
- * residue of the surface limit).  One projection of the four channels
+ * the discrete CFIE, eq. CFIEdis), scaled by 1/(j k eta0):
+ *   y = Z(k_f) x + (j / k_f) (K(k_f) + gram_coef G) x,
+ * Z the EFIE operator of aim_matvec_efie and K, G those of aim_matvec_mfie.
+ * With E_s = -j k eta0 Z J (the EFIE, tested: j k Z J = <f_m, E_inc>/eta0)
+ * and the MFIE above, gram_coef = -1/2 gives their sum divided by j k:
+ *   [Z + (j/k)(K - G/2)] J = (<f_m, E_inc> + eta0 <f_m, n x H_inc>) / (j k eta0)
+ * (the paper writes the same combination as L - (j/k0) K with its own sign
+ * convention for L and the incident-field vectors).  One projection of the four channels
  * serves both operators: the double layer takes its three current grids
  * from it.  Arguments and rules as for aim_matvec_mfie; the first call
  * builds both operators' tables and a [3 max_rhs][3N] field buffer. */
 aim_status aim_matvec_cfie(aim_plan plan, const void* x_dev, void* y_dev, int32_t nrhs,
                            const int32_t* freq_idx_host, double gram_coef, void* hip_stream);
+
+/* Plane waves tested with the RWG functions (3-point rule per triangle):
+ * params_host [nrhs][6] = (d, pol) with d the propagation direction
+ * (normalised here) and pol the electric polarisation; vector r at
+ * wavenumber k = k[freq_idx_host[r]] (NULL: all 0):
+ *   field 0: b[r][m] = <f_m, pol e^{-j k d.r}>            (the EFIE's E),
+ *   field 1: b[r][m] = <f_m, n x (d x pol) e^{-j k d.r}>   (eta0 <f_m, n x H_inc>,
+ *            the MFIE's right-hand side, n each triangle's unit normal).
+ * b_dev [nrhs][n_rwg] complex128.  Builds the EFIE tables if needed;
+ * blocking.  Same plan requirements as the EFIE. */
+aim_status aim_rwg_excitation(aim_plan plan, int32_t field, const double* params_host,
+                              int32_t nrhs, const int32_t* freq_idx_host, void* b_dev,
+                              void* hip_stream);
+
+/* Batched restarted GMRES (the Krylov loop of aim_solve: complex128,
+ * device Arnoldi, per-system stop) on an RWG operator: op 1 the EFIE Z,
+ * 2 the double layer K + gram_coef G, 3 the combined field
+ * Z + (j/k)(K + gram_coef G); vector r at wavenumber index freq_idx_host[r].
+ * b_dev, x_dev [nrhs][n_rwg] complex128, x_dev the initial guess on entry;
+ * opts as for aim_solve with pc AIM_PC_NONE and inner AIM_C128 only
+ * (AIM_ERR_INVALID_ARG otherwise); info[nrhs] filled.  AIM_ERR_NOT_CONVERGED
+ * if a system stops at max_iter (x holds its best iterate).  Blocking. */
+aim_status aim_solve_rwg(aim_plan plan, int32_t op, double gram_coef, const void* b_dev,
+                         void* x_dev, int32_t nrhs, const int32_t* freq_idx_host,
+                         const aim_solve_opts* opts, aim_solve_info* info, void* hip_stream);
 
 /* One stage of the matvec, for stage-level checks (see aim_stage for the
  * shapes).  Same rules as aim_matvec; grids are unpadded [nrhs][Nz][Ny][Nx]. */

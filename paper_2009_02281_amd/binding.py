@@ -33,7 +33,8 @@ EXPORTED = ["aim_setup", "aim_setup_host", "aim_destroy", "aim_plan_query", "aim
             "aim_matvec_static", "aim_conventional_fill", "aim_matvec_conventional",
             "aim_conventional_export", "aim_matvec_dlp", "aim_dlp_export",
             "aim_efie_setup", "aim_matvec_efie", "aim_efie_export", "aim_matvec_mfie",
-            "aim_mfie_export", "aim_matvec_cfie",
+            "aim_mfie_export", "aim_matvec_cfie", "aim_rwg_excitation",
+            "aim_solve_rwg",
             "aim_export_clusters", "aim_set_lin_term",
             "aim_export_lin_diag", "aim_apply_stage",
             "aim_excitation", "aim_solve", "aim_export_tables", "aim_profile_matvec",
@@ -131,6 +132,10 @@ def load_library(path: str = LIB_PATH):
     lib.aim_matvec_efie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), vp]
     lib.aim_matvec_mfie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
     lib.aim_matvec_cfie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
+    lib.aim_rwg_excitation.argtypes = [vp, i32, C.POINTER(C.c_double), i32,
+                                       C.POINTER(C.c_int32), vp, vp]
+    lib.aim_solve_rwg.argtypes = [vp, i32, C.c_double, vp, vp, i32, C.POINTER(C.c_int32),
+                                  C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     lib.aim_mfie_export.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), vp]
     lib.aim_efie_export.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -698,6 +703,57 @@ class Plan:
                                          C.c_void_p(y.data_ptr()), nrhs, fp,
                                          float(gram_coef), _stream_ptr(stream)))
         return y
+
+    def rwg_excitation(self, direction, pol, field: str = "E", nrhs=None, freq_idx=None,
+                       stream=None):
+        """Plane waves tested with the RWG functions: field "E" <f, pol e^{-jk d.r}>,
+        "H" <f, n x (d x pol) e^{-jk d.r}>; direction and pol of shape [3] or
+        [nrhs, 3].  Returns [nrhs, n_rwg] complex128."""
+        import torch
+        n = self.efie_setup(stream)["n_rwg"]
+        d = np.atleast_2d(np.asarray(direction, dtype=np.float64))
+        p = np.atleast_2d(np.asarray(pol, dtype=np.float64))
+        nr = max(d.shape[0], p.shape[0]) if nrhs is None else int(nrhs)
+        prm = np.ascontiguousarray(np.concatenate([np.broadcast_to(d, (nr, 3)),
+                                                   np.broadcast_to(p, (nr, 3))], axis=1))
+        b = torch.empty((nr, n), dtype=torch.complex128, device="cuda")
+        _, fp = _freq_arg(freq_idx, nr)
+        _check(self._lib.aim_rwg_excitation(self._plan, 0 if field == "E" else 1,
+                                            prm.ctypes.data_as(C.POINTER(C.c_double)), nr, fp,
+                                            C.c_void_p(b.data_ptr()), _stream_ptr(stream)))
+        return b
+
+    def solve_rwg(self, op: str, b, x0=None, freq_idx=None, gram_coef: float = -0.5,
+                  rtol: float = 1e-6, restart: int = 30, max_iter: int = 1000, stream=None,
+                  raise_on_fail=True):
+        """Batched GMRES on an RWG operator (op "efie", "mfie" for K + gram G,
+        "cfie" for Z + (j/k)(K + gram G)); b of shape [nrhs, n_rwg].  Returns
+        (x, SolveResult)."""
+        import torch
+        n = self.efie_setup(stream)["n_rwg"]
+        b2 = b.reshape(-1, n)
+        self._check_vec(b2, "c128", n, "b")
+        nrhs = b2.shape[0]
+        x = torch.zeros_like(b2) if x0 is None else x0.reshape(-1, n).clone()
+        opts = SolveOpts(rtol, restart, max_iter, 0, PREC["c128"], PC["none"], 0.0, PC["none"],
+                         0.0)
+        infos = (SolveInfo * nrhs)()
+        _, fp = _freq_arg(freq_idx, nrhs)
+        code = {"efie": 1, "mfie": 2, "cfie": 3}[op]
+        st = self._lib.aim_solve_rwg(self._plan, code, float(gram_coef),
+                                     C.c_void_p(b2.data_ptr()), C.c_void_p(x.data_ptr()), nrhs,
+                                     fp, C.byref(opts), infos, _stream_ptr(stream))
+        if st not in (AIM_OK, 6) or (st == 6 and raise_on_fail):
+            _check(st)
+        res = SolveResult(
+            iters=np.array([i.iters for i in infos]),
+            refinements=np.array([i.refinements for i in infos]),
+            matvecs=np.array([i.matvecs for i in infos]),
+            converged=np.array([bool(i.converged) for i in infos]),
+            rel_resid=np.array([i.rel_resid for i in infos]),
+            seconds=float(infos[0].seconds) if nrhs else 0.0, status=st,
+            fallback_used=np.array([bool(i.fallback_used) for i in infos]))
+        return x.reshape(b.shape), res
 
     def mfie_values(self, stream=None) -> dict:
         """C_K and the Gram entries on the RWG near list, and the build time."""

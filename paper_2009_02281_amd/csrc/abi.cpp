@@ -204,6 +204,11 @@ struct aim_plan_s {
   int32_t* d_mfie_freq = nullptr;   // [6 max_rhs]
   int32_t* h_mfie_freq = nullptr;   // pinned staging
   void* d_cfie_psi = nullptr;       // [3 max_rhs][3N] the double layer's field (combined call)
+  // the operator the Krylov solver applies: 0 the plan's scalar operator,
+  // else an RWG operator (aim_solve_rwg sets it for the duration of a solve)
+  int rwg_op = 0;
+  double rwg_gram = 0.0;
+  std::vector<int32_t> rwg_fr;      // per-vector wavenumber index of that solve
   std::vector<int32_t> mfie_cur_freq;
   double mfie_seconds = 0.0;
 
@@ -1122,6 +1127,17 @@ void ensure_efie(aim_plan p, hipStream_t s) {
   const auto& g = p->g;
   const int R = p->max_rhs;
   const int64_t P = 3 * t.N;
+  std::vector<double> nrm(3 * size_t(t.N));
+  for (int64_t j = 0; j < t.N; ++j) {
+    const double* c = &t.corners[9 * j];
+    const double e1[3] = {c[3] - c[0], c[4] - c[1], c[5] - c[2]};
+    const double e2[3] = {c[6] - c[0], c[7] - c[1], c[8] - c[2]};
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                         e1[0] * e2[1] - e1[1] * e2[0]};
+    const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int a = 0; a < 3; ++a) nrm[3 * j + a] = n[a] / l;
+  }
+  p->d_mfie_nrm = p->upload(nrm, s);  // unit normals (double layer, excitation)
   p->d_efie_vals = p->upload(e.vals, s);
   p->d_efie_trirwg = p->upload(e.tri_rwg, s);
   p->d_efie_te = p->upload(e.rwg_te.empty() ? std::vector<int32_t>(4, 0) : e.rwg_te, s);
@@ -1217,32 +1233,6 @@ void check_rwg_call(aim_plan p, const void* x, const void* y, int nrhs) {
 }
 }  // namespace
 
-aim_status aim_matvec_efie(aim_plan p, const void* x, void* y, int32_t nrhs,
-                           const int32_t* freq_idx_host, void* hip_stream) {
-  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
-  return guarded([&] {
-    check_rwg_call(p, x, y, nrhs);
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
-    ensure_efie(p, s);
-    stage_freq(fr, 4, p->efie_cur_freq, p->h_efie_freq, p->d_efie_freq, s);
-    const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
-    aim::launch_efie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
-    aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
-                                p->d_efie_grid, 4 * nrhs, s);
-    aim::launch_convolve<double>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid,
-                                 p->d_spec64, p->d_efie_freq, 4 * nrhs, p->d_tw64, s, nullptr,
-                                 p->sched[0]);
-    aim::CsrDevice none{};
-    none.n = P;  // interpolation only: the near rows are the test kernel's
-    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_efie_grid, nullptr,
-                                    p->d_efie_src, 4 * nrhs, true, false, s);
-    aim::launch_rwg_test(true, false, p->d_efie_src, nullptr, p->d_efie_vals, nullptr,
-                         p->d_efie_te, p->d_efie_rowptr, p->d_efie_col, p->d_efie_cc, nullptr,
-                         0.0, p->d_k, p->d_efie_freq, x, y, N, n, nrhs, s);
-  });
-}
-
 namespace {
 // The RWG double layer's tables on top of the EFIE's: the triangle pairs'
 // static gradient integrals and grid sums on the device, C_K and the Gram
@@ -1261,26 +1251,15 @@ void ensure_mfie(aim_plan p, hipStream_t s) {
     }
     aim::assemble_mfie_near(t, e, pv, p->mfie_ck, p->host_threads);
   }
-  std::vector<double> nrm(3 * size_t(t.N));
-  for (int64_t j = 0; j < t.N; ++j) {
-    const double* c = &t.corners[9 * j];
-    const double e1[3] = {c[3] - c[0], c[4] - c[1], c[5] - c[2]};
-    const double e2[3] = {c[6] - c[0], c[7] - c[1], c[8] - c[2]};
-    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                         e1[0] * e2[1] - e1[1] * e2[0]};
-    const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    for (int a = 0; a < 3; ++a) nrm[3 * j + a] = n[a] / l;
-  }
   const auto& g = p->g;
   const int R = p->max_rhs;
   p->d_mfie_ck = p->upload(p->mfie_ck, s);
-  p->d_mfie_nrm = p->upload(nrm, s);
   ensure_grad_spectra(p, s);
   p->d_mfie_grid = p->dalloc(size_t(6) * R * g.Ng * 16, s);
   p->d_mfie_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 6 * R, s);
   p->d_mfie_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 6 * R, s));
   AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_mfie_freq), sizeof(int32_t) * 6 * R, 0));
-  AIM_HIP(hipStreamSynchronize(s));  // nrm feeds an upload
+  AIM_HIP(hipStreamSynchronize(s));
   p->mfie_cur_freq.clear();
   p->mfie_ready = true;
   p->mfie_seconds = now_s() - t0;
@@ -1294,7 +1273,69 @@ void mfie_grid_stages(aim_plan p, int nrhs, hipStream_t s) {
                                p->sched[0]);
   aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, true, s);
 }
+
+// One product of an RWG operator (op 1: the EFIE, 2: the double layer
+// K + gram G, 3: the combined field Z + (j/k)(K + gram G)) on nrhs vectors,
+// vector r at wavenumber index fr[r]; the tables are built already.
+void rwg_matvec(aim_plan p, int op, const void* x, void* y, int nrhs,
+                const std::vector<int32_t>& fr, double gram, hipStream_t s) {
+  const bool efie = op == 1 || op == 3, dl = op == 2 || op == 3;
+  const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
+  aim::CsrDevice none{};
+  none.n = P;  // interpolation only: the near rows are the test kernel's
+  if (efie) stage_freq(fr, 4, p->efie_cur_freq, p->h_efie_freq, p->d_efie_freq, s);
+  if (dl) stage_freq(fr, 6, p->mfie_cur_freq, p->h_mfie_freq, p->d_mfie_freq, s);
+  if (efie) {
+    // the four channels; the double layer then takes its three current
+    // grids from this projection
+    aim::launch_efie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
+    aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
+                                p->d_efie_grid, 4 * nrhs, s);
+    if (dl) aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, false, s, p->d_efie_grid);
+    aim::launch_convolve<double>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid,
+                                 p->d_spec64, p->d_efie_freq, 4 * nrhs, p->d_tw64, s, nullptr,
+                                 p->sched[0]);
+    if (dl) {
+      aim::launch_convolve<double>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid,
+                                   p->d_dlp_spec, p->d_mfie_freq, 6 * nrhs, p->d_tw64, s, nullptr,
+                                   p->sched[0]);
+      aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, true, s);
+    }
+    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_efie_grid, nullptr,
+                                    p->d_efie_src, 4 * nrhs, true, false, s);
+    if (dl) {
+      if (!p->d_cfie_psi) p->d_cfie_psi = p->dalloc(size_t(3) * p->max_rhs * P * 16, s);
+      aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
+                                      p->d_cfie_psi, 3 * nrhs, true, false, s);
+    }
+    aim::launch_rwg_test(true, dl, p->d_efie_src, p->d_cfie_psi, p->d_efie_vals, p->d_mfie_nrm,
+                         p->d_efie_te, p->d_efie_rowptr, p->d_efie_col, p->d_efie_cc,
+                         p->d_mfie_ck, gram, p->d_k, p->d_efie_freq, x, y, N, n, nrhs, s);
+    return;
+  }
+  aim::launch_mfie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
+  aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
+                              p->d_mfie_grid, 3 * nrhs, s);
+  mfie_grid_stages(p, nrhs, s);
+  aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
+                                  p->d_efie_src, 3 * nrhs, true, false, s);
+  aim::launch_rwg_test(false, true, nullptr, p->d_efie_src, p->d_efie_vals, p->d_mfie_nrm,
+                       p->d_efie_te, p->d_efie_rowptr, p->d_efie_col, nullptr, p->d_mfie_ck,
+                       gram, p->d_k, p->d_mfie_freq, x, y, N, n, nrhs, s);
+}
 }  // namespace
+
+aim_status aim_matvec_efie(aim_plan p, const void* x, void* y, int32_t nrhs,
+                           const int32_t* freq_idx_host, void* hip_stream) {
+  if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    check_rwg_call(p, x, y, nrhs);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
+    ensure_efie(p, s);
+    rwg_matvec(p, 1, x, y, nrhs, fr, 0.0, s);
+  });
+}
 
 aim_status aim_matvec_mfie(aim_plan p, const void* x, void* y, int32_t nrhs,
                            const int32_t* freq_idx_host, double gram_coef, void* hip_stream) {
@@ -1305,19 +1346,7 @@ aim_status aim_matvec_mfie(aim_plan p, const void* x, void* y, int32_t nrhs,
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
     ensure_mfie(p, s);
-    stage_freq(fr, 6, p->mfie_cur_freq, p->h_mfie_freq, p->d_mfie_freq, s);
-    const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
-    aim::launch_mfie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
-    aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
-                                p->d_mfie_grid, 3 * nrhs, s);
-    mfie_grid_stages(p, nrhs, s);
-    aim::CsrDevice none{};
-    none.n = P;
-    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
-                                    p->d_efie_src, 3 * nrhs, true, false, s);
-    aim::launch_rwg_test(false, true, nullptr, p->d_efie_src, p->d_efie_vals, p->d_mfie_nrm,
-                         p->d_efie_te, p->d_efie_rowptr, p->d_efie_col, nullptr, p->d_mfie_ck,
-                         gram_coef, p->d_k, p->d_mfie_freq, x, y, N, n, nrhs, s);
+    rwg_matvec(p, 2, x, y, nrhs, fr, gram_coef, s);
   });
 }
 
@@ -1330,33 +1359,47 @@ aim_status aim_matvec_cfie(aim_plan p, const void* x, void* y, int32_t nrhs,
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
     ensure_mfie(p, s);
-    if (!p->d_cfie_psi) p->d_cfie_psi = p->dalloc(size_t(3) * p->max_rhs * 3 * p->t.N * 16, s);
-    stage_freq(fr, 4, p->efie_cur_freq, p->h_efie_freq, p->d_efie_freq, s);
-    stage_freq(fr, 6, p->mfie_cur_freq, p->h_mfie_freq, p->d_mfie_freq, s);
-    const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
-    // one projection of the four channels serves both operators: the
-    // double layer takes the three current grids from it
-    aim::launch_efie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
-    aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
-                                p->d_efie_grid, 4 * nrhs, s);
-    aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, false, s, p->d_efie_grid);
-    aim::launch_convolve<double>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid,
-                                 p->d_spec64, p->d_efie_freq, 4 * nrhs, p->d_tw64, s, nullptr,
-                                 p->sched[0]);
-    aim::launch_convolve<double>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid,
-                                 p->d_dlp_spec, p->d_mfie_freq, 6 * nrhs, p->d_tw64, s, nullptr,
-                                 p->sched[0]);
-    aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, true, s);
-    aim::CsrDevice none{};
-    none.n = P;
-    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_efie_grid, nullptr,
-                                    p->d_efie_src, 4 * nrhs, true, false, s);
-    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
-                                    p->d_cfie_psi, 3 * nrhs, true, false, s);
-    aim::launch_rwg_test(true, true, p->d_efie_src, p->d_cfie_psi, p->d_efie_vals,
-                         p->d_mfie_nrm, p->d_efie_te, p->d_efie_rowptr, p->d_efie_col,
-                         p->d_efie_cc, p->d_mfie_ck, gram_coef, p->d_k, p->d_efie_freq, x, y, N,
-                         n, nrhs, s);
+    rwg_matvec(p, 3, x, y, nrhs, fr, gram_coef, s);
+  });
+}
+
+aim_status aim_rwg_excitation(aim_plan p, int32_t field, const double* params, int32_t nrhs,
+                              const int32_t* freq_idx_host, void* b, void* hip_stream) {
+  if (!p || !params || !b) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  return guarded([&] {
+    efie_checks(p);
+    AIM_REQUIRE(field == 0 || field == 1, AIM_ERR_INVALID_ARG, "field must be 0 (E) or 1 (H)");
+    AIM_REQUIRE(nrhs >= 1 && nrhs <= p->max_rhs, AIM_ERR_INVALID_ARG,
+                "nrhs must be in 1..max_rhs (" + std::to_string(p->max_rhs) + ")");
+    std::vector<double> pr(params, params + size_t(6) * nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      double* d = &pr[6 * r];
+      for (int a = 0; a < 6; ++a)
+        AIM_REQUIRE(std::isfinite(d[a]), AIM_ERR_INVALID_ARG, "non-finite excitation parameter");
+      const double nn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      AIM_REQUIRE(nn > 0.0, AIM_ERR_INVALID_ARG, "zero plane-wave direction");
+      for (int a = 0; a < 3; ++a) d[a] /= nn;
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    ensure_efie(p, s);
+    const int32_t* df = set_freq(p, freq_idx_host, nrhs, s);
+    double* dpr = nullptr;
+    AIM_HIP(hipMalloc(&dpr, pr.size() * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(dpr, pr.data(), pr.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      try {
+        aim::launch_rwg_plane_wave(p->d_qpxyz, p->d_efie_vals, p->d_mfie_nrm, p->d_efie_te, dpr,
+                                   p->d_k, df, field, b, p->efie.n, nrhs, s);
+      } catch (...) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(dpr);
+        throw;
+      }
+      e = hipStreamSynchronize(s);
+    }
+    (void)hipFree(dpr);
+    AIM_HIP(e);
   });
 }
 
@@ -1754,10 +1797,15 @@ namespace {
 
 using cplx = std::complex<double>;
 
+// unknowns of the operator the solver applies
+int64_t op_n(aim_plan p) { return p->rwg_op ? p->efie.n : p->t.N; }
+
 void ensure_solver(aim_plan p, int nrhs, int m, hipStream_t s) {
   auto& w = p->sv;
-  const int64_t n = p->t.N;
-  if (w.nrhs >= nrhs && w.m >= m && w.n == n) return;
+  // vectors sized for the largest operator solved so far, so that solves
+  // of the scalar and the RWG operators share one workspace
+  const int64_t n = std::max(op_n(p), w.n);
+  if (w.nrhs >= nrhs && w.m >= m && w.n >= op_n(p)) return;
   p->graphs.clear();  // captured graphs point at the old staging buffers
   // buffers are never freed individually: the plan owns them until destroy
   const int R = std::max(nrhs, w.nrhs), M = std::max(m, w.m);
@@ -1845,6 +1893,10 @@ void graph_matvec(aim_plan p, aim_precision prec, const void* in, void* out, int
 
 void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, const int32_t* dfreq,
              hipStream_t s, const char* skip = nullptr) {
+  if (p->rwg_op) {  // an RWG operator (complex128; wavenumbers from the solve's list)
+    rwg_matvec(p, p->rwg_op, x, y, nrhs, p->rwg_fr, p->rwg_gram, s);
+    return;
+  }
   const int64_t cnt = p->t.N * int64_t(nrhs);
   if (skip && p->batch) {  // direct launches, stopped instances skipped, padding left
     if (prec == AIM_C128) {
@@ -2031,7 +2083,7 @@ void apply_M(aim_plan p, aim_pc_kind pc, const void* v, void* z, int nrhs, const
 }
 
 void norms_host(aim_plan p, const void* v, int nrhs, hipStream_t s, std::vector<double>& out) {
-  aim::launch_norms(v, p->t.N, nrhs, p->sv.partial, p->sv.nrm, s);
+  aim::launch_norms(v, op_n(p), nrhs, p->sv.partial, p->sv.nrm, s);
   AIM_HIP(hipMemcpyAsync(p->sv.nrm_host, p->sv.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
   AIM_HIP(hipStreamSynchronize(s));
   out.assign(p->sv.nrm_host, p->sv.nrm_host + nrhs);
@@ -2070,7 +2122,7 @@ void gmres_batch(aim_plan p, aim_precision prec, aim_pc_kind pc, const void* b, 
   auto tol_of = [&](int r) { return tols ? (*tols)[r] : tol; };
   std::vector<double> prev_rel;
   auto& w = p->sv;
-  const int64_t n = p->t.N;
+  const int64_t n = op_n(p);
   const size_t vec = size_t(n) * 16;
   // basis layout [i][r][n]: the i-th vectors of all systems are contiguous
   const int64_t si = nrhs, sr = 1;
@@ -2389,6 +2441,72 @@ extern "C" aim_status aim_solve(aim_plan p, const void* b, void* x, int32_t nrhs
     const double secs = now_s() - t0;
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
+      inf[r].rel_resid = rel[r];
+      inf[r].converged = rel[r] <= o.rtol ? 1 : 0;
+      inf[r].seconds = secs;
+      all = all && inf[r].converged;
+    }
+    std::memcpy(info, inf.data(), sizeof(aim_solve_info) * nrhs);
+    if (!all) result = AIM_ERR_NOT_CONVERGED;
+  });
+  if (st != AIM_OK) return st;
+  if (result != AIM_OK) return fail(result, "not every right-hand side reached rtol");
+  return AIM_OK;
+}
+
+// Krylov solves of the RWG operators (the same batched GMRES as aim_solve)
+extern "C" aim_status aim_solve_rwg(aim_plan p, int32_t op, double gram_coef, const void* b,
+                                    void* x, int32_t nrhs, const int32_t* freq_idx_host,
+                                    const aim_solve_opts* opts, aim_solve_info* info,
+                                    void* hip_stream) {
+  if (!p || !b || !x || !opts || !info) return fail(AIM_ERR_INVALID_ARG, "null argument");
+  aim_status result = AIM_OK;
+  const aim_status st = guarded([&] {
+    const aim_solve_opts& o = *opts;
+    AIM_REQUIRE(op >= 1 && op <= 3, AIM_ERR_INVALID_ARG, "op must be 1 (EFIE), 2 or 3");
+    AIM_REQUIRE(std::isfinite(gram_coef), AIM_ERR_INVALID_ARG, "gram_coef must be finite");
+    AIM_REQUIRE(o.rtol > 0.0 && std::isfinite(o.rtol), AIM_ERR_INVALID_ARG, "rtol must be positive");
+    AIM_REQUIRE(o.restart >= 1 && o.restart <= 200, AIM_ERR_INVALID_ARG, "restart must be in 1..200");
+    AIM_REQUIRE(o.max_iter >= 1, AIM_ERR_INVALID_ARG, "max_iter must be >= 1");
+    AIM_REQUIRE(o.pc == AIM_PC_NONE && o.inner == AIM_C128, AIM_ERR_INVALID_ARG,
+                "the RWG operators are solved unpreconditioned in complex128");
+    check_rwg_call(p, b, x, nrhs);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
+    if (op == 1) ensure_efie(p, s);
+    else ensure_mfie(p, s);
+    // the Krylov loop applies this operator for the duration of the call
+    struct Restore {
+      aim_plan q;
+      ~Restore() { q->rwg_op = 0; }
+    } restore{p};
+    p->rwg_op = op;
+    p->rwg_gram = gram_coef;
+    p->rwg_fr = fr;
+    const double t0 = now_s();
+    ensure_solver(p, nrhs, o.restart, s);
+    auto& w = p->sv;
+    const size_t vec = size_t(p->efie.n) * 16;
+    std::vector<double> bn;
+    norms_host(p, b, nrhs, s, bn);
+    for (int r = 0; r < nrhs; ++r)
+      AIM_REQUIRE(std::isfinite(bn[r]), AIM_ERR_BREAKDOWN, "non-finite right-hand side");
+    std::vector<double> scale(nrhs);
+    for (int r = 0; r < nrhs; ++r) scale[r] = bn[r] > 0.0 ? bn[r] : 1.0;
+    AIM_HIP(hipMemcpyAsync(w.xp, x, vec * nrhs, hipMemcpyDeviceToDevice, s));
+    CycleStats cs;
+    std::vector<double> rel;
+    gmres_batch(p, AIM_C128, AIM_PC_NONE, b, w.xp, nrhs, set_freq(p, freq_idx_host, nrhs, s),
+                scale, o.rtol, o.restart, o.max_iter, false, s, cs, rel);
+    AIM_HIP(hipMemcpyAsync(x, w.xp, vec * nrhs, hipMemcpyDeviceToDevice, s));
+    AIM_HIP(hipStreamSynchronize(s));
+    const double secs = now_s() - t0;
+    std::vector<aim_solve_info> inf(nrhs);
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+      std::memset(&inf[r], 0, sizeof(aim_solve_info));
+      inf[r].iters = cs.iters[r];
+      inf[r].matvecs = cs.matvecs;
       inf[r].rel_resid = rel[r];
       inf[r].converged = rel[r] <= o.rtol ? 1 : 0;
       inf[r].seconds = secs;

@@ -272,13 +272,21 @@ void launch_mfie_sources(const void* x, const double* vals, const int32_t* tri_r
 void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s,
                          const void* j_in = nullptr);  // currents from other grids (copied)
 // y for the EFIE (efie), the double layer (mfie) or the combined field of
-// eq. CFIEAIMx (both: y = y_E - (j/k_r) y_M), from psi_e [4][nrhs][3N] and
+// eq. CFIEAIMx (both: y = y_E + (j/k_r) y_M), from psi_e [4][nrhs][3N] and
 // psi_m [3][nrhs][3N]; cc = (C_A, C_phi), ck = (C_K, G) interleaved
 void launch_rwg_test(bool efie, bool mfie, const void* psi_e, const void* psi_m,
                      const double* vals, const double* nrm, const int32_t* rwg_te,
                      const int32_t* rowptr, const int32_t* col, const double* cc,
                      const double* ck, double beta, const double* kv, const int32_t* rhs_freq,
                      const void* x, void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
+
+// plane waves tested with the RWG functions (3-point rule): b[r][m] =
+// <f_m, pol_r e^{-j k d_r . r}> (field 0) or <f_m, n x (d_r x pol_r)
+// e^{-j k d_r . r}> (field 1), prm [nrhs][6] = (unit d, pol) on the device
+void launch_rwg_plane_wave(const double* qp, const double* vals, const double* nrm,
+                           const int32_t* rwg_te, const double* prm, const double* kv,
+                           const int32_t* rhs_freq, int field, void* b, int64_t nrwg, int nrhs,
+                           hipStream_t s);
 
 void launch_excitation(int kind, const double* qp_xyz, const double* qp_w, int64_t n,
                        const double* params, int n_params, const double* kvals,

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void mfie_combine_kernel(double2* __restrict__
 // three points each) its channel values against the interpolated fields --
 // EFIE: sum_c (w f_c) psi_c - k^-2 (w div f) psi_q; double layer:
 // (w f x n) . V -- plus its near row: (C_A - k^-2 C_phi) x and
-// (C_K + beta G) x.  Combined: y = y_E - (j/k) y_M.  LPR lanes per function:
+// (C_K + beta G) x.  Combined: y = y_E + (j/k) y_M.  LPR lanes per function:
 // lanes 0..5 take one point each, every lane strides over the near row, a
 // fixed butterfly sums them (fixed order: deterministic).  RB right-hand
 // sides per workgroup, so each near entry and channel value is loaded once.
@@ -224,10 +224,10 @@ __global__ __launch_bounds__(256) void rwg_test_kernel(
           const double ik2 = 1.0 / (k * k);
           yr = ar[j] - ik2 * qr[j];
           yi = ai[j] - ik2 * qi[j];
-          if constexpr (M) {  // - (j/k)(mr + j mi) = (mi - j mr)/k
+          if constexpr (M) {  // + (j/k)(mr + j mi) = (-mi + j mr)/k
             const double ik = 1.0 / k;
-            yr += ik * mi[j];
-            yi -= ik * mr[j];
+            yr -= ik * mi[j];
+            yi += ik * mr[j];
           }
         } else {
           yr = mr[j];
@@ -238,7 +238,57 @@ __global__ __launch_bounds__(256) void rwg_test_kernel(
   }
 }
 
+// b[r][m]: the plane wave pol_r e^{-j k_r d_r . r} tested with function m by
+// the 3-point rule over its two triangles: field 0 <f_m, E>, field 1
+// <f_m, n x (d x E)>; prm [nrhs][6] = (d unit, pol)
+__global__ __launch_bounds__(256) void rwg_plane_wave_kernel(
+    const double* __restrict__ qp, const double* __restrict__ vals,
+    const double* __restrict__ nrm, const int32_t* __restrict__ rwg_te,
+    const double* __restrict__ prm, const double* __restrict__ kv,
+    const int32_t* __restrict__ rhs_freq, int field, double2* __restrict__ b, int64_t nrwg) {
+  const int r = blockIdx.y;
+  const double* pr = prm + 6 * r;
+  const double k = kv[rhs_freq[r]];
+  for (int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; m < nrwg;
+       m += int64_t(gridDim.x) * blockDim.x) {
+    double br = 0.0, bi = 0.0;
+    for (int side = 0; side < 2; ++side) {
+      const int64_t t = rwg_te[4 * m + 2 * side];
+      const int e = rwg_te[4 * m + 2 * side + 1];
+      double vx = pr[3], vy = pr[4], vz = pr[5];
+      if (field == 1) {  // n x (d x pol)
+        const double cx = pr[1] * pr[5] - pr[2] * pr[4], cy = pr[2] * pr[3] - pr[0] * pr[5],
+                     cz = pr[0] * pr[4] - pr[1] * pr[3];
+        const double* n = nrm + 3 * t;
+        vx = n[1] * cz - n[2] * cy;
+        vy = n[2] * cx - n[0] * cz;
+        vz = n[0] * cy - n[1] * cx;
+      }
+      for (int q = 0; q < 3; ++q) {
+        const double* x = qp + 3 * (3 * t + q);
+        const double* v = vals + 36 * t + 12 * q + 4 * e;
+        const double a = v[0] * vx + v[1] * vy + v[2] * vz;
+        double sn, cs;
+        sincos(k * (pr[0] * x[0] + pr[1] * x[1] + pr[2] * x[2]), &sn, &cs);
+        br += a * cs;
+        bi -= a * sn;
+      }
+    }
+    b[int64_t(r) * nrwg + m] = make_double2(br, bi);
+  }
+}
+
 }  // namespace
+
+void launch_rwg_plane_wave(const double* qp, const double* vals, const double* nrm,
+                           const int32_t* rwg_te, const double* prm, const double* kv,
+                           const int32_t* rhs_freq, int field, void* b, int64_t nrwg, int nrhs,
+                           hipStream_t s) {
+  if (nrwg == 0) return;
+  hipLaunchKernelGGL(rwg_plane_wave_kernel, dim3(blocks(nrwg), nrhs), dim3(256), 0, s, qp, vals,
+                     nrm, rwg_te, prm, kv, rhs_freq, field, static_cast<double2*>(b), nrwg);
+  AIM_HIP(hipGetLastError());
+}
 
 void launch_mfie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {

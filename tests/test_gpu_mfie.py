@@ -109,7 +109,7 @@ def test_large_sphere_sampled_rows():
 
 
 def test_combined_field_operator():
-    """eq. CFIEAIMx: Z x - (j/k)(K + beta G) x from one call, against the two
+    """eq. CFIEAIMx: Z x + (j/k)(K + beta G) x from one call, against the two
     oracles on sampled rows, several vectors at two wavenumbers."""
     w = I.sphere_tiny(level=2, dims=(16, 16, 16), h=0.1)
     ks = [2 * math.pi, 8.5]
@@ -125,14 +125,14 @@ def test_combined_field_operator():
     rows = np.arange(0, m.n, 6)
     for r in range(3):
         k = ks[freq[r]]
-        ref = e.matvec_rows(x[r], k, rows) - 1j / k * m.matvec_rows(x[r], k, rows, -0.5)
+        ref = e.matvec_rows(x[r], k, rows) + 1j / k * m.matvec_rows(x[r], k, rows, -0.5)
         assert np.max(np.abs(y[r][rows] - ref)) <= TOL_Y * np.max(np.abs(ref)), r
     # the separate operators' calls agree with the combined one on every row
     xe = torch.from_numpy(x).cuda()
     ye = p.matvec_efie(xe, freq_idx=freq).cpu().numpy()
     ym = p.matvec_mfie(xe, freq_idx=freq, gram_coef=-0.5).cpu().numpy()
     kk = np.array([ks[f] for f in freq])[:, None]
-    comb = ye - 1j / kk * ym
+    comb = ye + 1j / kk * ym
     assert np.max(np.abs(y - comb)) <= 1e-13 * np.max(np.abs(comb))
     p.close()
 
