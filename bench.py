@@ -688,6 +688,27 @@ def efie_leg(reps: int = 20) -> dict:
                   file=sys.stderr, flush=True)
     xs = torch.from_numpy(I.complex_gaussian(p.n, w.seed_base)).cuda()
     res["scalar_ms_per_matvec"] = timed(p.matvec, xs, torch.empty_like(xs))
+    # a scattering solve as the paper runs it (Sec. V: the CFIE, GMRES): a
+    # plane wave along +z polarised along x, to 1e-6, unpreconditioned; the
+    # EFIE beside it
+    k = float(w.k[0])
+    bE = p.rwg_excitation([0, 0, 1], [1, 0, 0], field="E")
+    bH = p.rwg_excitation([0, 0, 1], [1, 0, 0], field="H")
+    solves = {}
+    for op, rhs in (("cfie", (bE + bH) / (1j * k)), ("efie", bE / (1j * k))):
+        t0 = time.perf_counter()
+        xs_, r = p.solve_rwg(op, rhs, gram_coef=-0.5, rtol=1e-6, restart=100, max_iter=3000,
+                             raise_on_fail=False)
+        torch.cuda.synchronize()
+        solves[op] = {"seconds": time.perf_counter() - t0, "iters": int(r.iters[0]),
+                      "rel_resid": float(r.rel_resid[0]), "converged": bool(r.converged[0])}
+        if op == "cfie":
+            xc = xs_
+        else:
+            solves["current_difference_cfie_vs_efie"] = float(
+                torch.linalg.vector_norm(xs_ - xc) / torch.linalg.vector_norm(xs_))
+        print(f"[bench] {op} solve on {w.name}: {solves[op]}", file=sys.stderr, flush=True)
+    res["plane_wave_solves"] = solves
     res["note"] = ("complex128; EFIE: three current channels and one charge channel projected "
                    "from the quadrature points and convolved with the plan's spectrum (4 grids "
                    "per vector); double layer (K - G/2): three current channels and their grid "
