@@ -137,6 +137,26 @@ def test_combined_field_operator():
     p.close()
 
 
+def test_combined_field_large_sphere_sampled_rows():
+    """The combined field on the 81,920-triangle sphere (the double layer
+    takes its currents from the EFIE's projection): sampled rows against the
+    two oracles."""
+    w = I.efie_sphere()
+    print(f"[gpu] combined field, {w.name}, sampled rows", flush=True)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    e = efie.EfieOracle(o)
+    m = mfie.MfieOracle(e)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
+                     max_rhs=1, precisions=("c128",))
+    k = float(w.k[0])
+    rows = np.sort(np.random.default_rng(77).choice(m.n, 10, replace=False))
+    x = I.complex_gaussian(m.n, 78)
+    y = p.matvec_cfie(torch.from_numpy(x).cuda(), gram_coef=-0.5).cpu().numpy()
+    ref = e.matvec_rows(x, k, rows) + 1j / k * m.matvec_rows(x, k, rows, -0.5)
+    assert np.linalg.norm(y[rows] - ref) <= TOL_Y * np.linalg.norm(ref)
+    p.close()
+
+
 def test_needs_the_mesh(tmp_path):
     w = I.sphere_tiny()
     p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
