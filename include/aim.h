@@ -383,17 +383,19 @@ aim_status aim_dlp_export(aim_plan plan, double* near_host, double* corr_host,
  * the mesh (AIM_ERR_STATE on loaded, host-only or batch plans); the device
  * buffers hold 4 max_rhs point-source vectors, grids and convolution
  * workspaces.
- * aim_matvec_efie: y = Z(k_f) x, x_dev and y_dev [nrhs][n_rwg] complex128
- * device buffers (caller-owned, not overlapping), freq_idx_host [nrhs]
- * indices into the plan's wavenumbers (NULL: all 0); asynchronous on
- * hip_stream.
+ * aim_matvec_efie: y = Z(k_f) x, x_dev and y_dev [nrhs][n_rwg] device
+ * buffers of the precision prec (caller-owned, not overlapping), freq_idx_host
+ * [nrhs] indices into the plan's wavenumbers (NULL: all 0); asynchronous on
+ * hip_stream.  AIM_C64 (the plan needs complex64 tables) runs the sources,
+ * projection, FFTs, interpolation and near rows in complex64 with the
+ * tables rounded from the complex128 ones.
  * aim_efie_export copies to the host, each pointer optional: tri_rwg [N][3]
  * (function on the edge opposite vertex e of triangle t, -1 none), the near
  * list rowptr [n_rwg + 1] and col [nnz], and C_A, C_phi [nnz]; blocking. */
 aim_status aim_efie_setup(aim_plan plan, int64_t* n_rwg, int64_t* nnz, double* seconds,
                           void* hip_stream);
-aim_status aim_matvec_efie(aim_plan plan, const void* x_dev, void* y_dev, int32_t nrhs,
-                           const int32_t* freq_idx_host, void* hip_stream);
+aim_status aim_matvec_efie(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
+                           int32_t nrhs, const int32_t* freq_idx_host, void* hip_stream);
 aim_status aim_efie_export(aim_plan plan, int32_t* tri_rwg, int32_t* rowptr, int32_t* col,
                            double* ca, double* cphi, void* hip_stream);
 
@@ -418,14 +420,15 @@ aim_status aim_efie_export(aim_plan plan, int32_t* tri_rwg, int32_t* rowptr, int
  * interpolated, tested with w_q f_m(r_q) x n; static entries from the
  * closed form of int (r - r')/R^3 over a triangle and the 3-point outer
  * rule, precorrection with the grid's static gradient samples.  x_dev,
- * y_dev [nrhs][n_rwg] complex128 (caller-owned, not overlapping);
- * freq_idx_host as for aim_matvec_efie.  The first call builds the EFIE's
+ * y_dev [nrhs][n_rwg] of precision prec (caller-owned, not overlapping);
+ * prec and freq_idx_host as for aim_matvec_efie.  The first call builds the EFIE's
  * tables if needed, then its own (blocking); asynchronous after that.
  * aim_mfie_export copies C_K = K_s,NR - K_s,P and G on the RWG near list
  * (order of aim_efie_export) to the host, and the build time; each pointer
  * optional; blocking.  Same plan requirements as the EFIE. */
-aim_status aim_matvec_mfie(aim_plan plan, const void* x_dev, void* y_dev, int32_t nrhs,
-                           const int32_t* freq_idx_host, double gram_coef, void* hip_stream);
+aim_status aim_matvec_mfie(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
+                           int32_t nrhs, const int32_t* freq_idx_host, double gram_coef,
+                           void* hip_stream);
 aim_status aim_mfie_export(aim_plan plan, double* ck_host, double* gram_host, double* seconds,
                            void* hip_stream);
 
@@ -441,8 +444,9 @@ aim_status aim_mfie_export(aim_plan plan, double* ck_host, double* gram_host, do
  * serves both operators: the double layer takes its three current grids
  * from it.  Arguments and rules as for aim_matvec_mfie; the first call
  * builds both operators' tables and a [3 max_rhs][3N] field buffer. */
-aim_status aim_matvec_cfie(aim_plan plan, const void* x_dev, void* y_dev, int32_t nrhs,
-                           const int32_t* freq_idx_host, double gram_coef, void* hip_stream);
+aim_status aim_matvec_cfie(aim_plan plan, aim_precision prec, const void* x_dev, void* y_dev,
+                           int32_t nrhs, const int32_t* freq_idx_host, double gram_coef,
+                           void* hip_stream);
 
 /* Plane waves tested with the RWG functions (3-point rule per triangle):
  * params_host [nrhs][6] = (d, pol) with d the propagation direction

@@ -129,9 +129,9 @@ def load_library(path: str = LIB_PATH):
     lib.aim_dlp_export.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
     lib.aim_efie_setup.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double), vp]
-    lib.aim_matvec_efie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), vp]
-    lib.aim_matvec_mfie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
-    lib.aim_matvec_cfie.argtypes = [vp, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
+    lib.aim_matvec_efie.argtypes = [vp, i32, vp, vp, i32, C.POINTER(C.c_int32), vp]
+    lib.aim_matvec_mfie.argtypes = [vp, i32, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
+    lib.aim_matvec_cfie.argtypes = [vp, i32, vp, vp, i32, C.POINTER(C.c_int32), C.c_double, vp]
     lib.aim_rwg_excitation.argtypes = [vp, i32, C.POINTER(C.c_double), i32,
                                        C.POINTER(C.c_int32), vp, vp]
     lib.aim_solve_rwg.argtypes = [vp, i32, C.c_double, vp, vp, i32, C.POINTER(C.c_int32),
@@ -659,47 +659,49 @@ class Plan:
                                         _stream_ptr(stream)))
         return {"n_rwg": int(n.value), "nnz": int(nnz.value), "seconds": float(sec.value)}
 
-    def matvec_efie(self, x, freq_idx=None, out=None, stream=None):
-        """y = Z x, the RWG EFIE operator under AIMx (complex128, x of
-        [n_rwg] or [nrhs, n_rwg])."""
+    def matvec_efie(self, x, freq_idx=None, out=None, stream=None, prec: str = "c128"):
+        """y = Z x, the RWG EFIE operator under AIMx (x of [n_rwg] or
+        [nrhs, n_rwg], complex128 or, with prec="c64", complex64)."""
         import torch
         n = self.efie_setup(stream)["n_rwg"]
-        self._check_vec(x, "c128", n, "x")
+        self._check_vec(x, prec, n, "x")
         nrhs = 1 if x.dim() == 1 else x.shape[0]
         y = torch.empty_like(x) if out is None else out
-        self._check_vec(y, "c128", n, "out")
+        self._check_vec(y, prec, n, "out")
         _, fp = _freq_arg(freq_idx, nrhs)
-        _check(self._lib.aim_matvec_efie(self._plan, C.c_void_p(x.data_ptr()),
+        _check(self._lib.aim_matvec_efie(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
                                          C.c_void_p(y.data_ptr()), nrhs, fp,
                                          _stream_ptr(stream)))
         return y
 
-    def matvec_mfie(self, x, freq_idx=None, gram_coef: float = 0.0, out=None, stream=None):
-        """y = (K + gram_coef G) x, the RWG double layer under AIMx
-        (complex128, x of [n_rwg] or [nrhs, n_rwg])."""
+    def matvec_mfie(self, x, freq_idx=None, gram_coef: float = 0.0, out=None, stream=None,
+                    prec: str = "c128"):
+        """y = (K + gram_coef G) x, the RWG double layer under AIMx (x of
+        [n_rwg] or [nrhs, n_rwg], complex128 or complex64)."""
         import torch
         n = self.efie_setup(stream)["n_rwg"]
-        self._check_vec(x, "c128", n, "x")
+        self._check_vec(x, prec, n, "x")
         nrhs = 1 if x.dim() == 1 else x.shape[0]
         y = torch.empty_like(x) if out is None else out
-        self._check_vec(y, "c128", n, "out")
+        self._check_vec(y, prec, n, "out")
         _, fp = _freq_arg(freq_idx, nrhs)
-        _check(self._lib.aim_matvec_mfie(self._plan, C.c_void_p(x.data_ptr()),
+        _check(self._lib.aim_matvec_mfie(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
                                          C.c_void_p(y.data_ptr()), nrhs, fp,
                                          float(gram_coef), _stream_ptr(stream)))
         return y
 
-    def matvec_cfie(self, x, freq_idx=None, gram_coef: float = 0.0, out=None, stream=None):
-        """y = Z x - (j/k)(K + gram_coef G) x, the combined-field operator
-        (complex128, x of [n_rwg] or [nrhs, n_rwg])."""
+    def matvec_cfie(self, x, freq_idx=None, gram_coef: float = 0.0, out=None, stream=None,
+                    prec: str = "c128"):
+        """y = Z x + (j/k)(K + gram_coef G) x, the combined-field operator
+        (x of [n_rwg] or [nrhs, n_rwg], complex128 or complex64)."""
         import torch
         n = self.efie_setup(stream)["n_rwg"]
-        self._check_vec(x, "c128", n, "x")
+        self._check_vec(x, prec, n, "x")
         nrhs = 1 if x.dim() == 1 else x.shape[0]
         y = torch.empty_like(x) if out is None else out
-        self._check_vec(y, "c128", n, "out")
+        self._check_vec(y, prec, n, "out")
         _, fp = _freq_arg(freq_idx, nrhs)
-        _check(self._lib.aim_matvec_cfie(self._plan, C.c_void_p(x.data_ptr()),
+        _check(self._lib.aim_matvec_cfie(self._plan, PREC[prec], C.c_void_p(x.data_ptr()),
                                          C.c_void_p(y.data_ptr()), nrhs, fp,
                                          float(gram_coef), _stream_ptr(stream)))
         return y

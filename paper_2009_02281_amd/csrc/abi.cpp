@@ -204,6 +204,13 @@ struct aim_plan_s {
   int32_t* d_mfie_freq = nullptr;   // [6 max_rhs]
   int32_t* h_mfie_freq = nullptr;   // pinned staging
   void* d_cfie_psi = nullptr;       // [3 max_rhs][3N] the double layer's field (combined call)
+  // complex64 copies of the RWG tables (plans with complex64 tables)
+  float* d_efie_vals32 = nullptr;
+  float* d_efie_cc32 = nullptr;
+  float* d_mfie_ck32 = nullptr;
+  float* d_mfie_nrm32 = nullptr;
+  aim::CsrDevice efie_p32{}, efie_pt32{};
+  void* d_dlp_spec32 = nullptr;     // complex64 spectra of the radial factor F
   // the operator the Krylov solver applies: 0 the plan's scalar operator,
   // else an RWG operator (aim_solve_rwg sets it for the duration of a solve)
   int rwg_op = 0;
@@ -988,12 +995,16 @@ void ensure_grad_spectra(aim_plan p, hipStream_t s) {
   if (p->d_dlp_spec) return;
   const auto& g = p->g;
   void* spec = p->dalloc(size_t(g.Nfold) * 16 * p->nfreq, s);
+  // and its complex64 rounding when the plan has complex64 tables
+  void* spec32 = (p->prec & (1u << AIM_C64)) ? p->dalloc(size_t(g.Nfold) * 8 * p->nfreq, s)
+                                             : nullptr;
   void* full = nullptr;
   AIM_HIP(hipMalloc(&full, size_t(8) * g.Ng * 16));
   try {
     for (int f = 0; f < p->nfreq; ++f)
       aim::launch_spectrum(g, p->k[f], p->t.h, full,
-                           static_cast<char*>(spec) + size_t(f) * g.Nfold * 16, nullptr,
+                           static_cast<char*>(spec) + size_t(f) * g.Nfold * 16,
+                           spec32 ? static_cast<char*>(spec32) + size_t(f) * g.Nfold * 8 : nullptr,
                            p->d_tw64, s, 1);
     AIM_HIP(hipStreamSynchronize(s));
   } catch (...) {
@@ -1003,6 +1014,7 @@ void ensure_grad_spectra(aim_plan p, hipStream_t s) {
   }
   AIM_HIP(hipFree(full));
   p->d_dlp_spec = spec;
+  p->d_dlp_spec32 = spec32;
 }
 
 // The double-layer operator's tables (Sec. III-B): unit normals, C_K on the
@@ -1162,6 +1174,22 @@ void ensure_efie(aim_plan p, hipStream_t s) {
   p->efie_pt.col = p->upload(e.pt_col, s);
   p->efie_pt.val = p->upload(e.pt_val, s);
   p->efie_pt.n = P;
+  if (p->prec & (1u << AIM_C64)) {
+    auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+    p->d_efie_vals32 = p->upload(f32(e.vals), s);
+    std::vector<float> cc32(2 * std::max<size_t>(e.ca.size(), 1), 0.0f);
+    for (size_t j = 0; j < e.ca.size(); ++j) {
+      cc32[2 * j] = float(e.ca[j]);
+      cc32[2 * j + 1] = float(e.cphi[j]);
+    }
+    p->d_efie_cc32 = p->upload(cc32, s);
+    p->d_mfie_nrm32 = p->upload(f32(nrm), s);
+    p->efie_p32 = p->efie_p;
+    p->efie_p32.val = p->upload(f32(e.p_val), s);
+    p->efie_pt32 = p->efie_pt;
+    p->efie_pt32.val = p->upload(f32(e.pt_val), s);
+    AIM_HIP(hipStreamSynchronize(s));  // the float vectors are temporaries
+  }
   p->d_efie_src = p->dalloc(size_t(4) * R * P * 16, s);
   p->d_efie_grid = p->dalloc(size_t(4) * R * g.Ng * 16, s);
   p->d_efie_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 4 * R, s);
@@ -1254,6 +1282,10 @@ void ensure_mfie(aim_plan p, hipStream_t s) {
   const auto& g = p->g;
   const int R = p->max_rhs;
   p->d_mfie_ck = p->upload(p->mfie_ck, s);
+  if (p->prec & (1u << AIM_C64)) {
+    p->d_mfie_ck32 = p->upload(std::vector<float>(p->mfie_ck.begin(), p->mfie_ck.end()), s);
+    AIM_HIP(hipStreamSynchronize(s));
+  }
   ensure_grad_spectra(p, s);
   p->d_mfie_grid = p->dalloc(size_t(6) * R * g.Ng * 16, s);
   p->d_mfie_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 6 * R, s);
@@ -1265,101 +1297,120 @@ void ensure_mfie(aim_plan p, hipStream_t s) {
   p->mfie_seconds = now_s() - t0;
 }
 
-// moments, the six convolutions with the radial factor, the field
-void mfie_grid_stages(aim_plan p, int nrhs, hipStream_t s) {
-  aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, false, s);
-  aim::launch_convolve<double>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid,
-                               p->d_dlp_spec, p->d_mfie_freq, 6 * nrhs, p->d_tw64, s, nullptr,
-                               p->sched[0]);
-  aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, true, s);
-}
-
 // One product of an RWG operator (op 1: the EFIE, 2: the double layer
 // K + gram G, 3: the combined field Z + (j/k)(K + gram G)) on nrhs vectors,
-// vector r at wavenumber index fr[r]; the tables are built already.
-void rwg_matvec(aim_plan p, int op, const void* x, void* y, int nrhs,
-                const std::vector<int32_t>& fr, double gram, hipStream_t s) {
+// vector r at wavenumber index fr[r], in complex128 (T = double) or
+// complex64 (T = float); the tables are built already.
+extern "C++" {
+template <typename T>
+void rwg_matvec_t(aim_plan p, int op, const void* x, void* y, int nrhs,
+                  const std::vector<int32_t>& fr, double gram, hipStream_t s) {
+  constexpr bool dbl = sizeof(T) == 8;
   const bool efie = op == 1 || op == 3, dl = op == 2 || op == 3;
   const int64_t N = p->t.N, P = 3 * N, n = p->efie.n;
+  const int pi = dbl ? int(AIM_C128) : int(AIM_C64);
+  const void* vals = dbl ? static_cast<const void*>(p->d_efie_vals) : p->d_efie_vals32;
+  const void* nrm = dbl ? static_cast<const void*>(p->d_mfie_nrm) : p->d_mfie_nrm32;
+  const void* cc = dbl ? static_cast<const void*>(p->d_efie_cc) : p->d_efie_cc32;
+  const void* ck = dbl ? static_cast<const void*>(p->d_mfie_ck) : p->d_mfie_ck32;
+  const aim::CsrDevice& Pp = dbl ? p->efie_p : p->efie_p32;
+  const aim::CsrDevice& Pt = dbl ? p->efie_pt : p->efie_pt32;
+  const void* spec = dbl ? p->d_spec64 : p->d_spec32;
+  const void* gspec = dbl ? p->d_dlp_spec : p->d_dlp_spec32;
+  void* const* tw = dbl ? p->d_tw64 : p->d_tw32;
+  const int* sched = p->sched[pi];
   aim::CsrDevice none{};
   none.n = P;  // interpolation only: the near rows are the test kernel's
   if (efie) stage_freq(fr, 4, p->efie_cur_freq, p->h_efie_freq, p->d_efie_freq, s);
   if (dl) stage_freq(fr, 6, p->mfie_cur_freq, p->h_mfie_freq, p->d_mfie_freq, s);
+  if (dl && !p->d_cfie_psi) p->d_cfie_psi = p->dalloc(size_t(3) * p->max_rhs * P * 16, s);
   if (efie) {
     // the four channels; the double layer then takes its three current
     // grids from this projection
-    aim::launch_efie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
-    aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
-                                p->d_efie_grid, 4 * nrhs, s);
-    if (dl) aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, false, s, p->d_efie_grid);
-    aim::launch_convolve<double>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid,
-                                 p->d_spec64, p->d_efie_freq, 4 * nrhs, p->d_tw64, s, nullptr,
-                                 p->sched[0]);
+    aim::launch_efie_sources<T>(x, vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
+    aim::launch_project<T>(p->g, Pp, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
+                           p->d_efie_grid, 4 * nrhs, s);
+    if (dl) aim::launch_mfie_moments<T>(p->g, p->d_mfie_grid, nrhs, false, s, p->d_efie_grid);
+    aim::launch_convolve<T>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid, spec,
+                            p->d_efie_freq, 4 * nrhs, tw, s, nullptr, sched);
     if (dl) {
-      aim::launch_convolve<double>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid,
-                                   p->d_dlp_spec, p->d_mfie_freq, 6 * nrhs, p->d_tw64, s, nullptr,
-                                   p->sched[0]);
-      aim::launch_mfie_moments(p->g, p->d_mfie_grid, nrhs, true, s);
+      aim::launch_convolve<T>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid, gspec,
+                              p->d_mfie_freq, 6 * nrhs, tw, s, nullptr, sched);
+      aim::launch_mfie_moments<T>(p->g, p->d_mfie_grid, nrhs, true, s);
     }
-    aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_efie_grid, nullptr,
-                                    p->d_efie_src, 4 * nrhs, true, false, s);
-    if (dl) {
-      if (!p->d_cfie_psi) p->d_cfie_psi = p->dalloc(size_t(3) * p->max_rhs * P * 16, s);
-      aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
-                                      p->d_cfie_psi, 3 * nrhs, true, false, s);
-    }
-    aim::launch_rwg_test(true, dl, p->d_efie_src, p->d_cfie_psi, p->d_efie_vals, p->d_mfie_nrm,
-                         p->d_efie_te, p->d_efie_rowptr, p->d_efie_col, p->d_efie_cc,
-                         p->d_mfie_ck, gram, p->d_k, p->d_efie_freq, x, y, N, n, nrhs, s);
+    aim::launch_interp_near<T>(p->g, Pt, none, p->d_efie_grid, nullptr, p->d_efie_src, 4 * nrhs,
+                               true, false, s);
+    if (dl)
+      aim::launch_interp_near<T>(p->g, Pt, none, p->d_mfie_grid, nullptr, p->d_cfie_psi,
+                                 3 * nrhs, true, false, s);
+    aim::launch_rwg_test<T>(true, dl, p->d_efie_src, p->d_cfie_psi, vals, nrm, p->d_efie_te,
+                            p->d_efie_rowptr, p->d_efie_col, cc, ck, gram, p->d_k,
+                            p->d_efie_freq, x, y, N, n, nrhs, s);
     return;
   }
-  aim::launch_mfie_sources(x, p->d_efie_vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
-  aim::launch_project<double>(p->g, p->efie_p, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
-                              p->d_mfie_grid, 3 * nrhs, s);
-  mfie_grid_stages(p, nrhs, s);
-  aim::launch_interp_near<double>(p->g, p->efie_pt, none, p->d_mfie_grid, nullptr,
-                                  p->d_efie_src, 3 * nrhs, true, false, s);
-  aim::launch_rwg_test(false, true, nullptr, p->d_efie_src, p->d_efie_vals, p->d_mfie_nrm,
-                       p->d_efie_te, p->d_efie_rowptr, p->d_efie_col, nullptr, p->d_mfie_ck,
-                       gram, p->d_k, p->d_mfie_freq, x, y, N, n, nrhs, s);
+  aim::launch_mfie_sources<T>(x, vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
+  aim::launch_project<T>(p->g, Pp, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
+                         p->d_mfie_grid, 3 * nrhs, s);
+  aim::launch_mfie_moments<T>(p->g, p->d_mfie_grid, nrhs, false, s);
+  aim::launch_convolve<T>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid, gspec,
+                          p->d_mfie_freq, 6 * nrhs, tw, s, nullptr, sched);
+  aim::launch_mfie_moments<T>(p->g, p->d_mfie_grid, nrhs, true, s);
+  aim::launch_interp_near<T>(p->g, Pt, none, p->d_mfie_grid, nullptr, p->d_efie_src, 3 * nrhs,
+                             true, false, s);
+  aim::launch_rwg_test<T>(false, true, nullptr, p->d_efie_src, vals, nrm, p->d_efie_te,
+                          p->d_efie_rowptr, p->d_efie_col, nullptr, ck, gram, p->d_k,
+                          p->d_mfie_freq, x, y, N, n, nrhs, s);
+}
+
+}  // extern "C++"
+
+void rwg_matvec(aim_plan p, aim_precision prec, int op, const void* x, void* y, int nrhs,
+                const std::vector<int32_t>& fr, double gram, hipStream_t s) {
+  if (prec == AIM_C128)
+    rwg_matvec_t<double>(p, op, x, y, nrhs, fr, gram, s);
+  else
+    rwg_matvec_t<float>(p, op, x, y, nrhs, fr, gram, s);
 }
 }  // namespace
 
-aim_status aim_matvec_efie(aim_plan p, const void* x, void* y, int32_t nrhs,
+aim_status aim_matvec_efie(aim_plan p, aim_precision prec, const void* x, void* y, int32_t nrhs,
                            const int32_t* freq_idx_host, void* hip_stream) {
   if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
     check_rwg_call(p, x, y, nrhs);
+    check_prec(p, prec);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
     ensure_efie(p, s);
-    rwg_matvec(p, 1, x, y, nrhs, fr, 0.0, s);
+    rwg_matvec(p, prec, 1, x, y, nrhs, fr, 0.0, s);
   });
 }
 
-aim_status aim_matvec_mfie(aim_plan p, const void* x, void* y, int32_t nrhs,
+aim_status aim_matvec_mfie(aim_plan p, aim_precision prec, const void* x, void* y, int32_t nrhs,
                            const int32_t* freq_idx_host, double gram_coef, void* hip_stream) {
   if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
     check_rwg_call(p, x, y, nrhs);
+    check_prec(p, prec);
     AIM_REQUIRE(std::isfinite(gram_coef), AIM_ERR_INVALID_ARG, "gram_coef must be finite");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
     ensure_mfie(p, s);
-    rwg_matvec(p, 2, x, y, nrhs, fr, gram_coef, s);
+    rwg_matvec(p, prec, 2, x, y, nrhs, fr, gram_coef, s);
   });
 }
 
-aim_status aim_matvec_cfie(aim_plan p, const void* x, void* y, int32_t nrhs,
+aim_status aim_matvec_cfie(aim_plan p, aim_precision prec, const void* x, void* y, int32_t nrhs,
                            const int32_t* freq_idx_host, double gram_coef, void* hip_stream) {
   if (!p || !x || !y) return fail(AIM_ERR_INVALID_ARG, "null argument");
   return guarded([&] {
     check_rwg_call(p, x, y, nrhs);
+    check_prec(p, prec);
     AIM_REQUIRE(std::isfinite(gram_coef), AIM_ERR_INVALID_ARG, "gram_coef must be finite");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const std::vector<int32_t> fr = freq_list(p, nrhs, freq_idx_host);
     ensure_mfie(p, s);
-    rwg_matvec(p, 3, x, y, nrhs, fr, gram_coef, s);
+    rwg_matvec(p, prec, 3, x, y, nrhs, fr, gram_coef, s);
   });
 }
 
@@ -1894,7 +1945,7 @@ void graph_matvec(aim_plan p, aim_precision prec, const void* in, void* out, int
 void apply_A(aim_plan p, aim_precision prec, const void* x, void* y, int nrhs, const int32_t* dfreq,
              hipStream_t s, const char* skip = nullptr) {
   if (p->rwg_op) {  // an RWG operator (complex128; wavenumbers from the solve's list)
-    rwg_matvec(p, p->rwg_op, x, y, nrhs, p->rwg_fr, p->rwg_gram, s);
+    rwg_matvec(p, AIM_C128, p->rwg_op, x, y, nrhs, p->rwg_fr, p->rwg_gram, s);
     return;
   }
   const int64_t cnt = p->t.N * int64_t(nrhs);

@@ -252,33 +252,36 @@ void launch_dlp_moments(const GridShape& g, void* grids, int nrhs, hipStream_t s
 void launch_dlp_combine(const GridShape& g, const void* grids, void* phi, int nrhs,
                         hipStream_t s);
 
-// RWG EFIE, complex128: src[c][r][3t + q] = sum_e vals[t][q][e][c] x[r][tri_rwg[t][e]]
+// RWG EFIE, complex128 (T = double) or complex64 (T = float): src[c][r][3t + q] = sum_e vals[t][q][e][c] x[r][tri_rwg[t][e]]
 // (c = x, y, z, charge; x is [nrhs][nrwg]); then, from the interpolated
 // channel potentials psi (same layout), y[r][n] = sum over the function's
 // two triangles and their points of the current channels' dot product minus
 // k_r^-2 times the charge channel, plus (C_A - k_r^-2 C_phi) x[r], with
 // k_r = kv[rhs_freq[r]] and cc [nnz][2] = (C_A, C_phi) interleaved
-void launch_efie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
+template <typename T>
+void launch_efie_sources(const void* x, const void* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
-// RWG double layer, complex128: the three current channels of x at the
-// points (src[a][r][p], as launch_efie_sources without the charge); the
-// grid moments M = (u - c) x J (combine false: grids [3 nrhs, 6 nrhs) from
+// RWG double layer: the three current channels of x at the points
+// (src[a][r][p], as launch_efie_sources without the charge); the grid
+// moments M = (u - c) x J (combine false: grids [3 nrhs, 6 nrhs) from
 // [0, 3 nrhs)) or, after the convolutions with the radial factor F, the field
-// V = -[(u - c) x (F * J) - F * M] into grids [0, 3 nrhs) (combine true); then
-// y[r][m] = sum over the function's points of (w f_m x n) . V(r_q) plus its
-// near row of (C_K + beta G), ck [nnz][2] = (C_K, G) interleaved
-void launch_mfie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
+// V = -[(u - c) x (F * J) - F * M] into grids [0, 3 nrhs) (combine true)
+template <typename T>
+void launch_mfie_sources(const void* x, const void* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
+template <typename T>
 void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s,
                          const void* j_in = nullptr);  // currents from other grids (copied)
 // y for the EFIE (efie), the double layer (mfie) or the combined field of
 // eq. CFIEAIMx (both: y = y_E + (j/k_r) y_M), from psi_e [4][nrhs][3N] and
-// psi_m [3][nrhs][3N]; cc = (C_A, C_phi), ck = (C_K, G) interleaved
+// psi_m [3][nrhs][3N]; cc = (C_A, C_phi), ck = (C_K, G) interleaved; T the
+// real type of every array but kv (wavenumbers, double)
+template <typename T>
 void launch_rwg_test(bool efie, bool mfie, const void* psi_e, const void* psi_m,
-                     const double* vals, const double* nrm, const int32_t* rwg_te,
-                     const int32_t* rowptr, const int32_t* col, const double* cc,
-                     const double* ck, double beta, const double* kv, const int32_t* rhs_freq,
-                     const void* x, void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
+                     const void* vals, const void* nrm, const int32_t* rwg_te,
+                     const int32_t* rowptr, const int32_t* col, const void* cc, const void* ck,
+                     double beta, const double* kv, const int32_t* rhs_freq, const void* x,
+                     void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
 
 // plane waves tested with the RWG functions (3-point rule): b[r][m] =
 // <f_m, pol_r e^{-j k d_r . r}> (field 0) or <f_m, n x (d_r x pol_r)

@@ -1,4 +1,4 @@
-// Device kernels of the RWG operators under AIMx, complex128: the EFIE (Sec.
+// Device kernels of the RWG operators under AIMx, complex128 or complex64: the EFIE (Sec.
 // II-A, eq. EFIEdis; Sec. II-B, eq. LAIMx) and the double layer (Sec. III-B,
 // eq. KAIMx).  One EFIE product y = Z x runs
 //
@@ -24,6 +24,26 @@
 namespace aim {
 namespace {
 
+template <typename T>
+struct C2T;
+template <>
+struct C2T<double> {
+  using t = double2;
+};
+template <>
+struct C2T<float> {
+  using t = float2;
+};
+template <typename T>
+using c2 = typename C2T<T>::t;
+template <typename T>
+__device__ __forceinline__ c2<T> mk2(T a, T b) {
+  c2<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+
 unsigned blocks(int64_t cnt, int per = 256) {
   int64_t g = (cnt + per - 1) / per;
   if (g > 8192) g = 8192;
@@ -33,28 +53,28 @@ unsigned blocks(int64_t cnt, int per = 256) {
 
 // src[c][r][p] for the point p = 3t + q: sum over the triangle's three edges
 // of the function's channel value at the point times its coefficient
-template <int C>
+template <int C, typename T>
 __global__ __launch_bounds__(256) void efie_sources_kernel(
-    const double2* __restrict__ x, const double* __restrict__ vals,
-    const int32_t* __restrict__ tri_rwg, double2* __restrict__ src, int64_t N, int64_t nrwg,
+    const c2<T>* __restrict__ x, const T* __restrict__ vals,
+    const int32_t* __restrict__ tri_rwg, c2<T>* __restrict__ src, int64_t N, int64_t nrwg,
     int nrhs) {
   const int r = blockIdx.y;
   const int64_t P = 3 * N;
   for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < P;
        p += int64_t(gridDim.x) * blockDim.x) {
     const int64_t t = p / 3;
-    const double* v = vals + 36 * t + 12 * (p - 3 * t);
-    double2 acc[C];
+    const T* v = vals + 36 * t + 12 * (p - 3 * t);
+    c2<T> acc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = make_double2(0.0, 0.0);
+    for (int c = 0; c < C; ++c) acc[c] = mk2<T>(T(0), T(0));
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       const int32_t n = tri_rwg[3 * t + e];
       if (n < 0) continue;
-      const double2 xv = x[int64_t(r) * nrwg + n];
+      const c2<T> xv = x[int64_t(r) * nrwg + n];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const double w = v[4 * e + c];
+        const T w = v[4 * e + c];
         acc[c].x += w * xv.x;
         acc[c].y += w * xv.y;
       }
@@ -70,44 +90,46 @@ __global__ __launch_bounds__(256) void efie_sources_kernel(
 // V(u) = sum_v grad G(r_u - r_v) x J(v) is -[(u - c) x (F * J)(u) - (F * M)(u)]
 // with the moments M(v) = (v - c) x J(v).  Grids: J_a of vector r at
 // a nrhs + r, M_a at (3 + a) nrhs + r; V overwrites J.
-__global__ __launch_bounds__(256) void mfie_moments_kernel(const double2* j_in, double2* g, int Nx,
+template <typename T>
+__global__ __launch_bounds__(256) void mfie_moments_kernel(const c2<T>* j_in, c2<T>* g, int Nx,
                                                            int Ny, int64_t Ng, int nrhs,
                                                            double cx, double cy, double cz) {
   const int r = blockIdx.y;
   for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
        u += int64_t(gridDim.x) * blockDim.x) {
-    const double dx = double(u % Nx) - cx, dy = double((u / Nx) % Ny) - cy,
-                 dz = double(u / (int64_t(Nx) * Ny)) - cz;
-    const double2 jx = j_in[int64_t(r) * Ng + u], jy = j_in[int64_t(nrhs + r) * Ng + u],
+    const T dx = T(double(u % Nx) - cx), dy = T(double((u / Nx) % Ny) - cy),
+            dz = T(double(u / (int64_t(Nx) * Ny)) - cz);
+    const c2<T> jx = j_in[int64_t(r) * Ng + u], jy = j_in[int64_t(nrhs + r) * Ng + u],
                   jz = j_in[int64_t(2 * nrhs + r) * Ng + u];
     if (j_in != g) {  // the currents come from another set of grids: copy them
       g[int64_t(r) * Ng + u] = jx;
       g[int64_t(nrhs + r) * Ng + u] = jy;
       g[int64_t(2 * nrhs + r) * Ng + u] = jz;
     }
-    g[int64_t(3 * nrhs + r) * Ng + u] = make_double2(dy * jz.x - dz * jy.x, dy * jz.y - dz * jy.y);
-    g[int64_t(4 * nrhs + r) * Ng + u] = make_double2(dz * jx.x - dx * jz.x, dz * jx.y - dx * jz.y);
-    g[int64_t(5 * nrhs + r) * Ng + u] = make_double2(dx * jy.x - dy * jx.x, dx * jy.y - dy * jx.y);
+    g[int64_t(3 * nrhs + r) * Ng + u] = mk2<T>(dy * jz.x - dz * jy.x, dy * jz.y - dz * jy.y);
+    g[int64_t(4 * nrhs + r) * Ng + u] = mk2<T>(dz * jx.x - dx * jz.x, dz * jx.y - dx * jz.y);
+    g[int64_t(5 * nrhs + r) * Ng + u] = mk2<T>(dx * jy.x - dy * jx.x, dx * jy.y - dy * jx.y);
   }
 }
 
-__global__ __launch_bounds__(256) void mfie_combine_kernel(double2* __restrict__ g, int Nx, int Ny,
+template <typename T>
+__global__ __launch_bounds__(256) void mfie_combine_kernel(c2<T>* __restrict__ g, int Nx, int Ny,
                                                            int64_t Ng, int nrhs, double cx,
                                                            double cy, double cz) {
   const int r = blockIdx.y;
   for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
        u += int64_t(gridDim.x) * blockDim.x) {
-    const double dx = double(u % Nx) - cx, dy = double((u / Nx) % Ny) - cy,
-                 dz = double(u / (int64_t(Nx) * Ny)) - cz;
-    double2* a0 = g + int64_t(r) * Ng + u;
-    double2* a1 = g + int64_t(nrhs + r) * Ng + u;
-    double2* a2 = g + int64_t(2 * nrhs + r) * Ng + u;
-    const double2 ax = *a0, ay = *a1, az = *a2;
-    const double2 bx = g[int64_t(3 * nrhs + r) * Ng + u], by = g[int64_t(4 * nrhs + r) * Ng + u],
+    const T dx = T(double(u % Nx) - cx), dy = T(double((u / Nx) % Ny) - cy),
+            dz = T(double(u / (int64_t(Nx) * Ny)) - cz);
+    c2<T>* a0 = g + int64_t(r) * Ng + u;
+    c2<T>* a1 = g + int64_t(nrhs + r) * Ng + u;
+    c2<T>* a2 = g + int64_t(2 * nrhs + r) * Ng + u;
+    const c2<T> ax = *a0, ay = *a1, az = *a2;
+    const c2<T> bx = g[int64_t(3 * nrhs + r) * Ng + u], by = g[int64_t(4 * nrhs + r) * Ng + u],
                   bz = g[int64_t(5 * nrhs + r) * Ng + u];
-    *a0 = make_double2(bx.x - (dy * az.x - dz * ay.x), bx.y - (dy * az.y - dz * ay.y));
-    *a1 = make_double2(by.x - (dz * ax.x - dx * az.x), by.y - (dz * ax.y - dx * az.y));
-    *a2 = make_double2(bz.x - (dx * ay.x - dy * ax.x), bz.y - (dx * ay.y - dy * ax.y));
+    *a0 = mk2<T>(bx.x - (dy * az.x - dz * ay.x), bx.y - (dy * az.y - dz * ay.y));
+    *a1 = mk2<T>(by.x - (dz * ax.x - dx * az.x), by.y - (dz * ax.y - dx * az.y));
+    *a2 = mk2<T>(bz.x - (dx * ay.x - dy * ax.x), bz.y - (dx * ay.y - dy * ax.y));
   }
 }
 
@@ -120,14 +142,14 @@ __global__ __launch_bounds__(256) void mfie_combine_kernel(double2* __restrict__
 // lanes 0..5 take one point each, every lane strides over the near row, a
 // fixed butterfly sums them (fixed order: deterministic).  RB right-hand
 // sides per workgroup, so each near entry and channel value is loaded once.
-template <int LPR, int RB, bool E, bool M>
+template <int LPR, int RB, bool E, bool M, typename T>
 __global__ __launch_bounds__(256) void rwg_test_kernel(
-    const double2* __restrict__ psi_e, const double2* __restrict__ psi_m,
-    const double* __restrict__ vals, const double* __restrict__ nrm,
+    const c2<T>* __restrict__ psi_e, const c2<T>* __restrict__ psi_m,
+    const T* __restrict__ vals, const T* __restrict__ nrm,
     const int32_t* __restrict__ rwg_te, const int32_t* __restrict__ rowptr,
-    const int32_t* __restrict__ col, const double2* __restrict__ cc,
-    const double2* __restrict__ ck, double beta, const double* __restrict__ kv,
-    const int32_t* __restrict__ rhs_freq, const double2* __restrict__ x, double2* __restrict__ y,
+    const int32_t* __restrict__ col, const c2<T>* __restrict__ cc,
+    const c2<T>* __restrict__ ck, T beta, const double* __restrict__ kv,
+    const int32_t* __restrict__ rhs_freq, const c2<T>* __restrict__ x, c2<T>* __restrict__ y,
     int64_t N, int64_t nrwg, int nrhs) {
   const int sub = threadIdx.x % LPR;
   const int64_t n = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / LPR;
@@ -135,23 +157,23 @@ __global__ __launch_bounds__(256) void rwg_test_kernel(
   const int nr = min(RB, nrhs - r0);
   const int64_t P = 3 * N;
   const int64_t cs = int64_t(nrhs) * P;  // channel stride of psi_e and psi_m
-  double ar[RB], ai[RB], qr[RB], qi[RB], mr[RB], mi[RB];
+  T ar[RB], ai[RB], qr[RB], qi[RB], mr[RB], mi[RB];
 #pragma unroll
-  for (int j = 0; j < RB; ++j) ar[j] = ai[j] = qr[j] = qi[j] = mr[j] = mi[j] = 0.0;
+  for (int j = 0; j < RB; ++j) ar[j] = ai[j] = qr[j] = qi[j] = mr[j] = mi[j] = T(0);
   if (n < nrwg) {
     if (sub < 6) {
       const int side = sub >= 3 ? 1 : 0, q = sub - 3 * side;
       const int64_t t = rwg_te[4 * n + 2 * side];
       const int e = rwg_te[4 * n + 2 * side + 1];
-      const double* v = vals + 36 * t + 12 * q + 4 * e;
-      const double v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+      const T* v = vals + 36 * t + 12 * q + 4 * e;
+      const T v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
       const int64_t off = int64_t(r0) * P + 3 * t + q;
       if constexpr (E) {
 #pragma unroll
         for (int j = 0; j < RB; ++j)
           if (j < nr) {
-            const double2* b = psi_e + off + int64_t(j) * P;
-            const double2 p0 = b[0], p1 = b[cs], p2 = b[2 * cs], p3 = b[3 * cs];
+            const c2<T>* b = psi_e + off + int64_t(j) * P;
+            const c2<T> p0 = b[0], p1 = b[cs], p2 = b[2 * cs], p3 = b[3 * cs];
             ar[j] = v0 * p0.x + v1 * p1.x + v2 * p2.x;
             ai[j] = v0 * p0.y + v1 * p1.y + v2 * p2.y;
             qr[j] = v3 * p3.x;
@@ -159,33 +181,33 @@ __global__ __launch_bounds__(256) void rwg_test_kernel(
           }
       }
       if constexpr (M) {
-        const double* nn = nrm + 3 * t;
-        const double t0 = v1 * nn[2] - v2 * nn[1], t1 = v2 * nn[0] - v0 * nn[2],
-                     t2 = v0 * nn[1] - v1 * nn[0];
+        const T* nn = nrm + 3 * t;
+        const T t0 = v1 * nn[2] - v2 * nn[1], t1 = v2 * nn[0] - v0 * nn[2],
+                t2 = v0 * nn[1] - v1 * nn[0];
 #pragma unroll
         for (int j = 0; j < RB; ++j)
           if (j < nr) {
-            const double2* b = psi_m + off + int64_t(j) * P;
-            const double2 p0 = b[0], p1 = b[cs], p2 = b[2 * cs];
+            const c2<T>* b = psi_m + off + int64_t(j) * P;
+            const c2<T> p0 = b[0], p1 = b[cs], p2 = b[2 * cs];
             mr[j] = t0 * p0.x + t1 * p1.x + t2 * p2.x;
             mi[j] = t0 * p0.y + t1 * p1.y + t2 * p2.y;
           }
       }
     }
-    const double2* xr = x + int64_t(r0) * nrwg;
+    const c2<T>* xr = x + int64_t(r0) * nrwg;
     for (int32_t k = rowptr[n] + sub; k < rowptr[n + 1]; k += LPR) {
       const int64_t m = col[k];
-      double2 c = make_double2(0.0, 0.0);
-      double w = 0.0;
+      c2<T> c = mk2<T>(T(0), T(0));
+      T w = T(0);
       if constexpr (E) c = cc[k];
       if constexpr (M) {
-        const double2 d = ck[k];
+        const c2<T> d = ck[k];
         w = d.x + beta * d.y;
       }
 #pragma unroll
       for (int j = 0; j < RB; ++j)
         if (j < nr) {
-          const double2 xv = xr[int64_t(j) * nrwg + m];
+          const c2<T> xv = xr[int64_t(j) * nrwg + m];
           if constexpr (E) {
             ar[j] += c.x * xv.x;
             ai[j] += c.x * xv.y;
@@ -218,14 +240,14 @@ __global__ __launch_bounds__(256) void rwg_test_kernel(
 #pragma unroll
     for (int j = 0; j < RB; ++j)
       if (j < nr) {
-        double yr = 0.0, yi = 0.0;
+        T yr = T(0), yi = T(0);
         if constexpr (E) {
-          const double k = kv[rhs_freq[r0 + j]];
-          const double ik2 = 1.0 / (k * k);
+          const double kd = kv[rhs_freq[r0 + j]];
+          const T ik2 = T(1.0 / (kd * kd));
           yr = ar[j] - ik2 * qr[j];
           yi = ai[j] - ik2 * qi[j];
           if constexpr (M) {  // + (j/k)(mr + j mi) = (-mi + j mr)/k
-            const double ik = 1.0 / k;
+            const T ik = T(1.0 / kd);
             yr -= ik * mi[j];
             yi += ik * mr[j];
           }
@@ -233,7 +255,7 @@ __global__ __launch_bounds__(256) void rwg_test_kernel(
           yr = mr[j];
           yi = mi[j];
         }
-        y[int64_t(r0 + j) * nrwg + n] = make_double2(yr, yi);
+        y[int64_t(r0 + j) * nrwg + n] = mk2<T>(yr, yi);
       }
   }
 }
@@ -290,41 +312,45 @@ void launch_rwg_plane_wave(const double* qp, const double* vals, const double* n
   AIM_HIP(hipGetLastError());
 }
 
-void launch_mfie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
+template <typename T>
+void launch_mfie_sources(const void* x, const void* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(efie_sources_kernel<3>, dim3(blocks(3 * N), nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(x), vals, tri_rwg, static_cast<double2*>(src),
-                     N, nrwg, nrhs);
+  hipLaunchKernelGGL((efie_sources_kernel<3, T>), dim3(blocks(3 * N), nrhs), dim3(256), 0, s,
+                     static_cast<const c2<T>*>(x), static_cast<const T*>(vals), tri_rwg,
+                     static_cast<c2<T>*>(src), N, nrwg, nrhs);
   AIM_HIP(hipGetLastError());
 }
 
+template <typename T>
 void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s,
                          const void* j_in) {
   const double cx = 0.5 * (g.N[0] - 1), cy = 0.5 * (g.N[1] - 1), cz = 0.5 * (g.N[2] - 1);
-  double2* gp = static_cast<double2*>(grids);
-  const double2* jp = j_in ? static_cast<const double2*>(j_in) : gp;
+  c2<T>* gp = static_cast<c2<T>*>(grids);
+  const c2<T>* jp = j_in ? static_cast<const c2<T>*>(j_in) : gp;
   if (combine)
-    hipLaunchKernelGGL(mfie_combine_kernel, dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s, gp,
-                       g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
-  else
-    hipLaunchKernelGGL(mfie_moments_kernel, dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s, jp,
+    hipLaunchKernelGGL((mfie_combine_kernel<T>), dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s,
                        gp, g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
+  else
+    hipLaunchKernelGGL((mfie_moments_kernel<T>), dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s,
+                       jp, gp, g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
   AIM_HIP(hipGetLastError());
 }
 
-void launch_efie_sources(const void* x, const double* vals, const int32_t* tri_rwg, void* src,
+template <typename T>
+void launch_efie_sources(const void* x, const void* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(efie_sources_kernel<4>, dim3(blocks(3 * N), nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(x), vals, tri_rwg, static_cast<double2*>(src),
-                     N, nrwg, nrhs);
+  hipLaunchKernelGGL((efie_sources_kernel<4, T>), dim3(blocks(3 * N), nrhs), dim3(256), 0, s,
+                     static_cast<const c2<T>*>(x), static_cast<const T*>(vals), tri_rwg,
+                     static_cast<c2<T>*>(src), N, nrwg, nrhs);
   AIM_HIP(hipGetLastError());
 }
 
+template <typename T>
 void launch_rwg_test(bool efie, bool mfie, const void* psi_e, const void* psi_m,
-                     const double* vals, const double* nrm, const int32_t* rwg_te,
-                     const int32_t* rowptr, const int32_t* col, const double* cc,
-                     const double* ck, double beta, const double* kv, const int32_t* rhs_freq,
-                     const void* x, void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
+                     const void* vals, const void* nrm, const int32_t* rwg_te,
+                     const int32_t* rowptr, const int32_t* col, const void* cc, const void* ck,
+                     double beta, const double* kv, const int32_t* rhs_freq, const void* x,
+                     void* y, int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
   if (nrwg == 0) return;
   AIM_REQUIRE(efie || mfie, AIM_ERR_INVALID_ARG, "no operator selected");
   constexpr int LPR = 16;
@@ -333,16 +359,18 @@ void launch_rwg_test(bool efie, bool mfie, const void* psi_e, const void* psi_m,
   int rb = 1;
   while (rb < 8 && 2 * rb <= nrhs && gx * ((nrhs + 2 * rb - 1) / (2 * rb)) >= 1024) rb *= 2;
   const dim3 grid(unsigned(gx), unsigned((nrhs + rb - 1) / rb));
-  const double2* pe = static_cast<const double2*>(psi_e);
-  const double2* pm = static_cast<const double2*>(psi_m);
-  const double2* c2 = reinterpret_cast<const double2*>(cc);
-  const double2* k2 = reinterpret_cast<const double2*>(ck);
-  const double2* xi = static_cast<const double2*>(x);
-  double2* yo = static_cast<double2*>(y);
+  const c2<T>* pe = static_cast<const c2<T>*>(psi_e);
+  const c2<T>* pm = static_cast<const c2<T>*>(psi_m);
+  const T* vl = static_cast<const T*>(vals);
+  const T* nr = static_cast<const T*>(nrm);
+  const c2<T>* cp = static_cast<const c2<T>*>(cc);
+  const c2<T>* kp = static_cast<const c2<T>*>(ck);
+  const c2<T>* xi = static_cast<const c2<T>*>(x);
+  c2<T>* yo = static_cast<c2<T>*>(y);
+  const T bt = T(beta);
 #define AIM_RWG_TEST(R, E, M)                                                                  \
-  hipLaunchKernelGGL((rwg_test_kernel<LPR, R, E, M>), grid, dim3(256), 0, s, pe, pm, vals,    \
-                     nrm, rwg_te, rowptr, col, c2, k2, beta, kv, rhs_freq, xi, yo, N, nrwg,   \
-                     nrhs)
+  hipLaunchKernelGGL((rwg_test_kernel<LPR, R, E, M, T>), grid, dim3(256), 0, s, pe, pm, vl,   \
+                     nr, rwg_te, rowptr, col, cp, kp, bt, kv, rhs_freq, xi, yo, N, nrwg, nrhs)
 #define AIM_RWG_RB(E, M)                      \
   switch (rb) {                               \
     case 1: AIM_RWG_TEST(1, E, M); break;     \
@@ -357,5 +385,21 @@ void launch_rwg_test(bool efie, bool mfie, const void* psi_e, const void* psi_m,
 #undef AIM_RWG_TEST
   AIM_HIP(hipGetLastError());
 }
+
+#define AIM_RWG_INSTANTIATE(T)                                                                 \
+  template void launch_mfie_sources<T>(const void*, const void*, const int32_t*, void*,       \
+                                       int64_t, int64_t, int, hipStream_t);                   \
+  template void launch_mfie_moments<T>(const GridShape&, void*, int, bool, hipStream_t,      \
+                                       const void*);                                          \
+  template void launch_efie_sources<T>(const void*, const void*, const int32_t*, void*,       \
+                                       int64_t, int64_t, int, hipStream_t);                   \
+  template void launch_rwg_test<T>(bool, bool, const void*, const void*, const void*,         \
+                                   const void*, const int32_t*, const int32_t*,               \
+                                   const int32_t*, const void*, const void*, double,          \
+                                   const double*, const int32_t*, const void*, void*,         \
+                                   int64_t, int64_t, int, hipStream_t);
+AIM_RWG_INSTANTIATE(double)
+AIM_RWG_INSTANTIATE(float)
+#undef AIM_RWG_INSTANTIATE
 
 }  // namespace aim

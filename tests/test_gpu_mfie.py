@@ -157,6 +157,36 @@ def test_combined_field_large_sphere_sampled_rows():
     p.close()
 
 
+def test_complex64_operators():
+    """The three RWG operators in complex64 (tables rounded from the
+    complex128 ones, FFTs and gathers in complex64) against the oracles at
+    the FP32 bar, several vectors at two wavenumbers."""
+    w = I.sphere_tiny(level=2, dims=(16, 16, 16), h=0.1)
+    ks = [2 * math.pi, 8.5]
+    print("[gpu] RWG operators in complex64, sphere-320", flush=True)
+    o = aimx.AimOracle(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold)
+    e = efie.EfieOracle(o)
+    m = mfie.MfieOracle(e)
+    p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, ks,
+                     max_rhs=3, precisions=("c128", "c64"))
+    x = I.complex_gaussian(m.n, 79, nrhs=3)
+    xd = torch.from_numpy(x).to(torch.complex64).cuda()
+    freq = [0, 1, 1]
+    rows = np.arange(0, m.n, 4)
+    ye = p.matvec_efie(xd, freq_idx=freq, prec="c64").cpu().numpy()
+    ym = p.matvec_mfie(xd, freq_idx=freq, gram_coef=-0.5, prec="c64").cpu().numpy()
+    yc = p.matvec_cfie(xd, freq_idx=freq, gram_coef=-0.5, prec="c64").cpu().numpy()
+    for r in range(3):
+        k = ks[freq[r]]
+        re_ = e.matvec_rows(x[r], k, rows)
+        rm = m.matvec_rows(x[r], k, rows, -0.5)
+        assert np.linalg.norm(ye[r][rows] - re_) <= 1e-5 * np.linalg.norm(re_), r
+        assert np.linalg.norm(ym[r][rows] - rm) <= 1e-5 * np.linalg.norm(rm), r
+        rc = re_ + 1j / k * rm
+        assert np.linalg.norm(yc[r][rows] - rc) <= 1e-5 * np.linalg.norm(rc), r
+    p.close()
+
+
 def test_needs_the_mesh(tmp_path):
     w = I.sphere_tiny()
     p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k)
