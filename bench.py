@@ -651,7 +651,7 @@ def efie_leg(reps: int = 20) -> dict:
     w = I.efie_sphere()
     t0 = time.perf_counter()
     p = binding.Plan(w.vertices, w.triangles, w.order, w.dims, w.h, w.near_threshold, w.k,
-                     precisions=("c128",), max_rhs=4)
+                     precisions=("c128", "c64"), max_rhs=4)
     plan_s = time.perf_counter() - t0
     info = p.efie_setup()
 
@@ -686,6 +686,17 @@ def efie_leg(reps: int = 20) -> dict:
                         "unknowns_matvecs_per_s": info["n_rwg"] * nrhs / (ms * 1e-3)}
             print(f"[bench] {name} on {w.name}: {nrhs} vector(s) {ms:.3f} ms per call",
                   file=sys.stderr, flush=True)
+    x32 = torch.from_numpy(I.complex_gaussian(info["n_rwg"], w.seed_base + 7)).to(
+        torch.complex64).cuda()
+    ops32 = (("efie", lambda x, out: p.matvec_efie(x, out=out, prec="c64")),
+             ("mfie", lambda x, out: p.matvec_mfie(x, gram_coef=-0.5, out=out, prec="c64")),
+             ("cfie", lambda x, out: p.matvec_cfie(x, gram_coef=-0.5, out=out, prec="c64")))
+    for name, fn in ops32:
+        ms = timed(fn, x32, torch.empty_like(x32))
+        res[f"{name}_c64_nrhs1"] = {"ms_per_call": ms,
+                                    "unknowns_matvecs_per_s": info["n_rwg"] / (ms * 1e-3)}
+        print(f"[bench] {name} c64 on {w.name}: {ms:.3f} ms per call", file=sys.stderr,
+              flush=True)
     xs = torch.from_numpy(I.complex_gaussian(p.n, w.seed_base)).cuda()
     res["scalar_ms_per_matvec"] = timed(p.matvec, xs, torch.empty_like(xs))
     # a scattering solve as the paper runs it (Sec. V: the CFIE, GMRES): a
