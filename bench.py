@@ -632,8 +632,9 @@ def dlp_leg(plan, w, reps: int = 20) -> dict:
     ms = a.elapsed_time(b) / reps
     res = {"workload": w.name, "first_call_seconds": first, "ms_per_matvec": ms,
            "unknowns_matvecs_per_s": w.n / (ms * 1e-3),
-           "note": "complex128; three gradient channels as four convolutions with one even "
-                   "kernel; the first call builds the tables"}
+           "note": "complex128; three gradient channels transformed forward, summed against "
+                   "the spectra of the components of grad G in one z pass, one grid "
+                   "transformed back; the first call builds the tables"}
     print(f"[bench] double layer on {w.name}: {ms:.3f} ms per matvec (first call "
           f"{first:.2f}s)", file=sys.stderr, flush=True)
     return res
@@ -720,12 +721,12 @@ def efie_leg(reps: int = 20) -> dict:
                 torch.linalg.vector_norm(xs_ - xc) / torch.linalg.vector_norm(xs_))
         print(f"[bench] {op} solve on {w.name}: {solves[op]}", file=sys.stderr, flush=True)
     res["plane_wave_solves"] = solves
-    res["note"] = ("complex128; EFIE: three current channels and one charge channel projected "
-                   "from the quadrature points and convolved with the plan's spectrum (4 grids "
-                   "per vector); double layer (K - G/2): three current channels and their grid "
-                   "moments convolved with the radial factor of grad G (6 grids); combined "
-                   "field: one projection, 10 grids; the scalar product on the same plan "
-                   "convolves one grid")
+    res["note"] = ("complex128 unless keyed c64; EFIE: three current channels and one charge "
+                   "channel projected from the quadrature points and convolved with the plan's "
+                   "spectrum (4 grids per vector); double layer (K - G/2): the three current "
+                   "channels' grids, their spectral cross product with grad G in one z pass "
+                   "(3 grids forward, 3 back); combined field: one projection, 4 grids forward, "
+                   "7 back; the scalar product on the same plan convolves one grid")
     p.close()
     return res
 

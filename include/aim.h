@@ -414,10 +414,11 @@ aim_status aim_efie_export(aim_plan plan, int32_t* tri_rwg, int32_t* rowptr, int
  * y flipped).  Evaluated as
  * K_s,NR - K_s,P + W H_grad(k) P on the RWG functions, near list, point
  * projection and wavenumbers of the EFIE above: three current channels
- * w_q f(r_q), their moments (u - c) x J on the grid, six convolutions with
- * the radial factor of grad G (self term 0 per component: eq. gH00 gives a
- * scalar for this vector kernel), the field combined on the grid and
- * interpolated, tested with w_q f_m(r_q) x n; static entries from the
+ * w_q f(r_q) projected and transformed forward, their spectral cross
+ * product with the three components of grad G sampled on the grid (self
+ * term 0 per component: eq. gH00 gives a scalar for this vector kernel) in
+ * one z pass, the field transformed back and interpolated, tested with
+ * w_q f_m(r_q) x n; static entries from the
  * closed form of int (r - r')/R^3 over a triangle and the 3-point outer
  * rule, precorrection with the grid's static gradient samples.  x_dev,
  * y_dev [nrhs][n_rwg] of precision prec (caller-owned, not overlapping);

@@ -164,10 +164,9 @@ struct aim_plan_s {
   bool dlp_ready = false;
   double* d_dlp_nrm = nullptr;     // [N][3] unit normals
   double* d_dlp_corr = nullptr;    // [nnz] C_K = K_s,NR - K_s,P on the near list
-  void* d_dlp_spec = nullptr;      // [nfreq] folded spectra of the radial factor F
   void* d_dlp_src = nullptr;       // [3 max_rhs][N] channel sources n_a x
-  void* d_dlp_grid = nullptr;      // [4 max_rhs][Ng] channel grids and moment sums
-  void* d_dlp_work = nullptr;      // convolution workspace of 4 max_rhs grids
+  void* d_dlp_grid = nullptr;      // [3 max_rhs][Ng] channel grids
+  void* d_dlp_work = nullptr;      // convolution workspace of 3 max_rhs grids
   void* d_dlp_phi = nullptr;       // [max_rhs][Ng] combined potential
   int32_t* d_dlp_freq = nullptr;   // [4 max_rhs] spectrum index per grid
   int32_t* h_dlp_freq = nullptr;   // pinned staging
@@ -199,8 +198,10 @@ struct aim_plan_s {
   std::vector<double> mfie_ck;      // [nnz][2] (C_K, Gram) on the RWG near list
   double* d_mfie_ck = nullptr;
   double* d_mfie_nrm = nullptr;     // [N][3] unit normals
-  void* d_mfie_grid = nullptr;      // [6 max_rhs][Ng] currents, moments, then the field
-  void* d_mfie_work = nullptr;      // convolution workspace of 6 max_rhs grids
+  void* d_mfie_grid = nullptr;      // [3 max_rhs][Ng] currents, then the field
+  void* d_mfie_work = nullptr;      // convolution workspace of 3 max_rhs grids
+  void* d_curl_spec = nullptr;      // [nfreq][3] folded spectra of the components of grad G
+  void* d_curl_spec32 = nullptr;    // their complex64 rounding
   int32_t* d_mfie_freq = nullptr;   // [6 max_rhs]
   int32_t* h_mfie_freq = nullptr;   // pinned staging
   void* d_cfie_psi = nullptr;       // [3 max_rhs][3N] the double layer's field (combined call)
@@ -210,7 +211,6 @@ struct aim_plan_s {
   float* d_mfie_ck32 = nullptr;
   float* d_mfie_nrm32 = nullptr;
   aim::CsrDevice efie_p32{}, efie_pt32{};
-  void* d_dlp_spec32 = nullptr;     // complex64 spectra of the radial factor F
   // the operator the Krylov solver applies: 0 the plan's scalar operator,
   // else an RWG operator (aim_solve_rwg sets it for the duration of a solve)
   int rwg_op = 0;
@@ -989,23 +989,25 @@ aim_status aim_matvec_conventional(aim_plan p, aim_precision prec, const void* x
 }
 
 namespace {
-// The folded spectra of the gradient kernels' radial factor F (Sec. III-B)
-// for every wavenumber of the plan, shared by both double-layer operators.
-void ensure_grad_spectra(aim_plan p, hipStream_t s) {
-  if (p->d_dlp_spec) return;
+// The folded spectra of the three components of grad G (Sec. III-B, the
+// kernel of eq. KAIMx) for every wavenumber of the plan, [freq][3][Nfold]:
+// the RWG double layer's grid operator as one cross product per frequency.
+void ensure_curl_spectra(aim_plan p, hipStream_t s) {
+  if (p->d_curl_spec) return;
   const auto& g = p->g;
-  void* spec = p->dalloc(size_t(g.Nfold) * 16 * p->nfreq, s);
-  // and its complex64 rounding when the plan has complex64 tables
-  void* spec32 = (p->prec & (1u << AIM_C64)) ? p->dalloc(size_t(g.Nfold) * 8 * p->nfreq, s)
-                                             : nullptr;
+  const size_t n3 = size_t(3) * g.Nfold;
+  void* spec = p->dalloc(n3 * 16 * p->nfreq, s);
+  void* spec32 = (p->prec & (1u << AIM_C64)) ? p->dalloc(n3 * 8 * p->nfreq, s) : nullptr;
   void* full = nullptr;
   AIM_HIP(hipMalloc(&full, size_t(8) * g.Ng * 16));
   try {
     for (int f = 0; f < p->nfreq; ++f)
-      aim::launch_spectrum(g, p->k[f], p->t.h, full,
-                           static_cast<char*>(spec) + size_t(f) * g.Nfold * 16,
-                           spec32 ? static_cast<char*>(spec32) + size_t(f) * g.Nfold * 8 : nullptr,
-                           p->d_tw64, s, 1);
+      for (int a = 0; a < 3; ++a) {
+        const size_t off = size_t(f) * n3 + size_t(a) * g.Nfold;
+        aim::launch_spectrum(g, p->k[f], p->t.h, full, static_cast<char*>(spec) + off * 16,
+                             spec32 ? static_cast<char*>(spec32) + off * 8 : nullptr, p->d_tw64,
+                             s, 2 + a);
+      }
     AIM_HIP(hipStreamSynchronize(s));
   } catch (...) {
     (void)hipStreamSynchronize(s);
@@ -1013,13 +1015,13 @@ void ensure_grad_spectra(aim_plan p, hipStream_t s) {
     throw;
   }
   AIM_HIP(hipFree(full));
-  p->d_dlp_spec = spec;
-  p->d_dlp_spec32 = spec32;
+  p->d_curl_spec = spec;
+  p->d_curl_spec32 = spec32;
 }
 
 // The double-layer operator's tables (Sec. III-B): unit normals, C_K on the
-// near list (device fill), the folded spectra of the radial factor F for
-// every wavenumber of the plan, and the buffers of max_rhs products.
+// near list (device fill), the folded spectra of grad G for every wavenumber
+// of the plan, and the buffers of max_rhs products.
 void ensure_dlp(aim_plan p, hipStream_t s) {
   if (p->dlp_ready) return;
   AIM_REQUIRE(p->t.corners.size() == 9 * size_t(p->t.N), AIM_ERR_STATE,
@@ -1045,13 +1047,13 @@ void ensure_dlp(aim_plan p, hipStream_t s) {
   const int R = p->max_rhs;
   p->d_dlp_nrm = p->upload(nrm, s);
   p->d_dlp_corr = p->upload(p->dlp_corr.empty() ? std::vector<double>(1, 0.0) : p->dlp_corr, s);
-  ensure_grad_spectra(p, s);
+  ensure_curl_spectra(p, s);
   p->d_dlp_src = p->dalloc(size_t(3) * R * N * 16, s);
-  p->d_dlp_grid = p->dalloc(size_t(4) * R * g.Ng * 16, s);
-  p->d_dlp_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 4 * R, s);
+  p->d_dlp_grid = p->dalloc(size_t(3) * R * g.Ng * 16, s);
+  p->d_dlp_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 3 * R, s);
   p->d_dlp_phi = p->dalloc(size_t(R) * g.Ng * 16, s);
-  p->d_dlp_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 4 * R, s));
-  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_dlp_freq), sizeof(int32_t) * 4 * R, 0));
+  p->d_dlp_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * R, s));
+  AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_dlp_freq), sizeof(int32_t) * R, 0));
   p->dlp_cur_freq.clear();
   p->dlp_ready = true;
   p->dlp_seconds = now_s() - t0;
@@ -1077,27 +1079,29 @@ aim_status aim_matvec_dlp(aim_plan p, const void* x, void* y, int32_t nrhs,
       }
     }
     ensure_dlp(p, s);
-    // one spectrum index per grid: the four grids of right-hand side r all use
-    // its wavenumber
-    std::vector<int32_t> f6(size_t(4) * nrhs);
-    for (int c = 0; c < 4; ++c)
-      for (int r = 0; r < nrhs; ++r) f6[size_t(c) * nrhs + r] = fr[r];
-    if (f6 != p->dlp_cur_freq) {
+    // one spectrum index per vector
+    if (fr != p->dlp_cur_freq) {
       AIM_HIP(hipStreamSynchronize(s));  // the staging buffer may still feed a copy
-      std::memcpy(p->h_dlp_freq, f6.data(), f6.size() * sizeof(int32_t));
-      AIM_HIP(hipMemcpyAsync(p->d_dlp_freq, p->h_dlp_freq, f6.size() * sizeof(int32_t),
+      std::memcpy(p->h_dlp_freq, fr.data(), fr.size() * sizeof(int32_t));
+      AIM_HIP(hipMemcpyAsync(p->d_dlp_freq, p->h_dlp_freq, fr.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, s));
-      p->dlp_cur_freq = f6;
+      p->dlp_cur_freq = fr;
     }
+    // three channels: projection, forward x and y passes, the z pass that
+    // sums their products with the gradient spectra into grid r of the
+    // workspace, inverse y and x passes of that one grid per vector
     const int64_t N = p->t.N;
     aim::launch_dlp_sources(x, p->d_dlp_nrm, p->d_dlp_src, N, nrhs, s);
     aim::launch_project<double>(p->g, p_dev(p, AIM_C128), p->d_pblk, p->nblk, p->d_dlp_src, N,
                                 p->d_dlp_grid, 3 * nrhs, s);
-    aim::launch_dlp_moments(p->g, p->d_dlp_grid, nrhs, s);
-    aim::launch_convolve<double>(p->g, p->d_dlp_grid, p->d_dlp_work, p->d_dlp_grid,
-                                 p->d_dlp_spec, p->d_dlp_freq, 4 * nrhs, p->d_tw64, s, nullptr,
-                                 p->sched[0]);
-    aim::launch_dlp_combine(p->g, p->d_dlp_grid, p->d_dlp_phi, nrhs, s);
+    aim::launch_convolve<double>(p->g, p->d_dlp_grid, p->d_dlp_work, nullptr, nullptr, nullptr,
+                                 3 * nrhs, p->d_tw64, s, nullptr, p->sched[0], 1, nullptr,
+                                 nullptr, 0, 1);
+    aim::launch_zcross<double>(p->g, p->d_dlp_work, p->d_dlp_work, p->d_curl_spec,
+                               p->d_dlp_freq, nrhs, p->d_tw64, s, p->sched[0], true);
+    aim::launch_convolve<double>(p->g, nullptr, p->d_dlp_work, p->d_dlp_phi, nullptr, nullptr,
+                                 nrhs, p->d_tw64, s, nullptr, p->sched[0], 1, nullptr, nullptr,
+                                 0, 4);
     aim::CsrDevice kc = csr_dev(p, AIM_C128);
     kc.val = p->d_dlp_corr;
     aim::launch_interp_near<double>(p->g, pt_dev(p, AIM_C128), kc, p->d_dlp_phi, x, y, nrhs,
@@ -1286,9 +1290,9 @@ void ensure_mfie(aim_plan p, hipStream_t s) {
     p->d_mfie_ck32 = p->upload(std::vector<float>(p->mfie_ck.begin(), p->mfie_ck.end()), s);
     AIM_HIP(hipStreamSynchronize(s));
   }
-  ensure_grad_spectra(p, s);
-  p->d_mfie_grid = p->dalloc(size_t(6) * R * g.Ng * 16, s);
-  p->d_mfie_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 6 * R, s);
+  ensure_curl_spectra(p, s);
+  p->d_mfie_grid = p->dalloc(size_t(3) * R * g.Ng * 16, s);
+  p->d_mfie_work = p->dalloc(size_t(aim::work_elems(g, aim::kLayouts - 1, 16)) * 16 * 3 * R, s);
   p->d_mfie_freq = static_cast<int32_t*>(p->dalloc(sizeof(int32_t) * 6 * R, s));
   AIM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_mfie_freq), sizeof(int32_t) * 6 * R, 0));
   AIM_HIP(hipStreamSynchronize(s));
@@ -1316,28 +1320,34 @@ void rwg_matvec_t(aim_plan p, int op, const void* x, void* y, int nrhs,
   const aim::CsrDevice& Pp = dbl ? p->efie_p : p->efie_p32;
   const aim::CsrDevice& Pt = dbl ? p->efie_pt : p->efie_pt32;
   const void* spec = dbl ? p->d_spec64 : p->d_spec32;
-  const void* gspec = dbl ? p->d_dlp_spec : p->d_dlp_spec32;
+  const void* cspec = dbl ? p->d_curl_spec : p->d_curl_spec32;
   void* const* tw = dbl ? p->d_tw64 : p->d_tw32;
   const int* sched = p->sched[pi];
   aim::CsrDevice none{};
   none.n = P;  // interpolation only: the near rows are the test kernel's
   if (efie) stage_freq(fr, 4, p->efie_cur_freq, p->h_efie_freq, p->d_efie_freq, s);
-  if (dl) stage_freq(fr, 6, p->mfie_cur_freq, p->h_mfie_freq, p->d_mfie_freq, s);
+  if (op == 2) stage_freq(fr, 1, p->mfie_cur_freq, p->h_mfie_freq, p->d_mfie_freq, s);
   if (dl && !p->d_cfie_psi) p->d_cfie_psi = p->dalloc(size_t(3) * p->max_rhs * P * 16, s);
   if (efie) {
-    // the four channels; the double layer then takes its three current
-    // grids from this projection
+    // the four channels; the double layer's cross-product z pass reads the
+    // three current channels' forward transforms before the EFIE's own z
+    // pass overwrites them, and writes its field into the double layer's
+    // workspace
     aim::launch_efie_sources<T>(x, vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
     aim::launch_project<T>(p->g, Pp, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
                            p->d_efie_grid, 4 * nrhs, s);
-    if (dl) aim::launch_mfie_moments<T>(p->g, p->d_mfie_grid, nrhs, false, s, p->d_efie_grid);
     aim::launch_convolve<T>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid, spec,
-                            p->d_efie_freq, 4 * nrhs, tw, s, nullptr, sched);
+                            p->d_efie_freq, 4 * nrhs, tw, s, nullptr, sched, 1, nullptr,
+                            nullptr, 0, 1);
     if (dl) {
-      aim::launch_convolve<T>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid, gspec,
-                              p->d_mfie_freq, 6 * nrhs, tw, s, nullptr, sched);
-      aim::launch_mfie_moments<T>(p->g, p->d_mfie_grid, nrhs, true, s);
+      aim::launch_zcross<T>(p->g, p->d_efie_work, p->d_mfie_work, cspec, p->d_efie_freq, nrhs,
+                            tw, s, sched);
+      aim::launch_convolve<T>(p->g, nullptr, p->d_mfie_work, p->d_mfie_grid, nullptr, nullptr,
+                              3 * nrhs, tw, s, nullptr, sched, 1, nullptr, nullptr, 0, 4);
     }
+    aim::launch_convolve<T>(p->g, p->d_efie_grid, p->d_efie_work, p->d_efie_grid, spec,
+                            p->d_efie_freq, 4 * nrhs, tw, s, nullptr, sched, 1, nullptr,
+                            nullptr, 0, 6);
     aim::launch_interp_near<T>(p->g, Pt, none, p->d_efie_grid, nullptr, p->d_efie_src, 4 * nrhs,
                                true, false, s);
     if (dl)
@@ -1348,13 +1358,17 @@ void rwg_matvec_t(aim_plan p, int op, const void* x, void* y, int nrhs,
                             p->d_efie_freq, x, y, N, n, nrhs, s);
     return;
   }
+  // the three current channels: forward x and y passes, the cross-product
+  // z pass in place, inverse y and x passes
   aim::launch_mfie_sources<T>(x, vals, p->d_efie_trirwg, p->d_efie_src, N, n, nrhs, s);
   aim::launch_project<T>(p->g, Pp, p->d_efie_pblk, p->efie_nblk, p->d_efie_src, P,
                          p->d_mfie_grid, 3 * nrhs, s);
-  aim::launch_mfie_moments<T>(p->g, p->d_mfie_grid, nrhs, false, s);
-  aim::launch_convolve<T>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid, gspec,
-                          p->d_mfie_freq, 6 * nrhs, tw, s, nullptr, sched);
-  aim::launch_mfie_moments<T>(p->g, p->d_mfie_grid, nrhs, true, s);
+  aim::launch_convolve<T>(p->g, p->d_mfie_grid, p->d_mfie_work, p->d_mfie_grid, nullptr,
+                          nullptr, 3 * nrhs, tw, s, nullptr, sched, 1, nullptr, nullptr, 0, 1);
+  aim::launch_zcross<T>(p->g, p->d_mfie_work, p->d_mfie_work, cspec, p->d_mfie_freq, nrhs, tw,
+                        s, sched);
+  aim::launch_convolve<T>(p->g, nullptr, p->d_mfie_work, p->d_mfie_grid, nullptr, nullptr,
+                          3 * nrhs, tw, s, nullptr, sched, 1, nullptr, nullptr, 0, 4);
   aim::launch_interp_near<T>(p->g, Pt, none, p->d_mfie_grid, nullptr, p->d_efie_src, 3 * nrhs,
                              true, false, s);
   aim::launch_rwg_test<T>(false, true, nullptr, p->d_efie_src, vals, nrm, p->d_efie_te,

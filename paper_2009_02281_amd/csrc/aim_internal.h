@@ -203,7 +203,22 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
                      int repeat = 1,  // each pass launched this many times (timing only)
                      // with P: q is not read; the x forward pass computes its
                      // lines as q = P x (x [nrhs][n]) itself
-                     const CsrDevice* P = nullptr, const void* x = nullptr, int64_t n = 0);
+                     const CsrDevice* P = nullptr, const void* x = nullptr, int64_t n = 0,
+                     // bit 0: the forward x and y passes (q -> work), bit 1:
+                     // the fused z pass, bit 2: the inverse y and x passes
+                     // (work -> phi)
+                     int stages = 7);
+// The double layers' z pass (Sec. III-B): for nvec vectors, three channels'
+// forward-transformed grids in work_in (channel c of vector r is workspace
+// grid c nvec + r), their spectral products with the gradient spectra spec3
+// ([freq][3][Nfold], from launch_spectrum kinds 2-4) -- dot false: the cross
+// product K x J (three grids), dot true: the sum -(K . q) (one grid, channel
+// 0) -- transformed back into work_out (may equal work_in); the
+// launch_convolve stages 1 before and 4 after it complete the product.
+template <typename T>
+void launch_zcross(const GridShape& g, const void* work_in, void* work_out, const void* spec3,
+                   const int32_t* vec_freq, int nvec, const void* const* tw, hipStream_t s,
+                   const int* sched, bool dot = false);
 // whether launch shape v exists for FFT pass `pass` (0 x forward, 1 y
 // forward, 2 fused z, 3 y inverse, 4 x inverse) of the grid g
 bool fft_variant_ok(bool dbl, const GridShape& g, int pass, int v);
@@ -238,18 +253,16 @@ void launch_interp_near(const GridShape& g, const CsrDevice& Pt, const CsrDevice
 // (complex128) and optionally its complex64 rounding.  kind 0: the grid
 // kernel G(k, R) with self term -jk/(4 pi); kind 1: the radial factor
 // F(R) = h (1 + jkR) e^{-jkR} / (4 pi R^3) of the double layer's gradient
-// channels (dG/dr'_a = (u_a - v_a) F), 0 at the origin.
+// channels (dG/dr'_a = (u_a - v_a) F), 0 at the origin; kinds 2, 3, 4: the
+// component x, y, z of the gradient with respect to the observation point,
+// -(u_a - v_a) F (odd along axis a; its folded spectrum is zero at the
+// frequencies 0 and N of that axis).
 void launch_spectrum(const GridShape& g, double k, double h, void* full_work, void* spec64,
                      void* spec32, const void* const* tw64, hipStream_t s, int kind = 0);
-// double-layer operator, complex128: xs[a][r] = n_a x[r] (three channels);
-// grids[0 .. 3 nrhs) hold the channels' projections q_a, and the moment sum
-// m = sum_a (v_a - c_a) q_a is written to grids[3 nrhs .. 4 nrhs), c the grid
-// centre; then phi[r] = sum_a (u_a - c_a) F*q_a - F*m from the four convolved
-// grids
+// double-layer operator, complex128: xs[a][r] = n_a x[r] (three channels,
+// projected to grids a nrhs + r, then convolved and summed by launch_zcross
+// with dot true)
 void launch_dlp_sources(const void* x, const double* nrm, void* xs, int64_t n, int nrhs,
-                        hipStream_t s);
-void launch_dlp_moments(const GridShape& g, void* grids, int nrhs, hipStream_t s);
-void launch_dlp_combine(const GridShape& g, const void* grids, void* phi, int nrhs,
                         hipStream_t s);
 
 // RWG EFIE, complex128 (T = double) or complex64 (T = float): src[c][r][3t + q] = sum_e vals[t][q][e][c] x[r][tri_rwg[t][e]]
@@ -262,16 +275,11 @@ template <typename T>
 void launch_efie_sources(const void* x, const void* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
 // RWG double layer: the three current channels of x at the points
-// (src[a][r][p], as launch_efie_sources without the charge); the grid
-// moments M = (u - c) x J (combine false: grids [3 nrhs, 6 nrhs) from
-// [0, 3 nrhs)) or, after the convolutions with the radial factor F, the field
-// V = -[(u - c) x (F * J) - F * M] into grids [0, 3 nrhs) (combine true)
+// (src[a][r][p], as launch_efie_sources without the charge); their grids'
+// field V = grad G x J is one spectral cross product (launch_zcross)
 template <typename T>
 void launch_mfie_sources(const void* x, const void* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s);
-template <typename T>
-void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s,
-                         const void* j_in = nullptr);  // currents from other grids (copied)
 // y for the EFIE (efie), the double layer (mfie) or the combined field of
 // eq. CFIEAIMx (both: y = y_E + (j/k_r) y_M), from psi_e [4][nrhs][3N] and
 // psi_m [3][nrhs][3N]; cc = (C_A, C_phi), ck = (C_K, G) interleaved; T the

@@ -10,9 +10,10 @@
 // with the projection, convolution and interpolation kernels of the scalar
 // operator (the point stencils in place of the merged triangle stencils).
 // The double layer's product runs three current channels through the same
-// projection, the moments (u - c) x J on the grid, six convolutions with the
-// radial factor of grad G, the field combined on the grid, interpolation of
-// its three components and mfie_test.
+// projection and forward transforms, one z pass that forms the spectral
+// cross product with the three components of grad G, the inverse transforms,
+// interpolation of the field's three components and the test kernel; the
+// combined field shares the EFIE's projection and forward transforms.
 // Both kernels here are gathers over small fixed fan-ins: a point reads the
 // three functions of its triangle, a function the six points of its two
 // triangles and its near-list row; every output is written once, with a
@@ -81,55 +82,6 @@ __global__ __launch_bounds__(256) void efie_sources_kernel(
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) src[(int64_t(c) * nrhs + r) * P + p] = acc[c];
-  }
-}
-
-// The double layer's grid stages (Sec. III-B, eq. KAIMx) in grid index
-// units about the grid centre c: with the radial factor F of the kernel
-// spectrum, grad G(r_u - r_v) = -(u - v) F(u - v), so the field
-// V(u) = sum_v grad G(r_u - r_v) x J(v) is -[(u - c) x (F * J)(u) - (F * M)(u)]
-// with the moments M(v) = (v - c) x J(v).  Grids: J_a of vector r at
-// a nrhs + r, M_a at (3 + a) nrhs + r; V overwrites J.
-template <typename T>
-__global__ __launch_bounds__(256) void mfie_moments_kernel(const c2<T>* j_in, c2<T>* g, int Nx,
-                                                           int Ny, int64_t Ng, int nrhs,
-                                                           double cx, double cy, double cz) {
-  const int r = blockIdx.y;
-  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
-       u += int64_t(gridDim.x) * blockDim.x) {
-    const T dx = T(double(u % Nx) - cx), dy = T(double((u / Nx) % Ny) - cy),
-            dz = T(double(u / (int64_t(Nx) * Ny)) - cz);
-    const c2<T> jx = j_in[int64_t(r) * Ng + u], jy = j_in[int64_t(nrhs + r) * Ng + u],
-                  jz = j_in[int64_t(2 * nrhs + r) * Ng + u];
-    if (j_in != g) {  // the currents come from another set of grids: copy them
-      g[int64_t(r) * Ng + u] = jx;
-      g[int64_t(nrhs + r) * Ng + u] = jy;
-      g[int64_t(2 * nrhs + r) * Ng + u] = jz;
-    }
-    g[int64_t(3 * nrhs + r) * Ng + u] = mk2<T>(dy * jz.x - dz * jy.x, dy * jz.y - dz * jy.y);
-    g[int64_t(4 * nrhs + r) * Ng + u] = mk2<T>(dz * jx.x - dx * jz.x, dz * jx.y - dx * jz.y);
-    g[int64_t(5 * nrhs + r) * Ng + u] = mk2<T>(dx * jy.x - dy * jx.x, dx * jy.y - dy * jx.y);
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void mfie_combine_kernel(c2<T>* __restrict__ g, int Nx, int Ny,
-                                                           int64_t Ng, int nrhs, double cx,
-                                                           double cy, double cz) {
-  const int r = blockIdx.y;
-  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
-       u += int64_t(gridDim.x) * blockDim.x) {
-    const T dx = T(double(u % Nx) - cx), dy = T(double((u / Nx) % Ny) - cy),
-            dz = T(double(u / (int64_t(Nx) * Ny)) - cz);
-    c2<T>* a0 = g + int64_t(r) * Ng + u;
-    c2<T>* a1 = g + int64_t(nrhs + r) * Ng + u;
-    c2<T>* a2 = g + int64_t(2 * nrhs + r) * Ng + u;
-    const c2<T> ax = *a0, ay = *a1, az = *a2;
-    const c2<T> bx = g[int64_t(3 * nrhs + r) * Ng + u], by = g[int64_t(4 * nrhs + r) * Ng + u],
-                  bz = g[int64_t(5 * nrhs + r) * Ng + u];
-    *a0 = mk2<T>(bx.x - (dy * az.x - dz * ay.x), bx.y - (dy * az.y - dz * ay.y));
-    *a1 = mk2<T>(by.x - (dz * ax.x - dx * az.x), by.y - (dz * ax.y - dx * az.y));
-    *a2 = mk2<T>(bz.x - (dx * ay.x - dy * ax.x), bz.y - (dx * ay.y - dy * ax.y));
   }
 }
 
@@ -322,21 +274,6 @@ void launch_mfie_sources(const void* x, const void* vals, const int32_t* tri_rwg
 }
 
 template <typename T>
-void launch_mfie_moments(const GridShape& g, void* grids, int nrhs, bool combine, hipStream_t s,
-                         const void* j_in) {
-  const double cx = 0.5 * (g.N[0] - 1), cy = 0.5 * (g.N[1] - 1), cz = 0.5 * (g.N[2] - 1);
-  c2<T>* gp = static_cast<c2<T>*>(grids);
-  const c2<T>* jp = j_in ? static_cast<const c2<T>*>(j_in) : gp;
-  if (combine)
-    hipLaunchKernelGGL((mfie_combine_kernel<T>), dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s,
-                       gp, g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
-  else
-    hipLaunchKernelGGL((mfie_moments_kernel<T>), dim3(blocks(g.Ng, 1024), nrhs), dim3(256), 0, s,
-                       jp, gp, g.N[0], g.N[1], g.Ng, nrhs, cx, cy, cz);
-  AIM_HIP(hipGetLastError());
-}
-
-template <typename T>
 void launch_efie_sources(const void* x, const void* vals, const int32_t* tri_rwg, void* src,
                          int64_t N, int64_t nrwg, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL((efie_sources_kernel<4, T>), dim3(blocks(3 * N), nrhs), dim3(256), 0, s,
@@ -389,8 +326,6 @@ void launch_rwg_test(bool efie, bool mfie, const void* psi_e, const void* psi_m,
 #define AIM_RWG_INSTANTIATE(T)                                                                 \
   template void launch_mfie_sources<T>(const void*, const void*, const int32_t*, void*,       \
                                        int64_t, int64_t, int, hipStream_t);                   \
-  template void launch_mfie_moments<T>(const GridShape&, void*, int, bool, hipStream_t,      \
-                                       const void*);                                          \
   template void launch_efie_sources<T>(const void*, const void*, const int32_t*, void*,       \
                                        int64_t, int64_t, int, hipStream_t);                   \
   template void launch_rwg_test<T>(bool, bool, const void*, const void*, const void*,         \

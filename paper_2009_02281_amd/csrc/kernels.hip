@@ -354,6 +354,10 @@ struct PassArgs {
   const void* pval;
   const void* px;
   int64_t px_bs;
+  // the double layer's cross-product z pass: stride between the three
+  // channels' grids, and between the three folded gradient spectra
+  int64_t ch_bs;
+  int64_t spec_cs;
 };
 
 template <typename T, int L, int TL, int NT, int MODE, bool COL, int RMAX, bool HALF>
@@ -529,6 +533,137 @@ __global__ __launch_bounds__(TL* NT) void fft_pass_kernel(const cx<T>* in, cx<T>
           }
         }
       }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z pass of the double-layer operators (Sec. III-B, eq. KAIMx) with the
+// spectra K^_a of the three components of grad G (each odd along its own
+// axis: the folded entry times -1 where the frequency along that axis lies
+// above N).  A workgroup takes the z lines at TL positions (kx, ky) of all
+// three channels, transforms them forward and forms
+//   DOT false (RWG double layer): V^ = K^ x J^, three products;
+//   DOT true (scalar double layer): -(K^ . q^), the channels q_a = n_a x
+//   convolved with dG/dr'_a = -K_a and summed, one product,
+// transforms the products back and writes the first Nz elements of each
+// line into `out` (in place when out == in; the DOT product goes to channel
+// 0).  The forward and inverse transforms, the element ownership and the
+// XCD-aware order of the rows are those of the fused z pass
+// (fft_pass_kernel, MODE 2).
+// ---------------------------------------------------------------------------
+template <typename T, int L, int TL, int NT, int RMAX, bool DOT>
+__global__ __launch_bounds__(TL* NT) void zcross_kernel(const cx<T>* in, cx<T>* out,
+                                                       const cx<T>* __restrict__ twg,
+                                                       PassArgs a) {
+  constexpr int NOUT = DOT ? 1 : 3;
+  constexpr int E = L / NT;
+  __shared__ cx<T> s[L * TL];
+  __shared__ cx<T> tw[L];
+  const int tid = threadIdx.x;
+  const int rhs = blockIdx.y;
+  in += rhs * a.in_bs;
+  out += rhs * a.out_bs;
+  const int l = tid & (TL - 1);
+  const int t = tid / TL;
+  int64_t line0 = int64_t(blockIdx.x) * TL;
+  if (a.Mx >= TL) {  // the fused z pass's order: mirrored rows on one XCD
+    const int nbx = a.Mx / TL;
+    const int nb = nbx * a.My;
+    const int b = int(blockIdx.x);
+    const int lb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int rowpos = lb / nbx, g = lb % nbx;
+    const int h = a.My / 2;
+    const int ky = rowpos == 0 ? 0
+                 : rowpos == a.My - 1 ? h
+                 : (rowpos & 1) ? (rowpos + 1) / 2 : a.My - rowpos / 2;
+    line0 = int64_t(ky) * a.Mx + int64_t(g) * TL;
+  }
+  const int64_t line = line0 + l;
+  const bool valid = line < a.nlines;
+  const int64_t mask = (int64_t(1) << a.lg_nli) - 1;
+  const int64_t li = line & mask, lo = line >> a.lg_nli;
+  const cx<T>* src = in + lo * a.in_os + li * a.in_p0;
+  cx<T>* dst = out + lo * a.out_os + li * a.out_p0;
+  cx<T>* sl = s + l;
+  using S0 = Sched<L, true, RMAX>;
+  constexpr int R0 = S0::radix(0), NB0 = L / (R0 * NT);
+  cx<T> v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int e = t + i * NT + r * (L / R0);
+        v[c][i * R0 + r] = (valid && r < R0 / 2) ? src[c * a.ch_bs + e * a.in_es]
+                                                 : mkc<T>(T(0), T(0));
+      }
+  using Fw = Sched<L, true, RMAX>;
+  constexpr int RM = Fw::radix(Fw::NST - 1);
+  static_assert(RM == Sched<L, false, RMAX>::radix(0),
+                "the forward transform must end with the radix the inverse starts with");
+  cx<T> kv[3][E];
+  if (valid) {
+    const int kx = int(li), ky = int(lo);
+    const bool ox = kx > a.Nx, oy = ky > a.Ny;
+    const int fx = ox ? a.Mx - kx : kx;
+    const int fy = oy ? a.My - ky : ky;
+    const cx<T>* sp = static_cast<const cx<T>*>(a.spec) + int64_t(a.rhs_freq[rhs]) * a.spec_fs +
+                      int64_t(fy) * (a.Nz + 1) * (a.Nx + 1) + fx;
+    const int64_t zst = int64_t(a.Nx + 1);
+#pragma unroll
+    for (int i = 0; i < L / (RM * NT); ++i)
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        const int e = t + i * NT + r * (L / RM);
+        const bool oz = e > a.Nz;
+        const int64_t o = int64_t(oz ? a.Mz - e : e) * zst;
+        cx<T> k0 = sp[o], k1 = sp[a.spec_cs + o], k2 = sp[2 * a.spec_cs + o];
+        if (ox) k0 = mkc<T>(-k0.x, -k0.y);
+        if (oy) k1 = mkc<T>(-k1.x, -k1.y);
+        if (oz) k2 = mkc<T>(-k2.x, -k2.y);
+        kv[0][i * RM + r] = k0;
+        kv[1][i * RM + r] = k1;
+        kv[2][i * RM + r] = k2;
+      }
+  }
+  for (int m = tid; m < L; m += TL * NT) tw[m] = twg[m];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) run_stages<T, L, NT, false, true, RMAX, 0, true>(v[c], sl, TL, t, tw);
+  if (valid && DOT) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const cx<T> a0 = cmul(kv[0][k], v[0][k]), a1 = cmul(kv[1][k], v[1][k]),
+                  a2 = cmul(kv[2][k], v[2][k]);
+      v[0][k] = mkc<T>(-((a0.x + a1.x) + a2.x), -((a0.y + a1.y) + a2.y));
+    }
+  } else if (valid) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const cx<T> jx = v[0][k], jy = v[1][k], jz = v[2][k];
+      const cx<T> ax = cmul(kv[1][k], jz), bx = cmul(kv[2][k], jy);
+      const cx<T> ay = cmul(kv[2][k], jx), by = cmul(kv[0][k], jz);
+      const cx<T> az = cmul(kv[0][k], jy), bz = cmul(kv[1][k], jx);
+      v[0][k] = mkc<T>(ax.x - bx.x, ax.y - bx.y);
+      v[1][k] = mkc<T>(ay.x - by.x, ay.y - by.y);
+      v[2][k] = mkc<T>(az.x - bz.x, az.y - bz.y);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NOUT; ++c) run_stages<T, L, NT, true, false, RMAX, 0>(v[c], sl, TL, t, tw);
+  using Sf = Sched<L, false, RMAX>;
+  constexpr int Rf = Sf::radix(Sf::NST - 1), NBf = L / (Rf * NT);
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c)
+#pragma unroll
+      for (int i = 0; i < NBf; ++i)
+#pragma unroll
+        for (int r = 0; r < Rf / 2; ++r) {  // the kept half: e < L/2
+          const int e = t + i * NT + r * (L / Rf);
+          dst[c * a.ch_bs + e * a.out_es] = v[c][i * Rf + r];
+        }
   }
 }
 
@@ -988,7 +1123,7 @@ template <typename T>
 void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, const void* spec,
                      const int32_t* rhs_freq, int nrhs, const void* const* tw, hipStream_t s,
                      hipEvent_t* between, const int* sched, int repeat, const CsrDevice* P,
-                     const void* x, int64_t n) {
+                     const void* x, int64_t n, int stages) {
   static const int kDefault[kSchedLen] = {0, 0, 0, 0, 0, 0, 0};
   if (!sched) sched = kDefault;
   auto mark = [&](int i) {
@@ -1017,19 +1152,22 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     a.Lout = Lout;
     return a;
   };
-  // x forward: rows (y, z) of q, Nx -> Mx, into A [Nz][Ny][Mx]
-  for (int r = 0; r < repeat; ++r)
-    row_pass<T>(Mx, false, q, A, tw[0], Nz, Ny, Nx, Mx, int64_t(Ny) * Nx, PA, Ng, W, Nx, Mx,
-                nrhs, s, sched[0], P, x, n);
-  mark(0);
-  // y forward: A [Nz][Ny][Mx] -> B [Nz][My][Mx]
-  {
-    const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, PA, Mx, PB, Ny, My);
-    for (int r = 0; r < repeat; ++r) fft_pass<T>(My, true, 0, A, B, tw[1], a, nrhs, s, sched[1]);
+  if (stages & 1) {
+    // x forward: rows (y, z) of q, Nx -> Mx, into A [Nz][Ny][Mx]
+    for (int r = 0; r < repeat; ++r)
+      row_pass<T>(Mx, false, q, A, tw[0], Nz, Ny, Nx, Mx, int64_t(Ny) * Nx, PA, Ng, W, Nx, Mx,
+                  nrhs, s, sched[0], P, x, n);
+    mark(0);
+    // y forward: A [Nz][Ny][Mx] -> B [Nz][My][Mx]
+    {
+      const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, PA, Mx, PB, Ny, My);
+      for (int r = 0; r < repeat; ++r)
+        fft_pass<T>(My, true, 0, A, B, tw[1], a, nrhs, s, sched[1]);
+    }
+    mark(1);
   }
-  mark(1);
   // z forward * spectrum * z inverse, in place on B, keeping z < Nz
-  {
+  if (stages & 2) {
     PassArgs a = col_args(int64_t(Mx) * My, PB, Mx, PB, Mx, Nz, Nz);
     a.spec = spec;
     a.spec_fs = g.Nfold;
@@ -1060,26 +1198,140 @@ void launch_convolve(const GridShape& g, const void* q, void* work, void* phi, c
     }
   }
   mark(2);
-  // y inverse: B [Nz][My][Mx] -> A [Nz][Ny][Mx]
-  {
-    const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, PB, Mx, PA, My, Ny);
-    for (int r = 0; r < repeat; ++r) fft_pass<T>(My, true, 1, B, A, tw[1], a, nrhs, s, sched[3]);
+  if (stages & 4) {
+    // y inverse: B [Nz][My][Mx] -> A [Nz][Ny][Mx]
+    {
+      const PassArgs a = col_args(int64_t(Mx) * Nz, Mx, PB, Mx, PA, My, Ny);
+      for (int r = 0; r < repeat; ++r)
+        fft_pass<T>(My, true, 1, B, A, tw[1], a, nrhs, s, sched[3]);
+    }
+    mark(3);
+    // x inverse: rows of A (Mx) -> phi (Nx)
+    for (int r = 0; r < repeat; ++r)
+      row_pass<T>(Mx, true, A, phi, tw[0], Nz, Ny, Mx, Nx, PA, int64_t(Ny) * Nx, W, Ng, Mx, Nx,
+                  nrhs, s, sched[4]);
   }
-  mark(3);
-  // x inverse: rows of A (Mx) -> phi (Nx)
-  for (int r = 0; r < repeat; ++r)
-    row_pass<T>(Mx, true, A, phi, tw[0], Nz, Ny, Mx, Nx, PA, int64_t(Ny) * Nx, W, Ng, Mx, Nx,
-                nrhs, s, sched[4]);
 }
+
+// the gradient z pass over nvec vectors' three channels (channel c of
+// vector r is workspace grid c nvec + r in both buffers)
+template <typename T, int L, int V>
+void zcross_shape(bool dot, const cx<T>* i, cx<T>* o, const cx<T>* w, const PassArgs& a,
+                  int nvec, hipStream_t s) {
+  using S = Shape<T, L, true, V>;
+  if constexpr (!S::OK || S::RMAX != 8) {
+    throw Error(AIM_ERR_INVALID_ARG, "gradient z pass: launch shape not available");
+  } else {
+    const dim3 grid(unsigned((a.nlines + S::TL - 1) / S::TL), unsigned(nvec));
+    if (dot)
+      hipLaunchKernelGGL((zcross_kernel<T, L, S::TL, S::NT, S::RMAX, true>), grid,
+                         dim3(S::THREADS), 0, s, i, o, w, a);
+    else
+      hipLaunchKernelGGL((zcross_kernel<T, L, S::TL, S::NT, S::RMAX, false>), grid,
+                         dim3(S::THREADS), 0, s, i, o, w, a);
+  }
+}
+
+template <typename T, int L>
+int zcross_elems(int v) {  // elements per thread of column shape v (0 if unavailable)
+  switch (v) {
+    case 0: return Shape<T, L, true, 0>::OK ? L / Shape<T, L, true, 0>::NT : 0;
+    case 1: return Shape<T, L, true, 1>::OK ? L / Shape<T, L, true, 1>::NT : 0;
+    case 2: return Shape<T, L, true, 2>::OK ? L / Shape<T, L, true, 2>::NT : 0;
+    case 3: return Shape<T, L, true, 3>::OK ? L / Shape<T, L, true, 3>::NT : 0;
+    default: return 0;
+  }
+}
+
+template <typename T, int L>
+void zcross_L(bool dot, int pref, const cx<T>* i, cx<T>* o, const cx<T>* w, const PassArgs& a,
+              int nvec, hipStream_t s) {
+  // the z pass's own shape when it is a radix-8 one holding at most 64
+  // bytes of each channel per thread, else the available radix-8 shape with
+  // the fewest elements per thread (six lines' worth of registers per thread)
+  constexpr int kMaxBytes = 64;
+  int v = -1;
+  if (pref >= 0 && pref < 4) {
+    const int e = zcross_elems<T, L>(pref);
+    if (e > 0 && e * int(sizeof(T)) <= kMaxBytes) v = pref;
+  }
+  if (v < 0) {
+    int best = 0;
+    for (int c = 0; c < 4; ++c) {
+      const int e = zcross_elems<T, L>(c);
+      if (e > 0 && (v < 0 || e < best)) v = c, best = e;
+    }
+  }
+  switch (v) {
+    case 0: zcross_shape<T, L, 0>(dot, i, o, w, a, nvec, s); break;
+    case 1: zcross_shape<T, L, 1>(dot, i, o, w, a, nvec, s); break;
+    case 2: zcross_shape<T, L, 2>(dot, i, o, w, a, nvec, s); break;
+    case 3: zcross_shape<T, L, 3>(dot, i, o, w, a, nvec, s); break;
+    default: throw Error(AIM_ERR_GRID, "no launch shape for the cross-product z pass");
+  }
+}
+
+template <typename T>
+void launch_zcross(const GridShape& g, const void* work_in, void* work_out, const void* spec3,
+                   const int32_t* vec_freq, int nvec, const void* const* tw, hipStream_t s,
+                   const int* sched, bool dot) {
+  static const int kDefault[kSchedLen] = {0, 0, 0, 0, 0, 0, 0};
+  if (!sched) sched = kDefault;
+  const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+  const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
+  const int64_t pad = kLayoutPadBytes[sched[5]] / int64_t(sizeof(cx<T>));
+  const int64_t PB = int64_t(My) * Mx + pad;
+  const int64_t W = work_elems(g, sched[5], sizeof(cx<T>));
+  PassArgs a{};
+  a.nlines = int64_t(Mx) * My;
+  a.lg_nli = ilog2(Mx);
+  a.in_es = a.out_es = PB;
+  a.in_os = a.out_os = Mx;
+  a.in_p0 = a.out_p0 = 1;
+  a.in_bs = a.out_bs = W;
+  a.Lin = a.Lout = Nz;
+  a.ch_bs = int64_t(nvec) * W;
+  a.spec = spec3;
+  a.spec_cs = g.Nfold;
+  a.spec_fs = 3 * g.Nfold;
+  a.rhs_freq = vec_freq;
+  a.Mx = Mx;
+  a.Nx = Nx;
+  a.My = My;
+  a.Ny = Ny;
+  a.Mz = Mz;
+  a.Nz = Nz;
+  const cx<T>* i = static_cast<const cx<T>*>(work_in);
+  cx<T>* o = static_cast<cx<T>*>(work_out);
+  const cx<T>* w = static_cast<const cx<T>*>(tw[2]);
+  const int pref = sched[2] < kFftShapesPerLine ? sched[2] : -1;
+  switch (Mz) {
+    case 16: zcross_L<T, 16>(dot, pref, i, o, w, a, nvec, s); break;
+    case 32: zcross_L<T, 32>(dot, pref, i, o, w, a, nvec, s); break;
+    case 64: zcross_L<T, 64>(dot, pref, i, o, w, a, nvec, s); break;
+    case 128: zcross_L<T, 128>(dot, pref, i, o, w, a, nvec, s); break;
+    case 256: zcross_L<T, 256>(dot, pref, i, o, w, a, nvec, s); break;
+    case 512: zcross_L<T, 512>(dot, pref, i, o, w, a, nvec, s); break;
+    default: throw Error(AIM_ERR_GRID, "unsupported FFT length");
+  }
+  AIM_HIP(hipGetLastError());
+}
+
+template void launch_zcross<double>(const GridShape&, const void*, void*, const void*,
+                                    const int32_t*, int, const void* const*, hipStream_t,
+                                    const int*, bool);
+template void launch_zcross<float>(const GridShape&, const void*, void*, const void*,
+                                   const int32_t*, int, const void* const*, hipStream_t,
+                                   const int*, bool);
 
 template void launch_convolve<double>(const GridShape&, const void*, void*, void*, const void*,
                                       const int32_t*, int, const void* const*, hipStream_t,
                                       hipEvent_t*, const int*, int, const CsrDevice*,
-                                      const void*, int64_t);
+                                      const void*, int64_t, int);
 template void launch_convolve<float>(const GridShape&, const void*, void*, void*, const void*,
                                      const int32_t*, int, const void* const*, hipStream_t,
                                      hipEvent_t*, const int*, int, const CsrDevice*, const void*,
-                                     int64_t);
+                                     int64_t, int);
 
 // ---------------------------------------------------------------------------
 // kernel spectrum: circulant embedding of G on the padded grid, full 3-D FFT,
@@ -1104,13 +1356,17 @@ __global__ void green_sample_kernel(double2* c, int Nx, int Ny, int Nz, double k
       const double dz = iz < Nz ? iz : iz - Mz;
       const double d2 = dx * dx + dy * dy + dz * dz;
       const double inv4pi = 0.07957747154594766788;  // 1/(4 pi)
-      if (kind == 1) {
-        // h (1 + jkR) e^{-jkR} / (4 pi R^3), 0 at the origin
+      if (kind >= 1) {
+        // kind 1: F = h (1 + jkR) e^{-jkR} / (4 pi R^3); kinds 2, 3, 4: the
+        // gradient of G with respect to the observation point, component
+        // a = kind - 2, i.e. -d_a F with d in node units; 0 at the origin
         if (d2 != 0.0) {
           const double R = h * sqrt(d2);
           double sn, cs;
           sincos(k * R, &sn, &cs);
-          const double a = h * inv4pi / (R * R * R), kr = k * R;
+          double a = h * inv4pi / (R * R * R);
+          if (kind >= 2) a *= -(kind == 2 ? dx : kind == 3 ? dy : dz);
+          const double kr = k * R;
           v.x = (cs + kr * sn) * a;
           v.y = (kr * cs - sn) * a;
         }
@@ -1130,7 +1386,7 @@ __global__ void green_sample_kernel(double2* c, int Nx, int Ny, int Nz, double k
 }
 
 __global__ void fold_spectrum_kernel(const double2* full, double2* s64, float2* s32, int Nx,
-                                     int Ny, int Nz, double scale) {
+                                     int Ny, int Nz, double scale, int odd) {
   const int Fx = Nx + 1, Fy = Ny + 1, Fz = Nz + 1;
   const int64_t total = int64_t(Fx) * Fy * Fz;
   const int Mx = 2 * Nx, My = 2 * Ny;
@@ -1141,6 +1397,10 @@ __global__ void fold_spectrum_kernel(const double2* full, double2* s64, float2* 
     double2 v = full[(int64_t(fz) * My + fy) * Mx + fx];
     v.x *= scale;
     v.y *= scale;
+    // a kernel odd along one axis has a spectrum odd along it, exactly zero
+    // at its frequencies 0 and N (there the transform only holds rounding)
+    const int fo = odd == 0 ? fx : odd == 1 ? fy : fz, no = odd == 0 ? Nx : odd == 1 ? Ny : Nz;
+    if (odd >= 0 && (fo == 0 || fo == no)) v.x = v.y = 0.0;
     s64[idx] = v;
     if (s32) {
       float2 w;
@@ -1192,7 +1452,7 @@ void launch_spectrum(const GridShape& g, double k, double h, void* full_work, vo
   }
   hipLaunchKernelGGL(fold_spectrum_kernel, dim3(2048), dim3(256), 0, s, F,
                      static_cast<double2*>(spec64), static_cast<float2*>(spec32), Nx, Ny, Nz,
-                     1.0 / double(Np));
+                     1.0 / double(Np), kind >= 2 ? kind - 2 : -1);
   AIM_HIP(hipGetLastError());
 }
 
@@ -2665,13 +2925,10 @@ void launch_zero_words(void* p, int64_t n, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // double-layer operator (Sec. III-B, eq. KAIMx): the far product
 // W sum_a H_grad,a P diag(n_a) x with the odd channel kernels
-// H_grad,a(u, v) = (u_a - v_a) F(|u - v|), F radial.  Since
-//   sum_v (u_a - v_a) F(u - v) q(v) = (u_a - c_a) (F * q)(u) - (F * ((v_a - c_a) q))(u)
-// for any centre c, and the second terms of the three channels add up before
-// the convolution: four convolutions with the one even kernel F through the
-// pruned FFT path, F*q_a for a = x, y, z and F*m with m = sum_a (v_a - c_a) q_a
-// (the centre keeps the two terms' magnitudes, and so the cancellation
-// between them, small).
+// H_grad,a(u, v) = (u_a - v_a) F(|u - v|), F radial: the channel sources
+// n_a x here, their projections and forward transforms, then one z pass
+// (zcross_kernel, DOT) that sums the three spectral products into one grid,
+// transformed back.
 // ---------------------------------------------------------------------------
 __global__ void dlp_sources_kernel(const double2* __restrict__ x, const double* __restrict__ nrm,
                                    double2* __restrict__ xs, int64_t n, int nrhs) {
@@ -2691,61 +2948,6 @@ void launch_dlp_sources(const void* x, const double* nrm, void* xs, int64_t n, i
                         hipStream_t s) {
   hipLaunchKernelGGL(dlp_sources_kernel, dim3(grid_for(n, 1024), nrhs), dim3(256), 0, s,
                      static_cast<const double2*>(x), nrm, static_cast<double2*>(xs), n, nrhs);
-  AIM_HIP(hipGetLastError());
-}
-
-__global__ void dlp_moments_kernel(double2* __restrict__ g, int Nx, int Ny, int64_t Ng,
-                                   int nrhs, double cx, double cy, double cz) {
-  const int r = blockIdx.y;
-  double2* m = g + int64_t(3 * nrhs + r) * Ng;
-  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
-       u += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t ix = u % Nx, iy = (u / Nx) % Ny, iz = u / (int64_t(Nx) * Ny);
-    const double d[3] = {double(ix) - cx, double(iy) - cy, double(iz) - cz};
-    double re = 0.0, im = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double2 v = g[(int64_t(a) * nrhs + r) * Ng + u];
-      re += d[a] * v.x;
-      im += d[a] * v.y;
-    }
-    m[u] = make_double2(re, im);
-  }
-}
-
-void launch_dlp_moments(const GridShape& g, void* grids, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(dlp_moments_kernel, dim3(grid_for(g.Ng, 1024), nrhs), dim3(256), 0, s,
-                     static_cast<double2*>(grids), g.N[0], g.N[1], g.Ng, nrhs,
-                     0.5 * (g.N[0] - 1), 0.5 * (g.N[1] - 1), 0.5 * (g.N[2] - 1));
-  AIM_HIP(hipGetLastError());
-}
-
-__global__ void dlp_combine_kernel(const double2* __restrict__ g, double2* __restrict__ phi,
-                                   int Nx, int Ny, int64_t Ng, int nrhs, double cx, double cy,
-                                   double cz) {
-  const int r = blockIdx.y;
-  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < Ng;
-       u += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t ix = u % Nx, iy = (u / Nx) % Ny, iz = u / (int64_t(Nx) * Ny);
-    const double d[3] = {double(ix) - cx, double(iy) - cy, double(iz) - cz};
-    const double2 m = g[(int64_t(3) * nrhs + r) * Ng + u];
-    double re = -m.x, im = -m.y;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double2 f = g[(int64_t(a) * nrhs + r) * Ng + u];
-      re += d[a] * f.x;
-      im += d[a] * f.y;
-    }
-    phi[int64_t(r) * Ng + u] = make_double2(re, im);
-  }
-}
-
-void launch_dlp_combine(const GridShape& g, const void* grids, void* phi, int nrhs,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(dlp_combine_kernel, dim3(grid_for(g.Ng, 1024), nrhs), dim3(256), 0, s,
-                     static_cast<const double2*>(grids), static_cast<double2*>(phi), g.N[0],
-                     g.N[1], g.Ng, nrhs, 0.5 * (g.N[0] - 1), 0.5 * (g.N[1] - 1),
-                     0.5 * (g.N[2] - 1));
   AIM_HIP(hipGetLastError());
 }
 
