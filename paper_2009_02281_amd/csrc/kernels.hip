@@ -1714,40 +1714,13 @@ __global__ __launch_bounds__(256) void interp_near_kernel(
   T ar[RB], ai[RB];
 #pragma unroll
   for (int j = 0; j < RB; ++j) ar[j] = ai[j] = T(0);
-  if (RB > 1 && i < n) {  // several vectors: batched entries (see row_gather)
+  if (i < n) {  // entries taken kRowBatch at a time (see row_gather)
     if constexpr (INTERP)
       row_gather<T, LPR, RB>(prow[i], prow[i + 1], sub, pcol, pval, phi + rhs0 * Ng, Ng, nr, ar,
                              ai);
     if constexpr (NEARC)
       row_gather<T, LPR, RB>(rowptr[i], rowptr[i + 1], sub, col, val, x + rhs0 * n, n, nr, ar,
                              ai);
-  } else if (i < n) {
-    if constexpr (INTERP) {
-      for (int k = prow[i] + sub; k < prow[i + 1]; k += LPR) {
-        const T w = pval[k];
-        const int64_t c = pcol[k];
-#pragma unroll
-        for (int j = 0; j < RB; ++j)
-          if (j < nr) {
-            const cx<T> v = phi[(rhs0 + j) * Ng + c];
-            ar[j] += w * v.x;
-            ai[j] += w * v.y;
-          }
-      }
-    }
-    if constexpr (NEARC) {
-      for (int k = rowptr[i] + sub; k < rowptr[i + 1]; k += LPR) {
-        const T v = val[k];
-        const int64_t c = col[k];
-#pragma unroll
-        for (int j = 0; j < RB; ++j)
-          if (j < nr) {
-            const cx<T> xv = x[(rhs0 + j) * n + c];
-            ar[j] += v * xv.x;
-            ai[j] += v * xv.y;
-          }
-      }
-    }
   }
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
